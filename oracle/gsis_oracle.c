@@ -1,0 +1,693 @@
+/*
+ * gsis_oracle.c -- plain FP64 CPU oracle of the steady gray source iteration
+ * (SI) and general synthetic iterative scheme (GSIS).
+ *
+ * TEST INFRASTRUCTURE ONLY: tests, the smoke check and the CPU-baseline leg of
+ * the benchmark call it; the product path never does. It shares no code,
+ * header, table or helper with the HIP library.
+ *
+ * Everything is written out per cell, per face and per ordinate, in the order
+ * the paper states the steps, with no blocking or fusion. OpenMP only splits
+ * independent ordinates (or independent rows of a factorisation); every sum
+ * is taken in a fixed order, so results do not depend on the thread count.
+ *
+ * Readings of the paper that this file fixes (the paper is silent there):
+ *  - steady state: the 1/(c dt) terms and the material equation are dropped;
+ *    the emission term sigma_a*phi_emit is the isotropic source q, so the
+ *    transport source is (sigma_s*phi + q)/(4 pi) and the synthetic source q;
+ *  - the transport increment system (Eq. RTE_d_mtx) is solved exactly, once
+ *    per outer iteration, by visiting cells in upwind order per ordinate;
+ *  - the synthetic equation uses the compact flux Gamma_f (phi_c - phi_nb)
+ *    for the diffusion part (its own Jacobian, Eq. Gamma_ij_def) and the
+ *    face average of the cell higher-order terms (Eq. Fij_d, second term);
+ *    the resulting SPD system is solved exactly;
+ *  - least squares use the existing face neighbours only, unweighted;
+ *  - the Barth-Jespersen limiter takes the extrema over the cell and its
+ *    face neighbours and checks all four faces;
+ *  - an upwind tie (Omega.n = 0) takes the cell's own value.
+ */
+#include "gsis_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define FOUR_PI (4.0 * M_PI)
+
+/* Face directions of a Cartesian cell: 0 = east (+x), 1 = west (-x),
+ * 2 = north (+y), 3 = south (-y). */
+static const double NX_[4] = {1.0, -1.0, 0.0, 0.0};
+static const double NY_[4] = {0.0, 0.0, 1.0, -1.0};
+static const int OPP_[4] = {1, 0, 3, 2};
+
+static int neighbour(const ora_problem *p, int i, int j, int f) {
+  int ii = i + (f == 0) - (f == 1);
+  int jj = j + (f == 2) - (f == 3);
+  if (ii < 0 || ii >= p->nx || jj < 0 || jj >= p->ny) return -1;
+  return jj * p->nx + ii;
+}
+
+/* Boundary-face index of cell (i,j) on side f (only valid if no neighbour). */
+static int bface(const ora_problem *p, int i, int j, int f) {
+  switch (f) {
+    case 1: return j;                         /* west  */
+    case 0: return p->ny + j;                 /* east  */
+    case 3: return 2 * p->ny + i;             /* south */
+    default: return 2 * p->ny + p->nx + i;    /* north */
+  }
+}
+
+/* x_f - x_c for face f (face centres sit midway on a uniform grid). */
+static double face_ox(const ora_problem *p, int f) { return 0.5 * p->dx * NX_[f]; }
+static double face_oy(const ora_problem *p, int f) { return 0.5 * p->dy * NY_[f]; }
+/* Face area over cell volume. */
+static double area_over_vol(const ora_problem *p, int f) {
+  return (f < 2) ? 1.0 / p->dx : 1.0 / p->dy;
+}
+static double face_area(const ora_problem *p, int f) { return (f < 2) ? p->dy : p->dx; }
+
+static double sig_t(const ora_problem *p, int c) { return p->sig_a[c] + p->sig_s[c]; }
+
+/* ------------------------------------------------------------------------ */
+/* Gradient: least squares over face neighbours (Eqs. Uj-Ui, LSF, LSM_mtx);  */
+/* with alsm=1 each neighbour centre x_j is replaced by the shifted point     */
+/* x'_j = x_ij + (sigma_t,j / sigma_t,i) r^R_ij (Eqs. shifted_j, new_vector,  */
+/* LSF_mdf).                                                                   */
+/* ------------------------------------------------------------------------ */
+static void gradient_cell(const ora_problem *p, int alsm, const double *U,
+                          int i, int j, double *gx, double *gy) {
+  const int c = j * p->nx + i;
+  double Mxx = 0, Mxy = 0, Myy = 0, bx = 0, by = 0;
+  for (int f = 0; f < 4; ++f) {
+    int nb = neighbour(p, i, j, f);
+    if (nb < 0) continue;
+    /* x_j - x_i */
+    double ex = NX_[f] * p->dx, ey = NY_[f] * p->dy;
+    if (alsm) {
+      /* face midpoint x_ij = x_i + (x_j - x_i)/2, r^R = x_j - x_ij */
+      double fx = 0.5 * ex, fy = 0.5 * ey;
+      double rx = ex - fx, ry = ey - fy;
+      double ratio = sig_t(p, nb) / sig_t(p, c);
+      ex = fx + ratio * rx;      /* x'_j - x_i */
+      ey = fy + ratio * ry;
+    }
+    double du = U[nb] - U[c];
+    Mxx += ex * ex; Mxy += ex * ey; Myy += ey * ey;
+    bx += ex * du;  by += ey * du;
+  }
+  if (Mxx > 0 && Myy > 0) {
+    double det = Mxx * Myy - Mxy * Mxy;
+    *gx = (bx * Myy - by * Mxy) / det;
+    *gy = (by * Mxx - bx * Mxy) / det;
+  } else if (Mxx > 0) {
+    *gx = bx / Mxx; *gy = 0.0;
+  } else if (Myy > 0) {
+    *gx = 0.0; *gy = by / Myy;
+  } else {
+    *gx = 0.0; *gy = 0.0;
+  }
+}
+
+void ora_gradient(const ora_problem *p, int alsm, const double *U, double *Gx,
+                  double *Gy) {
+  for (int j = 0; j < p->ny; ++j)
+    for (int i = 0; i < p->nx; ++i)
+      gradient_cell(p, alsm, U, i, j, &Gx[j * p->nx + i], &Gy[j * p->nx + i]);
+}
+
+/* Barth-Jespersen limiter (Sec. 4.1, Eq. Ii,k and its reference). */
+static double bj_cell(const ora_problem *p, const double *U, int i, int j,
+                      double gx, double gy) {
+  const int c = j * p->nx + i;
+  double umax = U[c], umin = U[c];
+  for (int f = 0; f < 4; ++f) {
+    int nb = neighbour(p, i, j, f);
+    if (nb < 0) continue;
+    if (U[nb] > umax) umax = U[nb];
+    if (U[nb] < umin) umin = U[nb];
+  }
+  double psi = 1.0;
+  for (int f = 0; f < 4; ++f) {
+    double delta = gx * face_ox(p, f) + gy * face_oy(p, f);
+    double pf = 1.0;
+    if (delta > 0) pf = fmin(1.0, (umax - U[c]) / delta);
+    else if (delta < 0) pf = fmin(1.0, (umin - U[c]) / delta);
+    if (pf < psi) psi = pf;
+  }
+  return psi;
+}
+
+void ora_bj_limiter(const ora_problem *p, const double *U, const double *Gx,
+                    const double *Gy, double *psi) {
+  for (int j = 0; j < p->ny; ++j)
+    for (int i = 0; i < p->nx; ++i) {
+      int c = j * p->nx + i;
+      psi[c] = bj_cell(p, U, i, j, Gx[c], Gy[c]);
+    }
+}
+
+/* Linear reconstruction of a cell field at the centre of face f of cell c
+ * (Eq. Ii,k): U_c + psi_c G_c . (x_f - x_c). With order 1 the gradient is
+ * absent and the face takes the cell value. */
+typedef struct {
+  const double *U, *Gx, *Gy, *psi;
+  int order;
+} recon;
+
+static double rec_face(const ora_problem *p, const recon *R, int c, int f) {
+  if (R->order < 2) return R->U[c];
+  return R->U[c] + R->psi[c] * (R->Gx[c] * face_ox(p, f) + R->Gy[c] * face_oy(p, f));
+}
+
+/* Build gradient and limiter of one ordinate field U (scratch: Gx, Gy, psi). */
+static void build_recon(const ora_problem *p, const ora_options *o,
+                        const double *U, double *Gx, double *Gy, double *psi,
+                        recon *R) {
+  R->U = U; R->Gx = Gx; R->Gy = Gy; R->psi = psi; R->order = o->order;
+  if (o->order < 2) return;
+  ora_gradient(p, o->alsm, U, Gx, Gy);
+  if (o->limiter) ora_bj_limiter(p, U, Gx, Gy, psi);
+  else for (int c = 0; c < p->nx * p->ny; ++c) psi[c] = 1.0;
+}
+
+/* Face value of ordinate k on face f of cell (i,j), upwinded (Eqs. Iij,
+ * micro_bc with alpha_w = 0). */
+static double face_value(const ora_problem *p, const recon *R, int i, int j,
+                         int f, int k) {
+  const int c = j * p->nx + i;
+  const double on = p->mu[k] * NX_[f] + p->eta[k] * NY_[f];
+  int nb = neighbour(p, i, j, f);
+  if (on >= 0) return rec_face(p, R, c, f);
+  if (nb >= 0) return rec_face(p, R, nb, OPP_[f]);
+  return p->bnd_in ? p->bnd_in[(size_t)bface(p, i, j, f) * p->K + k] : 0.0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Moments (Sec. 4.1 quadrature; Eqs. def_rho, def_F).                        */
+/* ------------------------------------------------------------------------ */
+static void moments(const ora_problem *p, const double *I, double *phi,
+                    double *Fx, double *Fy) {
+  const int N = p->nx * p->ny, K = p->K;
+#pragma omp parallel for schedule(static)
+  for (int c = 0; c < N; ++c) {
+    double s0 = 0, sx = 0, sy = 0;
+    for (int k = 0; k < K; ++k) {
+      double v = p->w[k] * I[(size_t)c * K + k];
+      s0 += v; sx += p->mu[k] * v; sy += p->eta[k] * v;
+    }
+    phi[c] = s0;
+    if (Fx) Fx[c] = sx;
+    if (Fy) Fy[c] = sy;
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Mesoscopic residual (Eq. RTE_d_res, steady):                               */
+/*   r = (sigma_s phi + q)/(4 pi) - sigma_t I - (1/V) sum_f (Omega.n_f) A_f I_f */
+/* ------------------------------------------------------------------------ */
+void ora_residual(const ora_problem *p, const ora_options *o, const double *I,
+                  double *r) {
+  const int N = p->nx * p->ny, K = p->K;
+  double *phi = (double *)malloc(sizeof(double) * N);
+  moments(p, I, phi, NULL, NULL);
+#pragma omp parallel
+  {
+    double *U = (double *)malloc(sizeof(double) * N * 4);
+    double *Gx = U + N, *Gy = U + 2 * N, *psi = U + 3 * N;
+#pragma omp for schedule(dynamic, 1)
+    for (int k = 0; k < K; ++k) {
+      for (int c = 0; c < N; ++c) U[c] = I[(size_t)c * K + k];
+      recon R;
+      build_recon(p, o, U, Gx, Gy, psi, &R);
+      for (int j = 0; j < p->ny; ++j)
+        for (int i = 0; i < p->nx; ++i) {
+          const int c = j * p->nx + i;
+          double div = 0.0;
+          for (int f = 0; f < 4; ++f) {
+            double on = p->mu[k] * NX_[f] + p->eta[k] * NY_[f];
+            div += on * area_over_vol(p, f) * face_value(p, &R, i, j, f, k);
+          }
+          r[(size_t)c * K + k] = (p->sig_s[c] * phi[c] + p->q[c]) / FOUR_PI
+                                 - sig_t(p, c) * U[c] - div;
+        }
+    }
+    free(U);
+  }
+  free(phi);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Increment solve (Eqs. RTE_d_increment, delta_Iij, RTE_d_mtx, elem_mtx):    */
+/*   d_ii dI_i + sum_{inflow faces} (Omega.A_ij / V_i) dI_j = r_i,            */
+/*   d_ii = sigma_t + sum_{outflow faces} Omega.A_ij / V_i,                   */
+/* first-order upwind increments, zero increments on inflow boundary faces.   */
+/* Cells are visited in upwind order, which makes the solve exact.            */
+/* ------------------------------------------------------------------------ */
+void ora_sweep(const ora_problem *p, const double *r, double *dI) {
+  const int nx = p->nx, ny = p->ny, K = p->K;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int k = 0; k < K; ++k) {
+    const int i0 = p->mu[k] >= 0 ? 0 : nx - 1, di = p->mu[k] >= 0 ? 1 : -1;
+    const int j0 = p->eta[k] >= 0 ? 0 : ny - 1, dj = p->eta[k] >= 0 ? 1 : -1;
+    for (int jj = 0, j = j0; jj < ny; ++jj, j += dj)
+      for (int ii = 0, i = i0; ii < nx; ++ii, i += di) {
+        const int c = j * nx + i;
+        double d = sig_t(p, c), rhs = r[(size_t)c * K + k];
+        for (int f = 0; f < 4; ++f) {
+          double on = p->mu[k] * NX_[f] + p->eta[k] * NY_[f];
+          if (on > 0) {
+            d += on * area_over_vol(p, f);
+          } else if (on < 0) {
+            int nb = neighbour(p, i, j, f);
+            if (nb >= 0) rhs -= on * area_over_vol(p, f) * dI[(size_t)nb * K + k];
+          }
+        }
+        dI[(size_t)c * K + k] = rhs / d;
+      }
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Synthetic-equation coefficients.                                           */
+/* Gamma_ij = -((sig_i r^L - sig_j r^R) . n) / (3 |sig_i r^L - sig_j r^R|^2)  */
+/* (Eq. Gamma_ij_com2), r^L = x_i - x_ij, r^R = x_j - x_ij.                   */
+/* kappa_iw = (x_iw - x_i).n / (3 sig_i |x_iw - x_i|^2) + 1/4                  */
+/* (normal part of Eq. macro_bc_delta_flux with Eq. macro_bc_delta_flux2).    */
+/* ------------------------------------------------------------------------ */
+static double gamma_face(const ora_problem *p, int c, int nb, int f) {
+  double rLx = -face_ox(p, f), rLy = -face_oy(p, f);       /* x_i - x_ij */
+  double rRx = face_ox(p, f), rRy = face_oy(p, f);         /* x_j - x_ij */
+  double vx = sig_t(p, c) * rLx - sig_t(p, nb) * rRx;
+  double vy = sig_t(p, c) * rLy - sig_t(p, nb) * rRy;
+  return -(vx * NX_[f] + vy * NY_[f]) / (3.0 * (vx * vx + vy * vy));
+}
+
+static double kappa_face(const ora_problem *p, int c, int f) {
+  double ox = face_ox(p, f), oy = face_oy(p, f);
+  return (ox * NX_[f] + oy * NY_[f]) / (3.0 * sig_t(p, c) * (ox * ox + oy * oy)) + 0.25;
+}
+
+void ora_face_coeffs(const ora_problem *p, double *gam_x, double *gam_y,
+                     double *kappa) {
+  const int nx = p->nx, ny = p->ny;
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i + 1 < nx; ++i)
+      gam_x[j * (nx - 1) + i] = gamma_face(p, j * nx + i, j * nx + i + 1, 0);
+  for (int j = 0; j + 1 < ny; ++j)
+    for (int i = 0; i < nx; ++i)
+      gam_y[j * nx + i] = gamma_face(p, j * nx + i, (j + 1) * nx + i, 2);
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i)
+      for (int f = 0; f < 4; ++f)
+        if (neighbour(p, i, j, f) < 0)
+          kappa[bface(p, i, j, f)] = kappa_face(p, j * nx + i, f);
+}
+
+/* D1 x (Eqs. MSE_d_mtx1, elem_mtx_M, steady, multiplied by V):               */
+/*   V sig_a x_c + sum_int A Gamma (x_c - x_nb) + sum_bnd A kappa x_c.         */
+void ora_synthetic_apply(const ora_problem *p, const double *x, double *y) {
+  const int nx = p->nx, ny = p->ny;
+  const double V = p->dx * p->dy;
+#pragma omp parallel for schedule(static)
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      const int c = j * nx + i;
+      double s = V * p->sig_a[c] * x[c];
+      for (int f = 0; f < 4; ++f) {
+        int nb = neighbour(p, i, j, f);
+        if (nb >= 0) s += face_area(p, f) * gamma_face(p, c, nb, f) * (x[c] - x[nb]);
+        else s += face_area(p, f) * kappa_face(p, c, f) * x[c];
+      }
+      y[c] = s;
+    }
+}
+
+/* Dense-band entry of D1: row c, column c - d (d = 0, 1 or nx). */
+typedef struct {
+  int N, bw;          /* bandwidth */
+  double *L;          /* band of L: L[c*(bw+1) + d] = L(c, c-d) */
+  int use_cg;
+} synth_factor;
+
+#define BAND_LIMIT (1L << 28)   /* doubles; above this CG is used */
+
+static int synth_factor_build(const ora_problem *p, synth_factor *S) {
+  const int nx = p->nx, ny = p->ny, N = nx * ny;
+  const int bw = ny > 1 ? nx : 1;
+  S->N = N; S->bw = bw; S->L = NULL;
+  S->use_cg = ((long)N * (bw + 1) > BAND_LIMIT);
+  if (S->use_cg) return 0;
+  double *L = (double *)calloc((size_t)N * (bw + 1), sizeof(double));
+  if (!L) return -3;
+  const double V = p->dx * p->dy;
+  /* assemble the lower band of D1 */
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      const int c = j * nx + i;
+      double diag = V * p->sig_a[c];
+      for (int f = 0; f < 4; ++f) {
+        int nb = neighbour(p, i, j, f);
+        if (nb >= 0) {
+          double a = face_area(p, f) * gamma_face(p, c, nb, f);
+          diag += a;
+          if (nb < c) L[(size_t)c * (bw + 1) + (c - nb)] = -a;
+        } else {
+          diag += face_area(p, f) * kappa_face(p, c, f);
+        }
+      }
+      L[(size_t)c * (bw + 1)] = diag;
+    }
+  /* banded Cholesky, left-looking: L(i,j) = (A(i,j) - sum_k L(i,k)L(j,k))/L(j,j) */
+  const size_t ld = bw + 1;
+  for (int jc = 0; jc < N; ++jc) {
+    double s = L[(size_t)jc * ld];
+    int k0 = jc - bw > 0 ? jc - bw : 0;
+    for (int k = k0; k < jc; ++k) {
+      double v = L[(size_t)jc * ld + (jc - k)];
+      s -= v * v;
+    }
+    if (!(s > 0)) { free(L); return -1; }
+    const double djj = sqrt(s);
+    L[(size_t)jc * ld] = djj;
+    int iend = jc + bw < N - 1 ? jc + bw : N - 1;
+#pragma omp parallel for schedule(static) if (bw >= 64)
+    for (int i = jc + 1; i <= iend; ++i) {
+      double t = L[(size_t)i * ld + (i - jc)];
+      int kk0 = i - bw > 0 ? i - bw : 0;
+      for (int k = kk0; k < jc; ++k)
+        t -= L[(size_t)i * ld + (i - k)] * L[(size_t)jc * ld + (jc - k)];
+      L[(size_t)i * ld + (i - jc)] = t / djj;
+    }
+  }
+  S->L = L;
+  return 0;
+}
+
+static void synth_factor_free(synth_factor *S) { free(S->L); S->L = NULL; }
+
+static int synth_cg(const ora_problem *p, const double *b, double *x) {
+  const int N = p->nx * p->ny;
+  double *r = malloc(sizeof(double) * N), *z = malloc(sizeof(double) * N),
+         *pp = malloc(sizeof(double) * N), *Ap = malloc(sizeof(double) * N),
+         *dg = malloc(sizeof(double) * N), *e = calloc(N, sizeof(double));
+  /* Jacobi preconditioner: the diagonal of D1 */
+  for (int c = 0; c < N; ++c) e[c] = 1.0;
+  /* diag(D1) = D1 applied to unit vectors would be O(N^2); assemble directly */
+  {
+    const int nx = p->nx, ny = p->ny;
+    const double V = p->dx * p->dy;
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        const int c = j * nx + i;
+        double d = V * p->sig_a[c];
+        for (int f = 0; f < 4; ++f) {
+          int nb = neighbour(p, i, j, f);
+          d += face_area(p, f) * (nb >= 0 ? gamma_face(p, c, nb, f) : kappa_face(p, c, f));
+        }
+        dg[c] = d;
+      }
+  }
+  double bn = 0;
+  for (int c = 0; c < N; ++c) { x[c] = 0; r[c] = b[c]; bn += b[c] * b[c]; }
+  bn = sqrt(bn);
+  int ret = 1;
+  if (bn == 0) ret = 0;
+  double rz = 0;
+  for (int c = 0; c < N; ++c) { z[c] = r[c] / dg[c]; pp[c] = z[c]; rz += r[c] * z[c]; }
+  for (int it = 0; it < 200000 && ret; ++it) {
+    ora_synthetic_apply(p, pp, Ap);
+    double pAp = 0;
+    for (int c = 0; c < N; ++c) pAp += pp[c] * Ap[c];
+    double a = rz / pAp, rn = 0;
+    for (int c = 0; c < N; ++c) { x[c] += a * pp[c]; r[c] -= a * Ap[c]; rn += r[c] * r[c]; }
+    if (sqrt(rn) <= 1e-14 * bn) { ret = 0; break; }
+    double rz2 = 0;
+    for (int c = 0; c < N; ++c) { z[c] = r[c] / dg[c]; rz2 += r[c] * z[c]; }
+    double bb = rz2 / rz;
+    rz = rz2;
+    for (int c = 0; c < N; ++c) pp[c] = z[c] + bb * pp[c];
+  }
+  free(r); free(z); free(pp); free(Ap); free(dg); free(e);
+  return ret == 0 ? 0 : -2;
+}
+
+static int synth_solve_with(const ora_problem *p, const synth_factor *S,
+                            const double *b, double *x) {
+  if (S->use_cg) return synth_cg(p, b, x);
+  const int N = S->N, bw = S->bw;
+  const size_t ld = bw + 1;
+  const double *L = S->L;
+  /* L y = b */
+  for (int i = 0; i < N; ++i) {
+    double t = b[i];
+    int k0 = i - bw > 0 ? i - bw : 0;
+    for (int k = k0; k < i; ++k) t -= L[(size_t)i * ld + (i - k)] * x[k];
+    x[i] = t / L[(size_t)i * ld];
+  }
+  /* L^T x = y */
+  for (int i = N - 1; i >= 0; --i) {
+    double t = x[i];
+    int k1 = i + bw < N - 1 ? i + bw : N - 1;
+    for (int k = i + 1; k <= k1; ++k) t -= L[(size_t)k * ld + (k - i)] * x[k];
+    x[i] = t / L[(size_t)i * ld];
+  }
+  return 0;
+}
+
+int ora_synthetic_solve(const ora_problem *p, const double *b, double *x) {
+  synth_factor S;
+  int e = synth_factor_build(p, &S);
+  if (e) return e;
+  e = synth_solve_with(p, &S, b, x);
+  synth_factor_free(&S);
+  return e;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Transport face fluxes F_T,f . n_f = sum_k w_k (Omega_k . n_f) I_f,k from   */
+/* an intensity field (boundary faces: the initial synthetic boundary flux,   */
+/* Sec. 4.4; interior faces: only for the transport-face variant).            */
+/* bflux[2(nx+ny)] uses the outward normal; fx[(nx-1)*ny] uses +x, fy uses +y. */
+/* ------------------------------------------------------------------------ */
+static void transport_face_fluxes(const ora_problem *p, const ora_options *o,
+                                  const double *I, double *bflux, double *fx,
+                                  double *fy) {
+  const int nx = p->nx, ny = p->ny, N = nx * ny, K = p->K;
+  const int nb_f = 2 * (nx + ny);
+  const int nfx = (nx - 1) * ny, nfy = nx * (ny - 1);
+  double *cb = calloc((size_t)nb_f * K, sizeof(double));
+  double *cx = fx ? calloc((size_t)(nfx > 0 ? nfx : 1) * K, sizeof(double)) : NULL;
+  double *cy = fy ? calloc((size_t)(nfy > 0 ? nfy : 1) * K, sizeof(double)) : NULL;
+#pragma omp parallel
+  {
+    double *U = (double *)malloc(sizeof(double) * N * 4);
+    double *Gx = U + N, *Gy = U + 2 * N, *psi = U + 3 * N;
+#pragma omp for schedule(dynamic, 1)
+    for (int k = 0; k < K; ++k) {
+      for (int c = 0; c < N; ++c) U[c] = I[(size_t)c * K + k];
+      recon R;
+      build_recon(p, o, U, Gx, Gy, psi, &R);
+      for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i)
+          for (int f = 0; f < 4; ++f) {
+            double on = p->mu[k] * NX_[f] + p->eta[k] * NY_[f];
+            if (neighbour(p, i, j, f) < 0) {
+              cb[(size_t)bface(p, i, j, f) * K + k] =
+                  p->w[k] * on * face_value(p, &R, i, j, f, k);
+            } else if (f == 0 && cx) {
+              cx[(size_t)(j * (nx - 1) + i) * K + k] = p->w[k] * on * face_value(p, &R, i, j, f, k);
+            } else if (f == 2 && cy) {
+              cy[(size_t)(j * nx + i) * K + k] = p->w[k] * on * face_value(p, &R, i, j, f, k);
+            }
+          }
+    }
+    free(U);
+  }
+  for (int b = 0; b < nb_f; ++b) {
+    double s = 0;
+    for (int k = 0; k < K; ++k) s += cb[(size_t)b * K + k];
+    bflux[b] = s;
+  }
+  if (cx) for (int f = 0; f < nfx; ++f) {
+    double s = 0;
+    for (int k = 0; k < K; ++k) s += cx[(size_t)f * K + k];
+    fx[f] = s;
+  }
+  if (cy) for (int f = 0; f < nfy; ++f) {
+    double s = 0;
+    for (int k = 0; k < K; ++k) s += cy[(size_t)f * K + k];
+    fy[f] = s;
+  }
+  free(cb); free(cx); free(cy);
+}
+
+/* ------------------------------------------------------------------------ */
+/* One outer iteration.                                                       */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  const ora_problem *p;
+  const ora_options *o;
+  synth_factor S;
+  int have_S;
+} ora_ctx;
+
+static int iterate_ctx(ora_ctx *X, const double *I_in, double *I_out,
+                       double *phi_out) {
+  const ora_problem *p = X->p;
+  const ora_options *o = X->o;
+  const int nx = p->nx, ny = p->ny, N = nx * ny, K = p->K;
+  const size_t NK = (size_t)N * K;
+  double *r = malloc(sizeof(double) * NK);
+  double *dI = malloc(sizeof(double) * NK);
+  if (!r || !dI) { free(r); free(dI); return -3; }
+
+  /* residual and exact increment solve */
+  ora_residual(p, o, I_in, r);
+  ora_sweep(p, r, dI);
+  free(r);
+  /* I^{m+1/2} = I^m + dI */
+#pragma omp parallel for schedule(static)
+  for (size_t t = 0; t < NK; ++t) I_out[t] = I_in[t] + dI[t];
+  free(dI);
+
+  double *ph = malloc(sizeof(double) * N * 3);
+  double *Fxh = ph + N, *Fyh = ph + 2 * N;
+  moments(p, I_out, ph, Fxh, Fyh);
+
+  if (o->method == 0) {
+    /* SI (Eq. SI_update) */
+    memcpy(phi_out, ph, sizeof(double) * N);
+    free(ph);
+    return 0;
+  }
+
+  /* GSIS: boundary (and, for the transport-face variant, interior) fluxes */
+  const int nb_f = 2 * (nx + ny);
+  double *bflux = malloc(sizeof(double) * nb_f);
+  double *fx = NULL, *fy = NULL;
+  if (o->hot_face == 1) {
+    fx = malloc(sizeof(double) * ((nx - 1) * ny + 1));
+    fy = malloc(sizeof(double) * (nx * (ny - 1) + 1));
+  }
+  transport_face_fluxes(p, o, I_out, bflux, fx, fy);
+
+  /* HoT_c = F_c + grad(phi)_c / (3 sigma_t) (Eq. GSIS_HoT), ALSM gradient */
+  double *gpx = malloc(sizeof(double) * N * 2), *gpy = gpx + N;
+  ora_gradient(p, o->alsm, ph, gpx, gpy);
+  double *hx = malloc(sizeof(double) * N * 2), *hy = hx + N;
+  for (int c = 0; c < N; ++c) {
+    hx[c] = Fxh[c] + gpx[c] / (3.0 * sig_t(p, c));
+    hy[c] = Fyh[c] + gpy[c] / (3.0 * sig_t(p, c));
+  }
+  /* right-hand side: V q - sum_int A h_f - sum_bnd A (F_T.n - kappa phi_half) */
+  const double V = p->dx * p->dy;
+  double *b = malloc(sizeof(double) * N);
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      const int c = j * nx + i;
+      double s = V * p->q[c];
+      for (int f = 0; f < 4; ++f) {
+        int nb = neighbour(p, i, j, f);
+        double A = face_area(p, f);
+        if (nb >= 0) {
+          double h;
+          if (o->hot_face == 0) {
+            /* central average of cell HoT (Eq. Fij_d, second term) */
+            h = 0.5 * ((hx[c] + hx[nb]) * NX_[f] + (hy[c] + hy[nb]) * NY_[f]);
+          } else {
+            /* transport face flux minus the implicit diffusion part */
+            double ft;
+            if (f == 0) ft = fx[j * (nx - 1) + i];
+            else if (f == 1) ft = -fx[j * (nx - 1) + i - 1];
+            else if (f == 2) ft = fy[j * nx + i];
+            else ft = -fy[(j - 1) * nx + i];
+            h = ft - gamma_face(p, c, nb, f) * (ph[c] - ph[nb]);
+          }
+          s -= A * h;
+        } else {
+          s -= A * (bflux[bface(p, i, j, f)] - kappa_face(p, c, f) * ph[c]);
+        }
+      }
+      b[c] = s;
+    }
+
+  /* synthetic solve D1 phi' = b */
+  int e = 0;
+  if (!X->have_S) {
+    e = synth_factor_build(p, &X->S);
+    if (e == 0) X->have_S = 1;
+  }
+  if (e == 0) e = synth_solve_with(p, &X->S, b, phi_out);
+
+  /* GSIS correction I^{m+1} = I^{m+1/2} + (phi' - phi_half)/(4 pi)
+   * (Eq. GSIS_update) */
+  if (e == 0) {
+#pragma omp parallel for schedule(static)
+    for (int c = 0; c < N; ++c) {
+      double dl = (phi_out[c] - ph[c]) / FOUR_PI;
+      for (int k = 0; k < K; ++k) I_out[(size_t)c * K + k] += dl;
+    }
+  }
+  free(b); free(hx); free(gpx); free(bflux); free(fx); free(fy); free(ph);
+  return e;
+}
+
+int ora_iterate(const ora_problem *p, const ora_options *o, const double *I_in,
+                double *I_out, double *phi_out) {
+  ora_ctx X = {p, o, {0, 0, NULL, 0}, 0};
+  int e = iterate_ctx(&X, I_in, I_out, phi_out);
+  if (X.have_S) synth_factor_free(&X.S);
+  return e;
+}
+
+/* Err(W) = sqrt( sum V (W^m - W^{m-1})^2 / sum V (W^m)^2 ) (Eq. Err_W). */
+static double err_w(const double *Wn, const double *Wo, int N, double V) {
+  double num = 0, den = 0;
+  for (int c = 0; c < N; ++c) {
+    double d = Wn[c] - Wo[c];
+    num += V * d * d;
+    den += V * Wn[c] * Wn[c];
+  }
+  if (den == 0) return num == 0 ? 0.0 : INFINITY;
+  return sqrt(num / den);
+}
+
+int ora_solve(const ora_problem *p, const ora_options *o, const double *I0,
+              double *phi, double *Fx, double *Fy, double *err_hist,
+              int *n_iter, double *final_err, double *I_final) {
+  const int N = p->nx * p->ny, K = p->K;
+  const size_t NK = (size_t)N * K;
+  const double V = p->dx * p->dy;
+  double *Ia = malloc(sizeof(double) * NK), *Ib = malloc(sizeof(double) * NK);
+  double *phi_old = malloc(sizeof(double) * N), *phi_new = malloc(sizeof(double) * N);
+  if (!Ia || !Ib || !phi_old || !phi_new) return -3;
+  if (I0) memcpy(Ia, I0, sizeof(double) * NK);
+  else memset(Ia, 0, sizeof(double) * NK);
+
+  ora_ctx X = {p, o, {0, 0, NULL, 0}, 0};
+  int status = 1, m = 0;
+  double err = INFINITY;
+  for (m = 0; m < o->max_iter; ++m) {
+    moments(p, Ia, phi_old, NULL, NULL);          /* phi^m */
+    int e = iterate_ctx(&X, Ia, Ib, phi_new);     /* phi^{m+1} */
+    if (e) { status = e; break; }
+    err = err_w(phi_new, phi_old, N, V);
+    if (err_hist) err_hist[m] = err;
+    double *t = Ia; Ia = Ib; Ib = t;
+    if (!isfinite(err)) { status = -2; ++m; break; }
+    if (err < o->tol) { status = 0; ++m; break; }
+  }
+  if (n_iter) *n_iter = m;
+  if (final_err) *final_err = err;
+  /* outputs: phi^{final} and F of the final intensity */
+  memcpy(phi, phi_new, sizeof(double) * N);
+  {
+    double *tmp = malloc(sizeof(double) * N);
+    moments(p, Ia, tmp, Fx, Fy);
+    free(tmp);
+  }
+  if (I_final) memcpy(I_final, Ia, sizeof(double) * NK);
+  if (X.have_S) synth_factor_free(&X.S);
+  free(Ia); free(Ib); free(phi_old); free(phi_new);
+  return status;
+}

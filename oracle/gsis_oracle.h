@@ -1,0 +1,90 @@
+/*
+ * gsis_oracle.h -- plain FP64 CPU oracle of the steady gray GSIS / SI method.
+ *
+ * TEST INFRASTRUCTURE ONLY. Nothing in the product path may include, link or
+ * call this file; only tests, the smoke check and the CPU-baseline leg of the
+ * benchmark do. It shares no code with the HIP library.
+ *
+ * Problem (Sec. 2.1 Eq. RTE_g, steady, no material coupling; Sec. 4.1):
+ *   Omega . grad I + sigma_t I = (sigma_s phi + q) / (4 pi),
+ *   phi = sum_k w_k I_k (zeroth moment, Eq. def_rho), F = sum_k w_k Omega_k I_k
+ *   (Eq. def_F), on a uniform nx x ny Cartesian grid, cell c = j*nx + i.
+ *
+ * Boundary faces are numbered W side (j = 0..ny-1), E side (ny + j),
+ * S side (2ny + i), N side (2ny + nx + i); bnd_in[f*K + k] is the incoming
+ * intensity (Eq. micro_bc with alpha_w = 0), NULL means vacuum.
+ */
+#ifndef GSIS_ORACLE_H
+#define GSIS_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+  int nx, ny;
+  double dx, dy;
+  int K;
+  const double *mu, *eta, *w;            /* [K] */
+  const double *sig_a, *sig_s, *q;       /* [nx*ny] */
+  const double *bnd_in;                  /* [2(nx+ny)][K] or NULL */
+} ora_problem;
+
+typedef struct {
+  int method;     /* 0 = source iteration, 1 = GSIS */
+  int order;      /* 1 = first-order upwind, 2 = second-order upwind */
+  int limiter;    /* Barth-Jespersen limiter on/off */
+  int alsm;       /* 1 = adaptive least squares (shifted points), 0 = plain LSQ */
+  int hot_face;   /* 0 = central average of cell HoT, 1 = transport face flux */
+  double tol;     /* stop when Err(phi) < tol */
+  int max_iter;
+} ora_options;
+
+/* ALSM / LSQ cell gradient of a cell field U[nx*ny] (Sec. 5, Eqs. LSF,
+ * LSM_mtx, shifted_j, new_vector, LSF_mdf). */
+void ora_gradient(const ora_problem *p, int alsm, const double *U,
+                  double *Gx, double *Gy);
+
+/* Barth-Jespersen limiter value per cell (Sec. 4.1 Eq. Ii,k). */
+void ora_bj_limiter(const ora_problem *p, const double *U, const double *Gx,
+                    const double *Gy, double *psi);
+
+/* Synthetic-equation face coefficients: Gamma on interior x faces
+ * [(nx-1)*ny] (face right of cell (i,j) at index j*(nx-1)+i) and y faces
+ * [nx*(ny-1)] (face above (i,j) at j*nx+i) (Eq. Gamma_ij_com2); kappa per
+ * boundary face [2(nx+ny)] (Eqs. macro_bc_delta_flux, macro_bc_delta_flux2). */
+void ora_face_coeffs(const ora_problem *p, double *gam_x, double *gam_y,
+                     double *kappa);
+
+/* Mesoscopic residual r[c*K+k] of I[c*K+k] (Eq. RTE_d_res, steady). */
+void ora_residual(const ora_problem *p, const ora_options *o, const double *I,
+                  double *r);
+
+/* Exact first-order-upwind increment solve per ordinate (Eqs.
+ * RTE_d_increment, delta_Iij, RTE_d_mtx, elem_mtx, steady). */
+void ora_sweep(const ora_problem *p, const double *r, double *dI);
+
+/* One outer iteration: I_in -> I_out (Eqs. SI_update or GSIS_update).
+ * phi_out receives phi^{m+1}. Returns 0 on success. */
+int ora_iterate(const ora_problem *p, const ora_options *o, const double *I_in,
+                double *I_out, double *phi_out);
+
+/* Full solve from I0 (NULL = 0). Outputs phi, Fx, Fy [nx*ny]; err_hist
+ * [max_iter] (may be NULL); I_final [nx*ny*K] (may be NULL).
+ * Returns 0 if converged, 1 if max_iter was reached, <0 on error. */
+int ora_solve(const ora_problem *p, const ora_options *o, const double *I0,
+              double *phi, double *Fx, double *Fy, double *err_hist,
+              int *n_iter, double *final_err, double *I_final);
+
+/* Solve the synthetic system D1 x = b exactly (banded Cholesky) or, above a
+ * size limit, by CG to a relative residual of 1e-14 (Eqs. MSE_d_mtx1,
+ * elem_mtx_M, steady). Exposed for tests. */
+int ora_synthetic_solve(const ora_problem *p, const double *b, double *x);
+
+/* Apply D1 (for tests). */
+void ora_synthetic_apply(const ora_problem *p, const double *x, double *y);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
