@@ -1,0 +1,171 @@
+/*
+ * gsis.h -- C-ABI of the MI355X (gfx950) steady gray GSIS / source-iteration
+ * solver library (libgsis.so).
+ *
+ * Problem (Sec. 2.1 Eq. RTE_g without the time derivative and the material
+ * equation; Sec. 4.1 Eq. RTE_d with dt -> infinity):
+ *     Omega . grad I + sigma_t I = (sigma_s phi + q) / (4 pi),
+ *     phi = sum_k w_k I_k (Eq. def_rho),  F = sum_k w_k Omega_k I_k (Eq. def_F),
+ * discretised by the cell-centred finite-volume scheme of Sec. 4.1
+ * (second-order upwind faces from an adaptive least-squares gradient, Sec. 5,
+ * and an optional Barth-Jespersen limiter) on a uniform Cartesian grid, and
+ * solved by source iteration (Eq. SI_update) or by GSIS (Eqs. GSIS_HoT,
+ * GSIS_dse, GSIS_update) with the synthetic equation of Sec. 4.2 solved on
+ * the GPU by conjugate gradients preconditioned with geometric multigrid.
+ * Convergence is Err(phi) of Eq. Err_W.
+ *
+ * Conventions shared by every call:
+ *  - cell c = j*nx + i (x fastest); cell (i,j) covers [i*dx,(i+1)*dx] x
+ *    [j*dy,(j+1)*dy];
+ *  - boundary faces are numbered W side (j = 0..ny-1), E side (ny + j),
+ *    S side (2*ny + i), N side (2*ny + nx + i);
+ *  - every floating-point array is IEEE double;
+ *  - the caller owns every buffer it passes; the library keeps no caller
+ *    pointer after a call returns (plans copy what they need);
+ *  - a context, and every plan made from it, must not be used by two host
+ *    threads at once.
+ *
+ * Errors: every call returns a gsis_status. On GSIS_E_* the call has no
+ * effect on its outputs and gsis_last_error() names the first offending
+ * argument (field and index) or the HIP error. GSIS_NOT_CONVERGED and
+ * GSIS_DIVERGED still write the last iterate and the full history.
+ */
+#ifndef GSIS_H
+#define GSIS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GSIS_OK = 0,
+  GSIS_NOT_CONVERGED = 1,   /* max_iter reached with Err >= tol */
+  GSIS_DIVERGED = 2,        /* Err became non-finite */
+  GSIS_E_INVALID_ARG = -1,  /* argument check failed; see gsis_last_error */
+  GSIS_E_DEVICE = -2,       /* a HIP call failed */
+  GSIS_E_OOM = -3,          /* device or host allocation failed */
+  GSIS_E_UNSUPPORTED = -4   /* option combination not implemented */
+} gsis_status;
+
+/* Opaque handles. A context binds one GPU; a plan holds one problem's
+ * device state (angular intensities, coefficients, multigrid hierarchy). */
+typedef struct gsis_ctx gsis_ctx;
+typedef struct gsis_plan gsis_plan;
+
+/* Create a context on HIP device `device` (ordinal). */
+gsis_status gsis_ctx_create(int32_t device, gsis_ctx **out);
+/* Destroy a context (NULL is a no-op). Plans made from it must be destroyed
+ * first. */
+void gsis_ctx_destroy(gsis_ctx *ctx);
+/* Message of the last failed call on ctx (or of the last failed
+ * gsis_ctx_create when ctx is NULL). Valid until the next call on ctx. */
+const char *gsis_last_error(const gsis_ctx *ctx);
+
+/* Problem statement (Sec. 4.1, Sec. 4.4). */
+typedef struct {
+  int32_t nx, ny;          /* cells per direction, >= 1 */
+  double dx, dy;           /* cell sizes, > 0 */
+  int32_t K;               /* number of ordinates, >= 1 */
+  const double *mu;        /* [K] x direction cosine of Omega_k */
+  const double *eta;       /* [K] y direction cosine; mu^2 + eta^2 <= 1 */
+  const double *w;         /* [K] quadrature weights, sum = 4 pi (1e-12 rel.) */
+  const double *sigma_a;   /* [nx*ny] absorption cross section, >= 0 */
+  const double *sigma_s;   /* [nx*ny] scattering cross section, >= 0;
+                              sigma_a + sigma_s > 0 in every cell */
+  const double *q;         /* [nx*ny] isotropic volumetric source integrated
+                              over the sphere (the transport source is
+                              q/(4 pi) per steradian) */
+  const double *bnd_in;    /* [2*(nx+ny)][K] incoming intensity per boundary
+                              face and ordinate (Eq. micro_bc, no
+                              reflection); entries with Omega_k . n_out >= 0
+                              are ignored; NULL = vacuum */
+} gsis_problem;
+
+enum { GSIS_SI = 0, GSIS_GSIS = 1 };
+enum { GSIS_FP64 = 0, GSIS_FP32_MIXED = 1 };
+enum { GSIS_HOT_CENTRAL = 0, GSIS_HOT_TRANSPORT = 1 };
+
+typedef struct {
+  int32_t method;        /* GSIS_SI or GSIS_GSIS (default) */
+  int32_t precision;     /* GSIS_FP64 (default) or GSIS_FP32_MIXED: FP32
+                            intensities, sweep and moment sums; FP64
+                            synthetic solve, update and Err */
+  int32_t order;         /* 1 = first-order upwind, 2 = second order (default) */
+  int32_t limiter;       /* Barth-Jespersen limiter on (1, default) or off */
+  int32_t alsm;          /* 1 = adaptive least squares (Sec. 5.2, default),
+                            0 = plain least squares (Sec. 5.1) */
+  int32_t hot_face;      /* GSIS_HOT_CENTRAL (default): face average of the
+                            cell higher-order terms (Eq. Fij_d);
+                            GSIS_HOT_TRANSPORT: transport face flux minus the
+                            compact diffusion flux */
+  double tol;            /* stop when Err(phi) < tol (Eq. Err_W); default 1e-6 */
+  int32_t max_iter;      /* outer iteration cap, >= 1; default 1000 */
+  double synth_rtol;     /* synthetic CG stops at ||r|| <= synth_rtol ||r0||
+                            (r0: residual of the warm start, the previous
+                            phi) or at ||r|| <= 1e-14 ||b||; default 1e-4 */
+  int32_t synth_max_iter;/* CG iteration cap per outer iteration; default 50 */
+  const double *I0;      /* optional warm start [nx*ny][K] (cell-major, the
+                            caller's ordinate order); NULL = zero */
+  void *stream;          /* hipStream_t to run on; NULL = default stream */
+  int32_t device_ptrs;   /* 1: every array in gsis_problem, I0 and
+                            gsis_result is device memory; 0: host memory */
+  int32_t profile;       /* 1: record HIP events around each phase so that
+                            gsis_plan_phase_times() can report them */
+} gsis_options;
+
+/* Fill *o with the defaults listed above. */
+gsis_status gsis_options_default(gsis_options *o);
+
+typedef struct {
+  double *phi;           /* [nx*ny] out: phi at the last iterate */
+  double *Fx, *Fy;       /* [nx*ny] out: radiative flux of the last iterate */
+  double *err_hist;      /* [max_iter] out: Err per iteration (may be NULL) */
+  int32_t n_iter;        /* out: iterations performed */
+  double final_err;      /* out: Err of the last iteration */
+} gsis_result;
+
+/* One-shot solve: plan, iterate until Err < tol or max_iter, read, destroy. */
+gsis_status gsis_solve(gsis_ctx *ctx, const gsis_problem *p,
+                       const gsis_options *o, gsis_result *r);
+
+/* Plans: set up once, then enqueue iterations. */
+gsis_status gsis_plan_create(gsis_ctx *ctx, const gsis_problem *p,
+                             const gsis_options *o, gsis_plan **out);
+void gsis_plan_destroy(gsis_plan *plan);
+/* Enqueue n more outer iterations on the plan's stream and return without
+ * waiting. Iterations after convergence (Err < tol) or after max_iter do no
+ * work, so the iterate stops exactly where a synchronous loop would. */
+gsis_status gsis_plan_iterate(gsis_plan *plan, int32_t n);
+/* Wait for the plan's stream, then report progress: iterations done and
+ * whether Err < tol was reached (converged = 1) or Err became non-finite
+ * (converged = -1). */
+gsis_status gsis_plan_status(gsis_plan *plan, int32_t *n_iter,
+                             int32_t *converged, double *last_err);
+/* Wait for the plan's stream and copy phi, F and the history into r (host or
+ * device pointers as the plan's device_ptrs says). */
+gsis_status gsis_plan_read(gsis_plan *plan, gsis_result *r);
+/* Reset the iterate to the warm start (or zero) and the history. */
+gsis_status gsis_plan_reset(gsis_plan *plan);
+
+enum {
+  GSIS_PHASE_SWEEP = 0,    /* transport residual + exact sweep + moments */
+  GSIS_PHASE_HOT = 1,      /* boundary fluxes, HoT, synthetic right-hand side */
+  GSIS_PHASE_SYNTH = 2,    /* synthetic CG + multigrid solve */
+  GSIS_PHASE_UPDATE = 3,   /* correction and Err */
+  GSIS_NUM_PHASES = 4
+};
+/* Wait for the plan's stream; ms[GSIS_NUM_PHASES] receives the summed
+ * duration of each phase over all profiled iterations (HIP events on the
+ * plan's stream), *n_iter the number of profiled iterations. Needs
+ * options.profile = 1. Clears the accumulated samples. */
+gsis_status gsis_plan_phase_times(gsis_plan *plan, double *ms, int32_t *n_iter);
+
+/* Library build string (compiler, target, options). */
+const char *gsis_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GSIS_H */

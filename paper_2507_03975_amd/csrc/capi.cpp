@@ -1,0 +1,666 @@
+// capi.cpp -- C-ABI of libgsis.so: argument checks, plan set-up (ordinate
+// regrouping, least-squares / synthetic coefficients, multigrid hierarchy)
+// and the outer-iteration driver. Every arithmetic step of an iteration runs
+// in the HIP kernels; the host only sets up coefficients once per plan.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/gsis.h"
+#include "gsis_internal.h"
+
+using namespace gsis;
+
+struct gsis_ctx {
+  int device = 0;
+  std::string err;
+};
+
+struct gsis_plan {
+  gsis_ctx *ctx = nullptr;
+  PlanDev P;
+  hipStream_t stream = nullptr;
+  int device_ptrs = 0;
+  int profile = 0;
+  std::vector<int> perm;          // internal ordinate -> caller ordinate
+  double swmu = 0, sweta = 0;     // sum_k w_k mu_k, sum_k w_k eta_k
+  std::vector<double> I0_host;    // warm start in the internal layout (may be empty)
+  std::vector<double> phi0_host;  // phi of the warm start
+  std::vector<void *> allocs;
+  double *host_scal = nullptr;    // pinned
+  // profiling: per iteration 5 events bracketing the 4 phases
+  std::vector<hipEvent_t> events;
+  int prof_iters = 0;
+};
+
+static thread_local std::string g_create_err;
+
+static gsis_status fail(gsis_ctx *ctx, gsis_status st, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (ctx) ctx->err = buf;
+  else g_create_err = buf;
+  return st;
+}
+
+#define HIPCHK(ctx, call)                                                             \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail(ctx, GSIS_E_DEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+extern "C" {
+
+const char *gsis_version(void) {
+  return "libgsis (HIP, gfx950) FP64 wavefront sweep + CG/GMG synthetic solve";
+}
+
+gsis_status gsis_ctx_create(int32_t device, gsis_ctx **out) {
+  if (!out) return fail(nullptr, GSIS_E_INVALID_ARG, "out is NULL");
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess || n == 0)
+    return fail(nullptr, GSIS_E_DEVICE, "no HIP device: %s", hipGetErrorString(e));
+  if (device < 0 || device >= n)
+    return fail(nullptr, GSIS_E_INVALID_ARG, "device %d out of range [0,%d)", device, n);
+  e = hipSetDevice(device);
+  if (e != hipSuccess) return fail(nullptr, GSIS_E_DEVICE, "hipSetDevice: %s", hipGetErrorString(e));
+  gsis_ctx *c = new gsis_ctx;
+  c->device = device;
+  *out = c;
+  return GSIS_OK;
+}
+
+void gsis_ctx_destroy(gsis_ctx *ctx) { delete ctx; }
+
+const char *gsis_last_error(const gsis_ctx *ctx) {
+  return ctx ? ctx->err.c_str() : g_create_err.c_str();
+}
+
+gsis_status gsis_options_default(gsis_options *o) {
+  if (!o) return GSIS_E_INVALID_ARG;
+  std::memset(o, 0, sizeof *o);
+  o->method = GSIS_GSIS;
+  o->precision = GSIS_FP64;
+  o->order = 2;
+  o->limiter = 1;
+  o->alsm = 1;
+  o->hot_face = GSIS_HOT_CENTRAL;
+  o->tol = 1e-6;
+  o->max_iter = 1000;
+  o->synth_rtol = 1e-4;
+  o->synth_max_iter = 50;
+  return GSIS_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ helpers
+namespace {
+
+// Copy n doubles from caller memory (host or device) to a host vector.
+gsis_status fetch(gsis_ctx *ctx, const double *src, size_t n, int dev, std::vector<double> &dst,
+                  const char *name) {
+  if (!src) return fail(ctx, GSIS_E_INVALID_ARG, "%s is NULL", name);
+  dst.resize(n);
+  if (n == 0) return GSIS_OK;
+  if (dev) {
+    hipError_t e = hipMemcpy(dst.data(), src, n * sizeof(double), hipMemcpyDeviceToHost);
+    if (e != hipSuccess)
+      return fail(ctx, GSIS_E_DEVICE, "reading %s: %s", name, hipGetErrorString(e));
+  } else {
+    std::memcpy(dst.data(), src, n * sizeof(double));
+  }
+  return GSIS_OK;
+}
+
+gsis_status check_problem(gsis_ctx *ctx, const gsis_problem *p, const gsis_options *o,
+                          std::vector<double> &mu, std::vector<double> &eta,
+                          std::vector<double> &w, std::vector<double> &sa,
+                          std::vector<double> &ss, std::vector<double> &q,
+                          std::vector<double> &bnd) {
+  if (!p) return fail(ctx, GSIS_E_INVALID_ARG, "problem is NULL");
+  if (!o) return fail(ctx, GSIS_E_INVALID_ARG, "options is NULL");
+  if (p->nx < 1 || p->ny < 1)
+    return fail(ctx, GSIS_E_INVALID_ARG, "nx, ny must be >= 1 (got %d, %d)", p->nx, p->ny);
+  if ((long long)p->nx * p->ny > (1LL << 28))
+    return fail(ctx, GSIS_E_INVALID_ARG, "nx*ny = %lld too large", (long long)p->nx * p->ny);
+  if (!(p->dx > 0) || !(p->dy > 0) || !std::isfinite(p->dx) || !std::isfinite(p->dy))
+    return fail(ctx, GSIS_E_INVALID_ARG, "dx, dy must be finite and > 0");
+  if (p->K < 1) return fail(ctx, GSIS_E_INVALID_ARG, "K must be >= 1 (got %d)", p->K);
+  if (o->method != GSIS_SI && o->method != GSIS_GSIS)
+    return fail(ctx, GSIS_E_INVALID_ARG, "options.method must be 0 or 1");
+  if (o->precision != GSIS_FP64 && o->precision != GSIS_FP32_MIXED)
+    return fail(ctx, GSIS_E_INVALID_ARG, "options.precision must be 0 or 1");
+  if (o->order != 1 && o->order != 2)
+    return fail(ctx, GSIS_E_INVALID_ARG, "options.order must be 1 or 2");
+  if (o->hot_face != GSIS_HOT_CENTRAL && o->hot_face != GSIS_HOT_TRANSPORT)
+    return fail(ctx, GSIS_E_INVALID_ARG, "options.hot_face must be 0 or 1");
+  if (o->max_iter < 1) return fail(ctx, GSIS_E_INVALID_ARG, "options.max_iter must be >= 1");
+  if (!(o->tol >= 0) || std::isnan(o->tol))
+    return fail(ctx, GSIS_E_INVALID_ARG, "options.tol must be >= 0");
+  if (!(o->synth_rtol > 0)) return fail(ctx, GSIS_E_INVALID_ARG, "options.synth_rtol must be > 0");
+  if (o->synth_max_iter < 1)
+    return fail(ctx, GSIS_E_INVALID_ARG, "options.synth_max_iter must be >= 1");
+  const int dev = o->device_ptrs;
+  const size_t N = (size_t)p->nx * p->ny, K = p->K;
+  gsis_status st;
+  if ((st = fetch(ctx, p->mu, K, dev, mu, "mu")) || (st = fetch(ctx, p->eta, K, dev, eta, "eta")) ||
+      (st = fetch(ctx, p->w, K, dev, w, "w")) ||
+      (st = fetch(ctx, p->sigma_a, N, dev, sa, "sigma_a")) ||
+      (st = fetch(ctx, p->sigma_s, N, dev, ss, "sigma_s")) ||
+      (st = fetch(ctx, p->q, N, dev, q, "q")))
+    return st;
+  double wsum = 0;
+  for (size_t k = 0; k < K; ++k) {
+    if (!std::isfinite(mu[k]) || !std::isfinite(eta[k]) || !std::isfinite(w[k]))
+      return fail(ctx, GSIS_E_INVALID_ARG, "quadrature entry %zu is not finite", k);
+    if (mu[k] * mu[k] + eta[k] * eta[k] > 1.0 + 1e-12)
+      return fail(ctx, GSIS_E_INVALID_ARG, "mu[%zu]^2 + eta[%zu]^2 > 1", k, k);
+    if (w[k] < 0) return fail(ctx, GSIS_E_INVALID_ARG, "w[%zu] < 0", k);
+    wsum += w[k];
+  }
+  if (std::fabs(wsum - kFourPi) > 1e-12 * kFourPi)
+    return fail(ctx, GSIS_E_INVALID_ARG, "sum(w) = %.17g, expected 4*pi", wsum);
+  for (size_t c = 0; c < N; ++c) {
+    if (!std::isfinite(sa[c]) || sa[c] < 0)
+      return fail(ctx, GSIS_E_INVALID_ARG, "sigma_a[%zu] must be finite and >= 0", c);
+    if (!std::isfinite(ss[c]) || ss[c] < 0)
+      return fail(ctx, GSIS_E_INVALID_ARG, "sigma_s[%zu] must be finite and >= 0", c);
+    if (!(sa[c] + ss[c] > 0))
+      return fail(ctx, GSIS_E_INVALID_ARG, "sigma_a[%zu] + sigma_s[%zu] must be > 0", c, c);
+    if (!std::isfinite(q[c])) return fail(ctx, GSIS_E_INVALID_ARG, "q[%zu] is not finite", c);
+  }
+  const size_t nbf = 2 * ((size_t)p->nx + p->ny);
+  if (p->bnd_in) {
+    if ((st = fetch(ctx, p->bnd_in, nbf * K, dev, bnd, "bnd_in"))) return st;
+    for (size_t t = 0; t < nbf * K; ++t)
+      if (!std::isfinite(bnd[t]))
+        return fail(ctx, GSIS_E_INVALID_ARG, "bnd_in[%zu][%zu] is not finite", t / K, t % K);
+  } else {
+    bnd.assign(nbf * K, 0.0);
+  }
+  return GSIS_OK;
+}
+
+template <typename T>
+gsis_status dalloc(gsis_plan *pl, T **p, size_t n) {
+  void *v = nullptr;
+  hipError_t e = hipMalloc(&v, std::max<size_t>(n, 1) * sizeof(T));
+  if (e != hipSuccess)
+    return fail(pl->ctx, GSIS_E_OOM, "hipMalloc(%zu bytes): %s", n * sizeof(T),
+                hipGetErrorString(e));
+  pl->allocs.push_back(v);
+  *p = (T *)v;
+  return GSIS_OK;
+}
+
+template <typename T>
+gsis_status upload(gsis_plan *pl, T **p, const std::vector<T> &h) {
+  gsis_status st = dalloc(pl, p, h.size());
+  if (st) return st;
+  if (!h.empty()) HIPCHK(pl->ctx, hipMemcpy(*p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  return GSIS_OK;
+}
+
+// Dense SPD inverse by Cholesky (coarsest multigrid level, n <= a few hundred).
+bool dense_spd_inverse(int n, std::vector<double> &A) {
+  std::vector<double> L(A);
+  for (int j = 0; j < n; ++j) {
+    double s = L[(size_t)j * n + j];
+    for (int k = 0; k < j; ++k) s -= L[(size_t)j * n + k] * L[(size_t)j * n + k];
+    if (!(s > 0)) return false;
+    const double d = std::sqrt(s);
+    L[(size_t)j * n + j] = d;
+    for (int i = j + 1; i < n; ++i) {
+      double t = L[(size_t)i * n + j];
+      for (int k = 0; k < j; ++k) t -= L[(size_t)i * n + k] * L[(size_t)j * n + k];
+      L[(size_t)i * n + j] = t / d;
+    }
+  }
+  // columns of A^{-1}: solve L L^T x = e_c
+  std::vector<double> x(n);
+  for (int c = 0; c < n; ++c) {
+    for (int i = 0; i < n; ++i) {
+      double t = (i == c) ? 1.0 : 0.0;
+      for (int k = 0; k < i; ++k) t -= L[(size_t)i * n + k] * x[k];
+      x[i] = t / L[(size_t)i * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      double t = x[i];
+      for (int k = i + 1; k < n; ++k) t -= L[(size_t)k * n + i] * x[k];
+      x[i] = t / L[(size_t)i * n + i];
+    }
+    for (int i = 0; i < n; ++i) A[(size_t)i * n + c] = x[i];
+  }
+  return true;
+}
+
+struct HostLevel {
+  int nx, ny, fx = 1, fy = 1;
+  std::vector<double> diag, ax, ay;
+};
+
+}  // namespace
+
+// ------------------------------------------------------------------- plans
+extern "C" gsis_status gsis_plan_create(gsis_ctx *ctx, const gsis_problem *p,
+                                        const gsis_options *o, gsis_plan **out) {
+  if (!ctx) return fail(nullptr, GSIS_E_INVALID_ARG, "ctx is NULL");
+  if (!out) return fail(ctx, GSIS_E_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  std::vector<double> mu, eta, w, sa, ss, q, bnd;
+  gsis_status st = check_problem(ctx, p, o, mu, eta, w, sa, ss, q, bnd);
+  if (st) return st;
+  if (o->precision != GSIS_FP64)
+    return fail(ctx, GSIS_E_UNSUPPORTED, "precision FP32_MIXED is not available in this build");
+  if (o->hot_face != GSIS_HOT_CENTRAL)
+    return fail(ctx, GSIS_E_UNSUPPORTED, "hot_face TRANSPORT is not available in this build");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+
+  gsis_plan *pl = new gsis_plan;
+  pl->ctx = ctx;
+  pl->stream = (hipStream_t)o->stream;
+  pl->device_ptrs = o->device_ptrs;
+  pl->profile = o->profile;
+  PlanDev &P = pl->P;
+  const int nx = p->nx, ny = p->ny, N = nx * ny, K = p->K;
+  P.nx = nx; P.ny = ny; P.N = N; P.K = K; P.nbf = 2 * (nx + ny);
+  P.dx = p->dx; P.dy = p->dy; P.V = p->dx * p->dy;
+  P.method = o->method; P.precision = o->precision; P.order = o->order;
+  P.limiter = o->limiter ? 1 : 0; P.alsm = o->alsm ? 1 : 0; P.hot_face = o->hot_face;
+  P.tol = o->tol; P.max_iter = o->max_iter; P.synth_rtol = o->synth_rtol;
+  P.synth_max_iter = o->synth_max_iter;
+  auto bail = [&](gsis_status s) {
+    gsis_plan_destroy(pl);
+    return s;
+  };
+
+  // -- regroup ordinates by quadrant (bit 0: mu < 0, bit 1: eta < 0)
+  pl->perm.clear();
+  for (int qd = 0; qd < 4; ++qd) {
+    P.qoff[qd] = (int)pl->perm.size();
+    for (int k = 0; k < K; ++k) {
+      int qk = (mu[k] < 0 ? 1 : 0) | (eta[k] < 0 ? 2 : 0);
+      if (qk == qd) pl->perm.push_back(k);
+    }
+    P.Kq[qd] = (int)pl->perm.size() - P.qoff[qd];
+  }
+  P.qoff[4] = K;
+  std::vector<double> amu(K), aeta(K), wv(K), wmu(K), weta(K);
+  pl->swmu = pl->sweta = 0;
+  for (int kk = 0; kk < K; ++kk) {
+    const int k = pl->perm[kk];
+    amu[kk] = std::fabs(mu[k]) / p->dx;
+    aeta[kk] = std::fabs(eta[k]) / p->dy;
+    wv[kk] = w[k];
+    wmu[kk] = w[k] * mu[k];
+    weta[kk] = w[k] * eta[k];
+    pl->swmu += wmu[kk];
+    pl->sweta += weta[kk];
+  }
+
+  // -- per-cell coefficients
+  std::vector<double> st_(N), cE(N), cW(N), cN(N), cS(N);
+  for (int c = 0; c < N; ++c) st_[c] = sa[c] + ss[c];
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      const int c = j * nx + i;
+      // distance from x_c to the (shifted) neighbour point along the normal
+      // (Eq. shifted_j): half a cell to the face, then sigma_nb/sigma_c times
+      // the half cell beyond it; plain least squares uses the centre.
+      auto dist = [&](int nb, double h) {
+        if (nb < 0) return 0.0;
+        return P.alsm ? 0.5 * h + (st_[nb] / st_[c]) * (0.5 * h) : h;
+      };
+      const double dE = dist(i + 1 < nx ? c + 1 : -1, p->dx);
+      const double dW = dist(i > 0 ? c - 1 : -1, p->dx);
+      const double dN = dist(j + 1 < ny ? c + nx : -1, p->dy);
+      const double dS = dist(j > 0 ? c - nx : -1, p->dy);
+      const double mx = dE * dE + dW * dW, my = dN * dN + dS * dS;
+      cE[c] = mx > 0 ? dE / mx : 0.0;
+      cW[c] = mx > 0 ? dW / mx : 0.0;
+      cN[c] = my > 0 ? dN / my : 0.0;
+      cS[c] = my > 0 ? dS / my : 0.0;
+    }
+  // kappa per boundary face (Eqs. macro_bc_delta_flux, macro_bc_delta_flux2)
+  std::vector<double> kap(P.nbf);
+  for (int j = 0; j < ny; ++j) {
+    kap[j] = 2.0 / (3.0 * st_[j * nx] * p->dx) + 0.25;
+    kap[ny + j] = 2.0 / (3.0 * st_[j * nx + nx - 1] * p->dx) + 0.25;
+  }
+  for (int i = 0; i < nx; ++i) {
+    kap[2 * ny + i] = 2.0 / (3.0 * st_[i] * p->dy) + 0.25;
+    kap[2 * ny + nx + i] = 2.0 / (3.0 * st_[(ny - 1) * nx + i] * p->dy) + 0.25;
+  }
+  // D1 (Eqs. MSE_d_mtx1, elem_mtx_M, Gamma_ij_com2), multiplied by V
+  std::vector<HostLevel> hl(1);
+  hl[0].nx = nx; hl[0].ny = ny;
+  hl[0].diag.assign(N, 0.0); hl[0].ax.assign(N, 0.0); hl[0].ay.assign(N, 0.0);
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      const int c = j * nx + i;
+      double d = P.V * sa[c];
+      if (i + 1 < nx) {
+        const double a = p->dy * 2.0 / (3.0 * (st_[c] * p->dx + st_[c + 1] * p->dx));
+        hl[0].ax[c] = a;
+      }
+      if (j + 1 < ny) {
+        const double a = p->dx * 2.0 / (3.0 * (st_[c] * p->dy + st_[c + nx] * p->dy));
+        hl[0].ay[c] = a;
+      }
+      if (i + 1 < nx) d += hl[0].ax[c]; else d += p->dy * kap[ny + j];
+      if (i > 0) d += hl[0].ax[c - 1]; else d += p->dy * kap[j];
+      if (j + 1 < ny) d += hl[0].ay[c]; else d += p->dx * kap[2 * ny + nx + i];
+      if (j > 0) d += hl[0].ay[c - nx]; else d += p->dx * kap[2 * ny + i];
+      hl[0].diag[c] = d;
+    }
+  // Galerkin coarsening. Aggregates are 2x2, or 2x1 / 1x2 when the
+  // couplings in one direction are much weaker than in the other (then
+  // merging across the weak direction would leave error the point smoother
+  // cannot reach).
+  const int kCoarseMax = 256;
+  while ((long)hl.back().nx * hl.back().ny > kCoarseMax && (hl.back().nx > 1 || hl.back().ny > 1)) {
+    HostLevel &F = hl.back();
+    double lx = 0, ly = 0;
+    long mx = 0, my = 0;
+    for (int j = 0; j < F.ny; ++j)
+      for (int i = 0; i < F.nx; ++i) {
+        const int c = j * F.nx + i;
+        if (i + 1 < F.nx) { lx += std::log(F.ax[c]); ++mx; }
+        if (j + 1 < F.ny) { ly += std::log(F.ay[c]); ++my; }
+      }
+    const double gx = mx ? std::exp(lx / mx) : 0.0, gy = my ? std::exp(ly / my) : 0.0;
+    F.fx = (F.nx > 1 && gx >= 0.25 * gy) ? 2 : 1;
+    F.fy = (F.ny > 1 && gy >= 0.25 * gx) ? 2 : 1;
+    HostLevel C;
+    C.nx = (F.nx + F.fx - 1) / F.fx;
+    C.ny = (F.ny + F.fy - 1) / F.fy;
+    const int Nc = C.nx * C.ny;
+    C.diag.assign(Nc, 0.0); C.ax.assign(Nc, 0.0); C.ay.assign(Nc, 0.0);
+    for (int j = 0; j < F.ny; ++j)
+      for (int i = 0; i < F.nx; ++i) {
+        const int c = j * F.nx + i;
+        const int Ci = i / F.fx, Cj = j / F.fy;
+        const int Cc = Cj * C.nx + Ci;
+        C.diag[Cc] += F.diag[c];
+        if (i + 1 < F.nx) {
+          const int Ci2 = (i + 1) / F.fx;
+          if (Ci2 == Ci) C.diag[Cc] -= 2.0 * F.ax[c];
+          else C.ax[Cc] += F.ax[c];
+        }
+        if (j + 1 < F.ny) {
+          const int Cj2 = (j + 1) / F.fy;
+          if (Cj2 == Cj) C.diag[Cc] -= 2.0 * F.ay[c];
+          else C.ay[Cc] += F.ay[c];
+        }
+      }
+    hl.push_back(std::move(C));
+  }
+  // dense inverse of the coarsest level
+  const HostLevel &Lc = hl.back();
+  const int nc = Lc.nx * Lc.ny;
+  std::vector<double> dense((size_t)nc * nc, 0.0);
+  for (int j = 0; j < Lc.ny; ++j)
+    for (int i = 0; i < Lc.nx; ++i) {
+      const int c = j * Lc.nx + i;
+      dense[(size_t)c * nc + c] = Lc.diag[c];
+      if (i + 1 < Lc.nx) {
+        dense[(size_t)c * nc + c + 1] = -Lc.ax[c];
+        dense[(size_t)(c + 1) * nc + c] = -Lc.ax[c];
+      }
+      if (j + 1 < Lc.ny) {
+        dense[(size_t)c * nc + c + Lc.nx] = -Lc.ay[c];
+        dense[(size_t)(c + Lc.nx) * nc + c] = -Lc.ay[c];
+      }
+    }
+  if (!dense_spd_inverse(nc, dense))
+    return bail(fail(ctx, GSIS_E_INVALID_ARG, "synthetic operator is not positive definite"));
+
+  // -- boundary intensities in the internal ordinate order
+  std::vector<double> bnd_int((size_t)P.nbf * K);
+  for (int f = 0; f < P.nbf; ++f)
+    for (int kk = 0; kk < K; ++kk) bnd_int[(size_t)f * K + kk] = bnd[(size_t)f * K + pl->perm[kk]];
+
+  // -- warm start
+  std::vector<double> phi0(N, 0.0);
+  if (o->I0) {
+    std::vector<double> I0;
+    if ((st = fetch(ctx, o->I0, (size_t)N * K, o->device_ptrs, I0, "I0"))) return bail(st);
+    pl->I0_host.assign((size_t)N * K, 0.0);
+    for (int kk = 0; kk < K; ++kk) {
+      const int k = pl->perm[kk];
+      const int qd = (mu[k] < 0 ? 1 : 0) | (eta[k] < 0 ? 2 : 0);
+      for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+          const int xl = (qd & 1) ? nx - 1 - i : i, yl = (qd & 2) ? ny - 1 - j : j;
+          pl->I0_host[(size_t)kk * N + (size_t)yl * nx + xl] = I0[(size_t)(j * nx + i) * K + k];
+        }
+    }
+    for (int c = 0; c < N; ++c) {
+      double s = 0;
+      for (int k = 0; k < K; ++k) s += w[k] * I0[(size_t)c * K + k];
+      phi0[c] = s;
+    }
+  }
+  pl->phi0_host = phi0;
+
+  // -- device allocations and uploads
+  if ((st = upload(pl, &P.amu, amu)) || (st = upload(pl, &P.aeta, aeta)) ||
+      (st = upload(pl, &P.w, wv)) || (st = upload(pl, &P.wmu, wmu)) ||
+      (st = upload(pl, &P.weta, weta)) || (st = dalloc(pl, &P.I[0], (size_t)N * K)) ||
+      (st = dalloc(pl, &P.I[1], (size_t)N * K)) || (st = dalloc(pl, &P.R, (size_t)N * K)) ||
+      (st = upload(pl, &P.sig_t, st_)) || (st = upload(pl, &P.sig_a, sa)) ||
+      (st = upload(pl, &P.sig_s, ss)) || (st = upload(pl, &P.q, q)) ||
+      (st = upload(pl, &P.cE, cE)) || (st = upload(pl, &P.cW, cW)) ||
+      (st = upload(pl, &P.cN, cN)) || (st = upload(pl, &P.cS, cS)) ||
+      (st = dalloc(pl, &P.src, N)) || (st = dalloc(pl, &P.phi, N)) ||
+      (st = dalloc(pl, &P.phih, N)) || (st = dalloc(pl, &P.Fx, N)) ||
+      (st = dalloc(pl, &P.Fy, N)) || (st = dalloc(pl, &P.delta, N)) ||
+      (st = dalloc(pl, &P.hx, N)) || (st = dalloc(pl, &P.hy, N)) ||
+      (st = dalloc(pl, &P.rhs, N)) || (st = upload(pl, &P.bnd, bnd_int)) ||
+      (st = dalloc(pl, &P.bflux, P.nbf)) || (st = upload(pl, &P.kappa, kap)) ||
+      (st = dalloc(pl, &P.cg_r, N)) || (st = dalloc(pl, &P.cg_z, N)) ||
+      (st = dalloc(pl, &P.cg_p, N)) || (st = dalloc(pl, &P.cg_Ap, N)) ||
+      (st = dalloc(pl, &P.scal, 16)) || (st = dalloc(pl, &P.err_hist, o->max_iter)) ||
+      (st = dalloc(pl, &P.state, 4)) || (st = dalloc(pl, &P.last_err, 1)))
+    return bail(st);
+  P.red_blocks = (N + 255) / 256;
+  if ((st = dalloc(pl, &P.red, 2 * (size_t)P.red_blocks + 2)) ||
+      (st = dalloc(pl, &P.err_parts, 2 * (size_t)P.red_blocks + 2)))
+    return bail(st);
+  P.mg.resize(hl.size());
+  for (size_t l = 0; l < hl.size(); ++l) {
+    MGLevel &L = P.mg[l];
+    L.nx = hl[l].nx; L.ny = hl[l].ny; L.fx = hl[l].fx; L.fy = hl[l].fy;
+    const size_t n = (size_t)L.nx * L.ny;
+    if ((st = upload(pl, &L.diag, hl[l].diag)) || (st = upload(pl, &L.ax, hl[l].ax)) ||
+        (st = upload(pl, &L.ay, hl[l].ay)) || (st = dalloc(pl, &L.x, n)) ||
+        (st = dalloc(pl, &L.b, n)) || (st = dalloc(pl, &L.r, n)))
+      return bail(st);
+  }
+  P.coarse_n = nc;
+  if ((st = upload(pl, &P.coarse_inv, dense))) return bail(st);
+  {
+    void *h = nullptr;
+    hipError_t e = hipHostMalloc(&h, 64, hipHostMallocDefault);
+    if (e != hipSuccess) return bail(fail(ctx, GSIS_E_OOM, "hipHostMalloc: %s", hipGetErrorString(e)));
+    pl->host_scal = (double *)h;
+  }
+  if ((st = gsis_plan_reset(pl))) return bail(st);
+  *out = pl;
+  return GSIS_OK;
+}
+
+extern "C" void gsis_plan_destroy(gsis_plan *pl) {
+  if (!pl) return;
+  if (pl->stream) (void)hipStreamSynchronize(pl->stream);
+  else (void)hipDeviceSynchronize();
+  for (void *v : pl->allocs) (void)hipFree(v);
+  for (hipEvent_t e : pl->events) (void)hipEventDestroy(e);
+  if (pl->host_scal) (void)hipHostFree(pl->host_scal);
+  delete pl;
+}
+
+extern "C" gsis_status gsis_plan_reset(gsis_plan *pl) {
+  if (!pl) return GSIS_E_INVALID_ARG;
+  gsis_ctx *ctx = pl->ctx;
+  PlanDev &P = pl->P;
+  const size_t NK = (size_t)P.N * P.K;
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  hipStream_t s = pl->stream;
+  if (!pl->I0_host.empty())
+    HIPCHK(ctx, hipMemcpyAsync(P.I[0], pl->I0_host.data(), NK * sizeof(double),
+                               hipMemcpyHostToDevice, s));
+  else
+    HIPCHK(ctx, hipMemsetAsync(P.I[0], 0, NK * sizeof(double), s));
+  HIPCHK(ctx, hipMemcpyAsync(P.phi, pl->phi0_host.data(), P.N * sizeof(double),
+                             hipMemcpyHostToDevice, s));
+  HIPCHK(ctx, hipMemsetAsync(P.delta, 0, P.N * sizeof(double), s));
+  HIPCHK(ctx, hipMemsetAsync(P.state, 0, 4 * sizeof(int32_t), s));
+  HIPCHK(ctx, hipMemsetAsync(P.err_hist, 0, P.max_iter * sizeof(double), s));
+  launch_source(P, s);
+  HIPCHK(ctx, hipGetLastError());
+  HIPCHK(ctx, hipStreamSynchronize(s));
+  pl->prof_iters = 0;
+  return GSIS_OK;
+}
+
+static gsis_status record(gsis_plan *pl, int slot) {
+  if (!pl->profile) return GSIS_OK;
+  const size_t idx = (size_t)pl->prof_iters * 5 + slot;
+  while (pl->events.size() <= idx) {
+    hipEvent_t e;
+    HIPCHK(pl->ctx, hipEventCreate(&e));
+    pl->events.push_back(e);
+  }
+  HIPCHK(pl->ctx, hipEventRecord(pl->events[idx], pl->stream));
+  return GSIS_OK;
+}
+
+extern "C" gsis_status gsis_plan_iterate(gsis_plan *pl, int32_t n) {
+  if (!pl) return GSIS_E_INVALID_ARG;
+  gsis_ctx *ctx = pl->ctx;
+  if (n < 0) return fail(ctx, GSIS_E_INVALID_ARG, "n must be >= 0");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  PlanDev &P = pl->P;
+  hipStream_t s = pl->stream;
+  gsis_status st;
+  for (int it = 0; it < n; ++it) {
+    if (pl->profile && pl->prof_iters >= 100000) pl->profile = 0;
+    if ((st = record(pl, 0))) return st;
+    launch_residual(P, s);
+    launch_sweep(P, s);
+    launch_moments(P, s);
+    if ((st = record(pl, 1))) return st;
+    if (P.method == GSIS_GSIS) {
+      launch_boundary_flux(P, s);
+      launch_hot_rhs(P, s);
+    }
+    if ((st = record(pl, 2))) return st;
+    if (P.method == GSIS_GSIS) launch_synth_solve(P, s, pl->host_scal);
+    if ((st = record(pl, 3))) return st;
+    launch_update(P, s);
+    if ((st = record(pl, 4))) return st;
+    HIPCHK(ctx, hipGetLastError());
+    if (pl->profile) pl->prof_iters++;
+  }
+  return GSIS_OK;
+}
+
+extern "C" gsis_status gsis_plan_status(gsis_plan *pl, int32_t *n_iter, int32_t *converged,
+                                        double *last_err) {
+  if (!pl) return GSIS_E_INVALID_ARG;
+  gsis_ctx *ctx = pl->ctx;
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  int32_t stv[4];
+  double le = 0;
+  HIPCHK(ctx, hipMemcpyAsync(stv, pl->P.state, sizeof stv, hipMemcpyDeviceToHost, pl->stream));
+  HIPCHK(ctx, hipMemcpyAsync(&le, pl->P.last_err, sizeof le, hipMemcpyDeviceToHost, pl->stream));
+  HIPCHK(ctx, hipStreamSynchronize(pl->stream));
+  if (n_iter) *n_iter = stv[0];
+  if (converged) *converged = stv[1] == 1 ? 1 : (stv[1] == -1 ? -1 : 0);
+  if (last_err) *last_err = le;
+  return GSIS_OK;
+}
+
+extern "C" gsis_status gsis_plan_read(gsis_plan *pl, gsis_result *r) {
+  if (!pl) return GSIS_E_INVALID_ARG;
+  gsis_ctx *ctx = pl->ctx;
+  if (!r) return fail(ctx, GSIS_E_INVALID_ARG, "result is NULL");
+  if (!r->phi || !r->Fx || !r->Fy) return fail(ctx, GSIS_E_INVALID_ARG, "result.phi/Fx/Fy is NULL");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  PlanDev &P = pl->P;
+  hipStream_t s = pl->stream;
+  int32_t n_iter = 0, conv = 0;
+  double le = 0;
+  gsis_status st = gsis_plan_status(pl, &n_iter, &conv, &le);
+  if (st) return st;
+  const size_t bytes = P.N * sizeof(double);
+  // F of the final iterate: F_half plus the pending correction's flux (hx, hy
+  // are free here and serve as staging).
+  launch_apply_delta_final(P, s, pl->swmu, pl->sweta, P.hx, P.hy);
+  HIPCHK(ctx, hipGetLastError());
+  const hipMemcpyKind k = pl->device_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  HIPCHK(ctx, hipMemcpyAsync(r->phi, P.phi, bytes, k, s));
+  HIPCHK(ctx, hipMemcpyAsync(r->Fx, P.hx, bytes, k, s));
+  HIPCHK(ctx, hipMemcpyAsync(r->Fy, P.hy, bytes, k, s));
+  if (r->err_hist && n_iter > 0)
+    HIPCHK(ctx, hipMemcpyAsync(r->err_hist, P.err_hist, n_iter * sizeof(double), k, s));
+  HIPCHK(ctx, hipStreamSynchronize(s));
+  r->n_iter = n_iter;
+  r->final_err = n_iter > 0 ? le : INFINITY;
+  return GSIS_OK;
+}
+
+extern "C" gsis_status gsis_plan_phase_times(gsis_plan *pl, double *ms, int32_t *n_iter) {
+  if (!pl) return GSIS_E_INVALID_ARG;
+  gsis_ctx *ctx = pl->ctx;
+  if (!ms) return fail(ctx, GSIS_E_INVALID_ARG, "ms is NULL");
+  HIPCHK(ctx, hipStreamSynchronize(pl->stream));
+  for (int ph = 0; ph < GSIS_NUM_PHASES; ++ph) ms[ph] = 0;
+  for (int it = 0; it < pl->prof_iters; ++it)
+    for (int ph = 0; ph < GSIS_NUM_PHASES; ++ph) {
+      float t = 0;
+      HIPCHK(ctx, hipEventElapsedTime(&t, pl->events[(size_t)it * 5 + ph],
+                                      pl->events[(size_t)it * 5 + ph + 1]));
+      ms[ph] += t;
+    }
+  if (n_iter) *n_iter = pl->prof_iters;
+  pl->prof_iters = 0;
+  return GSIS_OK;
+}
+
+extern "C" gsis_status gsis_solve(gsis_ctx *ctx, const gsis_problem *p, const gsis_options *o,
+                                  gsis_result *r) {
+  if (!ctx) return fail(nullptr, GSIS_E_INVALID_ARG, "ctx is NULL");
+  if (!r) return fail(ctx, GSIS_E_INVALID_ARG, "result is NULL");
+  gsis_plan *pl = nullptr;
+  gsis_status st = gsis_plan_create(ctx, p, o, &pl);
+  if (st) return st;
+  int32_t n = 0, conv = 0;
+  double le = 0;
+  const int chunk = 8;
+  while (true) {
+    const int todo = std::min(chunk, o->max_iter - n);
+    if ((st = gsis_plan_iterate(pl, todo))) break;
+    if ((st = gsis_plan_status(pl, &n, &conv, &le))) break;
+    if (conv != 0 || n >= o->max_iter) break;
+  }
+  if (st == GSIS_OK) st = gsis_plan_read(pl, r);
+  gsis_plan_destroy(pl);
+  if (st) return st;
+  if (conv == -1) return GSIS_DIVERGED;
+  if (conv == 0) return GSIS_NOT_CONVERGED;
+  return GSIS_OK;
+}

@@ -1,0 +1,299 @@
+"""ctypes binding of libgsis.so (the C-ABI declared in include/gsis.h).
+
+Argument marshalling only: every step of the solver runs in the library's HIP
+kernels. Arrays may be numpy arrays (host memory) or torch CUDA tensors
+(device memory; the plan then runs on torch's current stream). If the library
+has not been built, every call raises ``GSISError``: there is no CPU
+fallback.
+"""
+import ctypes
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgsis.so")
+_lib = None
+
+GSIS_OK, GSIS_NOT_CONVERGED, GSIS_DIVERGED = 0, 1, 2
+GSIS_E_INVALID_ARG, GSIS_E_DEVICE, GSIS_E_OOM, GSIS_E_UNSUPPORTED = -1, -2, -3, -4
+GSIS_SI, GSIS_GSIS = 0, 1
+GSIS_FP64, GSIS_FP32_MIXED = 0, 1
+GSIS_HOT_CENTRAL, GSIS_HOT_TRANSPORT = 0, 1
+GSIS_NUM_PHASES = 4
+PHASES = ("sweep", "hot", "synth", "update")
+
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class GSISError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("gsis status %d: %s" % (status, msg))
+        self.status = status
+
+
+class gsis_problem(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double),
+                ("K", ctypes.c_int32),
+                ("mu", ctypes.c_void_p), ("eta", ctypes.c_void_p), ("w", ctypes.c_void_p),
+                ("sigma_a", ctypes.c_void_p), ("sigma_s", ctypes.c_void_p),
+                ("q", ctypes.c_void_p), ("bnd_in", ctypes.c_void_p)]
+
+
+class gsis_options(ctypes.Structure):
+    _fields_ = [("method", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("order", ctypes.c_int32), ("limiter", ctypes.c_int32),
+                ("alsm", ctypes.c_int32), ("hot_face", ctypes.c_int32),
+                ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
+                ("synth_rtol", ctypes.c_double), ("synth_max_iter", ctypes.c_int32),
+                ("I0", ctypes.c_void_p), ("stream", ctypes.c_void_p),
+                ("device_ptrs", ctypes.c_int32), ("profile", ctypes.c_int32)]
+
+
+class gsis_result(ctypes.Structure):
+    _fields_ = [("phi", ctypes.c_void_p), ("Fx", ctypes.c_void_p), ("Fy", ctypes.c_void_p),
+                ("err_hist", ctypes.c_void_p), ("n_iter", ctypes.c_int32),
+                ("final_err", ctypes.c_double)]
+
+
+EXPORTS = ("gsis_ctx_create", "gsis_ctx_destroy", "gsis_last_error", "gsis_options_default",
+           "gsis_solve", "gsis_plan_create", "gsis_plan_destroy", "gsis_plan_iterate",
+           "gsis_plan_status", "gsis_plan_read", "gsis_plan_reset", "gsis_plan_phase_times",
+           "gsis_version")
+
+
+def load():
+    """Open libgsis.so (after torch, so both share one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise GSISError(GSIS_E_DEVICE, "libgsis.so is not built (run paper_2507_03975_amd.build)")
+    try:
+        import torch  # noqa: F401  (loads the HIP runtime torch uses)
+    except ImportError:
+        pass
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, ip, i32 = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32
+    lib.gsis_ctx_create.argtypes = [i32, ctypes.POINTER(vp)]
+    lib.gsis_ctx_destroy.argtypes = [vp]
+    lib.gsis_ctx_destroy.restype = None
+    lib.gsis_last_error.argtypes = [vp]
+    lib.gsis_last_error.restype = ctypes.c_char_p
+    lib.gsis_options_default.argtypes = [ctypes.POINTER(gsis_options)]
+    lib.gsis_solve.argtypes = [vp, ctypes.POINTER(gsis_problem), ctypes.POINTER(gsis_options),
+                               ctypes.POINTER(gsis_result)]
+    lib.gsis_plan_create.argtypes = [vp, ctypes.POINTER(gsis_problem),
+                                     ctypes.POINTER(gsis_options), ctypes.POINTER(vp)]
+    lib.gsis_plan_destroy.argtypes = [vp]
+    lib.gsis_plan_destroy.restype = None
+    lib.gsis_plan_iterate.argtypes = [vp, i32]
+    lib.gsis_plan_status.argtypes = [vp, ip, ip, _dp]
+    lib.gsis_plan_read.argtypes = [vp, ctypes.POINTER(gsis_result)]
+    lib.gsis_plan_reset.argtypes = [vp]
+    lib.gsis_plan_phase_times.argtypes = [vp, _dp, ip]
+    lib.gsis_version.argtypes = []
+    lib.gsis_version.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name not in ("gsis_ctx_destroy", "gsis_plan_destroy", "gsis_last_error",
+                        "gsis_version"):
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def gsis_version():
+    return load().gsis_version().decode()
+
+
+def gsis_last_error(ctx=None):
+    return load().gsis_last_error(ctx.handle if ctx is not None else None).decode()
+
+
+def _check(st, ctx=None, allow=(GSIS_OK,)):
+    if st not in allow:
+        raise GSISError(st, gsis_last_error(ctx))
+    return st
+
+
+class Context:
+    """gsis_ctx_create / gsis_ctx_destroy."""
+
+    def __init__(self, device=0):
+        lib = load()
+        h = ctypes.c_void_p()
+        _check(lib.gsis_ctx_create(int(device), ctypes.byref(h)))
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            load().gsis_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _is_torch(a):
+    return type(a).__module__.startswith("torch")
+
+
+class _Args:
+    """Pointers for one call; keeps host copies alive."""
+
+    def __init__(self, prob, I0=None):
+        keys = ("mu", "eta", "w", "sigma_a", "sigma_s", "q")
+        vals = [prob[k] for k in keys]
+        self.device = any(_is_torch(v) and v.is_cuda for v in vals)
+        self.keep = []
+        ptr = {}
+        for k, v in zip(keys, vals):
+            ptr[k] = self._ptr(v)
+        b = prob.get("bnd_in")
+        ptr["bnd_in"] = None if b is None else self._ptr(b)
+        self.I0 = None if I0 is None else self._ptr(I0)
+        K = int(len(prob["mu"]))
+        self.nx, self.ny, self.K = int(prob["nx"]), int(prob["ny"]), K
+        self.s = gsis_problem(self.nx, self.ny, float(prob["dx"]), float(prob["dy"]), K,
+                              ptr["mu"], ptr["eta"], ptr["w"], ptr["sigma_a"],
+                              ptr["sigma_s"], ptr["q"], ptr["bnd_in"])
+
+    def _ptr(self, a):
+        if _is_torch(a):
+            import torch
+            if a.is_cuda != self.device:
+                raise ValueError("mix of host and device arrays")
+            a = a.detach().to(torch.float64).contiguous()
+            self.keep.append(a)
+            return a.data_ptr()
+        if self.device:
+            raise ValueError("mix of host and device arrays")
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        self.keep.append(a)
+        return a.ctypes.data
+
+
+def make_options(method=GSIS_GSIS, precision=GSIS_FP64, order=2, limiter=1, alsm=1,
+                 hot_face=GSIS_HOT_CENTRAL, tol=1e-6, max_iter=1000, synth_rtol=1e-4,
+                 synth_max_iter=50, profile=0):
+    o = gsis_options()
+    load().gsis_options_default(ctypes.byref(o))
+    o.method, o.precision, o.order, o.limiter = int(method), int(precision), int(order), int(limiter)
+    o.alsm, o.hot_face, o.tol, o.max_iter = int(alsm), int(hot_face), float(tol), int(max_iter)
+    o.synth_rtol, o.synth_max_iter, o.profile = float(synth_rtol), int(synth_max_iter), int(profile)
+    return o
+
+
+def _stream_handle():
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+class Plan:
+    """gsis_plan_create / iterate / status / read / reset / phase_times / destroy."""
+
+    def __init__(self, ctx, prob, I0=None, **opts):
+        lib = load()
+        self.ctx = ctx
+        self.args = _Args(prob, I0)
+        o = make_options(**opts)
+        o.I0 = self.args.I0
+        o.device_ptrs = 1 if self.args.device else 0
+        o.stream = _stream_handle() if self.args.device else None
+        self.opts = o
+        h = ctypes.c_void_p()
+        _check(lib.gsis_plan_create(ctx.handle, ctypes.byref(self.args.s), ctypes.byref(o),
+                                    ctypes.byref(h)), ctx)
+        self.handle = h
+        self.N = self.args.nx * self.args.ny
+
+    def iterate(self, n):
+        _check(load().gsis_plan_iterate(self.handle, int(n)), self.ctx)
+
+    def status(self):
+        n, c, e = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        _check(load().gsis_plan_status(self.handle, ctypes.byref(n), ctypes.byref(c),
+                                       ctypes.byref(e)), self.ctx)
+        return n.value, c.value, e.value
+
+    def reset(self):
+        _check(load().gsis_plan_reset(self.handle), self.ctx)
+
+    def read(self, out=None):
+        """Return dict(phi, Fx, Fy, err_hist, n_iter, final_err); arrays are
+        numpy (host plans) or torch tensors on the plan's device."""
+        N, maxit = self.N, self.opts.max_iter
+        if self.args.device:
+            import torch
+            dev = self.args.keep[0].device
+            phi = torch.empty(N, dtype=torch.float64, device=dev)
+            fx, fy = torch.empty_like(phi), torch.empty_like(phi)
+            hist = torch.zeros(maxit, dtype=torch.float64, device=dev)
+            p = lambda t: t.data_ptr()
+        else:
+            phi, fx, fy, hist = np.empty(N), np.empty(N), np.empty(N), np.zeros(maxit)
+            p = lambda a: a.ctypes.data
+        r = gsis_result(p(phi), p(fx), p(fy), p(hist), 0, 0.0)
+        _check(load().gsis_plan_read(self.handle, ctypes.byref(r)), self.ctx)
+        return dict(phi=phi, Fx=fx, Fy=fy, err_hist=hist[:r.n_iter], n_iter=r.n_iter,
+                    final_err=r.final_err)
+
+    def phase_times(self):
+        ms = (ctypes.c_double * GSIS_NUM_PHASES)()
+        n = ctypes.c_int32()
+        _check(load().gsis_plan_phase_times(self.handle, ms, ctypes.byref(n)), self.ctx)
+        return {k: ms[i] for i, k in enumerate(PHASES)}, n.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().gsis_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def gsis_solve(ctx, prob, I0=None, **opts):
+    """One-shot solve (gsis_solve). Returns the result dict plus ``status``."""
+    lib = load()
+    a = _Args(prob, I0)
+    o = make_options(**opts)
+    o.I0 = a.I0
+    o.device_ptrs = 1 if a.device else 0
+    o.stream = _stream_handle() if a.device else None
+    N = a.nx * a.ny
+    if a.device:
+        import torch
+        dev = a.keep[0].device
+        phi = torch.empty(N, dtype=torch.float64, device=dev)
+        fx, fy = torch.empty_like(phi), torch.empty_like(phi)
+        hist = torch.zeros(o.max_iter, dtype=torch.float64, device=dev)
+        p = lambda t: t.data_ptr()
+    else:
+        phi, fx, fy, hist = np.empty(N), np.empty(N), np.empty(N), np.zeros(o.max_iter)
+        p = lambda x: x.ctypes.data
+    r = gsis_result(p(phi), p(fx), p(fy), p(hist), 0, 0.0)
+    st = lib.gsis_solve(ctx.handle, ctypes.byref(a.s), ctypes.byref(o), ctypes.byref(r))
+    _check(st, ctx, allow=(GSIS_OK, GSIS_NOT_CONVERGED, GSIS_DIVERGED))
+    return dict(phi=phi, Fx=fx, Fy=fy, err_hist=hist[:r.n_iter], n_iter=r.n_iter,
+                final_err=r.final_err, status=st)
+
+
+_default_ctx = None
+
+
+def solve(prob, I0=None, device=0, **opts):
+    """Convenience: gsis_solve on a per-process default context."""
+    global _default_ctx
+    if _default_ctx is None:
+        _default_ctx = Context(device)
+    return gsis_solve(_default_ctx, prob, I0, **opts)

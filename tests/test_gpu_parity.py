@@ -1,0 +1,173 @@
+"""Parity of the HIP path (through the C-ABI) with the FP64 CPU oracle.
+
+Iterates are compared at a fixed iteration count m (the map is the same on
+both sides, so they agree to rounding), converged fixed points to the stated
+tolerance, and edge cases (one cell, one row/column, ragged sizes, several
+sweep passes, K = 1, inflow on every side) element by element.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2507_03975_amd import gsis, inputs
+
+pytestmark = pytest.mark.gpu
+
+FOURPI = 4.0 * math.pi
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return gsis.Context(0)
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _rel(a, b):
+    s = max(np.abs(b).max(), 1e-300)
+    return np.abs(np.asarray(a) - b).max() / s
+
+
+def _fixed_m(ctx, p, m, **kw):
+    _say("fixed-m case nx=%d ny=%d K=%d m=%d %s" % (p["nx"], p["ny"], len(p["mu"]), m, kw))
+    g = gsis.gsis_solve(ctx, p, tol=0.0, max_iter=m, synth_rtol=1e-15, synth_max_iter=200, **kw)
+    o = oracle.solve(p, tol=0.0, max_iter=m, **kw)
+    assert g["n_iter"] == m == o["n_iter"]
+    return g, o
+
+
+VARIANTS = [dict(method=0, order=1, limiter=0, alsm=1),
+            dict(method=0, order=2, limiter=1, alsm=1),
+            dict(method=1, order=2, limiter=1, alsm=1),
+            dict(method=1, order=2, limiter=0, alsm=0),
+            dict(method=1, order=1, limiter=0, alsm=1)]
+
+
+@pytest.mark.parametrize("kw", VARIANTS)
+@pytest.mark.parametrize("shape", [(13, 9), (70, 67)])
+def test_iterate_parity_random(ctx, kw, shape):
+    p = inputs.random_problem(shape[0], shape[1], seed=shape[0], sigma_range=(0.05, 50.0))
+    for m in (1, 4):
+        g, o = _fixed_m(ctx, p, m, **kw)
+        assert _rel(g["phi"], o["phi"]) < 1e-12
+        assert _rel(g["Fx"], o["Fx"]) < 1e-11 and _rel(g["Fy"], o["Fy"]) < 1e-11
+        np.testing.assert_allclose(g["err_hist"], o["err_hist"], rtol=1e-9)
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (1, 7), (9, 1), (3, 1100), (130, 2)])
+@pytest.mark.parametrize("method", [0, 1])
+def test_edge_shapes(ctx, shape, method):
+    """One cell, one row or column, a 3 x 1100 strip (two sweep passes) and
+    a ragged 130 x 2 grid. SI iterates (no linear solve) agree to 1e-12; GSIS
+    iterates include the synthetic solve, whose rounding grows with the
+    condition number of D1 (about 1e6 on the 1100-cell strip), so they are
+    held to the FP64 bound 1e-10."""
+    p = inputs.random_problem(shape[0], shape[1], seed=7, sigma_range=(0.1, 5.0))
+    g, o = _fixed_m(ctx, p, 3, method=method)
+    assert _rel(g["phi"], o["phi"]) < (1e-12 if method == 0 else 1e-10)
+    assert _rel(g["Fx"], o["Fx"]) < 1e-10 and _rel(g["Fy"], o["Fy"]) < 1e-10
+
+
+def test_single_ordinate_and_axis_directions(ctx):
+    p = inputs.random_problem(11, 6, seed=3)
+    # K = 1 (a single direction carrying the whole sphere) and axis-aligned ordinates
+    p1 = dict(p, mu=np.array([0.6]), eta=np.array([-0.3]), w=np.array([FOURPI]),
+              bnd_in=np.full((34, 1), 0.05))
+    g, o = _fixed_m(ctx, p1, 3, method=1)
+    assert _rel(g["phi"], o["phi"]) < 1e-12
+    p2 = dict(p, mu=np.array([1.0, -1.0, 0.0, 0.0]), eta=np.array([0.0, 0.0, 1.0, -1.0]),
+              w=np.full(4, math.pi), bnd_in=np.full((34, 4), 0.02))
+    g, o = _fixed_m(ctx, p2, 3, method=1)
+    assert _rel(g["phi"], o["phi"]) < 1e-12
+
+
+def test_fixed_point_small_s4(ctx):
+    """32 x 32, S4, sigma_t = 1, c = 0.9: converged GSIS fixed point."""
+    p = inputs.small_s4_32()
+    for lim in (0, 1):
+        _say("fixed point small_s4_32 limiter=%d" % lim)
+        g = gsis.gsis_solve(ctx, p, tol=1e-13, max_iter=2000, limiter=lim, synth_rtol=1e-15,
+                            synth_max_iter=200)
+        o = oracle.solve(p, tol=1e-13, max_iter=2000, limiter=lim)
+        assert g["status"] == 0 and o["status"] == 0
+        assert abs(g["n_iter"] - o["n_iter"]) <= 2
+        assert _rel(g["phi"], o["phi"]) < 1e-10
+        assert _rel(g["Fx"], o["Fx"]) < 1e-9 and _rel(g["Fy"], o["Fy"]) < 1e-9
+
+
+def test_fixed_point_thick_square_small(ctx):
+    p = inputs.thick_square(128, inputs.quad_product(2, 16))
+    _say("fixed point thick_square 128 K=32")
+    g = gsis.gsis_solve(ctx, p, tol=1e-12, max_iter=300, limiter=0, synth_rtol=1e-15,
+                        synth_max_iter=300)
+    o = oracle.solve(p, tol=1e-12, max_iter=300, limiter=0)
+    assert g["status"] == 0 and o["status"] == 0
+    assert _rel(g["phi"], o["phi"]) < 1e-10
+    assert _rel(g["Fx"], o["Fx"]) < 1e-9
+
+
+def test_full_size_thick_square_iterates(ctx):
+    """The benchmark workload at full size (256 x 256, K = 128): iterates at
+    m = 2 agree with the oracle element by element."""
+    p = inputs.thick_square(256)
+    for method in (0, 1):
+        g, o = _fixed_m(ctx, p, 2, method=method)
+        assert _rel(g["phi"], o["phi"]) < 1e-12
+        assert _rel(g["Fx"], o["Fx"]) < 1e-10
+
+
+def test_device_pointers_and_determinism(ctx):
+    import torch
+    p = inputs.random_problem(40, 33, seed=5)
+    pd = {k: (torch.from_numpy(v).cuda() if isinstance(v, np.ndarray) else v) for k, v in p.items()}
+    _say("device pointers 40x33")
+    a = gsis.gsis_solve(ctx, pd, tol=1e-10, max_iter=200)
+    b = gsis.gsis_solve(ctx, pd, tol=1e-10, max_iter=200)
+    h = gsis.gsis_solve(ctx, p, tol=1e-10, max_iter=200)
+    assert torch.equal(a["phi"], b["phi"]) and torch.equal(a["Fx"], b["Fx"])
+    assert np.array_equal(a["phi"].cpu().numpy(), h["phi"])
+    assert a["n_iter"] == h["n_iter"]
+
+
+def test_warm_start_and_plan_api(ctx):
+    p = inputs.random_problem(20, 17, seed=8, sigma_range=(0.5, 5.0))
+    o = oracle.solve(p, tol=1e-12, max_iter=150, limiter=0, return_I=True)
+    assert o["status"] == 0
+    _say("plan api 20x17")
+    plan = gsis.Plan(ctx, p, tol=1e-12, max_iter=150, limiter=0, synth_rtol=1e-15)
+    plan.iterate(3)
+    n, conv, err = plan.status()
+    assert n == 3 and conv == 0
+    plan.iterate(200)
+    n, conv, err = plan.status()
+    assert conv == 1 and n == o["n_iter"] and err < 1e-12
+    r = plan.read()
+    assert _rel(r["phi"], o["phi"]) < 1e-10
+    plan.reset()
+    assert plan.status()[0] == 0
+    plan.close()
+    # warm start from the converged intensity: one iteration, Err tiny
+    g = gsis.gsis_solve(ctx, p, I0=o["I"], tol=1e-9, max_iter=5, limiter=0, synth_rtol=1e-15)
+    assert g["n_iter"] == 1 and g["status"] == 0
+
+
+def test_invalid_arguments(ctx):
+    p = inputs.random_problem(5, 4, seed=1)
+    bad = [dict(p, nx=0), dict(p, w=p["w"] * 1.01), dict(p, sigma_a=np.where(
+        np.arange(20) == 3, np.nan, p["sigma_a"])), dict(p, sigma_s=-p["sigma_s"])]
+    for b in bad:
+        with pytest.raises(gsis.GSISError) as e:
+            gsis.gsis_solve(ctx, b)
+        assert e.value.status == gsis.GSIS_E_INVALID_ARG
+    with pytest.raises(gsis.GSISError):
+        gsis.gsis_solve(ctx, p, max_iter=0)
+    r = gsis.gsis_solve(ctx, p, tol=1e-30, max_iter=3)
+    assert r["status"] == gsis.GSIS_NOT_CONVERGED and r["n_iter"] == 3
