@@ -1,0 +1,175 @@
+"""Benchmark: steady gray GSIS on one MI355X.
+
+Workload (default): 256 x 256 cells, 128 ordinates (4 Gauss-Legendre polar x
+32 Chebyshev azimuthal), thick square sigma_t = 1e3, c = 0.9999 inside,
+sigma_t = 1, c = 0.5 outside, unit source in the thick region, vacuum, FP64,
+Barth-Jespersen limiter on. A step is one outer GSIS iteration (transport
+residual + sweep + moments, boundary fluxes + HoT + synthetic right-hand side,
+CG/multigrid synthetic solve, correction + Err) on resident device data.
+
+Prints ONE JSON line. value = cell-ordinate updates per second over the timed
+steps (nx*ny*K per step). Also reported: the sweep phase against the HBM
+roofline (algorithmic 16 B per cell-ordinate: read I^m, write I^{m+1/2}),
+time-to-converge (Err < 1e-6) for GSIS and for source iteration, and the CPU
+oracle on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+ALG_BYTES_FP64 = 16.0
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(prob, n_iter):
+    """Time the FP64 oracle (as it stands) for n_iter GSIS iterations of the
+    same workload on this host's cores."""
+    import oracle
+    cores = len(os.sched_getaffinity(0))
+    t0 = time.perf_counter()
+    r = oracle.solve(prob, method=1, tol=0.0, max_iter=n_iter)
+    dt = time.perf_counter() - t0
+    N, K = prob["nx"] * prob["ny"], len(prob["mu"])
+    omp = os.environ.get("OMP_NUM_THREADS")
+    used = min(cores, int(omp)) if omp and omp.isdigit() else cores
+    return {"value": N * K * r["n_iter"] / dt, "unit": "cell-ordinate updates/s", "cores": used,
+            "kind": "oracle",
+            "sample": "%d GSIS iterations of the full %dx%dx%d workload from I=0 "
+                      "(incl. one banded-Cholesky factorisation), %.1f s" % (
+                          r["n_iter"], prob["nx"], prob["ny"], K, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-converge", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=40)
+    ap.add_argument("--si-cap", type=int, default=3000)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2507_03975_amd import gsis, inputs
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    prob = inputs.thick_square(256)
+    N, K = prob["nx"] * prob["ny"], len(prob["mu"])
+    pd = {k: (torch.from_numpy(v).to(dev) if isinstance(v, np.ndarray) else v)
+          for k, v in prob.items()}
+    ctx = gsis.Context(0)
+    opts = dict(method=gsis.GSIS_GSIS, limiter=1, synth_rtol=1e-4, synth_max_iter=50)
+
+    # ---- timed steps: K outer iterations from the initial state
+    plan = gsis.Plan(ctx, pd, tol=0.0, max_iter=args.steps + args.warmup + 1, profile=1, **opts)
+    plan.iterate(args.warmup)
+    torch.cuda.synchronize()
+    plan.reset()
+    plan.phase_times()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    plan.iterate(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    phases, nprof = plan.phase_times()
+    n_done = plan.status()[0]
+    assert n_done == args.steps, (n_done, args.steps)
+    plan.close()
+    ms_step = ms / args.steps
+    value = N * K * args.steps / (ms / 1e3)
+    sweep_ms = phases["sweep"] / max(nprof, 1)
+    achieved = ALG_BYTES_FP64 * N * K / (sweep_ms / 1e3) / 1e9
+    log("step %.3f ms; phases per step (ms): %s" % (
+        ms_step, {k: round(v / max(nprof, 1), 4) for k, v in phases.items()}))
+
+    out = {
+        "metric": "cell-ordinate updates/s; time-to-converge GSIS vs SI at rel resid 1e-6",
+        "value": value,
+        "unit": "cell-ordinate updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "GSIS FP64, 256x256 cells, 128 ordinates (GL4x Chebyshev32), "
+                               "thick square sigma_t=1e3 c=0.9999 in sigma_t=1 c=0.5, unit "
+                               "source in the thick region, vacuum, BJ limiter",
+                   "nx": 256, "ny": 256, "ordinates": K, "method": "GSIS",
+                   "step": "one outer iteration"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "transport sweep phase (residual + wavefront sweep + moments)",
+                     "algorithmic_bytes_per_launch": ALG_BYTES_FP64 * N * K,
+                     "avg_ms": sweep_ms},
+        "phase_ms_per_step": {k: v / max(nprof, 1) for k, v in phases.items()},
+    }
+
+    # ---- time to converge (Err < 1e-6), GSIS vs SI on the same GPU
+    if not args.no_converge:
+        res = {}
+        for name, method, cap in (("gsis", gsis.GSIS_GSIS, 500), ("si", gsis.GSIS_SI, args.si_cap)):
+            o2 = dict(opts, method=method)
+            pl = gsis.Plan(ctx, pd, tol=1e-6, max_iter=cap, **o2)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            done = 0
+            while True:
+                pl.iterate(min(64, cap - done))
+                n, conv, err = pl.status()
+                done = n
+                if conv != 0 or n >= cap:
+                    break
+            dt = time.perf_counter() - t0
+            r = pl.read()
+            pl.close()
+            hist = r["err_hist"].cpu().numpy() if hasattr(r["err_hist"], "cpu") else r["err_hist"]
+            ent = {"iterations": int(n), "seconds": dt, "final_err": float(err),
+                   "converged": bool(conv == 1)}
+            if conv != 1 and len(hist) > 200:
+                tail = hist[-200:]
+                rho = float(np.exp(np.mean(np.log(tail[1:] / tail[:-1]))))
+                if 0 < rho < 1:
+                    more = math.log(1e-6 / hist[-1]) / math.log(rho)
+                    ent.update(extrapolated=True, contraction=rho,
+                               iterations_extrapolated=int(n + more),
+                               seconds_extrapolated=dt * (n + more) / n)
+            res[name] = ent
+            log("%s: %s" % (name, ent))
+        g, s = res["gsis"], res["si"]
+        s_sec = s.get("seconds_extrapolated", s["seconds"])
+        out["time_to_converge"] = {"tol": 1e-6, "gsis": g, "si": s,
+                                   "si_over_gsis_time": s_sec / g["seconds"]}
+
+    if not args.no_cpu_baseline:
+        log("cpu baseline: oracle, %d iterations" % args.cpu_iters)
+        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_iters)
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
