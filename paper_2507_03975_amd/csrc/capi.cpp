@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -427,6 +428,25 @@ extern "C" gsis_status gsis_plan_create(gsis_ctx *ctx, const gsis_problem *p,
   if (!dense_spd_inverse(nc, dense))
     return bail(fail(ctx, GSIS_E_INVALID_ARG, "synthetic operator is not positive definite"));
 
+  // -- per-quadrant coefficient records in each quadrant's mirrored frame
+  std::vector<double> cellq((size_t)4 * N * 6, 0.0);
+  for (int qd = 0; qd < 4; ++qd)
+    for (int yl = 0; yl < ny; ++yl)
+      for (int xl = 0; xl < nx; ++xl) {
+        const int i = (qd & 1) ? nx - 1 - xl : xl, j = (qd & 2) ? ny - 1 - yl : yl;
+        const int c = j * nx + i;
+        double *r = &cellq[((size_t)qd * N + dg_idx(xl, yl, nx, ny)) * 6];
+        r[0] = (qd & 1) ? cW[c] : cE[c];
+        r[1] = (qd & 1) ? cE[c] : cW[c];
+        r[2] = (qd & 2) ? cS[c] : cN[c];
+        r[3] = (qd & 2) ? cN[c] : cS[c];
+        r[4] = st_[c];
+      }
+  {
+    const char *e = getenv("GSIS_SWEEP_REFERENCE");
+    P.sweep_impl = (e && e[0] == '1') ? 1 : 0;
+  }
+
   // -- boundary intensities in the internal ordinate order
   std::vector<double> bnd_int((size_t)P.nbf * K);
   for (int f = 0; f < P.nbf; ++f)
@@ -444,7 +464,7 @@ extern "C" gsis_status gsis_plan_create(gsis_ctx *ctx, const gsis_problem *p,
       for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) {
           const int xl = (qd & 1) ? nx - 1 - i : i, yl = (qd & 2) ? ny - 1 - j : j;
-          pl->I0_host[(size_t)kk * N + (size_t)yl * nx + xl] = I0[(size_t)(j * nx + i) * K + k];
+          pl->I0_host[(size_t)kk * N + dg_idx(xl, yl, nx, ny)] = I0[(size_t)(j * nx + i) * K + k];
         }
     }
     for (int c = 0; c < N; ++c) {
@@ -459,13 +479,17 @@ extern "C" gsis_status gsis_plan_create(gsis_ctx *ctx, const gsis_problem *p,
   if ((st = upload(pl, &P.amu, amu)) || (st = upload(pl, &P.aeta, aeta)) ||
       (st = upload(pl, &P.w, wv)) || (st = upload(pl, &P.wmu, wmu)) ||
       (st = upload(pl, &P.weta, weta)) || (st = dalloc(pl, &P.I[0], (size_t)N * K)) ||
-      (st = dalloc(pl, &P.I[1], (size_t)N * K)) || (st = dalloc(pl, &P.R, (size_t)N * K)) ||
+      (st = dalloc(pl, &P.I[1], (size_t)N * K)) ||
+      (st = dalloc(pl, &P.R, P.sweep_impl == 1 ? (size_t)N * K : 1)) ||
+      (st = upload(pl, &P.cellq, cellq)) || (st = dalloc(pl, &P.dynq, (size_t)4 * N * 2)) ||
+      (st = dalloc(pl, &P.rowbuf, (size_t)K * 3 * nx)) ||
       (st = upload(pl, &P.sig_t, st_)) || (st = upload(pl, &P.sig_a, sa)) ||
       (st = upload(pl, &P.sig_s, ss)) || (st = upload(pl, &P.q, q)) ||
       (st = upload(pl, &P.cE, cE)) || (st = upload(pl, &P.cW, cW)) ||
       (st = upload(pl, &P.cN, cN)) || (st = upload(pl, &P.cS, cS)) ||
       (st = dalloc(pl, &P.src, N)) || (st = dalloc(pl, &P.phi, N)) ||
       (st = dalloc(pl, &P.phih, N)) || (st = dalloc(pl, &P.Fx, N)) ||
+      (st = dalloc(pl, &P.mom_part, (size_t)12 * N)) ||
       (st = dalloc(pl, &P.Fy, N)) || (st = dalloc(pl, &P.delta, N)) ||
       (st = dalloc(pl, &P.hx, N)) || (st = dalloc(pl, &P.hy, N)) ||
       (st = dalloc(pl, &P.rhs, N)) || (st = upload(pl, &P.bnd, bnd_int)) ||
@@ -559,8 +583,7 @@ extern "C" gsis_status gsis_plan_iterate(gsis_plan *pl, int32_t n) {
   for (int it = 0; it < n; ++it) {
     if (pl->profile && pl->prof_iters >= 100000) pl->profile = 0;
     if ((st = record(pl, 0))) return st;
-    launch_residual(P, s);
-    launch_sweep(P, s);
+    launch_transport(P, s);
     launch_moments(P, s);
     if ((st = record(pl, 1))) return st;
     if (P.method == GSIS_GSIS) {

@@ -4,9 +4,9 @@
 //  * ordinates are regrouped by quadrant q (sign of mu, sign of eta); inside
 //    quadrant q the grid is mirrored so that every quadrant sweeps towards
 //    +x', +y' (local coordinates x' = i or nx-1-i, y' = j or ny-1-j);
-//  * the angular intensity is ordinate-major: I[kk][y'][x'] with kk the
-//    internal ordinate index (quadrant-major). A row of one ordinate is a
-//    contiguous stream, which is what a wavefront lane walks;
+//  * the angular intensity is ordinate-major, I[kk][dg_idx(x', y')] with kk
+//    the internal ordinate index (quadrant-major) and the cells of each
+//    ordinate in anti-diagonal order (dg_idx below);
 //  * every per-cell array is in the caller's order c = j*nx + i.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -17,6 +17,25 @@
 namespace gsis {
 
 constexpr double kFourPi = 12.566370614359172953850573533118;
+
+// Anti-diagonal storage order of an nx x ny grid (in a quadrant's mirrored
+// frame): cells are stored diagonal by diagonal (d = x + y), rows ascending
+// inside a diagonal. A wavefront step touches one diagonal, so the lanes of a
+// step read and write contiguous memory.
+__host__ __device__ inline long long dg_off(long long d, long long nx, long long ny) {
+  const long long A = nx < ny ? nx : ny, B = nx < ny ? ny : nx;
+  if (d <= A) return d * (d + 1) / 2;
+  long long o = A * (A + 1) / 2;
+  if (d <= B) return o + (d - A) * A;
+  o += (B - A) * A;
+  const long long t = d - B;
+  return o + t * (nx + ny - 1 - B) - t * (t - 1) / 2;
+}
+__host__ __device__ inline int dg_ylo(int d, int nx) { return d - nx + 1 > 0 ? d - nx + 1 : 0; }
+__host__ __device__ inline long long dg_idx(int x, int y, int nx, int ny) {
+  const int d = x + y;
+  return dg_off(d, nx, ny) + (y - dg_ylo(d, nx));
+}
 
 // One multigrid level of the synthetic operator D1 (5-point, SPD):
 //   (D x)_c = diag_c x_c - ax_c x_{c+1} - ax_{c-1} x_{c-1}
@@ -44,12 +63,19 @@ struct PlanDev {
   // intensities (two copies) and the residual buffer, [K][N] local layout
   double *I[2] = {nullptr, nullptr};
   double *R = nullptr;
+  // per quadrant, in that quadrant's mirrored frame: cellq[q][N][6] =
+  // (cE, cW, cN, cS, sigma_t, 0) with E/W/N/S local; dynq[q][2][N] =
+  // planes src and delta/(4 pi), rewritten after every update
+  double *cellq = nullptr, *dynq = nullptr;
+  double *rowbuf = nullptr;    // [K][3][nx] hand-off between sweep passes
+  int sweep_impl = 0;          // 0 fused wavefront sweep, 1 two-kernel reference
   // per cell
   double *sig_t = nullptr, *sig_a = nullptr, *sig_s = nullptr, *q = nullptr;
   double *cE = nullptr, *cW = nullptr, *cN = nullptr, *cS = nullptr;  // ALSM
   double *src = nullptr;       // (sigma_s phi^m + q)/(4 pi)
   double *phi = nullptr;       // phi^m
   double *phih = nullptr, *Fx = nullptr, *Fy = nullptr;  // moments of I^{m+1/2}
+  double *mom_part = nullptr;  // [4][3][N] per-quadrant partial moments
   double *delta = nullptr;     // pending GSIS correction (phi' - phi_half)
   double *hx = nullptr, *hy = nullptr;   // HoT
   double *rhs = nullptr;
@@ -74,8 +100,7 @@ struct PlanDev {
 };
 
 // ---- transport kernels (kernels_transport.hip)
-void launch_residual(const PlanDev &P, hipStream_t s);
-void launch_sweep(const PlanDev &P, hipStream_t s);
+void launch_transport(const PlanDev &P, hipStream_t s);   // residual + sweep
 void launch_moments(const PlanDev &P, hipStream_t s);
 void launch_boundary_flux(const PlanDev &P, hipStream_t s);
 

@@ -324,12 +324,25 @@ __global__ void k_err_finish(const double *part, int npart, double tol, int max_
   }
 }
 
-// src = (sigma_s phi + q) / (4 pi)
-__global__ void k_source(int n, const double *sig_s, const double *q, const double *phi,
-                         double *src, const int32_t *state) {
+// src = (sigma_s phi + q) / (4 pi); the mirrored per-quadrant copies of
+// (src, delta/(4 pi)) read by the fused sweep.
+__global__ void k_source(int nx, int ny, const double *sig_s, const double *q,
+                         const double *phi, const double *delta, double *src, double *dynq,
+                         const int32_t *state) {
   if (state[1] != 0) return;
+  const int n = nx * ny;
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c < n) src[c] = (sig_s[c] * phi[c] + q[c]) / kFourPi;
+  if (c >= n) return;
+  const double sc = (sig_s[c] * phi[c] + q[c]) / kFourPi;
+  const double dq = delta[c] / kFourPi;
+  src[c] = sc;
+  const int i = c % nx, j = c / nx;
+  for (int qd = 0; qd < 4; ++qd) {
+    const int xl = (qd & 1) ? nx - 1 - i : i, yl = (qd & 2) ? ny - 1 - j : j;
+    const size_t o = (size_t)qd * 2 * n + dg_idx(xl, yl, nx, ny);
+    dynq[o] = sc;          // plane 0 of quadrant qd
+    dynq[o + n] = dq;      // plane 1
+  }
 }
 
 // Final F with the pending correction: F = F_half + delta/(4 pi) sum_k w Omega_k
@@ -345,8 +358,8 @@ __global__ void k_final_flux(int n, const double *Fx, const double *Fy, const do
 }  // namespace
 
 void launch_source(const PlanDev &P, hipStream_t s) {
-  hipLaunchKernelGGL(k_source, dim3(nblk(P.N)), dim3(kRedBlock), 0, s, P.N, P.sig_s, P.q,
-                     P.phi, P.src, P.state);
+  hipLaunchKernelGGL(k_source, dim3(nblk(P.N)), dim3(kRedBlock), 0, s, P.nx, P.ny, P.sig_s, P.q,
+                     P.phi, P.delta, P.src, P.dynq, P.state);
 }
 
 void launch_hot_rhs(const PlanDev &P, hipStream_t s) {
@@ -416,8 +429,7 @@ void launch_update(const PlanDev &P, hipStream_t s) {
                      P.phih, P.phi, P.delta, P.err_parts, P.state);
   hipLaunchKernelGGL(k_err_finish, dim3(1), dim3(kRedBlock), 0, s, P.err_parts, nb, P.tol,
                      P.max_iter, P.err_hist, P.last_err, P.state);
-  hipLaunchKernelGGL(k_source, dim3(nb), dim3(kRedBlock), 0, s, P.N, P.sig_s, P.q, P.phi, P.src,
-                     P.state);
+  launch_source(P, s);
 }
 
 void launch_apply_delta_final(const PlanDev &P, hipStream_t s, double swmu, double sweta,

@@ -32,6 +32,8 @@ struct TArgs {
   const double *cE, *cW, *cN, *cS;
   const double *bnd;
   double *phih, *Fx, *Fy, *bflux;
+  const double *cellq, *dynq;
+  double *rowbuf;
   const int32_t *state;
 };
 
@@ -45,6 +47,7 @@ TArgs make_args(const PlanDev &P) {
   a.sig_t = P.sig_t; a.src = P.src; a.delta = P.delta;
   a.cE = P.cE; a.cW = P.cW; a.cN = P.cN; a.cS = P.cS;
   a.bnd = P.bnd; a.phih = P.phih; a.Fx = P.Fx; a.Fy = P.Fy; a.bflux = P.bflux;
+  a.cellq = P.cellq; a.dynq = P.dynq; a.rowbuf = P.rowbuf;
   a.state = P.state;
   return a;
 }
@@ -64,7 +67,7 @@ __device__ inline int gcell(const TArgs &a, int q, int xl, int yl) {
 
 // I^m at a local cell of ordinate kk (buffer value plus pending correction)
 __device__ inline double Im(const TArgs &a, const double *Ik, int q, int xl, int yl) {
-  return Ik[(size_t)yl * a.nx + xl] + a.delta[gcell(a, q, xl, yl)] * kInv4Pi;
+  return Ik[dg_idx(xl, yl, a.nx, a.ny)] + a.delta[gcell(a, q, xl, yl)] * kInv4Pi;
 }
 
 // Outgoing face values of a local cell (its local east and north faces):
@@ -133,7 +136,7 @@ __global__ void k_residual(TArgs a) {
   const int c = gcell(a, q, xl, yl);
   const double u = ld(xl, yl);
   const double r = a.src[c] - a.sig_t[c] * u - a.amu[kk] * (Fe - Few) - a.aeta[kk] * (Fn - Fns);
-  a.R[(size_t)kk * a.N + t] = r;
+  a.R[(size_t)kk * a.N + dg_idx(xl, yl, a.nx, a.ny)] = r;
 }
 
 // Exact increment solve for one ordinate per workgroup. Thread t of a pass
@@ -164,10 +167,10 @@ __global__ void k_sweep(TArgs a) {
       double below = __shfl_up(prev, 1, 64);
       if (lane == 0) {
         if (wave > 0) below = edge[(s + 1) & 1][wave - 1];
-        else below = (y0 > 0 && xl >= 0 && xl < a.nx) ? Rk[(size_t)(y0 - 1) * a.nx + xl] : 0.0;
+        else below = (y0 > 0 && xl >= 0 && xl < a.nx) ? Rk[dg_idx(xl, y0 - 1, a.nx, a.ny)] : 0.0;
       }
       if (rowok && xl >= 0 && xl < a.nx) {
-        const size_t o = (size_t)yl * a.nx + xl;
+        const size_t o = dg_idx(xl, yl, a.nx, a.ny);
         const int c = gcell(a, q, xl, yl);
         const double west = xl > 0 ? prev : 0.0;
         const double s_ = yl > 0 ? below : 0.0;
@@ -184,23 +187,296 @@ __global__ void k_sweep(TArgs a) {
   }
 }
 
-// phi, F of I^{m+1/2}: one thread per cell, sum over every ordinate.
-__global__ void k_moments(TArgs a) {
+
+// ---------------------------------------------------------------------------
+// Fused transport step: residual (Eq. RTE_d_res) and exact first-order-upwind
+// increment solve (Eqs. RTE_d_increment..elem_mtx) in one pass over I.
+//
+// One workgroup per ordinate covers the whole grid in the ordinate's
+// mirrored frame (flow towards +x', +y'). Thread t owns local row y0 + t and
+// walks its row; at step s it is at column x = s - t, so a workgroup step
+// advances one anti-diagonal and every dependency (west: the lane's own
+// previous value; south: lane t-1's previous value) is one step old.
+//   * I^m is read once: each lane keeps u(x-1), u(x), u(x+1) of its row in
+//     registers; u(x, y-1) and u(x, y+1) are the neighbours' window values
+//     (lane shifts; across waves an LDS slot written one step earlier).
+//   * face values F_e, F_n of a cell are computed once, by the cell's lane;
+//     the west face is the lane's previous F_e, the south face lane t-1's
+//     previous F_n.
+//   * loads for column x+1 are issued PF steps ahead into a register ring,
+//     so memory latency stays off the wavefront's critical path.
+// I^{m+1/2} = I^m + dI is written once.
+// ---------------------------------------------------------------------------
+__device__ inline double rcp64(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+struct Slot {
+  double ib, dq;       // I^m buffer value and delta/(4 pi) at column x+2
+  double src;          // (sigma_s phi + q)/(4 pi) at column x+1
+  double2 c0, c1;      // (cE, cW), (cN, cS) at column x+1, mirrored frame
+  double st;           // sigma_t at column x+1
+  int i1;              // storage index of column x+1 (clamped)
+};
+
+// Walks the anti-diagonals of an nx x ny grid one at a time (scalar state):
+// first storage index, first row and length of diagonal d, with d clamped
+// into the grid's diagonal range.
+struct DiagCursor {
+  int nx, ny, d, off, lo, len;
+  __device__ void init(int nx_, int ny_, int d0) {
+    nx = nx_; ny = ny_;
+    const int dc = min(max(d0, 0), nx + ny - 2);
+    d = d0;
+    off = (int)dg_off(dc, nx, ny);
+    lo = dg_ylo(dc, nx);
+    len = (int)(dg_off(dc + 1, nx, ny) - off);
+  }
+  __device__ void advance() {
+    ++d;
+    if (d >= 1 && d <= nx + ny - 2) {     // move to the next diagonal
+      off += len;
+      lo = d - nx + 1 > 0 ? d - nx + 1 : 0;
+      const int hi = d < ny - 1 ? d : ny - 1;
+      len = hi - lo + 1;
+    }
+  }
+  // storage index of row y on the current diagonal, clamped into it
+  __device__ int index(int y) const { return off + min(max(y - lo, 0), len - 1); }
+};
+
+constexpr int kSouthCap = 2048;   // south-inflow row staged in LDS up to this width
+
+// The lane is software-pipelined: at step s it solves the increment of
+// column x = s - t with the residual it formed at step s-1, and forms the
+// residual of column x+1 for step s+1. Only the recurrence
+// dI = b + cx dI_west + cy dI_south waits on the neighbour exchange.
+// GENERAL = false assumes ny <= blockDim.x (one pass) and nx <= kSouthCap, so
+// that no load outside the prefetch ring sits on the step path.
+template <int PF, int MAXW, bool GENERAL>
+__global__ void __launch_bounds__(MAXW * 64) k_sweep_fused(TArgs a) {
+  if (a.state[1] != 0) return;
+  const int kk = blockIdx.x;
+  const int q = quadrant_of(a, kk);
+  const int nx = a.nx, ny = a.ny, N = a.N;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nwav = blockDim.x >> 6;
+  const int rows_pp = blockDim.x;
+  const double ax = a.amu[kk], ay = a.aeta[kk];
+  const double hdx = 0.5 * a.dx, hdy = 0.5 * a.dy;
+  const bool second = a.order >= 2, lim = a.limiter != 0;
+  const double *Ik = Iin_of(a) + (size_t)kk * N;
+  double *Ok = Iout_of(a) + (size_t)kk * N;
+  const double *Cq = a.cellq + (size_t)q * N * 6;
+  const double2 *C2 = reinterpret_cast<const double2 *>(Cq);
+  const double *SRC = a.dynq + (size_t)q * 2 * N;   // plane 0: src, plane 1: delta/(4 pi)
+  const double *DQ = SRC + N;
+  double *RB = a.rowbuf + (size_t)kk * 3 * nx;
+  __shared__ double xup[2][MAXW][3];
+  __shared__ double xdn[2][MAXW];
+  __shared__ double south[kSouthCap];
+  // inflow on the local south face of row 0, staged once
+  for (int x = tid; x < min(nx, kSouthCap); x += blockDim.x) {
+    const int i = (q & 1) ? nx - 1 - x : x;
+    const int f = (q & 2) ? 2 * ny + nx + i : 2 * ny + i;
+    south[x] = a.bnd[(size_t)f * a.K + kk];
+  }
+  __syncthreads();
+
+  for (int y0 = 0; y0 < ny; y0 += rows_pp) {
+    const int rows = min(rows_pp, ny - y0);
+    const int y = y0 + tid;
+    const bool rowok = tid < rows;
+    const int yc = rowok ? y : y0;               // clamped row for addresses
+    const bool hn = y + 1 < ny, hs = y > 0;
+    const bool ntop = rowok && tid == rows - 1 && hn;   // north row lies in the next pass
+    const bool sfirst = tid == 0 && y0 > 0;             // south row lies in the previous pass
+    const bool handoff = rowok && tid == rows - 1 && y0 + rows < ny;
+    // inflow on the local west face of this row
+    double inW = 0.0;
+    if (rowok) {
+      const int j = (q & 2) ? ny - 1 - y : y;
+      const int f = (q & 1) ? ny + j : j;
+      inW = a.bnd[(size_t)f * a.K + kk];
+    }
+    // Every lane of a step sits on the same diagonal (x = d - y), so the
+    // diagonal's offset is scalar state and the lanes address consecutive
+    // cells. The cursor runs PF steps ahead, on the diagonal of column x+2
+    // of the step being loaded; indices of lanes outside the grid are
+    // clamped into the diagonal (never used).
+    DiagCursor cur;
+    cur.init(nx, ny, y0);                     // column x+1 of step -1
+    int inext = cur.index(yc);
+    auto load = [&](Slot &sl) {
+      const int i1 = inext;                    // column x+1
+      cur.advance();
+      inext = cur.index(yc);                   // column x+2
+      sl.i1 = i1;
+      sl.ib = Ik[inext];
+      sl.dq = DQ[inext];
+      sl.src = SRC[i1];
+      sl.c0 = C2[3 * i1];
+      sl.c1 = C2[3 * i1 + 1];
+      sl.st = Cq[6 * i1 + 4];
+    };
+    Slot ring[PF];
+#pragma unroll
+    for (int t = 0; t < PF; ++t) load(ring[t]);
+    // u of columns x, x+1, x+2 (the residual column is x+1). Lane 0 forms
+    // the residual of column 0 at step -1, so its window starts at u(0, y);
+    // the other lanes fill their windows from the ring before they start.
+    double uw = 0.0, uc = 0.0, ue;
+    {
+      const long long i00 = dg_idx(0, yc, nx, ny);
+      ue = Ik[i00] + DQ[i00];
+    }
+    // pipeline registers: residual of column x (b = r / d, cx, cy), face
+    // values of the residual column, increment of the chain column
+    double b_c = 0.0, cx_c = 0.0, cy_c = 0.0, u_c = 0.0;
+    int i_c = 0;
+    double Fe_p = 0.0, Fn_p = 0.0, dI_p = 0.0;
+    // steps -1 .. nx+rows-1, padded to a multiple of PF (padding steps have
+    // no active lane); at step s the chain column is s - tid and the
+    // residual column s - tid + 1
+    const int nsteps = ((nx + rows + 1 + PF - 1) / PF) * PF;
+    for (int sb = -1; sb < nsteps - 1; sb += PF) {
+#pragma unroll
+      for (int t = 0; t < PF; ++t) {
+        const int s = sb + t;
+        const int x = s - tid;                 // chain column
+        const int xr = x + 1;                  // residual column
+        uw = uc; uc = ue;
+        ue = ring[t].ib + ring[t].dq;          // u(x+2)
+        // --- exchange with the rows below and above
+        double sU = __shfl_up(uw, 1, 64);      // u(xr, y-1)
+        double sFn = __shfl_up(Fn_p, 1, 64);   // F_n(xr, y-1)
+        double sdI = __shfl_up(dI_p, 1, 64);   // dI(x, y-1)
+        double nU = __shfl_down(ue, 1, 64);    // u(xr, y+1)
+        if (lane == 0 && wave > 0) {
+          sU = xup[(s + 1) & 1][wave - 1][0];
+          sFn = xup[(s + 1) & 1][wave - 1][1];
+          sdI = xup[(s + 1) & 1][wave - 1][2];
+        }
+        if (lane == 63 && wave + 1 < nwav) nU = xdn[(s + 1) & 1][wave + 1];
+        const bool actc = rowok && x >= 0 && x < nx;      // chain
+        const bool actr = rowok && xr >= 0 && xr < nx;    // residual
+        if (GENERAL && sfirst) {                  // previous pass's top row
+          if (actr) { sU = RB[xr]; sFn = RB[nx + xr]; }
+          if (actc) sdI = RB[2 * nx + x];
+        }
+        if (GENERAL && actr && ntop) {            // next pass's bottom row
+          const int o = dg_idx(xr, y + 1, nx, ny);
+          nU = Ik[o] + DQ[o];
+        }
+        // --- increment of the chain column (uses last step's residual)
+        double dI = 0.0;
+        if (actc) {
+          const double dW = x > 0 ? dI_p : 0.0, dS = hs ? sdI : 0.0;
+          dI = fma(cx_c, dW, fma(cy_c, dS, b_c));
+          Ok[i_c] = u_c + dI;
+          if (GENERAL && handoff) RB[2 * nx + x] = dI;
+        }
+        // --- residual of column xr for the next step
+        double Fn = uc;
+        if (actr) {
+          const double u = uc;
+          const double st = ring[t].st;
+          double Fe = u;
+          if (second) {
+            const double UE = xr + 1 < nx ? ue : u, UW = xr > 0 ? uw : u;
+            const double UN = hn ? nU : u, US = hs ? sU : u;
+            const double gx = ring[t].c0.x * (UE - u) - ring[t].c0.y * (UW - u);
+            const double gy = ring[t].c1.x * (UN - u) - ring[t].c1.y * (US - u);
+            const double hx = gx * hdx, hy = gy * hdy;
+            double psi = 1.0;
+            if (lim) {
+              const double umax = fmax(fmax(fmax(u, UE), fmax(UW, UN)), US);
+              const double umin = fmin(fmin(fmin(u, UE), fmin(UW, UN)), US);
+              const double m = fmin(umax - u, u - umin);
+              const double M = fmax(fabs(hx), fabs(hy));
+              if (M > m) psi = m * rcp64(M);
+            }
+            Fe = fma(psi, hx, u);
+            Fn = fma(psi, hy, u);
+          }
+          double FnS = sFn;
+          if (!hs) {
+            if (!GENERAL || xr < kSouthCap) {
+              FnS = south[xr];
+            } else {
+              const int i = (q & 1) ? nx - 1 - xr : xr;
+              FnS = a.bnd[(size_t)((q & 2) ? 2 * ny + nx + i : 2 * ny + i) * a.K + kk];
+            }
+          }
+          const double FeW = xr > 0 ? Fe_p : inW;
+          const double r = ring[t].src - st * u - ax * (Fe - FeW) - ay * (Fn - FnS);
+          const double inv = rcp64(st + ax + ay);
+          b_c = r * inv; cx_c = ax * inv; cy_c = ay * inv;
+          u_c = u; i_c = ring[t].i1;
+          if (GENERAL && handoff) { RB[xr] = u; RB[nx + xr] = Fn; }
+          Fe_p = Fe;
+        }
+        Fn_p = Fn; dI_p = dI;
+        if (lane == 63) {
+          xup[s & 1][wave][0] = uc; xup[s & 1][wave][1] = Fn; xup[s & 1][wave][2] = dI;
+        }
+        if (lane == 0) xdn[s & 1][wave] = ring[(t + 1) % PF].ib + ring[(t + 1) % PF].dq;
+        load(ring[t]);                            // refill this slot PF steps ahead
+        __builtin_amdgcn_s_waitcnt(0xc07f);     // LDS writes done (lgkmcnt 0 only)
+        __builtin_amdgcn_s_barrier();
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// phi, F of I^{m+1/2} in two passes: per quadrant, one thread per stored
+// cell sums the quadrant's ordinates (contiguous reads) into partials at the
+// caller's cell index; then the four partials are added in a fixed order.
+__device__ inline void dg_cell(long long t, int nx, int ny, int &x, int &y) {
+  int lo = 0, hi = nx + ny - 2;               // find d with off(d) <= t < off(d+1)
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (dg_off(mid, nx, ny) <= t) lo = mid; else hi = mid - 1;
+  }
+  y = dg_ylo(lo, nx) + (int)(t - dg_off(lo, nx, ny));
+  x = lo - y;
+}
+
+__global__ void k_moments_q(TArgs a, double *part) {
+  if (a.state[1] != 0) return;
+  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  const int q = blockIdx.y;
+  if (t >= a.N) return;
+  int x, y;
+  dg_cell(t, a.nx, a.ny, x, y);
+  const int c = gcell(a, q, x, y);
+  const double *O = Iout_of(a);
+  double s0 = 0, sx = 0, sy = 0;
+  for (int kk = a.qoff[q]; kk < a.qoff[q + 1]; ++kk) {
+    const double v = O[(size_t)kk * a.N + t];
+    s0 += a.w[kk] * v;
+    sx += a.wmu[kk] * v;
+    sy += a.weta[kk] * v;
+  }
+  part[(size_t)(3 * q) * a.N + c] = s0;
+  part[(size_t)(3 * q + 1) * a.N + c] = sx;
+  part[(size_t)(3 * q + 2) * a.N + c] = sy;
+}
+
+__global__ void k_moments_combine(TArgs a, const double *part) {
   if (a.state[1] != 0) return;
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= a.N) return;
-  const int i = c % a.nx, j = c / a.nx;
   double s0 = 0, sx = 0, sy = 0;
   for (int q = 0; q < 4; ++q) {
-    const int xl = (q & 1) ? a.nx - 1 - i : i;
-    const int yl = (q & 2) ? a.ny - 1 - j : j;
-    const size_t o = (size_t)yl * a.nx + xl;
-    for (int kk = a.qoff[q]; kk < a.qoff[q + 1]; ++kk) {
-      const double v = Iout_of(a)[(size_t)kk * a.N + o];
-      s0 += a.w[kk] * v;
-      sx += a.wmu[kk] * v;
-      sy += a.weta[kk] * v;
-    }
+    s0 += part[(size_t)(3 * q) * a.N + c];
+    sx += part[(size_t)(3 * q + 1) * a.N + c];
+    sy += part[(size_t)(3 * q + 2) * a.N + c];
   }
   a.phih[c] = s0; a.Fx[c] = sx; a.Fy[c] = sy;
 }
@@ -232,7 +508,7 @@ __global__ void k_boundary_flux(TArgs a) {
       int xl = (q & 1) ? a.nx - 1 - i : i;
       int yl = (q & 2) ? a.ny - 1 - j : j;
       const double *Ok = Iout_of(a) + (size_t)kk * a.N;
-      auto ld = [&](int x, int y) { return Ok[(size_t)y * a.nx + x]; };
+      auto ld = [&](int x, int y) { return Ok[dg_idx(x, y, a.nx, a.ny)]; };
       double Fe, Fn;
       out_faces(a, q, xl, yl, ld, Fe, Fn);
       val = side < 2 ? Fe : Fn;
@@ -251,22 +527,30 @@ __global__ void k_boundary_flux(TArgs a) {
 
 }  // namespace
 
-void launch_residual(const PlanDev &P, hipStream_t s) {
-  TArgs a = make_args(P);
-  dim3 g((P.N + 255) / 256, P.K);
-  hipLaunchKernelGGL(k_residual, g, dim3(256), 0, s, a);
-}
-
-void launch_sweep(const PlanDev &P, hipStream_t s) {
+void launch_transport(const PlanDev &P, hipStream_t s) {
   TArgs a = make_args(P);
   int rows = ((P.ny + 63) / 64) * 64;
   if (rows > 1024) rows = 1024;
-  hipLaunchKernelGGL(k_sweep, dim3(P.K), dim3(rows), 0, s, a);
+  if (P.sweep_impl == 1) {
+    // two-kernel reference: residual into R, then the wavefront solve
+    dim3 g((P.N + 255) / 256, P.K);
+    hipLaunchKernelGGL(k_residual, g, dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_sweep, dim3(P.K), dim3(rows), 0, s, a);
+    return;
+  }
+  const int w = rows / 64;
+  const bool general = P.ny > rows || P.nx > kSouthCap;
+  if (general) hipLaunchKernelGGL((k_sweep_fused<2, 16, true>), dim3(P.K), dim3(rows), 0, s, a);
+  else if (w <= 4) hipLaunchKernelGGL((k_sweep_fused<6, 4, false>), dim3(P.K), dim3(rows), 0, s, a);
+  else if (w <= 8) hipLaunchKernelGGL((k_sweep_fused<4, 8, false>), dim3(P.K), dim3(rows), 0, s, a);
+  else hipLaunchKernelGGL((k_sweep_fused<2, 16, false>), dim3(P.K), dim3(rows), 0, s, a);
 }
 
 void launch_moments(const PlanDev &P, hipStream_t s) {
   TArgs a = make_args(P);
-  hipLaunchKernelGGL(k_moments, dim3((P.N + 255) / 256), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_moments_q, dim3((P.N + 255) / 256, 4), dim3(256), 0, s, a, P.mom_part);
+  hipLaunchKernelGGL(k_moments_combine, dim3((P.N + 255) / 256), dim3(256), 0, s, a,
+                     (const double *)P.mom_part);
 }
 
 void launch_boundary_flux(const PlanDev &P, hipStream_t s) {
