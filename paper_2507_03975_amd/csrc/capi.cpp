@@ -370,7 +370,7 @@ extern "C" gsis_status gsis_plan_create(gsis_ctx *ctx, const gsis_problem *p,
   // couplings in one direction are much weaker than in the other (then
   // merging across the weak direction would leave error the point smoother
   // cannot reach).
-  const int kCoarseMax = 256;
+  const int kCoarseMax = 64;   // dense inverse of the coarsest level: at most 64 x 64
   while ((long)hl.back().nx * hl.back().ny > kCoarseMax && (hl.back().nx > 1 || hl.back().ny > 1)) {
     HostLevel &F = hl.back();
     double lx = 0, ly = 0;
@@ -495,7 +495,8 @@ extern "C" gsis_status gsis_plan_create(gsis_ctx *ctx, const gsis_problem *p,
       (st = dalloc(pl, &P.rhs, N)) || (st = upload(pl, &P.bnd, bnd_int)) ||
       (st = dalloc(pl, &P.bflux, P.nbf)) || (st = upload(pl, &P.kappa, kap)) ||
       (st = dalloc(pl, &P.cg_r, N)) || (st = dalloc(pl, &P.cg_z, N)) ||
-      (st = dalloc(pl, &P.cg_p, N)) || (st = dalloc(pl, &P.cg_Ap, N)) ||
+      (st = dalloc(pl, &P.cg_p, N)) || (st = dalloc(pl, &P.cg_p2, N)) ||
+      (st = dalloc(pl, &P.cg_Ap, N)) ||
       (st = dalloc(pl, &P.scal, 16)) || (st = dalloc(pl, &P.err_hist, o->max_iter)) ||
       (st = dalloc(pl, &P.state, 4)) || (st = dalloc(pl, &P.last_err, 1)))
     return bail(st);
@@ -515,6 +516,7 @@ extern "C" gsis_status gsis_plan_create(gsis_ctx *ctx, const gsis_problem *p,
   }
   P.coarse_n = nc;
   if ((st = upload(pl, &P.coarse_inv, dense))) return bail(st);
+  prepare_synth(P);
   {
     void *h = nullptr;
     hipError_t e = hipHostMalloc(&h, 64, hipHostMallocDefault);
@@ -591,7 +593,7 @@ extern "C" gsis_status gsis_plan_iterate(gsis_plan *pl, int32_t n) {
       launch_hot_rhs(P, s);
     }
     if ((st = record(pl, 2))) return st;
-    if (P.method == GSIS_GSIS) launch_synth_solve(P, s, pl->host_scal);
+    if (P.method == GSIS_GSIS) launch_synth_solve(P, s, (int32_t *)pl->host_scal);
     if ((st = record(pl, 3))) return st;
     launch_update(P, s);
     if ((st = record(pl, 4))) return st;

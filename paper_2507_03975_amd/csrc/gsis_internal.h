@@ -87,7 +87,7 @@ struct PlanDev {
   std::vector<MGLevel> mg;
   double *coarse_inv = nullptr;  // dense inverse of the coarsest operator
   int coarse_n = 0;
-  double *cg_r = nullptr, *cg_z = nullptr, *cg_p = nullptr, *cg_Ap = nullptr;
+  double *cg_r = nullptr, *cg_z = nullptr, *cg_p = nullptr, *cg_p2 = nullptr, *cg_Ap = nullptr;
   double *red = nullptr;       // block partial sums
   double *scal = nullptr;      // device scalars (see kernels_synth.hip)
   int red_blocks = 0;
@@ -95,7 +95,8 @@ struct PlanDev {
   double *err_hist = nullptr;  // [max_iter]
   double *err_parts = nullptr; // block partials for Err
   int32_t *state = nullptr;    // [0] iterations done, [1] done flag (1 converged,
-                               // -1 diverged, 2 max_iter), [2] current I buffer
+                               // -1 diverged, 2 max_iter), [2] current I buffer,
+                               // [3] synthetic CG converged
   double *last_err = nullptr;
 };
 
@@ -107,7 +108,8 @@ void launch_boundary_flux(const PlanDev &P, hipStream_t s);
 // ---- synthetic / update kernels (kernels_synth.hip)
 void launch_source(const PlanDev &P, hipStream_t s);          // src from phi
 void launch_hot_rhs(const PlanDev &P, hipStream_t s);
-void launch_synth_solve(PlanDev &P, hipStream_t s, double *host_scal);
+void prepare_synth(PlanDev &P);
+void launch_synth_solve(PlanDev &P, hipStream_t s, int32_t *host_flag);
 void launch_update(const PlanDev &P, hipStream_t s);
 void launch_apply_delta_final(const PlanDev &P, hipStream_t s, double swmu, double sweta,
                               double *Fx_out, double *Fy_out);
