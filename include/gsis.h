@@ -113,6 +113,17 @@ typedef struct {
                             gsis_result is device memory; 0: host memory */
   int32_t profile;       /* 1: record HIP events around each phase so that
                             gsis_plan_phase_times() can report them */
+  double cfl_p;          /* global pseudo-time number CFL_p (Sec. 4.3, Eq.
+                            cfl_pse): adds 1/(CFL_p dx_ref) to the diagonal
+                            of every cell's increment solve; 0 = off
+                            (default). dx_ref = min(dx, dy) */
+  double beta;           /* local pseudo-time parameter beta (Eq. tau_pse):
+                            adds max over face neighbours j of
+                            |sigma_t,i r^L_ij - sigma_t,j r^R_ij| / (beta
+                            dx_ref) to cell i's increment-solve diagonal,
+                            which damps the increments of thin cells beside
+                            thick ones; 0 = off (default). Neither shift
+                            changes the fixed point (Eq. elem_main_shifted) */
 } gsis_options;
 
 /* Fill *o with the defaults listed above. */
@@ -150,11 +161,12 @@ gsis_status gsis_plan_read(gsis_plan *plan, gsis_result *r);
 gsis_status gsis_plan_reset(gsis_plan *plan);
 
 enum {
-  GSIS_PHASE_SWEEP = 0,    /* transport residual + exact sweep + moments */
-  GSIS_PHASE_HOT = 1,      /* boundary fluxes, HoT, synthetic right-hand side */
-  GSIS_PHASE_SYNTH = 2,    /* synthetic CG + multigrid solve */
-  GSIS_PHASE_UPDATE = 3,   /* correction and Err */
-  GSIS_NUM_PHASES = 4
+  GSIS_PHASE_SWEEP = 0,    /* transport residual + exact sweep (one kernel) */
+  GSIS_PHASE_MOMENTS = 1,  /* phi and F of the swept intensity */
+  GSIS_PHASE_HOT = 2,      /* boundary fluxes, HoT, synthetic right-hand side */
+  GSIS_PHASE_SYNTH = 3,    /* synthetic CG + multigrid solve */
+  GSIS_PHASE_UPDATE = 4,   /* correction and Err */
+  GSIS_NUM_PHASES = 5
 };
 /* Wait for the plan's stream; ms[GSIS_NUM_PHASES] receives the summed
  * duration of each phase over all profiled iterations (HIP events on the

@@ -39,7 +39,8 @@ class _Options(ctypes.Structure):
         ("method", ctypes.c_int), ("order", ctypes.c_int),
         ("limiter", ctypes.c_int), ("alsm", ctypes.c_int),
         ("hot_face", ctypes.c_int), ("tol", ctypes.c_double),
-        ("max_iter", ctypes.c_int),
+        ("max_iter", ctypes.c_int), ("cfl_p", ctypes.c_double),
+        ("beta", ctypes.c_double),
     ]
 
 
@@ -67,7 +68,9 @@ def _load():
         lib.ora_bj_limiter.argtypes = [P, _dp, _dp, _dp, _dp]
         lib.ora_face_coeffs.argtypes = [P, _dp, _dp, _dp]
         lib.ora_residual.argtypes = [P, O, _dp, _dp]
-        lib.ora_sweep.argtypes = [P, _dp, _dp]
+        lib.ora_sweep.argtypes = [P, O, _dp, _dp]
+        lib.ora_pseudo_shift.argtypes = [P, O, ctypes.c_int]
+        lib.ora_pseudo_shift.restype = ctypes.c_double
         lib.ora_iterate.argtypes = [P, O, _dp, _dp, _dp]
         lib.ora_iterate.restype = ctypes.c_int
         lib.ora_solve.argtypes = [P, O, _dp, _dp, _dp, _dp, _dp, ip, _dp, _dp]
@@ -99,9 +102,10 @@ class _Marshal:
                           _ptr(self.bnd))
 
 
-def _opts(method=1, order=2, limiter=1, alsm=1, hot_face=0, tol=1e-8, max_iter=1000):
+def _opts(method=1, order=2, limiter=1, alsm=1, hot_face=0, tol=1e-8, max_iter=1000,
+          cfl_p=0.0, beta=0.0):
     return _Options(int(method), int(order), int(limiter), int(alsm), int(hot_face),
-                    float(tol), int(max_iter))
+                    float(tol), int(max_iter), float(cfl_p), float(beta))
 
 
 def gradient(prob, U, alsm=1):
@@ -141,12 +145,23 @@ def residual(prob, I, **opts):
     return r
 
 
-def sweep(prob, r):
+def sweep(prob, r, **opts):
+    """Exact increment solve; ``cfl_p`` / ``beta`` add the pseudo-time shift."""
     m = _Marshal(prob)
     r = np.ascontiguousarray(r, dtype=np.float64)
     dI = np.empty_like(r)
-    _load().ora_sweep(ctypes.byref(m.s), _ptr(r), _ptr(dI))
+    o = _opts(**opts)
+    _load().ora_sweep(ctypes.byref(m.s), ctypes.byref(o), _ptr(r), _ptr(dI))
     return dI
+
+
+def pseudo_shift(prob, **opts):
+    """Per-cell pseudo-time shift of the increment-solve diagonal."""
+    m = _Marshal(prob)
+    o = _opts(**opts)
+    lib = _load()
+    return np.array([lib.ora_pseudo_shift(ctypes.byref(m.s), ctypes.byref(o), c)
+                     for c in range(m.nx * m.ny)])
 
 
 def iterate(prob, I, **opts):

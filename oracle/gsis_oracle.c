@@ -237,13 +237,44 @@ void ora_residual(const ora_problem *p, const ora_options *o, const double *I,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Pseudo-time diagonal shift (Sec. 4.3, Eqs. cfl_pse, tau_pse,               */
+/* elem_main_shifted). The speed of light cancels in 1/(c dt_p):              */
+/*   1/(c dt_p)  = 1 / (CFL_p dx_ref),                                        */
+/*   1/(c tau_p) = max_{j in N(i)} |sig_i r^L_ij - sig_j r^R_ij| / (beta dx_ref)*/
+/* with dx_ref = min(dx, dy). Only the increment solve sees the shift, so the */
+/* fixed point is unchanged.                                                  */
+/* ------------------------------------------------------------------------ */
+double ora_pseudo_shift(const ora_problem *p, const ora_options *o, int c) {
+  if (!o) return 0.0;
+  const double dref = p->dx < p->dy ? p->dx : p->dy;
+  double s = 0.0;
+  if (o->cfl_p > 0) s += 1.0 / (o->cfl_p * dref);
+  if (o->beta > 0) {
+    const int i = c % p->nx, j = c / p->nx;
+    double m = 0.0;
+    for (int f = 0; f < 4; ++f) {
+      const int nb = neighbour(p, i, j, f);
+      if (nb < 0) continue;
+      const double rLx = -face_ox(p, f), rLy = -face_oy(p, f);
+      const double rRx = face_ox(p, f), rRy = face_oy(p, f);
+      const double vx = sig_t(p, c) * rLx - sig_t(p, nb) * rRx;
+      const double vy = sig_t(p, c) * rLy - sig_t(p, nb) * rRy;
+      const double v = sqrt(vx * vx + vy * vy);
+      if (v > m) m = v;
+    }
+    s += m / (o->beta * dref);
+  }
+  return s;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Increment solve (Eqs. RTE_d_increment, delta_Iij, RTE_d_mtx, elem_mtx):    */
 /*   d_ii dI_i + sum_{inflow faces} (Omega.A_ij / V_i) dI_j = r_i,            */
-/*   d_ii = sigma_t + sum_{outflow faces} Omega.A_ij / V_i,                   */
+/*   d_ii = sigma_t + sum_{outflow faces} Omega.A_ij / V_i (+ pseudo shift),  */
 /* first-order upwind increments, zero increments on inflow boundary faces.   */
 /* Cells are visited in upwind order, which makes the solve exact.            */
 /* ------------------------------------------------------------------------ */
-void ora_sweep(const ora_problem *p, const double *r, double *dI) {
+void ora_sweep(const ora_problem *p, const ora_options *o, const double *r, double *dI) {
   const int nx = p->nx, ny = p->ny, K = p->K;
 #pragma omp parallel for schedule(dynamic, 1)
   for (int k = 0; k < K; ++k) {
@@ -252,7 +283,7 @@ void ora_sweep(const ora_problem *p, const double *r, double *dI) {
     for (int jj = 0, j = j0; jj < ny; ++jj, j += dj)
       for (int ii = 0, i = i0; ii < nx; ++ii, i += di) {
         const int c = j * nx + i;
-        double d = sig_t(p, c), rhs = r[(size_t)c * K + k];
+        double d = sig_t(p, c) + ora_pseudo_shift(p, o, c), rhs = r[(size_t)c * K + k];
         for (int f = 0; f < 4; ++f) {
           double on = p->mu[k] * NX_[f] + p->eta[k] * NY_[f];
           if (on > 0) {
@@ -543,7 +574,7 @@ static int iterate_ctx(ora_ctx *X, const double *I_in, double *I_out,
 
   /* residual and exact increment solve */
   ora_residual(p, o, I_in, r);
-  ora_sweep(p, r, dI);
+  ora_sweep(p, o, r, dI);
   free(r);
   /* I^{m+1/2} = I^m + dI */
 #pragma omp parallel for schedule(static)

@@ -38,6 +38,8 @@ typedef struct {
   int hot_face;   /* 0 = central average of cell HoT, 1 = transport face flux */
   double tol;     /* stop when Err(phi) < tol */
   int max_iter;
+  double cfl_p;   /* global pseudo-time number (Eq. cfl_pse); 0 = off */
+  double beta;    /* local pseudo-time parameter (Eq. tau_pse); 0 = off */
 } ora_options;
 
 /* ALSM / LSQ cell gradient of a cell field U[nx*ny] (Sec. 5, Eqs. LSF,
@@ -62,7 +64,13 @@ void ora_residual(const ora_problem *p, const ora_options *o, const double *I,
 
 /* Exact first-order-upwind increment solve per ordinate (Eqs.
  * RTE_d_increment, delta_Iij, RTE_d_mtx, elem_mtx, steady). */
-void ora_sweep(const ora_problem *p, const double *r, double *dI);
+void ora_sweep(const ora_problem *p, const ora_options *o, const double *r,
+               double *dI);
+
+/* Pseudo-time shift of the increment-solve diagonal per cell (Eq.
+ * elem_main_shifted without the physical time term); 0 when o is NULL or
+ * both parameters are 0. */
+double ora_pseudo_shift(const ora_problem *p, const ora_options *o, int c);
 
 /* One outer iteration: I_in -> I_out (Eqs. SI_update or GSIS_update).
  * phi_out receives phi^{m+1}. Returns 0 on success. */

@@ -35,7 +35,7 @@ struct gsis_plan {
   std::vector<double> phi0_host;  // phi of the warm start
   std::vector<void *> allocs;
   double *host_scal = nullptr;    // pinned
-  // profiling: per iteration 5 events bracketing the 4 phases
+  // profiling: per iteration GSIS_NUM_PHASES + 1 events bracketing the phases
   std::vector<hipEvent_t> events;
   int prof_iters = 0;
 };
@@ -101,6 +101,8 @@ gsis_status gsis_options_default(gsis_options *o) {
   o->max_iter = 1000;
   o->synth_rtol = 1e-4;
   o->synth_max_iter = 50;
+  o->cfl_p = 0.0;
+  o->beta = 0.0;
   return GSIS_OK;
 }
 
@@ -153,6 +155,10 @@ gsis_status check_problem(gsis_ctx *ctx, const gsis_problem *p, const gsis_optio
   if (!(o->synth_rtol > 0)) return fail(ctx, GSIS_E_INVALID_ARG, "options.synth_rtol must be > 0");
   if (o->synth_max_iter < 1)
     return fail(ctx, GSIS_E_INVALID_ARG, "options.synth_max_iter must be >= 1");
+  if (!(o->cfl_p >= 0) || !std::isfinite(o->cfl_p))
+    return fail(ctx, GSIS_E_INVALID_ARG, "options.cfl_p must be finite and >= 0");
+  if (!(o->beta >= 0) || !std::isfinite(o->beta))
+    return fail(ctx, GSIS_E_INVALID_ARG, "options.beta must be finite and >= 0");
   const int dev = o->device_ptrs;
   const size_t N = (size_t)p->nx * p->ny, K = p->K;
   gsis_status st;
@@ -428,7 +434,30 @@ extern "C" gsis_status gsis_plan_create(gsis_ctx *ctx, const gsis_problem *p,
   if (!dense_spd_inverse(nc, dense))
     return bail(fail(ctx, GSIS_E_INVALID_ARG, "synthetic operator is not positive definite"));
 
+  // -- pseudo-time shift of the increment-solve diagonal (Eqs. cfl_pse,
+  // tau_pse, elem_main_shifted); |sigma_i r^L - sigma_j r^R| is
+  // (sigma_i h + sigma_j h) / 2 for the face-normal width h
+  std::vector<double> shift(N, 0.0);
+  {
+    const double dref = std::min(p->dx, p->dy);
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        const int c = j * nx + i;
+        double sh = o->cfl_p > 0 ? 1.0 / (o->cfl_p * dref) : 0.0;
+        if (o->beta > 0) {
+          double m = 0.0;
+          if (i > 0) m = std::max(m, 0.5 * (st_[c] + st_[c - 1]) * p->dx);
+          if (i + 1 < nx) m = std::max(m, 0.5 * (st_[c] + st_[c + 1]) * p->dx);
+          if (j > 0) m = std::max(m, 0.5 * (st_[c] + st_[c - nx]) * p->dy);
+          if (j + 1 < ny) m = std::max(m, 0.5 * (st_[c] + st_[c + nx]) * p->dy);
+          sh += m / (o->beta * dref);
+        }
+        shift[c] = sh;
+      }
+  }
+
   // -- per-quadrant coefficient records in each quadrant's mirrored frame
+  //    (cE, cW, cN, cS, sigma_t, sigma_t + pseudo-time shift)
   std::vector<double> cellq((size_t)4 * N * 6, 0.0);
   for (int qd = 0; qd < 4; ++qd)
     for (int yl = 0; yl < ny; ++yl)
@@ -441,6 +470,7 @@ extern "C" gsis_status gsis_plan_create(gsis_ctx *ctx, const gsis_problem *p,
         r[2] = (qd & 2) ? cS[c] : cN[c];
         r[3] = (qd & 2) ? cN[c] : cS[c];
         r[4] = st_[c];
+        r[5] = st_[c] + shift[c];
       }
   {
     const char *e = getenv("GSIS_SWEEP_REFERENCE");
@@ -564,7 +594,7 @@ extern "C" gsis_status gsis_plan_reset(gsis_plan *pl) {
 
 static gsis_status record(gsis_plan *pl, int slot) {
   if (!pl->profile) return GSIS_OK;
-  const size_t idx = (size_t)pl->prof_iters * 5 + slot;
+  const size_t idx = (size_t)pl->prof_iters * (GSIS_NUM_PHASES + 1) + slot;
   while (pl->events.size() <= idx) {
     hipEvent_t e;
     HIPCHK(pl->ctx, hipEventCreate(&e));
@@ -586,17 +616,18 @@ extern "C" gsis_status gsis_plan_iterate(gsis_plan *pl, int32_t n) {
     if (pl->profile && pl->prof_iters >= 100000) pl->profile = 0;
     if ((st = record(pl, 0))) return st;
     launch_transport(P, s);
-    launch_moments(P, s);
     if ((st = record(pl, 1))) return st;
+    launch_moments(P, s);
+    if ((st = record(pl, 2))) return st;
     if (P.method == GSIS_GSIS) {
       launch_boundary_flux(P, s);
       launch_hot_rhs(P, s);
     }
-    if ((st = record(pl, 2))) return st;
-    if (P.method == GSIS_GSIS) launch_synth_solve(P, s, (int32_t *)pl->host_scal);
     if ((st = record(pl, 3))) return st;
-    launch_update(P, s);
+    if (P.method == GSIS_GSIS) launch_synth_solve(P, s, (int32_t *)pl->host_scal);
     if ((st = record(pl, 4))) return st;
+    launch_update(P, s);
+    if ((st = record(pl, 5))) return st;
     HIPCHK(ctx, hipGetLastError());
     if (pl->profile) pl->prof_iters++;
   }
@@ -657,8 +688,8 @@ extern "C" gsis_status gsis_plan_phase_times(gsis_plan *pl, double *ms, int32_t 
   for (int it = 0; it < pl->prof_iters; ++it)
     for (int ph = 0; ph < GSIS_NUM_PHASES; ++ph) {
       float t = 0;
-      HIPCHK(ctx, hipEventElapsedTime(&t, pl->events[(size_t)it * 5 + ph],
-                                      pl->events[(size_t)it * 5 + ph + 1]));
+      const size_t e0 = (size_t)it * (GSIS_NUM_PHASES + 1) + ph;
+      HIPCHK(ctx, hipEventElapsedTime(&t, pl->events[e0], pl->events[e0 + 1]));
       ms[ph] += t;
     }
   if (n_iter) *n_iter = pl->prof_iters;

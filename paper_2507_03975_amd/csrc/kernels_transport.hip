@@ -175,7 +175,8 @@ __global__ void k_sweep(TArgs a) {
         const double west = xl > 0 ? prev : 0.0;
         const double s_ = yl > 0 ? below : 0.0;
         const double r = Rk[o];
-        const double di = (r + ax * west + ay * s_) / (a.sig_t[c] + ax + ay);
+        const double sd = a.cellq[((size_t)q * a.N + o) * 6 + 5];
+        const double di = (r + ax * west + ay * s_) / (sd + ax + ay);
         Ok[o] = Ik[o] + a.delta[c] * kInv4Pi + di;
         if (top) Rk[o] = di;   // hand the top row to the next pass
         prev = di;
@@ -219,7 +220,8 @@ struct Slot {
   double ib, dq;       // I^m buffer value and delta/(4 pi) at column x+2
   double src;          // (sigma_s phi + q)/(4 pi) at column x+1
   double2 c0, c1;      // (cE, cW), (cN, cS) at column x+1, mirrored frame
-  double st;           // sigma_t at column x+1
+  double2 st;          // sigma_t and the increment-solve diagonal's sigma_t
+                       // plus pseudo-time shift, at column x+1
   int i1;              // storage index of column x+1 (clamped)
 };
 
@@ -251,6 +253,18 @@ struct DiagCursor {
 
 constexpr int kSouthCap = 2048;   // south-inflow row staged in LDS up to this width
 
+// Workgroups are dealt to the eight XCDs round-robin (workgroup b runs on
+// XCD b % 8). Workgroup b takes ordinate start(b % 8) + b / 8, which gives
+// every XCD a contiguous run of the (quadrant-sorted) ordinates, so each
+// XCD's L2 holds the per-cell records of one or two quadrants instead of
+// all four. A bijection of [0, K).
+__device__ inline int xcd_ordinate(int b, int K) {
+  const int x = b & 7;
+  int start = 0;
+  for (int xp = 0; xp < x; ++xp) start += (K - xp + 7) >> 3;
+  return start + (b >> 3);
+}
+
 // The lane is software-pipelined: at step s it solves the increment of
 // column x = s - t with the residual it formed at step s-1, and forms the
 // residual of column x+1 for step s+1. Only the recurrence
@@ -260,7 +274,7 @@ constexpr int kSouthCap = 2048;   // south-inflow row staged in LDS up to this w
 template <int PF, int MAXW, bool GENERAL>
 __global__ void __launch_bounds__(MAXW * 64) k_sweep_fused(TArgs a) {
   if (a.state[1] != 0) return;
-  const int kk = blockIdx.x;
+  const int kk = xcd_ordinate(blockIdx.x, a.K);
   const int q = quadrant_of(a, kk);
   const int nx = a.nx, ny = a.ny, N = a.N;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -321,7 +335,7 @@ __global__ void __launch_bounds__(MAXW * 64) k_sweep_fused(TArgs a) {
       sl.src = SRC[i1];
       sl.c0 = C2[3 * i1];
       sl.c1 = C2[3 * i1 + 1];
-      sl.st = Cq[6 * i1 + 4];
+      sl.st = C2[3 * i1 + 2];
     };
     Slot ring[PF];
 #pragma unroll
@@ -384,7 +398,7 @@ __global__ void __launch_bounds__(MAXW * 64) k_sweep_fused(TArgs a) {
         double Fn = uc;
         if (actr) {
           const double u = uc;
-          const double st = ring[t].st;
+          const double st = ring[t].st.x;
           double Fe = u;
           if (second) {
             const double UE = xr + 1 < nx ? ue : u, UW = xr > 0 ? uw : u;
@@ -414,7 +428,7 @@ __global__ void __launch_bounds__(MAXW * 64) k_sweep_fused(TArgs a) {
           }
           const double FeW = xr > 0 ? Fe_p : inW;
           const double r = ring[t].src - st * u - ax * (Fe - FeW) - ay * (Fn - FnS);
-          const double inv = rcp64(st + ax + ay);
+          const double inv = rcp64(ring[t].st.y + ax + ay);
           b_c = r * inv; cx_c = ax * inv; cy_c = ay * inv;
           u_c = u; i_c = ring[t].i1;
           if (GENERAL && handoff) { RB[xr] = u; RB[nx + xr] = Fn; }

@@ -21,8 +21,8 @@ GSIS_E_INVALID_ARG, GSIS_E_DEVICE, GSIS_E_OOM, GSIS_E_UNSUPPORTED = -1, -2, -3, 
 GSIS_SI, GSIS_GSIS = 0, 1
 GSIS_FP64, GSIS_FP32_MIXED = 0, 1
 GSIS_HOT_CENTRAL, GSIS_HOT_TRANSPORT = 0, 1
-GSIS_NUM_PHASES = 4
-PHASES = ("sweep", "hot", "synth", "update")
+GSIS_NUM_PHASES = 5
+PHASES = ("sweep", "moments", "hot", "synth", "update")
 
 _dp = ctypes.POINTER(ctypes.c_double)
 
@@ -49,7 +49,8 @@ class gsis_options(ctypes.Structure):
                 ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("synth_rtol", ctypes.c_double), ("synth_max_iter", ctypes.c_int32),
                 ("I0", ctypes.c_void_p), ("stream", ctypes.c_void_p),
-                ("device_ptrs", ctypes.c_int32), ("profile", ctypes.c_int32)]
+                ("device_ptrs", ctypes.c_int32), ("profile", ctypes.c_int32),
+                ("cfl_p", ctypes.c_double), ("beta", ctypes.c_double)]
 
 
 class gsis_result(ctypes.Structure):
@@ -181,12 +182,13 @@ class _Args:
 
 def make_options(method=GSIS_GSIS, precision=GSIS_FP64, order=2, limiter=1, alsm=1,
                  hot_face=GSIS_HOT_CENTRAL, tol=1e-6, max_iter=1000, synth_rtol=1e-4,
-                 synth_max_iter=50, profile=0):
+                 synth_max_iter=50, profile=0, cfl_p=0.0, beta=0.0):
     o = gsis_options()
     load().gsis_options_default(ctypes.byref(o))
     o.method, o.precision, o.order, o.limiter = int(method), int(precision), int(order), int(limiter)
     o.alsm, o.hot_face, o.tol, o.max_iter = int(alsm), int(hot_face), float(tol), int(max_iter)
     o.synth_rtol, o.synth_max_iter, o.profile = float(synth_rtol), int(synth_max_iter), int(profile)
+    o.cfl_p, o.beta = float(cfl_p), float(beta)
     return o
 
 

@@ -3,6 +3,7 @@ include/gsis.h declares, and reports errors cleanly without a device."""
 import ctypes
 import os
 import re
+import subprocess
 
 import pytest
 
@@ -32,15 +33,32 @@ def test_options_default():
     assert gsis.load().gsis_options_default(ctypes.byref(o)) == 0
     assert (o.method, o.precision, o.order, o.limiter, o.alsm, o.hot_face) == (1, 0, 2, 1, 1, 0)
     assert o.tol == 1e-6 and o.max_iter == 1000 and o.synth_max_iter == 50
-    assert o.synth_rtol == 1e-4
+    assert o.synth_rtol == 1e-4 and o.cfl_p == 0.0 and o.beta == 0.0
     assert gsis.load().gsis_options_default(None) == gsis.GSIS_E_INVALID_ARG
 
 
-def test_struct_layouts_match_header():
-    # field order and sizes of the public structs (LP64)
-    assert ctypes.sizeof(gsis.gsis_problem) == 4 + 4 + 8 + 8 + 8 + 7 * 8
-    assert gsis.gsis_options.tol.offset == 24
-    assert ctypes.sizeof(gsis.gsis_result) == 4 * 8 + 8 + 8
+def test_struct_layouts_match_header(tmp_path):
+    """Offsets and sizes of the public structs as the C compiler lays them out
+    from include/gsis.h equal the binding's ctypes layouts."""
+    structs = [gsis.gsis_problem, gsis.gsis_options, gsis.gsis_result]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "gsis.h"', "int main(void) {"]
+    for st in structs:
+        n = st.__name__
+        lines.append('printf("%s %%zu\\n", sizeof(%s));' % (n, n))
+        for f in st._fields_:
+            lines.append('printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (n, f[0], n, f[0]))
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), "-o", str(exe),
+                           str(src)])
+    got = dict(l.split() for l in subprocess.check_output([str(exe)], text=True).splitlines())
+    for st in structs:
+        n = st.__name__
+        assert int(got[n]) == ctypes.sizeof(st), n
+        for f in st._fields_:
+            assert int(got["%s.%s" % (n, f[0])]) == getattr(st, f[0]).offset, (n, f[0])
 
 
 def test_no_device_reports_error():

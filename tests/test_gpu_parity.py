@@ -190,3 +190,28 @@ def test_fused_sweep_matches_reference_kernels(ctx, shape, quad, monkeypatch):
                                        synth_rtol=1e-15, synth_max_iter=200)
         assert _rel(out["0"]["phi"], out["1"]["phi"]) < tol
         assert _rel(out["0"]["Fx"], out["1"]["Fx"]) < 10 * tol
+
+
+@pytest.mark.parametrize("kw", [dict(method=0, limiter=1), dict(method=1, limiter=1),
+                                dict(method=1, limiter=0, hot_face=0)])
+def test_pseudo_time_iterates(ctx, kw):
+    """Pseudo-time shifts (Eqs. cfl_pse, tau_pse) in the increment solve:
+    iterates at fixed m match the oracle."""
+    p = inputs.random_problem(37, 29, seed=31, sigma_range=(0.05, 500.0))
+    g, o = _fixed_m(ctx, p, 3, beta=4.0, cfl_p=0.5, **kw)
+    assert _rel(g["phi"], o["phi"]) < 1e-12
+    assert _rel(g["Fx"], o["Fx"]) < 1e-11
+
+
+def test_pseudo_time_checkerboard_fixed_point(ctx):
+    """7 x 7 block medium at 64 x 64: plain GSIS diverges there; with the
+    local pseudo time (beta = 10) the GPU converges to the oracle's point."""
+    p = inputs.checkerboard_blocks(64, inputs.quad_product(2, 16))
+    _say("checkerboard 64 beta=10 fixed point")
+    g = gsis.gsis_solve(ctx, p, tol=1e-12, max_iter=1000, limiter=0, beta=10.0,
+                        synth_rtol=1e-15, synth_max_iter=300)
+    o = oracle.solve(p, tol=1e-12, max_iter=1000, limiter=0, beta=10.0)
+    assert g["status"] == 0 and o["status"] == 0
+    assert abs(g["n_iter"] - o["n_iter"]) <= 3
+    assert _rel(g["phi"], o["phi"]) < 1e-10
+    assert _rel(g["Fx"], o["Fx"]) < 1e-9 and _rel(g["Fy"], o["Fy"]) < 1e-9

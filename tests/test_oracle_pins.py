@@ -384,3 +384,82 @@ def test_hot_wall_limits():
     phi = thick["phi"].reshape(40, 40)
     assert abs(phi[0, 20] - GOLD["hot_wall_thick_near_hot"]["value"]) < 0.05
     assert abs(phi[39, 20] - GOLD["hot_wall_thick_near_cold"]["value"]) < 0.02
+
+
+# -------------------------------------- pseudo-time shifts (Sec. 4.3, NEXT step)
+def test_pseudo_shift_closed_form():
+    """1/(c dt_p) = 1/(CFL_p dx_ref) and 1/(c tau_p) = max_j (sigma_i + sigma_j)
+    h_f / (2 beta dx_ref) on a Cartesian grid (|r^L| = |r^R| = h_f / 2)."""
+    p = inputs.random_problem(3, 2, seed=4)
+    p["dx"], p["dy"] = 0.5, 0.25
+    st = (p["sigma_a"] + p["sigma_s"]).reshape(2, 3)
+    beta, cfl = 7.0, 0.3
+    got = oracle.pseudo_shift(p, beta=beta, cfl_p=cfl).reshape(2, 3)
+    dref = 0.25
+    for j in range(2):
+        for i in range(3):
+            cand = []
+            if i > 0: cand.append((st[j, i] + st[j, i - 1]) * 0.5 / 2)
+            if i < 2: cand.append((st[j, i] + st[j, i + 1]) * 0.5 / 2)
+            cand.append((st[j, i] + st[1 - j, i]) * 0.25 / 2)
+            want = 1.0 / (cfl * dref) + max(cand) / (beta * dref)
+            assert abs(got[j, i] - want) < 1e-14 * want
+    assert np.all(oracle.pseudo_shift(p) == 0.0)
+    # a one-cell grid has no neighbour: only the global term remains
+    p1 = inputs.random_problem(1, 1, seed=4)
+    assert oracle.pseudo_shift(p1, beta=3.0)[0] == 0.0
+
+
+def test_pseudo_time_sweep_is_shifted_diagonal():
+    """With the shift s_i the increment solve uses d_ii + s_i: a residual
+    equal to (H + S) e_t applied to a unit vector gives back e_t."""
+    p = inputs.random_problem(4, 3, seed=6)
+    K = len(p["mu"])
+    s = oracle.pseudo_shift(p, beta=2.0, cfl_p=0.7)
+    rng = np.random.Generator(np.random.PCG64(60))
+    r = rng.uniform(-1, 1, (12, K))
+    d0 = oracle.sweep(p, r)
+    d1 = oracle.sweep(p, r, beta=2.0, cfl_p=0.7)
+    # H0 d0 = r and (H0 + S) d1 = r  =>  H0 (d0 - d1) = S d1
+    back = oracle.sweep(p, s[:, None] * d1)
+    np.testing.assert_allclose(d0 - d1, back, rtol=1e-10, atol=1e-13)
+
+
+@pytest.mark.parametrize("method,hot", [(0, 0), (1, 1)])
+def test_pseudo_time_keeps_fixed_point(method, hot):
+    """The shift only enters the increment solve (Eq. elem_main_shifted). At
+    an SI fixed point, and at a GSIS fixed point with transport face fluxes
+    in the HoT (where the correction vanishes), the residual is zero, so the
+    solution does not depend on the shift."""
+    p = inputs.random_problem(12, 10, seed=12, sigma_range=(0.5, 20.0))
+    a = oracle.solve(p, method=method, hot_face=hot, tol=1e-13, max_iter=3000, limiter=0)
+    b = oracle.solve(p, method=method, hot_face=hot, tol=1e-13, max_iter=3000, limiter=0,
+                     beta=5.0, cfl_p=2.0)
+    assert a["status"] == 0 and b["status"] == 0
+    assert b["n_iter"] > a["n_iter"]           # damped increments converge more slowly
+    assert np.abs(a["phi"] - b["phi"]).max() < 1e-10 * np.abs(a["phi"]).max()
+
+
+def test_pseudo_time_moves_central_gsis_fixed_point():
+    """With central HoT faces the GSIS fixed point keeps a nonzero increment
+    (it is not the SI solution), so it depends on the increment solve and
+    therefore on the shift; the move stays well inside the GSIS - SI gap."""
+    p = inputs.random_problem(12, 10, seed=12, sigma_range=(0.5, 20.0))
+    si = oracle.solve(p, method=0, tol=1e-13, max_iter=3000, limiter=0)
+    a = oracle.solve(p, method=1, tol=1e-13, max_iter=3000, limiter=0)
+    b = oracle.solve(p, method=1, tol=1e-13, max_iter=3000, limiter=0, beta=5.0)
+    gap = np.abs(a["phi"] - si["phi"]).max()
+    move = np.abs(a["phi"] - b["phi"]).max()
+    assert 1e-6 * gap < move < 0.2 * gap
+
+
+def test_pseudo_time_stabilises_opacity_jumps():
+    """Sec. 4.3: synthetic acceleration can turn unstable at opacity jumps,
+    and the local pseudo time damps the thin cells beside thick ones. On the
+    7 x 7 block medium at 64 x 64 (cell optical depths 0.007 - 111) plain
+    GSIS diverges; with beta = 10 it converges."""
+    p = inputs.checkerboard_blocks(64, inputs.quad_product(2, 16))
+    plain = oracle.solve(p, method=1, tol=1e-6, max_iter=40, limiter=0)
+    assert plain["status"] != 0 and plain["err_hist"][-1] > 1.0
+    damped = oracle.solve(p, method=1, tol=1e-6, max_iter=200, limiter=0, beta=10.0)
+    assert damped["status"] == 0 and damped["n_iter"] < 120
