@@ -32,6 +32,7 @@ struct gsis_plan {
   std::vector<int> perm;          // internal ordinate -> caller ordinate
   double swmu = 0, sweta = 0;     // sum_k w_k mu_k, sum_k w_k eta_k
   std::vector<double> I0_host;    // warm start in the internal layout (may be empty)
+  std::vector<float> I0_host_f;   // FP32-mixed: I0 - phi0/(4 pi) in the internal layout
   std::vector<double> phi0_host;  // phi of the warm start
   std::vector<void *> allocs;
   double *host_scal = nullptr;    // pinned
@@ -212,6 +213,21 @@ gsis_status dalloc(gsis_plan *pl, T **p, size_t n) {
   return GSIS_OK;
 }
 
+// One intensity buffer: N*K doubles, or N*K floats in FP32-mixed mode.
+gsis_status alloc_intensity(gsis_plan *pl, int which, size_t nk, bool f32) {
+  gsis_status st;
+  if (f32) {
+    float *p = nullptr;
+    st = dalloc(pl, &p, nk);
+    pl->P.I[which] = p;
+  } else {
+    double *p = nullptr;
+    st = dalloc(pl, &p, nk);
+    pl->P.I[which] = p;
+  }
+  return st;
+}
+
 template <typename T>
 gsis_status upload(gsis_plan *pl, T **p, const std::vector<T> &h) {
   gsis_status st = dalloc(pl, p, h.size());
@@ -269,8 +285,6 @@ extern "C" gsis_status gsis_plan_create(gsis_ctx *ctx, const gsis_problem *p,
   std::vector<double> mu, eta, w, sa, ss, q, bnd;
   gsis_status st = check_problem(ctx, p, o, mu, eta, w, sa, ss, q, bnd);
   if (st) return st;
-  if (o->precision != GSIS_FP64)
-    return fail(ctx, GSIS_E_UNSUPPORTED, "precision FP32_MIXED is not available in this build");
   if (o->hot_face != GSIS_HOT_CENTRAL)
     return fail(ctx, GSIS_E_UNSUPPORTED, "hot_face TRANSPORT is not available in this build");
   HIPCHK(ctx, hipSetDevice(ctx->device));
@@ -315,7 +329,11 @@ extern "C" gsis_status gsis_plan_create(gsis_ctx *ctx, const gsis_problem *p,
     weta[kk] = w[k] * eta[k];
     pl->swmu += wmu[kk];
     pl->sweta += weta[kk];
+    P.sw += wv[kk];
   }
+  P.swm = pl->swmu;
+  P.swe = pl->sweta;
+  const bool f32 = P.precision == GSIS_FP32_MIXED;
 
   // -- per-cell coefficients
   std::vector<double> st_(N), cE(N), cW(N), cN(N), cS(N);
@@ -502,16 +520,32 @@ extern "C" gsis_status gsis_plan_create(gsis_ctx *ctx, const gsis_problem *p,
       for (int k = 0; k < K; ++k) s += w[k] * I0[(size_t)c * K + k];
       phi0[c] = s;
     }
+    if (f32) {
+      // stored deviation from phi0/(4 pi); the first read adds base = phi0
+      pl->I0_host_f.resize((size_t)N * K);
+      for (int kk = 0; kk < K; ++kk) {
+        const int k = pl->perm[kk];
+        const int qd = (mu[k] < 0 ? 1 : 0) | (eta[k] < 0 ? 2 : 0);
+        for (int j = 0; j < ny; ++j)
+          for (int i = 0; i < nx; ++i) {
+            const int xl = (qd & 1) ? nx - 1 - i : i, yl = (qd & 2) ? ny - 1 - j : j;
+            const int c = j * nx + i;
+            pl->I0_host_f[(size_t)kk * N + dg_idx(xl, yl, nx, ny)] =
+                (float)(I0[(size_t)c * K + k] - phi0[c] / kFourPi);
+          }
+      }
+      pl->I0_host.clear();
+    }
   }
   pl->phi0_host = phi0;
 
   // -- device allocations and uploads
   if ((st = upload(pl, &P.amu, amu)) || (st = upload(pl, &P.aeta, aeta)) ||
       (st = upload(pl, &P.w, wv)) || (st = upload(pl, &P.wmu, wmu)) ||
-      (st = upload(pl, &P.weta, weta)) || (st = dalloc(pl, &P.I[0], (size_t)N * K)) ||
-      (st = dalloc(pl, &P.I[1], (size_t)N * K)) ||
+      (st = upload(pl, &P.weta, weta)) || (st = alloc_intensity(pl, 0, (size_t)N * K, f32)) ||
+      (st = alloc_intensity(pl, 1, (size_t)N * K, f32)) ||
       (st = dalloc(pl, &P.R, P.sweep_impl == 1 ? (size_t)N * K : 1)) ||
-      (st = upload(pl, &P.cellq, cellq)) || (st = dalloc(pl, &P.dynq, (size_t)4 * N * 2)) ||
+      (st = upload(pl, &P.cellq, cellq)) || (st = dalloc(pl, &P.dynq, (size_t)4 * N * 3)) ||
       (st = dalloc(pl, &P.rowbuf, (size_t)K * 3 * nx)) ||
       (st = upload(pl, &P.sig_t, st_)) || (st = upload(pl, &P.sig_a, sa)) ||
       (st = upload(pl, &P.sig_s, ss)) || (st = upload(pl, &P.q, q)) ||
@@ -530,6 +564,11 @@ extern "C" gsis_status gsis_plan_create(gsis_ctx *ctx, const gsis_problem *p,
       (st = dalloc(pl, &P.scal, 16)) || (st = dalloc(pl, &P.err_hist, o->max_iter)) ||
       (st = dalloc(pl, &P.state, 4)) || (st = dalloc(pl, &P.last_err, 1)))
     return bail(st);
+  if (f32) {
+    if ((st = dalloc(pl, &P.base, N))) return bail(st);
+  } else {
+    P.base = P.delta;
+  }
   P.red_blocks = (N + 255) / 256;
   if ((st = dalloc(pl, &P.red, 2 * (size_t)P.red_blocks + 2)) ||
       (st = dalloc(pl, &P.err_parts, 2 * (size_t)P.red_blocks + 2)))
@@ -575,14 +614,21 @@ extern "C" gsis_status gsis_plan_reset(gsis_plan *pl) {
   const size_t NK = (size_t)P.N * P.K;
   HIPCHK(ctx, hipSetDevice(ctx->device));
   hipStream_t s = pl->stream;
-  if (!pl->I0_host.empty())
+  const bool f32 = P.precision == GSIS_FP32_MIXED;
+  if (f32 && !pl->I0_host_f.empty())
+    HIPCHK(ctx, hipMemcpyAsync(P.I[0], pl->I0_host_f.data(), NK * sizeof(float),
+                               hipMemcpyHostToDevice, s));
+  else if (!f32 && !pl->I0_host.empty())
     HIPCHK(ctx, hipMemcpyAsync(P.I[0], pl->I0_host.data(), NK * sizeof(double),
                                hipMemcpyHostToDevice, s));
   else
-    HIPCHK(ctx, hipMemsetAsync(P.I[0], 0, NK * sizeof(double), s));
+    HIPCHK(ctx, hipMemsetAsync(P.I[0], 0, NK * (f32 ? sizeof(float) : sizeof(double)), s));
   HIPCHK(ctx, hipMemcpyAsync(P.phi, pl->phi0_host.data(), P.N * sizeof(double),
                              hipMemcpyHostToDevice, s));
   HIPCHK(ctx, hipMemsetAsync(P.delta, 0, P.N * sizeof(double), s));
+  if (f32)   // I^0 = Itilde + phi0/(4 pi)
+    HIPCHK(ctx, hipMemcpyAsync(P.base, pl->phi0_host.data(), P.N * sizeof(double),
+                               hipMemcpyHostToDevice, s));
   HIPCHK(ctx, hipMemsetAsync(P.state, 0, 4 * sizeof(int32_t), s));
   HIPCHK(ctx, hipMemsetAsync(P.err_hist, 0, P.max_iter * sizeof(double), s));
   launch_source(P, s);

@@ -14,6 +14,8 @@
 #include <vector>
 #include <string>
 
+#include "gsis.h"
+
 namespace gsis {
 
 constexpr double kFourPi = 12.566370614359172953850573533118;
@@ -60,12 +62,15 @@ struct PlanDev {
   // per internal ordinate
   double *amu = nullptr, *aeta = nullptr;   // |mu|/dx, |eta|/dy
   double *w = nullptr, *wmu = nullptr, *weta = nullptr;  // w, w*mu, w*eta (signed)
-  // intensities (two copies) and the residual buffer, [K][N] local layout
-  double *I[2] = {nullptr, nullptr};
+  double sw = 0, swm = 0, swe = 0;                        // their sums
+  // intensities (two copies; FP64, or FP32 deviations in FP32-mixed mode)
+  // and the residual buffer, [K][N] local layout
+  void *I[2] = {nullptr, nullptr};
   double *R = nullptr;
   // per quadrant, in that quadrant's mirrored frame: cellq[q][N][6] =
-  // (cE, cW, cN, cS, sigma_t, 0) with E/W/N/S local; dynq[q][2][N] =
-  // planes src and delta/(4 pi), rewritten after every update
+  // (cE, cW, cN, cS, sigma_t, sigma_t + pseudo-time shift) with E/W/N/S
+  // local; dynq[q][3][N] = planes src, base/(4 pi) and phi/(4 pi),
+  // rewritten after every update
   double *cellq = nullptr, *dynq = nullptr;
   double *rowbuf = nullptr;    // [K][3][nx] hand-off between sweep passes
   int sweep_impl = 0;          // 0 fused wavefront sweep, 1 two-kernel reference
@@ -77,6 +82,9 @@ struct PlanDev {
   double *phih = nullptr, *Fx = nullptr, *Fy = nullptr;  // moments of I^{m+1/2}
   double *mom_part = nullptr;  // [4][3][N] per-quadrant partial moments
   double *delta = nullptr;     // pending GSIS correction (phi' - phi_half)
+  double *base = nullptr;      // what the next read adds (over 4 pi) to the stored
+                               // intensity: delta (FP64; same array), or
+                               // phi^m + delta (FP32-mixed deviations)
   double *hx = nullptr, *hy = nullptr;   // HoT
   double *rhs = nullptr;
   // boundary

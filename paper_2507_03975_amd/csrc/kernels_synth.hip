@@ -646,9 +646,10 @@ void vcycle(const PlanDev &P, const double *r, double *z, bool first, hipStream_
 
 // ------------------------------------------------------------- update / Err
 // delta = phi' - phi_half (GSIS) or 0 (SI); Err partials; phi = phi_new.
-__global__ void k_update(int n, int method, double V, const double *phinew,
-                         const double *phih, double *phi, double *delta, double *part,
-                         const int32_t *state) {
+// FP32-mixed mode also records base = phi^m + delta (see the transport file).
+__global__ void k_update(int n, int method, int fp32, double V, const double *phinew,
+                         const double *phih, double *phi, double *delta, double *base,
+                         double *part, const int32_t *state) {
   __shared__ double sh[kRedBlock];
   if (state[1] != 0) return;
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -658,7 +659,9 @@ __global__ void k_update(int n, int method, double V, const double *phinew,
     const double d = pn - phi[c];
     num = V * d * d;
     den = V * pn * pn;
-    delta[c] = method ? pn - phih[c] : 0.0;
+    const double dl = method ? pn - phih[c] : 0.0;
+    delta[c] = dl;
+    if (fp32) base[c] = phi[c] + dl;
     phi[c] = pn;
   }
   double a = block_sum(num, sh);
@@ -689,24 +692,26 @@ __global__ void k_err_finish(const double *part, int npart, double tol, int max_
 }
 
 // src = (sigma_s phi + q) / (4 pi); the mirrored per-quadrant copies of
-// (src, delta/(4 pi)) read by the fused sweep.
-__global__ void k_source(int nx, int ny, const double *sig_s, const double *q,
-                         const double *phi, const double *delta, double *src, double *dynq,
+// (src, base/(4 pi), phi/(4 pi)) read by the fused sweep.
+__global__ void k_source(int nx, int ny, int fp32, const double *sig_s, const double *q,
+                         const double *phi, const double *base, double *src, double *dynq,
                          const int32_t *state) {
   if (state[1] != 0) return;
   const int n = nx * ny;
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n) return;
   const double sc = (sig_s[c] * phi[c] + q[c]) / kFourPi;
-  const double dq = delta[c] / kFourPi;
+  const double dq = base[c] / kFourPi;
+  const double pq = phi[c] / kFourPi;
   src[c] = sc;
   int i, j;
   cell_ij(c, nx, i, j);
   for (int qd = 0; qd < 4; ++qd) {
     const int xl = (qd & 1) ? nx - 1 - i : i, yl = (qd & 2) ? ny - 1 - j : j;
-    const size_t o = (size_t)qd * 2 * n + dg_idx(xl, yl, nx, ny);
+    const size_t o = (size_t)qd * 3 * n + dg_idx(xl, yl, nx, ny);
     dynq[o] = sc;          // plane 0 of quadrant qd
     dynq[o + n] = dq;      // plane 1
+    if (fp32) dynq[o + 2 * n] = pq;
   }
 }
 
@@ -723,8 +728,9 @@ __global__ void k_final_flux(int n, const double *Fx, const double *Fy, const do
 }  // namespace
 
 void launch_source(const PlanDev &P, hipStream_t s) {
-  hipLaunchKernelGGL(k_source, dim3(nblk(P.N)), dim3(kRedBlock), 0, s, P.nx, P.ny, P.sig_s, P.q,
-                     P.phi, P.delta, P.src, P.dynq, P.state);
+  hipLaunchKernelGGL(k_source, dim3(nblk(P.N)), dim3(kRedBlock), 0, s, P.nx, P.ny,
+                     P.precision == GSIS_FP32_MIXED ? 1 : 0, P.sig_s, P.q, P.phi, P.base, P.src,
+                     P.dynq, P.state);
 }
 
 void launch_hot_rhs(const PlanDev &P, hipStream_t s) {
@@ -792,8 +798,9 @@ void launch_synth_solve(PlanDev &P, hipStream_t s, int32_t *host_flag) {
 void launch_update(const PlanDev &P, hipStream_t s) {
   const int nb = nblk(P.N);
   const double *phinew = P.mg[0].x;
-  hipLaunchKernelGGL(k_update, dim3(nb), dim3(kRedBlock), 0, s, P.N, P.method, P.V, phinew,
-                     P.phih, P.phi, P.delta, P.err_parts, P.state);
+  hipLaunchKernelGGL(k_update, dim3(nb), dim3(kRedBlock), 0, s, P.N, P.method,
+                     P.precision == GSIS_FP32_MIXED ? 1 : 0, P.V, phinew, P.phih, P.phi,
+                     P.delta, P.base, P.err_parts, P.state);
   hipLaunchKernelGGL(k_err_finish, dim3(1), dim3(kRedBlock), 0, s, P.err_parts, nb, P.tol,
                      P.max_iter, P.err_hist, P.last_err, P.state);
   launch_source(P, s);

@@ -13,6 +13,15 @@
 //
 // The pending GSIS correction delta/(4 pi) (Eq. GSIS_update) is added to
 // I^m on every read, so the correction never costs a pass over I.
+//
+// Storage precision. In FP64 mode the buffers hold I itself and the read adds
+// base/(4 pi) with base = delta. In FP32-mixed mode they hold the FP32
+// deviation Itilde = I^{m+1/2} - phi^m/(4 pi) (phi^m: the FP64 scalar flux
+// the sweep started from), and the read adds base/(4 pi) with
+// base = phi^m + delta. Itilde is the anisotropic part plus the last
+// change of phi, small where the medium is thick, so its FP32 rounding stays
+// far below the cancellation sigma_t I - sigma_s phi/(4 pi); every residual,
+// sweep and moment operation runs in FP64.
 #include "gsis_internal.h"
 
 namespace gsis {
@@ -26,7 +35,11 @@ struct TArgs {
   int order, limiter;
   int qoff[5];
   const double *amu, *aeta, *w, *wmu, *weta;
-  double *I0, *I1;   // the two intensity buffers; state[2] names the current one
+  void *I0, *I1;     // the two intensity buffers (FP64 or FP32); state[2]
+                     // names the current one
+  int fp32;          // 1: buffers hold FP32 deviations (see above)
+  const double *phi; // phi^m (FP32 mode: the deviation's reference)
+  double sw, swm, swe;   // sum_k w_k, w_k mu_k, w_k eta_k
   double *R;
   const double *sig_t, *src, *delta;
   const double *cE, *cW, *cN, *cS;
@@ -48,12 +61,19 @@ TArgs make_args(const PlanDev &P) {
   a.cE = P.cE; a.cW = P.cW; a.cN = P.cN; a.cS = P.cS;
   a.bnd = P.bnd; a.phih = P.phih; a.Fx = P.Fx; a.Fy = P.Fy; a.bflux = P.bflux;
   a.cellq = P.cellq; a.dynq = P.dynq; a.rowbuf = P.rowbuf;
+  a.fp32 = P.precision == GSIS_FP32_MIXED ? 1 : 0;
+  a.phi = P.phi;
+  a.sw = P.sw; a.swm = P.swm; a.swe = P.swe;
   a.state = P.state;
   return a;
 }
 
-__device__ inline const double *Iin_of(const TArgs &a) { return a.state[2] ? a.I1 : a.I0; }
-__device__ inline double *Iout_of(const TArgs &a) { return a.state[2] ? a.I0 : a.I1; }
+template <typename T = double>
+__device__ inline const T *Iin_of(const TArgs &a) {
+  return (const T *)(a.state[2] ? a.I1 : a.I0);
+}
+template <typename T = double>
+__device__ inline T *Iout_of(const TArgs &a) { return (T *)(a.state[2] ? a.I0 : a.I1); }
 
 __device__ inline int quadrant_of(const TArgs &a, int kk) {
   return (kk >= a.qoff[1]) + (kk >= a.qoff[2]) + (kk >= a.qoff[3]);
@@ -216,8 +236,11 @@ __device__ inline double rcp64(double x) {
   return fma(r, e, r);
 }
 
+template <typename T>
 struct Slot {
-  double ib, dq;       // I^m buffer value and delta/(4 pi) at column x+2
+  T ib;                // I^m buffer value at column x+2
+  double dq;           // base/(4 pi) at column x+2
+  double sub;          // FP32 mode: phi^m/(4 pi) at column x+1
   double src;          // (sigma_s phi + q)/(4 pi) at column x+1
   double2 c0, c1;      // (cE, cW), (cN, cS) at column x+1, mirrored frame
   double2 st;          // sigma_t and the increment-solve diagonal's sigma_t
@@ -271,8 +294,9 @@ __device__ inline int xcd_ordinate(int b, int K) {
 // dI = b + cx dI_west + cy dI_south waits on the neighbour exchange.
 // GENERAL = false assumes ny <= blockDim.x (one pass) and nx <= kSouthCap, so
 // that no load outside the prefetch ring sits on the step path.
-template <int PF, int MAXW, bool GENERAL>
+template <int PF, int MAXW, bool GENERAL, typename T>
 __global__ void __launch_bounds__(MAXW * 64) k_sweep_fused(TArgs a) {
+  constexpr bool kF32 = sizeof(T) == 4;
   if (a.state[1] != 0) return;
   const int kk = xcd_ordinate(blockIdx.x, a.K);
   const int q = quadrant_of(a, kk);
@@ -283,12 +307,14 @@ __global__ void __launch_bounds__(MAXW * 64) k_sweep_fused(TArgs a) {
   const double ax = a.amu[kk], ay = a.aeta[kk];
   const double hdx = 0.5 * a.dx, hdy = 0.5 * a.dy;
   const bool second = a.order >= 2, lim = a.limiter != 0;
-  const double *Ik = Iin_of(a) + (size_t)kk * N;
-  double *Ok = Iout_of(a) + (size_t)kk * N;
+  const T *Ik = Iin_of<T>(a) + (size_t)kk * N;
+  T *Ok = Iout_of<T>(a) + (size_t)kk * N;
   const double *Cq = a.cellq + (size_t)q * N * 6;
   const double2 *C2 = reinterpret_cast<const double2 *>(Cq);
-  const double *SRC = a.dynq + (size_t)q * 2 * N;   // plane 0: src, plane 1: delta/(4 pi)
+  // planes: src, base/(4 pi), and (FP32 mode) phi^m/(4 pi)
+  const double *SRC = a.dynq + (size_t)q * 3 * N;
   const double *DQ = SRC + N;
+  const double *SUB = SRC + 2 * N;
   double *RB = a.rowbuf + (size_t)kk * 3 * nx;
   __shared__ double xup[2][MAXW][3];
   __shared__ double xdn[2][MAXW];
@@ -325,7 +351,7 @@ __global__ void __launch_bounds__(MAXW * 64) k_sweep_fused(TArgs a) {
     DiagCursor cur;
     cur.init(nx, ny, y0);                     // column x+1 of step -1
     int inext = cur.index(yc);
-    auto load = [&](Slot &sl) {
+    auto load = [&](Slot<T> &sl) {
       const int i1 = inext;                    // column x+1
       cur.advance();
       inext = cur.index(yc);                   // column x+2
@@ -336,8 +362,9 @@ __global__ void __launch_bounds__(MAXW * 64) k_sweep_fused(TArgs a) {
       sl.c0 = C2[3 * i1];
       sl.c1 = C2[3 * i1 + 1];
       sl.st = C2[3 * i1 + 2];
+      if constexpr (kF32) sl.sub = SUB[i1];
     };
-    Slot ring[PF];
+    Slot<T> ring[PF];
 #pragma unroll
     for (int t = 0; t < PF; ++t) load(ring[t]);
     // u of columns x, x+1, x+2 (the residual column is x+1). Lane 0 forms
@@ -346,11 +373,11 @@ __global__ void __launch_bounds__(MAXW * 64) k_sweep_fused(TArgs a) {
     double uw = 0.0, uc = 0.0, ue;
     {
       const long long i00 = dg_idx(0, yc, nx, ny);
-      ue = Ik[i00] + DQ[i00];
+      ue = (double)Ik[i00] + DQ[i00];
     }
     // pipeline registers: residual of column x (b = r / d, cx, cy), face
     // values of the residual column, increment of the chain column
-    double b_c = 0.0, cx_c = 0.0, cy_c = 0.0, u_c = 0.0;
+    double b_c = 0.0, cx_c = 0.0, cy_c = 0.0, u_c = 0.0, sub_c = 0.0;
     int i_c = 0;
     double Fe_p = 0.0, Fn_p = 0.0, dI_p = 0.0;
     // steps -1 .. nx+rows-1, padded to a multiple of PF (padding steps have
@@ -364,7 +391,7 @@ __global__ void __launch_bounds__(MAXW * 64) k_sweep_fused(TArgs a) {
         const int x = s - tid;                 // chain column
         const int xr = x + 1;                  // residual column
         uw = uc; uc = ue;
-        ue = ring[t].ib + ring[t].dq;          // u(x+2)
+        ue = (double)ring[t].ib + ring[t].dq;  // u(x+2)
         // --- exchange with the rows below and above
         double sU = __shfl_up(uw, 1, 64);      // u(xr, y-1)
         double sFn = __shfl_up(Fn_p, 1, 64);   // F_n(xr, y-1)
@@ -384,14 +411,15 @@ __global__ void __launch_bounds__(MAXW * 64) k_sweep_fused(TArgs a) {
         }
         if (GENERAL && actr && ntop) {            // next pass's bottom row
           const int o = dg_idx(xr, y + 1, nx, ny);
-          nU = Ik[o] + DQ[o];
+          nU = (double)Ik[o] + DQ[o];
         }
         // --- increment of the chain column (uses last step's residual)
         double dI = 0.0;
         if (actc) {
           const double dW = x > 0 ? dI_p : 0.0, dS = hs ? sdI : 0.0;
           dI = fma(cx_c, dW, fma(cy_c, dS, b_c));
-          Ok[i_c] = u_c + dI;
+          if constexpr (kF32) Ok[i_c] = (T)((u_c + dI) - sub_c);
+          else Ok[i_c] = u_c + dI;
           if (GENERAL && handoff) RB[2 * nx + x] = dI;
         }
         // --- residual of column xr for the next step
@@ -431,6 +459,7 @@ __global__ void __launch_bounds__(MAXW * 64) k_sweep_fused(TArgs a) {
           const double inv = rcp64(ring[t].st.y + ax + ay);
           b_c = r * inv; cx_c = ax * inv; cy_c = ay * inv;
           u_c = u; i_c = ring[t].i1;
+          if constexpr (kF32) sub_c = ring[t].sub;
           if (GENERAL && handoff) { RB[xr] = u; RB[nx + xr] = Fn; }
           Fe_p = Fe;
         }
@@ -438,7 +467,7 @@ __global__ void __launch_bounds__(MAXW * 64) k_sweep_fused(TArgs a) {
         if (lane == 63) {
           xup[s & 1][wave][0] = uc; xup[s & 1][wave][1] = Fn; xup[s & 1][wave][2] = dI;
         }
-        if (lane == 0) xdn[s & 1][wave] = ring[(t + 1) % PF].ib + ring[(t + 1) % PF].dq;
+        if (lane == 0) xdn[s & 1][wave] = (double)ring[(t + 1) % PF].ib + ring[(t + 1) % PF].dq;
         load(ring[t]);                            // refill this slot PF steps ahead
         __builtin_amdgcn_s_waitcnt(0xc07f);     // LDS writes done (lgkmcnt 0 only)
         __builtin_amdgcn_s_barrier();
@@ -461,6 +490,7 @@ __device__ inline void dg_cell(long long t, int nx, int ny, int &x, int &y) {
   x = lo - y;
 }
 
+template <typename T>
 __global__ void k_moments_q(TArgs a, double *part) {
   if (a.state[1] != 0) return;
   const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
@@ -469,10 +499,10 @@ __global__ void k_moments_q(TArgs a, double *part) {
   int x, y;
   dg_cell(t, a.nx, a.ny, x, y);
   const int c = gcell(a, q, x, y);
-  const double *O = Iout_of(a);
+  const T *O = Iout_of<T>(a);
   double s0 = 0, sx = 0, sy = 0;
   for (int kk = a.qoff[q]; kk < a.qoff[q + 1]; ++kk) {
-    const double v = O[(size_t)kk * a.N + t];
+    const double v = (double)O[(size_t)kk * a.N + t];
     s0 += a.w[kk] * v;
     sx += a.wmu[kk] * v;
     sy += a.weta[kk] * v;
@@ -491,6 +521,10 @@ __global__ void k_moments_combine(TArgs a, const double *part) {
     s0 += part[(size_t)(3 * q) * a.N + c];
     sx += part[(size_t)(3 * q + 1) * a.N + c];
     sy += part[(size_t)(3 * q + 2) * a.N + c];
+  }
+  if (a.fp32) {                               // I^{m+1/2} = Itilde + phi^m/(4 pi)
+    const double sub = a.phi[c] / kFourPi;
+    s0 += sub * a.sw; sx += sub * a.swm; sy += sub * a.swe;
   }
   a.phih[c] = s0; a.Fx[c] = sx; a.Fy[c] = sy;
 }
@@ -521,8 +555,13 @@ __global__ void k_boundary_flux(TArgs a) {
       int j = side == 2 ? 0 : side == 3 ? a.ny - 1 : pos;
       int xl = (q & 1) ? a.nx - 1 - i : i;
       int yl = (q & 2) ? a.ny - 1 - j : j;
-      const double *Ok = Iout_of(a) + (size_t)kk * a.N;
-      auto ld = [&](int x, int y) { return Ok[dg_idx(x, y, a.nx, a.ny)]; };
+      const long long base = (long long)kk * a.N;
+      const double *SUB = a.dynq + ((size_t)q * 3 + 2) * a.N;
+      auto ld = [&](int x, int y) {
+        const long long o = dg_idx(x, y, a.nx, a.ny);
+        if (a.fp32) return (double)Iout_of<float>(a)[base + o] + SUB[o];
+        return Iout_of<double>(a)[base + o];
+      };
       double Fe, Fn;
       out_faces(a, q, xl, yl, ld, Fe, Fn);
       val = side < 2 ? Fe : Fn;
@@ -541,28 +580,43 @@ __global__ void k_boundary_flux(TArgs a) {
 
 }  // namespace
 
+template <typename T>
+void launch_fused(const TArgs &a, const PlanDev &P, int rows, hipStream_t s) {
+  const int w = rows / 64;
+  const bool general = P.ny > rows || P.nx > kSouthCap;
+  if (general)
+    hipLaunchKernelGGL((k_sweep_fused<2, 16, true, T>), dim3(P.K), dim3(rows), 0, s, a);
+  else if (w <= 4)
+    hipLaunchKernelGGL((k_sweep_fused<6, 4, false, T>), dim3(P.K), dim3(rows), 0, s, a);
+  else if (w <= 8)
+    hipLaunchKernelGGL((k_sweep_fused<4, 8, false, T>), dim3(P.K), dim3(rows), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_sweep_fused<2, 16, false, T>), dim3(P.K), dim3(rows), 0, s, a);
+}
+
 void launch_transport(const PlanDev &P, hipStream_t s) {
   TArgs a = make_args(P);
   int rows = ((P.ny + 63) / 64) * 64;
   if (rows > 1024) rows = 1024;
-  if (P.sweep_impl == 1) {
+  if (P.sweep_impl == 1 && !a.fp32) {
     // two-kernel reference: residual into R, then the wavefront solve
     dim3 g((P.N + 255) / 256, P.K);
     hipLaunchKernelGGL(k_residual, g, dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_sweep, dim3(P.K), dim3(rows), 0, s, a);
     return;
   }
-  const int w = rows / 64;
-  const bool general = P.ny > rows || P.nx > kSouthCap;
-  if (general) hipLaunchKernelGGL((k_sweep_fused<2, 16, true>), dim3(P.K), dim3(rows), 0, s, a);
-  else if (w <= 4) hipLaunchKernelGGL((k_sweep_fused<6, 4, false>), dim3(P.K), dim3(rows), 0, s, a);
-  else if (w <= 8) hipLaunchKernelGGL((k_sweep_fused<4, 8, false>), dim3(P.K), dim3(rows), 0, s, a);
-  else hipLaunchKernelGGL((k_sweep_fused<2, 16, false>), dim3(P.K), dim3(rows), 0, s, a);
+  if (a.fp32) launch_fused<float>(a, P, rows, s);
+  else launch_fused<double>(a, P, rows, s);
 }
 
 void launch_moments(const PlanDev &P, hipStream_t s) {
   TArgs a = make_args(P);
-  hipLaunchKernelGGL(k_moments_q, dim3((P.N + 255) / 256, 4), dim3(256), 0, s, a, P.mom_part);
+  if (a.fp32)
+    hipLaunchKernelGGL(k_moments_q<float>, dim3((P.N + 255) / 256, 4), dim3(256), 0, s, a,
+                       P.mom_part);
+  else
+    hipLaunchKernelGGL(k_moments_q<double>, dim3((P.N + 255) / 256, 4), dim3(256), 0, s, a,
+                       P.mom_part);
   hipLaunchKernelGGL(k_moments_combine, dim3((P.N + 255) / 256), dim3(256), 0, s, a,
                      (const double *)P.mom_part);
 }
