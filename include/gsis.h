@@ -124,6 +124,9 @@ typedef struct {
                             which damps the increments of thin cells beside
                             thick ones; 0 = off (default). Neither shift
                             changes the fixed point (Eq. elem_main_shifted) */
+  int32_t graph;         /* batches only: 1 (default) captures one outer
+                            iteration in a hipGraph at gsis_batch_create and
+                            replays it; 0 enqueues kernels one by one */
 } gsis_options;
 
 /* Fill *o with the defaults listed above. */
@@ -173,6 +176,55 @@ enum {
  * plan's stream), *n_iter the number of profiled iterations. Needs
  * options.profile = 1. Clears the accumulated samples. */
 gsis_status gsis_plan_phase_times(gsis_plan *plan, double *ms, int32_t *n_iter);
+
+/* ------------------------------------------------------------------ batches
+ * Many independent problems of uneven size (grid, ordinates, media) solved
+ * together with shared options. Each keeps its own state and stops on its
+ * own Err < tol; finished problems turn their kernels into no-ops. One outer
+ * iteration runs the transport sweeps of all problems in one persistent
+ * launch (work items = (problem, ordinate), longest first; the launch
+ * configuration is chosen at creation by timing each compiled one on the
+ * batch), and every other step, including each CG and multigrid step of the
+ * synthetic solves, as one launch over all problems, each problem with its
+ * own hierarchy, scalars and stop flag. The synthetic CG runs a fixed number
+ * of iterations per outer iteration (the most any problem needed on the
+ * first outer iteration, plus 2, at most synth_max_iter), each problem
+ * stopping on its own test. options.I0 must be NULL; options.stream NULL
+ * makes the batch create its own stream (graph capture cannot use the
+ * default stream). */
+typedef struct gsis_batch gsis_batch;
+
+gsis_status gsis_batch_create(gsis_ctx *ctx, int32_t n, const gsis_problem *p /* [n] */,
+                              const gsis_options *o, gsis_batch **out);
+void gsis_batch_destroy(gsis_batch *b);
+/* Enqueue n outer iterations (graph replays, or eager launches). */
+gsis_status gsis_batch_iterate(gsis_batch *b, int32_t n);
+/* Wait, then report per problem (arrays of length n, each may be NULL) the
+ * iterations done, converged flag (1 / -1 / 0 as in gsis_plan_status) and
+ * last Err, and how many problems have stopped (converged, diverged or at
+ * max_iter). */
+gsis_status gsis_batch_status(gsis_batch *b, int32_t *n_iter, int32_t *converged,
+                              double *last_err, int32_t *n_finished);
+/* Results of problem i, as gsis_plan_read. */
+gsis_status gsis_batch_read(gsis_batch *b, int32_t i, gsis_result *r);
+/* Every problem back to its initial state. */
+gsis_status gsis_batch_reset(gsis_batch *b);
+
+typedef struct {
+  int32_t rows, prefetch;  /* chosen sweep configuration: rows per pass
+                              (workgroup size) and prefetch depth */
+  int32_t grid;            /* persistent workgroups launched */
+  int32_t cg_iters;        /* CG iterations per outer iteration */
+  int32_t n_configs;       /* compiled configurations timed (<= 8) */
+  int32_t config_rows[8], config_prefetch[8];
+  double config_ms[8];     /* measured sweep time of each (-1: did not fit) */
+} gsis_batch_tuning;
+gsis_status gsis_batch_get_tuning(gsis_batch *b, gsis_batch_tuning *t);
+
+/* One-shot: create, iterate until every problem stops, read r[0..n-1],
+ * destroy. Returns the worst per-problem status. */
+gsis_status gsis_solve_batch(gsis_ctx *ctx, int32_t n, const gsis_problem *p,
+                             const gsis_options *o, gsis_result *r /* [n] */);
 
 /* Library build string (compiler, target, options). */
 const char *gsis_version(void);

@@ -14,52 +14,9 @@
 #include <vector>
 
 #include "../../include/gsis.h"
-#include "gsis_internal.h"
+#include "plan.h"
 
-using namespace gsis;
-
-struct gsis_ctx {
-  int device = 0;
-  std::string err;
-};
-
-struct gsis_plan {
-  gsis_ctx *ctx = nullptr;
-  PlanDev P;
-  hipStream_t stream = nullptr;
-  int device_ptrs = 0;
-  int profile = 0;
-  std::vector<int> perm;          // internal ordinate -> caller ordinate
-  double swmu = 0, sweta = 0;     // sum_k w_k mu_k, sum_k w_k eta_k
-  std::vector<double> I0_host;    // warm start in the internal layout (may be empty)
-  std::vector<float> I0_host_f;   // FP32-mixed: I0 - phi0/(4 pi) in the internal layout
-  std::vector<double> phi0_host;  // phi of the warm start
-  std::vector<void *> allocs;
-  double *host_scal = nullptr;    // pinned
-  // profiling: per iteration GSIS_NUM_PHASES + 1 events bracketing the phases
-  std::vector<hipEvent_t> events;
-  int prof_iters = 0;
-};
-
-static thread_local std::string g_create_err;
-
-static gsis_status fail(gsis_ctx *ctx, gsis_status st, const char *fmt, ...) {
-  char buf[512];
-  va_list ap;
-  va_start(ap, fmt);
-  vsnprintf(buf, sizeof buf, fmt, ap);
-  va_end(ap);
-  if (ctx) ctx->err = buf;
-  else g_create_err = buf;
-  return st;
-}
-
-#define HIPCHK(ctx, call)                                                             \
-  do {                                                                                \
-    hipError_t e_ = (call);                                                           \
-    if (e_ != hipSuccess)                                                             \
-      return fail(ctx, GSIS_E_DEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
-  } while (0)
+thread_local std::string g_create_err;
 
 extern "C" {
 
@@ -104,6 +61,7 @@ gsis_status gsis_options_default(gsis_options *o) {
   o->synth_max_iter = 50;
   o->cfl_p = 0.0;
   o->beta = 0.0;
+  o->graph = 1;
   return GSIS_OK;
 }
 
@@ -201,18 +159,6 @@ gsis_status check_problem(gsis_ctx *ctx, const gsis_problem *p, const gsis_optio
   return GSIS_OK;
 }
 
-template <typename T>
-gsis_status dalloc(gsis_plan *pl, T **p, size_t n) {
-  void *v = nullptr;
-  hipError_t e = hipMalloc(&v, std::max<size_t>(n, 1) * sizeof(T));
-  if (e != hipSuccess)
-    return fail(pl->ctx, GSIS_E_OOM, "hipMalloc(%zu bytes): %s", n * sizeof(T),
-                hipGetErrorString(e));
-  pl->allocs.push_back(v);
-  *p = (T *)v;
-  return GSIS_OK;
-}
-
 // One intensity buffer: N*K doubles, or N*K floats in FP32-mixed mode.
 gsis_status alloc_intensity(gsis_plan *pl, int which, size_t nk, bool f32) {
   gsis_status st;
@@ -226,14 +172,6 @@ gsis_status alloc_intensity(gsis_plan *pl, int which, size_t nk, bool f32) {
     pl->P.I[which] = p;
   }
   return st;
-}
-
-template <typename T>
-gsis_status upload(gsis_plan *pl, T **p, const std::vector<T> &h) {
-  gsis_status st = dalloc(pl, p, h.size());
-  if (st) return st;
-  if (!h.empty()) HIPCHK(pl->ctx, hipMemcpy(*p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
-  return GSIS_OK;
 }
 
 // Dense SPD inverse by Cholesky (coarsest multigrid level, n <= a few hundred).
@@ -269,12 +207,131 @@ bool dense_spd_inverse(int n, std::vector<double> &A) {
   return true;
 }
 
-struct HostLevel {
-  int nx, ny, fx = 1, fy = 1;
-  std::vector<double> diag, ax, ay;
-};
 
 }  // namespace
+
+// Multigrid hierarchy of the level-0 synthetic operator hl[0] (Galerkin
+// coarsening) and the device state of a synthetic solve on P: levels, dense
+// coarsest inverse, CG vectors, block partials and scalars. P.N must be set.
+gsis_status setup_synth(gsis_plan *pl, PlanDev &P, std::vector<HostLevel> &hl) {
+  // Galerkin coarsening. Aggregates are 2x2, or 2x1 / 1x2 when the
+  // couplings in one direction are much weaker than in the other (then
+  // merging across the weak direction would leave error the point smoother
+  // cannot reach).
+  const int kCoarseMax = 64;   // dense inverse of the coarsest level: at most 64 x 64
+  while ((long)hl.back().nx * hl.back().ny > kCoarseMax && (hl.back().nx > 1 || hl.back().ny > 1)) {
+    HostLevel &F = hl.back();
+    double lx = 0, ly = 0;
+    long mx = 0, my = 0;
+    for (int j = 0; j < F.ny; ++j)
+      for (int i = 0; i < F.nx; ++i) {
+        const int c = j * F.nx + i;
+        if (i + 1 < F.nx) { lx += std::log(F.ax[c]); ++mx; }
+        if (j + 1 < F.ny) { ly += std::log(F.ay[c]); ++my; }
+      }
+    const double gx = mx ? std::exp(lx / mx) : 0.0, gy = my ? std::exp(ly / my) : 0.0;
+    F.fx = (F.nx > 1 && gx >= 0.25 * gy) ? 2 : 1;
+    F.fy = (F.ny > 1 && gy >= 0.25 * gx) ? 2 : 1;
+    HostLevel C;
+    C.nx = (F.nx + F.fx - 1) / F.fx;
+    C.ny = (F.ny + F.fy - 1) / F.fy;
+    const int Nc = C.nx * C.ny;
+    C.diag.assign(Nc, 0.0); C.ax.assign(Nc, 0.0); C.ay.assign(Nc, 0.0);
+    for (int j = 0; j < F.ny; ++j)
+      for (int i = 0; i < F.nx; ++i) {
+        const int c = j * F.nx + i;
+        const int Ci = i / F.fx, Cj = j / F.fy;
+        const int Cc = Cj * C.nx + Ci;
+        C.diag[Cc] += F.diag[c];
+        if (i + 1 < F.nx) {
+          const int Ci2 = (i + 1) / F.fx;
+          if (Ci2 == Ci) C.diag[Cc] -= 2.0 * F.ax[c];
+          else C.ax[Cc] += F.ax[c];
+        }
+        if (j + 1 < F.ny) {
+          const int Cj2 = (j + 1) / F.fy;
+          if (Cj2 == Cj) C.diag[Cc] -= 2.0 * F.ay[c];
+          else C.ay[Cc] += F.ay[c];
+        }
+      }
+    hl.push_back(std::move(C));
+  }
+  // dense inverse of the coarsest level
+  const HostLevel &Lc = hl.back();
+  const int nc = Lc.nx * Lc.ny;
+  std::vector<double> dense((size_t)nc * nc, 0.0);
+  for (int j = 0; j < Lc.ny; ++j)
+    for (int i = 0; i < Lc.nx; ++i) {
+      const int c = j * Lc.nx + i;
+      dense[(size_t)c * nc + c] = Lc.diag[c];
+      if (i + 1 < Lc.nx) {
+        dense[(size_t)c * nc + c + 1] = -Lc.ax[c];
+        dense[(size_t)(c + 1) * nc + c] = -Lc.ax[c];
+      }
+      if (j + 1 < Lc.ny) {
+        dense[(size_t)c * nc + c + Lc.nx] = -Lc.ay[c];
+        dense[(size_t)(c + Lc.nx) * nc + c] = -Lc.ay[c];
+      }
+    }
+  if (!dense_spd_inverse(nc, dense))
+    return fail(pl->ctx, GSIS_E_INVALID_ARG, "synthetic operator is not positive definite");
+
+  gsis_status st;
+  const int N = P.N;
+  if ((st = dalloc(pl, &P.cg_r, N)) || (st = dalloc(pl, &P.cg_z, N)) ||
+      (st = dalloc(pl, &P.cg_p, N)) || (st = dalloc(pl, &P.cg_p2, N)) ||
+      (st = dalloc(pl, &P.cg_Ap, N)) || (st = dalloc(pl, &P.scal, 16)))
+    return st;
+  P.red_blocks = (N + 255) / 256;
+  if ((st = dalloc(pl, &P.red, 2 * (size_t)P.red_blocks + 2))) return st;
+  P.mg.resize(hl.size());
+  for (size_t l = 0; l < hl.size(); ++l) {
+    MGLevel &L = P.mg[l];
+    L.nx = hl[l].nx; L.ny = hl[l].ny; L.fx = hl[l].fx; L.fy = hl[l].fy;
+    const size_t n = (size_t)L.nx * L.ny;
+    if ((st = upload(pl, &L.diag, hl[l].diag)) || (st = upload(pl, &L.ax, hl[l].ax)) ||
+        (st = upload(pl, &L.ay, hl[l].ay)) || (st = dalloc(pl, &L.x, n)) ||
+        (st = dalloc(pl, &L.b, n)) || (st = dalloc(pl, &L.r, n)))
+      return st;
+  }
+  P.coarse_n = nc;
+  if ((st = upload(pl, &P.coarse_inv, dense))) return st;
+  return GSIS_OK;
+}
+
+// Launch set of a single plan: its synthetic-step descriptor on the device
+// and block counts per level (no block tables). Needs every array of P.
+gsis_status make_single_set(gsis_plan *pl) {
+  PlanDev &P = pl->P;
+  SynthSet &S = P.S;
+  const SynthDesc D = make_synth_desc(P);
+  gsis_status st;
+  {
+    char *d = nullptr;
+    if ((st = dalloc(pl, &d, sizeof D))) return st;
+    HIPCHK(pl->ctx, hipMemcpy(d, &D, sizeof D, hipMemcpyHostToDevice));
+    S.desc = (SynthDesc *)d;
+  }
+  auto nb = [](int n) { return (n + 255) / 256; };
+  S.n = 1;
+  S.max_lc = D.lc;
+  P.lc = D.lc;
+  S.coarse_lds = coarse_lds_bytes(P);
+  S.synth_max_iter = P.synth_max_iter;
+  S.nb_cell = nb(P.N);
+  S.bt_cell = nullptr;
+  S.bt_fine.assign(D.lc, nullptr);
+  S.bt_restr.assign(D.lc, nullptr);
+  S.nb_fine.resize(D.lc);
+  S.nb_restr.resize(D.lc);
+  for (int l = 0; l < D.lc; ++l) {
+    S.nb_fine[l] = nb(P.mg[l].nx * P.mg[l].ny);
+    S.nb_restr[l] = nb(P.mg[l + 1].nx * P.mg[l + 1].ny);
+  }
+  S.state0 = P.state;
+  prepare_synth(S.coarse_lds);
+  return GSIS_OK;
+}
 
 // ------------------------------------------------------------------- plans
 extern "C" gsis_status gsis_plan_create(gsis_ctx *ctx, const gsis_problem *p,
@@ -390,68 +447,6 @@ extern "C" gsis_status gsis_plan_create(gsis_ctx *ctx, const gsis_problem *p,
       if (j > 0) d += hl[0].ay[c - nx]; else d += p->dx * kap[2 * ny + i];
       hl[0].diag[c] = d;
     }
-  // Galerkin coarsening. Aggregates are 2x2, or 2x1 / 1x2 when the
-  // couplings in one direction are much weaker than in the other (then
-  // merging across the weak direction would leave error the point smoother
-  // cannot reach).
-  const int kCoarseMax = 64;   // dense inverse of the coarsest level: at most 64 x 64
-  while ((long)hl.back().nx * hl.back().ny > kCoarseMax && (hl.back().nx > 1 || hl.back().ny > 1)) {
-    HostLevel &F = hl.back();
-    double lx = 0, ly = 0;
-    long mx = 0, my = 0;
-    for (int j = 0; j < F.ny; ++j)
-      for (int i = 0; i < F.nx; ++i) {
-        const int c = j * F.nx + i;
-        if (i + 1 < F.nx) { lx += std::log(F.ax[c]); ++mx; }
-        if (j + 1 < F.ny) { ly += std::log(F.ay[c]); ++my; }
-      }
-    const double gx = mx ? std::exp(lx / mx) : 0.0, gy = my ? std::exp(ly / my) : 0.0;
-    F.fx = (F.nx > 1 && gx >= 0.25 * gy) ? 2 : 1;
-    F.fy = (F.ny > 1 && gy >= 0.25 * gx) ? 2 : 1;
-    HostLevel C;
-    C.nx = (F.nx + F.fx - 1) / F.fx;
-    C.ny = (F.ny + F.fy - 1) / F.fy;
-    const int Nc = C.nx * C.ny;
-    C.diag.assign(Nc, 0.0); C.ax.assign(Nc, 0.0); C.ay.assign(Nc, 0.0);
-    for (int j = 0; j < F.ny; ++j)
-      for (int i = 0; i < F.nx; ++i) {
-        const int c = j * F.nx + i;
-        const int Ci = i / F.fx, Cj = j / F.fy;
-        const int Cc = Cj * C.nx + Ci;
-        C.diag[Cc] += F.diag[c];
-        if (i + 1 < F.nx) {
-          const int Ci2 = (i + 1) / F.fx;
-          if (Ci2 == Ci) C.diag[Cc] -= 2.0 * F.ax[c];
-          else C.ax[Cc] += F.ax[c];
-        }
-        if (j + 1 < F.ny) {
-          const int Cj2 = (j + 1) / F.fy;
-          if (Cj2 == Cj) C.diag[Cc] -= 2.0 * F.ay[c];
-          else C.ay[Cc] += F.ay[c];
-        }
-      }
-    hl.push_back(std::move(C));
-  }
-  // dense inverse of the coarsest level
-  const HostLevel &Lc = hl.back();
-  const int nc = Lc.nx * Lc.ny;
-  std::vector<double> dense((size_t)nc * nc, 0.0);
-  for (int j = 0; j < Lc.ny; ++j)
-    for (int i = 0; i < Lc.nx; ++i) {
-      const int c = j * Lc.nx + i;
-      dense[(size_t)c * nc + c] = Lc.diag[c];
-      if (i + 1 < Lc.nx) {
-        dense[(size_t)c * nc + c + 1] = -Lc.ax[c];
-        dense[(size_t)(c + 1) * nc + c] = -Lc.ax[c];
-      }
-      if (j + 1 < Lc.ny) {
-        dense[(size_t)c * nc + c + Lc.nx] = -Lc.ay[c];
-        dense[(size_t)(c + Lc.nx) * nc + c] = -Lc.ay[c];
-      }
-    }
-  if (!dense_spd_inverse(nc, dense))
-    return bail(fail(ctx, GSIS_E_INVALID_ARG, "synthetic operator is not positive definite"));
-
   // -- pseudo-time shift of the increment-solve diagonal (Eqs. cfl_pse,
   // tau_pse, elem_main_shifted); |sigma_i r^L - sigma_j r^R| is
   // (sigma_i h + sigma_j h) / 2 for the face-normal width h
@@ -558,10 +553,7 @@ extern "C" gsis_status gsis_plan_create(gsis_ctx *ctx, const gsis_problem *p,
       (st = dalloc(pl, &P.hx, N)) || (st = dalloc(pl, &P.hy, N)) ||
       (st = dalloc(pl, &P.rhs, N)) || (st = upload(pl, &P.bnd, bnd_int)) ||
       (st = dalloc(pl, &P.bflux, P.nbf)) || (st = upload(pl, &P.kappa, kap)) ||
-      (st = dalloc(pl, &P.cg_r, N)) || (st = dalloc(pl, &P.cg_z, N)) ||
-      (st = dalloc(pl, &P.cg_p, N)) || (st = dalloc(pl, &P.cg_p2, N)) ||
-      (st = dalloc(pl, &P.cg_Ap, N)) ||
-      (st = dalloc(pl, &P.scal, 16)) || (st = dalloc(pl, &P.err_hist, o->max_iter)) ||
+      (st = dalloc(pl, &P.err_hist, o->max_iter)) ||
       (st = dalloc(pl, &P.state, 4)) || (st = dalloc(pl, &P.last_err, 1)))
     return bail(st);
   if (f32) {
@@ -569,23 +561,13 @@ extern "C" gsis_status gsis_plan_create(gsis_ctx *ctx, const gsis_problem *p,
   } else {
     P.base = P.delta;
   }
-  P.red_blocks = (N + 255) / 256;
-  if ((st = dalloc(pl, &P.red, 2 * (size_t)P.red_blocks + 2)) ||
-      (st = dalloc(pl, &P.err_parts, 2 * (size_t)P.red_blocks + 2)))
+  if ((st = dalloc(pl, &P.err_parts, 2 * (size_t)((N + 255) / 256) + 2)) ||
+      (st = setup_synth(pl, P, hl)))
     return bail(st);
-  P.mg.resize(hl.size());
-  for (size_t l = 0; l < hl.size(); ++l) {
-    MGLevel &L = P.mg[l];
-    L.nx = hl[l].nx; L.ny = hl[l].ny; L.fx = hl[l].fx; L.fy = hl[l].fy;
-    const size_t n = (size_t)L.nx * L.ny;
-    if ((st = upload(pl, &L.diag, hl[l].diag)) || (st = upload(pl, &L.ax, hl[l].ax)) ||
-        (st = upload(pl, &L.ay, hl[l].ay)) || (st = dalloc(pl, &L.x, n)) ||
-        (st = dalloc(pl, &L.b, n)) || (st = dalloc(pl, &L.r, n)))
-      return bail(st);
-  }
-  P.coarse_n = nc;
-  if ((st = upload(pl, &P.coarse_inv, dense))) return bail(st);
-  prepare_synth(P);
+  if (P.mg.size() > (size_t)kMaxLevels)
+    return bail(fail(ctx, GSIS_E_INVALID_ARG, "multigrid hierarchy deeper than %d levels",
+                     kMaxLevels));
+  if ((st = make_single_set(pl))) return bail(st);
   {
     void *h = nullptr;
     hipError_t e = hipHostMalloc(&h, 64, hipHostMallocDefault);
@@ -631,7 +613,7 @@ extern "C" gsis_status gsis_plan_reset(gsis_plan *pl) {
                                hipMemcpyHostToDevice, s));
   HIPCHK(ctx, hipMemsetAsync(P.state, 0, 4 * sizeof(int32_t), s));
   HIPCHK(ctx, hipMemsetAsync(P.err_hist, 0, P.max_iter * sizeof(double), s));
-  launch_source(P, s);
+  launch_source(P.S, s);
   HIPCHK(ctx, hipGetLastError());
   HIPCHK(ctx, hipStreamSynchronize(s));
   pl->prof_iters = 0;
@@ -667,12 +649,12 @@ extern "C" gsis_status gsis_plan_iterate(gsis_plan *pl, int32_t n) {
     if ((st = record(pl, 2))) return st;
     if (P.method == GSIS_GSIS) {
       launch_boundary_flux(P, s);
-      launch_hot_rhs(P, s);
+      launch_hot_rhs(P.S, s);
     }
     if ((st = record(pl, 3))) return st;
-    if (P.method == GSIS_GSIS) launch_synth_solve(P, s, (int32_t *)pl->host_scal);
+    if (P.method == GSIS_GSIS) launch_synth_solve(P.S, s, (int32_t *)pl->host_scal);
     if ((st = record(pl, 4))) return st;
-    launch_update(P, s);
+    launch_update(P.S, s);
     if ((st = record(pl, 5))) return st;
     HIPCHK(ctx, hipGetLastError());
     if (pl->profile) pl->prof_iters++;

@@ -50,6 +50,56 @@ struct MGLevel {
   double *x = nullptr, *b = nullptr, *r = nullptr;  // work vectors (levels >= 1)
 };
 
+// ---- synthetic step, one problem or many: every kernel of the synthetic
+// step reads its problem from a device array of SynthDesc records, and a
+// block table (problem, block of that problem) spreads one launch over many
+// problems (NULL table: a single problem, block = blockIdx.x).
+constexpr int kMaxLevels = 40;
+constexpr int kMaxCoarseLevels = 10;
+struct CoarseLevels {
+  int nlev;
+  int nx[kMaxCoarseLevels], ny[kMaxCoarseLevels], fx[kMaxCoarseLevels], fy[kMaxCoarseLevels];
+  const double *dg[kMaxCoarseLevels], *ax[kMaxCoarseLevels], *ay[kMaxCoarseLevels];
+  int xoff[kMaxCoarseLevels];   // LDS offset of x_l (b_l follows, n_l later)
+  int aoff[kMaxCoarseLevels];   // LDS offset of (dg, ax, ay) of level l >= 1
+};
+struct LevelDev {
+  int nx, ny, fx, fy;
+  const double *dg, *ax, *ay;
+  double *x, *b;                // levels >= 1 (level 0 uses the CG's z and r)
+};
+struct SynthDesc {
+  int nx, ny, N;
+  double dx, dy, V;
+  int method, fp32, max_iter;
+  double tol, rtol;
+  const double *sig_t, *sig_s, *q, *cE, *cW, *cN, *cS, *kappa;
+  const double *phih, *Fx, *Fy, *bflux;
+  double *hx, *hy, *rhs, *phi, *delta, *base, *src, *dynq;
+  double *cg_r, *cg_z, *cg_p0, *cg_p1, *cg_Ap, *red, *scal, *err_parts, *err_hist, *last_err;
+  int32_t *state;
+  int nlev, lc;                 // levels; first level of the one-workgroup cycle
+  LevelDev lev[kMaxLevels];
+  CoarseLevels cl;
+  const double *coarse_inv;
+};
+// Host-side description of one launch set (a plan, or a batch of plans).
+struct SynthSet {
+  int n = 0;                          // problems
+  SynthDesc *desc = nullptr;          // device [n]
+  int max_lc = 0;                     // deepest first coarse level
+  size_t coarse_lds = 0;              // dynamic LDS of the coarse kernel
+  int synth_max_iter = 50;
+  // block tables (nullptr for a single problem) and their block counts
+  int2 *bt_cell = nullptr;            // level-0 cells of every problem
+  int nb_cell = 0;
+  std::vector<int2 *> bt_fine;        // [l]: level-l cells of problems with lc > l
+  std::vector<int> nb_fine;
+  std::vector<int2 *> bt_restr;       // [l]: level-(l+1) cells of problems with lc > l
+  std::vector<int> nb_restr;
+  int32_t *state0 = nullptr;          // single problem: its state (host checks)
+};
+
 struct PlanDev {
   // problem
   int nx = 0, ny = 0, N = 0, K = 0, nbf = 0;
@@ -106,21 +156,48 @@ struct PlanDev {
                                // -1 diverged, 2 max_iter), [2] current I buffer,
                                // [3] synthetic CG converged
   double *last_err = nullptr;
+  SynthSet S;                  // launch set of this plan alone
+  int lc = 0;                  // first level of the one-workgroup cycle
 };
 
 // ---- transport kernels (kernels_transport.hip)
 void launch_transport(const PlanDev &P, hipStream_t s);   // residual + sweep
+// Batched sweep: per-problem kernel arguments (fill_targs into a device
+// table of targs_bytes() records), work items (problem, internal ordinate),
+// a device counter, and one of the compiled launch configurations.
+struct BatchSweepConfig { int rows, pf; };
+constexpr int kNumBatchSweepConfigs = 6;
+extern const BatchSweepConfig kBatchSweepConfigs[kNumBatchSweepConfigs];
+size_t targs_bytes();
+void fill_targs(const PlanDev &P, void *dst);
+int sweep_batch_blocks_per_cu(int cfg, bool fp32);
+void launch_sweep_batch(const void *targs, const int2 *items, int n_items, int *counter, int cfg,
+                        bool fp32, int grid, hipStream_t s);
+// moments over blocks (problem, 256-cell block) and boundary fluxes over
+// (problem, boundary face) of a batch
+void launch_moments_batch(const void *targs, const int2 *bt_cell, int nb_cell, bool fp32,
+                          hipStream_t s);
+void launch_boundary_flux_batch(const void *targs, const int2 *bt_face, int nb_face,
+                                hipStream_t s);
 void launch_moments(const PlanDev &P, hipStream_t s);
 void launch_boundary_flux(const PlanDev &P, hipStream_t s);
 
 // ---- synthetic / update kernels (kernels_synth.hip)
-void launch_source(const PlanDev &P, hipStream_t s);          // src from phi
-void launch_hot_rhs(const PlanDev &P, hipStream_t s);
-void prepare_synth(PlanDev &P);
-void launch_synth_solve(PlanDev &P, hipStream_t s, int32_t *host_flag);
-void launch_update(const PlanDev &P, hipStream_t s);
+// Descriptor of plan P's synthetic step (host copy; P's arrays and levels
+// must exist) and the first level of its one-workgroup coarse cycle.
+SynthDesc make_synth_desc(const PlanDev &P);
+int coarse_start(const PlanDev &P);
+size_t coarse_lds_bytes(const PlanDev &P);
+void prepare_synth(size_t coarse_lds);      // kernel attribute for the LDS size
+void launch_source(const SynthSet &S, hipStream_t s);          // src from phi
+void launch_hot_rhs(const SynthSet &S, hipStream_t s);
+// host_flag: pinned int32[3] for the host's stop checks (single problem);
+// NULL never waits and enqueues exactly S.synth_max_iter iterations.
+void launch_synth_solve(const SynthSet &S, hipStream_t s, int32_t *host_flag);
+void launch_update(const SynthSet &S, hipStream_t s);
 void launch_apply_delta_final(const PlanDev &P, hipStream_t s, double swmu, double sweta,
                               double *Fx_out, double *Fy_out);
-void launch_d1_apply(const PlanDev &P, const double *x, double *y, hipStream_t s);
+// CG iterations of P's last synthetic solve (one device double)
+double *synth_iteration_counter(const PlanDev &P);
 
 }  // namespace gsis

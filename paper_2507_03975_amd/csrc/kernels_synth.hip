@@ -12,11 +12,17 @@
 //            Gauss-Seidel smoothing, dense inverse on the coarsest level).
 //  update  : delta = phi' - phi_half (Eq. GSIS_update, applied lazily by the
 //            transport kernels), Err (Eq. Err_W), next source.
+//
+// Every kernel takes its problem from a SynthDesc record. A launch covers one
+// problem (block table NULL) or many: the table maps each block to (problem,
+// block of that problem), so the problems of a batch advance together while
+// each keeps its own CG scalars, multigrid hierarchy and stop flags.
 // All reductions are two-stage with a fixed order, so results repeat bit for
-// bit.
+// bit, and a problem gets the same numbers alone or in a batch.
 #include "gsis_internal.h"
 
 #include <algorithm>
+#include <cstring>
 
 namespace gsis {
 namespace {
@@ -45,45 +51,57 @@ __device__ inline void cell_ij(int c, int nx, int &i, int &j) {
   i = r; j = q;
 }
 
+// The block's problem and its block index within that problem.
+struct Blk { int p, lb; };
+__device__ inline Blk blk(const int2 *bt) {
+  if (!bt) return {0, (int)blockIdx.x};
+  const int2 v = bt[blockIdx.x];
+  return {v.x, v.y};
+}
+
 // ---------------------------------------------------------------- HoT / RHS
-__global__ void k_hot(int nx, int ny, const double *phih, const double *Fx,
-                      const double *Fy, const double *sig_t, const double *cE,
-                      const double *cW, const double *cN, const double *cS,
-                      double *hx, double *hy, const int32_t *state) {
-  if (state[1] != 0) return;
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= nx * ny) return;
+__global__ void k_hot(const SynthDesc *ds, const int2 *bt) {
+  const Blk B = blk(bt);
+  const SynthDesc &D = ds[B.p];
+  if (D.state[1] != 0) return;
+  const int nx = D.nx, ny = D.ny;
+  const int c = B.lb * kRedBlock + threadIdx.x;
+  if (c >= D.N) return;
   int i, j;
   cell_ij(c, nx, i, j);
+  const double *phih = D.phih;
   const double u = phih[c];
   const double ue = i + 1 < nx ? phih[c + 1] : u, uw = i > 0 ? phih[c - 1] : u;
   const double un = j + 1 < ny ? phih[c + nx] : u, us = j > 0 ? phih[c - nx] : u;
-  const double gx = cE[c] * (ue - u) - cW[c] * (uw - u);
-  const double gy = cN[c] * (un - u) - cS[c] * (us - u);
-  hx[c] = Fx[c] + gx / (3.0 * sig_t[c]);
-  hy[c] = Fy[c] + gy / (3.0 * sig_t[c]);
+  const double gx = D.cE[c] * (ue - u) - D.cW[c] * (uw - u);
+  const double gy = D.cN[c] * (un - u) - D.cS[c] * (us - u);
+  D.hx[c] = D.Fx[c] + gx / (3.0 * D.sig_t[c]);
+  D.hy[c] = D.Fy[c] + gy / (3.0 * D.sig_t[c]);
 }
 
-__global__ void k_rhs(int nx, int ny, double dx, double dy, const double *q,
-                      const double *hx, const double *hy, const double *phih,
-                      const double *bflux, const double *kappa, double *b,
-                      const int32_t *state) {
-  if (state[1] != 0) return;
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= nx * ny) return;
+__global__ void k_rhs(const SynthDesc *ds, const int2 *bt) {
+  const Blk B = blk(bt);
+  const SynthDesc &D = ds[B.p];
+  if (D.state[1] != 0) return;
+  const int nx = D.nx, ny = D.ny;
+  const int c = B.lb * kRedBlock + threadIdx.x;
+  if (c >= D.N) return;
   int i, j;
   cell_ij(c, nx, i, j);
-  double s = dx * dy * q[c];
+  const double dx = D.dx, dy = D.dy;
+  const double *hx = D.hx, *hy = D.hy, *bflux = D.bflux, *kappa = D.kappa;
+  const double ph = D.phih[c];
+  double s = dx * dy * D.q[c];
   // east / west (area dy), north / south (area dx)
   if (i + 1 < nx) s -= dy * (0.5 * (hx[c] + hx[c + 1]));
-  else s -= dy * (bflux[ny + j] - kappa[ny + j] * phih[c]);
+  else s -= dy * (bflux[ny + j] - kappa[ny + j] * ph);
   if (i > 0) s += dy * (0.5 * (hx[c] + hx[c - 1]));
-  else s -= dy * (bflux[j] - kappa[j] * phih[c]);
+  else s -= dy * (bflux[j] - kappa[j] * ph);
   if (j + 1 < ny) s -= dx * (0.5 * (hy[c] + hy[c + nx]));
-  else s -= dx * (bflux[2 * ny + nx + i] - kappa[2 * ny + nx + i] * phih[c]);
+  else s -= dx * (bflux[2 * ny + nx + i] - kappa[2 * ny + nx + i] * ph);
   if (j > 0) s += dx * (0.5 * (hy[c] + hy[c - nx]));
-  else s -= dx * (bflux[2 * ny + i] - kappa[2 * ny + i] * phih[c]);
-  b[c] = s;
+  else s -= dx * (bflux[2 * ny + i] - kappa[2 * ny + i] * ph);
+  D.rhs[c] = s;
 }
 
 // ------------------------------------------------------- 5-point operator
@@ -99,237 +117,265 @@ __device__ inline double apply5(int nx, int ny, const double *dg, const double *
   return s;
 }
 
-// y = A x, optional partial of dot(x, y)
-__global__ void k_spmv_dot(int nx, int ny, const double *dg, const double *ax,
-                           const double *ay, const double *x, double *y, double *part,
-                           const int32_t *state) {
-  __shared__ double sh[kRedBlock];
-  if (state[1] != 0) return;
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  double v = 0.0;
-  if (c < nx * ny) {
-    double yc = apply5(nx, ny, dg, ax, ay, x, c);
-    y[c] = yc;
-    v = x[c] * yc;
-  }
-  double t = block_sum(v, sh);
-  if (part && threadIdx.x == 0) part[blockIdx.x] = t;
-}
-
 // Scalar slots
-enum { S_RZ = 0, S_PAP = 1, S_RR = 2, S_BB = 3, S_ALPHA = 4, S_BETA = 5, S_STOP = 6 };
+enum { S_RZ = 0, S_PAP = 1, S_RR = 2, S_BB = 3, S_ALPHA = 4, S_BETA = 5, S_STOP = 6,
+       S_NIT = 7 };
 
 // CG kernels run unless the outer iteration is done (state[1]) or this
 // synthetic solve has converged (state[3]).
 __device__ inline bool cg_off(const int32_t *st) { return st[1] != 0 || st[3] != 0; }
 
-// Sum npart partials, then: op 0 scal[slot] = s; 1 alpha = RZ / (PAP = s);
-// 2 beta = s / RZ, RZ = s; 3 RR = s, converged if RR <= STOP;
-// 4 RR = s, STOP = max(rtol^2 RR, 1e-28 BB), converged if RR <= STOP.
-__global__ void k_finish(const double *part, int npart, double *scal, int slot, int op,
-                         double rtol, int32_t *state) {
+inline int nblk(int n) { return (n + kRedBlock - 1) / kRedBlock; }
+__host__ __device__ inline int nblk_d(int n) { return (n + kRedBlock - 1) / kRedBlock; }
+
+// One workgroup per problem (blockIdx.x = problem). Sum the problem's
+// partials, then: op 0 scal[slot] = s; 1 alpha = RZ / (PAP = s); 2 beta =
+// s / RZ, RZ = s; 3 RR = s, count the iteration, converged if RR <= STOP;
+// 4 RR = s, STOP = max(rtol^2 RR, 1e-28 BB), converged if RR <= STOP,
+// iteration count 0. Partials: sel 0 red[0, nb), sel 1 red[nb, 2 nb), sel 2
+// the r.z partials (one value when the whole V-cycle ran in one workgroup).
+__global__ void k_finish(const SynthDesc *ds, int sel, int slot, int op) {
   __shared__ double sh[kRedBlock];
+  const SynthDesc &D = ds[blockIdx.x];
+  int32_t *state = D.state;
   if (cg_off(state)) return;
+  const int nb = nblk_d(D.N);
+  const double *part = D.red + (sel == 1 ? nb : 0);
+  const int npart = (sel == 2 && D.lc == 0) ? 1 : nb;
   double v = 0.0;
   for (int t = threadIdx.x; t < npart; t += blockDim.x) v += part[t];
   double s = block_sum(v, sh);
   if (threadIdx.x == 0) {
+    double *scal = D.scal;
     if (op == 0) scal[slot] = s;
     else if (op == 1) { scal[S_PAP] = s; scal[S_ALPHA] = scal[S_RZ] / s; }
     else if (op == 2) { scal[S_BETA] = s / scal[S_RZ]; scal[S_RZ] = s; }
-    else if (op == 3) { scal[S_RR] = s; if (!(s > scal[S_STOP])) state[3] = 1; }
-    else {
+    else if (op == 3) {
       scal[S_RR] = s;
-      const double stop = fmax(rtol * rtol * s, 1e-28 * scal[S_BB]);
+      scal[S_NIT] += 1.0;
+      if (!(s > scal[S_STOP])) state[3] = 1;
+    } else {
+      scal[S_RR] = s;
+      scal[S_NIT] = 0.0;
+      const double stop = fmax(D.rtol * D.rtol * s, 1e-28 * scal[S_BB]);
       scal[S_STOP] = stop;
       if (!(s > stop)) state[3] = 1;
     }
   }
 }
 
-// Start of a synthetic solve: warm start x = phi, clear the converged flag.
-__global__ void k_cg_begin(int n, const double *phi, double *x, int32_t *state) {
-  if (state[1] != 0) return;
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c < n) x[c] = phi[c];
-  if (c == 0) state[3] = 0;
-}
-
-// r = b - A x ; partials of r.r and b.b
-__global__ void k_cg_residual(int nx, int ny, const double *dg, const double *ax,
-                              const double *ay, const double *x, const double *b, double *r,
-                              double *part_rr, double *part_bb, const int32_t *state) {
+// Start of a synthetic solve: warm start x = phi, clear the converged flag;
+// r = b - A x; partials of r.r and b.b.
+__global__ void k_cg_begin(const SynthDesc *ds, const int2 *bt) {
   __shared__ double sh[kRedBlock];
-  if (state[1] != 0) return;
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const Blk B = blk(bt);
+  const SynthDesc &D = ds[B.p];
+  if (D.state[1] != 0) return;
+  const int c = B.lb * kRedBlock + threadIdx.x;
+  const LevelDev &L = D.lev[0];
   double rr = 0.0, bb = 0.0;
-  if (c < nx * ny) {
-    double rc = b[c] - apply5(nx, ny, dg, ax, ay, x, c);
-    r[c] = rc;
+  if (c < D.N) {
+    // x = phi for the cell and its neighbours (this kernel writes x)
+    auto X = [&](int k) { return D.phi[k]; };
+    int i, j;
+    cell_ij(c, L.nx, i, j);
+    const double xc = X(c);
+    double y = L.dg[c] * xc;
+    if (i + 1 < L.nx) y -= L.ax[c] * X(c + 1);
+    if (i > 0) y -= L.ax[c - 1] * X(c - 1);
+    if (j + 1 < L.ny) y -= L.ay[c] * X(c + L.nx);
+    if (j > 0) y -= L.ay[c - L.nx] * X(c - L.nx);
+    const double b = D.rhs[c];
+    const double rc = b - y;
+    L.x[c] = xc;
+    D.cg_r[c] = rc;
     rr = rc * rc;
-    bb = b[c] * b[c];
+    bb = b * b;
   }
+  if (B.lb == 0 && threadIdx.x == 0) D.state[3] = 0;
   double t = block_sum(rr, sh);
-  if (threadIdx.x == 0) part_rr[blockIdx.x] = t;
+  if (threadIdx.x == 0) D.red[B.lb] = t;
   t = block_sum(bb, sh);
-  if (threadIdx.x == 0) part_bb[blockIdx.x] = t;
+  if (threadIdx.x == 0) D.red[nblk_d(D.N) + B.lb] = t;
 }
 
 // p_new = z + beta p_old (= z on the first iteration), Ap = A p_new and a
 // partial of p_new . Ap. Neighbour values of p_new are formed from z and
-// p_old, so one kernel does both.
-__global__ void k_cg_pAp(int nx, int ny, const double *dg, const double *ax, const double *ay,
-                         const double *z, const double *pold, double *pnew, double *Ap,
-                         const double *scal, int first, double *part, const int32_t *state) {
+// p_old, so one kernel does both. par selects which p buffer is new.
+__global__ void k_cg_pAp(const SynthDesc *ds, const int2 *bt, int first, int par) {
   __shared__ double sh[kRedBlock];
-  if (cg_off(state)) return;
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  const double be = first ? 0.0 : scal[S_BETA];
+  const Blk B = blk(bt);
+  const SynthDesc &D = ds[B.p];
+  if (cg_off(D.state)) return;
+  const int c = B.lb * kRedBlock + threadIdx.x;
+  const LevelDev &L = D.lev[0];
+  const int nx = L.nx, ny = L.ny;
+  const double *z = D.cg_z;
+  const double *pold = par ? D.cg_p1 : D.cg_p0;
+  double *pnew = par ? D.cg_p0 : D.cg_p1;
+  const double be = first ? 0.0 : D.scal[S_BETA];
   auto P = [&](int k) { return first ? z[k] : z[k] + be * pold[k]; };
   double v = 0.0;
-  if (c < nx * ny) {
+  if (c < D.N) {
     int i, j;
-  cell_ij(c, nx, i, j);
+    cell_ij(c, nx, i, j);
     const double pc = P(c);
-    double y = dg[c] * pc;
-    if (i + 1 < nx) y -= ax[c] * P(c + 1);
-    if (i > 0) y -= ax[c - 1] * P(c - 1);
-    if (j + 1 < ny) y -= ay[c] * P(c + nx);
-    if (j > 0) y -= ay[c - nx] * P(c - nx);
+    double y = L.dg[c] * pc;
+    if (i + 1 < nx) y -= L.ax[c] * P(c + 1);
+    if (i > 0) y -= L.ax[c - 1] * P(c - 1);
+    if (j + 1 < ny) y -= L.ay[c] * P(c + nx);
+    if (j > 0) y -= L.ay[c - nx] * P(c - nx);
     pnew[c] = pc;
-    Ap[c] = y;
+    D.cg_Ap[c] = y;
     v = pc * y;
   }
   double t = block_sum(v, sh);
-  if (threadIdx.x == 0) part[blockIdx.x] = t;
+  if (threadIdx.x == 0) D.red[B.lb] = t;
 }
 
 // x += alpha p ; r -= alpha Ap ; partial of r.r
-__global__ void k_cg_update(int n, double *x, double *r, const double *p, const double *Ap,
-                            const double *scal, double *part, const int32_t *state) {
+__global__ void k_cg_update(const SynthDesc *ds, const int2 *bt, int par) {
   __shared__ double sh[kRedBlock];
-  if (cg_off(state)) return;
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const Blk B = blk(bt);
+  const SynthDesc &D = ds[B.p];
+  if (cg_off(D.state)) return;
+  const int c = B.lb * kRedBlock + threadIdx.x;
+  const double *p = par ? D.cg_p0 : D.cg_p1;
   double v = 0.0;
-  if (c < n) {
-    const double al = scal[S_ALPHA];
-    x[c] += al * p[c];
-    const double rc = r[c] - al * Ap[c];
-    r[c] = rc;
+  if (c < D.N) {
+    const double al = D.scal[S_ALPHA];
+    D.lev[0].x[c] += al * p[c];
+    const double rc = D.cg_r[c] - al * D.cg_Ap[c];
+    D.cg_r[c] = rc;
     v = rc * rc;
   }
   double t = block_sum(v, sh);
-  if (threadIdx.x == 0) part[blockIdx.x] = t;
+  if (threadIdx.x == 0) D.red[B.lb] = t;
 }
 
 // ------------------------------------------------------------ multigrid
+// Level l of a problem: vectors x, b are the CG's z, r on level 0.
+__device__ inline double *lev_x(const SynthDesc &D, int l) { return l == 0 ? D.cg_z : D.lev[l].x; }
+__device__ inline const double *lev_b(const SynthDesc &D, int l) {
+  return l == 0 ? D.cg_r : D.lev[l].b;
+}
+
 // Red-black Gauss-Seidel with colour (i + j) & 1 (0 red, 1 black).
 //   red:   x_r = (b + sum a x_nb) / d; with zero_init the neighbours are 0
-//          (first half sweep from x = 0). With part != nullptr also a partial
-//          of sum_c rdot_c x_c over all cells (the preconditioned residual
-//          product r.z; black cells are final at this point).
+//          (first half sweep from x = 0). With rz also a partial of
+//          sum_c r_c x_c over all cells (the preconditioned residual product
+//          r.z on level 0; black cells are final at this point).
 //   black: x_b = (b + sum a (x_nb + omega e_parent(nb))) / d, where e is the
-//          coarse-grid correction (nullptr: none). The red cells' own
+//          coarse-grid correction (corr = 0: none). The red cells' own
 //          corrected values are never needed: the red half sweep that
 //          follows overwrites them.
-__global__ void k_mg_red(int nx, int ny, const double *dg, const double *ax, const double *ay,
-                         double *x, const double *b, int zero_init, const double *rdot,
-                         double *part, const int32_t *state) {
+__global__ void k_mg_red(const SynthDesc *ds, const int2 *bt, int l, int zero_init, int rz) {
   __shared__ double sh[kRedBlock];
-  if (cg_off(state)) return;
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const Blk B = blk(bt);
+  const SynthDesc &D = ds[B.p];
+  if (cg_off(D.state)) return;
+  const LevelDev &L = D.lev[l];
+  const int nx = L.nx, ny = L.ny;
+  double *x = lev_x(D, l);
+  const double *b = lev_b(D, l);
+  const int c = B.lb * kRedBlock + threadIdx.x;
   double v = 0.0;
   if (c < nx * ny) {
     int i, j;
-  cell_ij(c, nx, i, j);
+    cell_ij(c, nx, i, j);
     double xc;
     if (((i + j) & 1) == 0) {
       double s = b[c];
       if (!zero_init) {
-        if (i + 1 < nx) s += ax[c] * x[c + 1];
-        if (i > 0) s += ax[c - 1] * x[c - 1];
-        if (j + 1 < ny) s += ay[c] * x[c + nx];
-        if (j > 0) s += ay[c - nx] * x[c - nx];
+        if (i + 1 < nx) s += L.ax[c] * x[c + 1];
+        if (i > 0) s += L.ax[c - 1] * x[c - 1];
+        if (j + 1 < ny) s += L.ay[c] * x[c + nx];
+        if (j > 0) s += L.ay[c - nx] * x[c - nx];
       }
-      xc = s / dg[c];
+      xc = s / L.dg[c];
       x[c] = xc;
     } else {
-      xc = part ? x[c] : 0.0;
+      xc = rz ? x[c] : 0.0;
     }
-    if (part) v = rdot[c] * xc;
+    if (rz) v = b[c] * xc;
   }
-  if (part) {
+  if (rz) {
     double t = block_sum(v, sh);
-    if (threadIdx.x == 0) part[blockIdx.x] = t;
+    if (threadIdx.x == 0) D.red[B.lb] = t;
   }
 }
 
-__global__ void k_mg_black(int nx, int ny, const double *dg, const double *ax, const double *ay,
-                           double *x, const double *b, const double *e, int fx, int fy, int cnx,
-                           double omega, const int32_t *state) {
-  if (cg_off(state)) return;
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_mg_black(const SynthDesc *ds, const int2 *bt, int l, int corr, double omega) {
+  const Blk B = blk(bt);
+  const SynthDesc &D = ds[B.p];
+  if (cg_off(D.state)) return;
+  const LevelDev &L = D.lev[l];
+  const int nx = L.nx, ny = L.ny;
+  const int c = B.lb * kRedBlock + threadIdx.x;
   if (c >= nx * ny) return;
   int i, j;
   cell_ij(c, nx, i, j);
   if (((i + j) & 1) != 1) return;
+  double *x = lev_x(D, l);
+  const double *b = lev_b(D, l);
+  const double *e = corr ? D.lev[l + 1].x : nullptr;
+  const int cnx = corr ? D.lev[l + 1].nx : 1, fx = L.fx, fy = L.fy;
   auto X = [&](int ii, int jj) {
     double v = x[jj * nx + ii];
     if (e) v += omega * e[(jj >> (fy >> 1)) * cnx + (ii >> (fx >> 1))];
     return v;
   };
   double s = b[c];
-  if (i + 1 < nx) s += ax[c] * X(i + 1, j);
-  if (i > 0) s += ax[c - 1] * X(i - 1, j);
-  if (j + 1 < ny) s += ay[c] * X(i, j + 1);
-  if (j > 0) s += ay[c - nx] * X(i, j - 1);
-  x[c] = s / dg[c];
+  if (i + 1 < nx) s += L.ax[c] * X(i + 1, j);
+  if (i > 0) s += L.ax[c - 1] * X(i - 1, j);
+  if (j + 1 < ny) s += L.ay[c] * X(i, j + 1);
+  if (j > 0) s += L.ay[c - nx] * X(i, j - 1);
+  x[c] = s / L.dg[c];
 }
 
-// r = b - A x on the fine level, then coarse b = sum over the fx x fy
-// children of each aggregate.
-__global__ void k_mg_restrict(int nx, int ny, const double *dg, const double *ax,
-                              const double *ay, const double *x, const double *b, int fx,
-                              int fy, int cnx, int cny, double *cb, const int32_t *state) {
-  if (cg_off(state)) return;
-  const int C = blockIdx.x * blockDim.x + threadIdx.x;
+// r = b - A x on level l, then the coarse b = sum over the fx x fy children
+// of each aggregate (blocks cover the coarse level l + 1).
+__global__ void k_mg_restrict(const SynthDesc *ds, const int2 *bt, int l) {
+  const Blk B = blk(bt);
+  const SynthDesc &D = ds[B.p];
+  if (cg_off(D.state)) return;
+  const LevelDev &L = D.lev[l], &CL = D.lev[l + 1];
+  const int nx = L.nx, ny = L.ny, cnx = CL.nx, cny = CL.ny;
+  const int C = B.lb * kRedBlock + threadIdx.x;
   if (C >= cnx * cny) return;
+  const double *x = lev_x(D, l);
+  const double *b = lev_b(D, l);
   int I, J;
   cell_ij(C, cnx, I, J);
   double s = 0.0;
-  for (int dj = 0; dj < fy; ++dj)
-    for (int di = 0; di < fx; ++di) {
-      const int i = fx * I + di, j = fy * J + dj;
+  for (int dj = 0; dj < L.fy; ++dj)
+    for (int di = 0; di < L.fx; ++di) {
+      const int i = L.fx * I + di, j = L.fy * J + dj;
       if (i < nx && j < ny) {
         const int c = j * nx + i;
-        s += b[c] - apply5(nx, ny, dg, ax, ay, x, c);
+        s += b[c] - apply5(nx, ny, L.dg, L.ax, L.ay, x, c);
       }
     }
-  cb[C] = s;
+  CL.b[C] = s;
 }
 
 // The coarse end of the V-cycle (every level with at most kCoarseWG cells,
-// down to the dense solve) in one workgroup of 1024 threads, so the half
-// sweeps are separated by workgroup barriers instead of kernel launches.
-// The top coarse level keeps its operator in registers (at most 4 cells per
-// thread), the lower levels in LDS; all vectors live in LDS.
+// down to the dense solve) in one workgroup of 1024 threads per problem, so
+// the half sweeps are separated by workgroup barriers instead of kernel
+// launches. The top coarse level keeps its operator in registers (at most 4
+// cells per thread), the lower levels in LDS; all vectors live in LDS.
 constexpr int kCoarseWG = 4096;
-constexpr int kMaxCoarseLevels = 10;
-struct CoarseLevels {
-  int nlev;
-  int nx[kMaxCoarseLevels], ny[kMaxCoarseLevels], fx[kMaxCoarseLevels], fy[kMaxCoarseLevels];
-  const double *dg[kMaxCoarseLevels], *ax[kMaxCoarseLevels], *ay[kMaxCoarseLevels];
-  int xoff[kMaxCoarseLevels];   // LDS offset of x_l (b_l follows, n_l later)
-  int aoff[kMaxCoarseLevels];   // LDS offset of (dg, ax, ay) of level l >= 1
-};
 
-__global__ void __launch_bounds__(1024) k_mg_coarse(CoarseLevels L, const double *bin,
-                                                    double *xout, const double *Ainv,
-                                                    double omega, double *part,
-                                                    const int32_t *state) {
+__global__ void __launch_bounds__(1024) k_mg_coarse(const SynthDesc *ds, double omega) {
   extern __shared__ double sm[];
   __shared__ double red[1024];
-  if (cg_off(state)) return;
+  const SynthDesc &D = ds[blockIdx.x];
+  if (cg_off(D.state)) return;
+  const CoarseLevels &L = D.cl;
+  const double *bin = D.lc == 0 ? D.cg_r : D.lev[D.lc].b;
+  double *xout = D.lc == 0 ? D.cg_z : D.lev[D.lc].x;
+  const double *Ainv = D.coarse_inv;
+  double *part = D.lc == 0 ? D.red : nullptr;
   const int tid = threadIdx.x, nt = blockDim.x;
   const int last = L.nlev - 1;
   const int n0 = L.nx[0] * L.ny[0];
@@ -558,16 +604,122 @@ __global__ void __launch_bounds__(1024) k_mg_coarse(CoarseLevels L, const double
   }
 }
 
-__global__ void k_copy(int n, const double *a, double *b, const int32_t *state) {
-  if (state[1] != 0) return;
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c < n) b[c] = a[c];
-}
-
-inline int nblk(int n) { return (n + kRedBlock - 1) / kRedBlock; }
 
 constexpr double kOmega = 1.7;   // coarse-grid correction scaling (aggregation MG)
 
+// ------------------------------------------------------------- update / Err
+// delta = phi' - phi_half (GSIS) or 0 (SI); Err partials; phi = phi_new.
+// FP32-mixed mode also records base = phi^m + delta (see the transport file).
+__global__ void k_update(const SynthDesc *ds, const int2 *bt) {
+  __shared__ double sh[kRedBlock];
+  const Blk B = blk(bt);
+  const SynthDesc &D = ds[B.p];
+  if (D.state[1] != 0) return;
+  const int c = B.lb * kRedBlock + threadIdx.x;
+  double num = 0.0, den = 0.0;
+  if (c < D.N) {
+    const double pn = D.method ? D.lev[0].x[c] : D.phih[c];
+    const double d = pn - D.phi[c];
+    num = D.V * d * d;
+    den = D.V * pn * pn;
+    const double dl = D.method ? pn - D.phih[c] : 0.0;
+    D.delta[c] = dl;
+    if (D.fp32) D.base[c] = D.phi[c] + dl;
+    D.phi[c] = pn;
+  }
+  double a = block_sum(num, sh);
+  double b = block_sum(den, sh);
+  if (threadIdx.x == 0) { D.err_parts[2 * B.lb] = a; D.err_parts[2 * B.lb + 1] = b; }
+}
+
+// One workgroup per problem: Err = sqrt(num/den) -> history, counters, done
+// flag.
+__global__ void k_err_finish(const SynthDesc *ds) {
+  __shared__ double sh[kRedBlock];
+  const SynthDesc &D = ds[blockIdx.x];
+  int32_t *state = D.state;
+  if (state[1] != 0) return;
+  const int npart = nblk_d(D.N);
+  double a = 0.0, b = 0.0;
+  for (int t = threadIdx.x; t < npart; t += blockDim.x) {
+    a += D.err_parts[2 * t];
+    b += D.err_parts[2 * t + 1];
+  }
+  double num = block_sum(a, sh);
+  double den = block_sum(b, sh);
+  if (threadIdx.x == 0) {
+    double err = den > 0.0 ? sqrt(num / den) : (num == 0.0 ? 0.0 : INFINITY);
+    const int m = state[0];
+    D.err_hist[m] = err;
+    *D.last_err = err;
+    state[0] = m + 1;
+    state[2] = 1 - state[2];   // I^{m+1} now lives in the other buffer
+    if (!isfinite(err)) state[1] = -1;
+    else if (err < D.tol) state[1] = 1;
+    else if (m + 1 >= D.max_iter) state[1] = 2;
+  }
+}
+
+// src = (sigma_s phi + q) / (4 pi); the mirrored per-quadrant copies of
+// (src, base/(4 pi), phi/(4 pi)) read by the fused sweep.
+__global__ void k_source(const SynthDesc *ds, const int2 *bt) {
+  const Blk B = blk(bt);
+  const SynthDesc &D = ds[B.p];
+  if (D.state[1] != 0) return;
+  const int nx = D.nx, ny = D.ny, n = D.N;
+  const int c = B.lb * kRedBlock + threadIdx.x;
+  if (c >= n) return;
+  const double sc = (D.sig_s[c] * D.phi[c] + D.q[c]) / kFourPi;
+  const double dq = D.base[c] / kFourPi;
+  const double pq = D.phi[c] / kFourPi;
+  D.src[c] = sc;
+  int i, j;
+  cell_ij(c, nx, i, j);
+  for (int qd = 0; qd < 4; ++qd) {
+    const int xl = (qd & 1) ? nx - 1 - i : i, yl = (qd & 2) ? ny - 1 - j : j;
+    const size_t o = (size_t)qd * 3 * n + dg_idx(xl, yl, nx, ny);
+    D.dynq[o] = sc;          // plane 0 of quadrant qd
+    D.dynq[o + n] = dq;      // plane 1
+    if (D.fp32) D.dynq[o + 2 * n] = pq;
+  }
+}
+
+// Final F with the pending correction: F = F_half + delta/(4 pi) sum_k w Omega_k
+__global__ void k_final_flux(int n, const double *Fx, const double *Fy, const double *delta,
+                             double swmu, double sweta, double *ox, double *oy) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const double d = delta[c] / kFourPi;
+  ox[c] = Fx[c] + d * swmu;
+  oy[c] = Fy[c] + d * sweta;
+}
+
+// z = M^{-1} r (one V(1,1) cycle with scaled coarse corrections) for every
+// problem of the set, then the r.z sum into scal (first: RZ = r.z;
+// otherwise beta = r.z / RZ, RZ = r.z).
+void vcycle(const SynthSet &S, bool first, hipStream_t s) {
+  const SynthDesc *ds = S.desc;
+  for (int l = 0; l < S.max_lc; ++l) {
+    hipLaunchKernelGGL(k_mg_red, dim3(S.nb_fine[l]), dim3(kRedBlock), 0, s, ds, S.bt_fine[l], l,
+                       1, 0);
+    hipLaunchKernelGGL(k_mg_black, dim3(S.nb_fine[l]), dim3(kRedBlock), 0, s, ds, S.bt_fine[l],
+                       l, 0, 0.0);
+    hipLaunchKernelGGL(k_mg_restrict, dim3(S.nb_restr[l]), dim3(kRedBlock), 0, s, ds,
+                       S.bt_restr[l], l);
+  }
+  hipLaunchKernelGGL(k_mg_coarse, dim3(S.n), dim3(1024), S.coarse_lds, s, ds, kOmega);
+  for (int l = S.max_lc - 1; l >= 0; --l) {
+    hipLaunchKernelGGL(k_mg_black, dim3(S.nb_fine[l]), dim3(kRedBlock), 0, s, ds, S.bt_fine[l],
+                       l, 1, kOmega);
+    hipLaunchKernelGGL(k_mg_red, dim3(S.nb_fine[l]), dim3(kRedBlock), 0, s, ds, S.bt_fine[l], l,
+                       0, l == 0 ? 1 : 0);
+  }
+  hipLaunchKernelGGL(k_finish, dim3(S.n), dim3(kRedBlock), 0, s, ds, 2, (int)S_RZ, first ? 0 : 2);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ host side
 size_t coarse_lds_bytes_from(const PlanDev &P, size_t lc) {
   size_t n = 0;
   for (size_t l = lc; l < P.mg.size(); ++l)
@@ -589,221 +741,99 @@ int coarse_start(const PlanDev &P) {
 
 size_t coarse_lds_bytes(const PlanDev &P) { return coarse_lds_bytes_from(P, coarse_start(P)); }
 
-// z = M^{-1} r (one V(1,1) cycle with scaled coarse corrections), then the
-// r.z sum into scal (first: RZ = r.z; otherwise beta = r.z / RZ, RZ = r.z).
-void vcycle(const PlanDev &P, const double *r, double *z, bool first, hipStream_t s) {
-  const int lc = coarse_start(P);
-  const int nlev = (int)P.mg.size();
-  // fine levels: pre-smooth and restrict
-  for (int l = 0; l < lc; ++l) {
-    const MGLevel &L = P.mg[l], &C = P.mg[l + 1];
-    const int n = L.nx * L.ny;
-    double *x = l == 0 ? z : L.x;
-    const double *b = l == 0 ? r : L.b;
-    hipLaunchKernelGGL(k_mg_red, dim3(nblk(n)), dim3(kRedBlock), 0, s, L.nx, L.ny, L.diag, L.ax,
-                       L.ay, x, b, 1, (const double *)nullptr, (double *)nullptr, P.state);
-    hipLaunchKernelGGL(k_mg_black, dim3(nblk(n)), dim3(kRedBlock), 0, s, L.nx, L.ny, L.diag, L.ax,
-                       L.ay, x, b, (const double *)nullptr, 1, 1, 1, 0.0, P.state);
-    hipLaunchKernelGGL(k_mg_restrict, dim3(nblk(C.nx * C.ny)), dim3(kRedBlock), 0, s, L.nx, L.ny,
-                       L.diag, L.ax, L.ay, x, b, L.fx, L.fy, C.nx, C.ny, C.b, P.state);
-  }
-  // coarse levels in one workgroup
-  {
-    CoarseLevels CL;
-    CL.nlev = nlev - lc;
-    int off = 0;
-    for (int t = 0; t < CL.nlev; ++t) {
-      const MGLevel &L = P.mg[lc + t];
-      const int n = L.nx * L.ny;
-      CL.nx[t] = L.nx; CL.ny[t] = L.ny; CL.fx[t] = L.fx; CL.fy[t] = L.fy;
-      CL.dg[t] = L.diag; CL.ax[t] = L.ax; CL.ay[t] = L.ay;
-      CL.xoff[t] = off;
-      off += 2 * n;
-      CL.aoff[t] = t == 0 ? 0 : off;
-      if (t > 0) off += 3 * n;
-    }
-    const double *bin = lc == 0 ? r : P.mg[lc].b;
-    double *xout = lc == 0 ? z : P.mg[lc].x;
-    hipLaunchKernelGGL(k_mg_coarse, dim3(1), dim3(1024), coarse_lds_bytes(P), s, CL, bin, xout,
-                       P.coarse_inv, kOmega, lc == 0 ? P.red : (double *)nullptr, P.state);
-  }
-  // fine levels: coarse correction folded into the black half sweep, then red
-  for (int l = lc - 1; l >= 0; --l) {
-    const MGLevel &L = P.mg[l], &C = P.mg[l + 1];
-    const int n = L.nx * L.ny;
-    double *x = l == 0 ? z : L.x;
-    const double *b = l == 0 ? r : L.b;
-    hipLaunchKernelGGL(k_mg_black, dim3(nblk(n)), dim3(kRedBlock), 0, s, L.nx, L.ny, L.diag, L.ax,
-                       L.ay, x, b, (const double *)C.x, L.fx, L.fy, C.nx, kOmega, P.state);
-    hipLaunchKernelGGL(k_mg_red, dim3(nblk(n)), dim3(kRedBlock), 0, s, L.nx, L.ny, L.diag, L.ax,
-                       L.ay, x, b, 0, l == 0 ? r : (const double *)nullptr,
-                       l == 0 ? P.red : (double *)nullptr, P.state);
-  }
-  const int npart = lc == 0 ? 1 : nblk(P.N);
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kRedBlock), 0, s, P.red, npart, P.scal, (int)S_RZ,
-                     first ? 0 : 2, 0.0, P.state);
-}
-
-// ------------------------------------------------------------- update / Err
-// delta = phi' - phi_half (GSIS) or 0 (SI); Err partials; phi = phi_new.
-// FP32-mixed mode also records base = phi^m + delta (see the transport file).
-__global__ void k_update(int n, int method, int fp32, double V, const double *phinew,
-                         const double *phih, double *phi, double *delta, double *base,
-                         double *part, const int32_t *state) {
-  __shared__ double sh[kRedBlock];
-  if (state[1] != 0) return;
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  double num = 0.0, den = 0.0;
-  if (c < n) {
-    const double pn = method ? phinew[c] : phih[c];
-    const double d = pn - phi[c];
-    num = V * d * d;
-    den = V * pn * pn;
-    const double dl = method ? pn - phih[c] : 0.0;
-    delta[c] = dl;
-    if (fp32) base[c] = phi[c] + dl;
-    phi[c] = pn;
-  }
-  double a = block_sum(num, sh);
-  double b = block_sum(den, sh);
-  if (threadIdx.x == 0) { part[2 * blockIdx.x] = a; part[2 * blockIdx.x + 1] = b; }
-}
-
-// Err = sqrt(num/den) -> history, counters, done flag.
-__global__ void k_err_finish(const double *part, int npart, double tol, int max_iter,
-                             double *hist, double *last_err, int32_t *state) {
-  __shared__ double sh[kRedBlock];
-  if (state[1] != 0) return;
-  double a = 0.0, b = 0.0;
-  for (int t = threadIdx.x; t < npart; t += blockDim.x) { a += part[2 * t]; b += part[2 * t + 1]; }
-  double num = block_sum(a, sh);
-  double den = block_sum(b, sh);
-  if (threadIdx.x == 0) {
-    double err = den > 0.0 ? sqrt(num / den) : (num == 0.0 ? 0.0 : INFINITY);
-    const int m = state[0];
-    hist[m] = err;
-    *last_err = err;
-    state[0] = m + 1;
-    state[2] = 1 - state[2];   // I^{m+1} now lives in the other buffer
-    if (!isfinite(err)) state[1] = -1;
-    else if (err < tol) state[1] = 1;
-    else if (m + 1 >= max_iter) state[1] = 2;
-  }
-}
-
-// src = (sigma_s phi + q) / (4 pi); the mirrored per-quadrant copies of
-// (src, base/(4 pi), phi/(4 pi)) read by the fused sweep.
-__global__ void k_source(int nx, int ny, int fp32, const double *sig_s, const double *q,
-                         const double *phi, const double *base, double *src, double *dynq,
-                         const int32_t *state) {
-  if (state[1] != 0) return;
-  const int n = nx * ny;
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n) return;
-  const double sc = (sig_s[c] * phi[c] + q[c]) / kFourPi;
-  const double dq = base[c] / kFourPi;
-  const double pq = phi[c] / kFourPi;
-  src[c] = sc;
-  int i, j;
-  cell_ij(c, nx, i, j);
-  for (int qd = 0; qd < 4; ++qd) {
-    const int xl = (qd & 1) ? nx - 1 - i : i, yl = (qd & 2) ? ny - 1 - j : j;
-    const size_t o = (size_t)qd * 3 * n + dg_idx(xl, yl, nx, ny);
-    dynq[o] = sc;          // plane 0 of quadrant qd
-    dynq[o + n] = dq;      // plane 1
-    if (fp32) dynq[o + 2 * n] = pq;
-  }
-}
-
-// Final F with the pending correction: F = F_half + delta/(4 pi) sum_k w Omega_k
-__global__ void k_final_flux(int n, const double *Fx, const double *Fy, const double *delta,
-                             double swmu, double sweta, double *ox, double *oy) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n) return;
-  const double d = delta[c] / kFourPi;
-  ox[c] = Fx[c] + d * swmu;
-  oy[c] = Fy[c] + d * sweta;
-}
-
-}  // namespace
-
-void launch_source(const PlanDev &P, hipStream_t s) {
-  hipLaunchKernelGGL(k_source, dim3(nblk(P.N)), dim3(kRedBlock), 0, s, P.nx, P.ny,
-                     P.precision == GSIS_FP32_MIXED ? 1 : 0, P.sig_s, P.q, P.phi, P.base, P.src,
-                     P.dynq, P.state);
-}
-
-void launch_hot_rhs(const PlanDev &P, hipStream_t s) {
-  hipLaunchKernelGGL(k_hot, dim3(nblk(P.N)), dim3(kRedBlock), 0, s, P.nx, P.ny, P.phih, P.Fx,
-                     P.Fy, P.sig_t, P.cE, P.cW, P.cN, P.cS, P.hx, P.hy, P.state);
-  hipLaunchKernelGGL(k_rhs, dim3(nblk(P.N)), dim3(kRedBlock), 0, s, P.nx, P.ny, P.dx, P.dy,
-                     P.q, P.hx, P.hy, P.phih, P.bflux, P.kappa, P.rhs, P.state);
-}
-
-void launch_d1_apply(const PlanDev &P, const double *x, double *y, hipStream_t s) {
-  const MGLevel &L = P.mg[0];
-  hipLaunchKernelGGL(k_spmv_dot, dim3(nblk(P.N)), dim3(kRedBlock), 0, s, L.nx, L.ny, L.diag,
-                     L.ax, L.ay, x, y, (double *)nullptr, P.state);
-}
-
-// Preconditioned CG on D1 phi' = rhs, warm-started from phi (the previous
-// synthetic solution). The solution lands in P.mg[0].x. host_scal is pinned
-// host memory (>= 4 doubles) used to read the residual norms.
-void prepare_synth(PlanDev &P) {
-  const size_t bytes = coarse_lds_bytes(P);
-  if (bytes > 64 * 1024)
+// The attribute is per kernel, not per plan: it is raised to the largest
+// amount any plan may ask for, so that a later plan with a smaller coarse
+// cycle never lowers it under an earlier one.
+void prepare_synth(size_t coarse_lds) {
+  if (coarse_lds > 64 * 1024)
     (void)hipFuncSetAttribute((const void *)k_mg_coarse, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)bytes);
+                              (int)kCoarseLdsBudget);
 }
 
-// Preconditioned CG on D1 phi' = rhs, warm-started from phi (the previous
-// synthetic solution); the solution lands in P.mg[0].x. The stop test runs
-// on the device (state[3]); the host looks at it every second iteration
-// after the fourth (host_flag: pinned int32[2]) and otherwise keeps
-// enqueueing, since a converged solve turns the remaining kernels into
-// no-ops.
-void launch_synth_solve(PlanDev &P, hipStream_t s, int32_t *host_flag) {
-  const MGLevel &L = P.mg[0];
-  const int n = P.N, nb = nblk(n);
-  double *x = L.x;
-  hipLaunchKernelGGL(k_cg_begin, dim3(nb), dim3(kRedBlock), 0, s, n, P.phi, x, P.state);
-  hipLaunchKernelGGL(k_cg_residual, dim3(nb), dim3(kRedBlock), 0, s, L.nx, L.ny, L.diag, L.ax,
-                     L.ay, x, P.rhs, P.cg_r, P.red, P.red + nb, P.state);
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kRedBlock), 0, s, P.red + nb, nb, P.scal, (int)S_BB,
-                     0, 0.0, P.state);
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kRedBlock), 0, s, P.red, nb, P.scal, (int)S_RR, 4,
-                     P.synth_rtol, P.state);
-  vcycle(P, P.cg_r, P.cg_z, true, s);
-  double *pbuf[2] = {P.cg_p, P.cg_p2};
-  for (int it = 0; it < P.synth_max_iter; ++it) {
-    double *pold = pbuf[it & 1], *pnew = pbuf[(it + 1) & 1];
-    hipLaunchKernelGGL(k_cg_pAp, dim3(nb), dim3(kRedBlock), 0, s, L.nx, L.ny, L.diag, L.ax, L.ay,
-                       P.cg_z, pold, pnew, P.cg_Ap, P.scal, it == 0 ? 1 : 0, P.red, P.state);
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(kRedBlock), 0, s, P.red, nb, P.scal, (int)S_PAP, 1,
-                       0.0, P.state);
-    hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(kRedBlock), 0, s, n, x, P.cg_r, pnew, P.cg_Ap,
-                       P.scal, P.red, P.state);
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(kRedBlock), 0, s, P.red, nb, P.scal, (int)S_RR, 3,
-                       0.0, P.state);
-    if (it + 1 == P.synth_max_iter) break;
-    if (it >= 3 && ((it - 3) & 1) == 0) {
-      hipMemcpyAsync(host_flag, P.state + 1, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, s);
-      hipStreamSynchronize(s);
+SynthDesc make_synth_desc(const PlanDev &P) {
+  SynthDesc D;
+  memset(&D, 0, sizeof D);
+  D.nx = P.nx; D.ny = P.ny; D.N = P.N;
+  D.dx = P.dx; D.dy = P.dy; D.V = P.V;
+  D.method = P.method; D.fp32 = P.precision == GSIS_FP32_MIXED ? 1 : 0; D.max_iter = P.max_iter;
+  D.tol = P.tol; D.rtol = P.synth_rtol;
+  D.sig_t = P.sig_t; D.sig_s = P.sig_s; D.q = P.q;
+  D.cE = P.cE; D.cW = P.cW; D.cN = P.cN; D.cS = P.cS; D.kappa = P.kappa;
+  D.phih = P.phih; D.Fx = P.Fx; D.Fy = P.Fy; D.bflux = P.bflux;
+  D.hx = P.hx; D.hy = P.hy; D.rhs = P.rhs; D.phi = P.phi; D.delta = P.delta; D.base = P.base;
+  D.src = P.src; D.dynq = P.dynq;
+  D.cg_r = P.cg_r; D.cg_z = P.cg_z; D.cg_p0 = P.cg_p; D.cg_p1 = P.cg_p2; D.cg_Ap = P.cg_Ap;
+  D.red = P.red; D.scal = P.scal; D.err_parts = P.err_parts; D.err_hist = P.err_hist;
+  D.last_err = P.last_err; D.state = P.state;
+  D.nlev = (int)P.mg.size();
+  for (int l = 0; l < D.nlev && l < kMaxLevels; ++l) {
+    const MGLevel &L = P.mg[l];
+    D.lev[l] = LevelDev{L.nx, L.ny, L.fx, L.fy, L.diag, L.ax, L.ay, L.x, L.b};
+  }
+  const int lc = coarse_start(P);
+  D.lc = lc;
+  CoarseLevels &CL = D.cl;
+  CL.nlev = D.nlev - lc;
+  int off = 0;
+  for (int t = 0; t < CL.nlev; ++t) {
+    const MGLevel &L = P.mg[lc + t];
+    const int n = L.nx * L.ny;
+    CL.nx[t] = L.nx; CL.ny[t] = L.ny; CL.fx[t] = L.fx; CL.fy[t] = L.fy;
+    CL.dg[t] = L.diag; CL.ax[t] = L.ax; CL.ay[t] = L.ay;
+    CL.xoff[t] = off;
+    off += 2 * n;
+    CL.aoff[t] = t == 0 ? 0 : off;
+    if (t > 0) off += 3 * n;
+  }
+  D.coarse_inv = P.coarse_inv;
+  return D;
+}
+
+void launch_source(const SynthSet &S, hipStream_t s) {
+  hipLaunchKernelGGL(k_source, dim3(S.nb_cell), dim3(kRedBlock), 0, s, S.desc, S.bt_cell);
+}
+
+void launch_hot_rhs(const SynthSet &S, hipStream_t s) {
+  hipLaunchKernelGGL(k_hot, dim3(S.nb_cell), dim3(kRedBlock), 0, s, S.desc, S.bt_cell);
+  hipLaunchKernelGGL(k_rhs, dim3(S.nb_cell), dim3(kRedBlock), 0, s, S.desc, S.bt_cell);
+}
+
+// Preconditioned CG on D1 phi' = rhs for every problem of the set, each
+// warm-started from its phi (the previous synthetic solution); solutions
+// land in level 0's x. The stop test runs on the device (state[3] per
+// problem); for a single problem the host looks at it every second
+// iteration after the fourth (host_flag: pinned int32[3]) and otherwise
+// keeps enqueueing, since a converged solve turns the remaining kernels into
+// no-ops. With host_flag = NULL (graph capture, batches) the host never
+// waits and enqueues exactly S.synth_max_iter iterations.
+void launch_synth_solve(const SynthSet &S, hipStream_t s, int32_t *host_flag) {
+  const SynthDesc *ds = S.desc;
+  const dim3 gc(S.nb_cell), bk(kRedBlock);
+  hipLaunchKernelGGL(k_cg_begin, gc, bk, 0, s, ds, S.bt_cell);
+  hipLaunchKernelGGL(k_finish, dim3(S.n), bk, 0, s, ds, 1, (int)S_BB, 0);
+  hipLaunchKernelGGL(k_finish, dim3(S.n), bk, 0, s, ds, 0, (int)S_RR, 4);
+  vcycle(S, true, s);
+  for (int it = 0; it < S.synth_max_iter; ++it) {
+    const int par = it & 1;
+    hipLaunchKernelGGL(k_cg_pAp, gc, bk, 0, s, ds, S.bt_cell, it == 0 ? 1 : 0, par);
+    hipLaunchKernelGGL(k_finish, dim3(S.n), bk, 0, s, ds, 0, (int)S_PAP, 1);
+    hipLaunchKernelGGL(k_cg_update, gc, bk, 0, s, ds, S.bt_cell, par);
+    hipLaunchKernelGGL(k_finish, dim3(S.n), bk, 0, s, ds, 0, (int)S_RR, 3);
+    if (it + 1 == S.synth_max_iter) break;
+    if (host_flag && S.state0 && it >= 3 && ((it - 3) & 1) == 0) {
+      (void)hipMemcpyAsync(host_flag, S.state0 + 1, 3 * sizeof(int32_t), hipMemcpyDeviceToHost,
+                           s);
+      (void)hipStreamSynchronize(s);
       if (host_flag[0] != 0 || host_flag[2] != 0) return;
     }
-    vcycle(P, P.cg_r, P.cg_z, false, s);
+    vcycle(S, false, s);
   }
 }
 
-void launch_update(const PlanDev &P, hipStream_t s) {
-  const int nb = nblk(P.N);
-  const double *phinew = P.mg[0].x;
-  hipLaunchKernelGGL(k_update, dim3(nb), dim3(kRedBlock), 0, s, P.N, P.method,
-                     P.precision == GSIS_FP32_MIXED ? 1 : 0, P.V, phinew, P.phih, P.phi,
-                     P.delta, P.base, P.err_parts, P.state);
-  hipLaunchKernelGGL(k_err_finish, dim3(1), dim3(kRedBlock), 0, s, P.err_parts, nb, P.tol,
-                     P.max_iter, P.err_hist, P.last_err, P.state);
-  launch_source(P, s);
+void launch_update(const SynthSet &S, hipStream_t s) {
+  hipLaunchKernelGGL(k_update, dim3(S.nb_cell), dim3(kRedBlock), 0, s, S.desc, S.bt_cell);
+  hipLaunchKernelGGL(k_err_finish, dim3(S.n), dim3(kRedBlock), 0, s, S.desc);
+  launch_source(S, s);
 }
 
 void launch_apply_delta_final(const PlanDev &P, hipStream_t s, double swmu, double sweta,
@@ -811,5 +841,7 @@ void launch_apply_delta_final(const PlanDev &P, hipStream_t s, double swmu, doub
   hipLaunchKernelGGL(k_final_flux, dim3(nblk(P.N)), dim3(kRedBlock), 0, s, P.N, P.Fx, P.Fy,
                      P.delta, swmu, sweta, Fx_out, Fy_out);
 }
+
+double *synth_iteration_counter(const PlanDev &P) { return P.scal + S_NIT; }
 
 }  // namespace gsis

@@ -24,6 +24,8 @@
 // sweep and moment operation runs in FP64.
 #include "gsis_internal.h"
 
+#include <cstring>
+
 namespace gsis {
 namespace {
 
@@ -45,6 +47,7 @@ struct TArgs {
   const double *cE, *cW, *cN, *cS;
   const double *bnd;
   double *phih, *Fx, *Fy, *bflux;
+  double *mom_part;
   const double *cellq, *dynq;
   double *rowbuf;
   const int32_t *state;
@@ -60,6 +63,7 @@ TArgs make_args(const PlanDev &P) {
   a.sig_t = P.sig_t; a.src = P.src; a.delta = P.delta;
   a.cE = P.cE; a.cW = P.cW; a.cN = P.cN; a.cS = P.cS;
   a.bnd = P.bnd; a.phih = P.phih; a.Fx = P.Fx; a.Fy = P.Fy; a.bflux = P.bflux;
+  a.mom_part = P.mom_part;
   a.cellq = P.cellq; a.dynq = P.dynq; a.rowbuf = P.rowbuf;
   a.fp32 = P.precision == GSIS_FP32_MIXED ? 1 : 0;
   a.phi = P.phi;
@@ -295,10 +299,8 @@ __device__ inline int xcd_ordinate(int b, int K) {
 // GENERAL = false assumes ny <= blockDim.x (one pass) and nx <= kSouthCap, so
 // that no load outside the prefetch ring sits on the step path.
 template <int PF, int MAXW, bool GENERAL, typename T>
-__global__ void __launch_bounds__(MAXW * 64) k_sweep_fused(TArgs a) {
+__device__ __forceinline__ void sweep_ordinate(const TArgs &a, const int kk) {
   constexpr bool kF32 = sizeof(T) == 4;
-  if (a.state[1] != 0) return;
-  const int kk = xcd_ordinate(blockIdx.x, a.K);
   const int q = quadrant_of(a, kk);
   const int nx = a.nx, ny = a.ny, N = a.N;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -477,6 +479,35 @@ __global__ void __launch_bounds__(MAXW * 64) k_sweep_fused(TArgs a) {
   }
 }
 
+template <int PF, int MAXW, bool GENERAL, typename T>
+__global__ void __launch_bounds__(MAXW * 64) k_sweep_fused(TArgs a) {
+  if (a.state[1] != 0) return;
+  sweep_ordinate<PF, MAXW, GENERAL, T>(a, xcd_ordinate(blockIdx.x, a.K));
+}
+
+// Batched sweep: one persistent launch for the ordinates of many problems.
+// Each workgroup takes work items (problem, ordinate) from a shared counter,
+// in the order of the item table (longest first), and runs the same sweep
+// with that problem's arguments; problems that have finished are skipped.
+// Every workgroup leaves once the counter passes the table.
+template <int PF, int MAXW, typename T>
+__global__ void __launch_bounds__(MAXW * 64)
+    k_sweep_batch(const TArgs *targs, const int2 *items, int n_items, int *counter) {
+  __shared__ int s_item;
+  while (true) {
+    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+    __syncthreads();
+    const int it = s_item;
+    __syncthreads();
+    if (it >= n_items) break;
+    const int2 pk = items[it];
+    const TArgs &a = targs[pk.x];
+    if (a.state[1] == 0) sweep_ordinate<PF, MAXW, true, T>(a, pk.y);
+  }
+}
+
+__global__ void k_zero_int(int *p) { *p = 0; }
+
 // phi, F of I^{m+1/2} in two passes: per quadrant, one thread per stored
 // cell sums the quadrant's ordinates (contiguous reads) into partials at the
 // caller's cell index; then the four partials are added in a fixed order.
@@ -491,10 +522,9 @@ __device__ inline void dg_cell(long long t, int nx, int ny, int &x, int &y) {
 }
 
 template <typename T>
-__global__ void k_moments_q(TArgs a, double *part) {
+__device__ __forceinline__ void moments_q(const TArgs &a, double *part, const long long t,
+                                          const int q) {
   if (a.state[1] != 0) return;
-  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  const int q = blockIdx.y;
   if (t >= a.N) return;
   int x, y;
   dg_cell(t, a.nx, a.ny, x, y);
@@ -512,9 +542,21 @@ __global__ void k_moments_q(TArgs a, double *part) {
   part[(size_t)(3 * q + 2) * a.N + c] = sy;
 }
 
-__global__ void k_moments_combine(TArgs a, const double *part) {
+template <typename T>
+__global__ void k_moments_q(TArgs a, double *part) {
+  moments_q<T>(a, part, blockIdx.x * (long long)blockDim.x + threadIdx.x, blockIdx.y);
+}
+
+// Batched launches: bt maps block -> (problem, block of that problem).
+template <typename T>
+__global__ void k_moments_q_b(const TArgs *tas, const int2 *bt) {
+  const int2 v = bt[blockIdx.x];
+  const TArgs &a = tas[v.x];
+  moments_q<T>(a, a.mom_part, v.y * (long long)blockDim.x + threadIdx.x, blockIdx.y);
+}
+
+__device__ __forceinline__ void moments_combine(const TArgs &a, const double *part, const int c) {
   if (a.state[1] != 0) return;
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= a.N) return;
   double s0 = 0, sx = 0, sy = 0;
   for (int q = 0; q < 4; ++q) {
@@ -529,11 +571,20 @@ __global__ void k_moments_combine(TArgs a, const double *part) {
   a.phih[c] = s0; a.Fx[c] = sx; a.Fy[c] = sy;
 }
 
+__global__ void k_moments_combine(TArgs a, const double *part) {
+  moments_combine(a, part, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+__global__ void k_moments_combine_b(const TArgs *tas, const int2 *bt) {
+  const int2 v = bt[blockIdx.x];
+  const TArgs &a = tas[v.x];
+  moments_combine(a, a.mom_part, v.y * blockDim.x + threadIdx.x);
+}
+
 // F_T . n_out on each boundary face: one workgroup per face, threads over
 // ordinates, fixed-order tree sum.
-__global__ void k_boundary_flux(TArgs a) {
+__device__ __forceinline__ void boundary_flux(const TArgs &a, const int f) {
   if (a.state[1] != 0) return;
-  const int f = blockIdx.x;
   int side, pos;
   if (f < a.ny) { side = 0; pos = f; }                       // W
   else if (f < 2 * a.ny) { side = 1; pos = f - a.ny; }        // E
@@ -578,6 +629,13 @@ __global__ void k_boundary_flux(TArgs a) {
   if (threadIdx.x == 0) a.bflux[f] = red[0];
 }
 
+__global__ void k_boundary_flux(TArgs a) { boundary_flux(a, blockIdx.x); }
+
+__global__ void k_boundary_flux_b(const TArgs *tas, const int2 *bt) {
+  const int2 v = bt[blockIdx.x];
+  boundary_flux(tas[v.x], v.y);
+}
+
 }  // namespace
 
 template <typename T>
@@ -609,6 +667,66 @@ void launch_transport(const PlanDev &P, hipStream_t s) {
   else launch_fused<double>(a, P, rows, s);
 }
 
+// ---- batched sweep
+size_t targs_bytes() { return sizeof(TArgs); }
+void fill_targs(const PlanDev &P, void *dst) {
+  const TArgs a = make_args(P);
+  memcpy(dst, &a, sizeof a);
+}
+
+namespace {
+template <int PF, int MAXW, typename T>
+const void *batch_kernel() {
+  return reinterpret_cast<const void *>(&k_sweep_batch<PF, MAXW, T>);
+}
+const void *batch_kernel_for(int cfg, bool fp32) {
+  switch (cfg) {
+    case 0: return fp32 ? batch_kernel<4, 1, float>() : batch_kernel<4, 1, double>();
+    case 1: return fp32 ? batch_kernel<6, 1, float>() : batch_kernel<6, 1, double>();
+    case 2: return fp32 ? batch_kernel<4, 2, float>() : batch_kernel<4, 2, double>();
+    case 3: return fp32 ? batch_kernel<6, 2, float>() : batch_kernel<6, 2, double>();
+    case 4: return fp32 ? batch_kernel<4, 4, float>() : batch_kernel<4, 4, double>();
+    case 5: return fp32 ? batch_kernel<2, 8, float>() : batch_kernel<2, 8, double>();
+    default: return nullptr;
+  }
+}
+}  // namespace
+
+const BatchSweepConfig kBatchSweepConfigs[kNumBatchSweepConfigs] = {
+    {64, 4}, {64, 6}, {128, 4}, {128, 6}, {256, 4}, {512, 2}};
+
+int sweep_batch_blocks_per_cu(int cfg, bool fp32) {
+  int nb = 0;
+  const void *k = batch_kernel_for(cfg, fp32);
+  if (!k || hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, kBatchSweepConfigs[cfg].rows, 0) !=
+                hipSuccess)
+    return 0;
+  return nb;
+}
+
+void launch_sweep_batch(const void *targs, const int2 *items, int n_items, int *counter, int cfg,
+                        bool fp32, int grid, hipStream_t s) {
+  const TArgs *ta = reinterpret_cast<const TArgs *>(targs);
+  const int rows = kBatchSweepConfigs[cfg].rows;
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, counter);
+#define GSIS_BATCH_LAUNCH(PF, W)                                                              \
+  if (fp32)                                                                                   \
+    hipLaunchKernelGGL((k_sweep_batch<PF, W, float>), dim3(grid), dim3(rows), 0, s, ta, items, \
+                       n_items, counter);                                                     \
+  else                                                                                        \
+    hipLaunchKernelGGL((k_sweep_batch<PF, W, double>), dim3(grid), dim3(rows), 0, s, ta,      \
+                       items, n_items, counter);
+  switch (cfg) {
+    case 0: GSIS_BATCH_LAUNCH(4, 1) break;
+    case 1: GSIS_BATCH_LAUNCH(6, 1) break;
+    case 2: GSIS_BATCH_LAUNCH(4, 2) break;
+    case 3: GSIS_BATCH_LAUNCH(6, 2) break;
+    case 4: GSIS_BATCH_LAUNCH(4, 4) break;
+    default: GSIS_BATCH_LAUNCH(2, 8) break;
+  }
+#undef GSIS_BATCH_LAUNCH
+}
+
 void launch_moments(const PlanDev &P, hipStream_t s) {
   TArgs a = make_args(P);
   if (a.fp32)
@@ -624,6 +742,22 @@ void launch_moments(const PlanDev &P, hipStream_t s) {
 void launch_boundary_flux(const PlanDev &P, hipStream_t s) {
   TArgs a = make_args(P);
   hipLaunchKernelGGL(k_boundary_flux, dim3(P.nbf), dim3(256), 0, s, a);
+}
+
+void launch_moments_batch(const void *targs, const int2 *bt_cell, int nb_cell, bool fp32,
+                          hipStream_t s) {
+  const TArgs *ta = reinterpret_cast<const TArgs *>(targs);
+  if (fp32)
+    hipLaunchKernelGGL(k_moments_q_b<float>, dim3(nb_cell, 4), dim3(256), 0, s, ta, bt_cell);
+  else
+    hipLaunchKernelGGL(k_moments_q_b<double>, dim3(nb_cell, 4), dim3(256), 0, s, ta, bt_cell);
+  hipLaunchKernelGGL(k_moments_combine_b, dim3(nb_cell), dim3(256), 0, s, ta, bt_cell);
+}
+
+void launch_boundary_flux_batch(const void *targs, const int2 *bt_face, int nb_face,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(k_boundary_flux_b, dim3(nb_face), dim3(256), 0, s,
+                     reinterpret_cast<const TArgs *>(targs), bt_face);
 }
 
 }  // namespace gsis

@@ -50,7 +50,15 @@ class gsis_options(ctypes.Structure):
                 ("synth_rtol", ctypes.c_double), ("synth_max_iter", ctypes.c_int32),
                 ("I0", ctypes.c_void_p), ("stream", ctypes.c_void_p),
                 ("device_ptrs", ctypes.c_int32), ("profile", ctypes.c_int32),
-                ("cfl_p", ctypes.c_double), ("beta", ctypes.c_double)]
+                ("cfl_p", ctypes.c_double), ("beta", ctypes.c_double),
+                ("graph", ctypes.c_int32)]
+
+
+class gsis_batch_tuning(ctypes.Structure):
+    _fields_ = [("rows", ctypes.c_int32), ("prefetch", ctypes.c_int32),
+                ("grid", ctypes.c_int32), ("cg_iters", ctypes.c_int32),
+                ("n_configs", ctypes.c_int32), ("config_rows", ctypes.c_int32 * 8),
+                ("config_prefetch", ctypes.c_int32 * 8), ("config_ms", ctypes.c_double * 8)]
 
 
 class gsis_result(ctypes.Structure):
@@ -62,6 +70,8 @@ class gsis_result(ctypes.Structure):
 EXPORTS = ("gsis_ctx_create", "gsis_ctx_destroy", "gsis_last_error", "gsis_options_default",
            "gsis_solve", "gsis_plan_create", "gsis_plan_destroy", "gsis_plan_iterate",
            "gsis_plan_status", "gsis_plan_read", "gsis_plan_reset", "gsis_plan_phase_times",
+           "gsis_batch_create", "gsis_batch_destroy", "gsis_batch_iterate", "gsis_batch_status",
+           "gsis_batch_read", "gsis_batch_reset", "gsis_batch_get_tuning", "gsis_solve_batch",
            "gsis_version")
 
 
@@ -95,11 +105,22 @@ def load():
     lib.gsis_plan_read.argtypes = [vp, ctypes.POINTER(gsis_result)]
     lib.gsis_plan_reset.argtypes = [vp]
     lib.gsis_plan_phase_times.argtypes = [vp, _dp, ip]
+    lib.gsis_batch_create.argtypes = [vp, i32, ctypes.POINTER(gsis_problem),
+                                      ctypes.POINTER(gsis_options), ctypes.POINTER(vp)]
+    lib.gsis_batch_destroy.argtypes = [vp]
+    lib.gsis_batch_destroy.restype = None
+    lib.gsis_batch_iterate.argtypes = [vp, i32]
+    lib.gsis_batch_status.argtypes = [vp, ip, ip, _dp, ip]
+    lib.gsis_batch_read.argtypes = [vp, i32, ctypes.POINTER(gsis_result)]
+    lib.gsis_batch_reset.argtypes = [vp]
+    lib.gsis_batch_get_tuning.argtypes = [vp, ctypes.POINTER(gsis_batch_tuning)]
+    lib.gsis_solve_batch.argtypes = [vp, i32, ctypes.POINTER(gsis_problem),
+                                     ctypes.POINTER(gsis_options), ctypes.POINTER(gsis_result)]
     lib.gsis_version.argtypes = []
     lib.gsis_version.restype = ctypes.c_char_p
     for name in EXPORTS:
-        if name not in ("gsis_ctx_destroy", "gsis_plan_destroy", "gsis_last_error",
-                        "gsis_version"):
+        if name not in ("gsis_ctx_destroy", "gsis_plan_destroy", "gsis_batch_destroy",
+                        "gsis_last_error", "gsis_version"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -182,13 +203,13 @@ class _Args:
 
 def make_options(method=GSIS_GSIS, precision=GSIS_FP64, order=2, limiter=1, alsm=1,
                  hot_face=GSIS_HOT_CENTRAL, tol=1e-6, max_iter=1000, synth_rtol=1e-4,
-                 synth_max_iter=50, profile=0, cfl_p=0.0, beta=0.0):
+                 synth_max_iter=50, profile=0, cfl_p=0.0, beta=0.0, graph=1):
     o = gsis_options()
     load().gsis_options_default(ctypes.byref(o))
     o.method, o.precision, o.order, o.limiter = int(method), int(precision), int(order), int(limiter)
     o.alsm, o.hot_face, o.tol, o.max_iter = int(alsm), int(hot_face), float(tol), int(max_iter)
     o.synth_rtol, o.synth_max_iter, o.profile = float(synth_rtol), int(synth_max_iter), int(profile)
-    o.cfl_p, o.beta = float(cfl_p), float(beta)
+    o.cfl_p, o.beta, o.graph = float(cfl_p), float(beta), int(graph)
     return o
 
 
@@ -299,3 +320,110 @@ def solve(prob, I0=None, device=0, **opts):
     if _default_ctx is None:
         _default_ctx = Context(device)
     return gsis_solve(_default_ctx, prob, I0, **opts)
+
+
+def _result_buffers(a, max_iter):
+    N = a.nx * a.ny
+    if a.device:
+        import torch
+        dev = a.keep[0].device
+        phi = torch.empty(N, dtype=torch.float64, device=dev)
+        fx, fy = torch.empty_like(phi), torch.empty_like(phi)
+        hist = torch.zeros(max_iter, dtype=torch.float64, device=dev)
+        p = lambda t: t.data_ptr()
+    else:
+        phi, fx, fy, hist = np.empty(N), np.empty(N), np.empty(N), np.zeros(max_iter)
+        p = lambda x: x.ctypes.data
+    return (phi, fx, fy, hist), gsis_result(p(phi), p(fx), p(fy), p(hist), 0, 0.0)
+
+
+class Batch:
+    """gsis_batch_create / iterate / status / read / reset / get_tuning /
+    destroy for a list of problem dicts (all host arrays or all device
+    tensors) sharing one set of options."""
+
+    def __init__(self, ctx, probs, **opts):
+        lib = load()
+        self.ctx = ctx
+        self.args = [_Args(p) for p in probs]
+        dev = {a.device for a in self.args}
+        if len(dev) != 1:
+            raise ValueError("mix of host and device problems")
+        self.device = dev.pop()
+        self.n = len(probs)
+        o = make_options(**opts)
+        o.device_ptrs = 1 if self.device else 0
+        o.stream = None
+        self.opts = o
+        arr = (gsis_problem * self.n)(*[a.s for a in self.args])
+        h = ctypes.c_void_p()
+        _check(lib.gsis_batch_create(ctx.handle, self.n, arr, ctypes.byref(o), ctypes.byref(h)),
+               ctx)
+        self.handle = h
+
+    def iterate(self, n=1):
+        _check(load().gsis_batch_iterate(self.handle, int(n)), self.ctx)
+
+    def status(self):
+        n = self.n
+        it, cv, er = (ctypes.c_int32 * n)(), (ctypes.c_int32 * n)(), (ctypes.c_double * n)()
+        fin = ctypes.c_int32()
+        _check(load().gsis_batch_status(self.handle, it, cv, er, ctypes.byref(fin)), self.ctx)
+        return list(it), list(cv), list(er), fin.value
+
+    def read(self, i):
+        bufs, r = _result_buffers(self.args[i], self.opts.max_iter)
+        _check(load().gsis_batch_read(self.handle, int(i), ctypes.byref(r)), self.ctx)
+        phi, fx, fy, hist = bufs
+        return dict(phi=phi, Fx=fx, Fy=fy, err_hist=hist[:r.n_iter], n_iter=r.n_iter,
+                    final_err=r.final_err)
+
+    def reset(self):
+        _check(load().gsis_batch_reset(self.handle), self.ctx)
+
+    def tuning(self):
+        t = gsis_batch_tuning()
+        _check(load().gsis_batch_get_tuning(self.handle, ctypes.byref(t)), self.ctx)
+        cfgs = [dict(rows=t.config_rows[c], prefetch=t.config_prefetch[c], ms=t.config_ms[c])
+                for c in range(t.n_configs)]
+        return dict(rows=t.rows, prefetch=t.prefetch, grid=t.grid, cg_iters=t.cg_iters,
+                    configs=cfgs)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().gsis_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def gsis_solve_batch(ctx, probs, **opts):
+    """One-shot batched solve (gsis_solve_batch); returns (results, status)."""
+    lib = load()
+    args = [_Args(p) for p in probs]
+    dev = {a.device for a in args}
+    if len(dev) != 1:
+        raise ValueError("mix of host and device problems")
+    device = dev.pop()
+    o = make_options(**opts)
+    o.device_ptrs = 1 if device else 0
+    o.stream = None
+    n = len(probs)
+    bufs, res = [], (gsis_result * n)()
+    for i, a in enumerate(args):
+        b, r = _result_buffers(a, o.max_iter)
+        bufs.append(b)
+        res[i] = r
+    arr = (gsis_problem * n)(*[a.s for a in args])
+    st = lib.gsis_solve_batch(ctx.handle, n, arr, ctypes.byref(o), res)
+    _check(st, ctx, allow=(GSIS_OK, GSIS_NOT_CONVERGED, GSIS_DIVERGED))
+    out = []
+    for i in range(n):
+        phi, fx, fy, hist = bufs[i]
+        out.append(dict(phi=phi, Fx=fx, Fy=fy, err_hist=hist[:res[i].n_iter],
+                        n_iter=res[i].n_iter, final_err=res[i].final_err))
+    return out, st

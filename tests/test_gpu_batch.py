@@ -1,0 +1,134 @@
+"""Batched form: many problems of uneven size in one plan (persistent sweep
+launch over (problem, ordinate) items, one block-diagonal synthetic solve,
+hipGraph-captured iterations), through the C-ABI, against the oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2507_03975_amd import gsis, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return gsis.Context(0)
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _rel(a, b):
+    a = a.cpu().numpy() if hasattr(a, "cpu") else np.asarray(a)
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def _mixed():
+    """Uneven shapes and quadratures: one cell, a strip needing two sweep
+    passes at every launch configuration, ragged sizes, K = 12 / 32 / 64."""
+    return [inputs.random_problem(1, 1, seed=1),
+            inputs.random_problem(37, 21, seed=2, sigma_range=(0.05, 50.0)),
+            inputs.random_problem(5, 600, seed=3, sigma_range=(0.1, 5.0)),
+            dict(inputs.random_problem(64, 48, seed=4, sigma_range=(0.05, 50.0)),
+                 **{k: v for k, v in zip(("mu", "eta", "w"), inputs.quad_product(2, 16))},
+                 bnd_in=None),
+            dict(inputs.random_problem(90, 130, seed=5, sigma_range=(0.5, 500.0)),
+                 **{k: v for k, v in zip(("mu", "eta", "w"), inputs.quad_product(4, 16))},
+                 bnd_in=None)]
+
+
+@pytest.mark.parametrize("graph", [0, 1])
+@pytest.mark.parametrize("method", [0, 1])
+def test_batch_iterates_match_oracle(ctx, graph, method):
+    probs = _mixed()
+    _say("batch iterates graph=%d method=%d" % (graph, method))
+    b = gsis.Batch(ctx, probs, method=method, tol=0.0, max_iter=3, synth_rtol=1e-15,
+                   synth_max_iter=300, graph=graph)
+    b.iterate(3)
+    it, conv, err, fin = b.status()
+    assert it == [3] * len(probs) and fin == len(probs)
+    tun = b.tuning()
+    _say("  tuning %s" % tun)
+    assert tun["rows"] in (64, 128, 256, 512)
+    for i, p in enumerate(probs):
+        g = b.read(i)
+        o = oracle.solve(p, method=method, tol=0.0, max_iter=3)
+        tol = 1e-12 if method == 0 else 1e-10
+        assert _rel(g["phi"], o["phi"]) < tol, i
+        assert _rel(g["Fx"], o["Fx"]) < 10 * tol and _rel(g["Fy"], o["Fy"]) < 10 * tol, i
+        np.testing.assert_allclose(g["err_hist"], o["err_hist"], rtol=1e-8)
+    b.reset()
+    assert b.status()[0] == [0] * len(probs)
+    b.close()
+
+
+def test_batch_fp32_iterates(ctx):
+    probs = _mixed()[1:]
+    b = gsis.Batch(ctx, probs, precision=gsis.GSIS_FP32_MIXED, tol=0.0, max_iter=3,
+                   synth_rtol=1e-15, synth_max_iter=300)
+    b.iterate(3)
+    for i, p in enumerate(probs):
+        g = b.read(i)
+        o = oracle.solve(p, tol=0.0, max_iter=3)
+        assert _rel(g["phi"], o["phi"]) < 1e-6 and _rel(g["Fx"], o["Fx"]) < 1e-6, i
+    b.close()
+
+
+def test_batch_converges_each_problem(ctx):
+    """Each problem stops on its own Err < tol; the converged fields agree
+    with the oracle's fixed points."""
+    probs = [inputs.small_s4_32(), inputs.random_problem(24, 40, seed=9, sigma_range=(0.5, 5.0)),
+             inputs.random_problem(33, 17, seed=3, sigma_range=(0.5, 20.0))]
+    out, st = gsis.gsis_solve_batch(ctx, probs, tol=1e-11, max_iter=400, limiter=0,
+                                    synth_rtol=1e-12, synth_max_iter=100)
+    assert st == gsis.GSIS_OK
+    for p, g in zip(probs, out):
+        o = oracle.solve(p, tol=1e-11, max_iter=400, limiter=0)
+        assert o["status"] == 0
+        assert g["final_err"] < 1e-11 and abs(g["n_iter"] - o["n_iter"]) <= 2
+        assert _rel(g["phi"], o["phi"]) < 1e-9
+
+
+def test_batch_matches_single_plans(ctx):
+    """A problem gets the same iterates in a batch as alone (same kernels,
+    its own CG scalars); with the CG converging inside the fixed count the
+    fields agree to rounding."""
+    probs = _mixed()[1:]
+    b = gsis.Batch(ctx, probs, tol=0.0, max_iter=4, synth_rtol=1e-13, synth_max_iter=300)
+    b.iterate(4)
+    for i, p in enumerate(probs):
+        g = b.read(i)
+        s = gsis.gsis_solve(ctx, p, tol=0.0, max_iter=4, synth_rtol=1e-13, synth_max_iter=300)
+        assert _rel(g["phi"], s["phi"]) < 1e-12, i
+    b.close()
+
+
+def test_full_batch_sampled(ctx):
+    """The 64-problem batch (grids 64..512, 32..128 ordinates, 8 x 8 random
+    blocks) at full size: after two iterations the problems small enough for
+    the oracle match it element by element; every problem's history is
+    finite."""
+    probs = inputs.batch_problems()
+    _say("full batch: %d problems" % len(probs))
+    b = gsis.Batch(ctx, probs, tol=0.0, max_iter=2, beta=20.0, synth_rtol=1e-14,
+                   synth_max_iter=400, graph=0)
+    b.iterate(2)
+    it, conv, err, fin = b.status()
+    assert it == [2] * len(probs) and all(np.isfinite(err))
+    _say("  tuning %s" % b.tuning())
+    checked = 0
+    for i, p in enumerate(probs):
+        if p["nx"] * p["ny"] * len(p["mu"]) > 64 * 64 * 128:
+            continue
+        g = b.read(i)
+        o = oracle.solve(p, tol=0.0, max_iter=2, beta=20.0)
+        assert _rel(g["phi"], o["phi"]) < 1e-9, i
+        checked += 1
+    assert checked >= 3
+    b.close()
