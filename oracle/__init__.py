@@ -78,6 +78,9 @@ def _load():
         lib.ora_synthetic_solve.argtypes = [P, _dp, _dp]
         lib.ora_synthetic_solve.restype = ctypes.c_int
         lib.ora_synthetic_apply.argtypes = [P, _dp, _dp]
+        lib.ora_adjoint.argtypes = [P, O, _dp, _dp, _dp, _dp, ctypes.c_double, ctypes.c_int,
+                                    _dp, _dp, _dp, _dp, ip, _dp]
+        lib.ora_adjoint.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -217,4 +220,28 @@ def solve(prob, I0=None, return_I=False, **opts):
                final_err=ferr.value, status=st)
     if return_I:
         out["I"] = If
+    return out
+
+
+def adjoint(prob, I_star, g_phi=None, g_Fx=None, g_Fy=None, tol=1e-12, max_iter=2000,
+            return_lambda=False, **opts):
+    """Adjoint of the fixed point I_star [N, K] (limiter off): lambda and
+    dJ/dsigma_a, dJ/dsigma_s, dJ/dq for J = <g_phi, phi*> + <g_F, F*>."""
+    m = _Marshal(prob)
+    N, K = m.nx * m.ny, m.K
+    o = _opts(**dict(opts, limiter=opts.get("limiter", 0)))
+    I_star = np.ascontiguousarray(I_star, dtype=np.float64)
+    f = lambda a: None if a is None else np.ascontiguousarray(a, dtype=np.float64).ravel()
+    gp, gx, gy = f(g_phi), f(g_Fx), f(g_Fy)
+    ga, gs, gq = np.zeros(N), np.zeros(N), np.zeros(N)
+    lam = np.zeros((N, K)) if return_lambda else None
+    hist = np.zeros(max(max_iter, 1))
+    n = ctypes.c_int(0)
+    st = _load().ora_adjoint(ctypes.byref(m.s), ctypes.byref(o), _ptr(I_star), _ptr(gp),
+                             _ptr(gx), _ptr(gy), float(tol), int(max_iter), _ptr(ga), _ptr(gs),
+                             _ptr(gq), _ptr(lam), ctypes.byref(n), _ptr(hist))
+    out = dict(g_sigma_a=ga, g_sigma_s=gs, g_q=gq, n_iter=n.value, status=st,
+               err_hist=hist[:n.value])
+    if return_lambda:
+        out["lambda"] = lam
     return out

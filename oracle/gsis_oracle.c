@@ -722,3 +722,409 @@ int ora_solve(const ora_problem *p, const ora_options *o, const double *I0,
   free(Ia); free(Ib); free(phi_old); free(phi_new);
   return status;
 }
+
+/* ======================================================================== */
+/* Adjoint of the GSIS / SI fixed point (limiter off, no pseudo time).        */
+/*                                                                            */
+/* With the limiter off one outer iteration is an affine map                  */
+/* I' = T(I; p) = G(p) I + c(p) of the intensity, p = (sigma_a, sigma_s, q)    */
+/* per cell. For an output J = <g_phi, phi*> + <g_F, F*> of the fixed point   */
+/* I* (phi* = sum_k w_k I*_k, F* = sum_k w_k Omega_k I*_k) the adjoint         */
+/* lambda solves lambda = G^T lambda + M^T g, and                             */
+/* dJ/dp = lambda^T dT(I*; p)/dp. Both are reverse passes through the steps   */
+/* of one iteration (residual, increment solve, moments, boundary fluxes,     */
+/* HoT, right-hand side, synthetic solve, correction), taken here one step at */
+/* a time in reverse order, per cell, face and ordinate. The gradient of the  */
+/* adaptive least squares on a Cartesian grid splits into x and y parts (the  */
+/* neighbours lie on the axes, so the 2x2 normal matrix is diagonal):         */
+/*   G_x = sum_f e_f (U_f - U_c) / sum_f e_f^2 over the x neighbours, with     */
+/*   e_f = +-(h/2)(1 + sigma_nb/sigma_c) (alsm) or +-h, the signed distance   */
+/*   to the shifted point (Eqs. shifted_j, LSF_mdf).                           */
+/* ======================================================================== */
+
+/* Signed shifted distance of neighbour nb across face f of cell c, and its
+ * derivatives with respect to sigma_t of c and of nb. */
+static double shifted_e(const ora_problem *p, int alsm, int c, int nb, int f,
+                        double *de_dc, double *de_dnb) {
+  const double h = (f < 2) ? p->dx : p->dy;
+  const double sgn = (f == 0 || f == 2) ? 1.0 : -1.0;
+  if (!alsm) { *de_dc = 0.0; *de_dnb = 0.0; return sgn * h; }
+  const double sc = sig_t(p, c), sn = sig_t(p, nb);
+  *de_dnb = sgn * 0.5 * h / sc;
+  *de_dc = -sgn * 0.5 * h * sn / (sc * sc);
+  return sgn * 0.5 * h * (1.0 + sn / sc);
+}
+
+/* Reverse of the gradient of cell (i,j): given the cotangents gbx, gby of
+ * (G_x, G_y), add dL/dU into Ub and dL/dsigma_t into stb. */
+static void gradient_cell_adj(const ora_problem *p, int alsm, const double *U, int i, int j,
+                              double gbx, double gby, double *Ub, double *stb) {
+  const int c = j * p->nx + i;
+  for (int axis = 0; axis < 2; ++axis) {
+    const double gb = axis == 0 ? gbx : gby;
+    if (gb == 0.0) continue;
+    const int f0 = axis == 0 ? 0 : 2;
+    double e[2] = {0, 0}, dec[2] = {0, 0}, den[2] = {0, 0}, du[2] = {0, 0};
+    int nbs[2] = {-1, -1};
+    double B = 0.0, M = 0.0;
+    for (int t = 0; t < 2; ++t) {
+      const int f = f0 + t;
+      const int nb = neighbour(p, i, j, f);
+      nbs[t] = nb;
+      if (nb < 0) continue;
+      e[t] = shifted_e(p, alsm, c, nb, f, &dec[t], &den[t]);
+      du[t] = U ? U[nb] - U[c] : 0.0;   /* only needed for stb */
+      B += e[t] * du[t];
+      M += e[t] * e[t];
+    }
+    if (!(M > 0)) continue;
+    const double G = B / M;
+    for (int t = 0; t < 2; ++t) {
+      if (nbs[t] < 0) continue;
+      /* dG/dU_nb = e/M, dG/dU_c = -e/M */
+      Ub[nbs[t]] += gb * e[t] / M;
+      Ub[c] -= gb * e[t] / M;
+      if (stb) {
+        /* dG/de = (du - 2 e G) / M */
+        const double ge = gb * (du[t] - 2.0 * e[t] * G) / M;
+        stb[c] += ge * dec[t];
+        stb[nbs[t]] += ge * den[t];
+      }
+    }
+  }
+}
+
+/* Reverse of rec_face (limiter off): cotangent vb of the value of cell c on
+ * face f. Needs the field U for the coefficient part. */
+static void rec_face_adj(const ora_problem *p, const ora_options *o, const double *U, int c,
+                         int f, double vb, double *Ub, double *stb) {
+  Ub[c] += vb;
+  if (o->order < 2) return;
+  gradient_cell_adj(p, o->alsm, U, c % p->nx, c / p->nx, vb * face_ox(p, f), vb * face_oy(p, f),
+                    Ub, stb);
+}
+
+/* Everything one iteration computes from I*, kept for the reverse pass. */
+typedef struct {
+  double *Ih;        /* I^{m+1/2} [N][K] */
+  double *dI;        /* increment [N][K] */
+  double *phim;      /* phi of I* */
+  double *ph, *Fxh, *Fyh;   /* moments of I^{m+1/2} */
+  double *bflux;     /* boundary transport fluxes */
+  double *gpx, *gpy; /* ALSM gradient of phi_half */
+  double *phin;      /* synthetic solution phi' */
+} fwd_tape;
+
+static void tape_free(fwd_tape *t) {
+  free(t->Ih); free(t->dI); free(t->phim); free(t->ph); free(t->bflux); free(t->gpx);
+  free(t->phin);
+}
+
+/* Right-hand side of the synthetic equation (central HoT faces). */
+static void synth_rhs(const ora_problem *p, const double *ph, const double *hx,
+                      const double *hy, const double *bflux, double *b) {
+  const int nx = p->nx, ny = p->ny;
+  const double V = p->dx * p->dy;
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      const int c = j * nx + i;
+      double s = V * p->q[c];
+      for (int f = 0; f < 4; ++f) {
+        int nb = neighbour(p, i, j, f);
+        double A = face_area(p, f);
+        if (nb >= 0)
+          s -= A * 0.5 * ((hx[c] + hx[nb]) * NX_[f] + (hy[c] + hy[nb]) * NY_[f]);
+        else
+          s -= A * (bflux[bface(p, i, j, f)] - kappa_face(p, c, f) * ph[c]);
+      }
+      b[c] = s;
+    }
+}
+
+static int tape_build(const ora_problem *p, const ora_options *o, const synth_factor *S,
+                      const double *I, fwd_tape *t) {
+  const int nx = p->nx, ny = p->ny, N = nx * ny, K = p->K;
+  const size_t NK = (size_t)N * K;
+  memset(t, 0, sizeof *t);
+  double *r = malloc(sizeof(double) * NK);
+  t->Ih = malloc(sizeof(double) * NK);
+  t->dI = malloc(sizeof(double) * NK);
+  t->phim = malloc(sizeof(double) * N);
+  t->ph = malloc(sizeof(double) * N * 3);
+  t->Fxh = t->ph + N; t->Fyh = t->ph + 2 * N;
+  t->bflux = malloc(sizeof(double) * 2 * (nx + ny));
+  t->gpx = malloc(sizeof(double) * N * 2); t->gpy = t->gpx + N;
+  t->phin = malloc(sizeof(double) * N);
+  ora_residual(p, o, I, r);
+  ora_sweep(p, o, r, t->dI);
+  free(r);
+  for (size_t q = 0; q < NK; ++q) t->Ih[q] = I[q] + t->dI[q];
+  moments(p, I, t->phim, NULL, NULL);
+  moments(p, t->Ih, t->ph, t->Fxh, t->Fyh);
+  if (o->method == 0) return 0;
+  transport_face_fluxes(p, o, t->Ih, t->bflux, NULL, NULL);
+  ora_gradient(p, o->alsm, t->ph, t->gpx, t->gpy);
+  double *hx = malloc(sizeof(double) * N * 2), *hy = hx + N, *b = malloc(sizeof(double) * N);
+  for (int c = 0; c < N; ++c) {
+    hx[c] = t->Fxh[c] + t->gpx[c] / (3.0 * sig_t(p, c));
+    hy[c] = t->Fyh[c] + t->gpy[c] / (3.0 * sig_t(p, c));
+  }
+  synth_rhs(p, t->ph, hx, hy, t->bflux, b);
+  int e = synth_solve_with(p, S, b, t->phin);
+  free(hx); free(b);
+  return e;
+}
+
+/* Parameter cotangents accumulated by the gradient pass. */
+typedef struct { double *st, *ss, *sa, *q; } par_bar;
+
+/* out = G^T lam (one reverse pass). With tape and pb non-NULL the same pass
+ * also accumulates lam^T dT/dp into pb; s_out (optional) receives the
+ * unweighted ordinate sum s = sum_k lam_k / (4 pi). */
+static int adjoint_pass(const ora_problem *p, const ora_options *o, const synth_factor *S,
+                        const double *I, const double *lam, double *out, const fwd_tape *tp,
+                        par_bar *pb, double *s_out) {
+  const int nx = p->nx, ny = p->ny, N = nx * ny, K = p->K;
+  const size_t NK = (size_t)N * K;
+  const double V = p->dx * p->dy;
+  const int nbf = 2 * (nx + ny);
+  double *Ihb = malloc(sizeof(double) * NK);      /* cotangent of I^{m+1/2} */
+  double *s = calloc(N, sizeof(double));
+  double *phb = calloc(N, sizeof(double));        /* of phi_half */
+  double *Fxb = calloc(N, sizeof(double)), *Fyb = calloc(N, sizeof(double));
+  double *bfb = calloc(nbf, sizeof(double));      /* of the boundary fluxes */
+  double *bb = calloc(N, sizeof(double));         /* of b (= D1^-1 s) */
+  memcpy(Ihb, lam, sizeof(double) * NK);
+  for (int c = 0; c < N; ++c) {
+    double t = 0;
+    for (int k = 0; k < K; ++k) t += lam[(size_t)c * K + k];
+    s[c] = t / FOUR_PI;
+  }
+  if (s_out) memcpy(s_out, s, sizeof(double) * N);
+  int e = 0;
+  if (o->method == 1) {
+    /* correction I' = I_half + (phi' - phi_half)/(4 pi):
+     * cotangent of phi' is s, of phi_half -s */
+    for (int c = 0; c < N; ++c) phb[c] = -s[c];
+    /* synthetic solve phi' = D1^-1 b: bb = D1^-1 s (D1 symmetric) */
+    e = synth_solve_with(p, S, s, bb);
+    if (pb && tp) {
+      /* D1 = V sigma_a + sum_int A Gamma (e_c - e_nb)(e_c - e_nb)^T
+       *      + sum_bnd A kappa e_c e_c^T; its cotangent is -bb phi'^T */
+      for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+          const int c = j * nx + i;
+          pb->sa[c] -= V * bb[c] * tp->phin[c];
+          pb->q[c] += V * bb[c];                              /* b = V q + ... */
+          for (int f = 0; f < 4; ++f) {
+            const int nb = neighbour(p, i, j, f);
+            const double A = face_area(p, f);
+            const double h = (f < 2) ? p->dx : p->dy;
+            if (nb >= 0) {
+              if (nb < c) continue;                           /* each face once */
+              const double gbar = -A * (bb[c] - bb[nb]) * (tp->phin[c] - tp->phin[nb]);
+              /* Gamma = 2 / (3 (sigma_c + sigma_nb) h) on the uniform grid */
+              const double sm = sig_t(p, c) + sig_t(p, nb);
+              const double dG = -2.0 / (3.0 * sm * sm * h);
+              pb->st[c] += gbar * dG;
+              pb->st[nb] += gbar * dG;
+            } else {
+              /* kappa = (o.n)/(3 sigma |o|^2) + 1/4: in b (+A kappa phi_half)
+               * and in D1 (+A kappa on the diagonal) */
+              const double kb = A * bb[c] * (tp->ph[c] - tp->phin[c]);
+              const double ox = face_ox(p, f), oy = face_oy(p, f);
+              const double on = ox * NX_[f] + oy * NY_[f];
+              const double st = sig_t(p, c);
+              pb->st[c] += kb * (-on / (3.0 * st * st * (ox * ox + oy * oy)));
+            }
+          }
+        }
+    }
+    /* b = V q - sum_int A 1/2 (HoT_c + HoT_nb).n - sum_bnd A (bflux - kappa phi_half) */
+    double *hxb = calloc(N, sizeof(double)), *hyb = calloc(N, sizeof(double));
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        const int c = j * nx + i;
+        for (int f = 0; f < 4; ++f) {
+          const int nb = neighbour(p, i, j, f);
+          const double A = face_area(p, f);
+          if (nb >= 0) {
+            hxb[c] -= bb[c] * A * 0.5 * NX_[f];
+            hxb[nb] -= bb[c] * A * 0.5 * NX_[f];
+            hyb[c] -= bb[c] * A * 0.5 * NY_[f];
+            hyb[nb] -= bb[c] * A * 0.5 * NY_[f];
+          } else {
+            bfb[bface(p, i, j, f)] -= bb[c] * A;
+            phb[c] += bb[c] * A * kappa_face(p, c, f);
+          }
+        }
+      }
+    /* HoT = F_half + grad(phi_half) / (3 sigma_t) */
+    for (int c = 0; c < N; ++c) { Fxb[c] = hxb[c]; Fyb[c] = hyb[c]; }
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        const int c = j * nx + i;
+        const double st = sig_t(p, c);
+        gradient_cell_adj(p, o->alsm, tp ? tp->ph : NULL, i, j, hxb[c] / (3.0 * st),
+                          hyb[c] / (3.0 * st), phb, pb ? pb->st : NULL);
+        if (pb && tp)
+          pb->st[c] += -(hxb[c] * tp->gpx[c] + hyb[c] * tp->gpy[c]) / (3.0 * st * st);
+      }
+    free(hxb); free(hyb);
+  }
+  /* moments of I_half */
+  for (int c = 0; c < N; ++c)
+    for (int k = 0; k < K; ++k)
+      Ihb[(size_t)c * K + k] += p->w[k] * (phb[c] + p->mu[k] * Fxb[c] + p->eta[k] * Fyb[c]);
+  /* boundary fluxes bflux_f = sum_k w_k (Omega_k.n_f) I_f,k(I_half):
+   * outgoing faces carry the reconstructed value of the boundary cell */
+  if (o->method == 1) {
+    double *U = malloc(sizeof(double) * N), *Ub = malloc(sizeof(double) * N);
+    for (int k = 0; k < K; ++k) {
+      for (int c = 0; c < N; ++c) { U[c] = tp ? tp->Ih[(size_t)c * K + k] : 0.0; Ub[c] = 0.0; }
+      for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i)
+          for (int f = 0; f < 4; ++f) {
+            if (neighbour(p, i, j, f) >= 0) continue;
+            const double on = p->mu[k] * NX_[f] + p->eta[k] * NY_[f];
+            if (on < 0) continue;   /* incoming: prescribed */
+            const double vb = bfb[bface(p, i, j, f)] * p->w[k] * on;
+            rec_face_adj(p, o, U, j * nx + i, f, vb, Ub, pb ? pb->st : NULL);
+          }
+      for (int c = 0; c < N; ++c) Ihb[(size_t)c * K + k] += Ub[c];
+    }
+    free(U); free(Ub);
+  }
+  /* I_half = I + dI: both get Ihb. dI = H^-1 r: rb = H^-T Ihb, visiting
+   * cells downstream first (the reverse of the increment solve's order). */
+  double *rb = malloc(sizeof(double) * NK);
+  for (int k = 0; k < K; ++k) {
+    const int i0 = p->mu[k] >= 0 ? nx - 1 : 0, di = p->mu[k] >= 0 ? -1 : 1;
+    const int j0 = p->eta[k] >= 0 ? ny - 1 : 0, dj = p->eta[k] >= 0 ? -1 : 1;
+    for (int jj = 0, j = j0; jj < ny; ++jj, j += dj)
+      for (int ii = 0, i = i0; ii < nx; ++ii, i += di) {
+        const int c = j * nx + i;
+        double d = sig_t(p, c) + ora_pseudo_shift(p, o, c), rhs = Ihb[(size_t)c * K + k];
+        for (int f = 0; f < 4; ++f) {
+          double on = p->mu[k] * NX_[f] + p->eta[k] * NY_[f];
+          if (on > 0) {
+            d += on * area_over_vol(p, f);
+            int nb = neighbour(p, i, j, f);
+            if (nb >= 0) rhs += on * area_over_vol(p, f) * rb[(size_t)nb * K + k];
+          }
+        }
+        rb[(size_t)c * K + k] = rhs / d;
+      }
+  }
+  /* diagonal of H (sigma_t): cotangent -rb dI */
+  if (pb && tp)
+    for (int c = 0; c < N; ++c)
+      for (int k = 0; k < K; ++k)
+        pb->st[c] -= rb[(size_t)c * K + k] * tp->dI[(size_t)c * K + k];
+  /* r = (sigma_s phi + q)/(4 pi) - sigma_t I - (1/V) sum_f (Omega.n) A I_f(I) */
+  memcpy(out, Ihb, sizeof(double) * NK);
+  double *Sb = calloc(N, sizeof(double));
+  for (int c = 0; c < N; ++c) {
+    double t = 0;
+    for (int k = 0; k < K; ++k) t += rb[(size_t)c * K + k];
+    Sb[c] = t;
+  }
+  {
+    double *U = malloc(sizeof(double) * N), *Ub = malloc(sizeof(double) * N);
+    for (int k = 0; k < K; ++k) {
+      for (int c = 0; c < N; ++c) { U[c] = I ? I[(size_t)c * K + k] : 0.0; Ub[c] = 0.0; }
+      for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+          const int c = j * nx + i;
+          const double r = rb[(size_t)c * K + k];
+          Ub[c] -= sig_t(p, c) * r;
+          if (pb && I) pb->st[c] -= r * U[c];
+          for (int f = 0; f < 4; ++f) {
+            const double on = p->mu[k] * NX_[f] + p->eta[k] * NY_[f];
+            const double vb = -on * area_over_vol(p, f) * r;   /* cotangent of I_f */
+            const int nb = neighbour(p, i, j, f);
+            if (on >= 0) rec_face_adj(p, o, U, c, f, vb, Ub, pb ? pb->st : NULL);
+            else if (nb >= 0) rec_face_adj(p, o, U, nb, OPP_[f], vb, Ub, pb ? pb->st : NULL);
+          }
+        }
+      for (int c = 0; c < N; ++c)
+        out[(size_t)c * K + k] += Ub[c] + p->w[k] * p->sig_s[c] * Sb[c] / FOUR_PI;
+    }
+    free(U); free(Ub);
+  }
+  if (pb && tp)
+    for (int c = 0; c < N; ++c) {
+      pb->ss[c] += tp->phim[c] * Sb[c] / FOUR_PI;
+      pb->q[c] += Sb[c] / FOUR_PI;
+    }
+  free(Ihb); free(s); free(phb); free(Fxb); free(Fyb); free(bfb); free(bb); free(rb); free(Sb);
+  return e;
+}
+
+int ora_adjoint(const ora_problem *p, const ora_options *o, const double *I_star,
+                const double *g_phi, const double *g_Fx, const double *g_Fy, double tol,
+                int max_iter, double *g_sa, double *g_ss, double *g_q, double *lam_out,
+                int *n_iter, double *err_hist) {
+  if (o->limiter || o->hot_face != 0 || o->cfl_p != 0 || o->beta != 0) return -4;
+  const int N = p->nx * p->ny, K = p->K;
+  const size_t NK = (size_t)N * K;
+  const double V = p->dx * p->dy;
+  synth_factor S = {0, 0, NULL, 0};
+  int e = 0;
+  if (o->method == 1 && (e = synth_factor_build(p, &S))) return e;
+  fwd_tape tp;
+  if ((e = tape_build(p, o, &S, I_star, &tp))) { tape_free(&tp); synth_factor_free(&S); return e; }
+  /* source M^T g: w_k (g_phi + mu_k g_Fx + eta_k g_Fy) */
+  double *src = malloc(sizeof(double) * NK), *la = malloc(sizeof(double) * NK),
+         *lb = malloc(sizeof(double) * NK);
+  for (int c = 0; c < N; ++c)
+    for (int k = 0; k < K; ++k)
+      src[(size_t)c * K + k] = p->w[k] * ((g_phi ? g_phi[c] : 0.0) +
+                                          p->mu[k] * (g_Fx ? g_Fx[c] : 0.0) +
+                                          p->eta[k] * (g_Fy ? g_Fy[c] : 0.0));
+  memcpy(la, src, sizeof(double) * NK);
+  double *s_old = malloc(sizeof(double) * N), *s_new = malloc(sizeof(double) * N);
+  int m = 0, status = 1;
+  for (int c = 0; c < N; ++c) {
+    double t = 0;
+    for (int k = 0; k < K; ++k) t += la[(size_t)c * K + k];
+    s_old[c] = t / FOUR_PI;
+  }
+  /* lambda^{n+1} = G^T lambda^n + M^T g until the ordinate sum settles */
+  for (m = 0; m < max_iter; ++m) {
+    if ((e = adjoint_pass(p, o, &S, NULL, la, lb, NULL, NULL, NULL))) { status = e; break; }
+    for (size_t t = 0; t < NK; ++t) lb[t] += src[t];
+    for (int c = 0; c < N; ++c) {
+      double t = 0;
+      for (int k = 0; k < K; ++k) t += lb[(size_t)c * K + k];
+      s_new[c] = t / FOUR_PI;
+    }
+    const double err = err_w(s_new, s_old, N, V);
+    if (err_hist) err_hist[m] = err;
+    double *t = la; la = lb; lb = t;
+    memcpy(s_old, s_new, sizeof(double) * N);
+    if (!isfinite(err)) { status = -2; ++m; break; }
+    if (err < tol) { status = 0; ++m; break; }
+  }
+  if (n_iter) *n_iter = m;
+  /* gradient: lambda^T dT(I*)/dp in one more reverse pass with the tape */
+  par_bar pb;
+  pb.st = calloc(N, sizeof(double)); pb.ss = calloc(N, sizeof(double));
+  pb.sa = calloc(N, sizeof(double)); pb.q = calloc(N, sizeof(double));
+  if (status >= 0) {
+    e = adjoint_pass(p, o, &S, I_star, la, lb, &tp, &pb, NULL);
+    if (e) status = e;
+  }
+  for (int c = 0; c < N; ++c) {
+    /* sigma_t = sigma_a + sigma_s */
+    if (g_sa) g_sa[c] = pb.sa[c] + pb.st[c];
+    if (g_ss) g_ss[c] = pb.ss[c] + pb.st[c];
+    if (g_q) g_q[c] = pb.q[c];
+  }
+  if (lam_out) memcpy(lam_out, la, sizeof(double) * NK);
+  free(pb.st); free(pb.ss); free(pb.sa); free(pb.q);
+  free(src); free(la); free(lb); free(s_old); free(s_new);
+  tape_free(&tp);
+  synth_factor_free(&S);
+  return status;
+}

@@ -92,6 +92,18 @@ int ora_synthetic_solve(const ora_problem *p, const double *b, double *x);
 /* Apply D1 (for tests). */
 void ora_synthetic_apply(const ora_problem *p, const double *x, double *y);
 
+/* Adjoint of the fixed point I* of the iteration (limiter off, central HoT
+ * faces, no pseudo time; method SI or GSIS): lambda = G^T lambda + M^T g for
+ * the output J = <g_phi, phi*> + <g_Fx, Fx*> + <g_Fy, Fy*> (any cotangent may
+ * be NULL), iterated until Err of sum_k lambda_k/(4 pi) < tol; then
+ * dJ/dsigma_a, dJ/dsigma_s, dJ/dq per cell (any output may be NULL) and,
+ * optionally, lambda [N][K]. Returns 0, 1 (not converged), <0 on error
+ * (-4: unsupported options). */
+int ora_adjoint(const ora_problem *p, const ora_options *o, const double *I_star,
+                const double *g_phi, const double *g_Fx, const double *g_Fy, double tol,
+                int max_iter, double *g_sa, double *g_ss, double *g_q, double *lam_out,
+                int *n_iter, double *err_hist);
+
 #ifdef __cplusplus
 }
 #endif

@@ -463,3 +463,62 @@ def test_pseudo_time_stabilises_opacity_jumps():
     assert plain["status"] != 0 and plain["err_hist"][-1] > 1.0
     damped = oracle.solve(p, method=1, tol=1e-6, max_iter=200, limiter=0, beta=10.0)
     assert damped["status"] == 0 and damped["n_iter"] < 120
+
+
+# ----------------------------------------------------- adjoint (P12 of the scope)
+def _adjoint_case(n, seed, kw):
+    p = inputs.random_problem(n, n + 1, seed=seed, sigma_range=(0.5, 5.0))
+    N = p["nx"] * p["ny"]
+    rng = np.random.Generator(np.random.PCG64(seed + 50))
+    g = rng.uniform(0, 1, N), rng.uniform(-1, 1, N), rng.uniform(-1, 1, N)
+    return p, g
+
+
+def _J(p, g, kw):
+    r = oracle.solve(p, tol=1e-14, max_iter=5000, **kw)
+    assert r["status"] == 0
+    return g[0] @ r["phi"] + g[1] @ r["Fx"] + g[2] @ r["Fy"]
+
+
+@pytest.mark.parametrize("kw", [dict(method=1, order=2, alsm=1), dict(method=0, order=2, alsm=1),
+                                dict(method=1, order=2, alsm=0), dict(method=1, order=1, alsm=1)])
+def test_adjoint_matches_central_differences(kw):
+    """dJ/dsigma_a, dJ/dsigma_s, dJ/dq of J = <g, (phi, Fx, Fy)> at the fixed
+    point against central differences of the converged forward solve
+    (h = 1e-5 relative, forward Err < 1e-14): every cell, 1e-6 relative."""
+    kw = dict(kw, limiter=0)
+    p, g = _adjoint_case(4, 11, kw)
+    r = oracle.solve(p, tol=1e-14, max_iter=5000, return_I=True, **kw)
+    a = oracle.adjoint(p, r["I"], *g, tol=1e-13, **kw)
+    assert a["status"] == 0
+    for name, key in (("sigma_a", "g_sigma_a"), ("sigma_s", "g_sigma_s"), ("q", "g_q")):
+        fd = np.zeros(len(p[name]))
+        for c in range(len(fd)):
+            h = 1e-5 * p[name][c]
+            v = p[name].copy(); v[c] += h
+            jp = _J(dict(p, **{name: v}), g, kw)
+            v = p[name].copy(); v[c] -= h
+            jm = _J(dict(p, **{name: v}), g, kw)
+            fd[c] = (jp - jm) / (2 * h)
+        assert np.abs(fd - a[key]).max() < 1e-6 * np.abs(fd).max(), name
+
+
+@pytest.mark.parametrize("method", [0, 1])
+def test_adjoint_duality(method):
+    """For the affine map I' = G I + c the fixed point is (I - G)^-1 c, so
+    J = <M^T g, I*> = <lambda, c> with c the first iterate from I = 0."""
+    kw = dict(method=method, limiter=0)
+    p, g = _adjoint_case(5, 4, kw)
+    p["bnd_in"] = np.full((2 * (p["nx"] + p["ny"]), len(p["mu"])), 0.03)
+    r = oracle.solve(p, tol=1e-14, max_iter=5000, return_I=True, **kw)
+    J = g[0] @ r["phi"] + g[1] @ r["Fx"] + g[2] @ r["Fy"]
+    a = oracle.adjoint(p, r["I"], *g, tol=1e-14, return_lambda=True, **kw)
+    c, _ = oracle.iterate(p, np.zeros_like(r["I"]), **kw)
+    assert abs(np.sum(a["lambda"] * c) - J) < 1e-11 * abs(J)
+
+
+def test_adjoint_rejects_nonsmooth_options():
+    p, g = _adjoint_case(3, 2, {})
+    I = np.zeros((p["nx"] * p["ny"], len(p["mu"])))
+    assert oracle.adjoint(p, I, *g, limiter=1)["status"] == -4
+    assert oracle.adjoint(p, I, *g, beta=5.0)["status"] == -4
