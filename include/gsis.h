@@ -226,6 +226,42 @@ gsis_status gsis_batch_get_tuning(gsis_batch *b, gsis_batch_tuning *t);
 gsis_status gsis_solve_batch(gsis_ctx *ctx, int32_t n, const gsis_problem *p,
                              const gsis_options *o, gsis_result *r /* [n] */);
 
+/* ------------------------------------------------------------------ adjoint
+ * Gradients of J = <g_phi, phi*> + <g_Fx, Fx*> + <g_Fy, Fy*> at the fixed
+ * point of a plan with respect to sigma_a, sigma_s and q of every cell. With
+ * the limiter off an outer iteration is affine in the intensity,
+ * I' = G I + c(sigma_a, sigma_s, q); the adjoint lambda = G^T lambda + M^T g
+ * (M: the moments of I) is iterated (each step one reverse pass of an outer
+ * iteration: unweighted ordinate sum, synthetic solve with D1, transposed
+ * right-hand side and HoT, transposed wall reconstruction, the increment
+ * solve swept downstream-first, transposed residual) until Err of
+ * sum_k lambda_k / (4 pi) < tol, and dJ/dp = lambda^T dT(I*)/dp is collected
+ * cell by cell. Any explicit dependence of an objective on the parameters
+ * is the caller's. Needs limiter = 0, precision FP64, central HoT faces and
+ * no pseudo-time shift (GSIS_E_UNSUPPORTED otherwise), and a plan that has
+ * converged (GSIS_E_INVALID_ARG otherwise); tighter forward tolerances give
+ * more accurate gradients (about the forward Err, relative). */
+typedef struct {
+  int32_t n_iter;         /* adjoint iterations */
+  double final_err;       /* Err of the ordinate sum at the last check */
+  int32_t forward_iter;   /* outer iterations of the forward solve */
+} gsis_adjoint_info;
+
+/* Cotangents g_* and gradients g_sigma_a, g_sigma_s, g_q are [nx*ny] in the
+ * caller's cell order, host or device memory as the plan's device_ptrs says;
+ * a NULL cotangent is zero, a NULL gradient is not written. The plan keeps
+ * three [nx*ny][K] adjoint arrays from the first call on. */
+gsis_status gsis_plan_adjoint(gsis_plan *plan, const double *g_phi, const double *g_Fx,
+                              const double *g_Fy, double tol, int32_t max_iter,
+                              double *g_sigma_a, double *g_sigma_s, double *g_q,
+                              gsis_adjoint_info *info /* may be NULL */);
+/* One-shot: plan, forward solve to options.tol, optional forward results
+ * (fwd may be NULL), adjoint to options.tol within options.max_iter. */
+gsis_status gsis_adjoint(gsis_ctx *ctx, const gsis_problem *p, const gsis_options *o,
+                         const double *g_phi, const double *g_Fx, const double *g_Fy,
+                         double *g_sigma_a, double *g_sigma_s, double *g_q, gsis_result *fwd,
+                         gsis_adjoint_info *info);
+
 /* Library build string (compiler, target, options). */
 const char *gsis_version(void);
 

@@ -21,7 +21,8 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I" + os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-function"]
 
-SOURCES = ["capi.cpp", "batch.cpp", "kernels_transport.hip", "kernels_synth.hip"]
+SOURCES = ["capi.cpp", "batch.cpp", "adjoint.cpp", "kernels_transport.hip",
+           "kernels_synth.hip", "kernels_adjoint.hip"]
 
 
 def _compile(src):

@@ -351,6 +351,7 @@ extern "C" gsis_status gsis_plan_create(gsis_ctx *ctx, const gsis_problem *p,
   pl->stream = (hipStream_t)o->stream;
   pl->device_ptrs = o->device_ptrs;
   pl->profile = o->profile;
+  pl->pseudo = (o->cfl_p > 0 || o->beta > 0) ? 1 : 0;
   PlanDev &P = pl->P;
   const int nx = p->nx, ny = p->ny, N = nx * ny, K = p->K;
   P.nx = nx; P.ny = ny; P.N = N; P.K = K; P.nbf = 2 * (nx + ny);
@@ -585,6 +586,7 @@ extern "C" void gsis_plan_destroy(gsis_plan *pl) {
   else (void)hipDeviceSynchronize();
   for (void *v : pl->allocs) (void)hipFree(v);
   for (hipEvent_t e : pl->events) (void)hipEventDestroy(e);
+  adjoint_release(pl);
   if (pl->host_scal) (void)hipHostFree(pl->host_scal);
   delete pl;
 }

@@ -200,4 +200,29 @@ void launch_apply_delta_final(const PlanDev &P, hipStream_t s, double swmu, doub
 // CG iterations of P's last synthetic solve (one device double)
 double *synth_iteration_counter(const PlanDev &P);
 
+// ---- adjoint (kernels_adjoint.hip)
+struct AdjointBuffers {
+  double *lam = nullptr, *ihb = nullptr, *rb = nullptr;          // [K][N]
+  double *s = nullptr, *s_old = nullptr, *bb = nullptr, *hxb = nullptr, *hyb = nullptr;
+  double *phb = nullptr, *Sb = nullptr, *bfb = nullptr;
+  double *part = nullptr;      // [4][5][N]
+  double *dbar = nullptr;      // [4][N]
+  double *stp = nullptr, *errp = nullptr, *hist = nullptr;
+  double *gphi = nullptr, *gFx = nullptr, *gFy = nullptr;        // device cotangents
+  double *g_sa = nullptr, *g_ss = nullptr, *g_q = nullptr;       // device gradients
+  int32_t *state = nullptr;    // synthetic-solve state of the adjoint solves
+  SynthSet S;                  // D1 bb = s with the plan's hierarchy
+  std::vector<char> args;      // kernel-argument image
+  int max_hist = 0;
+};
+size_t adjoint_args_bytes();
+void adj_fill_args(const PlanDev &P, const AdjointBuffers &B, const double *gphi,
+                   const double *gFx, const double *gFy, void *dst);
+// host_flag: pinned int32[3] for the synthetic solve's stop checks, or NULL
+void adj_launch_pass(const PlanDev &P, const AdjointBuffers &B, const void *args,
+                     const double *ihalf, const SynthSet &S, double *hist, int m,
+                     int32_t *host_flag, hipStream_t s);
+void adj_launch_gradient(const PlanDev &P, const void *args, const double *ihalf, double *g_sa,
+                         double *g_ss, double *g_q, hipStream_t s);
+
 }  // namespace gsis

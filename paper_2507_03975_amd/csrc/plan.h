@@ -35,6 +35,8 @@ struct gsis_plan {
   // profiling: per iteration GSIS_NUM_PHASES + 1 events bracketing the phases
   std::vector<hipEvent_t> events;
   int prof_iters = 0;
+  int pseudo = 0;                 // a pseudo-time shift is on
+  AdjointBuffers *adj = nullptr;  // adjoint state (first gsis_plan_adjoint)
 };
 
 extern thread_local std::string g_create_err;
@@ -89,3 +91,5 @@ struct HostLevel {
 gsis_status setup_synth(gsis_plan *pl, PlanDev &P, std::vector<HostLevel> &hl);
 // P.S for the plan alone (descriptor upload, block counts).
 gsis_status make_single_set(gsis_plan *pl);
+// Frees the adjoint's host-side state (device memory goes with the plan).
+void adjoint_release(gsis_plan *pl);

@@ -61,6 +61,11 @@ class gsis_batch_tuning(ctypes.Structure):
                 ("config_prefetch", ctypes.c_int32 * 8), ("config_ms", ctypes.c_double * 8)]
 
 
+class gsis_adjoint_info(ctypes.Structure):
+    _fields_ = [("n_iter", ctypes.c_int32), ("final_err", ctypes.c_double),
+                ("forward_iter", ctypes.c_int32)]
+
+
 class gsis_result(ctypes.Structure):
     _fields_ = [("phi", ctypes.c_void_p), ("Fx", ctypes.c_void_p), ("Fy", ctypes.c_void_p),
                 ("err_hist", ctypes.c_void_p), ("n_iter", ctypes.c_int32),
@@ -72,7 +77,7 @@ EXPORTS = ("gsis_ctx_create", "gsis_ctx_destroy", "gsis_last_error", "gsis_optio
            "gsis_plan_status", "gsis_plan_read", "gsis_plan_reset", "gsis_plan_phase_times",
            "gsis_batch_create", "gsis_batch_destroy", "gsis_batch_iterate", "gsis_batch_status",
            "gsis_batch_read", "gsis_batch_reset", "gsis_batch_get_tuning", "gsis_solve_batch",
-           "gsis_version")
+           "gsis_plan_adjoint", "gsis_adjoint", "gsis_version")
 
 
 def load():
@@ -116,6 +121,11 @@ def load():
     lib.gsis_batch_get_tuning.argtypes = [vp, ctypes.POINTER(gsis_batch_tuning)]
     lib.gsis_solve_batch.argtypes = [vp, i32, ctypes.POINTER(gsis_problem),
                                      ctypes.POINTER(gsis_options), ctypes.POINTER(gsis_result)]
+    lib.gsis_plan_adjoint.argtypes = [vp, vp, vp, vp, ctypes.c_double, i32, vp, vp, vp,
+                                      ctypes.POINTER(gsis_adjoint_info)]
+    lib.gsis_adjoint.argtypes = [vp, ctypes.POINTER(gsis_problem), ctypes.POINTER(gsis_options),
+                                 vp, vp, vp, vp, vp, vp, ctypes.POINTER(gsis_result),
+                                 ctypes.POINTER(gsis_adjoint_info)]
     lib.gsis_version.argtypes = []
     lib.gsis_version.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -272,6 +282,39 @@ class Plan:
         n = ctypes.c_int32()
         _check(load().gsis_plan_phase_times(self.handle, ms, ctypes.byref(n)), self.ctx)
         return {k: ms[i] for i, k in enumerate(PHASES)}, n.value
+
+    def adjoint(self, g_phi=None, g_Fx=None, g_Fy=None, tol=1e-10, max_iter=1000):
+        """gsis_plan_adjoint on the converged plan: returns (dJ/dsigma_a,
+        dJ/dsigma_s, dJ/dq, info dict) for J = <g_phi, phi> + <g_F, F>."""
+        N = self.args.nx * self.args.ny
+        keep = []
+
+        def cot(g):
+            if g is None:
+                return None
+            if self.args.device:
+                import torch
+                t = g.detach().to(torch.float64).contiguous()
+                keep.append(t)
+                return t.data_ptr()
+            a = np.ascontiguousarray(g, dtype=np.float64).ravel()
+            keep.append(a)
+            return a.ctypes.data
+        if self.args.device:
+            import torch
+            dev = self.args.keep[0].device
+            outs = [torch.empty(N, dtype=torch.float64, device=dev) for _ in range(3)]
+            ptr = lambda t: t.data_ptr()
+        else:
+            outs = [np.empty(N) for _ in range(3)]
+            ptr = lambda a: a.ctypes.data
+        info = gsis_adjoint_info()
+        st = load().gsis_plan_adjoint(self.handle, cot(g_phi), cot(g_Fx), cot(g_Fy), float(tol),
+                                      int(max_iter), ptr(outs[0]), ptr(outs[1]), ptr(outs[2]),
+                                      ctypes.byref(info))
+        _check(st, self.ctx, allow=(GSIS_OK, GSIS_NOT_CONVERGED))
+        return outs[0], outs[1], outs[2], dict(n_iter=info.n_iter, final_err=info.final_err,
+                                               forward_iter=info.forward_iter, status=st)
 
     def close(self):
         if getattr(self, "handle", None):

@@ -199,6 +199,26 @@ def detector_window(n=512):
     return m.ravel()
 
 
+def adjoint_fd_cells(n=512, seed=55):
+    """16 cells (caller's index j*n + i) for finite-difference checks of the
+    detector gradient: 4 in the detector window, 4 on the thick square's
+    east edge, 4 between the two, 4 anywhere; drawn with PCG64(seed)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    i0, i1 = (27 * n) // 32, (29 * n) // 32
+    j0, j1 = (15 * n) // 32, (17 * n) // 32
+    e = (3 * n) // 4 - 1
+    cells = []
+    for _ in range(4):
+        cells.append(int(rng.integers(j0, j1)) * n + int(rng.integers(i0, i1)))
+    for _ in range(4):
+        cells.append(int(rng.integers(n // 4, (3 * n) // 4)) * n + e)
+    for _ in range(4):
+        cells.append(int(rng.integers(j0, j1)) * n + int(rng.integers(e + 1, i0)))
+    for _ in range(4):
+        cells.append(int(rng.integers(0, n * n)))
+    return np.array(cells)
+
+
 def random_problem(nx, ny, quad=None, seed=0, sigma_range=(0.1, 10.0), c_range=(0.3, 0.95),
                    inflow=True):
     """Small random medium for parity tests: sigma_t log-uniform per cell,
