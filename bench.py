@@ -16,6 +16,7 @@ time-to-converge (Err < 1e-6) for GSIS and for source iteration, and the CPU
 oracle on a bounded sample of the same workload.
 """
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -27,6 +28,15 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 ALG_BYTES_FP64 = 16.0
+
+# HBM traffic of the sweep kernel from two rocprofv3 --pmc runs of
+# "bench.py --steps 3 --warmup 1 --no-converge --no-cpu-baseline --no-forms"
+# (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), scaled by what the same
+# counters read for a 256 MiB device copy (bench.py --copy-calibration):
+# FETCH_SIZE x 2.0, WRITE_SIZE x 1.0. Valid only for the kernel source whose
+# sha256 is recorded; any change to it turns the figure back to null.
+SWEEP_TRAFFIC = {"sha256": "c58f9c28f737b8731a712ba090c96993a3eb420d93fe10968cfae3a3852088c3",
+                 "bytes": 170216673}   # 103107809 fetched + 67108864 written
 
 
 def log(msg):
@@ -51,6 +61,129 @@ def cpu_baseline(prob, n_iter):
                           r["n_iter"], prob["nx"], prob["ny"], K, dt)}
 
 
+def sweep_traffic():
+    """Bytes per sweep launch from the PMC runs, if the kernel is unchanged."""
+    if SWEEP_TRAFFIC is None:
+        return None
+    src = os.path.join(ROOT, "paper_2507_03975_amd", "csrc", "kernels_transport.hip")
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if sha != SWEEP_TRAFFIC["sha256"]:
+        return None
+    return SWEEP_TRAFFIC["bytes"]
+
+
+def _converge(pl, cap, chunk=16):
+    """Iterate a plan or batch until it stops; returns wall seconds."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    while True:
+        pl.iterate(min(chunk, cap - done))
+        done += min(chunk, cap - done)
+        st = pl.status()
+        if hasattr(pl, "tuning"):
+            if st[3] == pl.n or done >= cap:
+                break
+        elif st[1] != 0 or done >= cap:
+            break
+    return time.perf_counter() - t0
+
+
+def _rel(a, b):
+    return float((a - b).abs().max() / b.abs().max())
+
+
+def measure_forms(ctx, gsis, inputs, np, torch, dev):
+    """FP32-mixed, batched and adjoint forms against the plain FP64 form."""
+    dv = lambda p: {k: (torch.from_numpy(v).to(dev) if isinstance(v, np.ndarray) else v)
+                    for k, v in p.items()}
+    forms = {}
+    # FP32-mixed: 1024 x 1024 x 128 block medium (local pseudo time beta = 10)
+    pc = dv(inputs.checkerboard_blocks(1024))
+    res = {}
+    for name, prec in (("fp64", gsis.GSIS_FP64), ("fp32_mixed", gsis.GSIS_FP32_MIXED)):
+        pl = gsis.Plan(ctx, pc, precision=prec, tol=1e-6, max_iter=1000, limiter=0, beta=10.0)
+        sec = _converge(pl, 1000)
+        n, conv, err = pl.status()
+        res[name] = dict(iterations=int(n), seconds=sec, converged=bool(conv == 1),
+                         fields=pl.read())
+        pl.close()
+        log("block medium %s: %d iterations, %.3f s" % (name, n, sec))
+    a, b = res["fp32_mixed"]["fields"], res["fp64"]["fields"]
+    forms["fp32_mixed"] = {
+        "workload": "1024x1024 cells, 128 ordinates, 7x7 blocks sigma_a logU[1e-2,1e2] "
+                    "sigma_s logU[1e-1,1e4] (seed 3), beta 10, limiter off, Err < 1e-6",
+        "fp64": {k: v for k, v in res["fp64"].items() if k != "fields"},
+        "fp32_mixed": {k: v for k, v in res["fp32_mixed"].items() if k != "fields"},
+        "time_ratio_fp32_over_fp64": res["fp32_mixed"]["seconds"] / res["fp64"]["seconds"],
+        "error_vs_fp64": {"phi": _rel(a["phi"], b["phi"]), "Fx": _rel(a["Fx"], b["Fx"]),
+                          "Fy": _rel(a["Fy"], b["Fy"])}}
+    del res, a, b, pc
+    # batched: 64 uneven problems in one batch vs 64 sequential plain FP64 solves
+    probs = [dv(p) for p in inputs.batch_problems()]
+    co = sum(int(p["nx"]) * int(p["ny"]) * len(p["mu"]) for p in probs)
+    kw = dict(tol=1e-6, max_iter=1500, limiter=0, beta=20.0)
+    bres = {}
+    for name, prec in (("batch_fp64", gsis.GSIS_FP64), ("batch_fp32_mixed", gsis.GSIS_FP32_MIXED)):
+        t0 = time.perf_counter()
+        bt = gsis.Batch(ctx, probs, precision=prec, **kw)
+        setup = time.perf_counter() - t0
+        bt.iterate(3)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        bt.iterate(10)
+        bt.status()
+        it_ms = (time.perf_counter() - t1) * 100.0
+        bt.reset()
+        sec = _converge(bt, 1500, chunk=20)
+        its, conv, err, fin = bt.status()
+        bres[name] = dict(seconds=sec, setup_seconds=setup, ms_per_iteration=it_ms,
+                          cell_ordinate_updates_per_s=co / (it_ms / 1e3),
+                          max_iterations=int(max(its)),
+                          converged=int(sum(1 for c in conv if c == 1)), tuning=bt.tuning())
+        bt.close()
+        log("batch %s: %.3f s, %.2f ms/iteration" % (name, sec, it_ms))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for p in probs:
+        gsis.gsis_solve(ctx, p, **kw)
+    torch.cuda.synchronize()
+    seq = time.perf_counter() - t0
+    log("sequential plain FP64 solves: %.3f s" % seq)
+    forms["batched"] = {
+        "workload": "64 problems, nx, ny in {64..512}, 32-128 ordinates, 8x8 blocks sigma_t "
+                    "logU[0.1,1e4], c U[0.5,0.9999] (seed 4), beta 20, limiter off, Err < 1e-6",
+        "cell_ordinates_per_iteration": co,
+        "sequential_plain_fp64_seconds": seq, **bres,
+        "speedup_batch_fp64_over_sequential": seq / bres["batch_fp64"]["seconds"]}
+    del probs
+    # adjoint: 512 x 512 x 128 noisy two-region medium, detector objective
+    pa = inputs.noisy_thick_square(512)
+    W = torch.from_numpy(inputs.detector_window(512)).to(dev)
+    pd = dv(pa)
+    V = pa["dx"] * pa["dy"]
+    gphi = torch.where(W, V * pd["sigma_a"], torch.zeros_like(pd["sigma_a"]))
+    pl = gsis.Plan(ctx, pd, tol=1e-6, max_iter=2000, limiter=0)
+    fsec = _converge(pl, 2000)
+    n, conv, err = pl.status()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ga, gs, gq, info = pl.adjoint(gphi, tol=1e-6, max_iter=2000)
+    torch.cuda.synchronize()
+    asec = time.perf_counter() - t0
+    pl.close()
+    log("adjoint: forward %d its %.3f s, adjoint %d its %.3f s" % (n, fsec, info["n_iter"], asec))
+    forms["adjoint"] = {
+        "workload": "512x512 cells, 128 ordinates, two-region medium with +-20% noise (seed 5), "
+                    "J = sum over the 32x32 detector of V sigma_a phi, limiter off, Err < 1e-6",
+        "forward": {"iterations": int(n), "seconds": fsec},
+        "adjoint": {"iterations": info["n_iter"], "seconds": asec},
+        "adjoint_over_forward_time": asec / fsec}
+    return forms
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -60,6 +193,8 @@ def main():
     ap.add_argument("--no-converge", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=40)
     ap.add_argument("--si-cap", type=int, default=3000)
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the FP32-mixed, batched and adjoint measurements")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy five times (the known-size "
                          "kernel that scales the FETCH_SIZE / WRITE_SIZE counters)")
@@ -135,7 +270,7 @@ def main():
                    "nx": 256, "ny": 256, "ordinates": K, "method": "GSIS",
                    "step": "one outer iteration"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": sweep_traffic(),
                      "kernel": "k_sweep_fused (transport residual + exact wavefront sweep)",
                      "algorithmic_bytes_per_launch": ALG_BYTES_FP64 * N * K,
                      "avg_ms": sweep_ms},
@@ -177,6 +312,9 @@ def main():
         s_sec = s.get("seconds_extrapolated", s["seconds"])
         out["time_to_converge"] = {"tol": 1e-6, "gsis": g, "si": s,
                                    "si_over_gsis_time": s_sec / g["seconds"]}
+
+    if not args.no_forms:
+        out["forms"] = measure_forms(ctx, gsis, inputs, np, torch, dev)
 
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle, %d iterations" % args.cpu_iters)
