@@ -237,23 +237,17 @@ gsis_status gsis_batch_create(gsis_ctx *ctx, int32_t n, const gsis_problem *p,
       for (int lb = 0; lb < nb(D[i].N); ++lb) t.push_back(make_int2(i, lb));
     S.nb_cell = (int)t.size();
     if ((st = bupload(b, &S.bt_cell, t))) return bail(st);
-    S.bt_fine.assign(max_lc, nullptr);
-    S.bt_restr.assign(max_lc, nullptr);
-    S.nb_fine.assign(max_lc, 0);
-    S.nb_restr.assign(max_lc, 0);
+    S.bt_tile.assign(max_lc, nullptr);
+    S.nb_tile.assign(max_lc, 0);
     for (int l = 0; l < max_lc; ++l) {
-      std::vector<int2> tf, tr;
+      std::vector<int2> tt;
       for (int i = 0; i < n; ++i) {
         if (D[i].lc <= l) continue;
-        for (int lb = 0; lb < nb((long long)D[i].lev[l].nx * D[i].lev[l].ny); ++lb)
-          tf.push_back(make_int2(i, lb));
-        for (int lb = 0; lb < nb((long long)D[i].lev[l + 1].nx * D[i].lev[l + 1].ny); ++lb)
-          tr.push_back(make_int2(i, lb));
+        for (int lb = 0; lb < tiles_of(D[i].lev[l].nx, D[i].lev[l].ny); ++lb)
+          tt.push_back(make_int2(i, lb));
       }
-      S.nb_fine[l] = (int)tf.size();
-      S.nb_restr[l] = (int)tr.size();
-      if ((st = bupload(b, &S.bt_fine[l], tf)) || (st = bupload(b, &S.bt_restr[l], tr)))
-        return bail(st);
+      S.nb_tile[l] = (int)tt.size();
+      if ((st = bupload(b, &S.bt_tile[l], tt))) return bail(st);
     }
     std::vector<int2> tfc;
     for (int i = 0; i < n; ++i)

@@ -320,14 +320,9 @@ gsis_status make_single_set(gsis_plan *pl) {
   S.synth_max_iter = P.synth_max_iter;
   S.nb_cell = nb(P.N);
   S.bt_cell = nullptr;
-  S.bt_fine.assign(D.lc, nullptr);
-  S.bt_restr.assign(D.lc, nullptr);
-  S.nb_fine.resize(D.lc);
-  S.nb_restr.resize(D.lc);
-  for (int l = 0; l < D.lc; ++l) {
-    S.nb_fine[l] = nb(P.mg[l].nx * P.mg[l].ny);
-    S.nb_restr[l] = nb(P.mg[l + 1].nx * P.mg[l + 1].ny);
-  }
+  S.bt_tile.assign(D.lc, nullptr);
+  S.nb_tile.resize(D.lc);
+  for (int l = 0; l < D.lc; ++l) S.nb_tile[l] = tiles_of(P.mg[l].nx, P.mg[l].ny);
   S.state0 = P.state;
   prepare_synth(S.coarse_lds);
   return GSIS_OK;

@@ -79,6 +79,7 @@ struct SynthDesc {
   double *cg_r, *cg_z, *cg_p0, *cg_p1, *cg_Ap, *red, *scal, *err_parts, *err_hist, *last_err;
   int32_t *state;
   int nlev, lc;                 // levels; first level of the one-workgroup cycle
+  int ntile0;                   // multigrid tiles of level 0
   LevelDev lev[kMaxLevels];
   CoarseLevels cl;
   const double *coarse_inv;
@@ -93,10 +94,8 @@ struct SynthSet {
   // block tables (nullptr for a single problem) and their block counts
   int2 *bt_cell = nullptr;            // level-0 cells of every problem
   int nb_cell = 0;
-  std::vector<int2 *> bt_fine;        // [l]: level-l cells of problems with lc > l
-  std::vector<int> nb_fine;
-  std::vector<int2 *> bt_restr;       // [l]: level-(l+1) cells of problems with lc > l
-  std::vector<int> nb_restr;
+  std::vector<int2 *> bt_tile;        // [l]: level-l tiles of problems with lc > l
+  std::vector<int> nb_tile;
   int32_t *state0 = nullptr;          // single problem: its state (host checks)
 };
 
@@ -188,6 +187,7 @@ void launch_boundary_flux(const PlanDev &P, hipStream_t s);
 SynthDesc make_synth_desc(const PlanDev &P);
 int coarse_start(const PlanDev &P);
 size_t coarse_lds_bytes(const PlanDev &P);
+int tiles_of(int nx, int ny);   // multigrid tiles covering an nx x ny level
 void prepare_synth(size_t coarse_lds);      // kernel attribute for the LDS size
 void launch_source(const SynthSet &S, hipStream_t s);          // src from phi
 void launch_hot_rhs(const SynthSet &S, hipStream_t s);

@@ -133,7 +133,8 @@ __host__ __device__ inline int nblk_d(int n) { return (n + kRedBlock - 1) / kRed
 // s / RZ, RZ = s; 3 RR = s, count the iteration, converged if RR <= STOP;
 // 4 RR = s, STOP = max(rtol^2 RR, 1e-28 BB), converged if RR <= STOP,
 // iteration count 0. Partials: sel 0 red[0, nb), sel 1 red[nb, 2 nb), sel 2
-// the r.z partials (one value when the whole V-cycle ran in one workgroup).
+// the r.z partials (one per level-0 tile, or one value when the whole
+// V-cycle ran in one workgroup).
 __global__ void k_finish(const SynthDesc *ds, int sel, int slot, int op) {
   __shared__ double sh[kRedBlock];
   const SynthDesc &D = ds[blockIdx.x];
@@ -141,7 +142,7 @@ __global__ void k_finish(const SynthDesc *ds, int sel, int slot, int op) {
   if (cg_off(state)) return;
   const int nb = nblk_d(D.N);
   const double *part = D.red + (sel == 1 ? nb : 0);
-  const int npart = (sel == 2 && D.lc == 0) ? 1 : nb;
+  const int npart = sel == 2 ? (D.lc == 0 ? 1 : D.ntile0) : nb;
   double v = 0.0;
   for (int t = threadIdx.x; t < npart; t += blockDim.x) v += part[t];
   double s = block_sum(v, sh);
@@ -260,103 +261,181 @@ __device__ inline const double *lev_b(const SynthDesc &D, int l) {
   return l == 0 ? D.cg_r : D.lev[l].b;
 }
 
-// Red-black Gauss-Seidel with colour (i + j) & 1 (0 red, 1 black).
-//   red:   x_r = (b + sum a x_nb) / d; with zero_init the neighbours are 0
-//          (first half sweep from x = 0). With rz also a partial of
-//          sum_c r_c x_c over all cells (the preconditioned residual product
-//          r.z on level 0; black cells are final at this point).
-//   black: x_b = (b + sum a (x_nb + omega e_parent(nb))) / d, where e is the
-//          coarse-grid correction (corr = 0: none). The red cells' own
-//          corrected values are never needed: the red half sweep that
-//          follows overwrites them.
-__global__ void k_mg_red(const SynthDesc *ds, const int2 *bt, int l, int zero_init, int rz) {
-  __shared__ double sh[kRedBlock];
-  const Blk B = blk(bt);
-  const SynthDesc &D = ds[B.p];
-  if (cg_off(D.state)) return;
-  const LevelDev &L = D.lev[l];
-  const int nx = L.nx, ny = L.ny;
-  double *x = lev_x(D, l);
-  const double *b = lev_b(D, l);
-  const int c = B.lb * kRedBlock + threadIdx.x;
-  double v = 0.0;
-  if (c < nx * ny) {
-    int i, j;
-    cell_ij(c, nx, i, j);
-    double xc;
-    if (((i + j) & 1) == 0) {
-      double s = b[c];
-      if (!zero_init) {
-        if (i + 1 < nx) s += L.ax[c] * x[c + 1];
-        if (i > 0) s += L.ax[c - 1] * x[c - 1];
-        if (j + 1 < ny) s += L.ay[c] * x[c + nx];
-        if (j > 0) s += L.ay[c - nx] * x[c - nx];
-      }
-      xc = s / L.dg[c];
-      x[c] = xc;
+// Fine multigrid levels, one tile of kTW x kTH cells per workgroup (one
+// thread per cell) with a ring of kHalo cells around it in LDS. Red-black
+// Gauss-Seidel uses the colour (i + j) & 1 of the level (0 red, 1 black).
+//
+//  down: one V(1,1) pre-smoothing from x = 0 -- red x = b / d, then black
+//        x = (b + sum a x_nb) / d -- then r = b - A x and the coarse
+//        b = sum of r over each aggregate's fx x fy children. Starting from
+//        zero makes every value a function of b, d and the couplings within
+//        two cells, so the tile and its ring are computed without waiting
+//        for other workgroups. x of the tile is kept for the way up.
+//  up:   black x = (b + sum a (x_nb + omega e_parent(nb))) / d with the
+//        coarse correction e, then red x = (b + sum a x_nb) / d; the black
+//        ring is recomputed so the red cells of the tile see final
+//        neighbours. On level 0 also a partial of r.z (b = r, x = z).
+// Cells outside the level hold d = 1, b = 0 and no couplings.
+constexpr int kTW = 32, kTH = 8, kHalo = 2;
+constexpr int kRW = kTW + 2 * kHalo, kRH = kTH + 2 * kHalo, kRN = kRW * kRH;
+static_assert(kTW * kTH == kRedBlock, "one thread per tile cell");
+
+struct Tile {
+  int nx, ny, i0, j0;
+};
+__device__ inline Tile tile_of(const LevelDev &L, int lb) {
+  const int tx = (L.nx + kTW - 1) / kTW;
+  int ti, tj;
+  cell_ij(lb, tx, ti, tj);
+  return {L.nx, L.ny, ti * kTW - kHalo, tj * kTH - kHalo};
+}
+
+// b, d and the east / north couplings of the region into LDS
+__device__ inline void load_region(const LevelDev &L, const double *b, const Tile &T, double *sb,
+                                   double *sd, double *sax, double *say) {
+  for (int r = threadIdx.x; r < kRN; r += blockDim.x) {
+    int ri, rj;
+    cell_ij(r, kRW, ri, rj);
+    const int gi = T.i0 + ri, gj = T.j0 + rj;
+    if (gi >= 0 && gi < T.nx && gj >= 0 && gj < T.ny) {
+      const int g = gj * T.nx + gi;
+      sb[r] = b[g];
+      sd[r] = L.dg[g];
+      sax[r] = gi + 1 < T.nx ? L.ax[g] : 0.0;
+      say[r] = gj + 1 < T.ny ? L.ay[g] : 0.0;
     } else {
-      xc = rz ? x[c] : 0.0;
+      sb[r] = 0.0; sd[r] = 1.0; sax[r] = 0.0; say[r] = 0.0;
     }
-    if (rz) v = b[c] * xc;
-  }
-  if (rz) {
-    double t = block_sum(v, sh);
-    if (threadIdx.x == 0) D.red[B.lb] = t;
   }
 }
 
-__global__ void k_mg_black(const SynthDesc *ds, const int2 *bt, int l, int corr, double omega) {
-  const Blk B = blk(bt);
-  const SynthDesc &D = ds[B.p];
-  if (cg_off(D.state)) return;
-  const LevelDev &L = D.lev[l];
-  const int nx = L.nx, ny = L.ny;
-  const int c = B.lb * kRedBlock + threadIdx.x;
-  if (c >= nx * ny) return;
-  int i, j;
-  cell_ij(c, nx, i, j);
-  if (((i + j) & 1) != 1) return;
-  double *x = lev_x(D, l);
-  const double *b = lev_b(D, l);
-  const double *e = corr ? D.lev[l + 1].x : nullptr;
-  const int cnx = corr ? D.lev[l + 1].nx : 1, fx = L.fx, fy = L.fy;
-  auto X = [&](int ii, int jj) {
-    double v = x[jj * nx + ii];
-    if (e) v += omega * e[(jj >> (fy >> 1)) * cnx + (ii >> (fx >> 1))];
-    return v;
-  };
-  double s = b[c];
-  if (i + 1 < nx) s += L.ax[c] * X(i + 1, j);
-  if (i > 0) s += L.ax[c - 1] * X(i - 1, j);
-  if (j + 1 < ny) s += L.ay[c] * X(i, j + 1);
-  if (j > 0) s += L.ay[c - nx] * X(i, j - 1);
-  x[c] = s / L.dg[c];
-}
-
-// r = b - A x on level l, then the coarse b = sum over the fx x fy children
-// of each aggregate (blocks cover the coarse level l + 1).
-__global__ void k_mg_restrict(const SynthDesc *ds, const int2 *bt, int l) {
+__global__ void __launch_bounds__(kRedBlock) k_mg_down(const SynthDesc *ds, const int2 *bt, int l) {
+  __shared__ double sb[kRN], sd[kRN], sax[kRN], say[kRN], sx[kRN];
   const Blk B = blk(bt);
   const SynthDesc &D = ds[B.p];
   if (cg_off(D.state)) return;
   const LevelDev &L = D.lev[l], &CL = D.lev[l + 1];
-  const int nx = L.nx, ny = L.ny, cnx = CL.nx, cny = CL.ny;
-  const int C = B.lb * kRedBlock + threadIdx.x;
-  if (C >= cnx * cny) return;
-  const double *x = lev_x(D, l);
   const double *b = lev_b(D, l);
-  int I, J;
-  cell_ij(C, cnx, I, J);
-  double s = 0.0;
-  for (int dj = 0; dj < L.fy; ++dj)
-    for (int di = 0; di < L.fx; ++di) {
-      const int i = L.fx * I + di, j = L.fy * J + dj;
-      if (i < nx && j < ny) {
-        const int c = j * nx + i;
-        s += b[c] - apply5(nx, ny, L.dg, L.ax, L.ay, x, c);
-      }
+  double *x = lev_x(D, l);
+  const Tile T = tile_of(L, B.lb);
+  load_region(L, b, T, sb, sd, sax, say);
+  __syncthreads();
+  // red half sweep from zero on the whole region
+  for (int r = threadIdx.x; r < kRN; r += blockDim.x) {
+    int ri, rj;
+    cell_ij(r, kRW, ri, rj);
+    sx[r] = (((T.i0 + ri + T.j0 + rj) & 1) == 0) ? sb[r] / sd[r] : 0.0;
+  }
+  __syncthreads();
+  // black half sweep on the tile and a ring of one
+  for (int r = threadIdx.x; r < kRN; r += blockDim.x) {
+    int ri, rj;
+    cell_ij(r, kRW, ri, rj);
+    if (ri < 1 || ri > kRW - 2 || rj < 1 || rj > kRH - 2) continue;
+    if (((T.i0 + ri + T.j0 + rj) & 1) != 1) continue;
+    double v = sb[r];
+    v += sax[r] * sx[r + 1];
+    v += sax[r - 1] * sx[r - 1];
+    v += say[r] * sx[r + kRW];
+    v += say[r - kRW] * sx[r - kRW];
+    sx[r] = v / sd[r];
+  }
+  __syncthreads();
+  // residual of the tile cell of this thread; x of the tile to global
+  const int ti = threadIdx.x % kTW, tj = threadIdx.x / kTW;
+  const int r = (tj + kHalo) * kRW + ti + kHalo;
+  const int gi = T.i0 + kHalo + ti, gj = T.j0 + kHalo + tj;
+  double y = sd[r] * sx[r];
+  y -= sax[r] * sx[r + 1];
+  y -= sax[r - 1] * sx[r - 1];
+  y -= say[r] * sx[r + kRW];
+  y -= say[r - kRW] * sx[r - kRW];
+  const double res = sb[r] - y;
+  const bool in = gi < T.nx && gj < T.ny;
+  if (in) x[gj * T.nx + gi] = sx[r];
+  __syncthreads();
+  sb[r] = in ? res : 0.0;   // the tile's residuals (the ring is no longer needed)
+  __syncthreads();
+  // restriction: coarse cells whose children lie in this tile
+  const int fx = L.fx, fy = L.fy, sx_ = fx >> 1, sy_ = fy >> 1;
+  const int cw = kTW >> sx_, ch = kTH >> sy_;
+  if ((int)threadIdx.x < cw * ch) {
+    const int ci = threadIdx.x % cw, cj = threadIdx.x / cw;
+    const int CI = ((T.i0 + kHalo) >> sx_) + ci, CJ = ((T.j0 + kHalo) >> sy_) + cj;
+    if (CI < CL.nx && CJ < CL.ny) {
+      double v = 0.0;
+      for (int dj = 0; dj < fy; ++dj)
+        for (int di = 0; di < fx; ++di) {
+          const int li = ci * fx + di, lj = cj * fy + dj;
+          if (T.i0 + kHalo + li < T.nx && T.j0 + kHalo + lj < T.ny)
+            v += sb[(lj + kHalo) * kRW + li + kHalo];
+        }
+      CL.b[CJ * CL.nx + CI] = v;
     }
-  CL.b[C] = s;
+  }
+}
+
+__global__ void __launch_bounds__(kRedBlock) k_mg_up(const SynthDesc *ds, const int2 *bt, int l,
+                                                     int rz, double omega) {
+  __shared__ double sb[kRN], sd[kRN], sax[kRN], say[kRN], sx[kRN], sh[kRedBlock];
+  const Blk B = blk(bt);
+  const SynthDesc &D = ds[B.p];
+  if (cg_off(D.state)) return;
+  const LevelDev &L = D.lev[l], &CL = D.lev[l + 1];
+  const double *b = lev_b(D, l);
+  double *x = lev_x(D, l);
+  const double *e = CL.x;
+  const Tile T = tile_of(L, B.lb);
+  const int sx_ = L.fx >> 1, sy_ = L.fy >> 1;
+  load_region(L, b, T, sb, sd, sax, say);
+  // the pre-smoothed x plus the scaled coarse correction: the black half
+  // sweep sees corrected red neighbours
+  __shared__ double sxc[kRN];
+  for (int r = threadIdx.x; r < kRN; r += blockDim.x) {
+    int ri, rj;
+    cell_ij(r, kRW, ri, rj);
+    const int gi = T.i0 + ri, gj = T.j0 + rj;
+    double v = 0.0;
+    if (gi >= 0 && gi < T.nx && gj >= 0 && gj < T.ny) {
+      v = x[gj * T.nx + gi];
+      v += omega * e[(gj >> sy_) * CL.nx + (gi >> sx_)];
+    }
+    sxc[r] = v;
+  }
+  __syncthreads();
+  // black half sweep on the tile and a ring of one, into sx
+  for (int r = threadIdx.x; r < kRN; r += blockDim.x) {
+    int ri, rj;
+    cell_ij(r, kRW, ri, rj);
+    if (ri < 1 || ri > kRW - 2 || rj < 1 || rj > kRH - 2) { sx[r] = 0.0; continue; }
+    if (((T.i0 + ri + T.j0 + rj) & 1) != 1) { sx[r] = 0.0; continue; }
+    double v = sb[r];
+    v += sax[r] * sxc[r + 1];
+    v += sax[r - 1] * sxc[r - 1];
+    v += say[r] * sxc[r + kRW];
+    v += say[r - kRW] * sxc[r - kRW];
+    sx[r] = v / sd[r];
+  }
+  __syncthreads();
+  // red half sweep on the tile with the new black neighbours
+  const int ti = threadIdx.x % kTW, tj = threadIdx.x / kTW;
+  const int r = (tj + kHalo) * kRW + ti + kHalo;
+  const int gi = T.i0 + kHalo + ti, gj = T.j0 + kHalo + tj;
+  double xv = sx[r];
+  if (((gi + gj) & 1) == 0) {
+    double v = sb[r];
+    v += sax[r] * sx[r + 1];
+    v += sax[r - 1] * sx[r - 1];
+    v += say[r] * sx[r + kRW];
+    v += say[r - kRW] * sx[r - kRW];
+    xv = v / sd[r];
+  }
+  const bool in = gi < T.nx && gj < T.ny;
+  if (in) x[gj * T.nx + gi] = xv;
+  if (rz) {
+    const double t = block_sum(in ? sb[r] * xv : 0.0, sh);
+    if (threadIdx.x == 0) D.red[B.lb] = t;
+  }
 }
 
 // The coarse end of the V-cycle (every level with at most kCoarseWG cells,
@@ -699,21 +778,12 @@ __global__ void k_final_flux(int n, const double *Fx, const double *Fy, const do
 // otherwise beta = r.z / RZ, RZ = r.z).
 void vcycle(const SynthSet &S, bool first, hipStream_t s) {
   const SynthDesc *ds = S.desc;
-  for (int l = 0; l < S.max_lc; ++l) {
-    hipLaunchKernelGGL(k_mg_red, dim3(S.nb_fine[l]), dim3(kRedBlock), 0, s, ds, S.bt_fine[l], l,
-                       1, 0);
-    hipLaunchKernelGGL(k_mg_black, dim3(S.nb_fine[l]), dim3(kRedBlock), 0, s, ds, S.bt_fine[l],
-                       l, 0, 0.0);
-    hipLaunchKernelGGL(k_mg_restrict, dim3(S.nb_restr[l]), dim3(kRedBlock), 0, s, ds,
-                       S.bt_restr[l], l);
-  }
+  for (int l = 0; l < S.max_lc; ++l)
+    hipLaunchKernelGGL(k_mg_down, dim3(S.nb_tile[l]), dim3(kRedBlock), 0, s, ds, S.bt_tile[l], l);
   hipLaunchKernelGGL(k_mg_coarse, dim3(S.n), dim3(1024), S.coarse_lds, s, ds, kOmega);
-  for (int l = S.max_lc - 1; l >= 0; --l) {
-    hipLaunchKernelGGL(k_mg_black, dim3(S.nb_fine[l]), dim3(kRedBlock), 0, s, ds, S.bt_fine[l],
-                       l, 1, kOmega);
-    hipLaunchKernelGGL(k_mg_red, dim3(S.nb_fine[l]), dim3(kRedBlock), 0, s, ds, S.bt_fine[l], l,
-                       0, l == 0 ? 1 : 0);
-  }
+  for (int l = S.max_lc - 1; l >= 0; --l)
+    hipLaunchKernelGGL(k_mg_up, dim3(S.nb_tile[l]), dim3(kRedBlock), 0, s, ds, S.bt_tile[l], l,
+                       l == 0 ? 1 : 0, kOmega);
   hipLaunchKernelGGL(k_finish, dim3(S.n), dim3(kRedBlock), 0, s, ds, 2, (int)S_RZ, first ? 0 : 2);
 }
 
@@ -740,6 +810,8 @@ int coarse_start(const PlanDev &P) {
 }
 
 size_t coarse_lds_bytes(const PlanDev &P) { return coarse_lds_bytes_from(P, coarse_start(P)); }
+
+int tiles_of(int nx, int ny) { return ((nx + kTW - 1) / kTW) * ((ny + kTH - 1) / kTH); }
 
 // The attribute is per kernel, not per plan: it is raised to the largest
 // amount any plan may ask for, so that a later plan with a smaller coarse
@@ -772,6 +844,7 @@ SynthDesc make_synth_desc(const PlanDev &P) {
   }
   const int lc = coarse_start(P);
   D.lc = lc;
+  D.ntile0 = tiles_of(P.mg[0].nx, P.mg[0].ny);
   CoarseLevels &CL = D.cl;
   CL.nlev = D.nlev - lc;
   int off = 0;

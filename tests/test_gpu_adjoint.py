@@ -81,9 +81,11 @@ def test_adjoint_full_size_against_central_differences(ctx):
     """512 x 512 x 128 noisy two-region medium, detector objective:
     dJ/dsigma at 16 sampled cells (4 in the window, 4 on the thick square's
     east edge, 4 between, 4 anywhere; seed 55) against central differences of
-    the GPU forward solve (h = 1e-4 relative). The differences carry the
-    forward solve's error over h, about 1e-13 J / h, so the bound is 1e-5
-    relative plus 1e-6 of the largest gradient."""
+    the GPU forward solve (h = 1e-3 relative: truncation about 1e-6
+    relative). The differences also carry the forward error over h: Err is
+    relative to the whole field, dominated by the thick square, so phi in the
+    thin detector region is known to about 1e-10 of itself; hence the bound
+    1e-5 relative plus 1e-6 of the largest gradient."""
     import torch
     n = 512
     p = inputs.noisy_thick_square(n)
@@ -112,7 +114,7 @@ def test_adjoint_full_size_against_central_differences(ctx):
     _say("  sampled cells %s" % list(cells))
     for name, grad in (("sigma_a", ga), ("sigma_s", gs)):
         for c in cells:
-            h = 1e-4 * float(pd[name][c])
+            h = 1e-3 * float(pd[name][c])
             plus = pd[name].clone(); plus[c] += h
             minus = pd[name].clone(); minus[c] -= h
             args_p = (plus, pd["sigma_s"]) if name == "sigma_a" else (pd["sigma_a"], plus)
