@@ -47,7 +47,8 @@ struct MGLevel {
   int nx = 0, ny = 0;
   int fx = 1, fy = 1;   // aggregate size towards the next coarser level
   double *diag = nullptr, *ax = nullptr, *ay = nullptr;
-  double *x = nullptr, *b = nullptr, *r = nullptr;  // work vectors (levels >= 1)
+  double *x = nullptr, *b = nullptr, *r = nullptr;  // work vectors (x, b: levels >= 1;
+                                                    // r: pre-smoothed x, every level)
 };
 
 // ---- synthetic step, one problem or many: every kernel of the synthetic
@@ -67,6 +68,7 @@ struct LevelDev {
   int nx, ny, fx, fy;
   const double *dg, *ax, *ay;
   double *x, *b;                // levels >= 1 (level 0 uses the CG's z and r)
+  double *xs;                   // pre-smoothed x of a fine level (tile kernels)
 };
 struct SynthDesc {
   int nx, ny, N;

@@ -128,41 +128,53 @@ __device__ inline bool cg_off(const int32_t *st) { return st[1] != 0 || st[3] !=
 inline int nblk(int n) { return (n + kRedBlock - 1) / kRedBlock; }
 __host__ __device__ inline int nblk_d(int n) { return (n + kRedBlock - 1) / kRedBlock; }
 
-// One workgroup per problem (blockIdx.x = problem). Sum the problem's
-// partials, then: op 0 scal[slot] = s; 1 alpha = RZ / (PAP = s); 2 beta =
-// s / RZ, RZ = s; 3 RR = s, count the iteration, converged if RR <= STOP;
-// 4 RR = s, STOP = max(rtol^2 RR, 1e-28 BB), converged if RR <= STOP,
-// iteration count 0. Partials: sel 0 red[0, nb), sel 1 red[nb, 2 nb), sel 2
-// the r.z partials (one per level-0 tile, or one value when the whole
-// V-cycle ran in one workgroup).
-__global__ void k_finish(const SynthDesc *ds, int sel, int slot, int op) {
-  __shared__ double sh[kRedBlock];
-  const SynthDesc &D = ds[blockIdx.x];
+// Finishing a reduction: sum the problem's partials in a fixed order, then
+// op 0 scal[slot] = s; 1 alpha = RZ / (PAP = s); 2 beta = s / RZ, RZ = s;
+// 3 RR = s, count the iteration, converged if RR <= STOP; 4 RR = s,
+// STOP = max(rtol^2 RR, 1e-28 BB), converged if RR <= STOP, iteration count
+// 0. Partials: sel 0 red[0, nb), sel 1 red[nb, 2 nb), sel 2 the r.z partials
+// (one per level-0 tile, or one value when the whole V-cycle ran in one
+// workgroup).
+__device__ inline void finish_apply(const SynthDesc &D, int slot, int op, double s) {
+  double *scal = D.scal;
   int32_t *state = D.state;
-  if (cg_off(state)) return;
+  if (op == 0) scal[slot] = s;
+  else if (op == 1) { scal[S_PAP] = s; scal[S_ALPHA] = scal[S_RZ] / s; }
+  else if (op == 2) { scal[S_BETA] = s / scal[S_RZ]; scal[S_RZ] = s; }
+  else if (op == 3) {
+    scal[S_RR] = s;
+    scal[S_NIT] += 1.0;
+    if (!(s > scal[S_STOP])) state[3] = 1;
+  } else {
+    scal[S_RR] = s;
+    scal[S_NIT] = 0.0;
+    const double stop = fmax(D.rtol * D.rtol * s, 1e-28 * scal[S_BB]);
+    scal[S_STOP] = stop;
+    if (!(s > stop)) state[3] = 1;
+  }
+}
+
+__device__ inline void finish_reduce(const SynthDesc &D, int sel, int slot, int op, double *sh) {
   const int nb = nblk_d(D.N);
   const double *part = D.red + (sel == 1 ? nb : 0);
   const int npart = sel == 2 ? (D.lc == 0 ? 1 : D.ntile0) : nb;
   double v = 0.0;
   for (int t = threadIdx.x; t < npart; t += blockDim.x) v += part[t];
-  double s = block_sum(v, sh);
-  if (threadIdx.x == 0) {
-    double *scal = D.scal;
-    if (op == 0) scal[slot] = s;
-    else if (op == 1) { scal[S_PAP] = s; scal[S_ALPHA] = scal[S_RZ] / s; }
-    else if (op == 2) { scal[S_BETA] = s / scal[S_RZ]; scal[S_RZ] = s; }
-    else if (op == 3) {
-      scal[S_RR] = s;
-      scal[S_NIT] += 1.0;
-      if (!(s > scal[S_STOP])) state[3] = 1;
-    } else {
-      scal[S_RR] = s;
-      scal[S_NIT] = 0.0;
-      const double stop = fmax(D.rtol * D.rtol * s, 1e-28 * scal[S_BB]);
-      scal[S_STOP] = stop;
-      if (!(s > stop)) state[3] = 1;
-    }
-  }
+  const double s = block_sum(v, sh);
+  if (threadIdx.x == 0) finish_apply(D, slot, op, s);
+}
+
+// One workgroup per problem (blockIdx.x = problem) finishes a reduction.
+// (Folding this into the producing kernel, with the last block to arrive
+// doing it, needs a device-scope release per block; on a GPU whose XCDs
+// each have their own L2 that writes back the L2 every time and cost more
+// than the launch it saves.)
+__global__ void k_finish(const SynthDesc *ds, int sel, int slot, int op) {
+  __shared__ double sh[kRedBlock];
+  const SynthDesc &D = ds[blockIdx.x];
+  if (cg_off(D.state)) return;
+  if (sel == 2 && D.lc == 0) return;   // finished by the coarse kernel
+  finish_reduce(D, sel, slot, op, sh);
 }
 
 // Start of a synthetic solve: warm start x = phi, clear the converged flag;
@@ -270,11 +282,15 @@ __device__ inline const double *lev_b(const SynthDesc &D, int l) {
 //        b = sum of r over each aggregate's fx x fy children. Starting from
 //        zero makes every value a function of b, d and the couplings within
 //        two cells, so the tile and its ring are computed without waiting
-//        for other workgroups. x of the tile is kept for the way up.
-//  up:   black x = (b + sum a (x_nb + omega e_parent(nb))) / d with the
+//        for other workgroups. The pre-smoothed x of the tile goes to the
+//        level's spare vector xs, not to x.
+//  up:   black x = (b + sum a (xs_nb + omega e_parent(nb))) / d with the
 //        coarse correction e, then red x = (b + sum a x_nb) / d; the black
 //        ring is recomputed so the red cells of the tile see final
-//        neighbours. On level 0 also a partial of r.z (b = r, x = z).
+//        neighbours. On level 0 also a partial of r.z (b = r, x = z). It
+//        reads the pre-smoothed xs of the ring and writes the final x into a
+//        different array, so tiles running later never see a neighbour's
+//        final values in place of its pre-smoothed ones.
 // Cells outside the level hold d = 1, b = 0 and no couplings.
 constexpr int kTW = 32, kTH = 8, kHalo = 2;
 constexpr int kRW = kTW + 2 * kHalo, kRH = kTH + 2 * kHalo, kRN = kRW * kRH;
@@ -316,7 +332,7 @@ __global__ void __launch_bounds__(kRedBlock) k_mg_down(const SynthDesc *ds, cons
   if (cg_off(D.state)) return;
   const LevelDev &L = D.lev[l], &CL = D.lev[l + 1];
   const double *b = lev_b(D, l);
-  double *x = lev_x(D, l);
+  double *xs = L.xs;
   const Tile T = tile_of(L, B.lb);
   load_region(L, b, T, sb, sd, sax, say);
   __syncthreads();
@@ -352,7 +368,7 @@ __global__ void __launch_bounds__(kRedBlock) k_mg_down(const SynthDesc *ds, cons
   y -= say[r - kRW] * sx[r - kRW];
   const double res = sb[r] - y;
   const bool in = gi < T.nx && gj < T.ny;
-  if (in) x[gj * T.nx + gi] = sx[r];
+  if (in) xs[gj * T.nx + gi] = sx[r];
   __syncthreads();
   sb[r] = in ? res : 0.0;   // the tile's residuals (the ring is no longer needed)
   __syncthreads();
@@ -376,7 +392,7 @@ __global__ void __launch_bounds__(kRedBlock) k_mg_down(const SynthDesc *ds, cons
 }
 
 __global__ void __launch_bounds__(kRedBlock) k_mg_up(const SynthDesc *ds, const int2 *bt, int l,
-                                                     int rz, double omega) {
+                                                     int rz, int first, double omega) {
   __shared__ double sb[kRN], sd[kRN], sax[kRN], say[kRN], sx[kRN], sh[kRedBlock];
   const Blk B = blk(bt);
   const SynthDesc &D = ds[B.p];
@@ -384,6 +400,7 @@ __global__ void __launch_bounds__(kRedBlock) k_mg_up(const SynthDesc *ds, const 
   const LevelDev &L = D.lev[l], &CL = D.lev[l + 1];
   const double *b = lev_b(D, l);
   double *x = lev_x(D, l);
+  const double *xs = L.xs;
   const double *e = CL.x;
   const Tile T = tile_of(L, B.lb);
   const int sx_ = L.fx >> 1, sy_ = L.fy >> 1;
@@ -397,7 +414,7 @@ __global__ void __launch_bounds__(kRedBlock) k_mg_up(const SynthDesc *ds, const 
     const int gi = T.i0 + ri, gj = T.j0 + rj;
     double v = 0.0;
     if (gi >= 0 && gi < T.nx && gj >= 0 && gj < T.ny) {
-      v = x[gj * T.nx + gi];
+      v = xs[gj * T.nx + gi];
       v += omega * e[(gj >> sy_) * CL.nx + (gi >> sx_)];
     }
     sxc[r] = v;
@@ -436,6 +453,7 @@ __global__ void __launch_bounds__(kRedBlock) k_mg_up(const SynthDesc *ds, const 
     const double t = block_sum(in ? sb[r] * xv : 0.0, sh);
     if (threadIdx.x == 0) D.red[B.lb] = t;
   }
+  (void)first;
 }
 
 // The coarse end of the V-cycle (every level with at most kCoarseWG cells,
@@ -445,7 +463,8 @@ __global__ void __launch_bounds__(kRedBlock) k_mg_up(const SynthDesc *ds, const 
 // cells per thread), the lower levels in LDS; all vectors live in LDS.
 constexpr int kCoarseWG = 4096;
 
-__global__ void __launch_bounds__(1024) k_mg_coarse(const SynthDesc *ds, double omega) {
+__global__ void __launch_bounds__(1024) k_mg_coarse(const SynthDesc *ds, double omega,
+                                                    int first) {
   extern __shared__ double sm[];
   __shared__ double red[1024];
   const SynthDesc &D = ds[blockIdx.x];
@@ -679,7 +698,10 @@ __global__ void __launch_bounds__(1024) k_mg_coarse(const SynthDesc *ds, double 
       if (tid < h) red[tid] += red[tid + h];
       __syncthreads();
     }
-    if (tid == 0) part[0] = red[0];
+    if (tid == 0) {
+      part[0] = red[0];
+      finish_apply(D, S_RZ, first ? 0 : 2, red[0]);   // the whole V-cycle ran here
+    }
   }
 }
 
@@ -780,11 +802,15 @@ void vcycle(const SynthSet &S, bool first, hipStream_t s) {
   const SynthDesc *ds = S.desc;
   for (int l = 0; l < S.max_lc; ++l)
     hipLaunchKernelGGL(k_mg_down, dim3(S.nb_tile[l]), dim3(kRedBlock), 0, s, ds, S.bt_tile[l], l);
-  hipLaunchKernelGGL(k_mg_coarse, dim3(S.n), dim3(1024), S.coarse_lds, s, ds, kOmega);
+  hipLaunchKernelGGL(k_mg_coarse, dim3(S.n), dim3(1024), S.coarse_lds, s, ds, kOmega,
+                     first ? 1 : 0);
   for (int l = S.max_lc - 1; l >= 0; --l)
     hipLaunchKernelGGL(k_mg_up, dim3(S.nb_tile[l]), dim3(kRedBlock), 0, s, ds, S.bt_tile[l], l,
-                       l == 0 ? 1 : 0, kOmega);
-  hipLaunchKernelGGL(k_finish, dim3(S.n), dim3(kRedBlock), 0, s, ds, 2, (int)S_RZ, first ? 0 : 2);
+                       l == 0 ? 1 : 0, first ? 1 : 0, kOmega);
+  // problems whose whole V-cycle ran in the coarse kernel were finished there
+  if (S.max_lc > 0)
+    hipLaunchKernelGGL(k_finish, dim3(S.n), dim3(kRedBlock), 0, s, ds, 2, (int)S_RZ,
+                       first ? 0 : 2);
 }
 
 }  // namespace
@@ -840,7 +866,7 @@ SynthDesc make_synth_desc(const PlanDev &P) {
   D.nlev = (int)P.mg.size();
   for (int l = 0; l < D.nlev && l < kMaxLevels; ++l) {
     const MGLevel &L = P.mg[l];
-    D.lev[l] = LevelDev{L.nx, L.ny, L.fx, L.fy, L.diag, L.ax, L.ay, L.x, L.b};
+    D.lev[l] = LevelDev{L.nx, L.ny, L.fx, L.fy, L.diag, L.ax, L.ay, L.x, L.b, L.r};
   }
   const int lc = coarse_start(P);
   D.lc = lc;
