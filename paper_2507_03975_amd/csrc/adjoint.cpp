@@ -124,7 +124,7 @@ gsis_status gsis_plan_adjoint(gsis_plan *pl, const double *g_phi, const double *
   while (m < max_iter) {
     const int todo = std::min(check, max_iter - m);
     for (int t = 0; t < todo; ++t, ++m)
-      adj_launch_pass(P, B, B.args.data(), ihalf, B.S, B.hist, m, (int32_t *)pl->host_scal, s);
+      adj_launch_pass(P, B, B.args.data(), ihalf, B.S, B.hist, m, (int32_t *)pl->host_scal + 4, s);
     HIPCHK(ctx, hipGetLastError());
     HIPCHK(ctx, hipMemcpyAsync(h.data(), B.hist, m * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(ctx, hipStreamSynchronize(s));
@@ -141,7 +141,7 @@ gsis_status gsis_plan_adjoint(gsis_plan *pl, const double *g_phi, const double *
   if (status == -1) return fail(ctx, GSIS_DIVERGED, "adjoint iteration diverged");
   // gradient: one more pass with lambda* (it recomputes every cotangent the
   // derivatives need), then the per-cell assembly
-  adj_launch_pass(P, B, B.args.data(), ihalf, B.S, nullptr, 0, (int32_t *)pl->host_scal, s);
+  adj_launch_pass(P, B, B.args.data(), ihalf, B.S, nullptr, 0, (int32_t *)pl->host_scal + 4, s);
   adj_launch_gradient(P, B.args.data(), ihalf, B.g_sa, B.g_ss, B.g_q, s);
   HIPCHK(ctx, hipGetLastError());
   const hipMemcpyKind k = pl->device_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;

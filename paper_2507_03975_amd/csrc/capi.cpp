@@ -282,8 +282,10 @@ gsis_status setup_synth(gsis_plan *pl, PlanDev &P, std::vector<HostLevel> &hl) {
       (st = dalloc(pl, &P.cg_p, N)) || (st = dalloc(pl, &P.cg_p2, N)) ||
       (st = dalloc(pl, &P.cg_Ap, N)) || (st = dalloc(pl, &P.scal, 16)))
     return st;
+  // block partials: p.Ap, r.r, b.b (one per 256 cells each), then r.z (one
+  // per level-0 multigrid tile)
   P.red_blocks = (N + 255) / 256;
-  if ((st = dalloc(pl, &P.red, 2 * (size_t)P.red_blocks + 2))) return st;
+  if ((st = dalloc(pl, &P.red, 3 * (size_t)P.red_blocks + tiles_of(P.nx, P.ny) + 2))) return st;
   P.mg.resize(hl.size());
   for (size_t l = 0; l < hl.size(); ++l) {
     MGLevel &L = P.mg[l];
@@ -467,7 +469,7 @@ extern "C" gsis_status gsis_plan_create(gsis_ctx *ctx, const gsis_problem *p,
 
   // -- per-quadrant coefficient records in each quadrant's mirrored frame
   //    (cE, cW, cN, cS, sigma_t, sigma_t + pseudo-time shift)
-  std::vector<double> cellq((size_t)4 * N * 6, 0.0);
+  std::vector<double> cellq((size_t)4 * N * 6, 0.0), sdq((size_t)4 * N, 0.0);
   for (int qd = 0; qd < 4; ++qd)
     for (int yl = 0; yl < ny; ++yl)
       for (int xl = 0; xl < nx; ++xl) {
@@ -480,10 +482,14 @@ extern "C" gsis_status gsis_plan_create(gsis_ctx *ctx, const gsis_problem *p,
         r[3] = (qd & 2) ? cN[c] : cS[c];
         r[4] = st_[c];
         r[5] = st_[c] + shift[c];
+        sdq[(size_t)qd * N + dg_idx(xl, yl, nx, ny)] = r[5];
       }
+  const std::vector<int2> rtiles = residual_tiles(nx, ny);
+  P.n_rtiles = (int)rtiles.size();
   {
+    // 1: two-kernel reference, 2: fused wavefront sweep (tests compare them)
     const char *e = getenv("GSIS_SWEEP_REFERENCE");
-    P.sweep_impl = (e && e[0] == '1') ? 1 : 0;
+    P.sweep_impl = (e && (e[0] == '1' || e[0] == '2')) ? e[0] - '0' : 0;
   }
 
   // -- boundary intensities in the internal ordinate order
@@ -537,7 +543,8 @@ extern "C" gsis_status gsis_plan_create(gsis_ctx *ctx, const gsis_problem *p,
       (st = alloc_intensity(pl, 1, (size_t)N * K, f32)) ||
       (st = dalloc(pl, &P.R, P.sweep_impl == 1 ? (size_t)N * K : 1)) ||
       (st = upload(pl, &P.cellq, cellq)) || (st = dalloc(pl, &P.dynq, (size_t)4 * N * 3)) ||
-      (st = dalloc(pl, &P.rowbuf, (size_t)K * 3 * nx)) ||
+      (st = dalloc(pl, &P.rowbuf, (size_t)K * 3 * nx)) || (st = upload(pl, &P.sdq, sdq)) ||
+      (st = upload(pl, &P.rtiles, rtiles)) || (st = upload(pl, &P.dso, diag_row0_table(nx, ny))) ||
       (st = upload(pl, &P.sig_t, st_)) || (st = upload(pl, &P.sig_a, sa)) ||
       (st = upload(pl, &P.sig_s, ss)) || (st = upload(pl, &P.q, q)) ||
       (st = upload(pl, &P.cE, cE)) || (st = upload(pl, &P.cW, cW)) ||
@@ -565,9 +572,13 @@ extern "C" gsis_status gsis_plan_create(gsis_ctx *ctx, const gsis_problem *p,
                      kMaxLevels));
   if ((st = make_single_set(pl))) return bail(st);
   {
+    // flags read back by the synthetic solve: [0, 3) state and [8] the CG
+    // count of the last forward solve; [4, 7) and [12] the same for the
+    // adjoint's solves
     void *h = nullptr;
     hipError_t e = hipHostMalloc(&h, 64, hipHostMallocDefault);
     if (e != hipSuccess) return bail(fail(ctx, GSIS_E_OOM, "hipHostMalloc: %s", hipGetErrorString(e)));
+    memset(h, 0, 64);
     pl->host_scal = (double *)h;
   }
   if ((st = gsis_plan_reset(pl))) return bail(st);

@@ -124,7 +124,13 @@ struct PlanDev {
   // rewritten after every update
   double *cellq = nullptr, *dynq = nullptr;
   double *rowbuf = nullptr;    // [K][3][nx] hand-off between sweep passes
-  int sweep_impl = 0;          // 0 fused wavefront sweep, 1 two-kernel reference
+  double *sdq = nullptr;       // [q][N] sigma_t + pseudo-time shift per stored cell
+  int2 *rtiles = nullptr;      // residual-kernel tiles (first diagonal, first row)
+  int *dso = nullptr;          // [kDiagPad + nx + ny - 1 + kDiagPad] storage index of
+                               // row 0 on each anti-diagonal (dg_off - ylo), padded
+  int n_rtiles = 0;
+  int sweep_impl = 0;          // 0 residual kernel + wavefront recurrence,
+                               // 1 two-kernel reference, 2 fused wavefront sweep
   // per cell
   double *sig_t = nullptr, *sig_a = nullptr, *sig_s = nullptr, *q = nullptr;
   double *cE = nullptr, *cW = nullptr, *cN = nullptr, *cS = nullptr;  // ALSM
@@ -163,6 +169,14 @@ struct PlanDev {
 
 // ---- transport kernels (kernels_transport.hip)
 void launch_transport(const PlanDev &P, hipStream_t s);   // residual + sweep
+// Tiles of the residual kernel for an nx x ny grid: (first diagonal, first
+// row) of each band of rows x run of diagonals that holds a cell.
+std::vector<int2> residual_tiles(int nx, int ny);
+// Storage index of row 0 on anti-diagonal d (dg_off(d) - ylo(d)), for d in
+// [-kDiagPad, nx + ny - 1 + kDiagPad); outside the grid's diagonals the value
+// sends every row out of the intensity buffer.
+constexpr int kDiagPad = 256;
+std::vector<int> diag_row0_table(int nx, int ny);
 // Batched sweep: per-problem kernel arguments (fill_targs into a device
 // table of targs_bytes() records), work items (problem, internal ordinate),
 // a device counter, and one of the compiled launch configurations.

@@ -117,9 +117,12 @@ __device__ inline double apply5(int nx, int ny, const double *dg, const double *
   return s;
 }
 
-// Scalar slots
+// Scalar slots. r.z of CG iteration k sits in slot rz_slot(k) (two
+// alternating slots, so a kernel can read iteration k-1's value while its
+// block 0 stores iteration k's).
 enum { S_RZ = 0, S_PAP = 1, S_RR = 2, S_BB = 3, S_ALPHA = 4, S_BETA = 5, S_STOP = 6,
-       S_NIT = 7 };
+       S_NIT = 7, S_RZ1 = 8 };
+__host__ __device__ inline int rz_slot(int k) { return (k & 1) ? S_RZ1 : S_RZ; }
 
 // CG kernels run unless the outer iteration is done (state[1]) or this
 // synthetic solve has converged (state[3]).
@@ -128,53 +131,66 @@ __device__ inline bool cg_off(const int32_t *st) { return st[1] != 0 || st[3] !=
 inline int nblk(int n) { return (n + kRedBlock - 1) / kRedBlock; }
 __host__ __device__ inline int nblk_d(int n) { return (n + kRedBlock - 1) / kRedBlock; }
 
-// Finishing a reduction: sum the problem's partials in a fixed order, then
-// op 0 scal[slot] = s; 1 alpha = RZ / (PAP = s); 2 beta = s / RZ, RZ = s;
-// 3 RR = s, count the iteration, converged if RR <= STOP; 4 RR = s,
-// STOP = max(rtol^2 RR, 1e-28 BB), converged if RR <= STOP, iteration count
-// 0. Partials: sel 0 red[0, nb), sel 1 red[nb, 2 nb), sel 2 the r.z partials
-// (one per level-0 tile, or one value when the whole V-cycle ran in one
-// workgroup).
-__device__ inline void finish_apply(const SynthDesc &D, int slot, int op, double s) {
-  double *scal = D.scal;
-  int32_t *state = D.state;
-  if (op == 0) scal[slot] = s;
-  else if (op == 1) { scal[S_PAP] = s; scal[S_ALPHA] = scal[S_RZ] / s; }
-  else if (op == 2) { scal[S_BETA] = s / scal[S_RZ]; scal[S_RZ] = s; }
-  else if (op == 3) {
-    scal[S_RR] = s;
-    scal[S_NIT] += 1.0;
-    if (!(s > scal[S_STOP])) state[3] = 1;
-  } else {
-    scal[S_RR] = s;
-    scal[S_NIT] = 0.0;
-    const double stop = fmax(D.rtol * D.rtol * s, 1e-28 * scal[S_BB]);
-    scal[S_STOP] = stop;
-    if (!(s > stop)) state[3] = 1;
-  }
-}
+// Block partials of a problem's reductions, in separate regions of its red
+// array (nb = level-0 blocks of 256 cells): [0, nb) p.Ap, [nb, 2 nb) r.r,
+// [2 nb, 3 nb) b.b, then r.z (one per level-0 tile, or a single value when
+// the whole V-cycle ran in one workgroup). A reduction is finished by the
+// kernel that needs its value: every block of it sums the partials in the
+// same fixed order, so all blocks hold the same number and results repeat
+// bit for bit; block 0 stores it for later kernels. This saves a launch
+// per reduction (folding the finish into the producing kernel instead would
+// need a device-scope release per block, which on a GPU whose XCDs each
+// have their own L2 writes back the L2 every time).
+__device__ inline double *red_pap(const SynthDesc &D) { return D.red; }
+__device__ inline double *red_rr(const SynthDesc &D) { return D.red + nblk_d(D.N); }
+__device__ inline double *red_bb(const SynthDesc &D) { return D.red + 2 * nblk_d(D.N); }
+__device__ inline double *red_rz(const SynthDesc &D) { return D.red + 3 * nblk_d(D.N); }
+__device__ inline int n_rz(const SynthDesc &D) { return D.lc == 0 ? 1 : D.ntile0; }
 
-__device__ inline void finish_reduce(const SynthDesc &D, int sel, int slot, int op, double *sh) {
-  const int nb = nblk_d(D.N);
-  const double *part = D.red + (sel == 1 ? nb : 0);
-  const int npart = sel == 2 ? (D.lc == 0 ? 1 : D.ntile0) : nb;
+__device__ inline double sum_partials(const double *p, int n, double *sh) {
   double v = 0.0;
-  for (int t = threadIdx.x; t < npart; t += blockDim.x) v += part[t];
-  const double s = block_sum(v, sh);
-  if (threadIdx.x == 0) finish_apply(D, slot, op, s);
+  for (int t = threadIdx.x; t < n; t += blockDim.x) v += p[t];
+  return block_sum(v, sh);
 }
 
-// One workgroup per problem (blockIdx.x = problem) finishes a reduction.
-// (Folding this into the producing kernel, with the last block to arrive
-// doing it, needs a device-scope release per block; on a GPU whose XCDs
-// each have their own L2 that writes back the L2 every time and cost more
-// than the launch it saves.)
-__global__ void k_finish(const SynthDesc *ds, int sel, int slot, int op) {
+// r.r of the iterate just updated: iteration count and convergence test
+// against STOP; first (after the warm start): also b.b, the count reset and
+// STOP = max(rtol^2 r0.r0, 1e-28 b.b). Every thread of the block returns
+// the same decision; thread 0 stores the scalars and the flag.
+__device__ inline bool finish_rr(const SynthDesc &D, bool first, double *sh) {
+  const int nb = nblk_d(D.N);
+  const double rr = sum_partials(red_rr(D), nb, sh);
+  double stop;
+  double bb = 0.0;
+  if (first) {
+    bb = sum_partials(red_bb(D), nb, sh);
+    stop = fmax(D.rtol * D.rtol * rr, 1e-28 * bb);
+  } else {
+    stop = D.scal[S_STOP];
+  }
+  const bool conv = !(rr > stop);
+  if (threadIdx.x == 0) {
+    double *scal = D.scal;
+    scal[S_RR] = rr;
+    if (first) {
+      scal[S_BB] = bb;
+      scal[S_STOP] = stop;
+      scal[S_NIT] = 0.0;
+    } else {
+      scal[S_NIT] += 1.0;
+    }
+    if (conv) D.state[3] = 1;
+  }
+  return conv;
+}
+
+// The r.r test of the last CG iteration when the iteration cap ends the
+// solve (one workgroup per problem).
+__global__ void k_finish_rr(const SynthDesc *ds) {
   __shared__ double sh[kRedBlock];
   const SynthDesc &D = ds[blockIdx.x];
   if (cg_off(D.state)) return;
-  if (sel == 2 && D.lc == 0) return;   // finished by the coarse kernel
-  finish_reduce(D, sel, slot, op, sh);
+  (void)finish_rr(D, false, sh);
 }
 
 // Start of a synthetic solve: warm start x = phi, clear the converged flag;
@@ -207,26 +223,34 @@ __global__ void k_cg_begin(const SynthDesc *ds, const int2 *bt) {
   }
   if (B.lb == 0 && threadIdx.x == 0) D.state[3] = 0;
   double t = block_sum(rr, sh);
-  if (threadIdx.x == 0) D.red[B.lb] = t;
+  if (threadIdx.x == 0) red_rr(D)[B.lb] = t;
   t = block_sum(bb, sh);
-  if (threadIdx.x == 0) D.red[nblk_d(D.N) + B.lb] = t;
+  if (threadIdx.x == 0) red_bb(D)[B.lb] = t;
 }
 
-// p_new = z + beta p_old (= z on the first iteration), Ap = A p_new and a
-// partial of p_new . Ap. Neighbour values of p_new are formed from z and
-// p_old, so one kernel does both. par selects which p buffer is new.
-__global__ void k_cg_pAp(const SynthDesc *ds, const int2 *bt, int first, int par) {
+// CG iteration it: r.z from the V-cycle's partials, beta = r.z / (previous
+// r.z); p_new = z + beta p_old (= z on the first iteration), Ap = A p_new and
+// a partial of p_new . Ap. Neighbour values of p_new are formed from z and
+// p_old, so one kernel does both. Buffers alternate with the parity of it.
+__global__ void k_cg_pAp(const SynthDesc *ds, const int2 *bt, int it) {
   __shared__ double sh[kRedBlock];
   const Blk B = blk(bt);
   const SynthDesc &D = ds[B.p];
   if (cg_off(D.state)) return;
+  const bool first = it == 0;
+  const int par = it & 1;
+  const double rz = sum_partials(red_rz(D), n_rz(D), sh);
+  const double be = first ? 0.0 : rz / D.scal[rz_slot(it - 1)];
+  if (B.lb == 0 && threadIdx.x == 0) {
+    D.scal[rz_slot(it)] = rz;
+    D.scal[S_BETA] = be;
+  }
   const int c = B.lb * kRedBlock + threadIdx.x;
   const LevelDev &L = D.lev[0];
   const int nx = L.nx, ny = L.ny;
   const double *z = D.cg_z;
   const double *pold = par ? D.cg_p1 : D.cg_p0;
   double *pnew = par ? D.cg_p0 : D.cg_p1;
-  const double be = first ? 0.0 : D.scal[S_BETA];
   auto P = [&](int k) { return first ? z[k] : z[k] + be * pold[k]; };
   double v = 0.0;
   if (c < D.N) {
@@ -243,27 +267,33 @@ __global__ void k_cg_pAp(const SynthDesc *ds, const int2 *bt, int first, int par
     v = pc * y;
   }
   double t = block_sum(v, sh);
-  if (threadIdx.x == 0) D.red[B.lb] = t;
+  if (threadIdx.x == 0) red_pap(D)[B.lb] = t;
 }
 
-// x += alpha p ; r -= alpha Ap ; partial of r.r
-__global__ void k_cg_update(const SynthDesc *ds, const int2 *bt, int par) {
+// CG iteration it: alpha = r.z / p.Ap; x += alpha p ; r -= alpha Ap ;
+// partial of r.r
+__global__ void k_cg_update(const SynthDesc *ds, const int2 *bt, int it) {
   __shared__ double sh[kRedBlock];
   const Blk B = blk(bt);
   const SynthDesc &D = ds[B.p];
   if (cg_off(D.state)) return;
+  const double pap = sum_partials(red_pap(D), nblk_d(D.N), sh);
+  const double al = D.scal[rz_slot(it)] / pap;
+  if (B.lb == 0 && threadIdx.x == 0) {
+    D.scal[S_PAP] = pap;
+    D.scal[S_ALPHA] = al;
+  }
   const int c = B.lb * kRedBlock + threadIdx.x;
-  const double *p = par ? D.cg_p0 : D.cg_p1;
+  const double *p = (it & 1) ? D.cg_p0 : D.cg_p1;
   double v = 0.0;
   if (c < D.N) {
-    const double al = D.scal[S_ALPHA];
     D.lev[0].x[c] += al * p[c];
     const double rc = D.cg_r[c] - al * D.cg_Ap[c];
     D.cg_r[c] = rc;
     v = rc * rc;
   }
   double t = block_sum(v, sh);
-  if (threadIdx.x == 0) D.red[B.lb] = t;
+  if (threadIdx.x == 0) red_rr(D)[B.lb] = t;
 }
 
 // ------------------------------------------------------------ multigrid
@@ -325,11 +355,16 @@ __device__ inline void load_region(const LevelDev &L, const double *b, const Til
   }
 }
 
-__global__ void __launch_bounds__(kRedBlock) k_mg_down(const SynthDesc *ds, const int2 *bt, int l) {
+__global__ void __launch_bounds__(kRedBlock) k_mg_down(const SynthDesc *ds, const int2 *bt, int l,
+                                                       int first) {
   __shared__ double sb[kRN], sd[kRN], sax[kRN], say[kRN], sx[kRN];
+  static_assert(kRN >= kRedBlock, "sb doubles as reduction scratch");
   const Blk B = blk(bt);
   const SynthDesc &D = ds[B.p];
   if (cg_off(D.state)) return;
+  // the r.r test of the CG step before this V-cycle (the other blocks go on:
+  // if it converged, their results are not used)
+  if (l == 0 && B.lb == 0) (void)finish_rr(D, first != 0, sb);
   const LevelDev &L = D.lev[l], &CL = D.lev[l + 1];
   const double *b = lev_b(D, l);
   double *xs = L.xs;
@@ -451,7 +486,7 @@ __global__ void __launch_bounds__(kRedBlock) k_mg_up(const SynthDesc *ds, const 
   if (in) x[gj * T.nx + gi] = xv;
   if (rz) {
     const double t = block_sum(in ? sb[r] * xv : 0.0, sh);
-    if (threadIdx.x == 0) D.red[B.lb] = t;
+    if (threadIdx.x == 0) red_rz(D)[B.lb] = t;
   }
   (void)first;
 }
@@ -469,11 +504,14 @@ __global__ void __launch_bounds__(1024) k_mg_coarse(const SynthDesc *ds, double 
   __shared__ double red[1024];
   const SynthDesc &D = ds[blockIdx.x];
   if (cg_off(D.state)) return;
+  // a problem whose whole V-cycle runs here also makes the r.r test of the
+  // CG step before it
+  if (D.lc == 0 && finish_rr(D, first != 0, red)) return;
   const CoarseLevels &L = D.cl;
   const double *bin = D.lc == 0 ? D.cg_r : D.lev[D.lc].b;
   double *xout = D.lc == 0 ? D.cg_z : D.lev[D.lc].x;
   const double *Ainv = D.coarse_inv;
-  double *part = D.lc == 0 ? D.red : nullptr;
+  double *part = D.lc == 0 ? red_rz(D) : nullptr;
   const int tid = threadIdx.x, nt = blockDim.x;
   const int last = L.nlev - 1;
   const int n0 = L.nx[0] * L.ny[0];
@@ -698,10 +736,7 @@ __global__ void __launch_bounds__(1024) k_mg_coarse(const SynthDesc *ds, double 
       if (tid < h) red[tid] += red[tid + h];
       __syncthreads();
     }
-    if (tid == 0) {
-      part[0] = red[0];
-      finish_apply(D, S_RZ, first ? 0 : 2, red[0]);   // the whole V-cycle ran here
-    }
+    if (tid == 0) part[0] = red[0];   // single block: the partial is the full sum
   }
 }
 
@@ -801,16 +836,13 @@ __global__ void k_final_flux(int n, const double *Fx, const double *Fy, const do
 void vcycle(const SynthSet &S, bool first, hipStream_t s) {
   const SynthDesc *ds = S.desc;
   for (int l = 0; l < S.max_lc; ++l)
-    hipLaunchKernelGGL(k_mg_down, dim3(S.nb_tile[l]), dim3(kRedBlock), 0, s, ds, S.bt_tile[l], l);
+    hipLaunchKernelGGL(k_mg_down, dim3(S.nb_tile[l]), dim3(kRedBlock), 0, s, ds, S.bt_tile[l], l,
+                       first ? 1 : 0);
   hipLaunchKernelGGL(k_mg_coarse, dim3(S.n), dim3(1024), S.coarse_lds, s, ds, kOmega,
                      first ? 1 : 0);
   for (int l = S.max_lc - 1; l >= 0; --l)
     hipLaunchKernelGGL(k_mg_up, dim3(S.nb_tile[l]), dim3(kRedBlock), 0, s, ds, S.bt_tile[l], l,
                        l == 0 ? 1 : 0, first ? 1 : 0, kOmega);
-  // problems whose whole V-cycle ran in the coarse kernel were finished there
-  if (S.max_lc > 0)
-    hipLaunchKernelGGL(k_finish, dim3(S.n), dim3(kRedBlock), 0, s, ds, 2, (int)S_RZ,
-                       first ? 0 : 2);
 }
 
 }  // namespace
@@ -905,27 +937,39 @@ void launch_hot_rhs(const SynthSet &S, hipStream_t s) {
 // keeps enqueueing, since a converged solve turns the remaining kernels into
 // no-ops. With host_flag = NULL (graph capture, batches) the host never
 // waits and enqueues exactly S.synth_max_iter iterations.
+// CG on D1 phi' = b, preconditioned by one V-cycle per iteration. Every
+// reduction is finished inside the kernel that needs it (see red_pap).
+// With host_flag (a single problem), the host stops launching once the
+// solve has converged: it checks the device flags after the V-cycle of the
+// iteration at which the previous solve converged (host_flag[8] keeps that
+// count) and after every later one, so a steady run waits once per solve.
+// Without it (batches, graph capture) exactly synth_max_iter iterations are
+// launched and converged problems skip their kernels.
 void launch_synth_solve(const SynthSet &S, hipStream_t s, int32_t *host_flag) {
   const SynthDesc *ds = S.desc;
   const dim3 gc(S.nb_cell), bk(kRedBlock);
   hipLaunchKernelGGL(k_cg_begin, gc, bk, 0, s, ds, S.bt_cell);
-  hipLaunchKernelGGL(k_finish, dim3(S.n), bk, 0, s, ds, 1, (int)S_BB, 0);
-  hipLaunchKernelGGL(k_finish, dim3(S.n), bk, 0, s, ds, 0, (int)S_RR, 4);
   vcycle(S, true, s);
+  const int guess = host_flag ? host_flag[8] : 0;
   for (int it = 0; it < S.synth_max_iter; ++it) {
-    const int par = it & 1;
-    hipLaunchKernelGGL(k_cg_pAp, gc, bk, 0, s, ds, S.bt_cell, it == 0 ? 1 : 0, par);
-    hipLaunchKernelGGL(k_finish, dim3(S.n), bk, 0, s, ds, 0, (int)S_PAP, 1);
-    hipLaunchKernelGGL(k_cg_update, gc, bk, 0, s, ds, S.bt_cell, par);
-    hipLaunchKernelGGL(k_finish, dim3(S.n), bk, 0, s, ds, 0, (int)S_RR, 3);
-    if (it + 1 == S.synth_max_iter) break;
-    if (host_flag && S.state0 && it >= 3 && ((it - 3) & 1) == 0) {
+    hipLaunchKernelGGL(k_cg_pAp, gc, bk, 0, s, ds, S.bt_cell, it);
+    hipLaunchKernelGGL(k_cg_update, gc, bk, 0, s, ds, S.bt_cell, it);
+    if (it + 1 == S.synth_max_iter) {
+      hipLaunchKernelGGL(k_finish_rr, dim3(S.n), bk, 0, s, ds);
+      break;
+    }
+    vcycle(S, false, s);   // its first kernel makes the r.r test of this step
+    const bool due = guess > 0 ? it + 1 >= guess : (it >= 3 && ((it - 3) & 1) == 0);
+    if (host_flag && S.state0 && due) {
       (void)hipMemcpyAsync(host_flag, S.state0 + 1, 3 * sizeof(int32_t), hipMemcpyDeviceToHost,
                            s);
       (void)hipStreamSynchronize(s);
-      if (host_flag[0] != 0 || host_flag[2] != 0) return;
+      if (host_flag[0] != 0) return;
+      if (host_flag[2] != 0) {
+        host_flag[8] = it + 1;
+        return;
+      }
     }
-    vcycle(S, false, s);
   }
 }
 

@@ -24,6 +24,7 @@
 // sweep and moment operation runs in FP64.
 #include "gsis_internal.h"
 
+#include <algorithm>
 #include <cstring>
 
 namespace gsis {
@@ -50,6 +51,10 @@ struct TArgs {
   double *mom_part;
   const double *cellq, *dynq;
   double *rowbuf;
+  const double *sdq;
+  const int2 *rtiles;
+  int n_rtiles;
+  const int *dso;    // row-0 storage index per diagonal, at offset kDiagPad
   const int32_t *state;
 };
 
@@ -65,6 +70,8 @@ TArgs make_args(const PlanDev &P) {
   a.bnd = P.bnd; a.phih = P.phih; a.Fx = P.Fx; a.Fy = P.Fy; a.bflux = P.bflux;
   a.mom_part = P.mom_part;
   a.cellq = P.cellq; a.dynq = P.dynq; a.rowbuf = P.rowbuf;
+  a.sdq = P.sdq; a.rtiles = P.rtiles; a.n_rtiles = P.n_rtiles;
+  a.dso = P.dso;
   a.fp32 = P.precision == GSIS_FP32_MIXED ? 1 : 0;
   a.phi = P.phi;
   a.sw = P.sw; a.swm = P.swm; a.swe = P.swe;
@@ -506,6 +513,382 @@ __global__ void __launch_bounds__(MAXW * 64)
   }
 }
 
+// ---------------------------------------------------------------------------
+// Split transport step: a residual kernel with no dependence between cells,
+// then the first-order-upwind recurrence alone on the wavefront.
+//
+// With v = I^m + dI the increment solve (Eqs. RTE_d_increment..elem_mtx),
+//   dI = b + cx dI_W + cy dI_S,   b = r / d, cx = ax / d, cy = ay / d,
+// reads v = bv + cx v_W + cy v_S with bv = u + b - cx u_W - cy u_S
+// (u = I^m; the W or S term is absent on an inflow face, where dI = 0). The
+// residual kernel forms bv for every cell, all cells in parallel, and writes
+// it into the output buffer; the recurrence reads it back in place and leaves
+// I^{m+1/2} there. In FP32-mixed mode both work on deviations from
+// phi^m/(4 pi): bv = ut + b - cx ut_W - cy ut_S with ut = u - phi^m/(4 pi),
+// so the recurrence yields Itilde directly. bv is rounded to the storage type
+// once; everything else is FP64.
+// ---------------------------------------------------------------------------
+
+// Shifts across the whole 64-lane wave (DPP wave_shr:1 / wave_shl:1): lane i
+// gets lane i-1's (i+1's) value; lane 0 (63) keeps its own.
+__device__ inline double shr1(double v) {
+  int lo = __double2loint(v), hi = __double2hiint(v);
+  lo = __builtin_amdgcn_update_dpp(lo, lo, 0x138, 0xf, 0xf, false);
+  hi = __builtin_amdgcn_update_dpp(hi, hi, 0x138, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ inline double shl1(double v) {
+  int lo = __double2loint(v), hi = __double2hiint(v);
+  lo = __builtin_amdgcn_update_dpp(lo, lo, 0x130, 0xf, 0xf, false);
+  hi = __builtin_amdgcn_update_dpp(hi, hi, 0x130, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+// shr1 with lane 0 taking fill (its own lane's fill) instead
+__device__ inline double shr1_fill(double v, double fill) {
+  int lo = __double2loint(fill), hi = __double2hiint(fill);
+  lo = __builtin_amdgcn_update_dpp(lo, __double2loint(v), 0x138, 0xf, 0xf, false);
+  hi = __builtin_amdgcn_update_dpp(hi, __double2hiint(v), 0x138, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+// lane l's value, l wave-uniform
+__device__ inline double rdlane(double v, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+
+// Second-order values on a cell's local east and north faces, u + psi h with
+// the ALSM gradient (Eqs. shifted_j, LSF_mdf) and the Barth-Jespersen
+// limiter; a missing neighbour is passed as u.
+__device__ __forceinline__ void face_pair(double u, double UE, double UW, double UN, double US,
+                                          double2 c0, double2 c1, double hdx, double hdy,
+                                          bool second, bool lim, double &Fe, double &Fn) {
+  Fe = u;
+  Fn = u;
+  if (!second) return;
+  const double gx = c0.x * (UE - u) - c0.y * (UW - u);
+  const double gy = c1.x * (UN - u) - c1.y * (US - u);
+  const double hx = gx * hdx, hy = gy * hdy;
+  double psi = 1.0;
+  if (lim) {
+    const double umax = fmax(fmax(fmax(u, UE), fmax(UW, UN)), US);
+    const double umin = fmin(fmin(fmin(u, UE), fmin(UW, UN)), US);
+    const double m = fmin(umax - u, u - umin);
+    const double M = fmax(fabs(hx), fabs(hy));
+    const double pl = m * rcp64(M);           // discarded unless M > m
+    psi = M > m ? pl : 1.0;
+  }
+  Fe = fma(psi, hx, u);
+  Fn = fma(psi, hy, u);
+}
+
+// Raw buffer stores (gfx9 resource word 3 = 0x00020000): a store whose byte
+// offset lies outside the resource's range is dropped by the hardware, so a
+// lane with no cell issues the same instruction as the others and no branch
+// splits a step (the load/store counters then stay exact for the waits).
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+constexpr unsigned kNoCell = 0x7ffffff0u;     // beyond every resource's range
+__device__ inline __amdgpu_buffer_rsrc_t buf_rsrc(const void *p, size_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, (int)bytes, 0x00020000);
+}
+__device__ inline void buf_store(double v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)off, 0, 0);
+}
+__device__ inline void buf_store(float v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)off, 0, 0);
+}
+
+// Residual tiles: a band of 64 rows (one per lane) x kRD diagonals, walked a
+// diagonal per step after one warm-up step on the diagonal before the tile.
+constexpr int kRD = 31;
+constexpr int kRSteps = kRD + 1;
+constexpr int kRWaves = 4;           // waves per workgroup, one ordinate each
+constexpr int kRPF = 4;              // steps of loads in flight
+
+template <typename T>
+struct RSlot {
+  T ib;                // stored value at the lookahead cell (diagonal d+1)
+  double dq;           // base/(4 pi) there
+  double sube;         // FP32 mode: phi^m/(4 pi) there
+  double src;          // source at the cell (diagonal d)
+  double2 c0, c1, st;  // its coefficient record
+  int ic;              // its storage index
+};
+
+// One wave per (ordinate, tile). Lane l owns row y = y0 + l; at step dd its
+// cell is (d0 + dd - y, y). Each lane keeps u of its row on diagonals d-1,
+// d, d+1; u(x, y-1) and u(x, y+1) are the neighbour lanes' window values and
+// the south face value is lane l-1's F_n of the previous step (DPP shifts).
+// Row y0-1 below lane 0 and row y0+64 above lane 63 come from a halo pass in
+// which lane j holds diagonal d0-2+j (u below), d0-1+j (F_n below) and
+// d0+j (u above); lanes 0 and 63 read them with readlane. Every load is
+// issued for every lane (addresses of cells outside the grid are clamped
+// into it and the values dropped).
+template <typename T>
+__global__ void __launch_bounds__(kRWaves * 64) k_resid(TArgs a) {
+  if (a.state[1] != 0) return;
+  constexpr bool kF32 = sizeof(T) == 4;
+  constexpr int PF = kRPF;
+  static_assert(kRSteps % PF == 0, "whole turns of the load ring");
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform per wave
+  // workgroup b runs on XCD b % 8; each XCD takes a contiguous run of
+  // ordinate groups (quadrant-sorted) and walks the tiles for them
+  const int K = a.K, G = (K + kRWaves - 1) / kRWaves;
+  const int xc = blockIdx.x & 7, bi = blockIdx.x >> 3;
+  const int gcnt = (G - xc + 7) >> 3;
+  if (gcnt <= 0) return;
+  const int tile = bi / gcnt;
+  if (tile >= a.n_rtiles) return;
+  int gstart = 0;
+  for (int xp = 0; xp < xc; ++xp) gstart += (G - xp + 7) >> 3;
+  const int kk = (gstart + bi % gcnt) * kRWaves + wave;
+  if (kk >= K) return;
+  const int2 tl = a.rtiles[tile];
+  const int d0 = tl.x, y0 = tl.y;
+  const int nx = a.nx, ny = a.ny, N = a.N;
+  const int q = quadrant_of(a, kk);
+  const double ax = a.amu[kk], ay = a.aeta[kk];
+  const double hdx = 0.5 * a.dx, hdy = 0.5 * a.dy;
+  const bool second = a.order >= 2, lim = a.limiter != 0;
+  const T *Ik = Iin_of<T>(a) + (size_t)kk * N;
+  const __amdgpu_buffer_rsrc_t Ob = buf_rsrc(Iout_of<T>(a) + (size_t)kk * N, (size_t)N * sizeof(T));
+  const double2 *C2 = reinterpret_cast<const double2 *>(a.cellq + (size_t)q * N * 6);
+  const double *SRC = a.dynq + (size_t)q * 3 * N;
+  const double *DQ = SRC + N;
+  const double *SUB = SRC + 2 * N;
+  const int y = y0 + lane;
+  const bool rowok = y < ny, hn = y + 1 < ny, hs = y > 0;
+  auto cidx = [&](int x, int yy) {
+    x = min(max(x, 0), nx - 1);
+    yy = min(max(yy, 0), ny - 1);
+    return (int)dg_idx(x, yy, nx, ny);
+  };
+  auto uof = [&](int i) { return (double)Ik[i] + DQ[i]; };
+  // ---- halo: hu = u(d0-2+j, y0-1), hsb = phi^m/(4 pi) there (FP32 mode),
+  // hf = F_n(d0-1+j, y0-1) or, on the first band, the south inflow of
+  // column d0+j; hnv = u(d0+j, y0+64)
+  double hu = 0.0, hsb = 0.0, hf = 0.0, hnv = 0.0;
+  {
+    const int ys = y0 - 1;
+    const int xu = d0 - 2 + lane - ys, xf = d0 - 1 + lane - ys, xn = d0 + lane - (y0 + 64);
+    const int iu = cidx(xu, ys), jf = cidx(xf, ys);
+    const double vu = uof(iu), vf = uof(jf);
+    const double ve = uof(cidx(xf + 1, ys)), vw = uof(cidx(xf - 1, ys));
+    const double vn = uof(cidx(xf, y0)), vs = uof(cidx(xf, ys - 1));
+    const double2 f0 = C2[3 * jf], f1 = C2[3 * jf + 1];
+    const double vN = uof(cidx(xn, y0 + 64));
+    double su = 0.0;
+    if constexpr (kF32) su = SUB[iu];
+    const int xi = min(d0 + lane, nx - 1);
+    const int gi = (q & 1) ? nx - 1 - xi : xi;
+    const double vin = a.bnd[(size_t)((q & 2) ? 2 * ny + nx + gi : 2 * ny + gi) * a.K + kk];
+    double Fe, Fn;
+    face_pair(vf, xf + 1 < nx ? ve : vf, xf > 0 ? vw : vf, vn, ys > 0 ? vs : vf, f0, f1, hdx, hdy,
+              second, lim, Fe, Fn);
+    if (y0 > 0) {
+      if (lane <= kRD && xu >= 0 && xu < nx) { hu = vu; hsb = su; }
+      if (lane < kRD && xf >= 0 && xf < nx) hf = Fn;
+    } else if (lane < kRD && d0 + lane < nx) {
+      hf = vin;
+    }
+    if (y0 + 64 < ny && lane <= kRD && xn >= 0 && xn < nx) hnv = vN;
+  }
+  // inflow on the local west face of the lane's row
+  double inW;
+  {
+    const int yr = min(y, ny - 1);
+    const int j = (q & 2) ? ny - 1 - yr : yr;
+    inW = a.bnd[(size_t)((q & 1) ? ny + j : j) * a.K + kk];
+  }
+  // ---- window u(d0-2, y), u(d0-1, y); then the load ring from step -1.
+  // Indices of lanes outside the grid are clamped into the diagonal.
+  DiagCursor cur;
+  cur.init(nx, ny, d0 - 2);
+  double uc, ue, subc = 0.0, sube = 0.0;
+  {
+    const int i0 = cur.index(y);
+    uc = uof(i0);
+    if constexpr (kF32) subc = SUB[i0];
+    cur.advance();
+    const int i1 = cur.index(y);
+    ue = uof(i1);
+    if constexpr (kF32) sube = SUB[i1];
+  }
+  int inext = cur.index(y);                   // diagonal d0 - 1
+  auto load = [&](RSlot<T> &sl) {
+    sl.ic = inext;
+    cur.advance();
+    inext = cur.index(y);
+    sl.ib = Ik[inext];
+    sl.dq = DQ[inext];
+    if constexpr (kF32) sl.sube = SUB[inext];
+    sl.src = SRC[sl.ic];
+    sl.c0 = C2[3 * sl.ic];
+    sl.c1 = C2[3 * sl.ic + 1];
+    sl.st = C2[3 * sl.ic + 2];
+  };
+  RSlot<T> ring[PF];
+#pragma unroll
+  for (int t = 0; t < PF; ++t) load(ring[t]);
+  double uw = 0.0, subw = 0.0, Fe_p = 0.0, Fn_p = 0.0;
+  for (int sb = 0; sb < kRSteps; sb += PF) {
+#pragma unroll
+    for (int t = 0; t < PF; ++t) {
+      const int dd = sb + t - 1;              // diagonal d0 + dd
+      RSlot<T> &sl = ring[t];
+      uw = uc; uc = ue; ue = (double)sl.ib + sl.dq;
+      if constexpr (kF32) { subw = subc; subc = sube; sube = sl.sube; }
+      double uS = shr1(uw), uN = shl1(ue), FnS = shr1(Fn_p), sS = 0.0;
+      if constexpr (kF32) sS = shr1(subw);
+      {
+        const double hu_l = rdlane(hu, dd + 1), hf_l = rdlane(hf, dd < 0 ? 0 : dd);
+        const double hn_l = rdlane(hnv, dd + 1);
+        if (lane == 0) { uS = hu_l; FnS = hf_l; }
+        if (lane == 63) uN = hn_l;
+        if constexpr (kF32) {
+          const double hs_l = rdlane(hsb, dd + 1);
+          if (lane == 0) sS = hs_l;
+        }
+      }
+      const int x = d0 + dd - y;
+      const double UE = x + 1 < nx ? ue : uc, UW = x > 0 ? uw : uc;
+      const double UN = hn ? uN : uc, US = hs ? uS : uc;
+      double Fe, Fn;
+      face_pair(uc, UE, UW, UN, US, sl.c0, sl.c1, hdx, hdy, second, lim, Fe, Fn);
+      {
+        const bool ok = dd >= 0 && rowok && x >= 0 && x < nx;
+        const double FeW = x > 0 ? Fe_p : inW;
+        const double r = sl.src - sl.st.x * uc - ax * (Fe - FeW) - ay * (Fn - FnS);
+        const double inv = rcp64(sl.st.y + (ax + ay));   // as in the recurrence
+        double t0 = kF32 ? uc - subc : uc;
+        const double tw = fma(-(ax * inv), kF32 ? uw - subw : uw, t0);
+        t0 = x > 0 ? tw : t0;
+        const double ts = fma(-(ay * inv), kF32 ? uS - sS : uS, t0);
+        t0 = hs ? ts : t0;
+        buf_store((T)(t0 + r * inv), Ob, ok ? (unsigned)sl.ic * (unsigned)sizeof(T) : kNoCell);
+      }
+      Fe_p = Fe;
+      Fn_p = Fn;
+      load(sl);                               // past the tile: clamped, unused
+    }
+  }
+}
+
+// Recurrence v = bv + cx v_W + cy v_S for one ordinate per workgroup; lane t
+// of a pass owns row y0 + t and at step s handles column s - t (every step
+// one anti-diagonal). v_W is the lane's previous value, v_S lane t-1's (a DPP
+// shift). A lane's value stays 0 until its row starts, and lane 0 of the
+// bottom row gets 0 from below, so the inflow faces need no test: their
+// terms multiply 0. Across waves the waves run LAG steps apart: wave w does
+// step s at time s + w LAG and the workgroup meets at a barrier every LAG
+// times, so the top lane's values that wave w+1 needs were written at least
+// one barrier earlier; they pass through an LDS ring of 4 LAG steps and are
+// read once per LAG steps. With MULTI, rows beyond one pass are handed over
+// in rowbuf (alternate halves, so a pass never writes what it reads).
+constexpr int kCPF = 8;              // steps of loads in flight
+constexpr int kCLag = 8;
+constexpr int kCMaxW = 16;           // up to 1024 rows per pass
+
+// Loads use the index dso[d] + y of the lane's row on the step's diagonal
+// d: for a lane with no cell it points at another diagonal or out of the
+// buffer (the hardware returns 0 there), and the value is never used.
+template <typename T, bool MULTI>
+__global__ void __launch_bounds__(kCMaxW * 64) k_chain(TArgs a) {
+  if (a.state[1] != 0) return;
+  constexpr int PF = kCPF, LAG = kCLag, R = 4 * kCLag;
+  static_assert((R & (R - 1)) == 0 && LAG == PF, "ring sizes");
+  static_assert(kCMaxW * kCLag + 2 * kCPF <= kDiagPad, "diagonal table padding");
+  const int kk = xcd_ordinate(blockIdx.x, a.K);
+  const int q = quadrant_of(a, kk);
+  const int nx = a.nx, ny = a.ny, N = a.N;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform per wave
+  const int rows_pp = blockDim.x;
+  const double ax = a.amu[kk], ay = a.aeta[kk], axy = ax + ay;
+  const T *Ok = Iout_of<T>(a) + (size_t)kk * N;
+  const __amdgpu_buffer_rsrc_t Ob = buf_rsrc(Ok, (size_t)N * sizeof(T));
+  const __amdgpu_buffer_rsrc_t Sb = buf_rsrc(a.sdq + (size_t)q * N, (size_t)N * 8);
+  // read through the constant address space: wave-uniform reads of it are
+  // scalar loads and stay out of the vector memory counter
+  const __attribute__((address_space(4))) int *DS =
+      (const __attribute__((address_space(4))) int *)(a.dso + kDiagPad);
+  double *RB = a.rowbuf + (size_t)kk * 3 * nx;
+  __shared__ double edge[kCMaxW][R];
+  for (int y0 = 0, pass = 0; y0 < ny; y0 += rows_pp, ++pass) {
+    const int rows = min(rows_pp, ny - y0);
+    const int nw = (rows + 63) >> 6;
+    const int y = y0 + tid;
+    const bool rowok = tid < rows;
+    const int xo = rowok ? tid : (1 << 30);   // x = s - xo; rows past the grid never act
+    const bool handoff = MULTI && rowok && tid == rows - 1 && y0 + rows < ny;
+    const __amdgpu_buffer_rsrc_t RBr = buf_rsrc(RB + (pass & 1) * nx, (size_t)nx * 8);
+    const __amdgpu_buffer_rsrc_t RBw = buf_rsrc(RB + ((pass + 1) & 1) * nx, (size_t)nx * 8);
+    const int nsteps = nx + rows - 1;
+    const int tend = ((nsteps + (nw - 1) * LAG + LAG - 1) / LAG) * LAG;
+    const int s0 = -wave * LAG;               // this wave's step at time 0
+    // The ring is filled by a first block of steps before any lane's row
+    // starts (no lane acts there), so every block of the loop, the first
+    // included, runs the same code and the loads keep PF steps in flight.
+    T rb_b[PF] = {};
+    double rb_sd[PF] = {}, rb_v[PF] = {};
+    unsigned rb_i[PF] = {};
+    auto load = [&](int t, int so, int st) {  // step st, row-0 index so of its diagonal
+      const unsigned i = (unsigned)(so + y);
+      rb_i[t] = i;
+      if constexpr (sizeof(T) == 8)
+        rb_b[t] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(Ob, (int)(i * 8u), 0, 0));
+      else
+        rb_b[t] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(Ob, (int)(i * 4u), 0, 0));
+      rb_sd[t] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(Sb, (int)(i * 8u), 0, 0));
+      if constexpr (MULTI) {
+        // v below the first row of a later pass (column = step for lane 0)
+        const unsigned c = (unsigned)min(max(st, 0), nx - 1);
+        rb_v[t] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(RBr, (int)(c * 8u), 0, 0));
+      }
+    };
+    double vp = 0.0;
+    for (int tb = -LAG; tb < tend; tb += LAG) {
+      const int sb = tb + s0;                 // this wave's first step of the block
+      // v below lane 0 for the block's steps: the wave below's top lane
+      // (written at least one barrier ago), the previous pass, or 0
+      double bl[LAG];
+      if (wave > 0) {
+#pragma unroll
+        for (int t2 = 0; t2 < LAG; ++t2) bl[t2] = edge[wave - 1][(sb - 1 + t2) & (R - 1)];
+      } else {
+#pragma unroll
+        for (int t2 = 0; t2 < LAG; ++t2) bl[t2] = (MULTI && y0 > 0) ? rb_v[t2] : 0.0;
+      }
+      int so[LAG];                            // diagonals of the loads issued in this block
+#pragma unroll
+      for (int t2 = 0; t2 < LAG; ++t2) so[t2] = DS[y0 + sb + PF + t2];
+      double vv[LAG];
+#pragma unroll
+      for (int t2 = 0; t2 < LAG; ++t2) {
+        const int s = sb + t2;
+        const int x = s - xo;
+        const bool act = (unsigned)x < (unsigned)nx;
+        const double vS = shr1_fill(vp, bl[t2]);
+        const double inv = rcp64(rb_sd[t2] + axy);
+        const double vn = fma(ax * inv, vp, fma(ay * inv, vS, (double)rb_b[t2]));
+        const double v = act ? vn : vp;
+        buf_store((T)v, Ob, act ? rb_i[t2] * (unsigned)sizeof(T) : kNoCell);
+        if constexpr (MULTI) buf_store(v, RBw, handoff && act ? (unsigned)x * 8u : kNoCell);
+        vp = v;
+        vv[t2] = v;
+        load(t2, so[t2], s + PF);
+      }
+      // the top lane's values of the block, for the wave above
+      if (lane == 63) {
+#pragma unroll
+        for (int t2 = 0; t2 < LAG; ++t2) edge[wave][(sb + t2) & (R - 1)] = vv[t2];
+      }
+      __syncthreads();
+    }
+    __syncthreads();
+  }
+}
+
 __global__ void k_zero_int(int *p) { *p = 0; }
 
 // phi, F of I^{m+1/2} in two passes: per quadrant, one thread per stored
@@ -663,8 +1046,44 @@ void launch_transport(const PlanDev &P, hipStream_t s) {
     hipLaunchKernelGGL(k_sweep, dim3(P.K), dim3(rows), 0, s, a);
     return;
   }
-  if (a.fp32) launch_fused<float>(a, P, rows, s);
-  else launch_fused<double>(a, P, rows, s);
+  if (P.sweep_impl == 2) {
+    if (a.fp32) launch_fused<float>(a, P, rows, s);
+    else launch_fused<double>(a, P, rows, s);
+    return;
+  }
+  // residual kernel, then the recurrence in place
+  const int G = (P.K + kRWaves - 1) / kRWaves;
+  const int nb = 8 * ((G + 7) / 8) * P.n_rtiles;
+  if (a.fp32) {
+    hipLaunchKernelGGL(k_resid<float>, dim3(nb), dim3(kRWaves * 64), 0, s, a);
+    if (P.ny > rows) hipLaunchKernelGGL((k_chain<float, true>), dim3(P.K), dim3(rows), 0, s, a);
+    else hipLaunchKernelGGL((k_chain<float, false>), dim3(P.K), dim3(rows), 0, s, a);
+  } else {
+    hipLaunchKernelGGL(k_resid<double>, dim3(nb), dim3(kRWaves * 64), 0, s, a);
+    if (P.ny > rows) hipLaunchKernelGGL((k_chain<double, true>), dim3(P.K), dim3(rows), 0, s, a);
+    else hipLaunchKernelGGL((k_chain<double, false>), dim3(P.K), dim3(rows), 0, s, a);
+  }
+}
+
+std::vector<int> diag_row0_table(int nx, int ny) {
+  const int nd = nx + ny - 1;
+  std::vector<int> t((size_t)nd + 2 * kDiagPad);
+  for (int e = 0; e < (int)t.size(); ++e) {
+    const int d = e - kDiagPad;
+    if (d < 0) t[e] = -(1 << 28);
+    else if (d >= nd) t[e] = 1 << 28;
+    else t[e] = (int)(dg_off(d, nx, ny) - dg_ylo(d, nx));
+  }
+  return t;
+}
+
+std::vector<int2> residual_tiles(int nx, int ny) {
+  std::vector<int2> t;
+  for (int y0 = 0; y0 < ny; y0 += 64) {
+    const int y1 = std::min(y0 + 63, ny - 1);
+    for (int d0 = y0; d0 <= y1 + nx - 1; d0 += kRD) t.push_back(make_int2(d0, y0));
+  }
+  return t;
 }
 
 // ---- batched sweep

@@ -174,22 +174,24 @@ def test_invalid_arguments(ctx):
 
 
 @pytest.mark.parametrize("shape,quad", [((37, 70), None), ((256, 256), "c2"), ((5, 1300), None)])
-def test_fused_sweep_matches_reference_kernels(ctx, shape, quad, monkeypatch):
-    """The fused wavefront sweep and the two-kernel reference (residual
-    kernel + wavefront solve) give the same iterates."""
+def test_sweep_forms_agree(ctx, shape, quad, monkeypatch):
+    """The three transport-step implementations -- residual kernel plus
+    wavefront recurrence (default), fused wavefront sweep, and the plain
+    two-kernel reference -- give the same iterates."""
     if quad == "c2":
         p = inputs.thick_square(256)
     else:
         p = inputs.random_problem(shape[0], shape[1], seed=21, sigma_range=(0.05, 20.0))
     for method, tol in ((0, 1e-13), (1, 1e-10)):
         out = {}
-        for ref in ("0", "1"):
+        for ref in ("0", "1", "2"):
             monkeypatch.setenv("GSIS_SWEEP_REFERENCE", ref)
-            _say("fused vs reference %s method=%d sweep_reference=%s" % (shape, method, ref))
+            _say("sweep forms %s method=%d sweep_reference=%s" % (shape, method, ref))
             out[ref] = gsis.gsis_solve(ctx, p, method=method, tol=0.0, max_iter=3,
                                        synth_rtol=1e-15, synth_max_iter=200)
-        assert _rel(out["0"]["phi"], out["1"]["phi"]) < tol
-        assert _rel(out["0"]["Fx"], out["1"]["Fx"]) < 10 * tol
+        for other in ("1", "2"):
+            assert _rel(out["0"]["phi"], out[other]["phi"]) < tol, other
+            assert _rel(out["0"]["Fx"], out[other]["Fx"]) < 10 * tol, other
 
 
 @pytest.mark.parametrize("kw", [dict(method=0, limiter=1), dict(method=1, limiter=1),
