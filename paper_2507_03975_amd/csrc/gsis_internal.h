@@ -61,8 +61,10 @@ struct CoarseLevels {
   int nlev;
   int nx[kMaxCoarseLevels], ny[kMaxCoarseLevels], fx[kMaxCoarseLevels], fy[kMaxCoarseLevels];
   const double *dg[kMaxCoarseLevels], *ax[kMaxCoarseLevels], *ay[kMaxCoarseLevels];
-  int xoff[kMaxCoarseLevels];   // LDS offset of x_l (b_l follows, n_l later)
-  int aoff[kMaxCoarseLevels];   // LDS offset of (dg, ax, ay) of level l >= 1
+  // LDS offsets (doubles): level 0 holds x, r; a level t >= 1 holds x, b,
+  // r and its operator (1/diag, ax, ay, diag at aoff + 0, n, 2n, 3n)
+  int xoff[kMaxCoarseLevels], boff[kMaxCoarseLevels], roff[kMaxCoarseLevels];
+  int aoff[kMaxCoarseLevels];
 };
 struct LevelDev {
   int nx, ny, fx, fy;

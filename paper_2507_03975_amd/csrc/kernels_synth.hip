@@ -491,17 +491,48 @@ __global__ void __launch_bounds__(kRedBlock) k_mg_up(const SynthDesc *ds, const 
   (void)first;
 }
 
-// The coarse end of the V-cycle (every level with at most kCoarseWG cells,
-// down to the dense solve) in one workgroup of 1024 threads per problem, so
-// the half sweeps are separated by workgroup barriers instead of kernel
-// launches. The top coarse level keeps its operator in registers (at most 4
-// cells per thread), the lower levels in LDS; all vectors live in LDS.
+// The coarse end of the V-cycle (every level from the first with at most
+// kCoarseWG cells down to the dense solve) in one workgroup of 1024 threads
+// per problem, so the half sweeps are separated by workgroup barriers
+// instead of kernel launches.
+//  * Each half sweep runs over the cells of one colour only: thread t takes
+//    the colour's cells number t, t + 1024 (colour_cell), so no lane idles
+//    on a cell of the other colour. Diagonals are applied as precomputed
+//    reciprocals.
+//  * The top coarse level keeps its cells' operator rows and right-hand
+//    side in registers (at most 2 cells of each colour per thread); lower
+//    levels keep theirs in LDS. Vectors live in LDS.
+//  * After the second (black) half sweep from zero the black residuals
+//    vanish, so only red cells form a residual for the restriction.
+//  * Going up, the scaled coarse correction is added to every cell first;
+//    the black half sweep then sees corrected red neighbours and both
+//    colours are recomputed (black, then red), as in the tile kernels.
 constexpr int kCoarseWG = 4096;
+constexpr int kCoarseThreads = 1024;
 
-__global__ void __launch_bounds__(1024) k_mg_coarse(const SynthDesc *ds, double omega,
-                                                    int first) {
+// Cell number e of colour k ((i + j) & 1 == k) of an nx x ny grid, cells of
+// a colour numbered row by row. Rows come in pairs holding nx cells of each
+// colour. False past the last cell of the colour.
+__device__ inline bool colour_cell(int e, int k, int nx, int ny, int &i, int &j) {
+  int r, p;
+  cell_ij(e, nx, r, p);                     // e = p nx + r
+  const int c0 = (nx + 1 - k) >> 1;         // colour-k cells of the even row
+  if (r < c0) { j = 2 * p; i = k + 2 * r; }
+  else { j = 2 * p + 1; i = (1 - k) + 2 * (r - c0); }
+  return j < ny;
+}
+
+// One cell of the top coarse level held by a thread.
+struct OwnCell {
+  int c, cE, cW, cN, cS;       // index; neighbour indices (itself when missing)
+  bool ok;
+  double d, id, aE, aW, aN, aS, b;
+};
+
+__global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(const SynthDesc *ds, double omega,
+                                                              int first) {
   extern __shared__ double sm[];
-  __shared__ double red[1024];
+  __shared__ double red[kCoarseThreads];
   const SynthDesc &D = ds[blockIdx.x];
   if (cg_off(D.state)) return;
   // a problem whose whole V-cycle runs here also makes the r.r test of the
@@ -511,163 +542,189 @@ __global__ void __launch_bounds__(1024) k_mg_coarse(const SynthDesc *ds, double 
   const double *bin = D.lc == 0 ? D.cg_r : D.lev[D.lc].b;
   double *xout = D.lc == 0 ? D.cg_z : D.lev[D.lc].x;
   const double *Ainv = D.coarse_inv;
-  double *part = D.lc == 0 ? red_rz(D) : nullptr;
   const int tid = threadIdx.x, nt = blockDim.x;
   const int last = L.nlev - 1;
-  const int n0 = L.nx[0] * L.ny[0];
-  auto X = [&](int l) { return sm + L.xoff[l]; };
-  auto B = [&](int l) { return sm + L.xoff[l] + L.nx[l] * L.ny[l]; };
-  // level-0 operator in registers: cells tid + k * nt, k < 4
-  double rd[4], re[4], rw[4], rn[4], rs[4];
+  const int nx0 = L.nx[0], ny0 = L.ny[0];
+  auto X = [&](int t) { return sm + L.xoff[t]; };
+  auto Bv = [&](int t) { return sm + L.boff[t]; };
+  auto Rv = [&](int t) { return sm + L.roff[t]; };
+  // ---- top level: own cells (colour k, slot m) with their operator rows
+  OwnCell own[2][2];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int c = tid + k * nt;
-    rd[k] = 1.0; re[k] = rw[k] = rn[k] = rs[k] = 0.0;
-    if (c < n0) {
-      const int nx = L.nx[0];
-      int i, j;
-      cell_ij(c, nx, i, j);
-      rd[k] = L.dg[0][c];
-      if (i + 1 < nx) re[k] = L.ax[0][c];
-      if (i > 0) rw[k] = L.ax[0][c - 1];
-      if (j + 1 < L.ny[0]) rn[k] = L.ay[0][c];
-      if (j > 0) rs[k] = L.ay[0][c - nx];
+  for (int k = 0; k < 2; ++k)
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      OwnCell &o = own[k][m];
+      int i = 0, j = 0;
+      o.ok = colour_cell(tid + m * nt, k, nx0, ny0, i, j);
+      if (!o.ok) { i = 0; j = 0; }
+      const int c = j * nx0 + i;
+      const bool hE = o.ok && i + 1 < nx0, hW = o.ok && i > 0;
+      const bool hN = o.ok && j + 1 < ny0, hS = o.ok && j > 0;
+      o.c = c;
+      o.cE = hE ? c + 1 : c; o.cW = hW ? c - 1 : c;
+      o.cN = hN ? c + nx0 : c; o.cS = hS ? c - nx0 : c;
+      o.d = o.ok ? L.dg[0][c] : 1.0;
+      o.aE = hE ? L.ax[0][c] : 0.0; o.aW = hW ? L.ax[0][c - 1] : 0.0;
+      o.aN = hN ? L.ay[0][c] : 0.0; o.aS = hS ? L.ay[0][c - nx0] : 0.0;
+      o.b = o.ok ? bin[c] : 0.0;
     }
-    if (c < n0) B(0)[c] = bin[c];
-  }
+#pragma unroll
+  for (int k = 0; k < 2; ++k)
+#pragma unroll
+    for (int m = 0; m < 2; ++m) own[k][m].id = 1.0 / own[k][m].d;
   // the coarsest level's dense inverse (n <= 64) in registers
   const int nd = L.nx[last] * L.ny[last];
   double ainv[4];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int row = tid >> 4, col = (tid & 15) + 16 * k;
-    ainv[k] = (row < nd && col < nd) ? Ainv[(size_t)row * nd + col] : 0.0;
+  for (int q = 0; q < 4; ++q) {
+    const int row = tid >> 4, col = (tid & 15) + 16 * q;
+    ainv[q] = (row < nd && col < nd) ? Ainv[(size_t)row * nd + col] : 0.0;
   }
-  // lower levels' operators into LDS
-  for (int l = 1; l < L.nlev; ++l) {
-    const int n = L.nx[l] * L.ny[l];
-    double *a = sm + L.aoff[l];
+  // lower levels' operators into LDS (reciprocal diagonal, ax, ay, diagonal)
+  for (int t = 1; t < L.nlev; ++t) {
+    const int n = L.nx[t] * L.ny[t];
+    double *a = sm + L.aoff[t];
     for (int c = tid; c < n; c += nt) {
-      a[c] = L.dg[l][c]; a[n + c] = L.ax[l][c]; a[2 * n + c] = L.ay[l][c];
+      const double d = L.dg[t][c];
+      a[c] = 1.0 / d; a[n + c] = L.ax[t][c]; a[2 * n + c] = L.ay[t][c]; a[3 * n + c] = d;
     }
   }
-  __syncthreads();
-  // one red (0) or black (1) half sweep of level l; e: coarse correction of
-  // the neighbours (scaled by omega), zero: neighbours are zero
-  auto half = [&](int l, int color, bool zero, const double *e) {
-    const int nx = L.nx[l], ny = L.ny[l], n = nx * ny;
-    double *x = X(l);
-    const double *b = B(l);
-    const int cnx = e ? L.nx[l + 1] : 1, fx = L.fx[l], fy = L.fy[l];
-    auto V = [&](int ii, int jj) {
-      double v = x[jj * nx + ii];
-      if (e) v += omega * e[(jj >> (fy >> 1)) * cnx + (ii >> (fx >> 1))];
-      return v;
-    };
-    if (l == 0) {
+  // ---- top-level pieces
+  double *x0 = X(0), *r0 = Rv(0);
+  auto top_half = [&](int k, bool zero) {
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int c = tid + k * nt;
-        if (c < n) {
-          int i, j;
-  cell_ij(c, nx, i, j);
-          if (((i + j) & 1) == color) {
-            double s = b[c];
-            if (!zero) {
-              if (i + 1 < nx) s += re[k] * V(i + 1, j);
-              if (i > 0) s += rw[k] * V(i - 1, j);
-              if (j + 1 < ny) s += rn[k] * V(i, j + 1);
-              if (j > 0) s += rs[k] * V(i, j - 1);
-            }
-            x[c] = s / rd[k];
-          }
-        }
+    for (int m = 0; m < 2; ++m) {
+      const OwnCell &o = own[k][m];
+      if (!o.ok) continue;
+      double s = o.b;
+      if (!zero) {
+        s = fma(o.aE, x0[o.cE], s);
+        s = fma(o.aW, x0[o.cW], s);
+        s = fma(o.aN, x0[o.cN], s);
+        s = fma(o.aS, x0[o.cS], s);
       }
-    } else {
-      const double *dg = sm + L.aoff[l], *ax = dg + n, *ay = dg + 2 * n;
+      x0[o.c] = s * o.id;
+    }
+  };
+  // level t >= 1: half sweep of colour k over the colour's cells
+  auto low_half = [&](int t, int k, bool zero) {
+    const int nx = L.nx[t], ny = L.ny[t], n = nx * ny;
+    double *x = X(t);
+    const double *b = Bv(t), *id = sm + L.aoff[t], *ax = id + n, *ay = id + 2 * n;
+    for (int e = tid; 2 * e < n + 1; e += nt) {
+      int i, j;
+      if (!colour_cell(e, k, nx, ny, i, j)) break;
+      const int c = j * nx + i;
+      double s = b[c];
+      if (!zero) {
+        if (i + 1 < nx) s = fma(ax[c], x[c + 1], s);
+        if (i > 0) s = fma(ax[c - 1], x[c - 1], s);
+        if (j + 1 < ny) s = fma(ay[c], x[c + nx], s);
+        if (j > 0) s = fma(ay[c - nx], x[c - nx], s);
+      }
+      x[c] = s * id[c];
+    }
+  };
+  // restriction of level t's residuals r_t into b_{t+1}
+  auto restrict_to = [&](int t) {
+    const int nx = L.nx[t], ny = L.ny[t], fx = L.fx[t], fy = L.fy[t];
+    const int cnx = L.nx[t + 1], cn = cnx * L.ny[t + 1];
+    const double *r = Rv(t);
+    double *cb = Bv(t + 1);
+    for (int C = tid; C < cn; C += nt) {
+      int I, J;
+      cell_ij(C, cnx, I, J);
+      double v = 0.0;
+      for (int dj = 0; dj < fy; ++dj)
+        for (int di = 0; di < fx; ++di) {
+          const int i = fx * I + di, j = fy * J + dj;
+          if (i < nx && j < ny) v += r[j * nx + i];
+        }
+      cb[C] = v;
+    }
+  };
+  // x_t += omega e_{t+1}(parent) on every cell of level t >= 1
+  auto low_correct = [&](int t) {
+    const int nx = L.nx[t], n = nx * L.ny[t], sx = L.fx[t] >> 1, sy = L.fy[t] >> 1;
+    const int cnx = L.nx[t + 1];
+    double *x = X(t);
+    const double *e = X(t + 1);
+    for (int c = tid; c < n; c += nt) {
+      int i, j;
+      cell_ij(c, nx, i, j);
+      x[c] = fma(omega, e[(j >> sy) * cnx + (i >> sx)], x[c]);
+    }
+  };
+  __syncthreads();
+  if (last == 0) {
+    // the top level is the coarsest: dense solve only
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+        if (own[k][m].ok) r0[own[k][m].c] = own[k][m].b;
+    __syncthreads();
+  } else {
+    // ---- down: top level, red from zero, black, red residuals, restrict
+    top_half(0, true);
+    __syncthreads();
+    top_half(1, false);
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const OwnCell &o = own[0][m];
+      if (o.ok) {
+        double s = o.b;
+        s = fma(o.aE, x0[o.cE], s);
+        s = fma(o.aW, x0[o.cW], s);
+        s = fma(o.aN, x0[o.cN], s);
+        s = fma(o.aS, x0[o.cS], s);
+        r0[o.c] = fma(-o.d, x0[o.c], s);
+      }
+      if (own[1][m].ok) r0[own[1][m].c] = 0.0;
+    }
+    __syncthreads();
+    restrict_to(0);
+    __syncthreads();
+    // lower levels
+    for (int t = 1; t < last; ++t) {
+      const int nx = L.nx[t], ny = L.ny[t], n = nx * ny;
+      low_half(t, 0, true);
+      __syncthreads();
+      low_half(t, 1, false);
+      __syncthreads();
+      const double *x = X(t), *b = Bv(t), *id = sm + L.aoff[t], *ax = id + n, *ay = id + 2 * n;
+      const double *dg = id + 3 * n;
+      double *r = Rv(t);
       for (int c = tid; c < n; c += nt) {
         int i, j;
-  cell_ij(c, nx, i, j);
-        if (((i + j) & 1) != color) continue;
-        double s = b[c];
-        if (!zero) {
-          if (i + 1 < nx) s += ax[c] * V(i + 1, j);
-          if (i > 0) s += ax[c - 1] * V(i - 1, j);
-          if (j + 1 < ny) s += ay[c] * V(i, j + 1);
-          if (j > 0) s += ay[c - nx] * V(i, j - 1);
+        cell_ij(c, nx, i, j);
+        double v = 0.0;
+        if (((i + j) & 1) == 0) {
+          double s = b[c];
+          if (i + 1 < nx) s = fma(ax[c], x[c + 1], s);
+          if (i > 0) s = fma(ax[c - 1], x[c - 1], s);
+          if (j + 1 < ny) s = fma(ay[c], x[c + nx], s);
+          if (j > 0) s = fma(ay[c - nx], x[c - nx], s);
+          v = fma(-dg[c], x[c], s);
         }
-        x[c] = s / dg[c];
+        r[c] = v;
       }
+      __syncthreads();
+      restrict_to(t);
+      __syncthreads();
     }
-    __syncthreads();
-  };
-  // residual of level l at cell c (operator from registers or LDS)
-  auto resid = [&](int l, int c) {
-    const int nx = L.nx[l], ny = L.ny[l], n = nx * ny;
-    int i, j;
-    cell_ij(c, nx, i, j);
-    const double *x = X(l);
-    double d, e_, w_, n_, s_;
-    if (l == 0) {
-      const int k = (c - tid) / nt;   // only called with c = tid + k * nt
-      d = rd[k]; e_ = re[k]; w_ = rw[k]; n_ = rn[k]; s_ = rs[k];
-    } else {
-      const double *dg = sm + L.aoff[l], *ax = dg + n, *ay = dg + 2 * n;
-      d = dg[c];
-      e_ = i + 1 < nx ? ax[c] : 0.0; w_ = i > 0 ? ax[c - 1] : 0.0;
-      n_ = j + 1 < ny ? ay[c] : 0.0; s_ = j > 0 ? ay[c - nx] : 0.0;
-    }
-    double y = d * x[c];
-    if (i + 1 < nx) y -= e_ * x[c + 1];
-    if (i > 0) y -= w_ * x[c - 1];
-    if (j + 1 < ny) y -= n_ * x[c + nx];
-    if (j > 0) y -= s_ * x[c - nx];
-    return B(l)[c] - y;
-  };
-  // down: pre-smooth, residual, restriction (the residual goes to LDS
-  // scratch first: level l's b is reused for it once x is final)
-  for (int l = 0; l < last; ++l) {
-    half(l, 0, true, nullptr);
-    half(l, 1, false, nullptr);
-    // residuals (at most 4 cells per thread) into b_l
-    const int n = L.nx[l] * L.ny[l];
-    double rr[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int c = tid + k * nt;
-      rr[k] = c < n ? resid(l, c) : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int c = tid + k * nt;
-      if (c < n) B(l)[c] = rr[k];
-    }
-    __syncthreads();
-    const int nx = L.nx[l], ny = L.ny[l], cnx = L.nx[l + 1], cny = L.ny[l + 1];
-    for (int C = tid; C < cnx * cny; C += nt) {
-      int I, J;
-  cell_ij(C, cnx, I, J);
-      double s = 0.0;
-      for (int dj = 0; dj < L.fy[l]; ++dj)
-        for (int di = 0; di < L.fx[l]; ++di) {
-          const int i = L.fx[l] * I + di, j = L.fy[l] * J + dj;
-          if (i < nx && j < ny) s += B(l)[j * nx + i];
-        }
-      B(l + 1)[C] = s;
-    }
-    __syncthreads();
   }
-  // dense solve on the coarsest level (n <= 64): 16 threads per row, the
-  // inverse preloaded in registers
+  // ---- dense solve on the coarsest level: 16 threads per row
   {
-    const double *b = B(last);
+    const double *b = last == 0 ? r0 : Bv(last);
     const int row = tid >> 4, col0 = tid & 15;
     double v = 0.0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int col = col0 + 16 * k;
-      if (row < nd && col < nd) v += ainv[k] * b[col];
+    for (int q = 0; q < 4; ++q) {
+      const int col = col0 + 16 * q;
+      if (row < nd && col < nd) v += ainv[q] * b[col];
     }
     v += __shfl_xor(v, 8, 64);
     v += __shfl_xor(v, 4, 64);
@@ -676,67 +733,52 @@ __global__ void __launch_bounds__(1024) k_mg_coarse(const SynthDesc *ds, double 
     if (col0 == 0 && row < nd) X(last)[row] = v;
     __syncthreads();
   }
-  // up: the restriction overwrote b_l with the residual, so the post
-  // smoothing needs the original right-hand side back: the top level reloads
-  // it from global memory, lower levels restore it from their residual and
-  // pre-smoothed x (b = r + A x).
-  for (int l = last - 1; l >= 0; --l) {
-    if (l == 0) {
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int c = tid + k * nt;
-        if (c < n0) B(0)[c] = bin[c];
-      }
-    } else {
-      // b = r + A x with the pre-smoothed x (unchanged since the residual)
-      const int n = L.nx[l] * L.ny[l], nx = L.nx[l], ny = L.ny[l];
-      const double *dg = sm + L.aoff[l], *ax = dg + n, *ay = dg + 2 * n;
-      const double *x = X(l);
-      double bv[4];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int c = tid + k * nt;
-        bv[k] = 0.0;
-        if (c < n) {
-          int i, j;
-  cell_ij(c, nx, i, j);
-          double y = dg[c] * x[c];
-          if (i + 1 < nx) y -= ax[c] * x[c + 1];
-          if (i > 0) y -= ax[c - 1] * x[c - 1];
-          if (j + 1 < ny) y -= ay[c] * x[c + nx];
-          if (j > 0) y -= ay[c - nx] * x[c - nx];
-          bv[k] = B(l)[c] + y;
-        }
-      }
+  // ---- up: lower levels, then the top level
+  if (last > 0) {
+    for (int t = last - 1; t >= 1; --t) {
+      low_correct(t);
       __syncthreads();
+      low_half(t, 1, false);
+      __syncthreads();
+      low_half(t, 0, false);
+      __syncthreads();
+    }
+    {
+      const int sx = L.fx[0] >> 1, sy = L.fy[0] >> 1, cnx = L.nx[1];
+      const double *e = X(1);
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int c = tid + k * nt;
-        if (c < n) B(l)[c] = bv[k];
-      }
+      for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+          const OwnCell &o = own[k][m];
+          if (!o.ok) continue;
+          int i, j;
+          cell_ij(o.c, nx0, i, j);
+          x0[o.c] = fma(omega, e[(j >> sy) * cnx + (i >> sx)], x0[o.c]);
+        }
     }
     __syncthreads();
-    half(l, 1, false, X(l + 1));
-    half(l, 0, false, nullptr);
+    top_half(1, false);
+    __syncthreads();
+    top_half(0, false);
+    __syncthreads();
   }
+  // ---- out: x of the top level; r.z when the whole V-cycle ran here
   double v = 0.0;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int c = tid + k * nt;
-    if (c < n0) {
-      xout[c] = X(0)[c];
-      if (part) v += bin[c] * X(0)[c];
+  for (int k = 0; k < 2; ++k)
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const OwnCell &o = own[k][m];
+      if (!o.ok) continue;
+      const double xv = x0[o.c];
+      xout[o.c] = xv;
+      v = fma(o.b, xv, v);
     }
-  }
-  if (part) {
-    // single block: the r.z partial is the full sum
-    red[tid] = v;
-    __syncthreads();
-    for (int h = nt / 2; h > 0; h >>= 1) {
-      if (tid < h) red[tid] += red[tid + h];
-      __syncthreads();
-    }
-    if (tid == 0) part[0] = red[0];   // single block: the partial is the full sum
+  if (D.lc == 0) {
+    // single block: the r.z partial is the whole sum
+    const double t = block_sum(v, red);
+    if (tid == 0) red_rz(D)[0] = t;
   }
 }
 
@@ -838,7 +880,7 @@ void vcycle(const SynthSet &S, bool first, hipStream_t s) {
   for (int l = 0; l < S.max_lc; ++l)
     hipLaunchKernelGGL(k_mg_down, dim3(S.nb_tile[l]), dim3(kRedBlock), 0, s, ds, S.bt_tile[l], l,
                        first ? 1 : 0);
-  hipLaunchKernelGGL(k_mg_coarse, dim3(S.n), dim3(1024), S.coarse_lds, s, ds, kOmega,
+  hipLaunchKernelGGL(k_mg_coarse, dim3(S.n), dim3(kCoarseThreads), S.coarse_lds, s, ds, kOmega,
                      first ? 1 : 0);
   for (int l = S.max_lc - 1; l >= 0; --l)
     hipLaunchKernelGGL(k_mg_up, dim3(S.nb_tile[l]), dim3(kRedBlock), 0, s, ds, S.bt_tile[l], l,
@@ -851,7 +893,7 @@ void vcycle(const SynthSet &S, bool first, hipStream_t s) {
 size_t coarse_lds_bytes_from(const PlanDev &P, size_t lc) {
   size_t n = 0;
   for (size_t l = lc; l < P.mg.size(); ++l)
-    n += (l == lc ? 2 : 5) * (size_t)P.mg[l].nx * P.mg[l].ny;
+    n += (l == lc ? 2 : 7) * (size_t)P.mg[l].nx * P.mg[l].ny;
   return n * sizeof(double);
 }
 
@@ -912,9 +954,17 @@ SynthDesc make_synth_desc(const PlanDev &P) {
     CL.nx[t] = L.nx; CL.ny[t] = L.ny; CL.fx[t] = L.fx; CL.fy[t] = L.fy;
     CL.dg[t] = L.diag; CL.ax[t] = L.ax; CL.ay[t] = L.ay;
     CL.xoff[t] = off;
-    off += 2 * n;
+    off += n;
+    if (t == 0) {
+      CL.boff[t] = 0;           // the top level's b stays in registers
+    } else {
+      CL.boff[t] = off;
+      off += n;
+    }
+    CL.roff[t] = off;
+    off += n;
     CL.aoff[t] = t == 0 ? 0 : off;
-    if (t > 0) off += 3 * n;
+    if (t > 0) off += 4 * n;
   }
   D.coarse_inv = P.coarse_inv;
   return D;
