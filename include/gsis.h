@@ -164,12 +164,15 @@ gsis_status gsis_plan_read(gsis_plan *plan, gsis_result *r);
 gsis_status gsis_plan_reset(gsis_plan *plan);
 
 enum {
-  GSIS_PHASE_SWEEP = 0,    /* transport residual + exact sweep (one kernel) */
-  GSIS_PHASE_MOMENTS = 1,  /* phi and F of the swept intensity */
-  GSIS_PHASE_HOT = 2,      /* boundary fluxes, HoT, synthetic right-hand side */
-  GSIS_PHASE_SYNTH = 3,    /* synthetic CG + multigrid solve */
-  GSIS_PHASE_UPDATE = 4,   /* correction and Err */
-  GSIS_NUM_PHASES = 5
+  GSIS_PHASE_RESIDUAL = 0, /* transport residual of every cell-ordinate (Eq. RTE_d_res),
+                              written as the recurrence's right-hand side */
+  GSIS_PHASE_SWEEP = 1,    /* exact first-order-upwind increment solve on the
+                              wavefront (Eqs. RTE_d_increment..elem_mtx) */
+  GSIS_PHASE_MOMENTS = 2,  /* phi and F of the swept intensity */
+  GSIS_PHASE_HOT = 3,      /* boundary fluxes, HoT, synthetic right-hand side */
+  GSIS_PHASE_SYNTH = 4,    /* synthetic CG + multigrid solve */
+  GSIS_PHASE_UPDATE = 5,   /* correction and Err */
+  GSIS_NUM_PHASES = 6
 };
 /* Wait for the plan's stream; ms[GSIS_NUM_PHASES] receives the summed
  * duration of each phase over all profiled iterations (HIP events on the

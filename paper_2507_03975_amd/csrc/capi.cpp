@@ -651,19 +651,21 @@ extern "C" gsis_status gsis_plan_iterate(gsis_plan *pl, int32_t n) {
   for (int it = 0; it < n; ++it) {
     if (pl->profile && pl->prof_iters >= 100000) pl->profile = 0;
     if ((st = record(pl, 0))) return st;
-    launch_transport(P, s);
+    launch_residual(P, s);
     if ((st = record(pl, 1))) return st;
-    launch_moments(P, s);
+    launch_sweep(P, s);
     if ((st = record(pl, 2))) return st;
+    launch_moments(P, s);
+    if ((st = record(pl, 3))) return st;
     if (P.method == GSIS_GSIS) {
       launch_boundary_flux(P, s);
       launch_hot_rhs(P.S, s);
     }
-    if ((st = record(pl, 3))) return st;
-    if (P.method == GSIS_GSIS) launch_synth_solve(P.S, s, (int32_t *)pl->host_scal);
     if ((st = record(pl, 4))) return st;
-    launch_update(P.S, s);
+    if (P.method == GSIS_GSIS) launch_synth_solve(P.S, s, (int32_t *)pl->host_scal);
     if ((st = record(pl, 5))) return st;
+    launch_update(P.S, s);
+    if ((st = record(pl, 6))) return st;
     HIPCHK(ctx, hipGetLastError());
     if (pl->profile) pl->prof_iters++;
   }

@@ -170,7 +170,10 @@ struct PlanDev {
 };
 
 // ---- transport kernels (kernels_transport.hip)
-void launch_transport(const PlanDev &P, hipStream_t s);   // residual + sweep
+// Transport step: residual of every cell-ordinate, then the wavefront
+// increment solve (for the fused kernel the residual launch is empty).
+void launch_residual(const PlanDev &P, hipStream_t s);
+void launch_sweep(const PlanDev &P, hipStream_t s);
 // Tiles of the residual kernel for an nx x ny grid: (first diagonal, first
 // row) of each band of rows x run of diagonals that holds a cell.
 std::vector<int2> residual_tiles(int nx, int ny);

@@ -51,18 +51,33 @@ __device__ inline void cell_ij(int c, int nx, int &i, int &j) {
   i = r; j = q;
 }
 
+// Problem descriptors and block tables are read through the constant
+// address space: they do not change while a kernel runs, so their
+// (wave-uniform) fields become scalar loads served by the scalar cache
+// rather than vector loads, each of which would cost a memory round trip.
+typedef __attribute__((address_space(4))) const SynthDesc CDesc;
+__device__ inline CDesc &cdesc(const SynthDesc *ds, int p) { return ((CDesc *)ds)[p]; }
+// a level's record copied out of a descriptor field by field
+__device__ inline LevelDev level(CDesc &D, int l) {
+  __attribute__((address_space(4))) const LevelDev &s = D.lev[l];
+  LevelDev L;
+  L.nx = s.nx; L.ny = s.ny; L.fx = s.fx; L.fy = s.fy;
+  L.dg = s.dg; L.ax = s.ax; L.ay = s.ay; L.x = s.x; L.b = s.b; L.xs = s.xs;
+  return L;
+}
+
 // The block's problem and its block index within that problem.
 struct Blk { int p, lb; };
 __device__ inline Blk blk(const int2 *bt) {
   if (!bt) return {0, (int)blockIdx.x};
-  const int2 v = bt[blockIdx.x];
-  return {v.x, v.y};
+  const __attribute__((address_space(4))) int *q = (const __attribute__((address_space(4))) int *)bt;
+  return {q[2 * blockIdx.x], q[2 * blockIdx.x + 1]};
 }
 
 // ---------------------------------------------------------------- HoT / RHS
 __global__ void k_hot(const SynthDesc *ds, const int2 *bt) {
   const Blk B = blk(bt);
-  const SynthDesc &D = ds[B.p];
+  CDesc &D = cdesc(ds, B.p);
   if (D.state[1] != 0) return;
   const int nx = D.nx, ny = D.ny;
   const int c = B.lb * kRedBlock + threadIdx.x;
@@ -81,7 +96,7 @@ __global__ void k_hot(const SynthDesc *ds, const int2 *bt) {
 
 __global__ void k_rhs(const SynthDesc *ds, const int2 *bt) {
   const Blk B = blk(bt);
-  const SynthDesc &D = ds[B.p];
+  CDesc &D = cdesc(ds, B.p);
   if (D.state[1] != 0) return;
   const int nx = D.nx, ny = D.ny;
   const int c = B.lb * kRedBlock + threadIdx.x;
@@ -141,11 +156,11 @@ __host__ __device__ inline int nblk_d(int n) { return (n + kRedBlock - 1) / kRed
 // per reduction (folding the finish into the producing kernel instead would
 // need a device-scope release per block, which on a GPU whose XCDs each
 // have their own L2 writes back the L2 every time).
-__device__ inline double *red_pap(const SynthDesc &D) { return D.red; }
-__device__ inline double *red_rr(const SynthDesc &D) { return D.red + nblk_d(D.N); }
-__device__ inline double *red_bb(const SynthDesc &D) { return D.red + 2 * nblk_d(D.N); }
-__device__ inline double *red_rz(const SynthDesc &D) { return D.red + 3 * nblk_d(D.N); }
-__device__ inline int n_rz(const SynthDesc &D) { return D.lc == 0 ? 1 : D.ntile0; }
+__device__ inline double *red_pap(CDesc &D) { return D.red; }
+__device__ inline double *red_rr(CDesc &D) { return D.red + nblk_d(D.N); }
+__device__ inline double *red_bb(CDesc &D) { return D.red + 2 * nblk_d(D.N); }
+__device__ inline double *red_rz(CDesc &D) { return D.red + 3 * nblk_d(D.N); }
+__device__ inline int n_rz(CDesc &D) { return D.lc == 0 ? 1 : D.ntile0; }
 
 __device__ inline double sum_partials(const double *p, int n, double *sh) {
   double v = 0.0;
@@ -157,7 +172,7 @@ __device__ inline double sum_partials(const double *p, int n, double *sh) {
 // against STOP; first (after the warm start): also b.b, the count reset and
 // STOP = max(rtol^2 r0.r0, 1e-28 b.b). Every thread of the block returns
 // the same decision; thread 0 stores the scalars and the flag.
-__device__ inline bool finish_rr(const SynthDesc &D, bool first, double *sh) {
+__device__ inline bool finish_rr(CDesc &D, bool first, double *sh) {
   const int nb = nblk_d(D.N);
   const double rr = sum_partials(red_rr(D), nb, sh);
   double stop;
@@ -188,7 +203,7 @@ __device__ inline bool finish_rr(const SynthDesc &D, bool first, double *sh) {
 // solve (one workgroup per problem).
 __global__ void k_finish_rr(const SynthDesc *ds) {
   __shared__ double sh[kRedBlock];
-  const SynthDesc &D = ds[blockIdx.x];
+  CDesc &D = cdesc(ds, blockIdx.x);
   if (cg_off(D.state)) return;
   (void)finish_rr(D, false, sh);
 }
@@ -198,10 +213,10 @@ __global__ void k_finish_rr(const SynthDesc *ds) {
 __global__ void k_cg_begin(const SynthDesc *ds, const int2 *bt) {
   __shared__ double sh[kRedBlock];
   const Blk B = blk(bt);
-  const SynthDesc &D = ds[B.p];
+  CDesc &D = cdesc(ds, B.p);
   if (D.state[1] != 0) return;
   const int c = B.lb * kRedBlock + threadIdx.x;
-  const LevelDev &L = D.lev[0];
+  const LevelDev L = level(D, 0);
   double rr = 0.0, bb = 0.0;
   if (c < D.N) {
     // x = phi for the cell and its neighbours (this kernel writes x)
@@ -235,7 +250,7 @@ __global__ void k_cg_begin(const SynthDesc *ds, const int2 *bt) {
 __global__ void k_cg_pAp(const SynthDesc *ds, const int2 *bt, int it) {
   __shared__ double sh[kRedBlock];
   const Blk B = blk(bt);
-  const SynthDesc &D = ds[B.p];
+  CDesc &D = cdesc(ds, B.p);
   if (cg_off(D.state)) return;
   const bool first = it == 0;
   const int par = it & 1;
@@ -246,7 +261,7 @@ __global__ void k_cg_pAp(const SynthDesc *ds, const int2 *bt, int it) {
     D.scal[S_BETA] = be;
   }
   const int c = B.lb * kRedBlock + threadIdx.x;
-  const LevelDev &L = D.lev[0];
+  const LevelDev L = level(D, 0);
   const int nx = L.nx, ny = L.ny;
   const double *z = D.cg_z;
   const double *pold = par ? D.cg_p1 : D.cg_p0;
@@ -275,7 +290,7 @@ __global__ void k_cg_pAp(const SynthDesc *ds, const int2 *bt, int it) {
 __global__ void k_cg_update(const SynthDesc *ds, const int2 *bt, int it) {
   __shared__ double sh[kRedBlock];
   const Blk B = blk(bt);
-  const SynthDesc &D = ds[B.p];
+  CDesc &D = cdesc(ds, B.p);
   if (cg_off(D.state)) return;
   const double pap = sum_partials(red_pap(D), nblk_d(D.N), sh);
   const double al = D.scal[rz_slot(it)] / pap;
@@ -298,8 +313,8 @@ __global__ void k_cg_update(const SynthDesc *ds, const int2 *bt, int it) {
 
 // ------------------------------------------------------------ multigrid
 // Level l of a problem: vectors x, b are the CG's z, r on level 0.
-__device__ inline double *lev_x(const SynthDesc &D, int l) { return l == 0 ? D.cg_z : D.lev[l].x; }
-__device__ inline const double *lev_b(const SynthDesc &D, int l) {
+__device__ inline double *lev_x(CDesc &D, int l) { return l == 0 ? D.cg_z : D.lev[l].x; }
+__device__ inline const double *lev_b(CDesc &D, int l) {
   return l == 0 ? D.cg_r : D.lev[l].b;
 }
 
@@ -360,12 +375,12 @@ __global__ void __launch_bounds__(kRedBlock) k_mg_down(const SynthDesc *ds, cons
   __shared__ double sb[kRN], sd[kRN], sax[kRN], say[kRN], sx[kRN];
   static_assert(kRN >= kRedBlock, "sb doubles as reduction scratch");
   const Blk B = blk(bt);
-  const SynthDesc &D = ds[B.p];
+  CDesc &D = cdesc(ds, B.p);
   if (cg_off(D.state)) return;
   // the r.r test of the CG step before this V-cycle (the other blocks go on:
   // if it converged, their results are not used)
   if (l == 0 && B.lb == 0) (void)finish_rr(D, first != 0, sb);
-  const LevelDev &L = D.lev[l], &CL = D.lev[l + 1];
+  const LevelDev L = level(D, l), CL = level(D, l + 1);
   const double *b = lev_b(D, l);
   double *xs = L.xs;
   const Tile T = tile_of(L, B.lb);
@@ -430,9 +445,9 @@ __global__ void __launch_bounds__(kRedBlock) k_mg_up(const SynthDesc *ds, const 
                                                      int rz, int first, double omega) {
   __shared__ double sb[kRN], sd[kRN], sax[kRN], say[kRN], sx[kRN], sh[kRedBlock];
   const Blk B = blk(bt);
-  const SynthDesc &D = ds[B.p];
+  CDesc &D = cdesc(ds, B.p);
   if (cg_off(D.state)) return;
-  const LevelDev &L = D.lev[l], &CL = D.lev[l + 1];
+  const LevelDev L = level(D, l), CL = level(D, l + 1);
   const double *b = lev_b(D, l);
   double *x = lev_x(D, l);
   const double *xs = L.xs;
@@ -533,12 +548,12 @@ __global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(const SynthDesc *d
                                                               int first) {
   extern __shared__ double sm[];
   __shared__ double red[kCoarseThreads];
-  const SynthDesc &D = ds[blockIdx.x];
+  CDesc &D = cdesc(ds, blockIdx.x);
   if (cg_off(D.state)) return;
   // a problem whose whole V-cycle runs here also makes the r.r test of the
   // CG step before it
   if (D.lc == 0 && finish_rr(D, first != 0, red)) return;
-  const CoarseLevels &L = D.cl;
+  __attribute__((address_space(4))) const CoarseLevels &L = D.cl;
   const double *bin = D.lc == 0 ? D.cg_r : D.lev[D.lc].b;
   double *xout = D.lc == 0 ? D.cg_z : D.lev[D.lc].x;
   const double *Ainv = D.coarse_inv;
@@ -791,7 +806,7 @@ constexpr double kOmega = 1.7;   // coarse-grid correction scaling (aggregation 
 __global__ void k_update(const SynthDesc *ds, const int2 *bt) {
   __shared__ double sh[kRedBlock];
   const Blk B = blk(bt);
-  const SynthDesc &D = ds[B.p];
+  CDesc &D = cdesc(ds, B.p);
   if (D.state[1] != 0) return;
   const int c = B.lb * kRedBlock + threadIdx.x;
   double num = 0.0, den = 0.0;
@@ -814,7 +829,7 @@ __global__ void k_update(const SynthDesc *ds, const int2 *bt) {
 // flag.
 __global__ void k_err_finish(const SynthDesc *ds) {
   __shared__ double sh[kRedBlock];
-  const SynthDesc &D = ds[blockIdx.x];
+  CDesc &D = cdesc(ds, blockIdx.x);
   int32_t *state = D.state;
   if (state[1] != 0) return;
   const int npart = nblk_d(D.N);
@@ -842,7 +857,7 @@ __global__ void k_err_finish(const SynthDesc *ds) {
 // (src, base/(4 pi), phi/(4 pi)) read by the fused sweep.
 __global__ void k_source(const SynthDesc *ds, const int2 *bt) {
   const Blk B = blk(bt);
-  const SynthDesc &D = ds[B.p];
+  CDesc &D = cdesc(ds, B.p);
   if (D.state[1] != 0) return;
   const int nx = D.nx, ny = D.ny, n = D.N;
   const int c = B.lb * kRedBlock + threadIdx.x;

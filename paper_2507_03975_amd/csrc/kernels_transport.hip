@@ -1035,31 +1035,45 @@ void launch_fused(const TArgs &a, const PlanDev &P, int rows, hipStream_t s) {
     hipLaunchKernelGGL((k_sweep_fused<2, 16, false, T>), dim3(P.K), dim3(rows), 0, s, a);
 }
 
-void launch_transport(const PlanDev &P, hipStream_t s) {
-  TArgs a = make_args(P);
-  int rows = ((P.ny + 63) / 64) * 64;
-  if (rows > 1024) rows = 1024;
-  if (P.sweep_impl == 1 && !a.fp32) {
-    // two-kernel reference: residual into R, then the wavefront solve
-    dim3 g((P.N + 255) / 256, P.K);
-    hipLaunchKernelGGL(k_residual, g, dim3(256), 0, s, a);
-    hipLaunchKernelGGL(k_sweep, dim3(P.K), dim3(rows), 0, s, a);
+namespace {
+int sweep_rows(const PlanDev &P) {
+  const int rows = ((P.ny + 63) / 64) * 64;
+  return rows > 1024 ? 1024 : rows;
+}
+}  // namespace
+
+// sweep_impl 0: residual kernel, then the recurrence in place; 1: plain
+// two-kernel reference (FP64 only; FP32 falls back to the fused kernel);
+// 2: fused wavefront sweep (nothing in the residual phase).
+void launch_residual(const PlanDev &P, hipStream_t s) {
+  const TArgs a = make_args(P);
+  if (P.sweep_impl == 2 || (P.sweep_impl == 1 && a.fp32)) return;
+  if (P.sweep_impl == 1) {
+    hipLaunchKernelGGL(k_residual, dim3((P.N + 255) / 256, P.K), dim3(256), 0, s, a);
     return;
   }
-  if (P.sweep_impl == 2) {
+  const int G = (P.K + kRWaves - 1) / kRWaves;
+  const int nb = 8 * ((G + 7) / 8) * P.n_rtiles;
+  if (a.fp32) hipLaunchKernelGGL(k_resid<float>, dim3(nb), dim3(kRWaves * 64), 0, s, a);
+  else hipLaunchKernelGGL(k_resid<double>, dim3(nb), dim3(kRWaves * 64), 0, s, a);
+}
+
+void launch_sweep(const PlanDev &P, hipStream_t s) {
+  const TArgs a = make_args(P);
+  const int rows = sweep_rows(P);
+  if (P.sweep_impl == 2 || (P.sweep_impl == 1 && a.fp32)) {
     if (a.fp32) launch_fused<float>(a, P, rows, s);
     else launch_fused<double>(a, P, rows, s);
     return;
   }
-  // residual kernel, then the recurrence in place
-  const int G = (P.K + kRWaves - 1) / kRWaves;
-  const int nb = 8 * ((G + 7) / 8) * P.n_rtiles;
+  if (P.sweep_impl == 1) {
+    hipLaunchKernelGGL(k_sweep, dim3(P.K), dim3(rows), 0, s, a);
+    return;
+  }
   if (a.fp32) {
-    hipLaunchKernelGGL(k_resid<float>, dim3(nb), dim3(kRWaves * 64), 0, s, a);
     if (P.ny > rows) hipLaunchKernelGGL((k_chain<float, true>), dim3(P.K), dim3(rows), 0, s, a);
     else hipLaunchKernelGGL((k_chain<float, false>), dim3(P.K), dim3(rows), 0, s, a);
   } else {
-    hipLaunchKernelGGL(k_resid<double>, dim3(nb), dim3(kRWaves * 64), 0, s, a);
     if (P.ny > rows) hipLaunchKernelGGL((k_chain<double, true>), dim3(P.K), dim3(rows), 0, s, a);
     else hipLaunchKernelGGL((k_chain<double, false>), dim3(P.K), dim3(rows), 0, s, a);
   }

@@ -21,8 +21,8 @@ GSIS_E_INVALID_ARG, GSIS_E_DEVICE, GSIS_E_OOM, GSIS_E_UNSUPPORTED = -1, -2, -3, 
 GSIS_SI, GSIS_GSIS = 0, 1
 GSIS_FP64, GSIS_FP32_MIXED = 0, 1
 GSIS_HOT_CENTRAL, GSIS_HOT_TRANSPORT = 0, 1
-GSIS_NUM_PHASES = 5
-PHASES = ("sweep", "moments", "hot", "synth", "update")
+GSIS_NUM_PHASES = 6
+PHASES = ("residual", "sweep", "moments", "hot", "synth", "update")
 
 _dp = ctypes.POINTER(ctypes.c_double)
 
