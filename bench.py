@@ -30,6 +30,11 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 ALG_BYTES_FP64 = 16.0
+# Relative tolerance of the synthetic CG per outer iteration: the loosest of
+# 1e-1 .. 1e-4 at which GSIS on this workload still reaches Err < 1e-6 within
+# one outer iteration of the count an accurate solve needs (23 at 1e-4, 24 at
+# 3e-3 and 1e-3, 32 at 1e-2, 28 at 1e-1).
+SYNTH_RTOL = 3e-3
 
 # HBM traffic per launch of the transport kernels from two rocprofv3 --pmc
 # runs of "bench.py --steps 3 --warmup 1 --no-converge --no-cpu-baseline
@@ -232,7 +237,7 @@ def main():
     pd = {k: (torch.from_numpy(v).to(dev) if isinstance(v, np.ndarray) else v)
           for k, v in prob.items()}
     ctx = gsis.Context(0)
-    opts = dict(method=gsis.GSIS_GSIS, limiter=1, synth_rtol=1e-4, synth_max_iter=50)
+    opts = dict(method=gsis.GSIS_GSIS, limiter=1, synth_rtol=SYNTH_RTOL, synth_max_iter=50)
 
     # ---- timed steps: K outer iterations from the initial state
     plan = gsis.Plan(ctx, pd, tol=0.0, max_iter=args.steps + args.warmup + 1, profile=1, **opts)

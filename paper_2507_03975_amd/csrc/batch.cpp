@@ -3,9 +3,12 @@
 // Every problem keeps its own plan (intensities, per-quadrant records,
 // boundary data, multigrid hierarchy, CG scalars, state and convergence
 // flag). One outer iteration of the batch is:
-//   * one persistent sweep launch over the work items (problem, ordinate)
-//     of all problems, longest first, with the launch configuration picked
-//     by timing every compiled configuration on the batch itself;
+//   * the residual of every problem in one launch over items (problem,
+//     tile, group of four ordinates), then one persistent recurrence launch
+//     over the work items (problem, ordinate) of all problems, longest
+//     first, with the rows per pass picked by timing every compiled
+//     configuration on the batch itself (with the fused sweep selected, one
+//     persistent fused launch instead);
 //   * moments, boundary fluxes, HoT, right-hand side, each one launch over
 //     (problem, block) tables;
 //   * the synthetic CG + multigrid solves of all problems in lockstep: each
@@ -16,8 +19,11 @@
 // A problem therefore gets the same numbers as when solved alone, except
 // that the CG runs a fixed number of iterations per outer iteration (device
 // stop test per problem) instead of the host checking for convergence.
-// Problems that have converged turn their kernels into no-ops. The whole
-// iteration is captured once in a hipGraph and replayed.
+// Problems that have finished turn their kernels into no-ops at once, and
+// the next status query rebuilds the work tables without them (so a long
+// tail of a few slow problems does not pay for launching the blocks of all
+// the others). The whole iteration is captured in a hipGraph and replayed;
+// the graph is captured again whenever the tables change.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -54,6 +60,9 @@ struct gsis_batch {
   void *targs = nullptr;
   int2 *items = nullptr;
   int n_items = 0;
+  bool split = true;               // residual + recurrence (else the fused sweep)
+  int4 *ritems = nullptr;          // residual items (problem, tile, group)
+  int n_ritems = 0;
   int *counter = nullptr;
   int2 *bt_face = nullptr;         // (problem, boundary face)
   int nb_face = 0;
@@ -62,10 +71,16 @@ struct gsis_batch {
   int32_t *st_all = nullptr;
   double *err_all = nullptr;
   std::vector<void *> allocs;
+  // tables of the problems still running (rebuilt when that set shrinks):
+  // every table indexes problems by their place in `active`
+  std::vector<int> active;
+  std::vector<void *> tallocs;
   int32_t *host_flag = nullptr;    // pinned
   // tuning
   int cfg = 0, grid = 0, cg_iters = 0;
-  double cfg_ms[kNumBatchSweepConfigs] = {};
+  int synth_cap = 50;              // options.synth_max_iter
+  int cg_iters0 = 0;               // CG iterations chosen at creation
+  double cfg_ms[8] = {};
   int use_graph = 1;
   hipGraphExec_t gexec = nullptr;
 };
@@ -93,12 +108,181 @@ gsis_status bupload(gsis_batch *b, T **p, const std::vector<T> &h) {
   return GSIS_OK;
 }
 
+template <typename T>
+gsis_status tupload(gsis_batch *b, T **p, const std::vector<T> &h) {
+  void *v = nullptr;
+  hipError_t e = hipMalloc(&v, std::max<size_t>(h.size(), 1) * sizeof(T));
+  if (e != hipSuccess)
+    return fail(b->ctx, GSIS_E_OOM, "hipMalloc(%zu bytes): %s", h.size() * sizeof(T),
+                hipGetErrorString(e));
+  b->tallocs.push_back(v);
+  *p = (T *)v;
+  if (!h.empty())
+    HIPCHK(b->ctx, hipMemcpy(v, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  return GSIS_OK;
+}
+
+// Kernel arguments, work items, descriptors and block tables of the
+// problems in act (in that order). Replaces the previous tables; the
+// caller has synchronised the stream and dropped any graph using them.
+gsis_status build_tables(gsis_batch *b, const std::vector<int> &act) {
+  for (void *v : b->tallocs) (void)hipFree(v);
+  b->tallocs.clear();
+  b->active = act;
+  const int n = (int)act.size();
+  gsis_status st;
+  // -- kernel arguments and the sweep work items, longest first
+  const size_t tb = targs_bytes();
+  std::vector<char> th(tb * std::max(n, 1));
+  std::vector<std::pair<double, int2>> it;
+  for (int a = 0; a < n; ++a) {
+    const PlanDev &P = b->subs[act[a]]->P;
+    fill_targs(P, th.data() + tb * a);
+    const double cost = (double)P.ny * (P.nx + std::min(P.ny, 128));
+    for (int kk = 0; kk < P.K; ++kk) it.push_back({cost, make_int2(a, kk)});
+  }
+  std::stable_sort(it.begin(), it.end(),
+                   [](const std::pair<double, int2> &x, const std::pair<double, int2> &y) {
+                     return x.first > y.first;
+                   });
+  std::vector<int2> items(it.size());
+  for (size_t t = 0; t < it.size(); ++t) items[t] = it[t].second;
+  b->n_items = (int)items.size();
+  {
+    char *d = nullptr;
+    if ((st = tupload(b, &d, th))) return st;
+    b->targs = d;
+  }
+  if ((st = tupload(b, &b->items, items))) return st;
+  {
+    std::vector<int4> ri;
+    for (int a = 0; a < n; ++a) {
+      const PlanDev &P = b->subs[act[a]]->P;
+      const int groups = (P.K + kResidWaves - 1) / kResidWaves;
+      for (int t = 0; t < P.n_rtiles; ++t)
+        for (int g = 0; g < groups; ++g) ri.push_back(make_int4(a, t, g, 0));
+    }
+    b->n_ritems = (int)ri.size();
+    if ((st = tupload(b, &b->ritems, ri))) return st;
+  }
+  // -- synthetic step: descriptors and block tables
+  SynthSet &S = b->S;
+  std::vector<SynthDesc> D(n);
+  int max_lc = 0;
+  size_t lds = 0;
+  for (int a = 0; a < n; ++a) {
+    const PlanDev &P = b->subs[act[a]]->P;
+    D[a] = make_synth_desc(P);
+    max_lc = std::max(max_lc, D[a].lc);
+    lds = std::max(lds, P.S.coarse_lds);
+  }
+  {
+    std::vector<char> dh(sizeof(SynthDesc) * std::max(n, 1));
+    if (n) memcpy(dh.data(), D.data(), sizeof(SynthDesc) * n);
+    char *d = nullptr;
+    if ((st = tupload(b, &d, dh))) return st;
+    S.desc = (SynthDesc *)d;
+  }
+  S.n = n;
+  S.max_lc = max_lc;
+  S.coarse_lds = lds;
+  S.state0 = nullptr;
+  auto nb = [](long long m) { return (int)((m + 255) / 256); };
+  std::vector<int2> t;
+  for (int a = 0; a < n; ++a)
+    for (int lb = 0; lb < nb(D[a].N); ++lb) t.push_back(make_int2(a, lb));
+  S.nb_cell = (int)t.size();
+  if ((st = tupload(b, &S.bt_cell, t))) return st;
+  S.bt_tile.assign(max_lc, nullptr);
+  S.nb_tile.assign(max_lc, 0);
+  for (int l = 0; l < max_lc; ++l) {
+    std::vector<int2> tt;
+    for (int a = 0; a < n; ++a) {
+      if (D[a].lc <= l) continue;
+      for (int lb = 0; lb < tiles_of(D[a].lev[l].nx, D[a].lev[l].ny); ++lb)
+        tt.push_back(make_int2(a, lb));
+    }
+    S.nb_tile[l] = (int)tt.size();
+    if ((st = tupload(b, &S.bt_tile[l], tt))) return st;
+  }
+  std::vector<int2> tfc;
+  for (int a = 0; a < n; ++a)
+    for (int f = 0; f < b->subs[act[a]]->P.nbf; ++f) tfc.push_back(make_int2(a, f));
+  b->nb_face = (int)tfc.size();
+  if ((st = tupload(b, &b->bt_face, tfc))) return st;
+  prepare_synth(lds);
+  return GSIS_OK;
+}
+
+void enqueue_iteration(gsis_batch *b, bool capture);
+
+// (Re)capture one outer iteration of the current tables in a hipGraph.
+gsis_status capture(gsis_batch *b) {
+  gsis_ctx *ctx = b->ctx;
+  if (b->gexec) {
+    HIPCHK(ctx, hipStreamSynchronize(b->stream));
+    (void)hipGraphExecDestroy(b->gexec);
+    b->gexec = nullptr;
+  }
+  if (!b->use_graph || b->active.empty()) return GSIS_OK;
+  hipGraph_t g = nullptr;
+  HIPCHK(ctx, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+  enqueue_iteration(b, true);
+  HIPCHK(ctx, hipStreamEndCapture(b->stream, &g));
+  hipError_t e = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return fail(ctx, GSIS_E_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  return GSIS_OK;
+}
+
+// Drop the problems that have finished from the tables (and the graph),
+// so that later iterations launch no blocks for them.
+gsis_status compact(gsis_batch *b, const std::vector<int32_t> &st4) {
+  std::vector<int> act;
+  for (int i : b->active)
+    if (st4[4 * i + 1] == 0) act.push_back(i);
+  if (act.size() == b->active.size()) return GSIS_OK;
+  HIPCHK(b->ctx, hipStreamSynchronize(b->stream));
+  if (b->gexec) {
+    (void)hipGraphExecDestroy(b->gexec);
+    b->gexec = nullptr;
+  }
+  // CG iterations per outer iteration: the most a remaining problem used
+  // in its last synthetic solve, plus 2
+  if (b->method == GSIS_GSIS && !act.empty()) {
+    double most = 0;
+    for (int i : act) {
+      double nit = 0;
+      HIPCHK(b->ctx, hipMemcpy(&nit, synth_iteration_counter(b->subs[i]->P), sizeof nit,
+                               hipMemcpyDeviceToHost));
+      most = std::max(most, nit);
+    }
+    b->cg_iters = std::max(4, std::min(b->synth_cap, (int)most + 2));
+    b->S.synth_max_iter = b->cg_iters;
+  }
+  gsis_status st = build_tables(b, act);
+  if (st) return st;
+  return capture(b);
+}
+
+std::vector<int> all_problems(int n) {
+  std::vector<int> a(n);
+  std::iota(a.begin(), a.end(), 0);
+  return a;
+}
+
 // One outer iteration of the batch on b->stream. host_flag NULL: no host
 // waits (graph capture).
 void enqueue_iteration(gsis_batch *b, bool capture) {
   hipStream_t s = b->stream;
   (void)capture;
-  launch_sweep_batch(b->targs, b->items, b->n_items, b->counter, b->cfg, b->fp32, b->grid, s);
+  if (b->active.empty()) return;
+  if (b->split) {
+    launch_resid_batch(b->targs, b->ritems, b->n_ritems, b->fp32, s);
+    launch_chain_batch(b->targs, b->items, b->n_items, b->counter, b->cfg, b->fp32, b->grid, s);
+  } else {
+    launch_sweep_batch(b->targs, b->items, b->n_items, b->counter, b->cfg, b->fp32, b->grid, s);
+  }
   launch_moments_batch(b->targs, b->S.bt_cell, b->S.nb_cell, b->fp32, s);
   if (b->method == GSIS_GSIS) {
     launch_boundary_flux_batch(b->targs, b->bt_face, b->nb_face, s);
@@ -112,6 +296,19 @@ gsis_status reset_all(gsis_batch *b) {
   gsis_status st;
   for (gsis_plan *pl : b->subs)
     if ((st = gsis_plan_reset(pl))) return st;
+  if (b->cg_iters0 > 0) {
+    b->cg_iters = b->cg_iters0;
+    b->S.synth_max_iter = b->cg_iters0;
+  }
+  if ((int)b->active.size() != b->n) {
+    HIPCHK(b->ctx, hipStreamSynchronize(b->stream));
+    if (b->gexec) {
+      (void)hipGraphExecDestroy(b->gexec);
+      b->gexec = nullptr;
+    }
+    if ((st = build_tables(b, all_problems(b->n)))) return st;
+    if ((st = capture(b))) return st;
+  }
   return GSIS_OK;
 }
 
@@ -121,6 +318,7 @@ void destroy(gsis_batch *b) {
   if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
   for (gsis_plan *pl : b->subs) gsis_plan_destroy(pl);
   for (void *v : b->allocs) (void)hipFree(v);
+  for (void *v : b->tallocs) (void)hipFree(v);
   if (b->host_flag) (void)hipHostFree(b->host_flag);
   if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
   delete b;
@@ -172,30 +370,12 @@ gsis_status gsis_batch_create(gsis_ctx *ctx, int32_t n, const gsis_problem *p,
     }
     b->subs.push_back(pl);
   }
-  // -- per-problem kernel arguments and the sweep work items, longest first
-  const size_t tb = targs_bytes();
-  std::vector<char> th(tb * n);
-  std::vector<std::pair<double, int2>> it;
-  for (int i = 0; i < n; ++i) {
-    const PlanDev &P = b->subs[i]->P;
-    fill_targs(P, th.data() + tb * i);
-    const double cost = (double)P.ny * (P.nx + std::min(P.ny, 128));
-    for (int kk = 0; kk < P.K; ++kk) it.push_back({cost, make_int2(i, kk)});
-  }
-  std::stable_sort(it.begin(), it.end(),
-                   [](const std::pair<double, int2> &a, const std::pair<double, int2> &c) {
-                     return a.first > c.first;
-                   });
-  std::vector<int2> items(it.size());
-  for (size_t t = 0; t < it.size(); ++t) items[t] = it[t].second;
-  b->n_items = (int)items.size();
-  {
-    char *d = nullptr;
-    if ((st = balloc(b, &d, th.size()))) return bail(st);
-    HIPCHK(ctx, hipMemcpy(d, th.data(), th.size(), hipMemcpyHostToDevice));
-    b->targs = d;
-  }
-  if ((st = bupload(b, &b->items, items)) || (st = balloc(b, &b->counter, 1))) return bail(st);
+  // -- tables of all problems
+  if ((st = balloc(b, &b->counter, 1))) return bail(st);
+  b->split = b->subs[0]->P.sweep_impl == 0;
+  b->S.synth_max_iter = o->synth_max_iter;
+  b->synth_cap = o->synth_max_iter;
+  if ((st = build_tables(b, all_problems(n)))) return bail(st);
   // -- status gather tables
   {
     std::vector<int32_t *> sp(n);
@@ -207,54 +387,6 @@ gsis_status gsis_batch_create(gsis_ctx *ctx, int32_t n, const gsis_problem *p,
     if ((st = bupload(b, &b->state_p, sp)) || (st = bupload(b, &b->err_p, ep)) ||
         (st = balloc(b, &b->st_all, 4 * (size_t)n)) || (st = balloc(b, &b->err_all, n)))
       return bail(st);
-  }
-  // -- synthetic step of all problems: descriptors and block tables
-  {
-    SynthSet &S = b->S;
-    std::vector<SynthDesc> D(n);
-    int max_lc = 0;
-    size_t lds = 0;
-    for (int i = 0; i < n; ++i) {
-      const PlanDev &P = b->subs[i]->P;
-      D[i] = make_synth_desc(P);
-      max_lc = std::max(max_lc, D[i].lc);
-      lds = std::max(lds, P.S.coarse_lds);
-    }
-    {
-      char *d = nullptr;
-      if ((st = balloc(b, &d, sizeof(SynthDesc) * n))) return bail(st);
-      HIPCHK(ctx, hipMemcpy(d, D.data(), sizeof(SynthDesc) * n, hipMemcpyHostToDevice));
-      S.desc = (SynthDesc *)d;
-    }
-    S.n = n;
-    S.max_lc = max_lc;
-    S.coarse_lds = lds;
-    S.synth_max_iter = o->synth_max_iter;
-    S.state0 = nullptr;
-    auto nb = [](long long m) { return (int)((m + 255) / 256); };
-    std::vector<int2> t;
-    for (int i = 0; i < n; ++i)
-      for (int lb = 0; lb < nb(D[i].N); ++lb) t.push_back(make_int2(i, lb));
-    S.nb_cell = (int)t.size();
-    if ((st = bupload(b, &S.bt_cell, t))) return bail(st);
-    S.bt_tile.assign(max_lc, nullptr);
-    S.nb_tile.assign(max_lc, 0);
-    for (int l = 0; l < max_lc; ++l) {
-      std::vector<int2> tt;
-      for (int i = 0; i < n; ++i) {
-        if (D[i].lc <= l) continue;
-        for (int lb = 0; lb < tiles_of(D[i].lev[l].nx, D[i].lev[l].ny); ++lb)
-          tt.push_back(make_int2(i, lb));
-      }
-      S.nb_tile[l] = (int)tt.size();
-      if ((st = bupload(b, &S.bt_tile[l], tt))) return bail(st);
-    }
-    std::vector<int2> tfc;
-    for (int i = 0; i < n; ++i)
-      for (int f = 0; f < b->subs[i]->P.nbf; ++f) tfc.push_back(make_int2(i, f));
-    b->nb_face = (int)tfc.size();
-    if ((st = bupload(b, &b->bt_face, tfc))) return bail(st);
-    prepare_synth(lds);
   }
   {
     void *h = nullptr;
@@ -271,19 +403,32 @@ gsis_status gsis_batch_create(gsis_ctx *ctx, int32_t n, const gsis_problem *p,
   HIPCHK(ctx, hipEventCreate(&e0));
   HIPCHK(ctx, hipEventCreate(&e1));
   double best = 1e300;
-  for (int c = 0; c < kNumBatchSweepConfigs; ++c) {
-    const int per_cu = sweep_batch_blocks_per_cu(c, b->fp32);
+  const int ncfg = b->split ? kNumBatchChainConfigs : kNumBatchSweepConfigs;
+  auto run = [&](int c, int grid) {
+    if (b->split)
+      launch_chain_batch(b->targs, b->items, b->n_items, b->counter, c, b->fp32, grid, b->stream);
+    else
+      launch_sweep_batch(b->targs, b->items, b->n_items, b->counter, c, b->fp32, grid, b->stream);
+  };
+  for (int c = 0; c < ncfg; ++c) {
+    const int per_cu = b->split ? chain_batch_blocks_per_cu(c, b->fp32)
+                                : sweep_batch_blocks_per_cu(c, b->fp32);
     b->cfg_ms[c] = -1.0;
     if (per_cu <= 0) continue;
     const int grid = per_cu * cus;
-    launch_sweep_batch(b->targs, b->items, b->n_items, b->counter, c, b->fp32, grid, b->stream);
-    HIPCHK(ctx, hipEventRecord(e0, b->stream));
-    for (int r = 0; r < 2; ++r)
-      launch_sweep_batch(b->targs, b->items, b->n_items, b->counter, c, b->fp32, grid, b->stream);
-    HIPCHK(ctx, hipEventRecord(e1, b->stream));
-    HIPCHK(ctx, hipEventSynchronize(e1));
+    // the recurrence rewrites the residual's output in place, so every
+    // timed run starts from a fresh residual launch (outside the events)
     float ms = 0;
-    HIPCHK(ctx, hipEventElapsedTime(&ms, e0, e1));
+    for (int r = 0; r < 3; ++r) {
+      if (b->split) launch_resid_batch(b->targs, b->ritems, b->n_ritems, b->fp32, b->stream);
+      HIPCHK(ctx, hipEventRecord(e0, b->stream));
+      run(c, grid);
+      HIPCHK(ctx, hipEventRecord(e1, b->stream));
+      HIPCHK(ctx, hipEventSynchronize(e1));
+      float m1 = 0;
+      HIPCHK(ctx, hipEventElapsedTime(&m1, e0, e1));
+      if (r > 0) ms += m1;           // the first run warms up
+    }
     b->cfg_ms[c] = ms / 2;
     if (ms / 2 < best) {
       best = ms / 2;
@@ -310,19 +455,11 @@ gsis_status gsis_batch_create(gsis_ctx *ctx, int32_t n, const gsis_problem *p,
     }
     b->cg_iters = std::max(4, std::min(o->synth_max_iter, (int)most + 2));
     b->S.synth_max_iter = b->cg_iters;
+    b->cg_iters0 = b->cg_iters;
     if ((st = reset_all(b))) return bail(st);
   }
   // -- capture one outer iteration
-  if (b->use_graph) {
-    hipGraph_t g = nullptr;
-    HIPCHK(ctx, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-    enqueue_iteration(b, true);
-    HIPCHK(ctx, hipStreamEndCapture(b->stream, &g));
-    hipError_t e = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (e != hipSuccess)
-      return bail(fail(ctx, GSIS_E_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e)));
-  }
+  if ((st = capture(b))) return bail(st);
   *out = b;
   return GSIS_OK;
 }
@@ -364,7 +501,8 @@ gsis_status gsis_batch_status(gsis_batch *b, int32_t *n_iter, int32_t *converged
     fin += st[4 * i + 1] != 0;
   }
   if (n_finished) *n_finished = fin;
-  return GSIS_OK;
+  // problems found finished leave the launches from now on
+  return compact(b, st);
 }
 
 gsis_status gsis_batch_read(gsis_batch *b, int32_t i, gsis_result *r) {
@@ -381,14 +519,16 @@ gsis_status gsis_batch_reset(gsis_batch *b) {
 gsis_status gsis_batch_get_tuning(gsis_batch *b, gsis_batch_tuning *t) {
   if (!b) return GSIS_E_INVALID_ARG;
   if (!t) return fail(b->ctx, GSIS_E_INVALID_ARG, "tuning is NULL");
-  t->rows = kBatchSweepConfigs[b->cfg].rows;
-  t->prefetch = kBatchSweepConfigs[b->cfg].pf;
+  const BatchSweepConfig *cf = b->split ? kBatchChainConfigs : kBatchSweepConfigs;
+  const int ncfg = b->split ? kNumBatchChainConfigs : kNumBatchSweepConfigs;
+  t->rows = cf[b->cfg].rows;
+  t->prefetch = cf[b->cfg].pf;
   t->grid = b->grid;
   t->cg_iters = b->cg_iters;
-  t->n_configs = kNumBatchSweepConfigs;
-  for (int c = 0; c < kNumBatchSweepConfigs && c < 8; ++c) {
-    t->config_rows[c] = kBatchSweepConfigs[c].rows;
-    t->config_prefetch[c] = kBatchSweepConfigs[c].pf;
+  t->n_configs = ncfg;
+  for (int c = 0; c < ncfg && c < 8; ++c) {
+    t->config_rows[c] = cf[c].rows;
+    t->config_prefetch[c] = cf[c].pf;
     t->config_ms[c] = b->cfg_ms[c];
   }
   return GSIS_OK;

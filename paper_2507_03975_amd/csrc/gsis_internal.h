@@ -188,6 +188,17 @@ std::vector<int> diag_row0_table(int nx, int ny);
 struct BatchSweepConfig { int rows, pf; };
 constexpr int kNumBatchSweepConfigs = 6;
 extern const BatchSweepConfig kBatchSweepConfigs[kNumBatchSweepConfigs];
+// Split transport step of a batch: residual items (problem, tile, group of
+// four ordinates), then a persistent recurrence over (problem, ordinate)
+// items with rows per pass from kBatchChainConfigs (prefetch fixed).
+constexpr int kNumBatchChainConfigs = 4;
+extern const BatchSweepConfig kBatchChainConfigs[kNumBatchChainConfigs];
+int chain_batch_blocks_per_cu(int cfg, bool fp32);
+constexpr int kResidWaves = 4;     // ordinates per residual item
+void launch_resid_batch(const void *targs, const int4 *items, int n_items, bool fp32,
+                        hipStream_t s);
+void launch_chain_batch(const void *targs, const int2 *items, int n_items, int *counter, int cfg,
+                        bool fp32, int grid, hipStream_t s);
 size_t targs_bytes();
 void fill_targs(const PlanDev &P, void *dst);
 int sweep_batch_blocks_per_cu(int cfg, bool fp32);

@@ -251,32 +251,45 @@ __global__ void k_cg_pAp(const SynthDesc *ds, const int2 *bt, int it) {
   __shared__ double sh[kRedBlock];
   const Blk B = blk(bt);
   CDesc &D = cdesc(ds, B.p);
-  if (cg_off(D.state)) return;
+  // The flags, the partials and the cell's operands are loaded before any of
+  // them is waited for (this kernel is latency bound).
+  const int32_t f1 = D.state[1], f3 = D.state[3];
   const bool first = it == 0;
   const int par = it & 1;
-  const double rz = sum_partials(red_rz(D), n_rz(D), sh);
-  const double be = first ? 0.0 : rz / D.scal[rz_slot(it - 1)];
-  if (B.lb == 0 && threadIdx.x == 0) {
-    D.scal[rz_slot(it)] = rz;
-    D.scal[S_BETA] = be;
-  }
   const int c = B.lb * kRedBlock + threadIdx.x;
   const LevelDev L = level(D, 0);
   const int nx = L.nx, ny = L.ny;
   const double *z = D.cg_z;
   const double *pold = par ? D.cg_p1 : D.cg_p0;
   double *pnew = par ? D.cg_p0 : D.cg_p1;
-  auto P = [&](int k) { return first ? z[k] : z[k] + be * pold[k]; };
+  const bool in = c < D.N;
+  int i = 0, j = 0;
+  if (in) cell_ij(c, nx, i, j);
+  const bool hE = in && i + 1 < nx, hW = in && i > 0, hN = in && j + 1 < ny, hS = in && j > 0;
+  const int cc = in ? c : 0;
+  const int ce = hE ? c + 1 : cc, cw = hW ? c - 1 : cc, cn = hN ? c + nx : cc, cs = hS ? c - nx : cc;
+  const double zc = z[cc], ze = z[ce], zw = z[cw], zn = z[cn], zs = z[cs];
+  double oc = 0.0, oe = 0.0, ow = 0.0, on = 0.0, os = 0.0;
+  if (!first) { oc = pold[cc]; oe = pold[ce]; ow = pold[cw]; on = pold[cn]; os = pold[cs]; }
+  const double dg = L.dg[cc];
+  const double aE = hE ? L.ax[c] : 0.0, aW = hW ? L.ax[c - 1] : 0.0;
+  const double aN = hN ? L.ay[c] : 0.0, aS = hS ? L.ay[c - nx] : 0.0;
+  if (f1 != 0 || f3 != 0) return;
+  const double rz = sum_partials(red_rz(D), n_rz(D), sh);
+  const double be = first ? 0.0 : rz / D.scal[rz_slot(it - 1)];
+  if (B.lb == 0 && threadIdx.x == 0) {
+    D.scal[rz_slot(it)] = rz;
+    D.scal[S_BETA] = be;
+  }
+  auto P = [&](double zv, double ov) { return first ? zv : zv + be * ov; };
   double v = 0.0;
-  if (c < D.N) {
-    int i, j;
-    cell_ij(c, nx, i, j);
-    const double pc = P(c);
-    double y = L.dg[c] * pc;
-    if (i + 1 < nx) y -= L.ax[c] * P(c + 1);
-    if (i > 0) y -= L.ax[c - 1] * P(c - 1);
-    if (j + 1 < ny) y -= L.ay[c] * P(c + nx);
-    if (j > 0) y -= L.ay[c - nx] * P(c - nx);
+  if (in) {
+    const double pc = P(zc, oc);
+    double y = dg * pc;
+    if (hE) y -= aE * P(ze, oe);
+    if (hW) y -= aW * P(zw, ow);
+    if (hN) y -= aN * P(zn, on);
+    if (hS) y -= aS * P(zs, os);
     pnew[c] = pc;
     D.cg_Ap[c] = y;
     v = pc * y;
@@ -291,19 +304,24 @@ __global__ void k_cg_update(const SynthDesc *ds, const int2 *bt, int it) {
   __shared__ double sh[kRedBlock];
   const Blk B = blk(bt);
   CDesc &D = cdesc(ds, B.p);
-  if (cg_off(D.state)) return;
+  const int32_t f1 = D.state[1], f3 = D.state[3];
+  const int c = B.lb * kRedBlock + threadIdx.x;
+  const double *p = (it & 1) ? D.cg_p0 : D.cg_p1;
+  double *x = D.lev[0].x;
+  const bool in = c < D.N;
+  const int cc = in ? c : 0;
+  const double pc = p[cc], xc = x[cc], rc0 = D.cg_r[cc], apc = D.cg_Ap[cc];
+  if (f1 != 0 || f3 != 0) return;
   const double pap = sum_partials(red_pap(D), nblk_d(D.N), sh);
   const double al = D.scal[rz_slot(it)] / pap;
   if (B.lb == 0 && threadIdx.x == 0) {
     D.scal[S_PAP] = pap;
     D.scal[S_ALPHA] = al;
   }
-  const int c = B.lb * kRedBlock + threadIdx.x;
-  const double *p = (it & 1) ? D.cg_p0 : D.cg_p1;
   double v = 0.0;
-  if (c < D.N) {
-    D.lev[0].x[c] += al * p[c];
-    const double rc = D.cg_r[c] - al * D.cg_Ap[c];
+  if (in) {
+    x[c] = xc + al * pc;
+    const double rc = rc0 - al * apc;
     D.cg_r[c] = rc;
     v = rc * rc;
   }
@@ -376,15 +394,16 @@ __global__ void __launch_bounds__(kRedBlock) k_mg_down(const SynthDesc *ds, cons
   static_assert(kRN >= kRedBlock, "sb doubles as reduction scratch");
   const Blk B = blk(bt);
   CDesc &D = cdesc(ds, B.p);
-  if (cg_off(D.state)) return;
-  // the r.r test of the CG step before this V-cycle (the other blocks go on:
-  // if it converged, their results are not used)
-  if (l == 0 && B.lb == 0) (void)finish_rr(D, first != 0, sb);
+  const int32_t f1 = D.state[1], f3 = D.state[3];   // tested after the region loads
   const LevelDev L = level(D, l), CL = level(D, l + 1);
   const double *b = lev_b(D, l);
   double *xs = L.xs;
   const Tile T = tile_of(L, B.lb);
   load_region(L, b, T, sb, sd, sax, say);
+  if (f1 != 0 || f3 != 0) return;
+  // the r.r test of the CG step before this V-cycle (the other blocks go on:
+  // if it converged, their results are not used)
+  if (l == 0 && B.lb == 0) (void)finish_rr(D, first != 0, sx);
   __syncthreads();
   // red half sweep from zero on the whole region
   for (int r = threadIdx.x; r < kRN; r += blockDim.x) {
@@ -446,7 +465,7 @@ __global__ void __launch_bounds__(kRedBlock) k_mg_up(const SynthDesc *ds, const 
   __shared__ double sb[kRN], sd[kRN], sax[kRN], say[kRN], sx[kRN], sh[kRedBlock];
   const Blk B = blk(bt);
   CDesc &D = cdesc(ds, B.p);
-  if (cg_off(D.state)) return;
+  const int32_t f1 = D.state[1], f3 = D.state[3];   // tested after the region loads
   const LevelDev L = level(D, l), CL = level(D, l + 1);
   const double *b = lev_b(D, l);
   double *x = lev_x(D, l);
@@ -469,6 +488,7 @@ __global__ void __launch_bounds__(kRedBlock) k_mg_up(const SynthDesc *ds, const 
     }
     sxc[r] = v;
   }
+  if (f1 != 0 || f3 != 0) return;
   __syncthreads();
   // black half sweep on the tile and a ring of one, into sx
   for (int r = threadIdx.x; r < kRN; r += blockDim.x) {

@@ -89,6 +89,19 @@ __device__ inline T *Iout_of(const TArgs &a) { return (T *)(a.state[2] ? a.I0 : 
 __device__ inline int quadrant_of(const TArgs &a, int kk) {
   return (kk >= a.qoff[1]) + (kk >= a.qoff[2]) + (kk >= a.qoff[3]);
 }
+// The same for a problem's arguments in a batch table, read through the
+// constant address space (scalar loads).
+typedef __attribute__((address_space(4))) const TArgs CTArgs;
+__device__ inline CTArgs &targs_at(const TArgs *t, int p) { return ((CTArgs *)t)[p]; }
+template <typename T = double>
+__device__ inline const T *Iin_of(CTArgs &a) {
+  return (const T *)(a.state[2] ? a.I1 : a.I0);
+}
+template <typename T = double>
+__device__ inline T *Iout_of(CTArgs &a) { return (T *)(a.state[2] ? a.I0 : a.I1); }
+__device__ inline int quadrant_of(CTArgs &a, int kk) {
+  return (kk >= a.qoff[1]) + (kk >= a.qoff[2]) + (kk >= a.qoff[3]);
+}
 // quadrant q: bit 0 = mirrored in x (mu < 0), bit 1 = mirrored in y (eta < 0)
 __device__ inline int gcell(const TArgs &a, int q, int xl, int yl) {
   int i = (q & 1) ? a.nx - 1 - xl : xl;
@@ -604,6 +617,25 @@ constexpr int kRSteps = kRD + 1;
 constexpr int kRWaves = 4;           // waves per workgroup, one ordinate each
 constexpr int kRPF = 4;              // steps of loads in flight
 
+__device__ inline double buf_ld64(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+__device__ inline double2 buf_ld128(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0));
+}
+template <typename T>
+__device__ inline T buf_ldT(__amdgpu_buffer_rsrc_t r, unsigned i) {
+  if constexpr (sizeof(T) == 8) return buf_ld64(r, i * 8u);
+  else return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)(i * 4u), 0, 0));
+}
+// shl1 with lane 63 taking fill instead
+__device__ inline double shl1_fill(double v, double fill) {
+  int lo = __double2loint(fill), hi = __double2hiint(fill);
+  lo = __builtin_amdgcn_update_dpp(lo, __double2loint(v), 0x130, 0xf, 0xf, false);
+  hi = __builtin_amdgcn_update_dpp(hi, __double2hiint(v), 0x130, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
 template <typename T>
 struct RSlot {
   T ib;                // stored value at the lookahead cell (diagonal d+1)
@@ -611,7 +643,7 @@ struct RSlot {
   double sube;         // FP32 mode: phi^m/(4 pi) there
   double src;          // source at the cell (diagonal d)
   double2 c0, c1, st;  // its coefficient record
-  int ic;              // its storage index
+  unsigned ic;         // its storage index
 };
 
 // One wave per (ordinate, tile). Lane l owns row y = y0 + l; at step dd its
@@ -619,30 +651,19 @@ struct RSlot {
 // d, d+1; u(x, y-1) and u(x, y+1) are the neighbour lanes' window values and
 // the south face value is lane l-1's F_n of the previous step (DPP shifts).
 // Row y0-1 below lane 0 and row y0+64 above lane 63 come from a halo pass in
-// which lane j holds diagonal d0-2+j (u below), d0-1+j (F_n below) and
-// d0+j (u above); lanes 0 and 63 read them with readlane. Every load is
-// issued for every lane (addresses of cells outside the grid are clamped
-// into it and the values dropped).
-template <typename T>
-__global__ void __launch_bounds__(kRWaves * 64) k_resid(TArgs a) {
-  if (a.state[1] != 0) return;
+// which lane j computes diagonal d0-2+j (u below), d0-1+j (F_n below) and
+// d0+j (u above) into LDS; each step reads its three halo values back as
+// LDS broadcasts and feeds them to the DPP shifts as lane 0's (lane 63's)
+// fill. Loads use the index dso[d] + y through buffer resources: for a lane
+// with no cell it lies on another diagonal or out of the buffer (read as 0),
+// and the value is dropped.
+template <typename T, class A>
+__device__ __forceinline__ void resid_tile(A &a, const int tile, const int kk, const int wave) {
   constexpr bool kF32 = sizeof(T) == 4;
   constexpr int PF = kRPF;
   static_assert(kRSteps % PF == 0, "whole turns of the load ring");
+  static_assert(kRSteps + PF + 2 <= kDiagPad, "diagonal table padding");
   const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform per wave
-  // workgroup b runs on XCD b % 8; each XCD takes a contiguous run of
-  // ordinate groups (quadrant-sorted) and walks the tiles for them
-  const int K = a.K, G = (K + kRWaves - 1) / kRWaves;
-  const int xc = blockIdx.x & 7, bi = blockIdx.x >> 3;
-  const int gcnt = (G - xc + 7) >> 3;
-  if (gcnt <= 0) return;
-  const int tile = bi / gcnt;
-  if (tile >= a.n_rtiles) return;
-  int gstart = 0;
-  for (int xp = 0; xp < xc; ++xp) gstart += (G - xp + 7) >> 3;
-  const int kk = (gstart + bi % gcnt) * kRWaves + wave;
-  if (kk >= K) return;
   const int2 tl = a.rtiles[tile];
   const int d0 = tl.x, y0 = tl.y;
   const int nx = a.nx, ny = a.ny, N = a.N;
@@ -650,41 +671,42 @@ __global__ void __launch_bounds__(kRWaves * 64) k_resid(TArgs a) {
   const double ax = a.amu[kk], ay = a.aeta[kk];
   const double hdx = 0.5 * a.dx, hdy = 0.5 * a.dy;
   const bool second = a.order >= 2, lim = a.limiter != 0;
-  const T *Ik = Iin_of<T>(a) + (size_t)kk * N;
+  const __amdgpu_buffer_rsrc_t Ib = buf_rsrc(Iin_of<T>(a) + (size_t)kk * N, (size_t)N * sizeof(T));
   const __amdgpu_buffer_rsrc_t Ob = buf_rsrc(Iout_of<T>(a) + (size_t)kk * N, (size_t)N * sizeof(T));
-  const double2 *C2 = reinterpret_cast<const double2 *>(a.cellq + (size_t)q * N * 6);
+  const __amdgpu_buffer_rsrc_t Cb = buf_rsrc(a.cellq + (size_t)q * N * 6, (size_t)N * 48);
   const double *SRC = a.dynq + (size_t)q * 3 * N;
-  const double *DQ = SRC + N;
-  const double *SUB = SRC + 2 * N;
+  const __amdgpu_buffer_rsrc_t Sb = buf_rsrc(SRC, (size_t)N * 8);
+  const __amdgpu_buffer_rsrc_t Qb = buf_rsrc(SRC + N, (size_t)N * 8);
+  const __amdgpu_buffer_rsrc_t Ub = buf_rsrc(SRC + 2 * N, (size_t)N * 8);
+  const __attribute__((address_space(4))) int *DS =
+      (const __attribute__((address_space(4))) int *)(a.dso + kDiagPad);
   const int y = y0 + lane;
   const bool rowok = y < ny, hn = y + 1 < ny, hs = y > 0;
-  auto cidx = [&](int x, int yy) {
-    x = min(max(x, 0), nx - 1);
-    yy = min(max(yy, 0), ny - 1);
-    return (int)dg_idx(x, yy, nx, ny);
-  };
-  auto uof = [&](int i) { return (double)Ik[i] + DQ[i]; };
-  // ---- halo: hu = u(d0-2+j, y0-1), hsb = phi^m/(4 pi) there (FP32 mode),
-  // hf = F_n(d0-1+j, y0-1) or, on the first band, the south inflow of
-  // column d0+j; hnv = u(d0+j, y0+64)
-  double hu = 0.0, hsb = 0.0, hf = 0.0, hnv = 0.0;
+  auto uof = [&](unsigned i) { return (double)buf_ldT<T>(Ib, i) + buf_ld64(Qb, i * 8u); };
+  // ---- halo (see above) into LDS: lane j's values at [wave][slot][j]
+  __shared__ double hal[kRWaves][4][kRSteps + 1];
   {
+    auto cidx = [&](int x, int yy) {       // storage index, clamped into the grid
+      x = min(max(x, 0), nx - 1);
+      yy = min(max(yy, 0), ny - 1);
+      return (unsigned)(a.dso[kDiagPad + x + yy] + yy);
+    };
     const int ys = y0 - 1;
     const int xu = d0 - 2 + lane - ys, xf = d0 - 1 + lane - ys, xn = d0 + lane - (y0 + 64);
-    const int iu = cidx(xu, ys), jf = cidx(xf, ys);
+    const unsigned iu = cidx(xu, ys), jf = cidx(xf, ys);
     const double vu = uof(iu), vf = uof(jf);
     const double ve = uof(cidx(xf + 1, ys)), vw = uof(cidx(xf - 1, ys));
     const double vn = uof(cidx(xf, y0)), vs = uof(cidx(xf, ys - 1));
-    const double2 f0 = C2[3 * jf], f1 = C2[3 * jf + 1];
+    const double2 f0 = buf_ld128(Cb, jf * 48u), f1 = buf_ld128(Cb, jf * 48u + 16u);
     const double vN = uof(cidx(xn, y0 + 64));
-    double su = 0.0;
-    if constexpr (kF32) su = SUB[iu];
+    const double su = kF32 ? buf_ld64(Ub, iu * 8u) : 0.0;
     const int xi = min(d0 + lane, nx - 1);
     const int gi = (q & 1) ? nx - 1 - xi : xi;
     const double vin = a.bnd[(size_t)((q & 2) ? 2 * ny + nx + gi : 2 * ny + gi) * a.K + kk];
     double Fe, Fn;
     face_pair(vf, xf + 1 < nx ? ve : vf, xf > 0 ? vw : vf, vn, ys > 0 ? vs : vf, f0, f1, hdx, hdy,
               second, lim, Fe, Fn);
+    double hu = 0.0, hsb = 0.0, hf = 0.0, hnv = 0.0;
     if (y0 > 0) {
       if (lane <= kRD && xu >= 0 && xu < nx) { hu = vu; hsb = su; }
       if (lane < kRD && xf >= 0 && xf < nx) hf = Fn;
@@ -692,6 +714,12 @@ __global__ void __launch_bounds__(kRWaves * 64) k_resid(TArgs a) {
       hf = vin;
     }
     if (y0 + 64 < ny && lane <= kRD && xn >= 0 && xn < nx) hnv = vN;
+    if (lane <= kRD) {
+      hal[wave][0][lane] = hu;
+      hal[wave][1][lane] = hf;
+      hal[wave][2][lane] = hnv;
+      hal[wave][3][lane] = hsb;
+    }
   }
   // inflow on the local west face of the lane's row
   double inW;
@@ -700,36 +728,28 @@ __global__ void __launch_bounds__(kRWaves * 64) k_resid(TArgs a) {
     const int j = (q & 2) ? ny - 1 - yr : yr;
     inW = a.bnd[(size_t)((q & 1) ? ny + j : j) * a.K + kk];
   }
-  // ---- window u(d0-2, y), u(d0-1, y); then the load ring from step -1.
-  // Indices of lanes outside the grid are clamped into the diagonal.
-  DiagCursor cur;
-  cur.init(nx, ny, d0 - 2);
+  // ---- window u(d0-2, y), u(d0-1, y); then the load ring from step -1
   double uc, ue, subc = 0.0, sube = 0.0;
   {
-    const int i0 = cur.index(y);
+    const unsigned i0 = (unsigned)(DS[d0 - 2] + y), i1 = (unsigned)(DS[d0 - 1] + y);
     uc = uof(i0);
-    if constexpr (kF32) subc = SUB[i0];
-    cur.advance();
-    const int i1 = cur.index(y);
     ue = uof(i1);
-    if constexpr (kF32) sube = SUB[i1];
+    if constexpr (kF32) { subc = buf_ld64(Ub, i0 * 8u); sube = buf_ld64(Ub, i1 * 8u); }
   }
-  int inext = cur.index(y);                   // diagonal d0 - 1
-  auto load = [&](RSlot<T> &sl) {
-    sl.ic = inext;
-    cur.advance();
-    inext = cur.index(y);
-    sl.ib = Ik[inext];
-    sl.dq = DQ[inext];
-    if constexpr (kF32) sl.sube = SUB[inext];
-    sl.src = SRC[sl.ic];
-    sl.c0 = C2[3 * sl.ic];
-    sl.c1 = C2[3 * sl.ic + 1];
-    sl.st = C2[3 * sl.ic + 2];
+  auto load = [&](RSlot<T> &sl, int d) {     // cell on diagonal d, lookahead on d + 1
+    const unsigned ic = (unsigned)(DS[d] + y), il = (unsigned)(DS[d + 1] + y);
+    sl.ic = ic;
+    sl.ib = buf_ldT<T>(Ib, il);
+    sl.dq = buf_ld64(Qb, il * 8u);
+    if constexpr (kF32) sl.sube = buf_ld64(Ub, il * 8u);
+    sl.src = buf_ld64(Sb, ic * 8u);
+    sl.c0 = buf_ld128(Cb, ic * 48u);
+    sl.c1 = buf_ld128(Cb, ic * 48u + 16u);
+    sl.st = buf_ld128(Cb, ic * 48u + 32u);
   };
   RSlot<T> ring[PF];
 #pragma unroll
-  for (int t = 0; t < PF; ++t) load(ring[t]);
+  for (int t = 0; t < PF; ++t) load(ring[t], d0 - 1 + t);
   double uw = 0.0, subw = 0.0, Fe_p = 0.0, Fn_p = 0.0;
   for (int sb = 0; sb < kRSteps; sb += PF) {
 #pragma unroll
@@ -738,18 +758,12 @@ __global__ void __launch_bounds__(kRWaves * 64) k_resid(TArgs a) {
       RSlot<T> &sl = ring[t];
       uw = uc; uc = ue; ue = (double)sl.ib + sl.dq;
       if constexpr (kF32) { subw = subc; subc = sube; sube = sl.sube; }
-      double uS = shr1(uw), uN = shl1(ue), FnS = shr1(Fn_p), sS = 0.0;
-      if constexpr (kF32) sS = shr1(subw);
-      {
-        const double hu_l = rdlane(hu, dd + 1), hf_l = rdlane(hf, dd < 0 ? 0 : dd);
-        const double hn_l = rdlane(hnv, dd + 1);
-        if (lane == 0) { uS = hu_l; FnS = hf_l; }
-        if (lane == 63) uN = hn_l;
-        if constexpr (kF32) {
-          const double hs_l = rdlane(hsb, dd + 1);
-          if (lane == 0) sS = hs_l;
-        }
-      }
+      // row below lane 0 / above lane 63 from the halo (LDS broadcasts)
+      const double uS = shr1_fill(uw, hal[wave][0][dd + 1]);
+      const double FnS = shr1_fill(Fn_p, hal[wave][1][dd < 0 ? 0 : dd]);
+      const double uN = shl1_fill(ue, hal[wave][2][dd + 1]);
+      double sS = 0.0;
+      if constexpr (kF32) sS = shr1_fill(subw, hal[wave][3][dd + 1]);
       const int x = d0 + dd - y;
       const double UE = x + 1 < nx ? ue : uc, UW = x > 0 ? uw : uc;
       const double UN = hn ? uN : uc, US = hs ? uS : uc;
@@ -765,13 +779,47 @@ __global__ void __launch_bounds__(kRWaves * 64) k_resid(TArgs a) {
         t0 = x > 0 ? tw : t0;
         const double ts = fma(-(ay * inv), kF32 ? uS - sS : uS, t0);
         t0 = hs ? ts : t0;
-        buf_store((T)(t0 + r * inv), Ob, ok ? (unsigned)sl.ic * (unsigned)sizeof(T) : kNoCell);
+        buf_store((T)(t0 + r * inv), Ob, ok ? sl.ic * (unsigned)sizeof(T) : kNoCell);
       }
       Fe_p = Fe;
       Fn_p = Fn;
-      load(sl);                               // past the tile: clamped, unused
+      load(sl, d0 + dd + PF);                 // past the tile: unused
     }
   }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kRWaves * 64) k_resid(TArgs a) {
+  if (a.state[1] != 0) return;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform per wave
+  // workgroup b runs on XCD b % 8; each XCD takes a contiguous run of
+  // ordinate groups (quadrant-sorted) and walks the tiles for them
+  const int K = a.K, G = (K + kRWaves - 1) / kRWaves;
+  const int xc = blockIdx.x & 7, bi = blockIdx.x >> 3;
+  const int gcnt = (G - xc + 7) >> 3;
+  if (gcnt <= 0) return;
+  const int tile = bi / gcnt;
+  if (tile >= a.n_rtiles) return;
+  int gstart = 0;
+  for (int xp = 0; xp < xc; ++xp) gstart += (G - xp + 7) >> 3;
+  const int kk = (gstart + bi % gcnt) * kRWaves + wave;
+  if (kk >= K) return;
+  resid_tile<T>(a, tile, kk, wave);
+}
+
+// Batched residual: one workgroup per item (problem, tile, group of four
+// ordinates) of every problem that has not finished.
+template <typename T>
+__global__ void __launch_bounds__(kRWaves * 64) k_resid_batch(const TArgs *targs,
+                                                             const int4 *items) {
+  const __attribute__((address_space(4))) int *it =
+      (const __attribute__((address_space(4))) int *)items + 4 * blockIdx.x;
+  CTArgs &a = targs_at(targs, it[0]);
+  if (a.state[1] != 0) return;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int kk = it[2] * kRWaves + wave;
+  if (kk >= a.K) return;
+  resid_tile<T>(a, it[1], kk, wave);
 }
 
 // Recurrence v = bv + cx v_W + cy v_S for one ordinate per workgroup; lane t
@@ -792,13 +840,11 @@ constexpr int kCMaxW = 16;           // up to 1024 rows per pass
 // Loads use the index dso[d] + y of the lane's row on the step's diagonal
 // d: for a lane with no cell it points at another diagonal or out of the
 // buffer (the hardware returns 0 there), and the value is never used.
-template <typename T, bool MULTI>
-__global__ void __launch_bounds__(kCMaxW * 64) k_chain(TArgs a) {
-  if (a.state[1] != 0) return;
+template <typename T, bool MULTI, class A>
+__device__ __forceinline__ void chain_ordinate(A &a, const int kk) {
   constexpr int PF = kCPF, LAG = kCLag, R = 4 * kCLag;
   static_assert((R & (R - 1)) == 0 && LAG == PF, "ring sizes");
   static_assert(kCMaxW * kCLag + 2 * kCPF <= kDiagPad, "diagonal table padding");
-  const int kk = xcd_ordinate(blockIdx.x, a.K);
   const int q = quadrant_of(a, kk);
   const int nx = a.nx, ny = a.ny, N = a.N;
   const int tid = threadIdx.x, lane = tid & 63;
@@ -889,6 +935,33 @@ __global__ void __launch_bounds__(kCMaxW * 64) k_chain(TArgs a) {
   }
 }
 
+template <typename T, bool MULTI>
+__global__ void __launch_bounds__(kCMaxW * 64) k_chain(TArgs a) {
+  if (a.state[1] != 0) return;
+  chain_ordinate<T, MULTI>(a, xcd_ordinate(blockIdx.x, a.K));
+}
+
+// Batched recurrence: a persistent launch whose workgroups take work items
+// (problem, ordinate) from a shared counter in the order of the item table
+// (longest first) and run the recurrence with that problem's arguments, in
+// row passes of blockDim rows; problems that have finished are skipped.
+// Every workgroup leaves once the counter passes the table.
+template <typename T>
+__global__ void __launch_bounds__(kCMaxW * 64)
+    k_chain_batch(const TArgs *targs, const int2 *items, int n_items, int *counter) {
+  __shared__ int s_item;
+  while (true) {
+    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+    __syncthreads();
+    const int it = s_item;
+    __syncthreads();
+    if (it >= n_items) break;
+    const int2 pk = items[it];
+    CTArgs &a = targs_at(targs, pk.x);
+    if (a.state[1] == 0) chain_ordinate<T, true>(a, pk.y);
+  }
+}
+
 __global__ void k_zero_int(int *p) { *p = 0; }
 
 // phi, F of I^{m+1/2} in two passes: per quadrant, one thread per stored
@@ -913,12 +986,30 @@ __device__ __forceinline__ void moments_q(const TArgs &a, double *part, const lo
   dg_cell(t, a.nx, a.ny, x, y);
   const int c = gcell(a, q, x, y);
   const T *O = Iout_of<T>(a);
+  // weights through the constant address space (scalar loads); the
+  // ordinates' values are loaded eight at a time before they are summed,
+  // in the same order as one at a time
+  typedef const __attribute__((address_space(4))) double cdouble;
+  cdouble *W = (cdouble *)a.w, *WM = (cdouble *)a.wmu, *WE = (cdouble *)a.weta;
   double s0 = 0, sx = 0, sy = 0;
-  for (int kk = a.qoff[q]; kk < a.qoff[q + 1]; ++kk) {
+  int kk = a.qoff[q];
+  const int ke = a.qoff[q + 1];
+  for (; kk + 8 <= ke; kk += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = (double)O[(size_t)(kk + u) * a.N + t];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      s0 += W[kk + u] * v[u];
+      sx += WM[kk + u] * v[u];
+      sy += WE[kk + u] * v[u];
+    }
+  }
+  for (; kk < ke; ++kk) {
     const double v = (double)O[(size_t)kk * a.N + t];
-    s0 += a.w[kk] * v;
-    sx += a.wmu[kk] * v;
-    sy += a.weta[kk] * v;
+    s0 += W[kk] * v;
+    sx += WM[kk] * v;
+    sy += WE[kk] * v;
   }
   part[(size_t)(3 * q) * a.N + c] = s0;
   part[(size_t)(3 * q + 1) * a.N + c] = sx;
@@ -1127,6 +1218,39 @@ const void *batch_kernel_for(int cfg, bool fp32) {
 
 const BatchSweepConfig kBatchSweepConfigs[kNumBatchSweepConfigs] = {
     {64, 4}, {64, 6}, {128, 4}, {128, 6}, {256, 4}, {512, 2}};
+
+const BatchSweepConfig kBatchChainConfigs[kNumBatchChainConfigs] = {
+    {64, kCPF}, {128, kCPF}, {256, kCPF}, {512, kCPF}};
+static_assert(kResidWaves == kRWaves, "residual items hold kRWaves ordinates");
+
+int chain_batch_blocks_per_cu(int cfg, bool fp32) {
+  int nb = 0;
+  const void *k = fp32 ? reinterpret_cast<const void *>(&k_chain_batch<float>)
+                       : reinterpret_cast<const void *>(&k_chain_batch<double>);
+  if (cfg < 0 || cfg >= kNumBatchChainConfigs ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, kBatchChainConfigs[cfg].rows, 0) !=
+          hipSuccess)
+    return 0;
+  return nb;
+}
+
+void launch_resid_batch(const void *targs, const int4 *items, int n_items, bool fp32,
+                        hipStream_t s) {
+  const TArgs *ta = reinterpret_cast<const TArgs *>(targs);
+  if (fp32) hipLaunchKernelGGL(k_resid_batch<float>, dim3(n_items), dim3(kRWaves * 64), 0, s, ta, items);
+  else hipLaunchKernelGGL(k_resid_batch<double>, dim3(n_items), dim3(kRWaves * 64), 0, s, ta, items);
+}
+
+void launch_chain_batch(const void *targs, const int2 *items, int n_items, int *counter, int cfg,
+                        bool fp32, int grid, hipStream_t s) {
+  const TArgs *ta = reinterpret_cast<const TArgs *>(targs);
+  const int rows = kBatchChainConfigs[cfg].rows;
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, counter);
+  if (fp32)
+    hipLaunchKernelGGL(k_chain_batch<float>, dim3(grid), dim3(rows), 0, s, ta, items, n_items, counter);
+  else
+    hipLaunchKernelGGL(k_chain_batch<double>, dim3(grid), dim3(rows), 0, s, ta, items, n_items, counter);
+}
 
 int sweep_batch_blocks_per_cu(int cfg, bool fp32) {
   int nb = 0;

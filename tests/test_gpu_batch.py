@@ -109,6 +109,29 @@ def test_batch_matches_single_plans(ctx):
     b.close()
 
 
+def test_batch_sweep_forms_agree(ctx, monkeypatch):
+    """The batch's split transport step (residual items, then the
+    persistent recurrence) and its fused persistent sweep give the same
+    iterates; the tuning reports the configuration table of the form used."""
+    probs = _mixed()
+    out = {}
+    for ref in ("0", "2"):
+        monkeypatch.setenv("GSIS_SWEEP_REFERENCE", ref)
+        _say("batch sweep form %s" % ref)
+        b = gsis.Batch(ctx, probs, tol=0.0, max_iter=3, synth_rtol=1e-15, synth_max_iter=300)
+        b.iterate(3)
+        tun = b.tuning()
+        _say("  tuning %s" % tun)
+        assert len(tun["configs"]) == (4 if ref == "0" else 6)
+        assert all(c["ms"] > 0 for c in tun["configs"])
+        out[ref] = [b.read(i) for i in range(len(probs))]
+        b.close()
+    for i in range(len(probs)):
+        a, c = out["0"][i], out["2"][i]
+        cp = c["phi"].cpu().numpy() if hasattr(c["phi"], "cpu") else np.asarray(c["phi"])
+        assert _rel(a["phi"], cp) < 1e-10, i
+
+
 def test_full_batch_sampled(ctx):
     """The 64-problem batch (grids 64..512, 32..128 ordinates, 8 x 8 random
     blocks) at full size: after two iterations the problems small enough for
