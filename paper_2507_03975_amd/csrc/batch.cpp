@@ -158,7 +158,9 @@ gsis_status build_tables(gsis_batch *b, const std::vector<int> &act) {
     std::vector<int4> ri;
     for (int a = 0; a < n; ++a) {
       const PlanDev &P = b->subs[act[a]]->P;
-      const int groups = (P.K + kResidWaves - 1) / kResidWaves;
+      int pairs = 0;
+      for (int q = 0; q < 4; ++q) pairs += (P.qoff[q + 1] - P.qoff[q] + 1) / 2;
+      const int groups = (pairs + kResidWaves - 1) / kResidWaves;
       for (int t = 0; t < P.n_rtiles; ++t)
         for (int g = 0; g < groups; ++g) ri.push_back(make_int4(a, t, g, 0));
     }

@@ -194,7 +194,7 @@ extern const BatchSweepConfig kBatchSweepConfigs[kNumBatchSweepConfigs];
 constexpr int kNumBatchChainConfigs = 4;
 extern const BatchSweepConfig kBatchChainConfigs[kNumBatchChainConfigs];
 int chain_batch_blocks_per_cu(int cfg, bool fp32);
-constexpr int kResidWaves = 4;     // ordinates per residual item
+constexpr int kResidWaves = 4;     // ordinate pairs (of one quadrant) per residual item
 void launch_resid_batch(const void *targs, const int4 *items, int n_items, bool fp32,
                         hipStream_t s);
 void launch_chain_batch(const void *targs, const int2 *items, int n_items, int *counter, int cfg,

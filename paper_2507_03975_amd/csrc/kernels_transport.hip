@@ -638,7 +638,7 @@ __device__ inline double shl1_fill(double v, double fill) {
 
 template <typename T>
 struct RSlot {
-  T ib;                // stored value at the lookahead cell (diagonal d+1)
+  T ib[2];             // stored values at the lookahead cell (diagonal d+1), per ordinate
   double dq;           // base/(4 pi) there
   double sube;         // FP32 mode: phi^m/(4 pi) there
   double src;          // source at the cell (diagonal d)
@@ -646,19 +646,43 @@ struct RSlot {
   unsigned ic;         // its storage index
 };
 
-// One wave per (ordinate, tile). Lane l owns row y = y0 + l; at step dd its
-// cell is (d0 + dd - y, y). Each lane keeps u of its row on diagonals d-1,
-// d, d+1; u(x, y-1) and u(x, y+1) are the neighbour lanes' window values and
-// the south face value is lane l-1's F_n of the previous step (DPP shifts).
-// Row y0-1 below lane 0 and row y0+64 above lane 63 come from a halo pass in
-// which lane j computes diagonal d0-2+j (u below), d0-1+j (F_n below) and
-// d0+j (u above) into LDS; each step reads its three halo values back as
-// LDS broadcasts and feeds them to the DPP shifts as lane 0's (lane 63's)
-// fill. Loads use the index dso[d] + y through buffer resources: for a lane
-// with no cell it lies on another diagonal or out of the buffer (read as 0),
-// and the value is dropped.
+// Ordinates are taken in pairs of one quadrant (the second may be absent
+// when the quadrant has an odd count): pair number pi of a problem.
+template <class A>
+__device__ inline void ordinate_pair(A &a, int pi, int &kA, int &kB) {
+  int q = 0, base = 0;
+  for (; q < 3; ++q) {
+    const int np = (a.qoff[q + 1] - a.qoff[q] + 1) >> 1;
+    if (pi < base + np) break;
+    base += np;
+  }
+  kA = a.qoff[q] + 2 * (pi - base);
+  kB = kA + 1 < a.qoff[q + 1] ? kA + 1 : -1;
+}
+template <class A>
+__device__ inline int ordinate_pairs(A &a) {
+  int n = 0;
+  for (int q = 0; q < 4; ++q) n += (a.qoff[q + 1] - a.qoff[q] + 1) >> 1;
+  return n;
+}
+
+// One wave per (pair of ordinates of one quadrant, tile). Lane l owns row
+// y = y0 + l; at step dd its cell is (d0 + dd - y, y), the same cell for
+// both ordinates, so the cell's records (coefficients, source, pending
+// correction) are loaded once for the two. Each lane keeps u of its row on
+// diagonals d-1, d, d+1 per ordinate; u(x, y-1) and u(x, y+1) are the
+// neighbour lanes' window values and the south face value is lane l-1's F_n
+// of the previous step (DPP shifts). Row y0-1 below lane 0 and row y0+64
+// above lane 63 come from a halo pass in which lane j computes diagonal
+// d0-2+j (u below), d0-1+j (F_n below) and d0+j (u above) into LDS; each
+// step reads its halo values back as LDS broadcasts and feeds them to the
+// DPP shifts as lane 0's (lane 63's) fill. Loads use the index dso[d] + y
+// through buffer resources: for a lane with no cell it lies on another
+// diagonal or out of the buffer (read as 0), and the value is dropped.
+// kB < 0: no second ordinate (its loads repeat kA's, its stores are dropped).
 template <typename T, class A>
-__device__ __forceinline__ void resid_tile(A &a, const int tile, const int kk, const int wave) {
+__device__ __forceinline__ void resid_tile(A &a, const int tile, const int kA, const int kB,
+                                           const int wave) {
   constexpr bool kF32 = sizeof(T) == 4;
   constexpr int PF = kRPF;
   static_assert(kRSteps % PF == 0, "whole turns of the load ring");
@@ -667,12 +691,20 @@ __device__ __forceinline__ void resid_tile(A &a, const int tile, const int kk, c
   const int2 tl = a.rtiles[tile];
   const int d0 = tl.x, y0 = tl.y;
   const int nx = a.nx, ny = a.ny, N = a.N;
-  const int q = quadrant_of(a, kk);
-  const double ax = a.amu[kk], ay = a.aeta[kk];
+  const int q = quadrant_of(a, kA);
+  const bool hasB = kB >= 0;
+  const int kk[2] = {kA, hasB ? kB : kA};
+  double ax[2], ay[2];
+  __amdgpu_buffer_rsrc_t Ib[2], Ob[2];
+#pragma unroll
+  for (int o = 0; o < 2; ++o) {
+    ax[o] = a.amu[kk[o]];
+    ay[o] = a.aeta[kk[o]];
+    Ib[o] = buf_rsrc(Iin_of<T>(a) + (size_t)kk[o] * N, (size_t)N * sizeof(T));
+    Ob[o] = buf_rsrc(Iout_of<T>(a) + (size_t)kk[o] * N, (o == 0 || hasB) ? (size_t)N * sizeof(T) : 0);
+  }
   const double hdx = 0.5 * a.dx, hdy = 0.5 * a.dy;
   const bool second = a.order >= 2, lim = a.limiter != 0;
-  const __amdgpu_buffer_rsrc_t Ib = buf_rsrc(Iin_of<T>(a) + (size_t)kk * N, (size_t)N * sizeof(T));
-  const __amdgpu_buffer_rsrc_t Ob = buf_rsrc(Iout_of<T>(a) + (size_t)kk * N, (size_t)N * sizeof(T));
   const __amdgpu_buffer_rsrc_t Cb = buf_rsrc(a.cellq + (size_t)q * N * 6, (size_t)N * 48);
   const double *SRC = a.dynq + (size_t)q * 3 * N;
   const __amdgpu_buffer_rsrc_t Sb = buf_rsrc(SRC, (size_t)N * 8);
@@ -682,9 +714,8 @@ __device__ __forceinline__ void resid_tile(A &a, const int tile, const int kk, c
       (const __attribute__((address_space(4))) int *)(a.dso + kDiagPad);
   const int y = y0 + lane;
   const bool rowok = y < ny, hn = y + 1 < ny, hs = y > 0;
-  auto uof = [&](unsigned i) { return (double)buf_ldT<T>(Ib, i) + buf_ld64(Qb, i * 8u); };
-  // ---- halo (see above) into LDS: lane j's values at [wave][slot][j]
-  __shared__ double hal[kRWaves][4][kRSteps + 1];
+  // ---- halo (see above) into LDS: lane j's values at [wave][ordinate][slot][j]
+  __shared__ double hal[kRWaves][2][4][kRSteps + 1];
   {
     auto cidx = [&](int x, int yy) {       // storage index, clamped into the grid
       x = min(max(x, 0), nx - 1);
@@ -693,53 +724,69 @@ __device__ __forceinline__ void resid_tile(A &a, const int tile, const int kk, c
     };
     const int ys = y0 - 1;
     const int xu = d0 - 2 + lane - ys, xf = d0 - 1 + lane - ys, xn = d0 + lane - (y0 + 64);
-    const unsigned iu = cidx(xu, ys), jf = cidx(xf, ys);
-    const double vu = uof(iu), vf = uof(jf);
-    const double ve = uof(cidx(xf + 1, ys)), vw = uof(cidx(xf - 1, ys));
-    const double vn = uof(cidx(xf, y0)), vs = uof(cidx(xf, ys - 1));
+    const unsigned iu = cidx(xu, ys), jf = cidx(xf, ys), je = cidx(xf + 1, ys);
+    const unsigned jw = cidx(xf - 1, ys), jn = cidx(xf, y0), js = cidx(xf, ys - 1);
+    const unsigned iN = cidx(xn, y0 + 64);
     const double2 f0 = buf_ld128(Cb, jf * 48u), f1 = buf_ld128(Cb, jf * 48u + 16u);
-    const double vN = uof(cidx(xn, y0 + 64));
     const double su = kF32 ? buf_ld64(Ub, iu * 8u) : 0.0;
+    const double qu = buf_ld64(Qb, iu * 8u), qf = buf_ld64(Qb, jf * 8u);
+    const double qe = buf_ld64(Qb, je * 8u), qw = buf_ld64(Qb, jw * 8u);
+    const double qn = buf_ld64(Qb, jn * 8u), qs = buf_ld64(Qb, js * 8u), qN = buf_ld64(Qb, iN * 8u);
     const int xi = min(d0 + lane, nx - 1);
     const int gi = (q & 1) ? nx - 1 - xi : xi;
-    const double vin = a.bnd[(size_t)((q & 2) ? 2 * ny + nx + gi : 2 * ny + gi) * a.K + kk];
-    double Fe, Fn;
-    face_pair(vf, xf + 1 < nx ? ve : vf, xf > 0 ? vw : vf, vn, ys > 0 ? vs : vf, f0, f1, hdx, hdy,
-              second, lim, Fe, Fn);
-    double hu = 0.0, hsb = 0.0, hf = 0.0, hnv = 0.0;
-    if (y0 > 0) {
-      if (lane <= kRD && xu >= 0 && xu < nx) { hu = vu; hsb = su; }
-      if (lane < kRD && xf >= 0 && xf < nx) hf = Fn;
-    } else if (lane < kRD && d0 + lane < nx) {
-      hf = vin;
-    }
-    if (y0 + 64 < ny && lane <= kRD && xn >= 0 && xn < nx) hnv = vN;
-    if (lane <= kRD) {
-      hal[wave][0][lane] = hu;
-      hal[wave][1][lane] = hf;
-      hal[wave][2][lane] = hnv;
-      hal[wave][3][lane] = hsb;
+    const size_t fs = (size_t)((q & 2) ? 2 * ny + nx + gi : 2 * ny + gi) * a.K;
+#pragma unroll
+    for (int o = 0; o < 2; ++o) {
+      const double vu = (double)buf_ldT<T>(Ib[o], iu) + qu, vf = (double)buf_ldT<T>(Ib[o], jf) + qf;
+      const double ve = (double)buf_ldT<T>(Ib[o], je) + qe, vw = (double)buf_ldT<T>(Ib[o], jw) + qw;
+      const double vn = (double)buf_ldT<T>(Ib[o], jn) + qn, vs = (double)buf_ldT<T>(Ib[o], js) + qs;
+      const double vN = (double)buf_ldT<T>(Ib[o], iN) + qN;
+      const double vin = a.bnd[fs + kk[o]];
+      double Fe, Fn;
+      face_pair(vf, xf + 1 < nx ? ve : vf, xf > 0 ? vw : vf, vn, ys > 0 ? vs : vf, f0, f1, hdx,
+                hdy, second, lim, Fe, Fn);
+      double hu = 0.0, hsb = 0.0, hf = 0.0, hnv = 0.0;
+      if (y0 > 0) {
+        if (lane <= kRD && xu >= 0 && xu < nx) { hu = vu; hsb = su; }
+        if (lane < kRD && xf >= 0 && xf < nx) hf = Fn;
+      } else if (lane < kRD && d0 + lane < nx) {
+        hf = vin;
+      }
+      if (y0 + 64 < ny && lane <= kRD && xn >= 0 && xn < nx) hnv = vN;
+      if (lane <= kRD) {
+        hal[wave][o][0][lane] = hu;
+        hal[wave][o][1][lane] = hf;
+        hal[wave][o][2][lane] = hnv;
+        hal[wave][o][3][lane] = hsb;
+      }
     }
   }
   // inflow on the local west face of the lane's row
-  double inW;
+  double inW[2];
   {
     const int yr = min(y, ny - 1);
     const int j = (q & 2) ? ny - 1 - yr : yr;
-    inW = a.bnd[(size_t)((q & 1) ? ny + j : j) * a.K + kk];
+    const size_t fw = (size_t)((q & 1) ? ny + j : j) * a.K;
+    inW[0] = a.bnd[fw + kk[0]];
+    inW[1] = a.bnd[fw + kk[1]];
   }
   // ---- window u(d0-2, y), u(d0-1, y); then the load ring from step -1
-  double uc, ue, subc = 0.0, sube = 0.0;
+  double uc[2], ue[2], subc = 0.0, sube = 0.0;
   {
     const unsigned i0 = (unsigned)(DS[d0 - 2] + y), i1 = (unsigned)(DS[d0 - 1] + y);
-    uc = uof(i0);
-    ue = uof(i1);
+    const double q0 = buf_ld64(Qb, i0 * 8u), q1 = buf_ld64(Qb, i1 * 8u);
+#pragma unroll
+    for (int o = 0; o < 2; ++o) {
+      uc[o] = (double)buf_ldT<T>(Ib[o], i0) + q0;
+      ue[o] = (double)buf_ldT<T>(Ib[o], i1) + q1;
+    }
     if constexpr (kF32) { subc = buf_ld64(Ub, i0 * 8u); sube = buf_ld64(Ub, i1 * 8u); }
   }
   auto load = [&](RSlot<T> &sl, int d) {     // cell on diagonal d, lookahead on d + 1
     const unsigned ic = (unsigned)(DS[d] + y), il = (unsigned)(DS[d + 1] + y);
     sl.ic = ic;
-    sl.ib = buf_ldT<T>(Ib, il);
+    sl.ib[0] = buf_ldT<T>(Ib[0], il);
+    sl.ib[1] = buf_ldT<T>(Ib[1], il);
     sl.dq = buf_ld64(Qb, il * 8u);
     if constexpr (kF32) sl.sube = buf_ld64(Ub, il * 8u);
     sl.src = buf_ld64(Sb, ic * 8u);
@@ -750,39 +797,42 @@ __device__ __forceinline__ void resid_tile(A &a, const int tile, const int kk, c
   RSlot<T> ring[PF];
 #pragma unroll
   for (int t = 0; t < PF; ++t) load(ring[t], d0 - 1 + t);
-  double uw = 0.0, subw = 0.0, Fe_p = 0.0, Fn_p = 0.0;
+  double uw[2] = {0.0, 0.0}, Fe_p[2] = {0.0, 0.0}, Fn_p[2] = {0.0, 0.0}, subw = 0.0;
   for (int sb = 0; sb < kRSteps; sb += PF) {
 #pragma unroll
     for (int t = 0; t < PF; ++t) {
       const int dd = sb + t - 1;              // diagonal d0 + dd
       RSlot<T> &sl = ring[t];
-      uw = uc; uc = ue; ue = (double)sl.ib + sl.dq;
       if constexpr (kF32) { subw = subc; subc = sube; sube = sl.sube; }
-      // row below lane 0 / above lane 63 from the halo (LDS broadcasts)
-      const double uS = shr1_fill(uw, hal[wave][0][dd + 1]);
-      const double FnS = shr1_fill(Fn_p, hal[wave][1][dd < 0 ? 0 : dd]);
-      const double uN = shl1_fill(ue, hal[wave][2][dd + 1]);
       double sS = 0.0;
-      if constexpr (kF32) sS = shr1_fill(subw, hal[wave][3][dd + 1]);
+      if constexpr (kF32) sS = shr1_fill(subw, hal[wave][0][3][dd + 1]);
       const int x = d0 + dd - y;
-      const double UE = x + 1 < nx ? ue : uc, UW = x > 0 ? uw : uc;
-      const double UN = hn ? uN : uc, US = hs ? uS : uc;
-      double Fe, Fn;
-      face_pair(uc, UE, UW, UN, US, sl.c0, sl.c1, hdx, hdy, second, lim, Fe, Fn);
-      {
-        const bool ok = dd >= 0 && rowok && x >= 0 && x < nx;
-        const double FeW = x > 0 ? Fe_p : inW;
-        const double r = sl.src - sl.st.x * uc - ax * (Fe - FeW) - ay * (Fn - FnS);
-        const double inv = rcp64(sl.st.y + (ax + ay));   // as in the recurrence
-        double t0 = kF32 ? uc - subc : uc;
-        const double tw = fma(-(ax * inv), kF32 ? uw - subw : uw, t0);
+      const bool ok = dd >= 0 && rowok && x >= 0 && x < nx;
+      const double inv0 = sl.st.y;
+#pragma unroll
+      for (int o = 0; o < 2; ++o) {
+        uw[o] = uc[o]; uc[o] = ue[o]; ue[o] = (double)sl.ib[o] + sl.dq;
+        // row below lane 0 / above lane 63 from the halo (LDS broadcasts)
+        const double uS = shr1_fill(uw[o], hal[wave][o][0][dd + 1]);
+        const double FnS = shr1_fill(Fn_p[o], hal[wave][o][1][dd < 0 ? 0 : dd]);
+        const double uN = shl1_fill(ue[o], hal[wave][o][2][dd + 1]);
+        const double u = uc[o];
+        const double UE = x + 1 < nx ? ue[o] : u, UW = x > 0 ? uw[o] : u;
+        const double UN = hn ? uN : u, US = hs ? uS : u;
+        double Fe, Fn;
+        face_pair(u, UE, UW, UN, US, sl.c0, sl.c1, hdx, hdy, second, lim, Fe, Fn);
+        const double FeW = x > 0 ? Fe_p[o] : inW[o];
+        const double r = sl.src - sl.st.x * u - ax[o] * (Fe - FeW) - ay[o] * (Fn - FnS);
+        const double inv = rcp64(inv0 + (ax[o] + ay[o]));   // as in the recurrence
+        double t0 = kF32 ? u - subc : u;
+        const double tw = fma(-(ax[o] * inv), kF32 ? uw[o] - subw : uw[o], t0);
         t0 = x > 0 ? tw : t0;
-        const double ts = fma(-(ay * inv), kF32 ? uS - sS : uS, t0);
+        const double ts = fma(-(ay[o] * inv), kF32 ? uS - sS : uS, t0);
         t0 = hs ? ts : t0;
-        buf_store((T)(t0 + r * inv), Ob, ok ? sl.ic * (unsigned)sizeof(T) : kNoCell);
+        buf_store((T)(t0 + r * inv), Ob[o], ok ? sl.ic * (unsigned)sizeof(T) : kNoCell);
+        Fe_p[o] = Fe;
+        Fn_p[o] = Fn;
       }
-      Fe_p = Fe;
-      Fn_p = Fn;
       load(sl, d0 + dd + PF);                 // past the tile: unused
     }
   }
@@ -793,8 +843,8 @@ __global__ void __launch_bounds__(kRWaves * 64) k_resid(TArgs a) {
   if (a.state[1] != 0) return;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform per wave
   // workgroup b runs on XCD b % 8; each XCD takes a contiguous run of
-  // ordinate groups (quadrant-sorted) and walks the tiles for them
-  const int K = a.K, G = (K + kRWaves - 1) / kRWaves;
+  // groups of ordinate pairs (quadrant-sorted) and walks the tiles for them
+  const int G = (ordinate_pairs(a) + kRWaves - 1) / kRWaves;
   const int xc = blockIdx.x & 7, bi = blockIdx.x >> 3;
   const int gcnt = (G - xc + 7) >> 3;
   if (gcnt <= 0) return;
@@ -802,13 +852,15 @@ __global__ void __launch_bounds__(kRWaves * 64) k_resid(TArgs a) {
   if (tile >= a.n_rtiles) return;
   int gstart = 0;
   for (int xp = 0; xp < xc; ++xp) gstart += (G - xp + 7) >> 3;
-  const int kk = (gstart + bi % gcnt) * kRWaves + wave;
-  if (kk >= K) return;
-  resid_tile<T>(a, tile, kk, wave);
+  const int pi = (gstart + bi % gcnt) * kRWaves + wave;
+  if (pi >= ordinate_pairs(a)) return;
+  int kA, kB;
+  ordinate_pair(a, pi, kA, kB);
+  resid_tile<T>(a, tile, kA, kB, wave);
 }
 
 // Batched residual: one workgroup per item (problem, tile, group of four
-// ordinates) of every problem that has not finished.
+// ordinate pairs) of every problem that has not finished.
 template <typename T>
 __global__ void __launch_bounds__(kRWaves * 64) k_resid_batch(const TArgs *targs,
                                                              const int4 *items) {
@@ -817,9 +869,11 @@ __global__ void __launch_bounds__(kRWaves * 64) k_resid_batch(const TArgs *targs
   CTArgs &a = targs_at(targs, it[0]);
   if (a.state[1] != 0) return;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int kk = it[2] * kRWaves + wave;
-  if (kk >= a.K) return;
-  resid_tile<T>(a, it[1], kk, wave);
+  const int pi = it[2] * kRWaves + wave;
+  if (pi >= ordinate_pairs(a)) return;
+  int kA, kB;
+  ordinate_pair(a, pi, kA, kB);
+  resid_tile<T>(a, it[1], kA, kB, wave);
 }
 
 // Recurrence v = bv + cx v_W + cy v_S for one ordinate per workgroup; lane t
@@ -1143,7 +1197,9 @@ void launch_residual(const PlanDev &P, hipStream_t s) {
     hipLaunchKernelGGL(k_residual, dim3((P.N + 255) / 256, P.K), dim3(256), 0, s, a);
     return;
   }
-  const int G = (P.K + kRWaves - 1) / kRWaves;
+  int pairs = 0;
+  for (int q = 0; q < 4; ++q) pairs += (P.qoff[q + 1] - P.qoff[q] + 1) / 2;
+  const int G = (pairs + kRWaves - 1) / kRWaves;
   const int nb = 8 * ((G + 7) / 8) * P.n_rtiles;
   if (a.fp32) hipLaunchKernelGGL(k_resid<float>, dim3(nb), dim3(kRWaves * 64), 0, s, a);
   else hipLaunchKernelGGL(k_resid<double>, dim3(nb), dim3(kRWaves * 64), 0, s, a);
