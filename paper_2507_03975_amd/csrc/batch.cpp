@@ -170,12 +170,13 @@ gsis_status build_tables(gsis_batch *b, const std::vector<int> &act) {
   // -- synthetic step: descriptors and block tables
   SynthSet &S = b->S;
   std::vector<SynthDesc> D(n);
-  int max_lc = 0;
+  int max_lc = 0, min_lc = 1 << 30;
   size_t lds = 0;
   for (int a = 0; a < n; ++a) {
     const PlanDev &P = b->subs[act[a]]->P;
     D[a] = make_synth_desc(P);
     max_lc = std::max(max_lc, D[a].lc);
+    min_lc = std::min(min_lc, D[a].lc);
     lds = std::max(lds, P.S.coarse_lds);
   }
   {
@@ -187,6 +188,7 @@ gsis_status build_tables(gsis_batch *b, const std::vector<int> &act) {
   }
   S.n = n;
   S.max_lc = max_lc;
+  S.min_lc = n ? min_lc : 0;
   S.coarse_lds = lds;
   S.state0 = nullptr;
   auto nb = [](long long m) { return (int)((m + 255) / 256); };

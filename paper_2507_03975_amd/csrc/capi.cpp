@@ -278,14 +278,16 @@ gsis_status setup_synth(gsis_plan *pl, PlanDev &P, std::vector<HostLevel> &hl) {
 
   gsis_status st;
   const int N = P.N;
-  if ((st = dalloc(pl, &P.cg_r, N)) || (st = dalloc(pl, &P.cg_z, N)) ||
+  if ((st = dalloc(pl, &P.cg_r, N)) || (st = dalloc(pl, &P.cg_r2, N)) ||
+      (st = dalloc(pl, &P.cg_z, N)) ||
       (st = dalloc(pl, &P.cg_p, N)) || (st = dalloc(pl, &P.cg_p2, N)) ||
       (st = dalloc(pl, &P.cg_Ap, N)) || (st = dalloc(pl, &P.scal, 16)))
     return st;
-  // block partials: p.Ap, r.r, b.b (one per 256 cells each), then r.z (one
-  // per level-0 multigrid tile)
+  // block partials: p.Ap, r.r, b.b (one per 256 cells each), then r.z and
+  // the r.r of the level-0 tile kernel (one per level-0 multigrid tile each)
   P.red_blocks = (N + 255) / 256;
-  if ((st = dalloc(pl, &P.red, 3 * (size_t)P.red_blocks + tiles_of(P.nx, P.ny) + 2))) return st;
+  if ((st = dalloc(pl, &P.red, 3 * (size_t)P.red_blocks + 2 * (size_t)tiles_of(P.nx, P.ny) + 2)))
+    return st;
   P.mg.resize(hl.size());
   for (size_t l = 0; l < hl.size(); ++l) {
     MGLevel &L = P.mg[l];
@@ -317,6 +319,7 @@ gsis_status make_single_set(gsis_plan *pl) {
   auto nb = [](int n) { return (n + 255) / 256; };
   S.n = 1;
   S.max_lc = D.lc;
+  S.min_lc = D.lc;
   P.lc = D.lc;
   S.coarse_lds = coarse_lds_bytes(P);
   S.synth_max_iter = P.synth_max_iter;

@@ -80,7 +80,8 @@ struct SynthDesc {
   const double *sig_t, *sig_s, *q, *cE, *cW, *cN, *cS, *kappa;
   const double *phih, *Fx, *Fy, *bflux;
   double *hx, *hy, *rhs, *phi, *delta, *base, *src, *dynq;
-  double *cg_r, *cg_z, *cg_p0, *cg_p1, *cg_Ap, *red, *scal, *err_parts, *err_hist, *last_err;
+  // r of the CG alternates between cg_r and cg_r2 with the V-cycle count
+  double *cg_r, *cg_r2, *cg_z, *cg_p0, *cg_p1, *cg_Ap, *red, *scal, *err_parts, *err_hist, *last_err;
   int32_t *state;
   int nlev, lc;                 // levels; first level of the one-workgroup cycle
   int ntile0;                   // multigrid tiles of level 0
@@ -93,6 +94,7 @@ struct SynthSet {
   int n = 0;                          // problems
   SynthDesc *desc = nullptr;          // device [n]
   int max_lc = 0;                     // deepest first coarse level
+  int min_lc = 0;                     // shallowest first coarse level
   size_t coarse_lds = 0;              // dynamic LDS of the coarse kernel
   int synth_max_iter = 50;
   // block tables (nullptr for a single problem) and their block counts
@@ -154,7 +156,8 @@ struct PlanDev {
   std::vector<MGLevel> mg;
   double *coarse_inv = nullptr;  // dense inverse of the coarsest operator
   int coarse_n = 0;
-  double *cg_r = nullptr, *cg_z = nullptr, *cg_p = nullptr, *cg_p2 = nullptr, *cg_Ap = nullptr;
+  double *cg_r = nullptr, *cg_r2 = nullptr, *cg_z = nullptr, *cg_p = nullptr, *cg_p2 = nullptr;
+  double *cg_Ap = nullptr;
   double *red = nullptr;       // block partial sums
   double *scal = nullptr;      // device scalars (see kernels_synth.hip)
   int red_blocks = 0;

@@ -29,14 +29,41 @@ namespace {
 
 constexpr int kRedBlock = 256;
 
+// v of the lane given by DPP control C (a permutation within rows of 16)
+template <int C>
+__device__ inline double dpp_d(double v) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)u, C, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), C, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+__device__ inline double read_lane(double v, int lane) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = __builtin_amdgcn_readlane((int)(unsigned)u, lane);
+  const unsigned hi = __builtin_amdgcn_readlane((int)(unsigned)(u >> 32), lane);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+// Sum over a full wave in a fixed order: quads by the lane permutations
+// xor 1 and xor 2 (every lane of a quad ends with the same sum, as addition
+// commutes exactly), the four quads of a row by rotations of 4 and 8, then
+// the four rows' sums read as scalars and added pairwise.
+__device__ inline double wave_sum(double v) {
+  v += dpp_d<0xB1>(v);    // quad_perm [1,0,3,2]
+  v += dpp_d<0x4E>(v);    // quad_perm [2,3,0,1]
+  v += dpp_d<0x124>(v);   // row_ror:4
+  v += dpp_d<0x128>(v);   // row_ror:8
+  return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
+}
+
+// Sum over the block (every lane of it active, blockDim a multiple of 64):
+// wave sums, then the waves' sums in wave order. Every thread gets the same
+// value; sh needs one entry per wave.
 __device__ inline double block_sum(double v, double *sh) {
-  sh[threadIdx.x] = v;
+  const double w = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = w;
   __syncthreads();
-  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
-    if ((int)threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
-    __syncthreads();
-  }
-  double r = sh[0];
+  double r = 0.0;
+  for (int k = 0; k < (int)(blockDim.x >> 6); ++k) r += sh[k];
   __syncthreads();
   return r;
 }
@@ -139,6 +166,11 @@ enum { S_RZ = 0, S_PAP = 1, S_RR = 2, S_BB = 3, S_ALPHA = 4, S_BETA = 5, S_STOP 
        S_NIT = 7, S_RZ1 = 8 };
 __host__ __device__ inline int rz_slot(int k) { return (k & 1) ? S_RZ1 : S_RZ; }
 
+// r of V-cycle v (v = 0 after the warm start, v = it + 1 after CG iteration
+// it): the buffers alternate, so a kernel that forms r_{v} for its tile and
+// halo never overwrites the r_{v-1} that neighbouring tiles still read.
+__device__ inline double *cg_rv(CDesc &D, int v) { return (v & 1) ? D.cg_r2 : D.cg_r; }
+
 // CG kernels run unless the outer iteration is done (state[1]) or this
 // synthetic solve has converged (state[3]).
 __device__ inline bool cg_off(const int32_t *st) { return st[1] != 0 || st[3] != 0; }
@@ -149,7 +181,8 @@ __host__ __device__ inline int nblk_d(int n) { return (n + kRedBlock - 1) / kRed
 // Block partials of a problem's reductions, in separate regions of its red
 // array (nb = level-0 blocks of 256 cells): [0, nb) p.Ap, [nb, 2 nb) r.r,
 // [2 nb, 3 nb) b.b, then r.z (one per level-0 tile, or a single value when
-// the whole V-cycle ran in one workgroup). A reduction is finished by the
+// the whole V-cycle ran in one workgroup), then r.r once more, one per
+// level-0 tile, from the tile kernel that makes the CG update. A reduction is finished by the
 // kernel that needs its value: every block of it sums the partials in the
 // same fixed order, so all blocks hold the same number and results repeat
 // bit for bit; block 0 stores it for later kernels. This saves a launch
@@ -160,6 +193,7 @@ __device__ inline double *red_pap(CDesc &D) { return D.red; }
 __device__ inline double *red_rr(CDesc &D) { return D.red + nblk_d(D.N); }
 __device__ inline double *red_bb(CDesc &D) { return D.red + 2 * nblk_d(D.N); }
 __device__ inline double *red_rz(CDesc &D) { return D.red + 3 * nblk_d(D.N); }
+__device__ inline double *red_rrt(CDesc &D) { return D.red + 3 * nblk_d(D.N) + D.ntile0; }
 __device__ inline int n_rz(CDesc &D) { return D.lc == 0 ? 1 : D.ntile0; }
 
 __device__ inline double sum_partials(const double *p, int n, double *sh) {
@@ -168,13 +202,16 @@ __device__ inline double sum_partials(const double *p, int n, double *sh) {
   return block_sum(v, sh);
 }
 
-// r.r of the iterate just updated: iteration count and convergence test
-// against STOP; first (after the warm start): also b.b, the count reset and
-// STOP = max(rtol^2 r0.r0, 1e-28 b.b). Every thread of the block returns
-// the same decision; thread 0 stores the scalars and the flag.
-__device__ inline bool finish_rr(CDesc &D, bool first, double *sh) {
+// r.r of the iterate just updated (partials per level-0 tile when the tile
+// kernel made the update, else per block of cells): iteration count and
+// convergence test against STOP; first (after the warm start): also b.b,
+// the count reset and STOP = max(rtol^2 r0.r0, 1e-28 b.b). Every thread of
+// the block returns the same decision; thread 0 stores the scalars and the
+// flag.
+__device__ inline bool finish_rr(CDesc &D, bool first, bool tiles, double *sh) {
   const int nb = nblk_d(D.N);
-  const double rr = sum_partials(red_rr(D), nb, sh);
+  const double rr = tiles ? sum_partials(red_rrt(D), D.ntile0, sh)
+                          : sum_partials(red_rr(D), nb, sh);
   double stop;
   double bb = 0.0;
   if (first) {
@@ -205,7 +242,7 @@ __global__ void k_finish_rr(const SynthDesc *ds) {
   __shared__ double sh[kRedBlock];
   CDesc &D = cdesc(ds, blockIdx.x);
   if (cg_off(D.state)) return;
-  (void)finish_rr(D, false, sh);
+  (void)finish_rr(D, false, false, sh);
 }
 
 // Start of a synthetic solve: warm start x = phi, clear the converged flag;
@@ -299,18 +336,21 @@ __global__ void k_cg_pAp(const SynthDesc *ds, const int2 *bt, int it) {
 }
 
 // CG iteration it: alpha = r.z / p.Ap; x += alpha p ; r -= alpha Ap ;
-// partial of r.r
-__global__ void k_cg_update(const SynthDesc *ds, const int2 *bt, int it) {
+// partial of r.r. With all = 0 only problems whose whole V-cycle runs in
+// the one-workgroup kernel take part: for the others the level-0 tile
+// kernel of the next V-cycle makes the update (cg_update_tile).
+__global__ void k_cg_update(const SynthDesc *ds, const int2 *bt, int it, int all) {
   __shared__ double sh[kRedBlock];
   const Blk B = blk(bt);
   CDesc &D = cdesc(ds, B.p);
+  if (!all && D.lc > 0) return;
   const int32_t f1 = D.state[1], f3 = D.state[3];
   const int c = B.lb * kRedBlock + threadIdx.x;
   const double *p = (it & 1) ? D.cg_p0 : D.cg_p1;
   double *x = D.lev[0].x;
   const bool in = c < D.N;
   const int cc = in ? c : 0;
-  const double pc = p[cc], xc = x[cc], rc0 = D.cg_r[cc], apc = D.cg_Ap[cc];
+  const double pc = p[cc], xc = x[cc], rc0 = cg_rv(D, it)[cc], apc = D.cg_Ap[cc];
   if (f1 != 0 || f3 != 0) return;
   const double pap = sum_partials(red_pap(D), nblk_d(D.N), sh);
   const double al = D.scal[rz_slot(it)] / pap;
@@ -320,9 +360,9 @@ __global__ void k_cg_update(const SynthDesc *ds, const int2 *bt, int it) {
   }
   double v = 0.0;
   if (in) {
-    x[c] = xc + al * pc;
-    const double rc = rc0 - al * apc;
-    D.cg_r[c] = rc;
+    x[c] = fma(al, pc, xc);
+    const double rc = fma(-al, apc, rc0);
+    cg_rv(D, it + 1)[c] = rc;
     v = rc * rc;
   }
   double t = block_sum(v, sh);
@@ -330,10 +370,11 @@ __global__ void k_cg_update(const SynthDesc *ds, const int2 *bt, int it) {
 }
 
 // ------------------------------------------------------------ multigrid
-// Level l of a problem: vectors x, b are the CG's z, r on level 0.
+// Level l of a problem: vectors x, b are the CG's z, r on level 0 (r of
+// V-cycle v).
 __device__ inline double *lev_x(CDesc &D, int l) { return l == 0 ? D.cg_z : D.lev[l].x; }
-__device__ inline const double *lev_b(CDesc &D, int l) {
-  return l == 0 ? D.cg_r : D.lev[l].b;
+__device__ inline const double *lev_b(CDesc &D, int l, int v) {
+  return l == 0 ? cg_rv(D, v) : D.lev[l].b;
 }
 
 // Fine multigrid levels, one tile of kTW x kTH cells per workgroup (one
@@ -346,7 +387,10 @@ __device__ inline const double *lev_b(CDesc &D, int l) {
 //        zero makes every value a function of b, d and the couplings within
 //        two cells, so the tile and its ring are computed without waiting
 //        for other workgroups. The pre-smoothed x of the tile goes to the
-//        level's spare vector xs, not to x.
+//        level's spare vector xs, not to x. On level 0 after a CG step it
+//        also makes that step's update (cg_update_tile): b = r_new =
+//        r_old - alpha Ap is formed on the whole region from r_old and Ap,
+//        which the previous kernel left complete.
 //  up:   black x = (b + sum a (xs_nb + omega e_parent(nb))) / d with the
 //        coarse correction e, then red x = (b + sum a x_nb) / d; the black
 //        ring is recomputed so the red cells of the tile see final
@@ -369,9 +413,11 @@ __device__ inline Tile tile_of(const LevelDev &L, int lb) {
   return {L.nx, L.ny, ti * kTW - kHalo, tj * kTH - kHalo};
 }
 
-// b, d and the east / north couplings of the region into LDS
+// b, d and the east / north couplings of the region into LDS; with ap also
+// Ap of the region into sap
 __device__ inline void load_region(const LevelDev &L, const double *b, const Tile &T, double *sb,
-                                   double *sd, double *sax, double *say) {
+                                   double *sd, double *sax, double *say,
+                                   const double *ap = nullptr, double *sap = nullptr) {
   for (int r = threadIdx.x; r < kRN; r += blockDim.x) {
     int ri, rj;
     cell_ij(r, kRW, ri, rj);
@@ -382,29 +428,76 @@ __device__ inline void load_region(const LevelDev &L, const double *b, const Til
       sd[r] = L.dg[g];
       sax[r] = gi + 1 < T.nx ? L.ax[g] : 0.0;
       say[r] = gj + 1 < T.ny ? L.ay[g] : 0.0;
+      if (ap) sap[r] = ap[g];
     } else {
       sb[r] = 0.0; sd[r] = 1.0; sax[r] = 0.0; say[r] = 0.0;
+      if (ap) sap[r] = 0.0;
     }
   }
 }
 
+// The CG update of iteration it = v - 1 folded into the level-0 tile kernel
+// of V-cycle v: alpha = r.z / p.Ap (every block sums the p.Ap partials in
+// the same order), r_v = r_{v-1} - alpha Ap on the region held in LDS (sb
+// holds r_{v-1}, sap Ap; afterwards sb holds r_v), and for the tile's own
+// cells x += alpha p, r_v to global and a partial of r_v . r_v.
+__device__ inline void cg_update_tile(CDesc &D, const Blk &B, const Tile &T, int v, double *sb,
+                                      const double *sap, double pc, double xc, double *sh) {
+  const int it = v - 1;
+  const double pap = sum_partials(red_pap(D), nblk_d(D.N), sh);
+  const double al = D.scal[rz_slot(it)] / pap;
+  if (B.lb == 0 && threadIdx.x == 0) {
+    D.scal[S_PAP] = pap;
+    D.scal[S_ALPHA] = al;
+  }
+  for (int r = threadIdx.x; r < kRN; r += blockDim.x) sb[r] = fma(-al, sap[r], sb[r]);
+  __syncthreads();
+  const int ti = threadIdx.x % kTW, tj = threadIdx.x / kTW;
+  const int r = (tj + kHalo) * kRW + ti + kHalo;
+  const int gi = T.i0 + kHalo + ti, gj = T.j0 + kHalo + tj;
+  double rr = 0.0;
+  if (gi < T.nx && gj < T.ny) {
+    const int g = gj * T.nx + gi;
+    const double rc = sb[r];
+    D.lev[0].x[g] = fma(al, pc, xc);
+    cg_rv(D, v)[g] = rc;
+    rr = rc * rc;
+  }
+  const double t = block_sum(rr, sh);
+  if (threadIdx.x == 0) red_rrt(D)[B.lb] = t;
+}
+
 __global__ void __launch_bounds__(kRedBlock) k_mg_down(const SynthDesc *ds, const int2 *bt, int l,
-                                                       int first) {
-  __shared__ double sb[kRN], sd[kRN], sax[kRN], say[kRN], sx[kRN];
-  static_assert(kRN >= kRedBlock, "sb doubles as reduction scratch");
+                                                       int v) {
+  __shared__ double sb[kRN], sd[kRN], sax[kRN], say[kRN], sx[kRN], sh[kRedBlock];
   const Blk B = blk(bt);
   CDesc &D = cdesc(ds, B.p);
   const int32_t f1 = D.state[1], f3 = D.state[3];   // tested after the region loads
   const LevelDev L = level(D, l), CL = level(D, l + 1);
-  const double *b = lev_b(D, l);
+  const bool upd = l == 0 && v > 0;
   double *xs = L.xs;
   const Tile T = tile_of(L, B.lb);
-  load_region(L, b, T, sb, sd, sax, say);
+  double pc = 0.0, xc = 0.0;
+  if (upd) {
+    // r_{v-1} and Ap of the region (Ap into sx, free until the sweeps), p
+    // and x of the thread's tile cell
+    load_region(L, cg_rv(D, v - 1), T, sb, sd, sax, say, D.cg_Ap, sx);
+    const int gi = T.i0 + kHalo + (int)threadIdx.x % kTW, gj = T.j0 + kHalo + (int)threadIdx.x / kTW;
+    if (gi < T.nx && gj < T.ny) {
+      const int g = gj * T.nx + gi;
+      pc = (((v - 1) & 1) ? D.cg_p0 : D.cg_p1)[g];
+      xc = D.lev[0].x[g];
+    }
+  } else {
+    load_region(L, lev_b(D, l, v), T, sb, sd, sax, say);
+  }
   if (f1 != 0 || f3 != 0) return;
-  // the r.r test of the CG step before this V-cycle (the other blocks go on:
-  // if it converged, their results are not used)
-  if (l == 0 && B.lb == 0) (void)finish_rr(D, first != 0, sx);
+  // the r.r test of the CG step before this V-cycle is made by the next
+  // kernel of the cycle (level 1 here, block 0; the other blocks go on: if
+  // it converged, their results are not used)
+  if (l == 1 && B.lb == 0) (void)finish_rr(D, v == 0, v > 0, sh);
   __syncthreads();
+  if (upd) cg_update_tile(D, B, T, v, sb, sx, pc, xc, sh);
   // red half sweep from zero on the whole region
   for (int r = threadIdx.x; r < kRN; r += blockDim.x) {
     int ri, rj;
@@ -448,26 +541,26 @@ __global__ void __launch_bounds__(kRedBlock) k_mg_down(const SynthDesc *ds, cons
     const int ci = threadIdx.x % cw, cj = threadIdx.x / cw;
     const int CI = ((T.i0 + kHalo) >> sx_) + ci, CJ = ((T.j0 + kHalo) >> sy_) + cj;
     if (CI < CL.nx && CJ < CL.ny) {
-      double v = 0.0;
+      double acc = 0.0;
       for (int dj = 0; dj < fy; ++dj)
         for (int di = 0; di < fx; ++di) {
           const int li = ci * fx + di, lj = cj * fy + dj;
           if (T.i0 + kHalo + li < T.nx && T.j0 + kHalo + lj < T.ny)
-            v += sb[(lj + kHalo) * kRW + li + kHalo];
+            acc += sb[(lj + kHalo) * kRW + li + kHalo];
         }
-      CL.b[CJ * CL.nx + CI] = v;
+      CL.b[CJ * CL.nx + CI] = acc;
     }
   }
 }
 
 __global__ void __launch_bounds__(kRedBlock) k_mg_up(const SynthDesc *ds, const int2 *bt, int l,
-                                                     int rz, int first, double omega) {
+                                                     int rz, int vc, double omega) {
   __shared__ double sb[kRN], sd[kRN], sax[kRN], say[kRN], sx[kRN], sh[kRedBlock];
   const Blk B = blk(bt);
   CDesc &D = cdesc(ds, B.p);
   const int32_t f1 = D.state[1], f3 = D.state[3];   // tested after the region loads
   const LevelDev L = level(D, l), CL = level(D, l + 1);
-  const double *b = lev_b(D, l);
+  const double *b = lev_b(D, l, vc);
   double *x = lev_x(D, l);
   const double *xs = L.xs;
   const double *e = CL.x;
@@ -523,7 +616,6 @@ __global__ void __launch_bounds__(kRedBlock) k_mg_up(const SynthDesc *ds, const 
     const double t = block_sum(in ? sb[r] * xv : 0.0, sh);
     if (threadIdx.x == 0) red_rz(D)[B.lb] = t;
   }
-  (void)first;
 }
 
 // The coarse end of the V-cycle (every level from the first with at most
@@ -565,16 +657,17 @@ struct OwnCell {
 };
 
 __global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(const SynthDesc *ds, double omega,
-                                                              int first) {
+                                                              int vc) {
   extern __shared__ double sm[];
   __shared__ double red[kCoarseThreads];
   CDesc &D = cdesc(ds, blockIdx.x);
   if (cg_off(D.state)) return;
-  // a problem whose whole V-cycle runs here also makes the r.r test of the
-  // CG step before it
-  if (D.lc == 0 && finish_rr(D, first != 0, red)) return;
+  // a problem whose V-cycle starts here or on level 1 makes the r.r test of
+  // the CG step before it here (level 1: the level-0 tile kernel made the
+  // update)
+  if (D.lc <= 1 && finish_rr(D, vc == 0, vc > 0 && D.lc == 1, red)) return;
   __attribute__((address_space(4))) const CoarseLevels &L = D.cl;
-  const double *bin = D.lc == 0 ? D.cg_r : D.lev[D.lc].b;
+  const double *bin = D.lc == 0 ? cg_rv(D, vc) : D.lev[D.lc].b;
   double *xout = D.lc == 0 ? D.cg_z : D.lev[D.lc].x;
   const double *Ainv = D.coarse_inv;
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -907,19 +1000,19 @@ __global__ void k_final_flux(int n, const double *Fx, const double *Fy, const do
   oy[c] = Fy[c] + d * sweta;
 }
 
-// z = M^{-1} r (one V(1,1) cycle with scaled coarse corrections) for every
-// problem of the set, then the r.z sum into scal (first: RZ = r.z;
-// otherwise beta = r.z / RZ, RZ = r.z).
-void vcycle(const SynthSet &S, bool first, hipStream_t s) {
+// z = M^{-1} r_v (one V(1,1) cycle with scaled coarse corrections) for
+// every problem of the set, with the partials of r.z. V-cycle v > 0 follows
+// CG iteration v - 1, whose update its level-0 tile kernel makes.
+void vcycle(const SynthSet &S, int v, hipStream_t s) {
   const SynthDesc *ds = S.desc;
   for (int l = 0; l < S.max_lc; ++l)
     hipLaunchKernelGGL(k_mg_down, dim3(S.nb_tile[l]), dim3(kRedBlock), 0, s, ds, S.bt_tile[l], l,
-                       first ? 1 : 0);
+                       v);
   hipLaunchKernelGGL(k_mg_coarse, dim3(S.n), dim3(kCoarseThreads), S.coarse_lds, s, ds, kOmega,
-                     first ? 1 : 0);
+                     v);
   for (int l = S.max_lc - 1; l >= 0; --l)
     hipLaunchKernelGGL(k_mg_up, dim3(S.nb_tile[l]), dim3(kRedBlock), 0, s, ds, S.bt_tile[l], l,
-                       l == 0 ? 1 : 0, first ? 1 : 0, kOmega);
+                       l == 0 ? 1 : 0, v, kOmega);
 }
 
 }  // namespace
@@ -969,7 +1062,7 @@ SynthDesc make_synth_desc(const PlanDev &P) {
   D.phih = P.phih; D.Fx = P.Fx; D.Fy = P.Fy; D.bflux = P.bflux;
   D.hx = P.hx; D.hy = P.hy; D.rhs = P.rhs; D.phi = P.phi; D.delta = P.delta; D.base = P.base;
   D.src = P.src; D.dynq = P.dynq;
-  D.cg_r = P.cg_r; D.cg_z = P.cg_z; D.cg_p0 = P.cg_p; D.cg_p1 = P.cg_p2; D.cg_Ap = P.cg_Ap;
+  D.cg_r = P.cg_r; D.cg_r2 = P.cg_r2; D.cg_z = P.cg_z; D.cg_p0 = P.cg_p; D.cg_p1 = P.cg_p2; D.cg_Ap = P.cg_Ap;
   D.red = P.red; D.scal = P.scal; D.err_parts = P.err_parts; D.err_hist = P.err_hist;
   D.last_err = P.last_err; D.state = P.state;
   D.nlev = (int)P.mg.size();
@@ -1034,16 +1127,20 @@ void launch_synth_solve(const SynthSet &S, hipStream_t s, int32_t *host_flag) {
   const SynthDesc *ds = S.desc;
   const dim3 gc(S.nb_cell), bk(kRedBlock);
   hipLaunchKernelGGL(k_cg_begin, gc, bk, 0, s, ds, S.bt_cell);
-  vcycle(S, true, s);
+  vcycle(S, 0, s);
   const int guess = host_flag ? host_flag[8] : 0;
   for (int it = 0; it < S.synth_max_iter; ++it) {
     hipLaunchKernelGGL(k_cg_pAp, gc, bk, 0, s, ds, S.bt_cell, it);
-    hipLaunchKernelGGL(k_cg_update, gc, bk, 0, s, ds, S.bt_cell, it);
     if (it + 1 == S.synth_max_iter) {
+      // no V-cycle follows: the update on its own, then the r.r test
+      hipLaunchKernelGGL(k_cg_update, gc, bk, 0, s, ds, S.bt_cell, it, 1);
       hipLaunchKernelGGL(k_finish_rr, dim3(S.n), bk, 0, s, ds);
       break;
     }
-    vcycle(S, false, s);   // its first kernel makes the r.r test of this step
+    // problems whose V-cycle runs wholly in the one-workgroup kernel have
+    // no level-0 tile kernel to make the update
+    if (S.min_lc == 0) hipLaunchKernelGGL(k_cg_update, gc, bk, 0, s, ds, S.bt_cell, it, 0);
+    vcycle(S, it + 1, s);   // makes the update (level 0) and the r.r test
     const bool due = guess > 0 ? it + 1 >= guess : (it >= 3 && ((it - 3) & 1) == 0);
     if (host_flag && S.state0 && due) {
       (void)hipMemcpyAsync(host_flag, S.state0 + 1, 3 * sizeof(int32_t), hipMemcpyDeviceToHost,
