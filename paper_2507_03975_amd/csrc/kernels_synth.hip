@@ -631,9 +631,14 @@ __global__ void __launch_bounds__(kRedBlock) k_mg_up(const SynthDesc *ds, const 
 //    levels keep theirs in LDS. Vectors live in LDS.
 //  * After the second (black) half sweep from zero the black residuals
 //    vanish, so only red cells form a residual for the restriction.
-//  * Going up, the scaled coarse correction is added to every cell first;
-//    the black half sweep then sees corrected red neighbours and both
-//    colours are recomputed (black, then red), as in the tile kernels.
+//  * Going up, the black half sweep reads its red neighbours with the
+//    scaled coarse correction added (x + omega e, formed where it is read:
+//    the corrected values of black cells are never read), then the red half
+//    sweep recomputes the red cells, as in the tile kernels.
+//  * The restriction of a level's residuals also makes the next level's
+//    first (red, from zero) half sweep, and below the top level it forms the
+//    red residuals where it reads them, so each level costs two barriers
+//    going down and two going up.
 constexpr int kCoarseWG = 4096;
 constexpr int kCoarseThreads = 1024;
 
@@ -652,6 +657,7 @@ __device__ inline bool colour_cell(int e, int k, int nx, int ny, int &i, int &j)
 // One cell of the top coarse level held by a thread.
 struct OwnCell {
   int c, cE, cW, cN, cS;       // index; neighbour indices (itself when missing)
+  int pE, pW, pN, pS;          // the neighbours' parents on the next level
   bool ok;
   double d, id, aE, aW, aN, aS, b;
 };
@@ -692,6 +698,14 @@ __global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(const SynthDesc *d
       o.c = c;
       o.cE = hE ? c + 1 : c; o.cW = hW ? c - 1 : c;
       o.cN = hN ? c + nx0 : c; o.cS = hS ? c - nx0 : c;
+      if (last > 0) {
+        const int sx = L.fx[0] >> 1, sy = L.fy[0] >> 1, cnx = L.nx[1];
+        const int iE = hE ? i + 1 : i, iW = hW ? i - 1 : i, jN = hN ? j + 1 : j, jS = hS ? j - 1 : j;
+        o.pE = (j >> sy) * cnx + (iE >> sx); o.pW = (j >> sy) * cnx + (iW >> sx);
+        o.pN = (jN >> sy) * cnx + (i >> sx); o.pS = (jS >> sy) * cnx + (i >> sx);
+      } else {
+        o.pE = o.pW = o.pN = o.pS = 0;
+      }
       o.d = o.ok ? L.dg[0][c] : 1.0;
       o.aE = hE ? L.ax[0][c] : 0.0; o.aW = hW ? L.ax[0][c - 1] : 0.0;
       o.aN = hN ? L.ay[0][c] : 0.0; o.aS = hS ? L.ay[0][c - nx0] : 0.0;
@@ -754,12 +768,56 @@ __global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(const SynthDesc *d
       x[c] = s * id[c];
     }
   };
-  // restriction of level t's residuals r_t into b_{t+1}
-  auto restrict_to = [&](int t) {
-    const int nx = L.nx[t], ny = L.ny[t], fx = L.fx[t], fy = L.fy[t];
+  // black half sweep of the top level with the coarse correction of its red
+  // neighbours formed where they are read
+  auto top_black_corr = [&]() {
+    const double *e = X(1);
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const OwnCell &o = own[1][m];
+      if (!o.ok) continue;
+      double s = o.b;
+      s = fma(o.aE, fma(omega, e[o.pE], x0[o.cE]), s);
+      s = fma(o.aW, fma(omega, e[o.pW], x0[o.cW]), s);
+      s = fma(o.aN, fma(omega, e[o.pN], x0[o.cN]), s);
+      s = fma(o.aS, fma(omega, e[o.pS], x0[o.cS]), s);
+      x0[o.c] = s * o.id;
+    }
+  };
+  // the same on level t >= 1
+  auto low_black_corr = [&](int t) {
+    const int nx = L.nx[t], ny = L.ny[t], n = nx * ny, sx = L.fx[t] >> 1, sy = L.fy[t] >> 1;
+    const int cnx = L.nx[t + 1];
+    double *x = X(t);
+    const double *e = X(t + 1);
+    const double *b = Bv(t), *id = sm + L.aoff[t], *ax = id + n, *ay = id + 2 * n;
+    auto xc = [&](int i, int j) {
+      return fma(omega, e[(j >> sy) * cnx + (i >> sx)], x[j * nx + i]);
+    };
+    for (int q = tid; 2 * q < n + 1; q += nt) {
+      int i, j;
+      if (!colour_cell(q, 1, nx, ny, i, j)) break;
+      const int c = j * nx + i;
+      double s = b[c];
+      if (i + 1 < nx) s = fma(ax[c], xc(i + 1, j), s);
+      if (i > 0) s = fma(ax[c - 1], xc(i - 1, j), s);
+      if (j + 1 < ny) s = fma(ay[c], xc(i, j + 1), s);
+      if (j > 0) s = fma(ay[c - nx], xc(i, j - 1), s);
+      x[c] = s * id[c];
+    }
+  };
+  // restriction of level t's residuals into b_{t+1} (level 0: the owners'
+  // residuals in r_0; below: the red residuals b - A x formed here, black
+  // ones being zero), and on a level t + 1 above the coarsest its red half
+  // sweep from zero, x = b / d
+  auto restrict_red = [&](int t) {
+    const int nx = L.nx[t], ny = L.ny[t], n = nx * ny, fx = L.fx[t], fy = L.fy[t];
     const int cnx = L.nx[t + 1], cn = cnx * L.ny[t + 1];
-    const double *r = Rv(t);
-    double *cb = Bv(t + 1);
+    const double *x = X(t), *b = Bv(t), *id = sm + L.aoff[t], *ax = id + n, *ay = id + 2 * n;
+    const double *dg = id + 3 * n, *r = Rv(t);
+    double *cb = Bv(t + 1), *cx = X(t + 1);
+    const double *cid = sm + L.aoff[t + 1];
+    const bool red_next = t + 1 < last;
     for (int C = tid; C < cn; C += nt) {
       int I, J;
       cell_ij(C, cnx, I, J);
@@ -767,21 +825,23 @@ __global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(const SynthDesc *d
       for (int dj = 0; dj < fy; ++dj)
         for (int di = 0; di < fx; ++di) {
           const int i = fx * I + di, j = fy * J + dj;
-          if (i < nx && j < ny) v += r[j * nx + i];
+          if (i >= nx || j >= ny) continue;
+          const int c = j * nx + i;
+          double rv = 0.0;
+          if (t == 0) {
+            rv = r[c];
+          } else if (((i + j) & 1) == 0) {
+            double q = b[c];
+            if (i + 1 < nx) q = fma(ax[c], x[c + 1], q);
+            if (i > 0) q = fma(ax[c - 1], x[c - 1], q);
+            if (j + 1 < ny) q = fma(ay[c], x[c + nx], q);
+            if (j > 0) q = fma(ay[c - nx], x[c - nx], q);
+            rv = fma(-dg[c], x[c], q);
+          }
+          v += rv;
         }
       cb[C] = v;
-    }
-  };
-  // x_t += omega e_{t+1}(parent) on every cell of level t >= 1
-  auto low_correct = [&](int t) {
-    const int nx = L.nx[t], n = nx * L.ny[t], sx = L.fx[t] >> 1, sy = L.fy[t] >> 1;
-    const int cnx = L.nx[t + 1];
-    double *x = X(t);
-    const double *e = X(t + 1);
-    for (int c = tid; c < n; c += nt) {
-      int i, j;
-      cell_ij(c, nx, i, j);
-      x[c] = fma(omega, e[(j >> sy) * cnx + (i >> sx)], x[c]);
+      if (red_next && ((I + J) & 1) == 0) cx[C] = v * cid[C];
     }
   };
   __syncthreads();
@@ -813,34 +873,13 @@ __global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(const SynthDesc *d
       if (own[1][m].ok) r0[own[1][m].c] = 0.0;
     }
     __syncthreads();
-    restrict_to(0);
+    restrict_red(0);
     __syncthreads();
-    // lower levels
+    // lower levels: black, then the restriction (with the next level's red)
     for (int t = 1; t < last; ++t) {
-      const int nx = L.nx[t], ny = L.ny[t], n = nx * ny;
-      low_half(t, 0, true);
-      __syncthreads();
       low_half(t, 1, false);
       __syncthreads();
-      const double *x = X(t), *b = Bv(t), *id = sm + L.aoff[t], *ax = id + n, *ay = id + 2 * n;
-      const double *dg = id + 3 * n;
-      double *r = Rv(t);
-      for (int c = tid; c < n; c += nt) {
-        int i, j;
-        cell_ij(c, nx, i, j);
-        double v = 0.0;
-        if (((i + j) & 1) == 0) {
-          double s = b[c];
-          if (i + 1 < nx) s = fma(ax[c], x[c + 1], s);
-          if (i > 0) s = fma(ax[c - 1], x[c - 1], s);
-          if (j + 1 < ny) s = fma(ay[c], x[c + nx], s);
-          if (j > 0) s = fma(ay[c - nx], x[c - nx], s);
-          v = fma(-dg[c], x[c], s);
-        }
-        r[c] = v;
-      }
-      __syncthreads();
-      restrict_to(t);
+      restrict_red(t);
       __syncthreads();
     }
   }
@@ -864,29 +903,12 @@ __global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(const SynthDesc *d
   // ---- up: lower levels, then the top level
   if (last > 0) {
     for (int t = last - 1; t >= 1; --t) {
-      low_correct(t);
-      __syncthreads();
-      low_half(t, 1, false);
+      low_black_corr(t);
       __syncthreads();
       low_half(t, 0, false);
       __syncthreads();
     }
-    {
-      const int sx = L.fx[0] >> 1, sy = L.fy[0] >> 1, cnx = L.nx[1];
-      const double *e = X(1);
-#pragma unroll
-      for (int k = 0; k < 2; ++k)
-#pragma unroll
-        for (int m = 0; m < 2; ++m) {
-          const OwnCell &o = own[k][m];
-          if (!o.ok) continue;
-          int i, j;
-          cell_ij(o.c, nx0, i, j);
-          x0[o.c] = fma(omega, e[(j >> sy) * cnx + (i >> sx)], x0[o.c]);
-        }
-    }
-    __syncthreads();
-    top_half(1, false);
+    top_black_corr();
     __syncthreads();
     top_half(0, false);
     __syncthreads();
