@@ -105,7 +105,7 @@ __device__ inline Blk blk(const int2 *bt) {
 __global__ void k_hot(const SynthDesc *ds, const int2 *bt) {
   const Blk B = blk(bt);
   CDesc &D = cdesc(ds, B.p);
-  if (D.state[1] != 0) return;
+  const int32_t f1 = D.state[1];   // tested after the operands are loaded
   const int nx = D.nx, ny = D.ny;
   const int c = B.lb * kRedBlock + threadIdx.x;
   if (c >= D.N) return;
@@ -117,14 +117,17 @@ __global__ void k_hot(const SynthDesc *ds, const int2 *bt) {
   const double un = j + 1 < ny ? phih[c + nx] : u, us = j > 0 ? phih[c - nx] : u;
   const double gx = D.cE[c] * (ue - u) - D.cW[c] * (uw - u);
   const double gy = D.cN[c] * (un - u) - D.cS[c] * (us - u);
-  D.hx[c] = D.Fx[c] + gx / (3.0 * D.sig_t[c]);
-  D.hy[c] = D.Fy[c] + gy / (3.0 * D.sig_t[c]);
+  const double hx = D.Fx[c] + gx / (3.0 * D.sig_t[c]);
+  const double hy = D.Fy[c] + gy / (3.0 * D.sig_t[c]);
+  if (f1 != 0) return;
+  D.hx[c] = hx;
+  D.hy[c] = hy;
 }
 
 __global__ void k_rhs(const SynthDesc *ds, const int2 *bt) {
   const Blk B = blk(bt);
   CDesc &D = cdesc(ds, B.p);
-  if (D.state[1] != 0) return;
+  const int32_t f1 = D.state[1];   // tested after the operands are loaded
   const int nx = D.nx, ny = D.ny;
   const int c = B.lb * kRedBlock + threadIdx.x;
   if (c >= D.N) return;
@@ -143,6 +146,7 @@ __global__ void k_rhs(const SynthDesc *ds, const int2 *bt) {
   else s -= dx * (bflux[2 * ny + nx + i] - kappa[2 * ny + nx + i] * ph);
   if (j > 0) s += dx * (0.5 * (hy[c] + hy[c - nx]));
   else s -= dx * (bflux[2 * ny + i] - kappa[2 * ny + i] * ph);
+  if (f1 != 0) return;
   D.rhs[c] = s;
 }
 
@@ -201,24 +205,47 @@ __device__ inline double sum_partials(const double *p, int n, double *sh) {
   for (int t = threadIdx.x; t < n; t += blockDim.x) v += p[t];
   return block_sum(v, sh);
 }
+// The thread's first partial, loaded early (before a kernel waits for its
+// flags), and the sum of all of them in the order of sum_partials.
+__device__ inline double first_partial(const double *p, int n) {
+  return (int)threadIdx.x < n ? p[threadIdx.x] : 0.0;
+}
+__device__ inline double sum_partials(const double *p, int n, double *sh, double first) {
+  double v = 0.0;
+  v += first;
+  for (int t = threadIdx.x + blockDim.x; t < n; t += blockDim.x) v += p[t];
+  return block_sum(v, sh);
+}
 
 // r.r of the iterate just updated (partials per level-0 tile when the tile
 // kernel made the update, else per block of cells): iteration count and
 // convergence test against STOP; first (after the warm start): also b.b,
 // the count reset and STOP = max(rtol^2 r0.r0, 1e-28 b.b). Every thread of
 // the block returns the same decision; thread 0 stores the scalars and the
-// flag.
-__device__ inline bool finish_rr(CDesc &D, bool first, bool tiles, double *sh) {
+// flag. Its operands can be loaded early (rr_prefetch), before the caller
+// waits for its flags.
+struct RRPre {
+  double rr, bb, stop;
+};
+__device__ inline RRPre rr_prefetch(CDesc &D, bool first, bool tiles) {
   const int nb = nblk_d(D.N);
-  const double rr = tiles ? sum_partials(red_rrt(D), D.ntile0, sh)
-                          : sum_partials(red_rr(D), nb, sh);
+  RRPre q;
+  q.rr = tiles ? first_partial(red_rrt(D), D.ntile0) : first_partial(red_rr(D), nb);
+  q.bb = first ? first_partial(red_bb(D), nb) : 0.0;
+  q.stop = D.scal[S_STOP];
+  return q;
+}
+__device__ inline bool finish_rr(CDesc &D, bool first, bool tiles, double *sh, const RRPre &q) {
+  const int nb = nblk_d(D.N);
+  const double rr = tiles ? sum_partials(red_rrt(D), D.ntile0, sh, q.rr)
+                          : sum_partials(red_rr(D), nb, sh, q.rr);
   double stop;
   double bb = 0.0;
   if (first) {
-    bb = sum_partials(red_bb(D), nb, sh);
+    bb = sum_partials(red_bb(D), nb, sh, q.bb);
     stop = fmax(D.rtol * D.rtol * rr, 1e-28 * bb);
   } else {
-    stop = D.scal[S_STOP];
+    stop = q.stop;
   }
   const bool conv = !(rr > stop);
   if (threadIdx.x == 0) {
@@ -241,8 +268,9 @@ __device__ inline bool finish_rr(CDesc &D, bool first, bool tiles, double *sh) {
 __global__ void k_finish_rr(const SynthDesc *ds) {
   __shared__ double sh[kRedBlock];
   CDesc &D = cdesc(ds, blockIdx.x);
+  const RRPre q = rr_prefetch(D, false, false);
   if (cg_off(D.state)) return;
-  (void)finish_rr(D, false, false, sh);
+  (void)finish_rr(D, false, false, sh, q);
 }
 
 // Start of a synthetic solve: warm start x = phi, clear the converged flag;
@@ -311,9 +339,11 @@ __global__ void k_cg_pAp(const SynthDesc *ds, const int2 *bt, int it) {
   const double dg = L.dg[cc];
   const double aE = hE ? L.ax[c] : 0.0, aW = hW ? L.ax[c - 1] : 0.0;
   const double aN = hN ? L.ay[c] : 0.0, aS = hS ? L.ay[c - nx] : 0.0;
+  const double rz0 = first_partial(red_rz(D), n_rz(D));
+  const double rz_prev = first ? 1.0 : D.scal[rz_slot(it - 1)];
   if (f1 != 0 || f3 != 0) return;
-  const double rz = sum_partials(red_rz(D), n_rz(D), sh);
-  const double be = first ? 0.0 : rz / D.scal[rz_slot(it - 1)];
+  const double rz = sum_partials(red_rz(D), n_rz(D), sh, rz0);
+  const double be = first ? 0.0 : rz / rz_prev;
   if (B.lb == 0 && threadIdx.x == 0) {
     D.scal[rz_slot(it)] = rz;
     D.scal[S_BETA] = be;
@@ -351,9 +381,10 @@ __global__ void k_cg_update(const SynthDesc *ds, const int2 *bt, int it, int all
   const bool in = c < D.N;
   const int cc = in ? c : 0;
   const double pc = p[cc], xc = x[cc], rc0 = cg_rv(D, it)[cc], apc = D.cg_Ap[cc];
+  const double pap0 = first_partial(red_pap(D), nblk_d(D.N)), rz = D.scal[rz_slot(it)];
   if (f1 != 0 || f3 != 0) return;
-  const double pap = sum_partials(red_pap(D), nblk_d(D.N), sh);
-  const double al = D.scal[rz_slot(it)] / pap;
+  const double pap = sum_partials(red_pap(D), nblk_d(D.N), sh, pap0);
+  const double al = rz / pap;
   if (B.lb == 0 && threadIdx.x == 0) {
     D.scal[S_PAP] = pap;
     D.scal[S_ALPHA] = al;
@@ -413,27 +444,61 @@ __device__ inline Tile tile_of(const LevelDev &L, int lb) {
   return {L.nx, L.ny, ti * kTW - kHalo, tj * kTH - kHalo};
 }
 
-// b, d and the east / north couplings of the region into LDS; with ap also
-// Ap of the region into sap
-__device__ inline void load_region(const LevelDev &L, const double *b, const Tile &T, double *sb,
-                                   double *sd, double *sax, double *say,
-                                   const double *ap = nullptr, double *sap = nullptr) {
-  for (int r = threadIdx.x; r < kRN; r += blockDim.x) {
+// b, d and the east / north couplings of the region into LDS (blockDim =
+// kRedBlock); AP: also Ap of the region into sap; XC: also the pre-smoothed
+// x plus the scaled coarse correction, xs + omega e(parent), into sxc. Every
+// load of the thread is issued (at a clamped, valid index) before any is
+// waited for, so the region costs one memory round trip.
+constexpr int kRegionPer = (kRN + kRedBlock - 1) / kRedBlock;
+template <bool AP, bool XC>
+__device__ inline void load_region_t(const LevelDev &L, const double *b, const Tile &T,
+                                     double *sb, double *sd, double *sax, double *say,
+                                     const double *ap, double *sap, const double *xs,
+                                     const double *e, int enx, int sx_, int sy_, double omega,
+                                     double *sxc) {
+  double vb[kRegionPer], vd[kRegionPer], vx[kRegionPer], vy[kRegionPer];
+  double va[kRegionPer], vs[kRegionPer], ve[kRegionPer];
+  bool in[kRegionPer], hx[kRegionPer], hy[kRegionPer];
+#pragma unroll
+  for (int k = 0; k < kRegionPer; ++k) {
+    const int r = threadIdx.x + k * kRedBlock;
     int ri, rj;
     cell_ij(r, kRW, ri, rj);
     const int gi = T.i0 + ri, gj = T.j0 + rj;
-    if (gi >= 0 && gi < T.nx && gj >= 0 && gj < T.ny) {
-      const int g = gj * T.nx + gi;
-      sb[r] = b[g];
-      sd[r] = L.dg[g];
-      sax[r] = gi + 1 < T.nx ? L.ax[g] : 0.0;
-      say[r] = gj + 1 < T.ny ? L.ay[g] : 0.0;
-      if (ap) sap[r] = ap[g];
-    } else {
-      sb[r] = 0.0; sd[r] = 1.0; sax[r] = 0.0; say[r] = 0.0;
-      if (ap) sap[r] = 0.0;
+    in[k] = r < kRN && gi >= 0 && gi < T.nx && gj >= 0 && gj < T.ny;
+    hx[k] = gi + 1 < T.nx;
+    hy[k] = gj + 1 < T.ny;
+    const int g = in[k] ? gj * T.nx + gi : 0;
+    vb[k] = b[g]; vd[k] = L.dg[g]; vx[k] = L.ax[g]; vy[k] = L.ay[g];
+    if (AP) va[k] = ap[g];
+    if (XC) {
+      vs[k] = xs[g];
+      ve[k] = e[in[k] ? (gj >> sy_) * enx + (gi >> sx_) : 0];
     }
   }
+#pragma unroll
+  for (int k = 0; k < kRegionPer; ++k) {
+    const int r = threadIdx.x + k * kRedBlock;
+    if (r >= kRN) continue;
+    sb[r] = in[k] ? vb[k] : 0.0;
+    sd[r] = in[k] ? vd[k] : 1.0;
+    sax[r] = in[k] && hx[k] ? vx[k] : 0.0;
+    say[r] = in[k] && hy[k] ? vy[k] : 0.0;
+    if (AP) sap[r] = in[k] ? va[k] : 0.0;
+    if (XC) {
+      double t = 0.0;
+      if (in[k]) {
+        t = vs[k];
+        t += omega * ve[k];
+      }
+      sxc[r] = t;
+    }
+  }
+}
+__device__ inline void load_region(const LevelDev &L, const double *b, const Tile &T, double *sb,
+                                   double *sd, double *sax, double *say) {
+  load_region_t<false, false>(L, b, T, sb, sd, sax, say, nullptr, nullptr, nullptr, nullptr, 0,
+                              0, 0, 0.0, nullptr);
 }
 
 // The CG update of iteration it = v - 1 folded into the level-0 tile kernel
@@ -441,11 +506,12 @@ __device__ inline void load_region(const LevelDev &L, const double *b, const Til
 // the same order), r_v = r_{v-1} - alpha Ap on the region held in LDS (sb
 // holds r_{v-1}, sap Ap; afterwards sb holds r_v), and for the tile's own
 // cells x += alpha p, r_v to global and a partial of r_v . r_v.
+// pap0 and rz: the thread's first p.Ap partial and r.z, loaded early.
 __device__ inline void cg_update_tile(CDesc &D, const Blk &B, const Tile &T, int v, double *sb,
-                                      const double *sap, double pc, double xc, double *sh) {
-  const int it = v - 1;
-  const double pap = sum_partials(red_pap(D), nblk_d(D.N), sh);
-  const double al = D.scal[rz_slot(it)] / pap;
+                                      const double *sap, double pc, double xc, double pap0,
+                                      double rz, double *sh) {
+  const double pap = sum_partials(red_pap(D), nblk_d(D.N), sh, pap0);
+  const double al = rz / pap;
   if (B.lb == 0 && threadIdx.x == 0) {
     D.scal[S_PAP] = pap;
     D.scal[S_ALPHA] = al;
@@ -477,11 +543,14 @@ __global__ void __launch_bounds__(kRedBlock) k_mg_down(const SynthDesc *ds, cons
   const bool upd = l == 0 && v > 0;
   double *xs = L.xs;
   const Tile T = tile_of(L, B.lb);
-  double pc = 0.0, xc = 0.0;
+  double pc = 0.0, xc = 0.0, pap0 = 0.0, rz = 0.0;
   if (upd) {
+    pap0 = first_partial(red_pap(D), nblk_d(D.N));
+    rz = D.scal[rz_slot(v - 1)];
     // r_{v-1} and Ap of the region (Ap into sx, free until the sweeps), p
     // and x of the thread's tile cell
-    load_region(L, cg_rv(D, v - 1), T, sb, sd, sax, say, D.cg_Ap, sx);
+    load_region_t<true, false>(L, cg_rv(D, v - 1), T, sb, sd, sax, say, D.cg_Ap, sx, nullptr,
+                               nullptr, 0, 0, 0, 0.0, nullptr);
     const int gi = T.i0 + kHalo + (int)threadIdx.x % kTW, gj = T.j0 + kHalo + (int)threadIdx.x / kTW;
     if (gi < T.nx && gj < T.ny) {
       const int g = gj * T.nx + gi;
@@ -491,13 +560,16 @@ __global__ void __launch_bounds__(kRedBlock) k_mg_down(const SynthDesc *ds, cons
   } else {
     load_region(L, lev_b(D, l, v), T, sb, sd, sax, say);
   }
-  if (f1 != 0 || f3 != 0) return;
   // the r.r test of the CG step before this V-cycle is made by the next
   // kernel of the cycle (level 1 here, block 0; the other blocks go on: if
   // it converged, their results are not used)
-  if (l == 1 && B.lb == 0) (void)finish_rr(D, v == 0, v > 0, sh);
+  const bool fin = l == 1 && B.lb == 0;
+  RRPre q = {0.0, 0.0, 0.0};
+  if (fin) q = rr_prefetch(D, v == 0, v > 0);
+  if (f1 != 0 || f3 != 0) return;
+  if (fin) (void)finish_rr(D, v == 0, v > 0, sh, q);
   __syncthreads();
-  if (upd) cg_update_tile(D, B, T, v, sb, sx, pc, xc, sh);
+  if (upd) cg_update_tile(D, B, T, v, sb, sx, pc, xc, pap0, rz, sh);
   // red half sweep from zero on the whole region
   for (int r = threadIdx.x; r < kRN; r += blockDim.x) {
     int ri, rj;
@@ -566,21 +638,11 @@ __global__ void __launch_bounds__(kRedBlock) k_mg_up(const SynthDesc *ds, const 
   const double *e = CL.x;
   const Tile T = tile_of(L, B.lb);
   const int sx_ = L.fx >> 1, sy_ = L.fy >> 1;
-  load_region(L, b, T, sb, sd, sax, say);
-  // the pre-smoothed x plus the scaled coarse correction: the black half
-  // sweep sees corrected red neighbours
+  // with the pre-smoothed x plus the scaled coarse correction: the black
+  // half sweep sees corrected red neighbours
   __shared__ double sxc[kRN];
-  for (int r = threadIdx.x; r < kRN; r += blockDim.x) {
-    int ri, rj;
-    cell_ij(r, kRW, ri, rj);
-    const int gi = T.i0 + ri, gj = T.j0 + rj;
-    double v = 0.0;
-    if (gi >= 0 && gi < T.nx && gj >= 0 && gj < T.ny) {
-      v = xs[gj * T.nx + gi];
-      v += omega * e[(gj >> sy_) * CL.nx + (gi >> sx_)];
-    }
-    sxc[r] = v;
-  }
+  load_region_t<false, true>(L, b, T, sb, sd, sax, say, nullptr, nullptr, xs, e, CL.nx, sx_, sy_,
+                             omega, sxc);
   if (f1 != 0 || f3 != 0) return;
   __syncthreads();
   // black half sweep on the tile and a ring of one, into sx
@@ -667,11 +729,14 @@ __global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(const SynthDesc *d
   extern __shared__ double sm[];
   __shared__ double red[kCoarseThreads];
   CDesc &D = cdesc(ds, blockIdx.x);
-  if (cg_off(D.state)) return;
   // a problem whose V-cycle starts here or on level 1 makes the r.r test of
   // the CG step before it here (level 1: the level-0 tile kernel made the
   // update)
-  if (D.lc <= 1 && finish_rr(D, vc == 0, vc > 0 && D.lc == 1, red)) return;
+  const bool fin = D.lc <= 1;
+  RRPre q = {0.0, 0.0, 0.0};
+  if (fin) q = rr_prefetch(D, vc == 0, vc > 0 && D.lc == 1);
+  if (cg_off(D.state)) return;
+  if (fin && finish_rr(D, vc == 0, vc > 0 && D.lc == 1, red, q)) return;
   __attribute__((address_space(4))) const CoarseLevels &L = D.cl;
   const double *bin = D.lc == 0 ? cg_rv(D, vc) : D.lev[D.lc].b;
   double *xout = D.lc == 0 ? D.cg_z : D.lev[D.lc].x;
@@ -942,17 +1007,21 @@ __global__ void k_update(const SynthDesc *ds, const int2 *bt) {
   __shared__ double sh[kRedBlock];
   const Blk B = blk(bt);
   CDesc &D = cdesc(ds, B.p);
-  if (D.state[1] != 0) return;
+  const int32_t f1 = D.state[1];   // tested after the operands are loaded
   const int c = B.lb * kRedBlock + threadIdx.x;
+  const bool in = c < D.N;
+  const int cc = in ? c : 0;
+  const double pn = D.method ? D.lev[0].x[cc] : D.phih[cc];
+  const double ph = D.phih[cc], po = D.phi[cc];
+  if (f1 != 0) return;
   double num = 0.0, den = 0.0;
-  if (c < D.N) {
-    const double pn = D.method ? D.lev[0].x[c] : D.phih[c];
-    const double d = pn - D.phi[c];
+  if (in) {
+    const double d = pn - po;
     num = D.V * d * d;
     den = D.V * pn * pn;
-    const double dl = D.method ? pn - D.phih[c] : 0.0;
+    const double dl = D.method ? pn - ph : 0.0;
     D.delta[c] = dl;
-    if (D.fp32) D.base[c] = D.phi[c] + dl;
+    if (D.fp32) D.base[c] = po + dl;
     D.phi[c] = pn;
   }
   double a = block_sum(num, sh);
@@ -993,13 +1062,14 @@ __global__ void k_err_finish(const SynthDesc *ds) {
 __global__ void k_source(const SynthDesc *ds, const int2 *bt) {
   const Blk B = blk(bt);
   CDesc &D = cdesc(ds, B.p);
-  if (D.state[1] != 0) return;
+  const int32_t f1 = D.state[1];   // tested after the operands are loaded
   const int nx = D.nx, ny = D.ny, n = D.N;
   const int c = B.lb * kRedBlock + threadIdx.x;
   if (c >= n) return;
   const double sc = (D.sig_s[c] * D.phi[c] + D.q[c]) / kFourPi;
   const double dq = D.base[c] / kFourPi;
   const double pq = D.phi[c] / kFourPi;
+  if (f1 != 0) return;
   D.src[c] = sc;
   int i, j;
   cell_ij(c, nx, i, j);
