@@ -197,6 +197,13 @@ gsis_status build_tables(gsis_batch *b, const std::vector<int> &act) {
     for (int lb = 0; lb < nb(D[a].N); ++lb) t.push_back(make_int2(a, lb));
   S.nb_cell = (int)t.size();
   if ((st = tupload(b, &S.bt_cell, t))) return st;
+  {
+    std::vector<int2> ts;
+    for (int a = 0; a < n; ++a)
+      for (int lb = 0; lb < source_tiles_of(D[a].nx, D[a].ny); ++lb) ts.push_back(make_int2(a, lb));
+    S.nb_src = (int)ts.size();
+    if ((st = tupload(b, &S.bt_src, ts))) return st;
+  }
   S.bt_tile.assign(max_lc, nullptr);
   S.nb_tile.assign(max_lc, 0);
   for (int l = 0; l < max_lc; ++l) {

@@ -325,6 +325,8 @@ gsis_status make_single_set(gsis_plan *pl) {
   S.synth_max_iter = P.synth_max_iter;
   S.nb_cell = nb(P.N);
   S.bt_cell = nullptr;
+  S.nb_src = source_tiles_of(P.nx, P.ny);
+  S.bt_src = nullptr;
   S.bt_tile.assign(D.lc, nullptr);
   S.nb_tile.resize(D.lc);
   for (int l = 0; l < D.lc; ++l) S.nb_tile[l] = tiles_of(P.mg[l].nx, P.mg[l].ny);

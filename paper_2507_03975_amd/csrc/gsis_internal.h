@@ -100,6 +100,8 @@ struct SynthSet {
   // block tables (nullptr for a single problem) and their block counts
   int2 *bt_cell = nullptr;            // level-0 cells of every problem
   int nb_cell = 0;
+  int2 *bt_src = nullptr;             // 16 x 16 cell tiles of every problem (source kernel)
+  int nb_src = 0;
   std::vector<int2 *> bt_tile;        // [l]: level-l tiles of problems with lc > l
   std::vector<int> nb_tile;
   int32_t *state0 = nullptr;          // single problem: its state (host checks)
@@ -223,6 +225,7 @@ SynthDesc make_synth_desc(const PlanDev &P);
 int coarse_start(const PlanDev &P);
 size_t coarse_lds_bytes(const PlanDev &P);
 int tiles_of(int nx, int ny);   // multigrid tiles covering an nx x ny level
+int source_tiles_of(int nx, int ny);   // 16 x 16 tiles of the source kernel
 void prepare_synth(size_t coarse_lds);      // kernel attribute for the LDS size
 void launch_source(const SynthSet &S, hipStream_t s);          // src from phi
 void launch_hot_rhs(const SynthSet &S, hipStream_t s);

@@ -1058,27 +1058,56 @@ __global__ void k_err_finish(const SynthDesc *ds) {
 }
 
 // src = (sigma_s phi + q) / (4 pi); the mirrored per-quadrant copies of
-// (src, base/(4 pi), phi/(4 pi)) read by the fused sweep.
-__global__ void k_source(const SynthDesc *ds, const int2 *bt) {
+// (src, base/(4 pi), phi/(4 pi)) read by the transport kernels, stored in
+// each quadrant's anti-diagonal order. One workgroup per 16 x 16 tile: the
+// values go through LDS, then for every quadrant thread t writes the tile's
+// t-th cell in that quadrant's anti-diagonal order, so the cells of a
+// diagonal run over consecutive lanes and consecutive addresses.
+constexpr int kSrcT = 16;
+static_assert(kSrcT * kSrcT == kRedBlock, "one thread per tile cell");
+__global__ void __launch_bounds__(kRedBlock) k_source(const SynthDesc *ds, const int2 *bt) {
+  __shared__ double s_sc[kRedBlock], s_dq[kRedBlock], s_pq[kRedBlock];
   const Blk B = blk(bt);
   CDesc &D = cdesc(ds, B.p);
   const int32_t f1 = D.state[1];   // tested after the operands are loaded
   const int nx = D.nx, ny = D.ny, n = D.N;
-  const int c = B.lb * kRedBlock + threadIdx.x;
-  if (c >= n) return;
-  const double sc = (D.sig_s[c] * D.phi[c] + D.q[c]) / kFourPi;
-  const double dq = D.base[c] / kFourPi;
-  const double pq = D.phi[c] / kFourPi;
-  if (f1 != 0) return;
-  D.src[c] = sc;
-  int i, j;
-  cell_ij(c, nx, i, j);
+  int ti, tj;
+  cell_ij(B.lb, (nx + kSrcT - 1) / kSrcT, ti, tj);
+  const int i0 = ti * kSrcT, j0 = tj * kSrcT;
+  const int t = threadIdx.x;
+  {
+    const int i = i0 + (t & (kSrcT - 1)), j = j0 + t / kSrcT;
+    const bool in = i < nx && j < ny;
+    const int c = in ? j * nx + i : 0;
+    const double sc = (D.sig_s[c] * D.phi[c] + D.q[c]) / kFourPi;
+    const double dq = D.base[c] / kFourPi;
+    const double pq = D.phi[c] / kFourPi;
+    if (f1 != 0) return;
+    if (in) D.src[c] = sc;
+    s_sc[t] = sc; s_dq[t] = dq; s_pq[t] = pq;
+  }
+  __syncthreads();
+  // cell t of a kSrcT x kSrcT square in anti-diagonal order (diagonal e = u +
+  // w, then w): (u, w) in the square's own frame
+  int e = 0, before = 0;
+  for (;; ++e) {
+    const int len = e < kSrcT ? e + 1 : 2 * kSrcT - 1 - e;
+    if (t < before + len) break;
+    before += len;
+  }
+  const int w = (e < kSrcT ? 0 : e - kSrcT + 1) + (t - before), u = e - w;
   for (int qd = 0; qd < 4; ++qd) {
+    // the square in quadrant qd's mirrored frame: u runs against x when x
+    // is mirrored, w against y when y is
+    const int i = (qd & 1) ? i0 + kSrcT - 1 - u : i0 + u;
+    const int j = (qd & 2) ? j0 + kSrcT - 1 - w : j0 + w;
+    if (i >= nx || j >= ny) continue;
     const int xl = (qd & 1) ? nx - 1 - i : i, yl = (qd & 2) ? ny - 1 - j : j;
     const size_t o = (size_t)qd * 3 * n + dg_idx(xl, yl, nx, ny);
-    D.dynq[o] = sc;          // plane 0 of quadrant qd
-    D.dynq[o + n] = dq;      // plane 1
-    if (D.fp32) D.dynq[o + 2 * n] = pq;
+    const int l = (j - j0) * kSrcT + (i - i0);
+    D.dynq[o] = s_sc[l];          // plane 0 of quadrant qd
+    D.dynq[o + n] = s_dq[l];      // plane 1
+    if (D.fp32) D.dynq[o + 2 * n] = s_pq[l];
   }
 }
 
@@ -1132,6 +1161,9 @@ int coarse_start(const PlanDev &P) {
 size_t coarse_lds_bytes(const PlanDev &P) { return coarse_lds_bytes_from(P, coarse_start(P)); }
 
 int tiles_of(int nx, int ny) { return ((nx + kTW - 1) / kTW) * ((ny + kTH - 1) / kTH); }
+int source_tiles_of(int nx, int ny) {
+  return ((nx + kSrcT - 1) / kSrcT) * ((ny + kSrcT - 1) / kSrcT);
+}
 
 // The attribute is per kernel, not per plan: it is raised to the largest
 // amount any plan may ask for, so that a later plan with a smaller coarse
@@ -1191,7 +1223,7 @@ SynthDesc make_synth_desc(const PlanDev &P) {
 }
 
 void launch_source(const SynthSet &S, hipStream_t s) {
-  hipLaunchKernelGGL(k_source, dim3(S.nb_cell), dim3(kRedBlock), 0, s, S.desc, S.bt_cell);
+  hipLaunchKernelGGL(k_source, dim3(S.nb_src), dim3(kRedBlock), 0, s, S.desc, S.bt_src);
 }
 
 void launch_hot_rhs(const SynthSet &S, hipStream_t s) {
