@@ -280,14 +280,16 @@ gsis_status setup_synth(gsis_plan *pl, PlanDev &P, std::vector<HostLevel> &hl) {
   const int N = P.N;
   if ((st = dalloc(pl, &P.cg_r, N)) || (st = dalloc(pl, &P.cg_r2, N)) ||
       (st = dalloc(pl, &P.cg_z, N)) ||
-      (st = dalloc(pl, &P.cg_p, N)) || (st = dalloc(pl, &P.cg_p2, N)) ||
-      (st = dalloc(pl, &P.cg_Ap, N)) || (st = dalloc(pl, &P.scal, 16)))
+      (st = dalloc(pl, &P.cg_p, N)) || (st = dalloc(pl, &P.cg_s0, N)) ||
+      (st = dalloc(pl, &P.cg_s1, N)) || (st = dalloc(pl, &P.cg_w, N)) ||
+      (st = dalloc(pl, &P.scal, 16)))
     return st;
-  // block partials: p.Ap, r.r, b.b (one per 256 cells each), then r.z and
-  // the r.r of the level-0 tile kernel (one per level-0 multigrid tile each)
+  // block partials: r.r and b.b (one per 256 cells each), then r.z, the
+  // r.r of the level-0 tile kernel and z.Az (one per level-0 multigrid tile
+  // each)
   P.red_blocks = (N + 255) / 256;
-  if ((st = dalloc(pl, &P.red, 3 * (size_t)P.red_blocks + 2 * (size_t)tiles_of(P.nx, P.ny) + 2)))
-    return st;
+  const size_t ntp = std::max<size_t>(tiles_of(P.nx, P.ny), P.red_blocks);
+  if ((st = dalloc(pl, &P.red, 2 * (size_t)P.red_blocks + 3 * ntp + 2))) return st;
   P.mg.resize(hl.size());
   for (size_t l = 0; l < hl.size(); ++l) {
     MGLevel &L = P.mg[l];

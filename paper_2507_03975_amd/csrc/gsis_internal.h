@@ -80,11 +80,14 @@ struct SynthDesc {
   const double *sig_t, *sig_s, *q, *cE, *cW, *cN, *cS, *kappa;
   const double *phih, *Fx, *Fy, *bflux;
   double *hx, *hy, *rhs, *phi, *delta, *base, *src, *dynq;
-  // r of the CG alternates between cg_r and cg_r2 with the V-cycle count
-  double *cg_r, *cg_r2, *cg_z, *cg_p0, *cg_p1, *cg_Ap, *red, *scal, *err_parts, *err_hist, *last_err;
+  // CG vectors: r alternates between cg_r and cg_r2 with the V-cycle count,
+  // s = A p between cg_s0 and cg_s1 with the iteration; z = M r, w = A z
+  double *cg_r, *cg_r2, *cg_z, *cg_p, *cg_s0, *cg_s1, *cg_w;
+  double *red, *scal, *err_parts, *err_hist, *last_err;
   int32_t *state;
   int nlev, lc;                 // levels; first level of the one-workgroup cycle
   int ntile0;                   // multigrid tiles of level 0
+  int ntp;                      // slots of each tile-partial region: max(ntile0, cell blocks)
   LevelDev lev[kMaxLevels];
   CoarseLevels cl;
   const double *coarse_inv;
@@ -158,8 +161,8 @@ struct PlanDev {
   std::vector<MGLevel> mg;
   double *coarse_inv = nullptr;  // dense inverse of the coarsest operator
   int coarse_n = 0;
-  double *cg_r = nullptr, *cg_r2 = nullptr, *cg_z = nullptr, *cg_p = nullptr, *cg_p2 = nullptr;
-  double *cg_Ap = nullptr;
+  double *cg_r = nullptr, *cg_r2 = nullptr, *cg_z = nullptr, *cg_p = nullptr;
+  double *cg_s0 = nullptr, *cg_s1 = nullptr, *cg_w = nullptr;
   double *red = nullptr;       // block partial sums
   double *scal = nullptr;      // device scalars (see kernels_synth.hip)
   int red_blocks = 0;

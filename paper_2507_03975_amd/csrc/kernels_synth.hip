@@ -166,9 +166,10 @@ __device__ inline double apply5(int nx, int ny, const double *dg, const double *
 // Scalar slots. r.z of CG iteration k sits in slot rz_slot(k) (two
 // alternating slots, so a kernel can read iteration k-1's value while its
 // block 0 stores iteration k's).
-enum { S_RZ = 0, S_PAP = 1, S_RR = 2, S_BB = 3, S_ALPHA = 4, S_BETA = 5, S_STOP = 6,
-       S_NIT = 7, S_RZ1 = 8 };
+enum { S_RZ = 0, S_ZW = 1, S_RR = 2, S_BB = 3, S_ALPHA = 4, S_BETA = 5, S_STOP = 6,
+       S_NIT = 7, S_RZ1 = 8, S_ALPHA1 = 9 };
 __host__ __device__ inline int rz_slot(int k) { return (k & 1) ? S_RZ1 : S_RZ; }
+__host__ __device__ inline int alpha_slot(int k) { return (k & 1) ? S_ALPHA1 : S_ALPHA; }
 
 // r of V-cycle v (v = 0 after the warm start, v = it + 1 after CG iteration
 // it): the buffers alternate, so a kernel that forms r_{v} for its tile and
@@ -183,22 +184,23 @@ inline int nblk(int n) { return (n + kRedBlock - 1) / kRedBlock; }
 __host__ __device__ inline int nblk_d(int n) { return (n + kRedBlock - 1) / kRedBlock; }
 
 // Block partials of a problem's reductions, in separate regions of its red
-// array (nb = level-0 blocks of 256 cells): [0, nb) p.Ap, [nb, 2 nb) r.r,
-// [2 nb, 3 nb) b.b, then r.z (one per level-0 tile, or a single value when
-// the whole V-cycle ran in one workgroup), then r.r once more, one per
-// level-0 tile, from the tile kernel that makes the CG update. A reduction is finished by the
+// array (nb = level-0 blocks of 256 cells): [0, nb) r.r, [nb, 2 nb) b.b,
+// then three regions of ntp = max(nb, level-0 tiles) slots: r.z (one per
+// level-0 tile, or per block of cells when the whole V-cycle ran in one
+// workgroup), r.r once more, one per level-0 tile, from the tile kernel
+// that makes the CG update, and z.Az (like r.z). A reduction is finished by the
 // kernel that needs its value: every block of it sums the partials in the
 // same fixed order, so all blocks hold the same number and results repeat
 // bit for bit; block 0 stores it for later kernels. This saves a launch
 // per reduction (folding the finish into the producing kernel instead would
 // need a device-scope release per block, which on a GPU whose XCDs each
 // have their own L2 writes back the L2 every time).
-__device__ inline double *red_pap(CDesc &D) { return D.red; }
-__device__ inline double *red_rr(CDesc &D) { return D.red + nblk_d(D.N); }
-__device__ inline double *red_bb(CDesc &D) { return D.red + 2 * nblk_d(D.N); }
-__device__ inline double *red_rz(CDesc &D) { return D.red + 3 * nblk_d(D.N); }
-__device__ inline double *red_rrt(CDesc &D) { return D.red + 3 * nblk_d(D.N) + D.ntile0; }
-__device__ inline int n_rz(CDesc &D) { return D.lc == 0 ? 1 : D.ntile0; }
+__device__ inline double *red_rr(CDesc &D) { return D.red; }
+__device__ inline double *red_bb(CDesc &D) { return D.red + nblk_d(D.N); }
+__device__ inline double *red_rz(CDesc &D) { return D.red + 2 * nblk_d(D.N); }
+__device__ inline double *red_rrt(CDesc &D) { return D.red + 2 * nblk_d(D.N) + D.ntp; }
+__device__ inline double *red_zw(CDesc &D) { return D.red + 2 * nblk_d(D.N) + 2 * D.ntp; }
+__device__ inline int n_rz(CDesc &D) { return D.lc == 0 ? nblk_d(D.N) : D.ntile0; }
 
 __device__ inline double sum_partials(const double *p, int n, double *sh) {
   double v = 0.0;
@@ -308,67 +310,56 @@ __global__ void k_cg_begin(const SynthDesc *ds, const int2 *bt) {
   if (threadIdx.x == 0) red_bb(D)[B.lb] = t;
 }
 
-// CG iteration it: r.z from the V-cycle's partials, beta = r.z / (previous
-// r.z); p_new = z + beta p_old (= z on the first iteration), Ap = A p_new and
-// a partial of p_new . Ap. Neighbour values of p_new are formed from z and
-// p_old, so one kernel does both. Buffers alternate with the parity of it.
-__global__ void k_cg_pAp(const SynthDesc *ds, const int2 *bt, int it) {
-  __shared__ double sh[kRedBlock];
-  const Blk B = blk(bt);
-  CDesc &D = cdesc(ds, B.p);
-  // The flags, the partials and the cell's operands are loaded before any of
-  // them is waited for (this kernel is latency bound).
-  const int32_t f1 = D.state[1], f3 = D.state[3];
-  const bool first = it == 0;
-  const int par = it & 1;
-  const int c = B.lb * kRedBlock + threadIdx.x;
-  const LevelDev L = level(D, 0);
-  const int nx = L.nx, ny = L.ny;
-  const double *z = D.cg_z;
-  const double *pold = par ? D.cg_p1 : D.cg_p0;
-  double *pnew = par ? D.cg_p0 : D.cg_p1;
-  const bool in = c < D.N;
-  int i = 0, j = 0;
-  if (in) cell_ij(c, nx, i, j);
-  const bool hE = in && i + 1 < nx, hW = in && i > 0, hN = in && j + 1 < ny, hS = in && j > 0;
-  const int cc = in ? c : 0;
-  const int ce = hE ? c + 1 : cc, cw = hW ? c - 1 : cc, cn = hN ? c + nx : cc, cs = hS ? c - nx : cc;
-  const double zc = z[cc], ze = z[ce], zw = z[cw], zn = z[cn], zs = z[cs];
-  double oc = 0.0, oe = 0.0, ow = 0.0, on = 0.0, os = 0.0;
-  if (!first) { oc = pold[cc]; oe = pold[ce]; ow = pold[cw]; on = pold[cn]; os = pold[cs]; }
-  const double dg = L.dg[cc];
-  const double aE = hE ? L.ax[c] : 0.0, aW = hW ? L.ax[c - 1] : 0.0;
-  const double aN = hN ? L.ay[c] : 0.0, aS = hS ? L.ay[c - nx] : 0.0;
-  const double rz0 = first_partial(red_rz(D), n_rz(D));
-  const double rz_prev = first ? 1.0 : D.scal[rz_slot(it - 1)];
-  if (f1 != 0 || f3 != 0) return;
-  const double rz = sum_partials(red_rz(D), n_rz(D), sh, rz0);
-  const double be = first ? 0.0 : rz / rz_prev;
+// CG in the form of Chronopoulos and Gear: the V-cycle of iteration it
+// gives z = M r and, on its finest level, w = A z with partials of
+// gamma = r.z and delta = z.w in one pass, so an iteration needs a single
+// global reduction. Then
+//   beta = gamma / gamma_prev (0 on the first iteration),
+//   alpha = gamma / (delta - beta gamma / alpha_prev) (gamma / delta first),
+//   p = z + beta p, s = w + beta s (= A p), x += alpha p, r -= alpha s,
+// which is preconditioned CG with A p carried by a recurrence instead of a
+// product. s alternates between two buffers with the parity of it.
+struct CGCoef {
+  double be, al;
+};
+__device__ inline CGCoef cg_coef(bool first, double ga, double de, double ga_prev,
+                                 double al_prev) {
+  if (first) return {0.0, ga / de};
+  const double be = ga / ga_prev;
+  return {be, ga / (de - be * ga / al_prev)};
+}
+__device__ inline double *cg_s(CDesc &D, int it) { return (it & 1) ? D.cg_s1 : D.cg_s0; }
+// the update's scalar operands, loaded before the caller waits for its flags
+struct UpdPre {
+  double rz0, zw0, ga_prev, al_prev;
+};
+__device__ inline UpdPre upd_prefetch(CDesc &D, int it) {
+  UpdPre q;
+  q.rz0 = first_partial(red_rz(D), n_rz(D));
+  q.zw0 = first_partial(red_zw(D), n_rz(D));
+  q.ga_prev = it > 0 ? D.scal[rz_slot(it - 1)] : 1.0;
+  q.al_prev = it > 0 ? D.scal[alpha_slot(it - 1)] : 1.0;
+  return q;
+}
+// every block forms the coefficients from the same partials in the same
+// order; block 0 stores gamma, delta, alpha and beta
+__device__ inline CGCoef upd_coef(CDesc &D, const Blk &B, int it, const UpdPre &q, double *sh) {
+  const double ga = sum_partials(red_rz(D), n_rz(D), sh, q.rz0);
+  const double de = sum_partials(red_zw(D), n_rz(D), sh, q.zw0);
+  const CGCoef k = cg_coef(it == 0, ga, de, q.ga_prev, q.al_prev);
   if (B.lb == 0 && threadIdx.x == 0) {
-    D.scal[rz_slot(it)] = rz;
-    D.scal[S_BETA] = be;
+    D.scal[rz_slot(it)] = ga;
+    D.scal[alpha_slot(it)] = k.al;
+    D.scal[S_BETA] = k.be;
+    D.scal[S_ZW] = de;
   }
-  auto P = [&](double zv, double ov) { return first ? zv : zv + be * ov; };
-  double v = 0.0;
-  if (in) {
-    const double pc = P(zc, oc);
-    double y = dg * pc;
-    if (hE) y -= aE * P(ze, oe);
-    if (hW) y -= aW * P(zw, ow);
-    if (hN) y -= aN * P(zn, on);
-    if (hS) y -= aS * P(zs, os);
-    pnew[c] = pc;
-    D.cg_Ap[c] = y;
-    v = pc * y;
-  }
-  double t = block_sum(v, sh);
-  if (threadIdx.x == 0) red_pap(D)[B.lb] = t;
+  return k;
 }
 
-// CG iteration it: alpha = r.z / p.Ap; x += alpha p ; r -= alpha Ap ;
-// partial of r.r. With all = 0 only problems whose whole V-cycle runs in
-// the one-workgroup kernel take part: for the others the level-0 tile
-// kernel of the next V-cycle makes the update (cg_update_tile).
+// CG iteration it on every cell of a problem, with the partial of r.r.
+// With all = 0 only problems whose whole V-cycle runs in the one-workgroup
+// kernel take part: for the others the level-0 tile kernel of the next
+// V-cycle makes the update (cg_update_tile).
 __global__ void k_cg_update(const SynthDesc *ds, const int2 *bt, int it, int all) {
   __shared__ double sh[kRedBlock];
   const Blk B = blk(bt);
@@ -376,23 +367,22 @@ __global__ void k_cg_update(const SynthDesc *ds, const int2 *bt, int it, int all
   if (!all && D.lc > 0) return;
   const int32_t f1 = D.state[1], f3 = D.state[3];
   const int c = B.lb * kRedBlock + threadIdx.x;
-  const double *p = (it & 1) ? D.cg_p0 : D.cg_p1;
   double *x = D.lev[0].x;
   const bool in = c < D.N;
   const int cc = in ? c : 0;
-  const double pc = p[cc], xc = x[cc], rc0 = cg_rv(D, it)[cc], apc = D.cg_Ap[cc];
-  const double pap0 = first_partial(red_pap(D), nblk_d(D.N)), rz = D.scal[rz_slot(it)];
+  const double zc = D.cg_z[cc], wc = D.cg_w[cc], xc = x[cc], rc0 = cg_rv(D, it)[cc];
+  const double pc0 = it > 0 ? D.cg_p[cc] : 0.0, sc0 = it > 0 ? cg_s(D, it - 1)[cc] : 0.0;
+  const UpdPre q = upd_prefetch(D, it);
   if (f1 != 0 || f3 != 0) return;
-  const double pap = sum_partials(red_pap(D), nblk_d(D.N), sh, pap0);
-  const double al = rz / pap;
-  if (B.lb == 0 && threadIdx.x == 0) {
-    D.scal[S_PAP] = pap;
-    D.scal[S_ALPHA] = al;
-  }
+  const CGCoef k = upd_coef(D, B, it, q, sh);
   double v = 0.0;
   if (in) {
-    x[c] = fma(al, pc, xc);
-    const double rc = fma(-al, apc, rc0);
+    const double pc = it > 0 ? fma(k.be, pc0, zc) : zc;
+    const double sc = it > 0 ? fma(k.be, sc0, wc) : wc;
+    D.cg_p[c] = pc;
+    cg_s(D, it)[c] = sc;
+    x[c] = fma(k.al, pc, xc);
+    const double rc = fma(-k.al, sc, rc0);
     cg_rv(D, it + 1)[c] = rc;
     v = rc * rc;
   }
@@ -420,12 +410,12 @@ __device__ inline const double *lev_b(CDesc &D, int l, int v) {
 //        for other workgroups. The pre-smoothed x of the tile goes to the
 //        level's spare vector xs, not to x. On level 0 after a CG step it
 //        also makes that step's update (cg_update_tile): b = r_new =
-//        r_old - alpha Ap is formed on the whole region from r_old and Ap,
-//        which the previous kernel left complete.
+//        r_old - alpha (w + beta s_old) is formed on the whole region from
+//        r_old, w and s_old, which earlier kernels left complete.
 //  up:   black x = (b + sum a (xs_nb + omega e_parent(nb))) / d with the
 //        coarse correction e, then red x = (b + sum a x_nb) / d; the black
 //        ring is recomputed so the red cells of the tile see final
-//        neighbours. On level 0 also a partial of r.z (b = r, x = z). It
+//        neighbours. Level 0 has its own kernel (k_mg_up0). It
 //        reads the pre-smoothed xs of the ring and writes the final x into a
 //        different array, so tiles running later never see a neighbour's
 //        final values in place of its pre-smoothed ones.
@@ -445,7 +435,8 @@ __device__ inline Tile tile_of(const LevelDev &L, int lb) {
 }
 
 // b, d and the east / north couplings of the region into LDS (blockDim =
-// kRedBlock); AP: also Ap of the region into sap; XC: also the pre-smoothed
+// kRedBlock); AP: also ap (and ap2 unless NULL) of the region into sap
+// (sap2); XC: also the pre-smoothed
 // x plus the scaled coarse correction, xs + omega e(parent), into sxc. Every
 // load of the thread is issued (at a clamped, valid index) before any is
 // waited for, so the region costs one memory round trip.
@@ -455,9 +446,10 @@ __device__ inline void load_region_t(const LevelDev &L, const double *b, const T
                                      double *sb, double *sd, double *sax, double *say,
                                      const double *ap, double *sap, const double *xs,
                                      const double *e, int enx, int sx_, int sy_, double omega,
-                                     double *sxc) {
+                                     double *sxc, const double *ap2 = nullptr,
+                                     double *sap2 = nullptr) {
   double vb[kRegionPer], vd[kRegionPer], vx[kRegionPer], vy[kRegionPer];
-  double va[kRegionPer], vs[kRegionPer], ve[kRegionPer];
+  double va[kRegionPer], va2[kRegionPer], vs[kRegionPer], ve[kRegionPer];
   bool in[kRegionPer], hx[kRegionPer], hy[kRegionPer];
 #pragma unroll
   for (int k = 0; k < kRegionPer; ++k) {
@@ -471,6 +463,7 @@ __device__ inline void load_region_t(const LevelDev &L, const double *b, const T
     const int g = in[k] ? gj * T.nx + gi : 0;
     vb[k] = b[g]; vd[k] = L.dg[g]; vx[k] = L.ax[g]; vy[k] = L.ay[g];
     if (AP) va[k] = ap[g];
+    if (AP) va2[k] = ap2 ? ap2[g] : 0.0;
     if (XC) {
       vs[k] = xs[g];
       ve[k] = e[in[k] ? (gj >> sy_) * enx + (gi >> sx_) : 0];
@@ -485,6 +478,7 @@ __device__ inline void load_region_t(const LevelDev &L, const double *b, const T
     sax[r] = in[k] && hx[k] ? vx[k] : 0.0;
     say[r] = in[k] && hy[k] ? vy[k] : 0.0;
     if (AP) sap[r] = in[k] ? va[k] : 0.0;
+    if (AP && sap2) sap2[r] = in[k] ? va2[k] : 0.0;
     if (XC) {
       double t = 0.0;
       if (in[k]) {
@@ -502,21 +496,23 @@ __device__ inline void load_region(const LevelDev &L, const double *b, const Til
 }
 
 // The CG update of iteration it = v - 1 folded into the level-0 tile kernel
-// of V-cycle v: alpha = r.z / p.Ap (every block sums the p.Ap partials in
-// the same order), r_v = r_{v-1} - alpha Ap on the region held in LDS (sb
-// holds r_{v-1}, sap Ap; afterwards sb holds r_v), and for the tile's own
-// cells x += alpha p, r_v to global and a partial of r_v . r_v.
-// pap0 and rz: the thread's first p.Ap partial and r.z, loaded early.
+// of V-cycle v: beta and alpha from the r.z and z.w partials (every block
+// sums them in the same order), then on the region held in LDS s = w + beta
+// s_old (sw holds w, ss s_old; afterwards ss holds s) and r_v = r_{v-1} -
+// alpha s (sb holds r_{v-1}, afterwards r_v); for the tile's own cells p =
+// z + beta p, x += alpha p, s and r_v to global and a partial of r_v . r_v.
+// zc, pc0, xc: the cell's z, p and x; q: the update's scalars, all loaded
+// early.
 __device__ inline void cg_update_tile(CDesc &D, const Blk &B, const Tile &T, int v, double *sb,
-                                      const double *sap, double pc, double xc, double pap0,
-                                      double rz, double *sh) {
-  const double pap = sum_partials(red_pap(D), nblk_d(D.N), sh, pap0);
-  const double al = rz / pap;
-  if (B.lb == 0 && threadIdx.x == 0) {
-    D.scal[S_PAP] = pap;
-    D.scal[S_ALPHA] = al;
+                                      const double *sw, double *ss, double zc, double pc0,
+                                      double xc, const UpdPre &q, double *sh) {
+  const int it = v - 1;
+  const CGCoef k = upd_coef(D, B, it, q, sh);
+  for (int r = threadIdx.x; r < kRN; r += blockDim.x) {
+    const double sv = it > 0 ? fma(k.be, ss[r], sw[r]) : sw[r];
+    ss[r] = sv;
+    sb[r] = fma(-k.al, sv, sb[r]);
   }
-  for (int r = threadIdx.x; r < kRN; r += blockDim.x) sb[r] = fma(-al, sap[r], sb[r]);
   __syncthreads();
   const int ti = threadIdx.x % kTW, tj = threadIdx.x / kTW;
   const int r = (tj + kHalo) * kRW + ti + kHalo;
@@ -524,8 +520,11 @@ __device__ inline void cg_update_tile(CDesc &D, const Blk &B, const Tile &T, int
   double rr = 0.0;
   if (gi < T.nx && gj < T.ny) {
     const int g = gj * T.nx + gi;
+    const double pc = it > 0 ? fma(k.be, pc0, zc) : zc;
     const double rc = sb[r];
-    D.lev[0].x[g] = fma(al, pc, xc);
+    D.cg_p[g] = pc;
+    cg_s(D, it)[g] = ss[r];
+    D.lev[0].x[g] = fma(k.al, pc, xc);
     cg_rv(D, v)[g] = rc;
     rr = rc * rc;
   }
@@ -535,7 +534,7 @@ __device__ inline void cg_update_tile(CDesc &D, const Blk &B, const Tile &T, int
 
 __global__ void __launch_bounds__(kRedBlock) k_mg_down(const SynthDesc *ds, const int2 *bt, int l,
                                                        int v) {
-  __shared__ double sb[kRN], sd[kRN], sax[kRN], say[kRN], sx[kRN], sh[kRedBlock];
+  __shared__ double sb[kRN], sd[kRN], sax[kRN], say[kRN], sx[kRN], ss[kRN], sh[kRedBlock];
   const Blk B = blk(bt);
   CDesc &D = cdesc(ds, B.p);
   const int32_t f1 = D.state[1], f3 = D.state[3];   // tested after the region loads
@@ -543,18 +542,21 @@ __global__ void __launch_bounds__(kRedBlock) k_mg_down(const SynthDesc *ds, cons
   const bool upd = l == 0 && v > 0;
   double *xs = L.xs;
   const Tile T = tile_of(L, B.lb);
-  double pc = 0.0, xc = 0.0, pap0 = 0.0, rz = 0.0;
+  double zc = 0.0, pc0 = 0.0, xc = 0.0;
+  UpdPre q = {0.0, 0.0, 1.0, 1.0};
   if (upd) {
-    pap0 = first_partial(red_pap(D), nblk_d(D.N));
-    rz = D.scal[rz_slot(v - 1)];
-    // r_{v-1} and Ap of the region (Ap into sx, free until the sweeps), p
-    // and x of the thread's tile cell
-    load_region_t<true, false>(L, cg_rv(D, v - 1), T, sb, sd, sax, say, D.cg_Ap, sx, nullptr,
-                               nullptr, 0, 0, 0, 0.0, nullptr);
+    const int it = v - 1;
+    q = upd_prefetch(D, it);
+    // r_{v-1}, w and s_old of the region (w into sx, free until the
+    // sweeps), z, p and x of the thread's tile cell
+    load_region_t<true, false>(L, cg_rv(D, it), T, sb, sd, sax, say, D.cg_w, sx, nullptr,
+                               nullptr, 0, 0, 0, 0.0, nullptr, it > 0 ? cg_s(D, it - 1) : nullptr,
+                               ss);
     const int gi = T.i0 + kHalo + (int)threadIdx.x % kTW, gj = T.j0 + kHalo + (int)threadIdx.x / kTW;
     if (gi < T.nx && gj < T.ny) {
       const int g = gj * T.nx + gi;
-      pc = (((v - 1) & 1) ? D.cg_p0 : D.cg_p1)[g];
+      zc = D.cg_z[g];
+      if (it > 0) pc0 = D.cg_p[g];
       xc = D.lev[0].x[g];
     }
   } else {
@@ -564,12 +566,12 @@ __global__ void __launch_bounds__(kRedBlock) k_mg_down(const SynthDesc *ds, cons
   // kernel of the cycle (level 1 here, block 0; the other blocks go on: if
   // it converged, their results are not used)
   const bool fin = l == 1 && B.lb == 0;
-  RRPre q = {0.0, 0.0, 0.0};
-  if (fin) q = rr_prefetch(D, v == 0, v > 0);
+  RRPre qr = {0.0, 0.0, 0.0};
+  if (fin) qr = rr_prefetch(D, v == 0, v > 0);
   if (f1 != 0 || f3 != 0) return;
-  if (fin) (void)finish_rr(D, v == 0, v > 0, sh, q);
+  if (fin) (void)finish_rr(D, v == 0, v > 0, sh, qr);
   __syncthreads();
-  if (upd) cg_update_tile(D, B, T, v, sb, sx, pc, xc, pap0, rz, sh);
+  if (upd) cg_update_tile(D, B, T, v, sb, sx, ss, zc, pc0, xc, q, sh);
   // red half sweep from zero on the whole region
   for (int r = threadIdx.x; r < kRN; r += blockDim.x) {
     int ri, rj;
@@ -626,7 +628,7 @@ __global__ void __launch_bounds__(kRedBlock) k_mg_down(const SynthDesc *ds, cons
 }
 
 __global__ void __launch_bounds__(kRedBlock) k_mg_up(const SynthDesc *ds, const int2 *bt, int l,
-                                                     int rz, int vc, double omega) {
+                                                     int vc, double omega) {
   __shared__ double sb[kRN], sd[kRN], sax[kRN], say[kRN], sx[kRN], sh[kRedBlock];
   const Blk B = blk(bt);
   CDesc &D = cdesc(ds, B.p);
@@ -674,9 +676,113 @@ __global__ void __launch_bounds__(kRedBlock) k_mg_up(const SynthDesc *ds, const 
   }
   const bool in = gi < T.nx && gj < T.ny;
   if (in) x[gj * T.nx + gi] = xv;
-  if (rz) {
-    const double t = block_sum(in ? sb[r] * xv : 0.0, sh);
-    if (threadIdx.x == 0) red_rz(D)[B.lb] = t;
+}
+
+// Level 0 going up: as k_mg_up, over a ring of three, so that z is final on
+// the tile and a ring of one (black on the tile and a ring of two, red on
+// the tile and a ring of one); then w = A z on the tile, z and w to global,
+// and partials of r.z and z.w for the CG (b = r).
+constexpr int kU0Halo = 3, kU0W = kTW + 2 * kU0Halo, kU0H = kTH + 2 * kU0Halo;
+constexpr int kU0N = kU0W * kU0H, kU0Per = (kU0N + kRedBlock - 1) / kRedBlock;
+__global__ void __launch_bounds__(kRedBlock) k_mg_up0(const SynthDesc *ds, const int2 *bt, int vc,
+                                                      double omega) {
+  __shared__ double sb[kU0N], sd[kU0N], sax[kU0N], say[kU0N], sxc[kU0N], sx[kU0N];
+  __shared__ double sh[kRedBlock];
+  const Blk B = blk(bt);
+  CDesc &D = cdesc(ds, B.p);
+  const int32_t f1 = D.state[1], f3 = D.state[3];   // tested after the region loads
+  const LevelDev L = level(D, 0), CL = level(D, 1);
+  const double *b = cg_rv(D, vc);
+  const int nx = L.nx, ny = L.ny, sx_ = L.fx >> 1, sy_ = L.fy >> 1;
+  int ti, tj;
+  cell_ij(B.lb, (nx + kTW - 1) / kTW, ti, tj);
+  const int i0 = ti * kTW - kU0Halo, j0 = tj * kTH - kU0Halo;
+  {
+    // every load of the thread first (clamped, valid indices), then LDS
+    double vb[kU0Per], vd[kU0Per], vx[kU0Per], vy[kU0Per], vs[kU0Per], ve[kU0Per];
+    bool in[kU0Per], hx[kU0Per], hy[kU0Per];
+#pragma unroll
+    for (int k = 0; k < kU0Per; ++k) {
+      const int r = threadIdx.x + k * kRedBlock;
+      int ri, rj;
+      cell_ij(r, kU0W, ri, rj);
+      const int gi = i0 + ri, gj = j0 + rj;
+      in[k] = r < kU0N && gi >= 0 && gi < nx && gj >= 0 && gj < ny;
+      hx[k] = gi + 1 < nx;
+      hy[k] = gj + 1 < ny;
+      const int g = in[k] ? gj * nx + gi : 0;
+      vb[k] = b[g]; vd[k] = L.dg[g]; vx[k] = L.ax[g]; vy[k] = L.ay[g]; vs[k] = L.xs[g];
+      ve[k] = CL.x[in[k] ? (gj >> sy_) * CL.nx + (gi >> sx_) : 0];
+    }
+#pragma unroll
+    for (int k = 0; k < kU0Per; ++k) {
+      const int r = threadIdx.x + k * kRedBlock;
+      if (r >= kU0N) continue;
+      sb[r] = in[k] ? vb[k] : 0.0;
+      sd[r] = in[k] ? vd[k] : 1.0;
+      sax[r] = in[k] && hx[k] ? vx[k] : 0.0;
+      say[r] = in[k] && hy[k] ? vy[k] : 0.0;
+      double t = 0.0;
+      if (in[k]) {
+        t = vs[k];
+        t += omega * ve[k];
+      }
+      sxc[r] = t;
+    }
+  }
+  if (f1 != 0 || f3 != 0) return;
+  __syncthreads();
+  // black on the region less a ring of one, into sx (other cells 0)
+  for (int r = threadIdx.x; r < kU0N; r += blockDim.x) {
+    int ri, rj;
+    cell_ij(r, kU0W, ri, rj);
+    if (ri < 1 || ri > kU0W - 2 || rj < 1 || rj > kU0H - 2 || ((i0 + ri + j0 + rj) & 1) != 1) {
+      sx[r] = 0.0;
+      continue;
+    }
+    double v = sb[r];
+    v += sax[r] * sxc[r + 1];
+    v += sax[r - 1] * sxc[r - 1];
+    v += say[r] * sxc[r + kU0W];
+    v += say[r - kU0W] * sxc[r - kU0W];
+    sx[r] = v / sd[r];
+  }
+  __syncthreads();
+  // red on the region less a ring of two (reads black cells only)
+  for (int r = threadIdx.x; r < kU0N; r += blockDim.x) {
+    int ri, rj;
+    cell_ij(r, kU0W, ri, rj);
+    if (ri < 2 || ri > kU0W - 3 || rj < 2 || rj > kU0H - 3 || ((i0 + ri + j0 + rj) & 1) != 0)
+      continue;
+    double v = sb[r];
+    v += sax[r] * sx[r + 1];
+    v += sax[r - 1] * sx[r - 1];
+    v += say[r] * sx[r + kU0W];
+    v += say[r - kU0W] * sx[r - kU0W];
+    sx[r] = v / sd[r];
+  }
+  __syncthreads();
+  // the tile cell of this thread: z, w = A z, partials of r.z and z.w
+  const int ci = threadIdx.x % kTW, cj = threadIdx.x / kTW;
+  const int r = (cj + kU0Halo) * kU0W + ci + kU0Halo;
+  const int gi = i0 + kU0Halo + ci, gj = j0 + kU0Halo + cj;
+  const bool in = gi < nx && gj < ny;
+  const double zv = sx[r];
+  double wv = sd[r] * zv;
+  wv -= sax[r] * sx[r + 1];
+  wv -= sax[r - 1] * sx[r - 1];
+  wv -= say[r] * sx[r + kU0W];
+  wv -= say[r - kU0W] * sx[r - kU0W];
+  if (in) {
+    const int g = gj * nx + gi;
+    D.cg_z[g] = zv;
+    D.cg_w[g] = wv;
+  }
+  const double trz = block_sum(in ? sb[r] * zv : 0.0, sh);
+  const double tzw = block_sum(in ? zv * wv : 0.0, sh);
+  if (threadIdx.x == 0) {
+    red_rz(D)[B.lb] = trz;
+    red_zw(D)[B.lb] = tzw;
   }
 }
 
@@ -978,22 +1084,51 @@ __global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(const SynthDesc *d
     top_half(0, false);
     __syncthreads();
   }
-  // ---- out: x of the top level; r.z when the whole V-cycle ran here
-  double v = 0.0;
+  // ---- out: x of the top level (when the top level is level 0, k_cg_zw
+  // then forms w = A z and the CG's partials)
 #pragma unroll
   for (int k = 0; k < 2; ++k)
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
       const OwnCell &o = own[k][m];
-      if (!o.ok) continue;
-      const double xv = x0[o.c];
-      xout[o.c] = xv;
-      v = fma(o.b, xv, v);
+      if (o.ok) xout[o.c] = x0[o.c];
     }
-  if (D.lc == 0) {
-    // single block: the r.z partial is the whole sum
-    const double t = block_sum(v, red);
-    if (tid == 0) red_rz(D)[0] = t;
+}
+
+// For a problem whose whole V-cycle ran in the one-workgroup kernel: w = A z
+// and partials of r.z and z.w per block of cells (r of V-cycle vc).
+__global__ void k_cg_zw(const SynthDesc *ds, const int2 *bt, int vc) {
+  __shared__ double sh[kRedBlock];
+  const Blk B = blk(bt);
+  CDesc &D = cdesc(ds, B.p);
+  if (D.lc > 0) return;
+  const int32_t f1 = D.state[1], f3 = D.state[3];
+  const LevelDev L = level(D, 0);
+  const int nx = L.nx, ny = L.ny;
+  const int c = B.lb * kRedBlock + threadIdx.x;
+  const bool in = c < D.N;
+  int i = 0, j = 0;
+  if (in) cell_ij(c, nx, i, j);
+  const bool hE = in && i + 1 < nx, hW = in && i > 0, hN = in && j + 1 < ny, hS = in && j > 0;
+  const int cc = in ? c : 0;
+  const double *z = D.cg_z;
+  const double zc = z[cc], ze = z[hE ? c + 1 : cc], zw = z[hW ? c - 1 : cc];
+  const double zn = z[hN ? c + nx : cc], zs = z[hS ? c - nx : cc];
+  const double dg = L.dg[cc], aE = L.ax[cc], aW = L.ax[hW ? c - 1 : cc];
+  const double aN = L.ay[cc], aS = L.ay[hS ? c - nx : cc];
+  const double rc = cg_rv(D, vc)[cc];
+  if (f1 != 0 || f3 != 0) return;
+  double wv = dg * zc;
+  if (hE) wv -= aE * ze;
+  if (hW) wv -= aW * zw;
+  if (hN) wv -= aN * zn;
+  if (hS) wv -= aS * zs;
+  if (in) D.cg_w[c] = wv;
+  const double trz = block_sum(in ? rc * zc : 0.0, sh);
+  const double tzw = block_sum(in ? zc * wv : 0.0, sh);
+  if (threadIdx.x == 0) {
+    red_rz(D)[B.lb] = trz;
+    red_zw(D)[B.lb] = tzw;
   }
 }
 
@@ -1131,9 +1266,14 @@ void vcycle(const SynthSet &S, int v, hipStream_t s) {
                        v);
   hipLaunchKernelGGL(k_mg_coarse, dim3(S.n), dim3(kCoarseThreads), S.coarse_lds, s, ds, kOmega,
                      v);
-  for (int l = S.max_lc - 1; l >= 0; --l)
-    hipLaunchKernelGGL(k_mg_up, dim3(S.nb_tile[l]), dim3(kRedBlock), 0, s, ds, S.bt_tile[l], l,
-                       l == 0 ? 1 : 0, v, kOmega);
+  for (int l = S.max_lc - 1; l >= 1; --l)
+    hipLaunchKernelGGL(k_mg_up, dim3(S.nb_tile[l]), dim3(kRedBlock), 0, s, ds, S.bt_tile[l], l, v,
+                       kOmega);
+  if (S.max_lc > 0)
+    hipLaunchKernelGGL(k_mg_up0, dim3(S.nb_tile[0]), dim3(kRedBlock), 0, s, ds, S.bt_tile[0], v,
+                       kOmega);
+  if (S.min_lc == 0)
+    hipLaunchKernelGGL(k_cg_zw, dim3(S.nb_cell), dim3(kRedBlock), 0, s, ds, S.bt_cell, v);
 }
 
 }  // namespace
@@ -1186,7 +1326,8 @@ SynthDesc make_synth_desc(const PlanDev &P) {
   D.phih = P.phih; D.Fx = P.Fx; D.Fy = P.Fy; D.bflux = P.bflux;
   D.hx = P.hx; D.hy = P.hy; D.rhs = P.rhs; D.phi = P.phi; D.delta = P.delta; D.base = P.base;
   D.src = P.src; D.dynq = P.dynq;
-  D.cg_r = P.cg_r; D.cg_r2 = P.cg_r2; D.cg_z = P.cg_z; D.cg_p0 = P.cg_p; D.cg_p1 = P.cg_p2; D.cg_Ap = P.cg_Ap;
+  D.cg_r = P.cg_r; D.cg_r2 = P.cg_r2; D.cg_z = P.cg_z; D.cg_p = P.cg_p;
+  D.cg_s0 = P.cg_s0; D.cg_s1 = P.cg_s1; D.cg_w = P.cg_w;
   D.red = P.red; D.scal = P.scal; D.err_parts = P.err_parts; D.err_hist = P.err_hist;
   D.last_err = P.last_err; D.state = P.state;
   D.nlev = (int)P.mg.size();
@@ -1197,6 +1338,7 @@ SynthDesc make_synth_desc(const PlanDev &P) {
   const int lc = coarse_start(P);
   D.lc = lc;
   D.ntile0 = tiles_of(P.mg[0].nx, P.mg[0].ny);
+  D.ntp = std::max(D.ntile0, nblk(P.N));
   CoarseLevels &CL = D.cl;
   CL.nlev = D.nlev - lc;
   int off = 0;
@@ -1231,22 +1373,21 @@ void launch_hot_rhs(const SynthSet &S, hipStream_t s) {
   hipLaunchKernelGGL(k_rhs, dim3(S.nb_cell), dim3(kRedBlock), 0, s, S.desc, S.bt_cell);
 }
 
-// Preconditioned CG on D1 phi' = rhs for every problem of the set, each
-// warm-started from its phi (the previous synthetic solution); solutions
-// land in level 0's x. The stop test runs on the device (state[3] per
-// problem); for a single problem the host looks at it every second
-// iteration after the fourth (host_flag: pinned int32[3]) and otherwise
-// keeps enqueueing, since a converged solve turns the remaining kernels into
-// no-ops. With host_flag = NULL (graph capture, batches) the host never
-// waits and enqueues exactly S.synth_max_iter iterations.
-// CG on D1 phi' = b, preconditioned by one V-cycle per iteration. Every
-// reduction is finished inside the kernel that needs it (see red_pap).
-// With host_flag (a single problem), the host stops launching once the
-// solve has converged: it checks the device flags after the V-cycle of the
-// iteration at which the previous solve converged (host_flag[8] keeps that
-// count) and after every later one, so a steady run waits once per solve.
-// Without it (batches, graph capture) exactly synth_max_iter iterations are
-// launched and converged problems skip their kernels.
+// Preconditioned CG (the Chronopoulos-Gear form, see cg_coef) on D1 phi' =
+// rhs for every problem of the set, each warm-started from its phi (the
+// previous synthetic solution), preconditioned by one V-cycle per
+// iteration; solutions land in level 0's x. An iteration is one V-cycle:
+// its level-0 down kernel makes the previous iteration's update, its
+// level-0 up kernel forms w = A z and the partials of r.z and z.w, and
+// every reduction is finished inside the kernel that needs it (see the
+// partial regions above). The stop test runs on the device (state[3] per
+// problem). With host_flag (a single problem), the host stops launching
+// once the solve has converged: it checks the device flags after the
+// V-cycle of the iteration at which the previous solve converged
+// (host_flag[8] keeps that count) and after every later one, so a steady
+// run waits once per solve. Without it (batches, graph capture) exactly
+// synth_max_iter iterations are launched and converged problems skip their
+// kernels.
 void launch_synth_solve(const SynthSet &S, hipStream_t s, int32_t *host_flag) {
   const SynthDesc *ds = S.desc;
   const dim3 gc(S.nb_cell), bk(kRedBlock);
@@ -1254,7 +1395,6 @@ void launch_synth_solve(const SynthSet &S, hipStream_t s, int32_t *host_flag) {
   vcycle(S, 0, s);
   const int guess = host_flag ? host_flag[8] : 0;
   for (int it = 0; it < S.synth_max_iter; ++it) {
-    hipLaunchKernelGGL(k_cg_pAp, gc, bk, 0, s, ds, S.bt_cell, it);
     if (it + 1 == S.synth_max_iter) {
       // no V-cycle follows: the update on its own, then the r.r test
       hipLaunchKernelGGL(k_cg_update, gc, bk, 0, s, ds, S.bt_cell, it, 1);
