@@ -169,9 +169,9 @@ enum {
   GSIS_PHASE_SWEEP = 1,    /* exact first-order-upwind increment solve on the
                               wavefront (Eqs. RTE_d_increment..elem_mtx) */
   GSIS_PHASE_MOMENTS = 2,  /* phi and F of the swept intensity */
-  GSIS_PHASE_HOT = 3,      /* boundary fluxes, HoT, synthetic right-hand side */
-  GSIS_PHASE_SYNTH = 4,    /* synthetic CG + multigrid solve */
-  GSIS_PHASE_UPDATE = 5,   /* correction and Err */
+  GSIS_PHASE_HOT = 3,      /* boundary fluxes, HoT */
+  GSIS_PHASE_SYNTH = 4,    /* synthetic right-hand side, CG + multigrid solve */
+  GSIS_PHASE_UPDATE = 5,   /* correction, Err and the next source */
   GSIS_NUM_PHASES = 6
 };
 /* Wait for the plan's stream; ms[GSIS_NUM_PHASES] receives the summed

@@ -297,8 +297,8 @@ void enqueue_iteration(gsis_batch *b, bool capture) {
   launch_moments_batch(b->targs, b->S.bt_cell, b->S.nb_cell, b->fp32, s);
   if (b->method == GSIS_GSIS) {
     launch_boundary_flux_batch(b->targs, b->bt_face, b->nb_face, s);
-    launch_hot_rhs(b->S, s);
-    launch_synth_solve(b->S, s, nullptr);
+    launch_hot(b->S, s);
+    launch_synth_solve(b->S, s, nullptr, true);
   }
   launch_update(b->S, s);
 }

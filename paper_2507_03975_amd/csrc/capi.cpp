@@ -666,10 +666,10 @@ extern "C" gsis_status gsis_plan_iterate(gsis_plan *pl, int32_t n) {
     if ((st = record(pl, 3))) return st;
     if (P.method == GSIS_GSIS) {
       launch_boundary_flux(P, s);
-      launch_hot_rhs(P.S, s);
+      launch_hot(P.S, s);
     }
     if ((st = record(pl, 4))) return st;
-    if (P.method == GSIS_GSIS) launch_synth_solve(P.S, s, (int32_t *)pl->host_scal);
+    if (P.method == GSIS_GSIS) launch_synth_solve(P.S, s, (int32_t *)pl->host_scal, true);
     if ((st = record(pl, 5))) return st;
     launch_update(P.S, s);
     if ((st = record(pl, 6))) return st;

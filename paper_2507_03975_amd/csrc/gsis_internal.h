@@ -231,10 +231,12 @@ int tiles_of(int nx, int ny);   // multigrid tiles covering an nx x ny level
 int source_tiles_of(int nx, int ny);   // 16 x 16 tiles of the source kernel
 void prepare_synth(size_t coarse_lds);      // kernel attribute for the LDS size
 void launch_source(const SynthSet &S, hipStream_t s);          // src from phi
-void launch_hot_rhs(const SynthSet &S, hipStream_t s);
+void launch_hot(const SynthSet &S, hipStream_t s);               // HoT of every cell
 // host_flag: pinned int32[3] for the host's stop checks (single problem);
 // NULL never waits and enqueues exactly S.synth_max_iter iterations.
-void launch_synth_solve(const SynthSet &S, hipStream_t s, int32_t *host_flag);
+// rhs_from_hot: the first kernel forms the right-hand side from the HoT
+// (forward solve); otherwise it reads the descriptor's rhs (adjoint).
+void launch_synth_solve(const SynthSet &S, hipStream_t s, int32_t *host_flag, bool rhs_from_hot);
 void launch_update(const SynthSet &S, hipStream_t s);
 void launch_apply_delta_final(const PlanDev &P, hipStream_t s, double swmu, double sweta,
                               double *Fx_out, double *Fy_out);

@@ -124,15 +124,9 @@ __global__ void k_hot(const SynthDesc *ds, const int2 *bt) {
   D.hy[c] = hy;
 }
 
-__global__ void k_rhs(const SynthDesc *ds, const int2 *bt) {
-  const Blk B = blk(bt);
-  CDesc &D = cdesc(ds, B.p);
-  const int32_t f1 = D.state[1];   // tested after the operands are loaded
+// b_c of cell c = (i, j) from the HoT of the cell and its neighbours
+__device__ inline double rhs_at(CDesc &D, int c, int i, int j) {
   const int nx = D.nx, ny = D.ny;
-  const int c = B.lb * kRedBlock + threadIdx.x;
-  if (c >= D.N) return;
-  int i, j;
-  cell_ij(c, nx, i, j);
   const double dx = D.dx, dy = D.dy;
   const double *hx = D.hx, *hy = D.hy, *bflux = D.bflux, *kappa = D.kappa;
   const double ph = D.phih[c];
@@ -146,8 +140,7 @@ __global__ void k_rhs(const SynthDesc *ds, const int2 *bt) {
   else s -= dx * (bflux[2 * ny + nx + i] - kappa[2 * ny + nx + i] * ph);
   if (j > 0) s += dx * (0.5 * (hy[c] + hy[c - nx]));
   else s -= dx * (bflux[2 * ny + i] - kappa[2 * ny + i] * ph);
-  if (f1 != 0) return;
-  D.rhs[c] = s;
+  return s;
 }
 
 // ------------------------------------------------------- 5-point operator
@@ -277,27 +270,38 @@ __global__ void k_finish_rr(const SynthDesc *ds) {
 
 // Start of a synthetic solve: warm start x = phi, clear the converged flag;
 // r = b - A x; partials of r.r and b.b.
+// RHS: the right-hand side b is formed here from the HoT (and stored)
+// rather than read.
+template <bool RHS>
 __global__ void k_cg_begin(const SynthDesc *ds, const int2 *bt) {
   __shared__ double sh[kRedBlock];
   const Blk B = blk(bt);
   CDesc &D = cdesc(ds, B.p);
-  if (D.state[1] != 0) return;
+  const int32_t f1 = D.state[1];   // tested after the operands are loaded
   const int c = B.lb * kRedBlock + threadIdx.x;
   const LevelDev L = level(D, 0);
+  const bool in = c < D.N;
+  const int cc = in ? c : 0;
+  int i, j;
+  cell_ij(cc, L.nx, i, j);
+  const bool hE = i + 1 < L.nx, hW = i > 0, hN = j + 1 < L.ny, hS = j > 0;
+  // x = phi for the cell and its neighbours (this kernel writes x)
+  const double *X = D.phi;
+  const double xc = X[cc], xe = X[hE ? cc + 1 : cc], xw = X[hW ? cc - 1 : cc];
+  const double xn = X[hN ? cc + L.nx : cc], xs = X[hS ? cc - L.nx : cc];
+  const double dg = L.dg[cc], aE = L.ax[cc], aW = L.ax[hW ? cc - 1 : cc];
+  const double aN = L.ay[cc], aS = L.ay[hS ? cc - L.nx : cc];
+  const double b = RHS ? rhs_at(D, cc, i, j) : D.rhs[cc];
+  if (f1 != 0) return;
   double rr = 0.0, bb = 0.0;
-  if (c < D.N) {
-    // x = phi for the cell and its neighbours (this kernel writes x)
-    auto X = [&](int k) { return D.phi[k]; };
-    int i, j;
-    cell_ij(c, L.nx, i, j);
-    const double xc = X(c);
-    double y = L.dg[c] * xc;
-    if (i + 1 < L.nx) y -= L.ax[c] * X(c + 1);
-    if (i > 0) y -= L.ax[c - 1] * X(c - 1);
-    if (j + 1 < L.ny) y -= L.ay[c] * X(c + L.nx);
-    if (j > 0) y -= L.ay[c - L.nx] * X(c - L.nx);
-    const double b = D.rhs[c];
+  if (in) {
+    double y = dg * xc;
+    if (hE) y -= aE * xe;
+    if (hW) y -= aW * xw;
+    if (hN) y -= aN * xn;
+    if (hS) y -= aS * xs;
     const double rc = b - y;
+    if (RHS) D.rhs[c] = b;
     L.x[c] = xc;
     D.cg_r[c] = rc;
     rr = rc * rc;
@@ -1166,9 +1170,7 @@ __global__ void k_update(const SynthDesc *ds, const int2 *bt) {
 
 // One workgroup per problem: Err = sqrt(num/den) -> history, counters, done
 // flag.
-__global__ void k_err_finish(const SynthDesc *ds) {
-  __shared__ double sh[kRedBlock];
-  CDesc &D = cdesc(ds, blockIdx.x);
+__device__ inline void err_finish(CDesc &D, double *sh) {
   int32_t *state = D.state;
   if (state[1] != 0) return;
   const int npart = nblk_d(D.N);
@@ -1200,10 +1202,8 @@ __global__ void k_err_finish(const SynthDesc *ds) {
 // diagonal run over consecutive lanes and consecutive addresses.
 constexpr int kSrcT = 16;
 static_assert(kSrcT * kSrcT == kRedBlock, "one thread per tile cell");
-__global__ void __launch_bounds__(kRedBlock) k_source(const SynthDesc *ds, const int2 *bt) {
-  __shared__ double s_sc[kRedBlock], s_dq[kRedBlock], s_pq[kRedBlock];
-  const Blk B = blk(bt);
-  CDesc &D = cdesc(ds, B.p);
+__device__ inline void source_tile(CDesc &D, const Blk &B, double *s_sc, double *s_dq,
+                                   double *s_pq) {
   const int32_t f1 = D.state[1];   // tested after the operands are loaded
   const int nx = D.nx, ny = D.ny, n = D.N;
   int ti, tj;
@@ -1244,6 +1244,33 @@ __global__ void __launch_bounds__(kRedBlock) k_source(const SynthDesc *ds, const
     D.dynq[o + n] = s_dq[l];      // plane 1
     if (D.fp32) D.dynq[o + 2 * n] = s_pq[l];
   }
+}
+
+__global__ void __launch_bounds__(kRedBlock) k_source(const SynthDesc *ds, const int2 *bt) {
+  __shared__ double s_sc[kRedBlock], s_dq[kRedBlock], s_pq[kRedBlock];
+  const Blk B = blk(bt);
+  source_tile(cdesc(ds, B.p), B, s_sc, s_dq, s_pq);
+}
+
+// End of an outer iteration: blocks [0, n) finish Err of problem blockIdx.x,
+// the others make source tiles (table bt, or one problem's tiles in order).
+// The two do not depend on each other; the source is written also on the
+// iteration that ends the solve.
+__global__ void __launch_bounds__(kRedBlock) k_err_source(const SynthDesc *ds, const int2 *bt,
+                                                          int n) {
+  __shared__ double s_sc[kRedBlock], s_dq[kRedBlock], s_pq[kRedBlock];
+  if ((int)blockIdx.x < n) {
+    err_finish(cdesc(ds, blockIdx.x), s_sc);
+    return;
+  }
+  const int idx = blockIdx.x - n;
+  Blk B = {0, idx};
+  if (bt) {
+    const __attribute__((address_space(4))) int *q =
+        (const __attribute__((address_space(4))) int *)bt;
+    B = {q[2 * idx], q[2 * idx + 1]};
+  }
+  source_tile(cdesc(ds, B.p), B, s_sc, s_dq, s_pq);
 }
 
 // Final F with the pending correction: F = F_half + delta/(4 pi) sum_k w Omega_k
@@ -1368,9 +1395,8 @@ void launch_source(const SynthSet &S, hipStream_t s) {
   hipLaunchKernelGGL(k_source, dim3(S.nb_src), dim3(kRedBlock), 0, s, S.desc, S.bt_src);
 }
 
-void launch_hot_rhs(const SynthSet &S, hipStream_t s) {
+void launch_hot(const SynthSet &S, hipStream_t s) {
   hipLaunchKernelGGL(k_hot, dim3(S.nb_cell), dim3(kRedBlock), 0, s, S.desc, S.bt_cell);
-  hipLaunchKernelGGL(k_rhs, dim3(S.nb_cell), dim3(kRedBlock), 0, s, S.desc, S.bt_cell);
 }
 
 // Preconditioned CG (the Chronopoulos-Gear form, see cg_coef) on D1 phi' =
@@ -1388,10 +1414,11 @@ void launch_hot_rhs(const SynthSet &S, hipStream_t s) {
 // run waits once per solve. Without it (batches, graph capture) exactly
 // synth_max_iter iterations are launched and converged problems skip their
 // kernels.
-void launch_synth_solve(const SynthSet &S, hipStream_t s, int32_t *host_flag) {
+void launch_synth_solve(const SynthSet &S, hipStream_t s, int32_t *host_flag, bool rhs_from_hot) {
   const SynthDesc *ds = S.desc;
   const dim3 gc(S.nb_cell), bk(kRedBlock);
-  hipLaunchKernelGGL(k_cg_begin, gc, bk, 0, s, ds, S.bt_cell);
+  if (rhs_from_hot) hipLaunchKernelGGL(k_cg_begin<true>, gc, bk, 0, s, ds, S.bt_cell);
+  else hipLaunchKernelGGL(k_cg_begin<false>, gc, bk, 0, s, ds, S.bt_cell);
   vcycle(S, 0, s);
   const int guess = host_flag ? host_flag[8] : 0;
   for (int it = 0; it < S.synth_max_iter; ++it) {
@@ -1421,8 +1448,8 @@ void launch_synth_solve(const SynthSet &S, hipStream_t s, int32_t *host_flag) {
 
 void launch_update(const SynthSet &S, hipStream_t s) {
   hipLaunchKernelGGL(k_update, dim3(S.nb_cell), dim3(kRedBlock), 0, s, S.desc, S.bt_cell);
-  hipLaunchKernelGGL(k_err_finish, dim3(S.n), dim3(kRedBlock), 0, s, S.desc);
-  launch_source(S, s);
+  hipLaunchKernelGGL(k_err_source, dim3(S.n + S.nb_src), dim3(kRedBlock), 0, s, S.desc, S.bt_src,
+                     S.n);
 }
 
 void launch_apply_delta_final(const PlanDev &P, hipStream_t s, double swmu, double sweta,
