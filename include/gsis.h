@@ -168,8 +168,8 @@ enum {
                               written as the recurrence's right-hand side */
   GSIS_PHASE_SWEEP = 1,    /* exact first-order-upwind increment solve on the
                               wavefront (Eqs. RTE_d_increment..elem_mtx) */
-  GSIS_PHASE_MOMENTS = 2,  /* phi and F of the swept intensity */
-  GSIS_PHASE_HOT = 3,      /* boundary fluxes, HoT */
+  GSIS_PHASE_MOMENTS = 2,  /* phi and F of the swept intensity, boundary fluxes */
+  GSIS_PHASE_HOT = 3,      /* HoT */
   GSIS_PHASE_SYNTH = 4,    /* synthetic right-hand side, CG + multigrid solve */
   GSIS_PHASE_UPDATE = 5,   /* correction, Err and the next source */
   GSIS_NUM_PHASES = 6

@@ -662,10 +662,9 @@ extern "C" gsis_status gsis_plan_iterate(gsis_plan *pl, int32_t n) {
     if ((st = record(pl, 1))) return st;
     launch_sweep(P, s);
     if ((st = record(pl, 2))) return st;
-    launch_moments(P, s);
+    launch_moments(P, s, P.method == GSIS_GSIS);
     if ((st = record(pl, 3))) return st;
     if (P.method == GSIS_GSIS) {
-      launch_boundary_flux(P, s);
       launch_hot(P.S, s);
     }
     if ((st = record(pl, 4))) return st;

@@ -218,8 +218,8 @@ void launch_moments_batch(const void *targs, const int2 *bt_cell, int nb_cell, b
                           hipStream_t s);
 void launch_boundary_flux_batch(const void *targs, const int2 *bt_face, int nb_face,
                                 hipStream_t s);
-void launch_moments(const PlanDev &P, hipStream_t s);
-void launch_boundary_flux(const PlanDev &P, hipStream_t s);
+// phi, F of the swept intensity; with bflux also the boundary faces' F_T . n
+void launch_moments(const PlanDev &P, hipStream_t s, bool bflux);
 
 // ---- synthetic / update kernels (kernels_synth.hip)
 // Descriptor of plan P's synthetic step (host copy; P's arrays and levels

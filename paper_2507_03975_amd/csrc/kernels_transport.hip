@@ -1034,7 +1034,7 @@ __device__ inline void dg_cell(long long t, int nx, int ny, int &x, int &y) {
 template <typename T>
 __device__ __forceinline__ void moments_q(const TArgs &a, double *part, const long long t,
                                           const int q) {
-  if (a.state[1] != 0) return;
+  const int f1 = a.state[1];   // tested once the first values are loaded
   if (t >= a.N) return;
   int x, y;
   dg_cell(t, a.nx, a.ny, x, y);
@@ -1048,10 +1048,15 @@ __device__ __forceinline__ void moments_q(const TArgs &a, double *part, const lo
   double s0 = 0, sx = 0, sy = 0;
   int kk = a.qoff[q];
   const int ke = a.qoff[q + 1];
+  bool tested = false;
   for (; kk + 8 <= ke; kk += 8) {
     double v[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) v[u] = (double)O[(size_t)(kk + u) * a.N + t];
+    if (!tested) {
+      if (f1 != 0) return;
+      tested = true;
+    }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       s0 += W[kk + u] * v[u];
@@ -1059,6 +1064,7 @@ __device__ __forceinline__ void moments_q(const TArgs &a, double *part, const lo
       sy += WE[kk + u] * v[u];
     }
   }
+  if (f1 != 0) return;
   for (; kk < ke; ++kk) {
     const double v = (double)O[(size_t)kk * a.N + t];
     s0 += W[kk] * v;
@@ -1084,16 +1090,21 @@ __global__ void k_moments_q_b(const TArgs *tas, const int2 *bt) {
 }
 
 __device__ __forceinline__ void moments_combine(const TArgs &a, const double *part, const int c) {
-  if (a.state[1] != 0) return;
+  const int f1 = a.state[1];   // tested after the loads
   if (c >= a.N) return;
+  double v[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) v[k] = part[(size_t)k * a.N + c];
+  const double ph = a.fp32 ? a.phi[c] : 0.0;
+  if (f1 != 0) return;
   double s0 = 0, sx = 0, sy = 0;
   for (int q = 0; q < 4; ++q) {
-    s0 += part[(size_t)(3 * q) * a.N + c];
-    sx += part[(size_t)(3 * q + 1) * a.N + c];
-    sy += part[(size_t)(3 * q + 2) * a.N + c];
+    s0 += v[3 * q];
+    sx += v[3 * q + 1];
+    sy += v[3 * q + 2];
   }
   if (a.fp32) {                               // I^{m+1/2} = Itilde + phi^m/(4 pi)
-    const double sub = a.phi[c] / kFourPi;
+    const double sub = ph / kFourPi;
     s0 += sub * a.sw; sx += sub * a.swm; sy += sub * a.swe;
   }
   a.phih[c] = s0; a.Fx[c] = sx; a.Fy[c] = sy;
@@ -1112,7 +1123,7 @@ __global__ void k_moments_combine_b(const TArgs *tas, const int2 *bt) {
 // F_T . n_out on each boundary face: one workgroup per face, threads over
 // ordinates, fixed-order tree sum.
 __device__ __forceinline__ void boundary_flux(const TArgs &a, const int f) {
-  if (a.state[1] != 0) return;
+  const int f1 = a.state[1];   // tested before the store
   int side, pos;
   if (f < a.ny) { side = 0; pos = f; }                       // W
   else if (f < 2 * a.ny) { side = 1; pos = f - a.ny; }        // E
@@ -1154,10 +1165,15 @@ __device__ __forceinline__ void boundary_flux(const TArgs &a, const int f) {
     if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
     __syncthreads();
   }
-  if (threadIdx.x == 0) a.bflux[f] = red[0];
+  if (threadIdx.x == 0 && f1 == 0) a.bflux[f] = red[0];
 }
 
-__global__ void k_boundary_flux(TArgs a) { boundary_flux(a, blockIdx.x); }
+// The moments' combine (blocks [0, nbc)) and the boundary faces' F_T . n (the
+// other blocks) in one launch: both only read the swept intensity.
+__global__ void k_combine_bflux(TArgs a, const double *part, int nbc) {
+  if ((int)blockIdx.x < nbc) moments_combine(a, part, blockIdx.x * blockDim.x + threadIdx.x);
+  else boundary_flux(a, blockIdx.x - nbc);
+}
 
 __global__ void k_boundary_flux_b(const TArgs *tas, const int2 *bt) {
   const int2 v = bt[blockIdx.x];
@@ -1340,21 +1356,19 @@ void launch_sweep_batch(const void *targs, const int2 *items, int n_items, int *
 #undef GSIS_BATCH_LAUNCH
 }
 
-void launch_moments(const PlanDev &P, hipStream_t s) {
+void launch_moments(const PlanDev &P, hipStream_t s, bool bflux) {
   TArgs a = make_args(P);
+  const int nbc = (P.N + 255) / 256;
   if (a.fp32)
-    hipLaunchKernelGGL(k_moments_q<float>, dim3((P.N + 255) / 256, 4), dim3(256), 0, s, a,
-                       P.mom_part);
+    hipLaunchKernelGGL(k_moments_q<float>, dim3(nbc, 4), dim3(256), 0, s, a, P.mom_part);
   else
-    hipLaunchKernelGGL(k_moments_q<double>, dim3((P.N + 255) / 256, 4), dim3(256), 0, s, a,
-                       P.mom_part);
-  hipLaunchKernelGGL(k_moments_combine, dim3((P.N + 255) / 256), dim3(256), 0, s, a,
-                     (const double *)P.mom_part);
-}
-
-void launch_boundary_flux(const PlanDev &P, hipStream_t s) {
-  TArgs a = make_args(P);
-  hipLaunchKernelGGL(k_boundary_flux, dim3(P.nbf), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_moments_q<double>, dim3(nbc, 4), dim3(256), 0, s, a, P.mom_part);
+  if (bflux)
+    hipLaunchKernelGGL(k_combine_bflux, dim3(nbc + P.nbf), dim3(256), 0, s, a,
+                       (const double *)P.mom_part, nbc);
+  else
+    hipLaunchKernelGGL(k_moments_combine, dim3(nbc), dim3(256), 0, s, a,
+                       (const double *)P.mom_part);
 }
 
 void launch_moments_batch(const void *targs, const int2 *bt_cell, int nb_cell, bool fp32,
