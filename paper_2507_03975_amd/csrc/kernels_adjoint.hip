@@ -194,40 +194,53 @@ __global__ void k_a_phbar(AArgs a, const double *kappa) {
 // Ih_bar = lambda + w (phb + mu hbx + eta hby) + the outflow-wall
 // reconstruction transposed (GSIS); lambda alone (SI).
 __global__ void k_a_ihalf(AArgs a) {
+  // one thread per stored cell of quadrant blockIdx.y, looping over the
+  // quadrant's ordinates: the cell's cotangents, boundary terms and record
+  // entries are loaded once for all of them
   const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  const int kk = blockIdx.y;
+  const int q = blockIdx.y;
   if (t >= a.N) return;
-  const size_t o = (size_t)kk * a.N + t;
-  double v = a.lam[o];
-  if (a.method == 1) {
-    const int q = quadrant_of(a, kk);
+  const bool gsis = a.method == 1;
+  double phb = 0.0, hxb = 0.0, hyb = 0.0;
+  double be = 0.0, be2 = 0.0, bn = 0.0, bn2 = 0.0, ce = 0.0, ce2 = 0.0, cn = 0.0, cn2 = 0.0;
+  bool xe = false, xe2 = false, yn = false, yn2 = false;
+  const double hx = 0.5 * a.dx, hy = 0.5 * a.dy;
+  const int so = a.order >= 2;
+  if (gsis) {
     int x, y;
     dg_cell(t, a.nx, a.ny, x, y);
     const int c = gcell(a, q, x, y);
-    v += a.w[kk] * a.phb[c] + a.wmu[kk] * a.hxb[c] + a.weta[kk] * a.hyb[c];
+    phb = a.phb[c]; hxb = a.hxb[c]; hyb = a.hyb[c];
     const double *Cq = a.cellq + (size_t)q * a.N * 6;
-    const double hx = 0.5 * a.dx, hy = 0.5 * a.dy;
-    const double wmx = fabs(a.wmu[kk]), wmy = fabs(a.weta[kk]);
-    const int so = a.order >= 2;
     // local east face of the last column: value u_c + hx (cW (u_c - u_w))
-    if (x == a.nx - 1) {
-      const double vb = a.bfb[face_e(a, q, y)] * wmx;
-      v += vb * (1.0 + (so && x > 0 ? hx * Cq[6 * t + 1] : 0.0));
-    }
-    if (so && x == a.nx - 2) {
-      const long long te = dg_idx(x + 1, y, a.nx, a.ny);
-      v -= a.bfb[face_e(a, q, y)] * wmx * hx * Cq[6 * te + 1];
-    }
-    if (y == a.ny - 1) {
-      const double vb = a.bfb[face_n(a, q, x)] * wmy;
-      v += vb * (1.0 + (so && y > 0 ? hy * Cq[6 * t + 3] : 0.0));
-    }
-    if (so && y == a.ny - 2) {
-      const long long tn = dg_idx(x, y + 1, a.nx, a.ny);
-      v -= a.bfb[face_n(a, q, x)] * wmy * hy * Cq[6 * tn + 3];
-    }
+    xe = x == a.nx - 1;
+    xe2 = so && x == a.nx - 2;
+    yn = y == a.ny - 1;
+    yn2 = so && y == a.ny - 2;
+    if (xe) { be = a.bfb[face_e(a, q, y)]; ce = so && x > 0 ? hx * Cq[6 * t + 1] : 0.0; }
+    if (xe2) { be2 = a.bfb[face_e(a, q, y)]; ce2 = Cq[6 * dg_idx(x + 1, y, a.nx, a.ny) + 1]; }
+    if (yn) { bn = a.bfb[face_n(a, q, x)]; cn = so && y > 0 ? hy * Cq[6 * t + 3] : 0.0; }
+    if (yn2) { bn2 = a.bfb[face_n(a, q, x)]; cn2 = Cq[6 * dg_idx(x, y + 1, a.nx, a.ny) + 3]; }
   }
-  a.ihb[o] = v;
+  for (int kk = a.qoff[q]; kk < a.qoff[q + 1]; ++kk) {
+    const size_t o = (size_t)kk * a.N + t;
+    double v = a.lam[o];
+    if (gsis) {
+      v += a.w[kk] * phb + a.wmu[kk] * hxb + a.weta[kk] * hyb;
+      const double wmx = fabs(a.wmu[kk]), wmy = fabs(a.weta[kk]);
+      if (xe) {
+        const double vb = be * wmx;
+        v += vb * (1.0 + ce);
+      }
+      if (xe2) v -= be2 * wmx * hx * ce2;
+      if (yn) {
+        const double vb = bn * wmy;
+        v += vb * (1.0 + cn);
+      }
+      if (yn2) v -= bn2 * wmy * hy * cn2;
+    }
+    a.ihb[o] = v;
+  }
 }
 
 // rb = H^-T ihb per ordinate: rb_c = (ihb_c + ax rb_east + ay rb_north) / d_c,
@@ -284,56 +297,65 @@ __global__ void k_a_sweep(AArgs a) {
 // E_c = u_c + hx (cE (u_e - u_c) - cW (u_w - u_c)) the east face value; so
 // Ebar_c = -ax (rb_c - rb_e) and ubar_d collects Ebar of d, d-1, d+1.
 __global__ void k_a_out(AArgs a) {
+  // one thread per stored cell of quadrant blockIdx.y, looping over the
+  // quadrant's ordinates: the cell's record entries, neighbour positions and
+  // cotangents are loaded once for all of them
   const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  const int kk = blockIdx.y;
+  const int q = blockIdx.y;
   if (t >= a.N) return;
-  const int q = quadrant_of(a, kk);
   const int nx = a.nx, ny = a.ny;
   int x, y;
   dg_cell(t, nx, ny, x, y);
   const int c = gcell(a, q, x, y);
   const double *Cq = a.cellq + (size_t)q * a.N * 6;
-  const double *R = a.rb + (size_t)kk * a.N;
-  const double ax = a.amu[kk], ay = a.aeta[kk];
   const double hx = 0.5 * a.dx, hy = 0.5 * a.dy;
   auto I = [&](int xx, int yy) { return dg_idx(xx, yy, nx, ny); };
-  auto Eb = [&](int xx) {       // Ebar at local column xx of row y
-    const double r = R[I(xx, y)];
-    return -ax * (xx + 1 < nx ? r - R[I(xx + 1, y)] : r);
-  };
-  auto Nb = [&](int yy) {
-    const double r = R[I(x, yy)];
-    return -ay * (yy + 1 < ny ? r - R[I(x, yy + 1)] : r);
-  };
-  const size_t o = (size_t)kk * a.N + t;
-  const double rc = R[t];
-  double v = a.ihb[o] - Cq[6 * t + 4] * rc;
-  double ub = 0.0;
-  {
-    const double e0 = Eb(x);
-    if (a.order >= 2) {
-      ub += e0 * (1.0 - hx * Cq[6 * t + 0] + hx * Cq[6 * t + 1]);
-      if (x > 0) ub += Eb(x - 1) * hx * Cq[6 * I(x - 1, y) + 0];
-      if (x + 1 < nx) ub -= Eb(x + 1) * hx * Cq[6 * I(x + 1, y) + 1];
-    } else {
-      ub += e0;
+  const bool hE = x + 1 < nx, hE2 = x + 2 < nx, hW = x > 0;
+  const bool hN = y + 1 < ny, hN2 = y + 2 < ny, hS = y > 0;
+  const long long tE = hE ? I(x + 1, y) : t, tE2 = hE2 ? I(x + 2, y) : t, tW = hW ? I(x - 1, y) : t;
+  const long long tN = hN ? I(x, y + 1) : t, tN2 = hN2 ? I(x, y + 2) : t, tS = hS ? I(x, y - 1) : t;
+  const bool so = a.order >= 2;
+  const double c0 = Cq[6 * t + 0], c1 = Cq[6 * t + 1], c2 = Cq[6 * t + 2], c3 = Cq[6 * t + 3];
+  const double c4 = Cq[6 * t + 4];
+  const double cW0 = Cq[6 * tW + 0], cE1 = Cq[6 * tE + 1], cS2 = Cq[6 * tS + 2], cN3 = Cq[6 * tN + 3];
+  const double sgs = a.sig_s[c], sbc = a.Sb[c];
+  const double gp = a.gphi ? a.gphi[c] : 0.0, gx = a.gFx ? a.gFx[c] : 0.0;
+  const double gy = a.gFy ? a.gFy[c] : 0.0;
+  for (int kk = a.qoff[q]; kk < a.qoff[q + 1]; ++kk) {
+    const double *R = a.rb + (size_t)kk * a.N;
+    const double ax = a.amu[kk], ay = a.aeta[kk];
+    const double r0 = R[t], rE = R[tE], rE2 = R[tE2], rW = R[tW];
+    const double rN = R[tN], rN2 = R[tN2], rS = R[tS];
+    const size_t o = (size_t)kk * a.N + t;
+    double v = a.ihb[o] - c4 * r0;
+    double ub = 0.0;
+    {
+      // Ebar at columns x, x - 1, x + 1 of row y; Nbar likewise
+      const double e0 = -ax * (hE ? r0 - rE : r0);
+      if (so) {
+        ub += e0 * (1.0 - hx * c0 + hx * c1);
+        if (hW) ub += (-ax * (rW - r0)) * hx * cW0;
+        if (hE) ub -= (-ax * (hE2 ? rE - rE2 : rE)) * hx * cE1;
+      } else {
+        ub += e0;
+      }
+      const double n0 = -ay * (hN ? r0 - rN : r0);
+      if (so) {
+        ub += n0 * (1.0 - hy * c2 + hy * c3);
+        if (hS) ub += (-ay * (rS - r0)) * hy * cS2;
+        if (hN) ub -= (-ay * (hN2 ? rN - rN2 : rN)) * hy * cN3;
+      } else {
+        ub += n0;
+      }
     }
-    const double n0 = Nb(y);
-    if (a.order >= 2) {
-      ub += n0 * (1.0 - hy * Cq[6 * t + 2] + hy * Cq[6 * t + 3]);
-      if (y > 0) ub += Nb(y - 1) * hy * Cq[6 * I(x, y - 1) + 2];
-      if (y + 1 < ny) ub -= Nb(y + 1) * hy * Cq[6 * I(x, y + 1) + 3];
-    } else {
-      ub += n0;
-    }
+    v += ub;
+    v += a.w[kk] * sgs * sbc * kInv4Pi;
+    double g = 0.0;
+    if (a.gphi) g += a.w[kk] * gp;
+    if (a.gFx) g += a.wmu[kk] * gx;
+    if (a.gFy) g += a.weta[kk] * gy;
+    a.lam[o] = v + g;
   }
-  v += ub;
-  v += a.w[kk] * a.sig_s[c] * a.Sb[c] * kInv4Pi;
-  double g = 0.0;
-  if (a.gphi) g += a.w[kk] * a.gphi[c];
-  if (a.gFx) g += a.wmu[kk] * a.gFx[c];
-  if (a.gFy) g += a.weta[kk] * a.gFy[c];
-  a.lam[o] = v + g;
 }
 
 // Gradient pass, per quadrant and stored cell, summed over the quadrant's
@@ -535,13 +557,13 @@ void adj_launch_pass(const PlanDev &P, const AdjointBuffers &B, const void *args
     hipLaunchKernelGGL(k_a_hbar, dim3(nb), dim3(kB), 0, s, a);
     hipLaunchKernelGGL(k_a_phbar, dim3(nb), dim3(kB), 0, s, a, (const double *)P.kappa);
   }
-  hipLaunchKernelGGL(k_a_ihalf, dim3(nb, P.K), dim3(kB), 0, s, a);
+  hipLaunchKernelGGL(k_a_ihalf, dim3(nb, 4), dim3(kB), 0, s, a);
   int rows = ((P.ny + 63) / 64) * 64;
   if (rows > 1024) rows = 1024;
   hipLaunchKernelGGL(k_a_sweep, dim3(P.K), dim3(rows), 0, s, a);
   hipLaunchKernelGGL(k_a_qsum, dim3(nb, 4), dim3(kB), 0, s, a, (const double *)a.rb);
   hipLaunchKernelGGL(k_a_combine, dim3(nb), dim3(kB), 0, s, a, a.Sb, 1.0, 0);
-  hipLaunchKernelGGL(k_a_out, dim3(nb, P.K), dim3(kB), 0, s, a);
+  hipLaunchKernelGGL(k_a_out, dim3(nb, 4), dim3(kB), 0, s, a);
   (void)B;
 }
 
