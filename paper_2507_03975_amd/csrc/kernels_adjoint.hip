@@ -26,6 +26,7 @@
 // transport residual on I*, the wall reconstruction on I^{m+1/2}, the HoT on
 // phi^{m+1/2}), 1/(3 sigma_t) in the HoT, kappa, Gamma, and sigma_a in D1.
 #include "gsis_internal.h"
+#include "wave_ops.h"
 
 #include <cstring>
 
@@ -42,6 +43,8 @@ struct AArgs {
   const double *w, *wmu, *weta, *amu, *aeta;                  // internal ordinates
   const double *sig_t, *sig_s, *cE, *cW, *cN, *cS;            // caller's cell order
   const double *cellq;                                        // [4][N][6] mirrored
+  const double *sdq;                                          // [4][N] sigma_t + shift, stored order
+  const int *dso;                                             // row-0 storage index per diagonal
   const double *Ih;                                           // I^{m+1/2} [K][N]
   const double *delta, *phi, *phih;
   const double *gphi, *gFx, *gFy;                             // cotangents or null
@@ -292,6 +295,84 @@ __global__ void k_a_sweep(AArgs a) {
   }
 }
 
+// The same sweep for grids of at most 1024 rows, shaped like the forward
+// recurrence: lane t owns reversed row t, step s is reversed anti-diagonal s
+// (local diagonal nx + ny - 2 - s, so a step's storage indices are one table
+// entry plus the lane's row), rb_north is lane t-1's previous value (a DPP
+// shift), waves run kAL steps apart and meet at a barrier every kAL steps
+// (the top lane's values through an LDS ring), and the operands of a step
+// (ihb, sigma_t + shift) are loaded kAL steps ahead. Out-of-range indices
+// fall outside the buffer resources: their loads read 0, their stores are
+// dropped. rb = ihb / d + (ax / d) rb_east + (ay / d) rb_north.
+constexpr int kAL = 8, kAR = 4 * kAL, kAMaxW = 16;
+static_assert(kAMaxW * kAL + 2 * kAL <= kDiagPad, "diagonal table padding");
+__global__ void __launch_bounds__(kAMaxW * 64) k_a_chain(AArgs a) {
+  const int kk = blockIdx.x;
+  const int q = quadrant_of(a, kk);
+  const int nx = a.nx, ny = a.ny, N = a.N;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const double ax = a.amu[kk], ay = a.aeta[kk], axy = ax + ay;
+  const __amdgpu_buffer_rsrc_t Sr = buf_rsrc(a.ihb + (size_t)kk * N, (size_t)N * 8);
+  const __amdgpu_buffer_rsrc_t Dr = buf_rsrc(a.sdq + (size_t)q * N, (size_t)N * 8);
+  const __amdgpu_buffer_rsrc_t Or = buf_rsrc(a.rb + (size_t)kk * N, (size_t)N * 8);
+  const __attribute__((address_space(4))) int *DS =
+      (const __attribute__((address_space(4))) int *)(a.dso + kDiagPad);
+  __shared__ double edge[kAMaxW][kAR];
+  const int rows = ny;                      // one pass: blockDim >= ny
+  const int nw = (rows + 63) >> 6;
+  const bool rowok = tid < rows;
+  const int yl = ny - 1 - tid;              // local row of reversed row tid
+  const int xo = rowok ? tid : (1 << 30);   // reversed column = s - xo
+  const int D = nx + ny - 2;
+  const int nsteps = nx + rows - 1;
+  const int tend = ((nsteps + (nw - 1) * kAL + kAL - 1) / kAL) * kAL;
+  const int s0 = -wave * kAL;               // this wave's step at time 0
+  double rb_s[kAL] = {}, rb_d[kAL] = {};
+  unsigned rb_i[kAL] = {};
+  auto load = [&](int t, int so) {          // row-0 storage index so of the step's diagonal
+    const unsigned i = (unsigned)(so + yl);
+    rb_i[t] = i;
+    rb_s[t] = buf_ld64(Sr, i * 8u);
+    rb_d[t] = buf_ld64(Dr, i * 8u);
+  };
+  double vp = 0.0;
+  for (int tb = -kAL; tb < tend; tb += kAL) {
+    const int sb = tb + s0;
+    double bl[kAL];
+    if (wave > 0) {
+#pragma unroll
+      for (int t2 = 0; t2 < kAL; ++t2) bl[t2] = edge[wave - 1][(sb - 1 + t2) & (kAR - 1)];
+    } else {
+#pragma unroll
+      for (int t2 = 0; t2 < kAL; ++t2) bl[t2] = 0.0;
+    }
+    int so[kAL];
+#pragma unroll
+    for (int t2 = 0; t2 < kAL; ++t2) so[t2] = DS[D - (sb + kAL + t2)];
+    double vv[kAL];
+#pragma unroll
+    for (int t2 = 0; t2 < kAL; ++t2) {
+      const int s = sb + t2;
+      const int xr = s - xo;
+      const bool act = (unsigned)xr < (unsigned)nx;
+      const double vN = shr1_fill(vp, bl[t2]);
+      const double inv = rcp64(rb_d[t2] + axy);
+      const double vn = fma(ax * inv, vp, fma(ay * inv, vN, rb_s[t2] * inv));
+      const double v = act ? vn : vp;
+      buf_store(v, Or, act ? rb_i[t2] * 8u : kNoCell);
+      vp = v;
+      vv[t2] = v;
+      load(t2, so[t2]);
+    }
+    if (lane == 63) {
+#pragma unroll
+      for (int t2 = 0; t2 < kAL; ++t2) edge[wave][(sb + t2) & (kAR - 1)] = vv[t2];
+    }
+    __syncthreads();
+  }
+}
+
 // lambda' = ihb - sigma_t rb - Div2^T rb + w sigma_s Sb / (4 pi) + M^T g.
 // In the ordinate's frame r_c = ... - ax (E_c - E_w) - ay (N_c - N_s) with
 // E_c = u_c + hx (cE (u_e - u_c) - cW (u_w - u_c)) the east face value; so
@@ -533,6 +614,8 @@ void adj_fill_args(const PlanDev &P, const AdjointBuffers &B, const double *gphi
   a.sig_t = P.sig_t; a.sig_s = P.sig_s;
   a.cE = P.cE; a.cW = P.cW; a.cN = P.cN; a.cS = P.cS;
   a.cellq = P.cellq;
+  a.sdq = P.sdq;
+  a.dso = P.dso;
   a.delta = P.delta; a.phi = P.phi; a.phih = P.phih;
   a.gphi = gphi; a.gFx = gFx; a.gFy = gFy;
   a.lam = B.lam; a.ihb = B.ihb; a.rb = B.rb;
@@ -560,7 +643,8 @@ void adj_launch_pass(const PlanDev &P, const AdjointBuffers &B, const void *args
   hipLaunchKernelGGL(k_a_ihalf, dim3(nb, 4), dim3(kB), 0, s, a);
   int rows = ((P.ny + 63) / 64) * 64;
   if (rows > 1024) rows = 1024;
-  hipLaunchKernelGGL(k_a_sweep, dim3(P.K), dim3(rows), 0, s, a);
+  if (P.ny <= kAMaxW * 64) hipLaunchKernelGGL(k_a_chain, dim3(P.K), dim3(rows), 0, s, a);
+  else hipLaunchKernelGGL(k_a_sweep, dim3(P.K), dim3(rows), 0, s, a);
   hipLaunchKernelGGL(k_a_qsum, dim3(nb, 4), dim3(kB), 0, s, a, (const double *)a.rb);
   hipLaunchKernelGGL(k_a_combine, dim3(nb), dim3(kB), 0, s, a, a.Sb, 1.0, 0);
   hipLaunchKernelGGL(k_a_out, dim3(nb, 4), dim3(kB), 0, s, a);
