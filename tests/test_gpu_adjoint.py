@@ -34,13 +34,13 @@ def _cot(N, seed):
     return rng.uniform(0, 1, N), rng.uniform(-1, 1, N), rng.uniform(-1, 1, N)
 
 
-def _gpu_adjoint(ctx, p, g, **kw):
+def _gpu_adjoint(ctx, p, g, adj_tol=1e-13, **kw):
     plan = gsis.Plan(ctx, p, tol=1e-13, max_iter=3000, synth_rtol=1e-13, synth_max_iter=200,
                      limiter=0, **kw)
     plan.iterate(3000)
     n, conv, err = plan.status()
     assert conv == 1
-    out = plan.adjoint(*g, tol=1e-13, max_iter=3000)
+    out = plan.adjoint(*g, tol=adj_tol, max_iter=3000)
     plan.close()
     return out
 
@@ -60,6 +60,23 @@ def test_adjoint_matches_oracle(ctx, kw, shape):
     assert _rel(ga, o["g_sigma_a"]) < 1e-9
     assert _rel(gs, o["g_sigma_s"]) < 1e-9
     assert _rel(gq, o["g_q"]) < 1e-9
+
+
+def test_adjoint_tall_strip_against_oracle(ctx):
+    """A 3 x 1100 strip: more than 1024 rows per ordinate, so the adjoint
+    sweep takes its two-pass form. The adjoint iteration of this strip
+    levels off near 1e-13, so both sides stop at 1e-12."""
+    p = inputs.random_problem(3, 1100, seed=4, sigma_range=(0.5, 5.0))
+    g = _cot(3 * 1100, 7)
+    _say("adjoint strip 3 x 1100")
+    ga, gs, gq, info = _gpu_adjoint(ctx, p, g, adj_tol=1e-12, method=1)
+    assert info["status"] == gsis.GSIS_OK
+    r = oracle.solve(p, tol=1e-14, max_iter=5000, limiter=0, return_I=True, method=1)
+    o = oracle.adjoint(p, r["I"], *g, tol=1e-12, max_iter=5000, limiter=0, method=1)
+    assert o["status"] == 0
+    assert _rel(ga, o["g_sigma_a"]) < 1e-8
+    assert _rel(gs, o["g_sigma_s"]) < 1e-8
+    assert _rel(gq, o["g_q"]) < 1e-8
 
 
 def test_adjoint_two_region_against_oracle(ctx):
