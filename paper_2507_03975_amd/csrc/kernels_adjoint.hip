@@ -196,7 +196,7 @@ __global__ void k_a_phbar(AArgs a, const double *kappa) {
 
 // Ih_bar = lambda + w (phb + mu hbx + eta hby) + the outflow-wall
 // reconstruction transposed (GSIS); lambda alone (SI).
-__global__ void k_a_ihalf(AArgs a) {
+__global__ void __launch_bounds__(kB) k_a_ihalf(AArgs a) {
   // one thread per stored cell of quadrant blockIdx.y, looping over the
   // quadrant's ordinates: the cell's cotangents, boundary terms and record
   // entries are loaded once for all of them
@@ -225,12 +225,12 @@ __global__ void k_a_ihalf(AArgs a) {
     if (yn) { bn = a.bfb[face_n(a, q, x)]; cn = so && y > 0 ? hy * Cq[6 * t + 3] : 0.0; }
     if (yn2) { bn2 = a.bfb[face_n(a, q, x)]; cn2 = Cq[6 * dg_idx(x, y + 1, a.nx, a.ny) + 3]; }
   }
-  for (int kk = a.qoff[q]; kk < a.qoff[q + 1]; ++kk) {
-    const size_t o = (size_t)kk * a.N + t;
-    double v = a.lam[o];
+  typedef const __attribute__((address_space(4))) double cdouble;
+  cdouble *W = (cdouble *)a.w, *WM = (cdouble *)a.wmu, *WE = (cdouble *)a.weta;
+  auto one = [&](int kk, double v) {
     if (gsis) {
-      v += a.w[kk] * phb + a.wmu[kk] * hxb + a.weta[kk] * hyb;
-      const double wmx = fabs(a.wmu[kk]), wmy = fabs(a.weta[kk]);
+      v += W[kk] * phb + WM[kk] * hxb + WE[kk] * hyb;
+      const double wmx = fabs(WM[kk]), wmy = fabs(WE[kk]);
       if (xe) {
         const double vb = be * wmx;
         v += vb * (1.0 + ce);
@@ -242,8 +242,20 @@ __global__ void k_a_ihalf(AArgs a) {
       }
       if (yn2) v -= bn2 * wmy * hy * cn2;
     }
-    a.ihb[o] = v;
+    a.ihb[(size_t)kk * a.N + t] = v;
+  };
+  // eight ordinates' lambda loaded before any ihb is stored
+  constexpr int U = 8;
+  int kk = a.qoff[q];
+  const int ke = a.qoff[q + 1];
+  for (; kk + U <= ke; kk += U) {
+    double l[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) l[u] = a.lam[(size_t)(kk + u) * a.N + t];
+#pragma unroll
+    for (int u = 0; u < U; ++u) one(kk + u, l[u]);
   }
+  for (; kk < ke; ++kk) one(kk, a.lam[(size_t)kk * a.N + t]);
 }
 
 // rb = H^-T ihb per ordinate: rb_c = (ihb_c + ax rb_east + ay rb_north) / d_c,
@@ -377,7 +389,7 @@ __global__ void __launch_bounds__(kAMaxW * 64) k_a_chain(AArgs a) {
 // In the ordinate's frame r_c = ... - ax (E_c - E_w) - ay (N_c - N_s) with
 // E_c = u_c + hx (cE (u_e - u_c) - cW (u_w - u_c)) the east face value; so
 // Ebar_c = -ax (rb_c - rb_e) and ubar_d collects Ebar of d, d-1, d+1.
-__global__ void k_a_out(AArgs a) {
+__global__ void __launch_bounds__(kB) k_a_out(AArgs a) {
   // one thread per stored cell of quadrant blockIdx.y, looping over the
   // quadrant's ordinates: the cell's record entries, neighbour positions and
   // cotangents are loaded once for all of them
@@ -402,13 +414,16 @@ __global__ void k_a_out(AArgs a) {
   const double sgs = a.sig_s[c], sbc = a.Sb[c];
   const double gp = a.gphi ? a.gphi[c] : 0.0, gx = a.gFx ? a.gFx[c] : 0.0;
   const double gy = a.gFy ? a.gFy[c] : 0.0;
-  for (int kk = a.qoff[q]; kk < a.qoff[q + 1]; ++kk) {
-    const double *R = a.rb + (size_t)kk * a.N;
-    const double ax = a.amu[kk], ay = a.aeta[kk];
-    const double r0 = R[t], rE = R[tE], rE2 = R[tE2], rW = R[tW];
-    const double rN = R[tN], rN2 = R[tN2], rS = R[tS];
-    const size_t o = (size_t)kk * a.N + t;
-    double v = a.ihb[o] - c4 * r0;
+  // ordinate weights through the constant address space (scalar loads)
+  typedef const __attribute__((address_space(4))) double cdouble;
+  cdouble *W = (cdouble *)a.w, *WM = (cdouble *)a.wmu, *WE = (cdouble *)a.weta;
+  cdouble *AM = (cdouble *)a.amu, *AE = (cdouble *)a.aeta;
+  // ordinate kk from its loaded values (rb at the cell and its neighbours,
+  // ihb at the cell)
+  auto one = [&](int kk, double r0, double rE, double rE2, double rW, double rN, double rN2,
+                 double rS, double ih) {
+    const double ax = AM[kk], ay = AE[kk];
+    double v = ih - c4 * r0;
     double ub = 0.0;
     {
       // Ebar at columns x, x - 1, x + 1 of row y; Nbar likewise
@@ -430,12 +445,33 @@ __global__ void k_a_out(AArgs a) {
       }
     }
     v += ub;
-    v += a.w[kk] * sgs * sbc * kInv4Pi;
+    v += W[kk] * sgs * sbc * kInv4Pi;
     double g = 0.0;
-    if (a.gphi) g += a.w[kk] * gp;
-    if (a.gFx) g += a.wmu[kk] * gx;
-    if (a.gFy) g += a.weta[kk] * gy;
-    a.lam[o] = v + g;
+    if (a.gphi) g += W[kk] * gp;
+    if (a.gFx) g += WM[kk] * gx;
+    if (a.gFy) g += WE[kk] * gy;
+    a.lam[(size_t)kk * a.N + t] = v + g;
+  };
+  // four ordinates at a time: every load before any store (the arrays do
+  // not overlap, which the compiler cannot see)
+  constexpr int U = 4;
+  int kk = a.qoff[q];
+  const int ke = a.qoff[q + 1];
+  for (; kk + U <= ke; kk += U) {
+    double r0[U], rE[U], rE2[U], rW[U], rN[U], rN2[U], rS[U], ih[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const double *R = a.rb + (size_t)(kk + u) * a.N;
+      r0[u] = R[t]; rE[u] = R[tE]; rE2[u] = R[tE2]; rW[u] = R[tW];
+      rN[u] = R[tN]; rN2[u] = R[tN2]; rS[u] = R[tS];
+      ih[u] = a.ihb[(size_t)(kk + u) * a.N + t];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) one(kk + u, r0[u], rE[u], rE2[u], rW[u], rN[u], rN2[u], rS[u], ih[u]);
+  }
+  for (; kk < ke; ++kk) {
+    const double *R = a.rb + (size_t)kk * a.N;
+    one(kk, R[t], R[tE], R[tE2], R[tW], R[tN], R[tN2], R[tS], a.ihb[(size_t)kk * a.N + t]);
   }
 }
 
