@@ -1,15 +1,17 @@
 // kernels_synth.hip -- macroscopic (synthetic) step of GSIS on gfx950.
 //
-//  hot_rhs : HoT_c = F_c + grad(phi)_c / (3 sigma_t) with the adaptive
+//  hot     : HoT_c = F_c + grad(phi)_c / (3 sigma_t) with the adaptive
 //            least-squares gradient (Eqs. GSIS_HoT, LSF_mdf); right-hand side
 //            b_c = V q - sum_int A 1/2 (HoT_c + HoT_nb).n
 //                  - sum_bnd A (F_T.n - kappa phi_half)        (Eqs. MSE_d, Fij_d,
-//                                                  macro_bc_delta_flux)
+//                                                  macro_bc_delta_flux),
+//            formed by the kernel that starts the CG
 //  solve   : D1 phi' = b, D1 = V sigma_a + sum_int A Gamma (.) + sum_bnd A kappa
 //            (Eqs. Gamma_ij_def, MSE_d_mtx1, elem_mtx_M, Gamma_ij_com2), by
-//            CG preconditioned with a geometric multigrid V-cycle
-//            (2x2 aggregation, Galerkin coarse operators, red-black
-//            Gauss-Seidel smoothing, dense inverse on the coarsest level).
+//            CG (one reduction per iteration, the Chronopoulos-Gear form)
+//            preconditioned with a geometric multigrid V-cycle (2x2
+//            aggregation, Galerkin coarse operators, red-black Gauss-Seidel
+//            smoothing, dense inverse on the coarsest level).
 //  update  : delta = phi' - phi_half (Eq. GSIS_update, applied lazily by the
 //            transport kernels), Err (Eq. Err_W), next source.
 //
