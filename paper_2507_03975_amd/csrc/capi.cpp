@@ -668,12 +668,20 @@ extern "C" gsis_status gsis_plan_iterate(gsis_plan *pl, int32_t n) {
       launch_hot(P.S, s);
     }
     if ((st = record(pl, 4))) return st;
-    if (P.method == GSIS_GSIS) launch_synth_solve(P.S, s, (int32_t *)pl->host_scal, true);
+    // the synthetic solve copies the device flags to the host once while it
+    // runs (host_flag[0]: the outer iteration's done flag); cleared first,
+    // so a nonzero value below was read during this iteration
+    int32_t *host_flag = (int32_t *)pl->host_scal;
+    host_flag[0] = 0;
+    if (P.method == GSIS_GSIS) launch_synth_solve(P.S, s, host_flag, true);
     if ((st = record(pl, 5))) return st;
     launch_update(P.S, s);
     if ((st = record(pl, 6))) return st;
     HIPCHK(ctx, hipGetLastError());
     if (pl->profile) pl->prof_iters++;
+    // an earlier iteration ended the solve (converged, diverged or at the
+    // iteration cap): the remaining ones would only launch kernels that exit
+    if (host_flag[0] != 0) break;
   }
   return GSIS_OK;
 }
