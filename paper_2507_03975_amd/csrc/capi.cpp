@@ -347,7 +347,7 @@ extern "C" gsis_status gsis_plan_create(gsis_ctx *ctx, const gsis_problem *p,
   gsis_status st = check_problem(ctx, p, o, mu, eta, w, sa, ss, q, bnd);
   if (st) return st;
   if (o->hot_face != GSIS_HOT_CENTRAL)
-    return fail(ctx, GSIS_E_UNSUPPORTED, "hot_face TRANSPORT is not available in this build");
+    return fail(ctx, GSIS_E_UNSUPPORTED, "hot_face TRANSPORT is not available on the GPU (oracle only)");
   HIPCHK(ctx, hipSetDevice(ctx->device));
 
   gsis_plan *pl = new gsis_plan;
