@@ -109,6 +109,27 @@ def test_batch_matches_single_plans(ctx):
     b.close()
 
 
+def test_batch_mixed_coarse_starts(ctx):
+    """Problems whose one-workgroup coarse cycle starts on level 0, 1, 2 and
+    3 (37 x 21, 90 x 130, 200 x 180, 400 x 300) in one batch: the CG update
+    runs in the per-cell kernel for the first and in the level-0 tile kernel
+    for the others, side by side in the same launches; each matches its
+    single plan."""
+    probs = [inputs.random_problem(37, 21, seed=2, sigma_range=(0.05, 50.0)),
+             inputs.random_problem(90, 130, seed=5, sigma_range=(0.5, 500.0)),
+             inputs.random_problem(200, 180, seed=6, sigma_range=(0.1, 50.0)),
+             inputs.random_problem(400, 300, seed=7, sigma_range=(0.1, 50.0))]
+    _say("batch of mixed coarse starts")
+    b = gsis.Batch(ctx, probs, tol=0.0, max_iter=3, synth_rtol=1e-13, synth_max_iter=300)
+    b.iterate(3)
+    for i, p in enumerate(probs):
+        g = b.read(i)
+        s = gsis.gsis_solve(ctx, p, tol=0.0, max_iter=3, synth_rtol=1e-13, synth_max_iter=300)
+        assert _rel(g["phi"], s["phi"]) < 1e-12, i
+        assert _rel(g["Fx"], s["Fx"]) < 1e-11, i
+    b.close()
+
+
 def test_batch_sweep_forms_agree(ctx, monkeypatch):
     """The batch's split transport step (residual items, then the
     persistent recurrence) and its fused persistent sweep give the same
