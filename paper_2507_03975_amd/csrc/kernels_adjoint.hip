@@ -533,7 +533,7 @@ __global__ void k_a_coef_q(AArgs a) {
 // Per cell: coefficient cotangents (all quadrants + the HoT gradient), their
 // distance cotangents dbar (cE = dE / (dE^2 + dW^2), cW = dW / (...)), and
 // every sigma_t term that involves this cell alone.
-__global__ void k_a_grad1(AArgs a, const double *kappa) {
+__global__ void k_a_grad1(AArgs a) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= a.N) return;
   int i, j;
@@ -694,7 +694,7 @@ void adj_launch_gradient(const PlanDev &P, const void *args, const double *ihalf
   a.Ih = ihalf;
   const int N = P.N, nb = nb_(N);
   hipLaunchKernelGGL(k_a_coef_q, dim3(nb, 4), dim3(kB), 0, s, a);
-  hipLaunchKernelGGL(k_a_grad1, dim3(nb), dim3(kB), 0, s, a, (const double *)P.kappa);
+  hipLaunchKernelGGL(k_a_grad1, dim3(nb), dim3(kB), 0, s, a);
   hipLaunchKernelGGL(k_a_grad2, dim3(nb), dim3(kB), 0, s, a, g_sa, g_ss, g_q);
 }
 

@@ -145,19 +145,6 @@ __device__ inline double rhs_at(CDesc &D, int c, int i, int j) {
   return s;
 }
 
-// ------------------------------------------------------- 5-point operator
-__device__ inline double apply5(int nx, int ny, const double *dg, const double *ax,
-                                const double *ay, const double *x, int c) {
-  int i, j;
-  cell_ij(c, nx, i, j);
-  double s = dg[c] * x[c];
-  if (i + 1 < nx) s -= ax[c] * x[c + 1];
-  if (i > 0) s -= ax[c - 1] * x[c - 1];
-  if (j + 1 < ny) s -= ay[c] * x[c + nx];
-  if (j > 0) s -= ay[c - nx] * x[c - nx];
-  return s;
-}
-
 // Scalar slots. r.z of CG iteration k sits in slot rz_slot(k) (two
 // alternating slots, so a kernel can read iteration k-1's value while its
 // block 0 stores iteration k's).
@@ -197,13 +184,9 @@ __device__ inline double *red_rrt(CDesc &D) { return D.red + 2 * nblk_d(D.N) + D
 __device__ inline double *red_zw(CDesc &D) { return D.red + 2 * nblk_d(D.N) + 2 * D.ntp; }
 __device__ inline int n_rz(CDesc &D) { return D.lc == 0 ? nblk_d(D.N) : D.ntile0; }
 
-__device__ inline double sum_partials(const double *p, int n, double *sh) {
-  double v = 0.0;
-  for (int t = threadIdx.x; t < n; t += blockDim.x) v += p[t];
-  return block_sum(v, sh);
-}
 // The thread's first partial, loaded early (before a kernel waits for its
-// flags), and the sum of all of them in the order of sum_partials.
+// flags), and the sum of all n partials: thread t adds p[t], p[t + blockDim],
+// ... in that order, then block_sum.
 __device__ inline double first_partial(const double *p, int n) {
   return (int)threadIdx.x < n ? p[threadIdx.x] : 0.0;
 }
@@ -635,7 +618,7 @@ __global__ void __launch_bounds__(kRedBlock) k_mg_down(const SynthDesc *ds, cons
 
 __global__ void __launch_bounds__(kRedBlock) k_mg_up(const SynthDesc *ds, const int2 *bt, int l,
                                                      int vc, double omega) {
-  __shared__ double sb[kRN], sd[kRN], sax[kRN], say[kRN], sx[kRN], sh[kRedBlock];
+  __shared__ double sb[kRN], sd[kRN], sax[kRN], say[kRN], sx[kRN];
   const Blk B = blk(bt);
   CDesc &D = cdesc(ds, B.p);
   const int32_t f1 = D.state[1], f3 = D.state[3];   // tested after the region loads
