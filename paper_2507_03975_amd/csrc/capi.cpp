@@ -498,6 +498,31 @@ extern "C" gsis_status gsis_plan_create(gsis_ctx *ctx, const gsis_problem *p,
     const char *e = getenv("GSIS_SWEEP_REFERENCE");
     P.sweep_impl = (e && (e[0] == '1' || e[0] == '2')) ? e[0] - '0' : 0;
   }
+  {
+    // workgroups per ordinate in the recurrence (GSIS_CHAIN_PARTS=1..4 sets
+    // it): a step costs a wave about the same whatever the rest of the chip
+    // does, but waves sharing a SIMD take turns, so parts of about 256 rows
+    // (one wave per SIMD); more parts while the ordinates fill fewer than
+    // half the CUs; at most 4, each a multiple of 64 rows and at most 1024,
+    // the top part not empty
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) !=
+        hipSuccess)
+      cus = 0;
+    int parts = std::min((ny + 255) / 256, 4);
+    while (parts < 4 && 2 * K * parts < cus) parts *= 2;
+    const char *e = getenv("GSIS_CHAIN_PARTS");
+    if (e && e[0] >= '1' && e[0] <= '4' && e[1] == 0) parts = e[0] - '0';
+    parts = std::max(1, std::min(parts, 4));
+    int rows = 0;
+    for (; parts > 1; --parts) {
+      rows = ((ny + parts - 1) / parts + 63) / 64 * 64;
+      if (rows <= 1024 && (parts - 1) * rows < ny) break;
+    }
+    if (P.sweep_impl != 0) parts = 1;
+    P.chain_parts = parts;
+    P.chain_rows = parts > 1 ? rows : 0;
+  }
 
   // -- boundary intensities in the internal ordinate order
   std::vector<double> bnd_int((size_t)P.nbf * K);
@@ -564,7 +589,10 @@ extern "C" gsis_status gsis_plan_create(gsis_ctx *ctx, const gsis_problem *p,
       (st = dalloc(pl, &P.rhs, N)) || (st = upload(pl, &P.bnd, bnd_int)) ||
       (st = dalloc(pl, &P.bflux, P.nbf)) || (st = upload(pl, &P.kappa, kap)) ||
       (st = dalloc(pl, &P.err_hist, o->max_iter)) ||
-      (st = dalloc(pl, &P.state, 4)) || (st = dalloc(pl, &P.last_err, 1)))
+      (st = dalloc(pl, &P.state, 5)) || (st = dalloc(pl, &P.last_err, 1)))
+    return bail(st);
+  if (P.chain_parts > 1 &&
+      (st = dalloc(pl, &P.hand, (size_t)K * (P.chain_parts - 1) * nx)))
     return bail(st);
   if (f32) {
     if ((st = dalloc(pl, &P.base, N))) return bail(st);
@@ -626,7 +654,8 @@ extern "C" gsis_status gsis_plan_reset(gsis_plan *pl) {
   if (f32)   // I^0 = Itilde + phi0/(4 pi)
     HIPCHK(ctx, hipMemcpyAsync(P.base, pl->phi0_host.data(), P.N * sizeof(double),
                                hipMemcpyHostToDevice, s));
-  HIPCHK(ctx, hipMemsetAsync(P.state, 0, 4 * sizeof(int32_t), s));
+  HIPCHK(ctx, hipMemsetAsync(P.state, 0, 5 * sizeof(int32_t), s));
+  launch_hand_reset(P, s);
   HIPCHK(ctx, hipMemsetAsync(P.err_hist, 0, P.max_iter * sizeof(double), s));
   launch_source(P.S, s);
   HIPCHK(ctx, hipGetLastError());
@@ -691,11 +720,15 @@ extern "C" gsis_status gsis_plan_status(gsis_plan *pl, int32_t *n_iter, int32_t 
   if (!pl) return GSIS_E_INVALID_ARG;
   gsis_ctx *ctx = pl->ctx;
   HIPCHK(ctx, hipSetDevice(ctx->device));
-  int32_t stv[4];
+  int32_t stv[5];
   double le = 0;
   HIPCHK(ctx, hipMemcpyAsync(stv, pl->P.state, sizeof stv, hipMemcpyDeviceToHost, pl->stream));
   HIPCHK(ctx, hipMemcpyAsync(&le, pl->P.last_err, sizeof le, hipMemcpyDeviceToHost, pl->stream));
   HIPCHK(ctx, hipStreamSynchronize(pl->stream));
+  if (stv[4] != 0)
+    return fail(ctx, GSIS_E_DEVICE,
+                "the recurrence's workgroups of one ordinate stopped waiting for each other; "
+                "reset the plan");
   if (n_iter) *n_iter = stv[0];
   if (converged) *converged = stv[1] == 1 ? 1 : (stv[1] == -1 ? -1 : 0);
   if (last_err) *last_err = le;

@@ -133,6 +133,10 @@ struct PlanDev {
   // rewritten after every update
   double *cellq = nullptr, *dynq = nullptr;
   double *rowbuf = nullptr;    // [K][3][nx] hand-off between sweep passes
+  unsigned long long *hand = nullptr;  // [K][chain_parts - 1][nx] row hand-over
+                               // between the workgroups of a split recurrence
+  int chain_parts = 1;         // workgroups per ordinate in the recurrence
+  int chain_rows = 0;          // rows per part (a multiple of 64, <= 1024)
   double *sdq = nullptr;       // [q][N] sigma_t + pseudo-time shift per stored cell
   int2 *rtiles = nullptr;      // residual-kernel tiles (first diagonal, first row)
   int *dso = nullptr;          // [kDiagPad + nx + ny - 1 + kDiagPad] storage index of
@@ -171,7 +175,8 @@ struct PlanDev {
   double *err_parts = nullptr; // block partials for Err
   int32_t *state = nullptr;    // [0] iterations done, [1] done flag (1 converged,
                                // -1 diverged, 2 max_iter), [2] current I buffer,
-                               // [3] synthetic CG converged
+                               // [3] synthetic CG converged, [4] a split
+                               // recurrence's hand-over timed out
   double *last_err = nullptr;
   SynthSet S;                  // launch set of this plan alone
   int lc = 0;                  // first level of the one-workgroup cycle
@@ -182,6 +187,9 @@ struct PlanDev {
 // increment solve (for the fused kernel the residual launch is empty).
 void launch_residual(const PlanDev &P, hipStream_t s);
 void launch_sweep(const PlanDev &P, hipStream_t s);
+// Puts every entry of the split recurrence's hand-over buffer in its empty
+// state (plan set-up and reset; the recurrence keeps it so between launches).
+void launch_hand_reset(const PlanDev &P, hipStream_t s);
 // Tiles of the residual kernel for an nx x ny grid: (first diagonal, first
 // row) of each band of rows x run of diagonals that holds a cell.
 std::vector<int2> residual_tiles(int nx, int ny);

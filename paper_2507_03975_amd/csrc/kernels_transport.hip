@@ -57,6 +57,9 @@ struct TArgs {
   int n_rtiles;
   const int *dso;    // row-0 storage index per diagonal, at offset kDiagPad
   const int32_t *state;
+  unsigned long long *hand;   // row hand-over between the parts of a split
+                              // recurrence, [K][parts - 1][nx]
+  int32_t *hand_err;          // set when a part gave up waiting for the one below
 };
 
 TArgs make_args(const PlanDev &P) {
@@ -77,6 +80,8 @@ TArgs make_args(const PlanDev &P) {
   a.phi = P.phi;
   a.sw = P.sw; a.swm = P.swm; a.swe = P.swe;
   a.state = P.state;
+  a.hand = P.hand;
+  a.hand_err = P.state + 4;
   return a;
 }
 
@@ -823,17 +828,36 @@ __global__ void __launch_bounds__(kRWaves * 64) k_resid_batch(const TArgs *targs
 // one barrier earlier; they pass through an LDS ring of 4 LAG steps and are
 // read once per LAG steps. With MULTI, rows beyond one pass are handed over
 // in rowbuf (alternate halves, so a pass never writes what it reads).
+//
+// SPLIT spreads the rows of one ordinate over np workgroups (part p takes
+// rows [p rows_pp, (p + 1) rows_pp)), so that an ordinate keeps two or more
+// CUs busy: the recurrence's rate per CU is set by the L2 requests one CU
+// keeps in flight. The top row of part p reaches part p + 1 through
+// hand[(kk (np - 1) + p) nx + x], written by its top lane with device-scope
+// stores (no fence: every entry is its own flag). An entry holds kHandEmpty
+// until it is written; wave 0 of part p + 1 polls the entries of its next
+// block of steps with device-scope loads, and puts kHandEmpty back once it has
+// read them, which leaves the buffer ready for the next launch. Part p + 1
+// has the higher workgroup index, so it is dispatched after part p and a
+// waiting part never holds back the part it waits for; a wait still ends after
+// kHandSpin polls, setting hand_err (the results are then not valid), and
+// that wave waits no more in this launch.
 constexpr int kCPF = 8;              // steps of loads in flight
 constexpr int kCLag = 8;
 constexpr int kCMaxW = 16;           // up to 1024 rows per pass
+constexpr unsigned long long kHandEmpty = 0x7ff4dead0000beefull;  // signalling NaN:
+                                     // no arithmetic result has this pattern
+constexpr int kHandSpin = 1 << 20;
 
 // Loads use the index dso[d] + y of the lane's row on the step's diagonal
 // d: for a lane with no cell it points at another diagonal or out of the
 // buffer (the hardware returns 0 there), and the value is never used.
-template <typename T, bool MULTI, class A>
-__device__ __forceinline__ void chain_ordinate(A &a, const int kk) {
+template <typename T, bool MULTI, bool SPLIT = false, class A>
+__device__ __forceinline__ void chain_ordinate(A &a, const int kk, const int part = 0,
+                                               const int np = 1) {
   constexpr int PF = kCPF, LAG = kCLag, R = 4 * kCLag;
   static_assert((R & (R - 1)) == 0 && LAG == PF, "ring sizes");
+  static_assert(!(SPLIT && MULTI), "a split recurrence runs one pass per part");
   static_assert(kCMaxW * kCLag + 2 * kCPF <= kDiagPad, "diagonal table padding");
   const int q = quadrant_of(a, kk);
   const int nx = a.nx, ny = a.ny, N = a.N;
@@ -850,7 +874,18 @@ __device__ __forceinline__ void chain_ordinate(A &a, const int kk) {
       (const __attribute__((address_space(4))) int *)(a.dso + kDiagPad);
   double *RB = a.rowbuf + (size_t)kk * 3 * nx;
   __shared__ double edge[kCMaxW][R];
-  for (int y0 = 0, pass = 0; y0 < ny; y0 += rows_pp, ++pass) {
+  // SPLIT: Hr the part below's top row (read), Hw this part's (written;
+  // an empty resource for the top part)
+  unsigned long long *Hr = nullptr;
+  __amdgpu_buffer_rsrc_t Hw = buf_rsrc(nullptr, 0);
+  if constexpr (SPLIT) {
+    unsigned long long *H = a.hand + (size_t)kk * (np - 1) * nx;
+    if (part > 0) Hr = H + (size_t)(part - 1) * nx;
+    if (part + 1 < np) Hw = buf_rsrc(H + (size_t)part * nx, (size_t)nx * 8);
+  }
+  const int ybeg = SPLIT ? part * rows_pp : 0;
+  const int yend = SPLIT ? min(ny, ybeg + rows_pp) : ny;
+  for (int y0 = ybeg, pass = 0; y0 < yend; y0 += rows_pp, ++pass) {
     const int rows = min(rows_pp, ny - y0);
     const int nw = (rows + 63) >> 6;
     const int y = y0 + tid;
@@ -883,14 +918,46 @@ __device__ __forceinline__ void chain_ordinate(A &a, const int kk) {
       }
     };
     double vp = 0.0;
+    // SPLIT, wave 0 of a part above the first: lane l < LAG holds the hand-over
+    // entry of column (block's first step) + l, loaded one block ahead; 0 for
+    // columns outside the grid
+    unsigned long long hv = 0;
+    bool gave_up = false;                     // a wait timed out: wait no more
+    const bool top_lane = SPLIT && tid == rows - 1;   // this part's top row
     for (int tb = -LAG; tb < tend; tb += LAG) {
       const int sb = tb + s0;                 // this wave's first step of the block
       // v below lane 0 for the block's steps: the wave below's top lane
-      // (written at least one barrier ago), the previous pass, or 0
+      // (written at least one barrier ago), the part below, the previous
+      // pass, or 0
       double bl[LAG];
       if (wave > 0) {
 #pragma unroll
         for (int t2 = 0; t2 < LAG; ++t2) bl[t2] = edge[wave - 1][(sb - 1 + t2) & (R - 1)];
+      } else if (SPLIT && part > 0) {
+        const int c = sb + lane;
+        const bool mine = lane < LAG && (unsigned)c < (unsigned)nx;
+        // (the test sits outside the polling loop: a wait at a loop header
+        // would cover every load in flight, this one only the entry's)
+        if (__ballot(hv == kHandEmpty) != 0 && !gave_up) {
+          for (int spin = 0;; ++spin) {   // the part below is behind
+            if (spin == kHandSpin) {
+              if (lane == 0) __hip_atomic_store(a.hand_err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              gave_up = true;
+              break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+            if (mine) hv = __hip_atomic_load(Hr + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (__ballot(hv == kHandEmpty) == 0) break;
+          }
+        }
+        const double hd = __builtin_bit_cast(double, hv);
+#pragma unroll
+        for (int t2 = 0; t2 < LAG; ++t2) bl[t2] = rdlane(hd, t2);
+        if (mine) __hip_atomic_store(Hr + c, kHandEmpty, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int cn = c + LAG;
+        hv = 0;
+        if (lane < LAG && (unsigned)cn < (unsigned)nx)
+          hv = __hip_atomic_load(Hr + cn, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       } else {
 #pragma unroll
         for (int t2 = 0; t2 < LAG; ++t2) bl[t2] = (MULTI && y0 > 0) ? rb_v[t2] : 0.0;
@@ -910,6 +977,11 @@ __device__ __forceinline__ void chain_ordinate(A &a, const int kk) {
         const double v = act ? vn : vp;
         buf_store((T)v, Ob, act ? rb_i[t2] * (unsigned)sizeof(T) : kNoCell);
         if constexpr (MULTI) buf_store(v, RBw, handoff && act ? (unsigned)x * 8u : kNoCell);
+        if constexpr (SPLIT) {
+          if (wave == nw - 1 && part + 1 < np)   // device scope (sc1): seen by the part above
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), Hw,
+                                                  top_lane && act ? (int)(x * 8) : (int)kNoCell, 0, 16);
+        }
         vp = v;
         vv[t2] = v;
         load(t2, so[t2], s + PF);
@@ -929,6 +1001,20 @@ template <typename T, bool MULTI>
 __global__ void __launch_bounds__(kCMaxW * 64) k_chain(TArgs a) {
   if (a.state[1] != 0) return;
   chain_ordinate<T, MULTI>(a, xcd_ordinate(blockIdx.x, a.K));
+}
+
+// Split recurrence: workgroup b is part b / K of ordinate b % K (the same XCD
+// for every part of an ordinate when K is a multiple of 8).
+template <typename T>
+__global__ void __launch_bounds__(kCMaxW * 64) k_chain_split(TArgs a, int np) {
+  if (a.state[1] != 0) return;
+  const int part = blockIdx.x / a.K;
+  chain_ordinate<T, false, true>(a, xcd_ordinate(blockIdx.x - part * a.K, a.K), part, np);
+}
+
+__global__ void k_fill_u64(unsigned long long *p, size_t n, unsigned long long v) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
 }
 
 // Batched recurrence: a persistent launch whose workgroups take work items
@@ -1169,6 +1255,12 @@ void launch_sweep(const PlanDev &P, hipStream_t s) {
     hipLaunchKernelGGL(k_sweep, dim3(P.K), dim3(rows), 0, s, a);
     return;
   }
+  if (P.chain_parts > 1) {
+    const dim3 g(P.chain_parts * P.K), b(P.chain_rows);
+    if (a.fp32) hipLaunchKernelGGL(k_chain_split<float>, g, b, 0, s, a, P.chain_parts);
+    else hipLaunchKernelGGL(k_chain_split<double>, g, b, 0, s, a, P.chain_parts);
+    return;
+  }
   if (a.fp32) {
     if (P.ny > rows) hipLaunchKernelGGL((k_chain<float, true>), dim3(P.K), dim3(rows), 0, s, a);
     else hipLaunchKernelGGL((k_chain<float, false>), dim3(P.K), dim3(rows), 0, s, a);
@@ -1201,6 +1293,13 @@ std::vector<int2> residual_tiles(int nx, int ny) {
 
 // ---- batched sweep
 size_t targs_bytes() { return sizeof(TArgs); }
+
+void launch_hand_reset(const PlanDev &P, hipStream_t s) {
+  if (P.chain_parts <= 1) return;
+  const size_t n = (size_t)P.K * (P.chain_parts - 1) * P.nx;
+  hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, P.hand, n,
+                     kHandEmpty);
+}
 void fill_targs(const PlanDev &P, void *dst) {
   const TArgs a = make_args(P);
   memcpy(dst, &a, sizeof a);

@@ -194,6 +194,35 @@ def test_sweep_forms_agree(ctx, shape, quad, monkeypatch):
             assert _rel(out["0"]["Fx"], out[other]["Fx"]) < 10 * tol, other
 
 
+@pytest.mark.parametrize("shape,quad,prec", [((256, 256), (4, 32), 0), ((256, 256), (4, 32), 1),
+                                             ((100, 130), (2, 8), 0), ((40, 1100), (2, 4), 0),
+                                             ((200, 65), (2, 4), 0)])
+def test_split_recurrence_bitwise(ctx, shape, quad, prec, monkeypatch):
+    """The wavefront recurrence with one ordinate's rows spread over several
+    workgroups (the top row handed to the part above through device memory)
+    gives the same bits as one workgroup per ordinate: every value is formed
+    from the same operands in the same order. Asked for 2, 3 and 4 parts the
+    shapes give 128/128 (twice) and 64 x 4 rows (256 rows); 128/2 and
+    64/64/2 (twice; 130 rows); 576/524, 384/384/332 and 320/320/320/140 rows
+    (1100 rows, more than one workgroup holds); and 64/1 rows (65 rows), as
+    well as the default choice."""
+    nx, ny = shape
+    p = inputs.random_problem(nx, ny, quad=inputs.quad_product(*quad), seed=61,
+                              sigma_range=(0.05, 50.0))
+    out = {}
+    for parts in ("1", "2", "3", "4", "default"):
+        if parts == "default":
+            monkeypatch.delenv("GSIS_CHAIN_PARTS", raising=False)
+        else:
+            monkeypatch.setenv("GSIS_CHAIN_PARTS", parts)
+        _say("split recurrence %s K=%d precision=%d parts=%s" % (shape, quad[0] * quad[1], prec, parts))
+        out[parts] = gsis.gsis_solve(ctx, p, tol=0.0, max_iter=3, precision=prec,
+                                     synth_rtol=1e-13, synth_max_iter=200)
+    for parts in ("2", "3", "4", "default"):
+        for f in ("phi", "Fx", "Fy"):
+            assert np.array_equal(np.asarray(out["1"][f]), np.asarray(out[parts][f])), (parts, f)
+
+
 @pytest.mark.parametrize("kw", [dict(method=0, limiter=1), dict(method=1, limiter=1),
                                 dict(method=1, limiter=0, hot_face=0)])
 def test_pseudo_time_iterates(ctx, kw):
