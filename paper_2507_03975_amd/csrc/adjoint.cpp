@@ -148,7 +148,13 @@ gsis_status gsis_plan_adjoint(gsis_plan *pl, const double *g_phi, const double *
   if (g_sigma_a) HIPCHK(ctx, hipMemcpyAsync(g_sigma_a, B.g_sa, N * sizeof(double), k, s));
   if (g_sigma_s) HIPCHK(ctx, hipMemcpyAsync(g_sigma_s, B.g_ss, N * sizeof(double), k, s));
   if (g_q) HIPCHK(ctx, hipMemcpyAsync(g_q, B.g_q, N * sizeof(double), k, s));
+  int32_t hand_err = 0;
+  HIPCHK(ctx, hipMemcpyAsync(&hand_err, P.state + 4, sizeof hand_err, hipMemcpyDeviceToHost, s));
   HIPCHK(ctx, hipStreamSynchronize(s));
+  if (hand_err != 0)
+    return fail(ctx, GSIS_E_DEVICE,
+                "the sweep's workgroups of one ordinate stopped waiting for each other; "
+                "reset the plan");
   if (info) {
     info->n_iter = m;
     info->final_err = err;

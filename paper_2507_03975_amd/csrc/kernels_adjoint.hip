@@ -54,6 +54,8 @@ struct AArgs {
   double *dbar;                                               // [4][N]
   double *stp;                                                // [N]
   double *errp;
+  unsigned long long *hand;                                   // split sweep hand-over
+  int32_t *hand_err;
 };
 
 __device__ inline int quadrant_of(const AArgs &a, int kk) {
@@ -316,10 +318,15 @@ __global__ void k_a_sweep(AArgs a) {
 // (ihb, sigma_t + shift) are loaded kAL steps ahead. Out-of-range indices
 // fall outside the buffer resources: their loads read 0, their stores are
 // dropped. rb = ihb / d + (ax / d) rb_east + (ay / d) rb_north.
+// SPLIT: as the forward recurrence, the reversed rows spread over np
+// workgroups (workgroup b is part b / K of ordinate b % K), the last reversed
+// row of a part handed to the next through the plan's hand-over buffer.
 constexpr int kAL = 8, kAR = 4 * kAL, kAMaxW = 16;
 static_assert(kAMaxW * kAL + 2 * kAL <= kDiagPad, "diagonal table padding");
-__global__ void __launch_bounds__(kAMaxW * 64) k_a_chain(AArgs a) {
-  const int kk = blockIdx.x;
+template <bool SPLIT>
+__global__ void __launch_bounds__(kAMaxW * 64) k_a_chain(AArgs a, int np) {
+  const int part = SPLIT ? blockIdx.x / a.K : 0;
+  const int kk = blockIdx.x - part * a.K;
   const int q = quadrant_of(a, kk);
   const int nx = a.nx, ny = a.ny, N = a.N;
   const int tid = threadIdx.x, lane = tid & 63;
@@ -331,11 +338,22 @@ __global__ void __launch_bounds__(kAMaxW * 64) k_a_chain(AArgs a) {
   const __attribute__((address_space(4))) int *DS =
       (const __attribute__((address_space(4))) int *)(a.dso + kDiagPad);
   __shared__ double edge[kAMaxW][kAR];
-  const int rows = ny;                      // one pass: blockDim >= ny
+  const int r0 = part * (int)blockDim.x;    // first reversed row of this part
+  const int rows = min((int)blockDim.x, ny - r0);   // one pass per part
   const int nw = (rows + 63) >> 6;
   const bool rowok = tid < rows;
-  const int yl = ny - 1 - tid;              // local row of reversed row tid
+  const int yl = ny - 1 - (r0 + tid);       // local row of reversed row r0 + tid
   const int xo = rowok ? tid : (1 << 30);   // reversed column = s - xo
+  unsigned long long *Hr = nullptr;
+  __amdgpu_buffer_rsrc_t Hw = buf_rsrc(nullptr, 0);
+  if (SPLIT) {
+    unsigned long long *H = a.hand + (size_t)kk * (np - 1) * nx;
+    if (part > 0) Hr = H + (size_t)(part - 1) * nx;
+    if (part + 1 < np) Hw = buf_rsrc(H + (size_t)part * nx, (size_t)nx * 8);
+  }
+  unsigned long long hv = 0;
+  bool gave_up = false;
+  const bool last_lane = SPLIT && tid == rows - 1;
   const int D = nx + ny - 2;
   const int nsteps = nx + rows - 1;
   const int tend = ((nsteps + (nw - 1) * kAL + kAL - 1) / kAL) * kAL;
@@ -355,13 +373,15 @@ __global__ void __launch_bounds__(kAMaxW * 64) k_a_chain(AArgs a) {
     if (wave > 0) {
 #pragma unroll
       for (int t2 = 0; t2 < kAL; ++t2) bl[t2] = edge[wave - 1][(sb - 1 + t2) & (kAR - 1)];
+    } else if (SPLIT && part > 0) {
+      hand_take<kAL>(Hr, nx, sb, hv, gave_up, a.hand_err, bl);
     } else {
 #pragma unroll
       for (int t2 = 0; t2 < kAL; ++t2) bl[t2] = 0.0;
     }
     int so[kAL];
 #pragma unroll
-    for (int t2 = 0; t2 < kAL; ++t2) so[t2] = DS[D - (sb + kAL + t2)];
+    for (int t2 = 0; t2 < kAL; ++t2) so[t2] = DS[D - (r0 + sb + kAL + t2)];
     double vv[kAL];
 #pragma unroll
     for (int t2 = 0; t2 < kAL; ++t2) {
@@ -373,6 +393,8 @@ __global__ void __launch_bounds__(kAMaxW * 64) k_a_chain(AArgs a) {
       const double vn = fma(ax * inv, vp, fma(ay * inv, vN, rb_s[t2] * inv));
       const double v = act ? vn : vp;
       buf_store(v, Or, act ? rb_i[t2] * 8u : kNoCell);
+      if (SPLIT && wave == nw - 1 && part + 1 < np)
+        hand_put(Hw, v, last_lane && act ? (unsigned)xr * 8u : kNoCell);
       vp = v;
       vv[t2] = v;
       load(t2, so[t2]);
@@ -657,6 +679,8 @@ void adj_fill_args(const PlanDev &P, const AdjointBuffers &B, const double *gphi
   a.lam = B.lam; a.ihb = B.ihb; a.rb = B.rb;
   a.s = B.s; a.s_old = B.s_old; a.bb = B.bb; a.hxb = B.hxb; a.hyb = B.hyb; a.phb = B.phb;
   a.Sb = B.Sb; a.bfb = B.bfb; a.part = B.part; a.dbar = B.dbar; a.stp = B.stp; a.errp = B.errp;
+  a.hand = P.hand;
+  a.hand_err = P.state + 4;
   memcpy(dst, &a, sizeof a);
 }
 
@@ -679,7 +703,11 @@ void adj_launch_pass(const PlanDev &P, const AdjointBuffers &B, const void *args
   hipLaunchKernelGGL(k_a_ihalf, dim3(nb, 4), dim3(kB), 0, s, a);
   int rows = ((P.ny + 63) / 64) * 64;
   if (rows > 1024) rows = 1024;
-  if (P.ny <= kAMaxW * 64) hipLaunchKernelGGL(k_a_chain, dim3(P.K), dim3(rows), 0, s, a);
+  if (P.chain_parts > 1)
+    hipLaunchKernelGGL(k_a_chain<true>, dim3(P.chain_parts * P.K), dim3(P.chain_rows), 0, s, a,
+                       P.chain_parts);
+  else if (P.ny <= kAMaxW * 64)
+    hipLaunchKernelGGL(k_a_chain<false>, dim3(P.K), dim3(rows), 0, s, a, 1);
   else hipLaunchKernelGGL(k_a_sweep, dim3(P.K), dim3(rows), 0, s, a);
   hipLaunchKernelGGL(k_a_qsum, dim3(nb, 4), dim3(kB), 0, s, a, (const double *)a.rb);
   hipLaunchKernelGGL(k_a_combine, dim3(nb), dim3(kB), 0, s, a, a.Sb, 1.0, 0);

@@ -830,24 +830,17 @@ __global__ void __launch_bounds__(kRWaves * 64) k_resid_batch(const TArgs *targs
 // in rowbuf (alternate halves, so a pass never writes what it reads).
 //
 // SPLIT spreads the rows of one ordinate over np workgroups (part p takes
-// rows [p rows_pp, (p + 1) rows_pp)), so that an ordinate keeps two or more
-// CUs busy: the recurrence's rate per CU is set by the L2 requests one CU
-// keeps in flight. The top row of part p reaches part p + 1 through
-// hand[(kk (np - 1) + p) nx + x], written by its top lane with device-scope
-// stores (no fence: every entry is its own flag). An entry holds kHandEmpty
-// until it is written; wave 0 of part p + 1 polls the entries of its next
-// block of steps with device-scope loads, and puts kHandEmpty back once it has
-// read them, which leaves the buffer ready for the next launch. Part p + 1
-// has the higher workgroup index, so it is dispatched after part p and a
-// waiting part never holds back the part it waits for; a wait still ends after
-// kHandSpin polls, setting hand_err (the results are then not valid), and
-// that wave waits no more in this launch.
+// rows [p rows_pp, (p + 1) rows_pp)): a wave's step costs about the same
+// whatever else runs, but waves that share a SIMD take turns, so parts of
+// about four waves keep one wave per SIMD. The top row of part p reaches
+// part p + 1 through hand[(kk (np - 1) + p) nx + x] (hand_take / hand_put).
+// Part p + 1 has the higher workgroup index, so it is dispatched after part
+// p and a waiting part never holds back the part it waits for; a wait still
+// ends after kHandSpin polls, setting hand_err (the results are then not
+// valid).
 constexpr int kCPF = 8;              // steps of loads in flight
 constexpr int kCLag = 8;
 constexpr int kCMaxW = 16;           // up to 1024 rows per pass
-constexpr unsigned long long kHandEmpty = 0x7ff4dead0000beefull;  // signalling NaN:
-                                     // no arithmetic result has this pattern
-constexpr int kHandSpin = 1 << 20;
 
 // Loads use the index dso[d] + y of the lane's row on the step's diagonal
 // d: for a lane with no cell it points at another diagonal or out of the
@@ -934,30 +927,7 @@ __device__ __forceinline__ void chain_ordinate(A &a, const int kk, const int par
 #pragma unroll
         for (int t2 = 0; t2 < LAG; ++t2) bl[t2] = edge[wave - 1][(sb - 1 + t2) & (R - 1)];
       } else if (SPLIT && part > 0) {
-        const int c = sb + lane;
-        const bool mine = lane < LAG && (unsigned)c < (unsigned)nx;
-        // (the test sits outside the polling loop: a wait at a loop header
-        // would cover every load in flight, this one only the entry's)
-        if (__ballot(hv == kHandEmpty) != 0 && !gave_up) {
-          for (int spin = 0;; ++spin) {   // the part below is behind
-            if (spin == kHandSpin) {
-              if (lane == 0) __hip_atomic_store(a.hand_err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-              gave_up = true;
-              break;
-            }
-            __builtin_amdgcn_s_sleep(2);
-            if (mine) hv = __hip_atomic_load(Hr + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (__ballot(hv == kHandEmpty) == 0) break;
-          }
-        }
-        const double hd = __builtin_bit_cast(double, hv);
-#pragma unroll
-        for (int t2 = 0; t2 < LAG; ++t2) bl[t2] = rdlane(hd, t2);
-        if (mine) __hip_atomic_store(Hr + c, kHandEmpty, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const int cn = c + LAG;
-        hv = 0;
-        if (lane < LAG && (unsigned)cn < (unsigned)nx)
-          hv = __hip_atomic_load(Hr + cn, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        hand_take<LAG>(Hr, nx, sb, hv, gave_up, a.hand_err, bl);   // lane 0's column is its step
       } else {
 #pragma unroll
         for (int t2 = 0; t2 < LAG; ++t2) bl[t2] = (MULTI && y0 > 0) ? rb_v[t2] : 0.0;
@@ -978,9 +948,8 @@ __device__ __forceinline__ void chain_ordinate(A &a, const int kk, const int par
         buf_store((T)v, Ob, act ? rb_i[t2] * (unsigned)sizeof(T) : kNoCell);
         if constexpr (MULTI) buf_store(v, RBw, handoff && act ? (unsigned)x * 8u : kNoCell);
         if constexpr (SPLIT) {
-          if (wave == nw - 1 && part + 1 < np)   // device scope (sc1): seen by the part above
-            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), Hw,
-                                                  top_lane && act ? (int)(x * 8) : (int)kNoCell, 0, 16);
+          if (wave == nw - 1 && part + 1 < np)
+            hand_put(Hw, v, top_lane && act ? (unsigned)x * 8u : kNoCell);
         }
         vp = v;
         vv[t2] = v;

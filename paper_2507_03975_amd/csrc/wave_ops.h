@@ -77,5 +77,52 @@ __device__ inline T buf_ldT(__amdgpu_buffer_rsrc_t r, unsigned i) {
   else return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)(i * 4u), 0, 0));
 }
 
+// Row hand-over between the workgroups of a split wavefront recurrence (one
+// ordinate's rows spread over parts): the producing part's top lane writes
+// its value of each column with a device-scope store; an entry holds
+// kHandEmpty until written, so every entry is its own ready flag and no fence
+// is needed. The consuming wave takes the entries of a block of LAG steps
+// (columns c0 .. c0 + LAG - 1), loaded one block ahead, polls while any is
+// still empty (at most kHandSpin polls, then sets *err and waits no more),
+// and puts kHandEmpty back, which leaves the buffer ready for the next launch.
+constexpr unsigned long long kHandEmpty = 0x7ff4dead0000beefull;  // a signalling
+                                     // NaN: no arithmetic result has this pattern
+constexpr int kHandSpin = 1 << 20;
+
+template <int LAG>
+__device__ __forceinline__ void hand_take(unsigned long long *Hr, int nx, int c0,
+                                          unsigned long long &hv, bool &gave_up, int32_t *err,
+                                          double (&bl)[LAG]) {
+  const int lane = threadIdx.x & 63;
+  const int c = c0 + lane;
+  const bool mine = lane < LAG && (unsigned)c < (unsigned)nx;
+  // (the test sits outside the polling loop: a wait at a loop header would
+  // cover every load in flight, this one only the entry's)
+  if (__ballot(hv == kHandEmpty) != 0 && !gave_up) {
+    for (int spin = 0;; ++spin) {   // the producing part is behind
+      if (spin == kHandSpin) {
+        if (lane == 0) __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        gave_up = true;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+      if (mine) hv = __hip_atomic_load(Hr + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (__ballot(hv == kHandEmpty) == 0) break;
+    }
+  }
+  const double hd = __builtin_bit_cast(double, hv);
+#pragma unroll
+  for (int t2 = 0; t2 < LAG; ++t2) bl[t2] = rdlane(hd, t2);
+  if (mine) __hip_atomic_store(Hr + c, kHandEmpty, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const int cn = c + LAG;
+  hv = 0;
+  if (lane < LAG && (unsigned)cn < (unsigned)nx)
+    hv = __hip_atomic_load(Hr + cn, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// the producing side: a device-scope (sc1) store, dropped at kNoCell
+__device__ inline void hand_put(__amdgpu_buffer_rsrc_t Hw, double v, unsigned off) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), Hw, (int)off, 0, 16);
+}
+
 }  // namespace
 }  // namespace gsis

@@ -62,13 +62,19 @@ def test_adjoint_matches_oracle(ctx, kw, shape):
     assert _rel(gq, o["g_q"]) < 1e-9
 
 
-def test_adjoint_tall_strip_against_oracle(ctx):
-    """A 3 x 1100 strip: more than 1024 rows per ordinate, so the adjoint
-    sweep takes its two-pass form. The adjoint iteration of this strip
-    levels off near 1e-13, so both sides stop at 1e-12."""
+@pytest.mark.parametrize("parts", ["1", None])
+def test_adjoint_tall_strip_against_oracle(ctx, parts, monkeypatch):
+    """A 3 x 1100 strip: more than 1024 rows per ordinate, so with one
+    workgroup per ordinate the adjoint sweep takes its two-pass form; by
+    default its rows are spread over four workgroups. The adjoint iteration
+    of this strip levels off near 1e-13, so both sides stop at 1e-12."""
+    if parts is None:
+        monkeypatch.delenv("GSIS_CHAIN_PARTS", raising=False)
+    else:
+        monkeypatch.setenv("GSIS_CHAIN_PARTS", parts)
     p = inputs.random_problem(3, 1100, seed=4, sigma_range=(0.5, 5.0))
     g = _cot(3 * 1100, 7)
-    _say("adjoint strip 3 x 1100")
+    _say("adjoint strip 3 x 1100 parts=%s" % parts)
     ga, gs, gq, info = _gpu_adjoint(ctx, p, g, adj_tol=1e-12, method=1)
     assert info["status"] == gsis.GSIS_OK
     r = oracle.solve(p, tol=1e-14, max_iter=5000, limiter=0, return_I=True, method=1)
@@ -163,3 +169,22 @@ def test_autograd_function(ctx):
     assert _rel(sa.grad, want_sa) < 1e-8
     assert _rel(ss.grad, o["g_sigma_s"]) < 1e-8
     assert _rel(q.grad, o["g_q"]) < 1e-8
+
+
+def test_adjoint_split_sweep_bitwise(ctx, monkeypatch):
+    """The downstream-first sweep with an ordinate's rows spread over 2, 3
+    or 4 workgroups gives the same gradients, bit for bit, as one workgroup
+    per ordinate (40 x 300 cells, 16 ordinates: 192/108, 128/128/44 and
+    128/128/44 rows, 4 parts falling back to 3)."""
+    p = inputs.random_problem(40, 300, quad=inputs.quad_product(2, 8), seed=9,
+                              sigma_range=(0.5, 5.0))
+    g = _cot(40 * 300, 3)
+    out = {}
+    for parts in ("1", "2", "3", "4"):
+        monkeypatch.setenv("GSIS_CHAIN_PARTS", parts)
+        _say("adjoint split sweep parts=%s" % parts)
+        out[parts] = _gpu_adjoint(ctx, p, g, adj_tol=1e-10, method=1)
+        assert out[parts][3]["status"] == gsis.GSIS_OK
+    for parts in ("2", "3", "4"):
+        for t in range(3):
+            assert np.array_equal(np.asarray(out["1"][t]), np.asarray(out[parts][t])), (parts, t)
