@@ -74,6 +74,46 @@ def cpu_baseline(prob, n_iter):
                           r["n_iter"], prob["nx"], prob["ny"], K, dt)}
 
 
+def measure_controls(ctx, gsis, pd, opts, N, K, args, phases, nprof, achieved, torch, dev):
+    """The transport step alone (residual + recurrence) as cell-ordinate
+    updates/s, the same steps with the limiter off (the residual's arithmetic
+    control), and a measured copy ceiling: a 1 GiB FP64 device copy, bytes
+    read + written per second."""
+    n = max(nprof, 1)
+    tr_ms = (phases["residual"] + phases["sweep"]) / n
+    res = {"transport": {"kernels": "residual + recurrence", "ms": tr_ms,
+                         "cell_ordinate_updates_per_s": N * K / (tr_ms / 1e3)}}
+    plan = gsis.Plan(ctx, pd, tol=0.0, max_iter=args.steps + args.warmup + 1, profile=1,
+                     **dict(opts, limiter=0))
+    plan.iterate(args.warmup)
+    torch.cuda.synchronize()
+    plan.reset()
+    plan.phase_times()
+    plan.iterate(args.steps)
+    torch.cuda.synchronize()
+    ph, m = plan.phase_times()
+    plan.close()
+    m = max(m, 1)
+    res["limiter_off"] = {"residual_ms": ph["residual"] / m, "sweep_ms": ph["sweep"] / m,
+                          "limiter_on_residual_ms": phases["residual"] / n}
+    x = torch.ones(128 << 20, dtype=torch.float64, device=dev)
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(10):
+        y.copy_(x)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    gbs = 2 * x.numel() * 8 * 10 / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del x, y
+    res["copy_ceiling"] = {"GB_per_s": gbs, "recurrence_frac_of_copy": achieved / gbs}
+    log("controls: %s" % res)
+    return res
+
+
 def kernel_traffic(phase):
     """Bytes per sweep launch from the PMC runs, if the kernel is unchanged."""
     if TRAFFIC.get(phase) is None:
@@ -328,6 +368,8 @@ def main():
                                    "si_over_gsis_time": s_sec / g["seconds"]}
 
     if not args.no_forms:
+        out["controls"] = measure_controls(ctx, gsis, pd, opts, N, K, args, phases, nprof,
+                                           achieved, torch, dev)
         out["forms"] = measure_forms(ctx, gsis, inputs, np, torch, dev)
 
     if not args.no_cpu_baseline:
