@@ -155,9 +155,10 @@ gsis_status gsis_plan_iterate(gsis_plan *plan, int32_t n);
 /* Wait for the plan's stream, then report progress: iterations done and
  * whether Err < tol was reached (converged = 1) or Err became non-finite
  * (converged = -1). Returns GSIS_E_DEVICE if the workgroups that share one
- * ordinate's wavefront recurrence (rows of more than 256 are spread over up
- * to 4 of them; GSIS_CHAIN_PARTS=1..4 in the environment at plan creation
- * fixes the count) stopped waiting for each other: the iterate is then not
+ * ordinate's wavefront recurrence (its rows are spread over up to 4 of them
+ * when ny > 256 or when the ordinates alone would fill under half the CUs;
+ * GSIS_CHAIN_PARTS=1..4 in the environment at plan creation fixes the
+ * count) stopped waiting for each other: the iterate is then not
  * valid until gsis_plan_reset. */
 gsis_status gsis_plan_status(gsis_plan *plan, int32_t *n_iter,
                              int32_t *converged, double *last_err);
