@@ -237,6 +237,36 @@ def measure_forms(ctx, gsis, inputs, np, torch, dev):
     return forms
 
 
+def paper_2d_table(ctx, gsis, inputs, np, torch, dev):
+    """The paper's 2D steady experiment (Sec. 5.2.1, Table table:2d_const):
+    uniform pure scatterer, hot bottom wall (1/(4 pi)), other walls
+    1e-6/(4 pi), 40x40 and 100x100 cells, Gauss-Legendre 36 x 48 with the
+    polar axis along x (1728 ordinates), Err < 1e-6, limiter off. GSIS and SI
+    iteration counts and GPU seconds (plan set-up excluded; synthetic CG to
+    relative residual 1e-8)."""
+    quad = inputs.quad_gl_product_full(36, 48)
+    rows = []
+    for n in (40, 100):
+        for st in (0.2, 1.0, 10.0, 20.0, 50.0, 100.0):
+            p = inputs.hot_wall_square(n, st, quad)
+            pd = {k: (torch.from_numpy(v).to(dev) if isinstance(v, np.ndarray) else v)
+                  for k, v in p.items()}
+            row = {"cells": "%dx%d" % (n, n), "sigma_t": st}
+            for name, method in (("gsis", gsis.GSIS_GSIS), ("si", gsis.GSIS_SI)):
+                pl = gsis.Plan(ctx, pd, method=method, tol=1e-6, max_iter=20000, limiter=0,
+                               synth_rtol=1e-8, synth_max_iter=200)
+                sec = _converge(pl, 20000, chunk=64)
+                it, conv, err = pl.status()
+                pl.close()
+                row[name] = {"iterations": int(it), "seconds": sec, "converged": bool(conv == 1)}
+            rows.append(row)
+            log("paper 2D %s sigma_t %g: GSIS %d its %.3f s, SI %d its %.3f s" % (
+                row["cells"], st, row["gsis"]["iterations"], row["gsis"]["seconds"],
+                row["si"]["iterations"], row["si"]["seconds"]))
+    return {"workload": "hot bottom wall, uniform pure scatterer, GL 36x48 (K = 1728), "
+                        "Err < 1e-6, limiter off", "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -248,6 +278,9 @@ def main():
     ap.add_argument("--si-cap", type=int, default=3000)
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the FP32-mixed, batched and adjoint measurements")
+    ap.add_argument("--paper-2d", action="store_true",
+                    help="only run the paper's 2D hot-wall table (GSIS and SI iteration "
+                         "counts and GPU seconds, 40x40 and 100x100, six opacities)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy five times (the known-size "
                          "kernel that scales the FETCH_SIZE / WRITE_SIZE counters)")
@@ -271,6 +304,10 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n, "copies": 5}))
+        return
+    if args.paper_2d:
+        print(json.dumps({"paper_2d": paper_2d_table(gsis.Context(0), gsis, inputs, np, torch,
+                                                     dev)}), flush=True)
         return
     prob = inputs.thick_square(256)
     N, K = prob["nx"] * prob["ny"], len(prob["mu"])

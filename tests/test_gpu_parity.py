@@ -223,6 +223,25 @@ def test_split_recurrence_bitwise(ctx, shape, quad, prec, monkeypatch):
             assert np.array_equal(np.asarray(out["1"][f]), np.asarray(out[parts][f])), (parts, f)
 
 
+@pytest.mark.parametrize("sigma_t", [1.0, 10.0])
+def test_hot_wall_against_oracle(ctx, sigma_t):
+    """The paper's 2D steady problem (Sec. 5.2.1): a pure scatterer
+    (sigma_a = 0 everywhere, so only the wall terms keep D1 definite) lit by
+    a hot bottom wall, 40 x 40 cells, 64 ordinates, limiter off. GSIS and SI
+    reach Err < 1e-8 in the oracle's number of iterations (to within one) at
+    the oracle's fixed point."""
+    p = inputs.hot_wall_square(40, sigma_t, inputs.quad_product(4, 16))
+    for method in (1, 0):
+        _say("hot wall sigma_t=%g method=%d" % (sigma_t, method))
+        g = gsis.gsis_solve(ctx, p, method=method, tol=1e-8, max_iter=3000, limiter=0,
+                            synth_rtol=1e-13, synth_max_iter=300)
+        o = oracle.solve(p, method=method, tol=1e-8, max_iter=3000, limiter=0)
+        assert g["status"] == 0 and o["status"] == 0
+        assert abs(g["n_iter"] - o["n_iter"]) <= 1, (g["n_iter"], o["n_iter"])
+        assert _rel(g["phi"], o["phi"]) < 1e-7
+        assert _rel(g["Fy"], o["Fy"]) < 1e-7
+
+
 @pytest.mark.parametrize("kw", [dict(method=0, limiter=1), dict(method=1, limiter=1),
                                 dict(method=1, limiter=0, hot_face=0)])
 def test_pseudo_time_iterates(ctx, kw):
