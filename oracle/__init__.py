@@ -40,7 +40,8 @@ class _Options(ctypes.Structure):
         ("limiter", ctypes.c_int), ("alsm", ctypes.c_int),
         ("hot_face", ctypes.c_int), ("tol", ctypes.c_double),
         ("max_iter", ctypes.c_int), ("cfl_p", ctypes.c_double),
-        ("beta", ctypes.c_double),
+        ("beta", ctypes.c_double), ("synth_form", ctypes.c_int),
+        ("synth_sub", ctypes.c_int),
     ]
 
 
@@ -78,6 +79,9 @@ def _load():
         lib.ora_synthetic_solve.argtypes = [P, _dp, _dp]
         lib.ora_synthetic_solve.restype = ctypes.c_int
         lib.ora_synthetic_apply.argtypes = [P, _dp, _dp]
+        lib.ora_wide_correction.argtypes = [P, ctypes.c_int, _dp, _dp]
+        lib.ora_synthetic_wide.argtypes = [P, ctypes.c_int, _dp, ctypes.c_int, _dp]
+        lib.ora_synthetic_wide.restype = ctypes.c_int
         lib.ora_adjoint.argtypes = [P, O, _dp, _dp, _dp, _dp, ctypes.c_double, ctypes.c_int,
                                     _dp, _dp, _dp, _dp, ip, _dp]
         lib.ora_adjoint.restype = ctypes.c_int
@@ -106,9 +110,10 @@ class _Marshal:
 
 
 def _opts(method=1, order=2, limiter=1, alsm=1, hot_face=0, tol=1e-8, max_iter=1000,
-          cfl_p=0.0, beta=0.0):
+          cfl_p=0.0, beta=0.0, synth_form=0, synth_sub=1):
     return _Options(int(method), int(order), int(limiter), int(alsm), int(hot_face),
-                    float(tol), int(max_iter), float(cfl_p), float(beta))
+                    float(tol), int(max_iter), float(cfl_p), float(beta), int(synth_form),
+                    int(synth_sub))
 
 
 def gradient(prob, U, alsm=1):
@@ -127,6 +132,26 @@ def bj_limiter(prob, U, gx, gy):
     psi = np.empty_like(U)
     _load().ora_bj_limiter(ctypes.byref(m.s), _ptr(U), _ptr(gx), _ptr(gy), _ptr(psi))
     return psi
+
+
+def wide_correction(prob, x, alsm=1):
+    """corr(x) of the face-averaged synthetic balance D1 x = b + corr(x)
+    (Eq. Fij_d against the compact Gamma flux)."""
+    m = _Marshal(prob)
+    x = np.ascontiguousarray(x, dtype=np.float64).ravel()
+    out = np.empty_like(x)
+    _load().ora_wide_correction(ctypes.byref(m.s), int(alsm), _ptr(x), _ptr(out))
+    return out
+
+
+def synthetic_wide(prob, b, x0, n_sub, alsm=1):
+    """n_sub defect-correction sub-iterations x <- D1^{-1} (b + corr(x))."""
+    m = _Marshal(prob)
+    b = np.ascontiguousarray(b, dtype=np.float64).ravel()
+    x = np.array(x0, dtype=np.float64).ravel()
+    st = _load().ora_synthetic_wide(ctypes.byref(m.s), int(alsm), _ptr(b), int(n_sub), _ptr(x))
+    assert st == 0, st
+    return x
 
 
 def face_coeffs(prob):

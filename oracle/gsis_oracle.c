@@ -495,6 +495,60 @@ int ora_synthetic_solve(const ora_problem *p, const double *b, double *x) {
 }
 
 /* ------------------------------------------------------------------------ */
+/* Face-averaged diffusive flux (Eq. Fij_d): the synthetic balance            */
+/*   V sig_a x + sum_int A [-(w_c + w_nb) . n / 2 + h_f]                       */
+/*             + sum_bnd A [F_T . n + kappa (x_c - phi_half_c)] = V q,         */
+/* w = grad(x) / (3 sig_t), is D1 x = b + corr(x) with the compact b; its     */
+/* defect correction D1 dx = R1(x) (Eqs. MSE_d1, Gamma_ij_def, MSE_d_mtx1)    */
+/* reads x^{s+1} = D1^{-1} (b + corr(x^s)).                                   */
+/* ------------------------------------------------------------------------ */
+void ora_wide_correction(const ora_problem *p, int alsm, const double *x, double *corr) {
+  const int nx = p->nx, ny = p->ny, N = nx * ny;
+  double *gx = malloc(sizeof(double) * N * 2), *gy = gx + N;
+  ora_gradient(p, alsm, x, gx, gy);
+  for (int c = 0; c < N; ++c) {
+    gx[c] /= 3.0 * sig_t(p, c);
+    gy[c] /= 3.0 * sig_t(p, c);
+  }
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      const int c = j * nx + i;
+      double s = 0.0;
+      for (int f = 0; f < 4; ++f) {
+        int nb = neighbour(p, i, j, f);
+        if (nb < 0) continue;
+        double wn = 0.5 * ((gx[c] + gx[nb]) * NX_[f] + (gy[c] + gy[nb]) * NY_[f]);
+        s += face_area(p, f) * (gamma_face(p, c, nb, f) * (x[c] - x[nb]) + wn);
+      }
+      corr[c] = s;
+    }
+  free(gx);
+}
+
+static int synth_wide_with(const ora_problem *p, const synth_factor *S, int alsm,
+                           const double *b, int n_sub, double *x) {
+  const int N = p->nx * p->ny;
+  double *bs = malloc(sizeof(double) * N * 2), *corr = bs + N;
+  int e = 0;
+  for (int s = 0; s < n_sub && e == 0; ++s) {
+    ora_wide_correction(p, alsm, x, corr);
+    for (int c = 0; c < N; ++c) bs[c] = b[c] + corr[c];
+    e = synth_solve_with(p, S, bs, x);
+  }
+  free(bs);
+  return e;
+}
+
+int ora_synthetic_wide(const ora_problem *p, int alsm, const double *b, int n_sub, double *x) {
+  synth_factor S;
+  int e = synth_factor_build(p, &S);
+  if (e) return e;
+  e = synth_wide_with(p, &S, alsm, b, n_sub, x);
+  synth_factor_free(&S);
+  return e;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Transport face fluxes F_T,f . n_f = sum_k w_k (Omega_k . n_f) I_f,k from   */
 /* an intensity field (boundary faces: the initial synthetic boundary flux,   */
 /* Sec. 4.4; interior faces: only for the transport-face variant).            */
@@ -648,7 +702,15 @@ static int iterate_ctx(ora_ctx *X, const double *I_in, double *I_out,
     e = synth_factor_build(p, &X->S);
     if (e == 0) X->have_S = 1;
   }
-  if (e == 0) e = synth_solve_with(p, &X->S, b, phi_out);
+  if (e == 0) {
+    if (o->synth_form == 1) {
+      /* sub-iterations from phi^{m+1/2} */
+      memcpy(phi_out, ph, sizeof(double) * N);
+      e = synth_wide_with(p, &X->S, o->alsm, b, o->synth_sub, phi_out);
+    } else {
+      e = synth_solve_with(p, &X->S, b, phi_out);
+    }
+  }
 
   /* GSIS correction I^{m+1} = I^{m+1/2} + (phi' - phi_half)/(4 pi)
    * (Eq. GSIS_update) */
@@ -694,6 +756,10 @@ int ora_solve(const ora_problem *p, const ora_options *o, const double *I0,
   if (!Ia || !Ib || !phi_old || !phi_new) return -3;
   if (I0) memcpy(Ia, I0, sizeof(double) * NK);
   else memset(Ia, 0, sizeof(double) * NK);
+  if (o->synth_form == 1 && (o->hot_face != 0 || o->synth_sub < 1)) {
+    free(Ia); free(Ib); free(phi_old); free(phi_new);
+    return -1;
+  }
 
   ora_ctx X = {p, o, {0, 0, NULL, 0}, 0};
   int status = 1, m = 0;
@@ -1065,7 +1131,8 @@ int ora_adjoint(const ora_problem *p, const ora_options *o, const double *I_star
                 const double *g_phi, const double *g_Fx, const double *g_Fy, double tol,
                 int max_iter, double *g_sa, double *g_ss, double *g_q, double *lam_out,
                 int *n_iter, double *err_hist) {
-  if (o->limiter || o->hot_face != 0 || o->cfl_p != 0 || o->beta != 0) return -4;
+  if (o->limiter || o->hot_face != 0 || o->cfl_p != 0 || o->beta != 0 || o->synth_form != 0)
+    return -4;
   const int N = p->nx * p->ny, K = p->K;
   const size_t NK = (size_t)N * K;
   const double V = p->dx * p->dy;

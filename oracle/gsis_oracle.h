@@ -40,6 +40,13 @@ typedef struct {
   int max_iter;
   double cfl_p;   /* global pseudo-time number (Eq. cfl_pse); 0 = off */
   double beta;    /* local pseudo-time parameter (Eq. tau_pse); 0 = off */
+  int synth_form; /* 0 = compact diffusion flux Gamma (x_c - x_nb) in the
+                     synthetic balance; 1 = the face average of the cells'
+                     diffusive fluxes (Eq. Fij_d), reached by synth_sub
+                     defect-correction sub-iterations with the compact
+                     matrix D1 (Eqs. MSE_d1, Gamma_ij_def, MSE_d_mtx1) from
+                     phi^{m+1/2}; central HoT faces only */
+  int synth_sub;  /* sub-iterations of synth_form 1 (>= 1) */
 } ora_options;
 
 /* ALSM / LSQ cell gradient of a cell field U[nx*ny] (Sec. 5, Eqs. LSF,
@@ -91,6 +98,18 @@ int ora_synthetic_solve(const ora_problem *p, const double *b, double *x);
 
 /* Apply D1 (for tests). */
 void ora_synthetic_apply(const ora_problem *p, const double *x, double *y);
+
+/* The synthetic balance with the face-averaged diffusive flux of Eq. Fij_d
+ * differs from the compact one (D1 x = b) on interior faces only:
+ *   D1 x = b + corr(x),  corr_c = sum over interior faces f of c of
+ *   A_f [Gamma_f (x_c - x_nb) + (w_c + w_nb) . n_f / 2],
+ * w = grad(x) / (3 sigma_t) with the ALSM (alsm = 1) or LSQ gradient. */
+void ora_wide_correction(const ora_problem *p, int alsm, const double *x, double *corr);
+
+/* n_sub sub-iterations x <- D1^{-1} (b + corr(x)) from the given x, each an
+ * exact solve: the defect correction D1 dx = R1(x) of Eqs. MSE_d1 and
+ * MSE_d_mtx1, R1 the residual of the face-averaged balance. */
+int ora_synthetic_wide(const ora_problem *p, int alsm, const double *b, int n_sub, double *x);
 
 /* Adjoint of the fixed point I* of the iteration (limiter off, central HoT
  * faces, no pseudo time; method SI or GSIS): lambda = G^T lambda + M^T g for

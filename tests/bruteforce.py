@@ -164,7 +164,8 @@ def increment(p, r):
     return dI
 
 
-def iterate(p, I, method=1, order=2, lim=True, alsm=True, hot_face=0):
+def iterate(p, I, method=1, order=2, lim=True, alsm=True, hot_face=0, synth_form=0,
+            synth_sub=1):
     nx, ny, dx, dy = p["nx"], p["ny"], p["dx"], p["dy"]
     N, K = nx * ny, len(p["mu"])
     V = dx * dy
@@ -202,5 +203,28 @@ def iterate(p, I, method=1, order=2, lim=True, alsm=True, hot_face=0):
         kap = 2.0 / (3.0 * st[c] * (dx if nxx else dy)) + 0.25
         D[c, c] += A * kap
         b[c] -= A * (FTb[t] - kap * ph[c])
-    phn = np.linalg.solve(D, b)
+    if synth_form == 0:
+        phn = np.linalg.solve(D, b)
+    else:
+        # the balance with the face average of the cells' diffusive fluxes
+        # -(grad x / (3 sigma_t)) . n (Eq. Fij_d), assembled densely from the
+        # least-squares gradient of every unit vector, then synth_sub
+        # defect-correction steps D dx = b - Aw x from x = phi^{m+1/2}
+        Gx, Gy = np.zeros((N, N)), np.zeros((N, N))
+        for k in range(N):
+            e = np.zeros(N)
+            e[k] = 1.0
+            g = gradient(p, e, alsm)
+            Gx[:, k] = g[:, 0] / (3 * st)
+            Gy[:, k] = g[:, 1] / (3 * st)
+        Aw = np.diag(V * p["sigma_a"].astype(float))
+        for c, nb, nxx, nyy, A in interior:
+            row = -0.5 * ((Gx[c] + Gx[nb]) * nxx + (Gy[c] + Gy[nb]) * nyy)
+            Aw[c] += A * row
+            Aw[nb] -= A * row
+        for c, nxx, nyy, A, bb in boundary:
+            Aw[c, c] += A * (2.0 / (3.0 * st[c] * (dx if nxx else dy)) + 0.25)
+        phn = ph.copy()
+        for _ in range(synth_sub):
+            phn = phn + np.linalg.solve(D, b - Aw @ phn)
     return Ih + ((phn - ph) / (4 * math.pi))[:, None], phn

@@ -336,7 +336,11 @@ def test_limiter_cases():
 @pytest.mark.parametrize("kw", [dict(method=1, order=2, limiter=1, alsm=1, hot_face=0),
                                 dict(method=1, order=2, limiter=0, alsm=0, hot_face=1),
                                 dict(method=0, order=1, limiter=0, alsm=1, hot_face=0),
-                                dict(method=1, order=1, limiter=0, alsm=1, hot_face=0)])
+                                dict(method=1, order=1, limiter=0, alsm=1, hot_face=0),
+                                dict(method=1, order=2, limiter=0, alsm=1, hot_face=0,
+                                     synth_form=1, synth_sub=3),
+                                dict(method=1, order=2, limiter=1, alsm=0, hot_face=0,
+                                     synth_form=1, synth_sub=1)])
 def test_bruteforce_iteration(n, seed, kw):
     p = inputs.random_problem(n, n + 1, seed=seed)
     rng = np.random.Generator(np.random.PCG64(seed + 100))
@@ -349,9 +353,77 @@ def test_bruteforce_iteration(n, seed, kw):
     np.testing.assert_allclose(d_o, d_b, rtol=1e-12, atol=1e-14)
     I_o, ph_o = oracle.iterate(p, I, **kw)
     I_b, ph_b = bruteforce.iterate(p, I, kw["method"], kw["order"], kw["limiter"], kw["alsm"],
-                                   kw["hot_face"])
+                                   kw["hot_face"], kw.get("synth_form", 0),
+                                   kw.get("synth_sub", 1))
     np.testing.assert_allclose(I_o, I_b, rtol=1e-11, atol=1e-13)
     np.testing.assert_allclose(ph_o, ph_b, rtol=1e-11, atol=1e-13)
+
+
+# ------------------------- face-averaged synthetic flux (Eq. Fij_d), sub-iterations
+@pytest.mark.parametrize("alsm", [1, 0])
+def test_wide_correction_vanishes_on_linear_fields(alsm):
+    """In a uniform medium the least-squares gradient of a linear field is
+    exact in every cell (one-sided at the walls), so the face average of the
+    cells' diffusive fluxes equals the compact Gamma flux: corr = 0."""
+    p = inputs.homogeneous(7, 6, inputs.quad_s4(), sigma_t=3.0, c=0.6, q=1.0)
+    p["dx"], p["dy"] = 0.13, 0.29
+    X = np.array([(i + 0.5) * 0.13 for j in range(6) for i in range(7)])
+    Y = np.array([(j + 0.5) * 0.29 for j in range(6) for i in range(7)])
+    x = 1.7 - 2.3 * X + 0.9 * Y
+    corr = oracle.wide_correction(p, x, alsm=alsm)
+    scale = np.abs(oracle.synthetic_apply(p, x)).max()
+    assert np.abs(corr).max() < 1e-13 * scale
+    # and not for a curved field: the odd-even part is what differs
+    assert np.abs(oracle.wide_correction(p, X * X, alsm=alsm)).max() > 1e-6 * scale
+
+
+@pytest.mark.parametrize("alsm", [1, 0])
+def test_wide_subiterations_reach_dense_solution(alsm):
+    """On a 4 x 3 grid with jumping sigma: the face-averaged balance
+    assembled densely from the independent least-squares gradient (Aw), the
+    oracle's sub-iterations x <- x + D1^{-1} (b - Aw x) contract (spectral
+    radius < 1 here) and reach Aw^{-1} b; one sub-iteration from x0 matches
+    its dense formula."""
+    p = inputs.random_problem(4, 3, seed=17, sigma_range=(0.3, 30.0))
+    N = 12
+    D1 = np.stack([oracle.synthetic_apply(p, np.eye(N)[k]) for k in range(N)], 1)
+    corr = np.stack([oracle.wide_correction(p, np.eye(N)[k], alsm=alsm) for k in range(N)], 1)
+    # the same operator from the independent gradient: Aw = D1 - corr
+    st = p["sigma_a"] + p["sigma_s"]
+    V = p["dx"] * p["dy"]
+    G = np.stack([bruteforce.gradient(p, np.eye(N)[k], alsm) for k in range(N)], 2)
+    W = G / (3 * st)[:, None, None]
+    interior, boundary = bruteforce._faces(4, 3, p["dx"], p["dy"])
+    Aw = np.diag(V * p["sigma_a"])
+    for c, nb, nxx, nyy, A in interior:
+        row = -0.5 * ((W[c, 0] + W[nb, 0]) * nxx + (W[c, 1] + W[nb, 1]) * nyy)
+        Aw[c] += A * row
+        Aw[nb] -= A * row
+    for c, nxx, nyy, A, bb in boundary:
+        Aw[c, c] += A * (2.0 / (3.0 * st[c] * (p["dx"] if nxx else p["dy"])) + 0.25)
+    np.testing.assert_allclose(D1 - corr, Aw, rtol=1e-12, atol=1e-12 * np.abs(Aw).max())
+    rho = np.abs(np.linalg.eigvals(np.linalg.solve(D1, D1 - Aw))).max()
+    assert rho < 1.0
+    rng = np.random.Generator(np.random.PCG64(5))
+    b, x0 = rng.uniform(-1, 1, N), rng.uniform(-1, 1, N)
+    x1 = oracle.synthetic_wide(p, b, x0, 1, alsm=alsm)
+    np.testing.assert_allclose(x1, x0 + np.linalg.solve(D1, b - Aw @ x0), rtol=1e-11, atol=1e-13)
+    n_sub = int(math.ceil(math.log(1e-14) / math.log(rho))) + 5
+    xs = oracle.synthetic_wide(p, b, x0, n_sub, alsm=alsm)
+    np.testing.assert_allclose(xs, np.linalg.solve(Aw, b), rtol=1e-10, atol=1e-12)
+
+
+def test_wide_form_infinite_medium_and_rejections():
+    """The face-averaged synthetic flux keeps the infinite-medium solution
+    (P1) and is refused with transport-face HoT and with no sub-iteration."""
+    p = inputs.homogeneous(6, 5, inputs.quad_s4(), sigma_t=2.0, c=0.7, q=3.0)
+    sa = p["sigma_a"][0]
+    p["bnd_in"] = np.full((2 * (6 + 5), 12), 3.0 / (FOURPI * sa))
+    r = oracle.solve(p, tol=1e-14, max_iter=400, limiter=0, synth_form=1, synth_sub=2)
+    assert r["status"] == 0
+    np.testing.assert_allclose(r["phi"], 3.0 / sa, rtol=1e-12)
+    assert oracle.solve(p, max_iter=3, synth_form=1, synth_sub=2, hot_face=1)["status"] < 0
+    assert oracle.solve(p, max_iter=3, synth_form=1, synth_sub=0)["status"] < 0
 
 
 @pytest.mark.parametrize("method,hot", [(0, 0), (1, 0), (1, 1)])
