@@ -234,6 +234,26 @@ def measure_forms(ctx, gsis, inputs, np, torch, dev):
         "forward": {"iterations": int(n), "seconds": fsec},
         "adjoint": {"iterations": info["n_iter"], "seconds": asec},
         "adjoint_over_forward_time": asec / fsec}
+    # face-averaged synthetic flux (Eq. Fij_d) by sub-iterations against the
+    # compact flux, on the headline workload
+    pc = dv(inputs.thick_square(256))
+    base = dict(method=gsis.GSIS_GSIS, limiter=1, tol=1e-6, max_iter=500, synth_rtol=3e-3,
+                synth_max_iter=50)
+    res = {}
+    for name, extra in (("compact", {}), ("face_average_sub2", dict(synth_form=1, synth_sub=2)),
+                        ("face_average_sub4", dict(synth_form=1, synth_sub=4))):
+        pl = gsis.Plan(ctx, pc, **dict(base, **extra))
+        sec = _converge(pl, 500)
+        n, conv, err = pl.status()
+        res[name] = dict(iterations=int(n), seconds=sec, converged=bool(conv == 1),
+                         phi=pl.read()["phi"])
+        pl.close()
+        log("synthetic flux %s: %d iterations, %.4f s" % (name, n, sec))
+    ref = res["compact"]["phi"]
+    forms["synthetic_flux"] = {
+        "workload": "thick square 256x256x128 as the timed steps, GSIS to Err < 1e-6",
+        **{k: {**{a: b for a, b in v.items() if a != "phi"},
+               "phi_rel_diff_vs_compact": _rel(v["phi"], ref)} for k, v in res.items()}}
     return forms
 
 

@@ -127,6 +127,19 @@ typedef struct {
   int32_t graph;         /* batches only: 1 (default) captures one outer
                             iteration in a hipGraph at gsis_batch_create and
                             replays it; 0 enqueues kernels one by one */
+  int32_t synth_form;    /* synthetic balance (GSIS): 0 (default) takes the
+                            compact diffusion flux Gamma_f (phi_c - phi_nb)
+                            on interior faces; 1 takes the face average of
+                            the cells' diffusive fluxes, -(grad phi_c /
+                            (3 sigma_t,c) + grad phi_nb / (3 sigma_t,nb)) .
+                            n / 2 (Eq. Fij_d), reached by synth_sub
+                            defect-correction sub-iterations with the
+                            compact matrix (Eqs. MSE_d1, Gamma_ij_def,
+                            MSE_d_mtx1) from phi^{m+1/2}, each a CG +
+                            multigrid solve. Single plans only (a batch
+                            returns GSIS_E_UNSUPPORTED), not with the
+                            adjoint, and with central HoT faces */
+  int32_t synth_sub;     /* sub-iterations for synth_form 1 (>= 1); default 4 */
 } gsis_options;
 
 /* Fill *o with the defaults listed above. */

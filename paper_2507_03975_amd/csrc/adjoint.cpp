@@ -83,9 +83,11 @@ gsis_status gsis_plan_adjoint(gsis_plan *pl, const double *g_phi, const double *
   if (!pl) return GSIS_E_INVALID_ARG;
   gsis_ctx *ctx = pl->ctx;
   PlanDev &P = pl->P;
-  if (P.limiter || P.precision != GSIS_FP64 || P.hot_face != GSIS_HOT_CENTRAL || pl->pseudo)
+  if (P.limiter || P.precision != GSIS_FP64 || P.hot_face != GSIS_HOT_CENTRAL || pl->pseudo ||
+      P.synth_form != 0)
     return fail(ctx, GSIS_E_UNSUPPORTED,
-                "the adjoint needs limiter = 0, FP64, central HoT faces and no pseudo time");
+                "the adjoint needs limiter = 0, FP64, central HoT faces, no pseudo time and "
+                "the compact synthetic flux");
   if (max_iter < 1) return fail(ctx, GSIS_E_INVALID_ARG, "max_iter must be >= 1");
   if (!(tol >= 0)) return fail(ctx, GSIS_E_INVALID_ARG, "tol must be >= 0");
   HIPCHK(ctx, hipSetDevice(ctx->device));

@@ -298,7 +298,7 @@ void enqueue_iteration(gsis_batch *b, bool capture) {
   if (b->method == GSIS_GSIS) {
     launch_boundary_flux_batch(b->targs, b->bt_face, b->nb_face, s);
     launch_hot(b->S, s);
-    launch_synth_solve(b->S, s, nullptr, true);
+    launch_synth_solve(b->S, s, nullptr, 1);
   }
   launch_update(b->S, s);
 }
@@ -347,6 +347,8 @@ gsis_status gsis_batch_create(gsis_ctx *ctx, int32_t n, const gsis_problem *p,
   if (n < 1) return fail(ctx, GSIS_E_INVALID_ARG, "n must be >= 1 (got %d)", n);
   if (!p || !o) return fail(ctx, GSIS_E_INVALID_ARG, "problems or options is NULL");
   if (o->I0) return fail(ctx, GSIS_E_INVALID_ARG, "options.I0 must be NULL for a batch");
+  if (o->synth_form != 0)
+    return fail(ctx, GSIS_E_UNSUPPORTED, "options.synth_form 1 is available for single plans only");
   HIPCHK(ctx, hipSetDevice(ctx->device));
   gsis_batch *b = new gsis_batch;
   b->ctx = ctx;

@@ -62,6 +62,8 @@ gsis_status gsis_options_default(gsis_options *o) {
   o->cfl_p = 0.0;
   o->beta = 0.0;
   o->graph = 1;
+  o->synth_form = 0;
+  o->synth_sub = 4;
   return GSIS_OK;
 }
 
@@ -118,6 +120,10 @@ gsis_status check_problem(gsis_ctx *ctx, const gsis_problem *p, const gsis_optio
     return fail(ctx, GSIS_E_INVALID_ARG, "options.cfl_p must be finite and >= 0");
   if (!(o->beta >= 0) || !std::isfinite(o->beta))
     return fail(ctx, GSIS_E_INVALID_ARG, "options.beta must be finite and >= 0");
+  if (o->synth_form != 0 && o->synth_form != 1)
+    return fail(ctx, GSIS_E_INVALID_ARG, "options.synth_form must be 0 or 1");
+  if (o->synth_form == 1 && o->synth_sub < 1)
+    return fail(ctx, GSIS_E_INVALID_ARG, "options.synth_sub must be >= 1");
   const int dev = o->device_ptrs;
   const size_t N = (size_t)p->nx * p->ny, K = p->K;
   gsis_status st;
@@ -284,6 +290,9 @@ gsis_status setup_synth(gsis_plan *pl, PlanDev &P, std::vector<HostLevel> &hl) {
       (st = dalloc(pl, &P.cg_s1, N)) || (st = dalloc(pl, &P.cg_w, N)) ||
       (st = dalloc(pl, &P.scal, 16)))
     return st;
+  if (P.synth_form == 1 &&
+      ((st = dalloc(pl, &P.wide_wx, N)) || (st = dalloc(pl, &P.wide_wy, N))))
+    return st;
   // block partials: r.r and b.b (one per 256 cells each), then r.z, the
   // r.r of the level-0 tile kernel and z.Az (one per level-0 multigrid tile
   // each)
@@ -364,6 +373,8 @@ extern "C" gsis_status gsis_plan_create(gsis_ctx *ctx, const gsis_problem *p,
   P.limiter = o->limiter ? 1 : 0; P.alsm = o->alsm ? 1 : 0; P.hot_face = o->hot_face;
   P.tol = o->tol; P.max_iter = o->max_iter; P.synth_rtol = o->synth_rtol;
   P.synth_max_iter = o->synth_max_iter;
+  P.synth_form = o->method == GSIS_GSIS ? o->synth_form : 0;
+  P.synth_sub = o->synth_sub;
   auto bail = [&](gsis_status s) {
     gsis_plan_destroy(pl);
     return s;
@@ -702,7 +713,16 @@ extern "C" gsis_status gsis_plan_iterate(gsis_plan *pl, int32_t n) {
     // so a nonzero value below was read during this iteration
     int32_t *host_flag = (int32_t *)pl->host_scal;
     host_flag[0] = 0;
-    if (P.method == GSIS_GSIS) launch_synth_solve(P.S, s, host_flag, true);
+    if (P.method == GSIS_GSIS && P.synth_form == 1) {
+      // face-averaged balance: sub-iterations from phi^{m+1/2}
+      for (int sub = 0; sub < P.synth_sub; ++sub) {
+        launch_wide_grad(P.S, s, sub == 0);
+        launch_synth_solve(P.S, s, host_flag, 2);
+        if (host_flag[0] != 0) break;
+      }
+    } else if (P.method == GSIS_GSIS) {
+      launch_synth_solve(P.S, s, host_flag, 1);
+    }
     if ((st = record(pl, 5))) return st;
     launch_update(P.S, s);
     if ((st = record(pl, 6))) return st;

@@ -83,6 +83,7 @@ struct SynthDesc {
   // CG vectors: r alternates between cg_r and cg_r2 with the V-cycle count,
   // s = A p between cg_s0 and cg_s1 with the iteration; z = M r, w = A z
   double *cg_r, *cg_r2, *cg_z, *cg_p, *cg_s0, *cg_s1, *cg_w;
+  double *wx, *wy;              // face-averaged balance: grad(x) / (3 sigma_t)
   double *red, *scal, *err_parts, *err_hist, *last_err;
   int32_t *state;
   int nlev, lc;                 // levels; first level of the one-workgroup cycle
@@ -167,6 +168,10 @@ struct PlanDev {
   int coarse_n = 0;
   double *cg_r = nullptr, *cg_r2 = nullptr, *cg_z = nullptr, *cg_p = nullptr;
   double *cg_s0 = nullptr, *cg_s1 = nullptr, *cg_w = nullptr;
+  // synthetic balance: 0 compact Gamma flux; 1 face average of the cells'
+  // diffusive fluxes (Eq. Fij_d) by synth_sub defect-correction solves
+  int synth_form = 0, synth_sub = 1;
+  double *wide_wx = nullptr, *wide_wy = nullptr;
   double *red = nullptr;       // block partial sums
   double *scal = nullptr;      // device scalars (see kernels_synth.hip)
   int red_blocks = 0;
@@ -240,11 +245,17 @@ int source_tiles_of(int nx, int ny);   // 16 x 16 tiles of the source kernel
 void prepare_synth(size_t coarse_lds);      // kernel attribute for the LDS size
 void launch_source(const SynthSet &S, hipStream_t s);          // src from phi
 void launch_hot(const SynthSet &S, hipStream_t s);               // HoT of every cell
+// grad(x) / (3 sigma_t) of the level-0 iterate for the face-averaged
+// balance; first: x = phi^{m+1/2}, copied into the iterate
+void launch_wide_grad(const SynthSet &S, hipStream_t s, bool first);
 // host_flag: pinned int32[3] for the host's stop checks (single problem);
 // NULL never waits and enqueues exactly S.synth_max_iter iterations.
-// rhs_from_hot: the first kernel forms the right-hand side from the HoT
-// (forward solve); otherwise it reads the descriptor's rhs (adjoint).
-void launch_synth_solve(const SynthSet &S, hipStream_t s, int32_t *host_flag, bool rhs_from_hot);
+// rhs_mode 1: the first kernel forms the right-hand side from the HoT
+// (forward solve), warm start phi; 2: the same plus the face-averaged
+// balance's correction at the level-0 iterate, which is the warm start (one
+// defect-correction sub-iteration, after launch_wide_grad); 0: it reads the
+// descriptor's rhs (adjoint).
+void launch_synth_solve(const SynthSet &S, hipStream_t s, int32_t *host_flag, int rhs_mode);
 void launch_update(const SynthSet &S, hipStream_t s);
 void launch_apply_delta_final(const PlanDev &P, hipStream_t s, double swmu, double sweta,
                               double *Fx_out, double *Fy_out);

@@ -696,7 +696,7 @@ void adj_launch_pass(const PlanDev &P, const AdjointBuffers &B, const void *args
   hipLaunchKernelGGL(k_a_combine, dim3(nb), dim3(kB), 0, s, a, a.s, kInv4Pi, hist ? 1 : 0);
   if (hist) hipLaunchKernelGGL(k_a_err, dim3(1), dim3(kB), 0, s, a, nb, hist, m);
   if (P.method == GSIS_GSIS) {
-    launch_synth_solve(S, s, host_flag, false);
+    launch_synth_solve(S, s, host_flag, 0);
     hipLaunchKernelGGL(k_a_hbar, dim3(nb), dim3(kB), 0, s, a);
     hipLaunchKernelGGL(k_a_phbar, dim3(nb), dim3(kB), 0, s, a, (const double *)P.kappa);
   }

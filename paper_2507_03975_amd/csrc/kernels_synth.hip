@@ -257,7 +257,14 @@ __global__ void k_finish_rr(const SynthDesc *ds) {
 // r = b - A x; partials of r.r and b.b.
 // RHS: the right-hand side b is formed here from the HoT (and stored)
 // rather than read.
-template <bool RHS>
+// MODE 0: b given in rhs (the adjoint), warm start phi; 1: b from the HoT
+// (rhs_at), warm start phi; 2: the face-averaged balance (Eq. Fij_d) by a
+// defect-correction sub-iteration: b = rhs_at + corr(x) with x the level-0
+// iterate, which is also the warm start, and corr_c = sum over interior
+// faces of a_f (x_c - x_nb) + A_f (w_c + w_nb) . n_f / 2, a_f = A_f Gamma_f
+// the operator's off-diagonals and w = grad(x) / (3 sigma_t) from
+// k_wide_grad: then D1 x' = b is D1 (x' - x) = R1(x).
+template <int MODE>
 __global__ void k_cg_begin(const SynthDesc *ds, const int2 *bt) {
   __shared__ double sh[kRedBlock];
   const Blk B = blk(bt);
@@ -270,13 +277,24 @@ __global__ void k_cg_begin(const SynthDesc *ds, const int2 *bt) {
   int i, j;
   cell_ij(cc, L.nx, i, j);
   const bool hE = i + 1 < L.nx, hW = i > 0, hN = j + 1 < L.ny, hS = j > 0;
-  // x = phi for the cell and its neighbours (this kernel writes x)
-  const double *X = D.phi;
+  // warm start x for the cell and its neighbours (this kernel writes x)
+  const double *X = MODE == 2 ? L.x : D.phi;
   const double xc = X[cc], xe = X[hE ? cc + 1 : cc], xw = X[hW ? cc - 1 : cc];
   const double xn = X[hN ? cc + L.nx : cc], xs = X[hS ? cc - L.nx : cc];
   const double dg = L.dg[cc], aE = L.ax[cc], aW = L.ax[hW ? cc - 1 : cc];
   const double aN = L.ay[cc], aS = L.ay[hS ? cc - L.nx : cc];
-  const double b = RHS ? rhs_at(D, cc, i, j) : D.rhs[cc];
+  double b = MODE != 0 ? rhs_at(D, cc, i, j) : D.rhs[cc];
+  if (MODE == 2) {
+    const double *WX = D.wx, *WY = D.wy;
+    const double wxc = WX[cc], wyc = WY[cc];
+    const double hdy = 0.5 * D.dy, hdx = 0.5 * D.dx;
+    double corr = 0.0;
+    if (hE) corr += aE * (xc - xe) + hdy * (wxc + WX[cc + 1]);
+    if (hW) corr += aW * (xc - xw) - hdy * (wxc + WX[cc - 1]);
+    if (hN) corr += aN * (xc - xn) + hdx * (wyc + WY[cc + L.nx]);
+    if (hS) corr += aS * (xc - xs) - hdx * (wyc + WY[cc - L.nx]);
+    b += corr;
+  }
   if (f1 != 0) return;
   double rr = 0.0, bb = 0.0;
   if (in) {
@@ -286,7 +304,7 @@ __global__ void k_cg_begin(const SynthDesc *ds, const int2 *bt) {
     if (hN) y -= aN * xn;
     if (hS) y -= aS * xs;
     const double rc = b - y;
-    if (RHS) D.rhs[c] = b;
+    if (MODE != 0) D.rhs[c] = b;
     L.x[c] = xc;
     D.cg_r[c] = rc;
     rr = rc * rc;
@@ -297,6 +315,33 @@ __global__ void k_cg_begin(const SynthDesc *ds, const int2 *bt) {
   if (threadIdx.x == 0) red_rr(D)[B.lb] = t;
   t = block_sum(bb, sh);
   if (threadIdx.x == 0) red_bb(D)[B.lb] = t;
+}
+
+// w = grad(x) / (3 sigma_t) of the level-0 iterate (the HoT's gradient
+// coefficients), for the face-averaged balance; FIRST: x = phi^{m+1/2},
+// also copied into the iterate (the sub-iterations start there).
+template <bool FIRST>
+__global__ void k_wide_grad(const SynthDesc *ds, const int2 *bt) {
+  const Blk B = blk(bt);
+  CDesc &D = cdesc(ds, B.p);
+  const int32_t f1 = D.state[1];   // tested after the operands are loaded
+  const int nx = D.nx, ny = D.ny;
+  const int c = B.lb * kRedBlock + threadIdx.x;
+  if (c >= D.N) return;
+  int i, j;
+  cell_ij(c, nx, i, j);
+  const LevelDev L = level(D, 0);
+  const double *X = FIRST ? D.phih : L.x;
+  const double u = X[c];
+  const double ue = i + 1 < nx ? X[c + 1] : u, uw = i > 0 ? X[c - 1] : u;
+  const double un = j + 1 < ny ? X[c + nx] : u, us = j > 0 ? X[c - nx] : u;
+  const double gx = D.cE[c] * (ue - u) - D.cW[c] * (uw - u);
+  const double gy = D.cN[c] * (un - u) - D.cS[c] * (us - u);
+  const double s3 = 3.0 * D.sig_t[c];
+  if (f1 != 0) return;
+  D.wx[c] = gx / s3;
+  D.wy[c] = gy / s3;
+  if (FIRST) L.x[c] = u;
 }
 
 // CG in the form of Chronopoulos and Gear: the V-cycle of iteration it
@@ -1340,6 +1385,7 @@ SynthDesc make_synth_desc(const PlanDev &P) {
   D.src = P.src; D.dynq = P.dynq;
   D.cg_r = P.cg_r; D.cg_r2 = P.cg_r2; D.cg_z = P.cg_z; D.cg_p = P.cg_p;
   D.cg_s0 = P.cg_s0; D.cg_s1 = P.cg_s1; D.cg_w = P.cg_w;
+  D.wx = P.wide_wx; D.wy = P.wide_wy;
   D.red = P.red; D.scal = P.scal; D.err_parts = P.err_parts; D.err_hist = P.err_hist;
   D.last_err = P.last_err; D.state = P.state;
   D.nlev = (int)P.mg.size();
@@ -1380,6 +1426,13 @@ void launch_source(const SynthSet &S, hipStream_t s) {
   hipLaunchKernelGGL(k_source, dim3(S.nb_src), dim3(kRedBlock), 0, s, S.desc, S.bt_src);
 }
 
+void launch_wide_grad(const SynthSet &S, hipStream_t s, bool first) {
+  if (first)
+    hipLaunchKernelGGL(k_wide_grad<true>, dim3(S.nb_cell), dim3(kRedBlock), 0, s, S.desc, S.bt_cell);
+  else
+    hipLaunchKernelGGL(k_wide_grad<false>, dim3(S.nb_cell), dim3(kRedBlock), 0, s, S.desc, S.bt_cell);
+}
+
 void launch_hot(const SynthSet &S, hipStream_t s) {
   hipLaunchKernelGGL(k_hot, dim3(S.nb_cell), dim3(kRedBlock), 0, s, S.desc, S.bt_cell);
 }
@@ -1399,11 +1452,12 @@ void launch_hot(const SynthSet &S, hipStream_t s) {
 // run waits once per solve. Without it (batches, graph capture) exactly
 // synth_max_iter iterations are launched and converged problems skip their
 // kernels.
-void launch_synth_solve(const SynthSet &S, hipStream_t s, int32_t *host_flag, bool rhs_from_hot) {
+void launch_synth_solve(const SynthSet &S, hipStream_t s, int32_t *host_flag, int rhs_mode) {
   const SynthDesc *ds = S.desc;
   const dim3 gc(S.nb_cell), bk(kRedBlock);
-  if (rhs_from_hot) hipLaunchKernelGGL(k_cg_begin<true>, gc, bk, 0, s, ds, S.bt_cell);
-  else hipLaunchKernelGGL(k_cg_begin<false>, gc, bk, 0, s, ds, S.bt_cell);
+  if (rhs_mode == 1) hipLaunchKernelGGL(k_cg_begin<1>, gc, bk, 0, s, ds, S.bt_cell);
+  else if (rhs_mode == 2) hipLaunchKernelGGL(k_cg_begin<2>, gc, bk, 0, s, ds, S.bt_cell);
+  else hipLaunchKernelGGL(k_cg_begin<0>, gc, bk, 0, s, ds, S.bt_cell);
   vcycle(S, 0, s);
   const int guess = host_flag ? host_flag[8] : 0;
   for (int it = 0; it < S.synth_max_iter; ++it) {

@@ -51,7 +51,8 @@ class gsis_options(ctypes.Structure):
                 ("I0", ctypes.c_void_p), ("stream", ctypes.c_void_p),
                 ("device_ptrs", ctypes.c_int32), ("profile", ctypes.c_int32),
                 ("cfl_p", ctypes.c_double), ("beta", ctypes.c_double),
-                ("graph", ctypes.c_int32)]
+                ("graph", ctypes.c_int32), ("synth_form", ctypes.c_int32),
+                ("synth_sub", ctypes.c_int32)]
 
 
 class gsis_batch_tuning(ctypes.Structure):
@@ -213,13 +214,15 @@ class _Args:
 
 def make_options(method=GSIS_GSIS, precision=GSIS_FP64, order=2, limiter=1, alsm=1,
                  hot_face=GSIS_HOT_CENTRAL, tol=1e-6, max_iter=1000, synth_rtol=1e-4,
-                 synth_max_iter=50, profile=0, cfl_p=0.0, beta=0.0, graph=1):
+                 synth_max_iter=50, profile=0, cfl_p=0.0, beta=0.0, graph=1, synth_form=0,
+                 synth_sub=4):
     o = gsis_options()
     load().gsis_options_default(ctypes.byref(o))
     o.method, o.precision, o.order, o.limiter = int(method), int(precision), int(order), int(limiter)
     o.alsm, o.hot_face, o.tol, o.max_iter = int(alsm), int(hot_face), float(tol), int(max_iter)
     o.synth_rtol, o.synth_max_iter, o.profile = float(synth_rtol), int(synth_max_iter), int(profile)
     o.cfl_p, o.beta, o.graph = float(cfl_p), float(beta), int(graph)
+    o.synth_form, o.synth_sub = int(synth_form), int(synth_sub)
     return o
 
 

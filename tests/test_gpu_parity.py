@@ -223,6 +223,56 @@ def test_split_recurrence_bitwise(ctx, shape, quad, prec, monkeypatch):
             assert np.array_equal(np.asarray(out["1"][f]), np.asarray(out[parts][f])), (parts, f)
 
 
+@pytest.mark.parametrize("kw", [dict(synth_sub=1, limiter=0), dict(synth_sub=3, limiter=1),
+                                dict(synth_sub=2, limiter=0, alsm=0)])
+@pytest.mark.parametrize("shape", [(37, 29), (70, 67)])
+def test_wide_synthetic_iterates(ctx, kw, shape):
+    """The synthetic balance with the face average of the cells' diffusive
+    fluxes (Eq. Fij_d), reached by defect-correction sub-iterations with the
+    compact matrix, each a CG + multigrid solve on the GPU: iterates at
+    fixed m match the oracle's exact sub-iterations."""
+    p = inputs.random_problem(shape[0], shape[1], seed=41, sigma_range=(0.05, 50.0))
+    g, o = _fixed_m(ctx, p, 3, method=1, synth_form=1, **kw)
+    assert _rel(g["phi"], o["phi"]) < 1e-11
+    assert _rel(g["Fx"], o["Fx"]) < 1e-10 and _rel(g["Fy"], o["Fy"]) < 1e-10
+
+
+def test_wide_synthetic_fixed_point(ctx):
+    """GSIS with the face-averaged synthetic flux converges (4
+    sub-iterations, limiter off) to the oracle's fixed point, in its number
+    of outer iterations to within one."""
+    p = inputs.random_problem(24, 20, seed=43, sigma_range=(0.5, 5.0))
+    kw = dict(method=1, limiter=0, synth_form=1, synth_sub=4)
+    g = gsis.gsis_solve(ctx, p, tol=1e-10, max_iter=500, synth_rtol=1e-14,
+                        synth_max_iter=200, **kw)
+    o = oracle.solve(p, tol=1e-10, max_iter=500, **kw)
+    assert g["status"] == 0 and o["status"] == 0
+    assert abs(g["n_iter"] - o["n_iter"]) <= 1, (g["n_iter"], o["n_iter"])
+    assert _rel(g["phi"], o["phi"]) < 1e-8
+
+
+def test_wide_synthetic_rejections(ctx):
+    """synth_form 1 needs at least one sub-iteration and a single plan, and
+    the adjoint refuses it."""
+    p = inputs.random_problem(6, 5, seed=2)
+    with pytest.raises(gsis.GSISError) as e:
+        gsis.gsis_solve(ctx, p, synth_form=1, synth_sub=0)
+    assert e.value.status == gsis.GSIS_E_INVALID_ARG
+    with pytest.raises(gsis.GSISError) as e:
+        gsis.gsis_solve(ctx, p, synth_form=2)
+    assert e.value.status == gsis.GSIS_E_INVALID_ARG
+    with pytest.raises(gsis.GSISError) as e:
+        gsis.Batch(ctx, [p, p], synth_form=1)
+    assert e.value.status == gsis.GSIS_E_UNSUPPORTED
+    plan = gsis.Plan(ctx, p, tol=1e-10, max_iter=500, limiter=0, synth_form=1)
+    plan.iterate(500)
+    assert plan.status()[1] == 1
+    with pytest.raises(gsis.GSISError) as e:
+        plan.adjoint(np.ones(30))
+    assert e.value.status == gsis.GSIS_E_UNSUPPORTED
+    plan.close()
+
+
 @pytest.mark.parametrize("sigma_t", [1.0, 10.0])
 def test_hot_wall_against_oracle(ctx, sigma_t):
     """The paper's 2D steady problem (Sec. 5.2.1): a pure scatterer
