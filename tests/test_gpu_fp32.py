@@ -34,7 +34,8 @@ def _rel(a, b):
 
 
 @pytest.mark.parametrize("kw", [dict(method=0, limiter=1), dict(method=1, limiter=1),
-                                dict(method=1, limiter=0, beta=3.0)])
+                                dict(method=1, limiter=0, beta=3.0),
+                                dict(method=1, limiter=1, synth_form=1, synth_sub=2)])
 def test_fp32_iterates(ctx, kw):
     """At fixed m the only difference is the FP32 rounding of the stored
     deviation, about 6e-8 of |I - phi/(4 pi)| per iteration."""
