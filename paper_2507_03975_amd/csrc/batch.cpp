@@ -297,7 +297,7 @@ void enqueue_iteration(gsis_batch *b, bool capture) {
   launch_moments_batch(b->targs, b->S.bt_cell, b->S.nb_cell, b->fp32, s);
   if (b->method == GSIS_GSIS) {
     launch_boundary_flux_batch(b->targs, b->bt_face, b->nb_face, s);
-    launch_hot(b->S, s);
+    launch_hot(b->S, s, false);
     launch_synth_solve(b->S, s, nullptr, 1);
   }
   launch_update(b->S, s);

@@ -705,7 +705,7 @@ extern "C" gsis_status gsis_plan_iterate(gsis_plan *pl, int32_t n) {
     launch_moments(P, s, P.method == GSIS_GSIS);
     if ((st = record(pl, 3))) return st;
     if (P.method == GSIS_GSIS) {
-      launch_hot(P.S, s);
+      launch_hot(P.S, s, true);
     }
     if ((st = record(pl, 4))) return st;
     // the synthetic solve copies the device flags to the host once while it

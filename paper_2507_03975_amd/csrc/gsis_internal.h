@@ -78,7 +78,10 @@ struct SynthDesc {
   int method, fp32, max_iter;
   double tol, rtol;
   const double *sig_t, *sig_s, *q, *cE, *cW, *cN, *cS, *kappa;
-  const double *phih, *Fx, *Fy, *bflux;
+  double *phih, *Fx, *Fy;       // moments of I^{m+1/2} (k_hot<true> writes them)
+  const double *bflux;
+  const double *mom_part;       // [4][3][N] per-quadrant partial moments
+  double sw, swm, swe;          // sums of w, w mu, w eta (FP32-mixed base terms)
   double *hx, *hy, *rhs, *phi, *delta, *base, *src, *dynq;
   // CG vectors: r alternates between cg_r and cg_r2 with the V-cycle count,
   // s = A p between cg_s0 and cg_s1 with the iteration; z = M r, w = A z
@@ -231,7 +234,9 @@ void launch_moments_batch(const void *targs, const int2 *bt_cell, int nb_cell, b
                           hipStream_t s);
 void launch_boundary_flux_batch(const void *targs, const int2 *bt_face, int nb_face,
                                 hipStream_t s);
-// phi, F of the swept intensity; with bflux also the boundary faces' F_T . n
+// phi, F of the swept intensity; with bflux (GSIS) only the per-quadrant
+// partials, which launch_hot(.., true) combines, and the boundary faces'
+// F_T . n in the same launch
 void launch_moments(const PlanDev &P, hipStream_t s, bool bflux);
 
 // ---- synthetic / update kernels (kernels_synth.hip)
@@ -244,7 +249,9 @@ int tiles_of(int nx, int ny);   // multigrid tiles covering an nx x ny level
 int source_tiles_of(int nx, int ny);   // 16 x 16 tiles of the source kernel
 void prepare_synth(size_t coarse_lds);      // kernel attribute for the LDS size
 void launch_source(const SynthSet &S, hipStream_t s);          // src from phi
-void launch_hot(const SynthSet &S, hipStream_t s);               // HoT of every cell
+// HoT of every cell; combine: first phi, F of I^{m+1/2} from the quadrant
+// partials (a single plan; batches combine in their own launch)
+void launch_hot(const SynthSet &S, hipStream_t s, bool combine);
 // grad(x) / (3 sigma_t) of the level-0 iterate for the face-averaged
 // balance; first: x = phi^{m+1/2}, copied into the iterate
 void launch_wide_grad(const SynthSet &S, hipStream_t s, bool first);

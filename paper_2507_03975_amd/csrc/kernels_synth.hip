@@ -104,24 +104,57 @@ __device__ inline Blk blk(const int2 *bt) {
 }
 
 // ---------------------------------------------------------------- HoT / RHS
+// COMBINE: phi and F of I^{m+1/2} are first summed from the four quadrant
+// partials (for the cell and, phi only, its neighbours; quadrants in order,
+// plus the FP32-mixed base term), and the cell's values stored.
+template <bool COMBINE>
 __global__ void k_hot(const SynthDesc *ds, const int2 *bt) {
   const Blk B = blk(bt);
   CDesc &D = cdesc(ds, B.p);
   const int32_t f1 = D.state[1];   // tested after the operands are loaded
-  const int nx = D.nx, ny = D.ny;
+  const int nx = D.nx, ny = D.ny, N = D.N;
   const int c = B.lb * kRedBlock + threadIdx.x;
-  if (c >= D.N) return;
+  if (c >= N) return;
   int i, j;
   cell_ij(c, nx, i, j);
-  const double *phih = D.phih;
-  const double u = phih[c];
-  const double ue = i + 1 < nx ? phih[c + 1] : u, uw = i > 0 ? phih[c - 1] : u;
-  const double un = j + 1 < ny ? phih[c + nx] : u, us = j > 0 ? phih[c - nx] : u;
+  const int ce = i + 1 < nx ? c + 1 : c, cw = i > 0 ? c - 1 : c;
+  const int cn = j + 1 < ny ? c + nx : c, cs = j > 0 ? c - nx : c;
+  double u, ue, uw, un, us, fx, fy;
+  if (COMBINE) {
+    const double *P = D.mom_part;
+    auto phi_at = [&](int cc) {
+      double s0 = 0.0;
+      for (int q = 0; q < 4; ++q) s0 += P[(size_t)(3 * q) * N + cc];
+      if (D.fp32) s0 += D.phi[cc] / kFourPi * D.sw;
+      return s0;
+    };
+    u = phi_at(c); ue = phi_at(ce); uw = phi_at(cw); un = phi_at(cn); us = phi_at(cs);
+    double sx = 0.0, sy = 0.0;
+    for (int q = 0; q < 4; ++q) {
+      sx += P[(size_t)(3 * q + 1) * N + c];
+      sy += P[(size_t)(3 * q + 2) * N + c];
+    }
+    if (D.fp32) {
+      const double sub = D.phi[c] / kFourPi;
+      sx += sub * D.swm;
+      sy += sub * D.swe;
+    }
+    fx = sx; fy = sy;
+  } else {
+    const double *phih = D.phih;
+    u = phih[c]; ue = phih[ce]; uw = phih[cw]; un = phih[cn]; us = phih[cs];
+    fx = D.Fx[c]; fy = D.Fy[c];
+  }
   const double gx = D.cE[c] * (ue - u) - D.cW[c] * (uw - u);
   const double gy = D.cN[c] * (un - u) - D.cS[c] * (us - u);
-  const double hx = D.Fx[c] + gx / (3.0 * D.sig_t[c]);
-  const double hy = D.Fy[c] + gy / (3.0 * D.sig_t[c]);
+  const double hx = fx + gx / (3.0 * D.sig_t[c]);
+  const double hy = fy + gy / (3.0 * D.sig_t[c]);
   if (f1 != 0) return;
+  if (COMBINE) {
+    D.phih[c] = u;
+    D.Fx[c] = fx;
+    D.Fy[c] = fy;
+  }
   D.hx[c] = hx;
   D.hy[c] = hy;
 }
@@ -1381,6 +1414,7 @@ SynthDesc make_synth_desc(const PlanDev &P) {
   D.sig_t = P.sig_t; D.sig_s = P.sig_s; D.q = P.q;
   D.cE = P.cE; D.cW = P.cW; D.cN = P.cN; D.cS = P.cS; D.kappa = P.kappa;
   D.phih = P.phih; D.Fx = P.Fx; D.Fy = P.Fy; D.bflux = P.bflux;
+  D.mom_part = P.mom_part; D.sw = P.sw; D.swm = P.swm; D.swe = P.swe;
   D.hx = P.hx; D.hy = P.hy; D.rhs = P.rhs; D.phi = P.phi; D.delta = P.delta; D.base = P.base;
   D.src = P.src; D.dynq = P.dynq;
   D.cg_r = P.cg_r; D.cg_r2 = P.cg_r2; D.cg_z = P.cg_z; D.cg_p = P.cg_p;
@@ -1433,8 +1467,11 @@ void launch_wide_grad(const SynthSet &S, hipStream_t s, bool first) {
     hipLaunchKernelGGL(k_wide_grad<false>, dim3(S.nb_cell), dim3(kRedBlock), 0, s, S.desc, S.bt_cell);
 }
 
-void launch_hot(const SynthSet &S, hipStream_t s) {
-  hipLaunchKernelGGL(k_hot, dim3(S.nb_cell), dim3(kRedBlock), 0, s, S.desc, S.bt_cell);
+void launch_hot(const SynthSet &S, hipStream_t s, bool combine) {
+  if (combine)
+    hipLaunchKernelGGL(k_hot<true>, dim3(S.nb_cell), dim3(kRedBlock), 0, s, S.desc, S.bt_cell);
+  else
+    hipLaunchKernelGGL(k_hot<false>, dim3(S.nb_cell), dim3(kRedBlock), 0, s, S.desc, S.bt_cell);
 }
 
 // Preconditioned CG (the Chronopoulos-Gear form, see cg_coef) on D1 phi' =

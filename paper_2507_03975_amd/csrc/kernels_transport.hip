@@ -1159,11 +1159,18 @@ __device__ __forceinline__ void boundary_flux(const TArgs &a, const int f) {
   if (threadIdx.x == 0 && f1 == 0) a.bflux[f] = red[0];
 }
 
-// The moments' combine (blocks [0, nbc)) and the boundary faces' F_T . n (the
-// other blocks) in one launch: both only read the swept intensity.
-__global__ void k_combine_bflux(TArgs a, const double *part, int nbc) {
-  if ((int)blockIdx.x < nbc) moments_combine(a, part, blockIdx.x * blockDim.x + threadIdx.x);
-  else boundary_flux(a, blockIdx.x - nbc);
+// The boundary faces' F_T . n (blocks [0, nbf)) and the per-quadrant moment
+// partials (the other blocks, quadrant-major) in one launch: both only read
+// the swept intensity; the four partials are combined by the HoT kernel.
+template <typename T>
+__global__ void k_moments_q_bflux(TArgs a, double *part, int nbc) {
+  const int b = (int)blockIdx.x - a.nbf;
+  if (b < 0) {
+    boundary_flux(a, blockIdx.x);
+    return;
+  }
+  const int q = b / nbc;
+  moments_q<T>(a, part, (b - q * nbc) * (long long)blockDim.x + threadIdx.x, q);
 }
 
 __global__ void k_boundary_flux_b(const TArgs *tas, const int2 *bt) {
@@ -1363,16 +1370,18 @@ void launch_sweep_batch(const void *targs, const int2 *items, int n_items, int *
 void launch_moments(const PlanDev &P, hipStream_t s, bool bflux) {
   TArgs a = make_args(P);
   const int nbc = (P.N + 255) / 256;
+  if (bflux) {   // the combine follows in the HoT kernel
+    const dim3 g(P.nbf + 4 * nbc);
+    if (a.fp32) hipLaunchKernelGGL(k_moments_q_bflux<float>, g, dim3(256), 0, s, a, P.mom_part, nbc);
+    else hipLaunchKernelGGL(k_moments_q_bflux<double>, g, dim3(256), 0, s, a, P.mom_part, nbc);
+    return;
+  }
   if (a.fp32)
     hipLaunchKernelGGL(k_moments_q<float>, dim3(nbc, 4), dim3(256), 0, s, a, P.mom_part);
   else
     hipLaunchKernelGGL(k_moments_q<double>, dim3(nbc, 4), dim3(256), 0, s, a, P.mom_part);
-  if (bflux)
-    hipLaunchKernelGGL(k_combine_bflux, dim3(nbc + P.nbf), dim3(256), 0, s, a,
-                       (const double *)P.mom_part, nbc);
-  else
-    hipLaunchKernelGGL(k_moments_combine, dim3(nbc), dim3(256), 0, s, a,
-                       (const double *)P.mom_part);
+  hipLaunchKernelGGL(k_moments_combine, dim3(nbc), dim3(256), 0, s, a,
+                     (const double *)P.mom_part);
 }
 
 void launch_moments_batch(const void *targs, const int2 *bt_cell, int nb_cell, bool fp32,
