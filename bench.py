@@ -6,16 +6,22 @@ sigma_t = 1, c = 0.5 outside, unit source in the thick region, vacuum, FP64,
 Barth-Jespersen limiter on. A step is one outer GSIS iteration (transport
 residual + sweep + moments, boundary fluxes + HoT + synthetic right-hand side,
 CG/multigrid synthetic solve, correction + Err) on resident device data.
+``--config block1024 [--precision fp32]`` times the 1024 x 1024 x 128 block
+medium instead (the configuration whose intensities do not fit the 256 MB
+last-level cache), for profiling.
 
 Prints ONE JSON line. value = cell-ordinate updates per second over the timed
-steps (nx*ny*K per step). Also reported: the dominant transport kernel (the
-residual kernel or the wavefront recurrence, whichever takes longer) against
-the HBM roofline (algorithmic 16 B per cell-ordinate for either: the residual
-reads I^m and writes the recurrence's right-hand side, the recurrence reads
-that and writes I^{m+1/2}; durations come from HIP events recorded on the
-plan's stream around each launch in every timed step),
-time-to-converge (Err < 1e-6) for GSIS and for source iteration, and the CPU
-oracle on a bounded sample of the same workload.
+steps (nx*ny*K per step). The roofline object charges the transport step's
+algorithmic bytes (one read of I^m and one write of I^{m+1/2} per
+cell-ordinate: 16 B in FP64, 8 B in FP32-mixed) to the transport step as a
+whole, the residual kernel plus the wavefront recurrence (their durations
+come from HIP events recorded on the plan's stream around each launch in
+every timed step), and lists each kernel with its measured HBM traffic; the
+synthetic solve and the whole iteration are reported beside it.
+Also reported: time-to-converge (Err < 1e-6) for GSIS and for source
+iteration, the three additions against the plain FP64 form, and, in the CPU
+leg, the oracle timed on a bounded sample of the same workload and the
+oracle's fixed points the GPU results are compared with.
 """
 import argparse
 import hashlib
@@ -29,56 +35,77 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-ALG_BYTES_FP64 = 16.0
+ALG_BYTES = {"fp64": 16.0, "fp32": 8.0}
+# Algorithmic bytes of one synthetic CG iteration per cell of the finest
+# level: the CG update reads x, r, p, s, z, w and writes x, r, p, s (80 B);
+# the V-cycle's level-0 smoothing and restriction read r and the 5-point
+# operator (diag, ax, ay) and write the pre-smoothed iterate and the
+# restricted residual (48 B); its prolongation and post-smoothing read the
+# pre-smoothed iterate, the operator and r and write z and w = A z (56 B);
+# the coarser levels add a third of the finest level's V-cycle traffic.
+SYNTH_BYTES_PER_CELL = 80.0 + (48.0 + 56.0) * 4.0 / 3.0
 # Relative tolerance of the synthetic CG per outer iteration: the loosest of
 # 1e-1 .. 1e-4 at which GSIS on this workload still reaches Err < 1e-6 within
 # one outer iteration of the count an accurate solve needs (23 at 1e-4, 24 at
 # 3e-3 and 1e-3, 32 at 1e-2, 28 at 1e-1).
 SYNTH_RTOL = 3e-3
 
-# HBM traffic per launch of the transport kernels from two rocprofv3 --pmc
-# runs of "bench.py --steps 3 --warmup 1 --no-converge --no-cpu-baseline
-# --no-forms" (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), scaled by what
-# the same counters read for a 256 MiB device copy (bench.py
-# --copy-calibration). Valid only for the kernel source whose sha256 is
-# recorded; any change to it turns the figure back to null.
-TRAFFIC = {"sha256": "aada88ad40a8e778e96b3e439eba5ec0c37fb6df6b71f16466f892893c9b7b77",
-           # FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (the 256 MiB copy reads 131084.5 KiB
-           # of FETCH_SIZE and 262144 KiB of WRITE_SIZE per dispatch)
-           "residual": 246280523,   # 85178.0 KiB fetched x 2.0 + 70168.6 KiB written
-           "sweep": 138751331}      # 34863.1 KiB fetched x 2.0 + 65779.8 KiB written
+# HBM traffic per launch of the transport kernels, per timed configuration,
+# from two rocprofv3 --pmc runs of "bench.py --config <cfg> --precision <p>
+# --steps 3 --warmup 1 --no-converge --no-cpu-baseline --no-forms"
+# (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), scaled by what the same
+# counters read for a 256 MiB device copy (bench.py --copy-calibration: it
+# reads 131084.5 KiB of FETCH_SIZE and 262144 KiB of WRITE_SIZE per dispatch,
+# so FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0). Valid only for the kernel source
+# whose sha256 is recorded; any change to it turns the figures back to null.
+TRAFFIC = {}
 KERNELS = {"residual": "k_resid (second-order residual of every cell-ordinate, ALSM gradient "
                        "and BJ limiter, written as the recurrence's right-hand side)",
-           "sweep": "k_chain (first-order-upwind recurrence on the anti-diagonal wavefront)"}
+           "sweep": "k_chain / k_chain_split (first-order-upwind recurrence on the "
+                    "anti-diagonal wavefront)"}
 
 
 def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(prob, n_iter):
-    """Time the FP64 oracle (as it stands) for n_iter GSIS iterations of the
-    same workload on this host's cores."""
+def cpu_leg(prob, n_iter, inputs, with_refs):
+    """The CPU leg: the FP64 oracle (as it stands) timed for up to n_iter
+    GSIS iterations of the same workload on this host's cores, stopping at
+    Err < 1e-6 (the same options as the GPU's timed steps, limiter on); its
+    converged fields are the reference of the headline solve. With
+    with_refs, also the oracle's FP64 fixed point of the block medium at
+    256 x 256 x 128 (beta 10, limiter off, Err < 1e-6), the reference of the
+    FP32-mixed form."""
     import oracle
     cores = len(os.sched_getaffinity(0))
     t0 = time.perf_counter()
-    r = oracle.solve(prob, method=1, tol=0.0, max_iter=n_iter)
+    r = oracle.solve(prob, method=1, tol=1e-6, max_iter=n_iter)
     dt = time.perf_counter() - t0
     N, K = prob["nx"] * prob["ny"], len(prob["mu"])
     omp = os.environ.get("OMP_NUM_THREADS")
     used = min(cores, int(omp)) if omp and omp.isdigit() else cores
-    return {"value": N * K * r["n_iter"] / dt, "unit": "cell-ordinate updates/s", "cores": used,
+    base = {"value": N * K * r["n_iter"] / dt, "unit": "cell-ordinate updates/s", "cores": used,
             "kind": "oracle",
-            "sample": "%d GSIS iterations of the full %dx%dx%d workload from I=0 "
+            "sample": "%d GSIS iterations (Err %.2e) of the full %dx%dx%d workload from I=0 "
                       "(incl. one banded-Cholesky factorisation), %.1f s" % (
-                          r["n_iter"], prob["nx"], prob["ny"], K, dt)}
+                          r["n_iter"], r["final_err"], prob["nx"], prob["ny"], K, dt)}
+    refs = {"headline": r}
+    if with_refs:
+        t0 = time.perf_counter()
+        refs["block256"] = oracle.solve(inputs.checkerboard_blocks(256), method=1, tol=1e-6,
+                                        max_iter=500, beta=10.0, limiter=0)
+        log("oracle block medium 256: %d iterations, %.1f s" % (
+            refs["block256"]["n_iter"], time.perf_counter() - t0))
+    return base, refs
 
 
 def measure_controls(ctx, gsis, pd, opts, N, K, args, phases, nprof, achieved, torch, dev):
     """The transport step alone (residual + recurrence) as cell-ordinate
     updates/s, the same steps with the limiter off (the residual's arithmetic
     control), and a measured copy ceiling: a 1 GiB FP64 device copy, bytes
-    read + written per second."""
+    read + written per second, with the transport step's algorithmic rate as
+    a fraction of it."""
     n = max(nprof, 1)
     tr_ms = (phases["residual"] + phases["sweep"]) / n
     res = {"transport": {"kernels": "residual + recurrence", "ms": tr_ms,
@@ -109,21 +136,23 @@ def measure_controls(ctx, gsis, pd, opts, N, K, args, phases, nprof, achieved, t
     torch.cuda.synchronize()
     gbs = 2 * x.numel() * 8 * 10 / (e0.elapsed_time(e1) / 1e3) / 1e9
     del x, y
-    res["copy_ceiling"] = {"GB_per_s": gbs, "recurrence_frac_of_copy": achieved / gbs}
+    res["copy_ceiling"] = {"GB_per_s": gbs, "transport_frac_of_copy": achieved / gbs}
     log("controls: %s" % res)
     return res
 
 
-def kernel_traffic(phase):
-    """Bytes per sweep launch from the PMC runs, if the kernel is unchanged."""
-    if TRAFFIC.get(phase) is None:
+def kernel_traffic(cfg, phase):
+    """Bytes per launch of a transport kernel from the PMC runs of this
+    configuration, if the kernel source is unchanged since they were taken."""
+    t = TRAFFIC.get(cfg)
+    if not t or t.get(phase) is None:
         return None
     src = os.path.join(ROOT, "paper_2507_03975_amd", "csrc", "kernels_transport.hip")
     with open(src, "rb") as f:
         sha = hashlib.sha256(f.read()).hexdigest()
-    if sha != TRAFFIC["sha256"]:
+    if sha != t["sha256"]:
         return None
-    return TRAFFIC[phase]
+    return t[phase]
 
 
 def _converge(pl, cap, chunk=16):
@@ -153,6 +182,17 @@ def measure_forms(ctx, gsis, inputs, np, torch, dev):
     dv = lambda p: {k: (torch.from_numpy(v).to(dev) if isinstance(v, np.ndarray) else v)
                     for k, v in p.items()}
     forms = {}
+    # FP32-mixed and FP64 fixed points of the block medium at 256 x 256 x 128,
+    # kept for the comparison with the oracle's (CPU leg)
+    p256 = dv(inputs.checkerboard_blocks(256))
+    fp256 = {}
+    for name, prec in (("fp64", gsis.GSIS_FP64), ("fp32_mixed", gsis.GSIS_FP32_MIXED)):
+        pl = gsis.Plan(ctx, p256, precision=prec, tol=1e-6, max_iter=500, limiter=0, beta=10.0)
+        _converge(pl, 500)
+        f = pl.read()
+        fp256[name] = {k: f[k].cpu().numpy() for k in ("phi", "Fx", "Fy")}
+        pl.close()
+    del p256
     # FP32-mixed: 1024 x 1024 x 128 block medium (local pseudo time beta = 10)
     pc = dv(inputs.checkerboard_blocks(1024))
     res = {}
@@ -171,8 +211,9 @@ def measure_forms(ctx, gsis, inputs, np, torch, dev):
         "fp64": {k: v for k, v in res["fp64"].items() if k != "fields"},
         "fp32_mixed": {k: v for k, v in res["fp32_mixed"].items() if k != "fields"},
         "time_ratio_fp32_over_fp64": res["fp32_mixed"]["seconds"] / res["fp64"]["seconds"],
-        "error_vs_fp64": {"phi": _rel(a["phi"], b["phi"]), "Fx": _rel(a["Fx"], b["Fx"]),
-                          "Fy": _rel(a["Fy"], b["Fy"])}}
+        "error_vs_gpu_fp64": {"phi": _rel(a["phi"], b["phi"]), "Fx": _rel(a["Fx"], b["Fx"]),
+                              "Fy": _rel(a["Fy"], b["Fy"])},
+        "block256_fields": fp256}
     del res, a, b, pc
     # batched: 64 uneven problems in one batch vs 64 sequential plain FP64 solves
     probs = [dv(p) for p in inputs.batch_problems()]
@@ -295,6 +336,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-converge", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=40)
+    ap.add_argument("--config", choices=("thick256", "block1024"), default="thick256",
+                    help="timed workload: the 256x256x128 thick square (default) or the "
+                         "1024x1024x128 block medium (timed steps only)")
+    ap.add_argument("--precision", choices=("fp64", "fp32"), default="fp64")
     ap.add_argument("--si-cap", type=int, default=3000)
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the FP32-mixed, batched and adjoint measurements")
@@ -329,12 +374,26 @@ def main():
         print(json.dumps({"paper_2d": paper_2d_table(gsis.Context(0), gsis, inputs, np, torch,
                                                      dev)}), flush=True)
         return
-    prob = inputs.thick_square(256)
+    block = args.config == "block1024"
+    fp32 = args.precision == "fp32"
+    if block:
+        prob = inputs.checkerboard_blocks(1024)
+        opts = dict(method=gsis.GSIS_GSIS, limiter=0, beta=10.0)
+        wname = ("GSIS %s, 1024x1024 cells, 128 ordinates (GL4x Chebyshev32), 7x7 blocks "
+                 "sigma_a logU[1e-2,1e2] sigma_s logU[1e-1,1e4] (seed 3), unit source, vacuum, "
+                 "beta 10, limiter off" % ("FP32-mixed" if fp32 else "FP64"))
+    else:
+        prob = inputs.thick_square(256)
+        opts = dict(method=gsis.GSIS_GSIS, limiter=1)
+        wname = ("GSIS %s, 256x256 cells, 128 ordinates (GL4x Chebyshev32), thick square "
+                 "sigma_t=1e3 c=0.9999 in sigma_t=1 c=0.5, unit source in the thick region, "
+                 "vacuum, BJ limiter" % ("FP32-mixed" if fp32 else "FP64"))
+    opts.update(synth_rtol=SYNTH_RTOL, synth_max_iter=50,
+                precision=gsis.GSIS_FP32_MIXED if fp32 else gsis.GSIS_FP64)
     N, K = prob["nx"] * prob["ny"], len(prob["mu"])
     pd = {k: (torch.from_numpy(v).to(dev) if isinstance(v, np.ndarray) else v)
           for k, v in prob.items()}
     ctx = gsis.Context(0)
-    opts = dict(method=gsis.GSIS_GSIS, limiter=1, synth_rtol=SYNTH_RTOL, synth_max_iter=50)
 
     # ---- timed steps: K outer iterations from the initial state
     plan = gsis.Plan(ctx, pd, tol=0.0, max_iter=args.steps + args.warmup + 1, profile=1, **opts)
@@ -352,15 +411,29 @@ def main():
     ms = e0.elapsed_time(e1)
     phases, nprof = plan.phase_times()
     n_done = plan.status()[0]
+    vcycles = plan.synth_vcycles()
     assert n_done == args.steps, (n_done, args.steps)
     plan.close()
     ms_step = ms / args.steps
     value = N * K * args.steps / (ms / 1e3)
-    dom = max(("residual", "sweep"), key=lambda k: phases[k])
-    dom_ms = phases[dom] / max(nprof, 1)
-    achieved = ALG_BYTES_FP64 * N * K / (dom_ms / 1e3) / 1e9
-    log("step %.3f ms; phases per step (ms): %s" % (
-        ms_step, {k: round(v / max(nprof, 1), 4) for k, v in phases.items()}))
+    nprof = max(nprof, 1)
+    per = {k: v / nprof for k, v in phases.items()}
+    alg = ALG_BYTES[args.precision] * N * K           # one read of I^m, one write of I^{m+1/2}
+    tr_ms = per["residual"] + per["sweep"]
+    achieved = alg / (tr_ms / 1e3) / 1e9
+    cfg_key = "%s_%s" % (args.config, args.precision)
+    kern = {}
+    for ph in ("residual", "sweep"):
+        t = kernel_traffic(cfg_key, ph)
+        kern[ph] = {"kernel": KERNELS[ph], "avg_ms": per[ph], "traffic": t,
+                    "traffic_over_transport_algorithmic": None if t is None else t / alg}
+    traffic = None
+    if kern["residual"]["traffic"] is not None and kern["sweep"]["traffic"] is not None:
+        traffic = kern["residual"]["traffic"] + kern["sweep"]["traffic"]
+    vc_step = vcycles / args.steps
+    synth_bytes = SYNTH_BYTES_PER_CELL * N * vc_step
+    log("step %.3f ms; phases per step (ms): %s; V-cycles per step %.2f" % (
+        ms_step, {k: round(v, 4) for k, v in per.items()}, vc_step))
 
     out = {
         "metric": "cell-ordinate updates/s; time-to-converge GSIS vs SI at rel resid 1e-6",
@@ -373,22 +446,35 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32" if fp32 else "f64",
         "data": "synthetic",
-        "config": {"workload": "GSIS FP64, 256x256 cells, 128 ordinates (GL4x Chebyshev32), "
-                               "thick square sigma_t=1e3 c=0.9999 in sigma_t=1 c=0.5, unit "
-                               "source in the thick region, vacuum, BJ limiter",
-                   "nx": 256, "ny": 256, "ordinates": K, "method": "GSIS",
-                   "step": "one outer iteration"},
+        "config": {"workload": wname, "nx": prob["nx"], "ny": prob["ny"], "ordinates": K,
+                   "method": "GSIS", "step": "one outer iteration"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": kernel_traffic(dom),
-                     "kernel": KERNELS[dom],
-                     "algorithmic_bytes_per_launch": ALG_BYTES_FP64 * N * K,
-                     "avg_ms": dom_ms},
-        "phase_ms_per_step": {k: v / max(nprof, 1) for k, v in phases.items()},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "transport step: k_resid + recurrence (the two launches of "
+                               "Eqs. RTE_d_res..elem_mtx)",
+                     "algorithmic_bytes_per_launch": alg,
+                     "algorithmic_bytes_per_cell_ordinate": ALG_BYTES[args.precision],
+                     "avg_ms": tr_ms, "kernels": kern,
+                     "whole_iteration": {"ms": ms_step,
+                                         "achieved": alg / (ms_step / 1e3) / 1e9,
+                                         "frac": alg / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS},
+                     "synthetic": {"ms": per["synth"], "vcycles_per_step": vc_step,
+                                   "algorithmic_bytes_per_cell_per_cg_iteration":
+                                       SYNTH_BYTES_PER_CELL,
+                                   "achieved": synth_bytes / (per["synth"] / 1e3) / 1e9
+                                   if per["synth"] > 0 else None,
+                                   "frac": synth_bytes / (per["synth"] / 1e3) / 1e9 /
+                                   HBM_PEAK_GBS if per["synth"] > 0 else None}},
+        "phase_ms_per_step": per,
     }
+    if block:
+        print(json.dumps(out), flush=True)
+        return
 
     # ---- time to converge (Err < 1e-6), GSIS vs SI on the same GPU
+    gsis_phi = None
     if not args.no_converge:
         res = {}
         for name, method, cap in (("gsis", gsis.GSIS_GSIS, 500), ("si", gsis.GSIS_SI, args.si_cap)):
@@ -407,8 +493,12 @@ def main():
             r = pl.read()
             pl.close()
             hist = r["err_hist"].cpu().numpy() if hasattr(r["err_hist"], "cpu") else r["err_hist"]
+            th = r["tres_hist"].cpu().numpy() if hasattr(r["tres_hist"], "cpu") else r["tres_hist"]
             ent = {"iterations": int(n), "seconds": dt, "final_err": float(err),
-                   "converged": bool(conv == 1)}
+                   "converged": bool(conv == 1),
+                   "final_transport_residual": float(th[-1]) if len(th) else None}
+            if name == "gsis":
+                gsis_phi = {k: r[k].cpu().numpy() for k in ("phi", "Fx", "Fy")}
             if conv != 1 and len(hist) > 200:
                 tail = hist[-200:]
                 rho = float(np.exp(np.mean(np.log(tail[1:] / tail[:-1]))))
@@ -421,20 +511,34 @@ def main():
             log("%s: %s" % (name, ent))
         g, s = res["gsis"], res["si"]
         s_sec = s.get("seconds_extrapolated", s["seconds"])
-        out["time_to_converge"] = {"tol": 1e-6, "gsis": g, "si": s,
+        out["time_to_converge"] = {"tol": 1e-6, "synth_rtol": SYNTH_RTOL, "gsis": g, "si": s,
                                    "si_over_gsis_time": s_sec / g["seconds"]}
 
     if not args.no_forms:
         out["controls"] = measure_controls(ctx, gsis, pd, opts, N, K, args, phases, nprof,
                                            achieved, torch, dev)
         out["forms"] = measure_forms(ctx, gsis, inputs, np, torch, dev)
+    f256 = out.get("forms", {}).get("fp32_mixed", {}).pop("block256_fields", None)
 
     if not args.no_cpu_baseline:
-        log("cpu baseline: oracle, %d iterations" % args.cpu_iters)
-        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_iters)
+        log("cpu leg: oracle, up to %d iterations" % args.cpu_iters)
+        base, refs = cpu_leg(prob, args.cpu_iters, inputs, f256 is not None)
+        out["cpu_baseline"] = base
+        relnp = lambda a, b: float(np.abs(a - b).max() / np.abs(b).max())
+        o = refs["headline"]
+        if gsis_phi is not None and o["final_err"] < 1e-6:
+            out["time_to_converge"]["gsis"]["error_vs_oracle"] = {
+                "oracle_iterations": int(o["n_iter"]),
+                **{k: relnp(gsis_phi[k], o[k]) for k in ("phi", "Fx", "Fy")}}
+        if f256 is not None and refs.get("block256", {}).get("status") == 0:
+            o = refs["block256"]
+            out["forms"]["fp32_mixed"]["error_vs_oracle"] = {
+                "workload": "the same block medium at 256x256 cells, 128 ordinates, both "
+                            "converged to Err < 1e-6 (oracle %d iterations)" % o["n_iter"],
+                **{prec: {k: relnp(f256[prec][k], o[k]) for k in ("phi", "Fx", "Fy")}
+                   for prec in ("fp64", "fp32_mixed")}}
 
     print(json.dumps(out), flush=True)
-
 
 if __name__ == "__main__":
     main()

@@ -42,7 +42,13 @@ extern "C" {
 typedef enum {
   GSIS_OK = 0,
   GSIS_NOT_CONVERGED = 1,   /* max_iter reached with Err >= tol */
-  GSIS_DIVERGED = 2,        /* Err became non-finite */
+  GSIS_DIVERGED = 2,        /* Err became non-finite, or the change
+                               ||phi^{m+1} - phi^m||_V grew above 1e3 times
+                               its smallest value in the solve so far
+                               (floored at 1e-9 ||phi^{m+1}||_V): the outer
+                               iteration is unstable (GSIS at strong opacity
+                               jumps needs the pseudo-time shift of Sec.
+                               4.3, options.beta) */
   GSIS_E_INVALID_ARG = -1,  /* argument check failed; see gsis_last_error */
   GSIS_E_DEVICE = -2,       /* a HIP call failed */
   GSIS_E_OOM = -3,          /* device or host allocation failed */
@@ -65,7 +71,9 @@ const char *gsis_last_error(const gsis_ctx *ctx);
 
 /* Problem statement (Sec. 4.1, Sec. 4.4). */
 typedef struct {
-  int32_t nx, ny;          /* cells per direction, >= 1 */
+  int32_t nx, ny;          /* cells per direction, >= 1, with nx*ny at most
+                              GSIS_MAX_CELLS (GSIS_E_INVALID_ARG otherwise,
+                              before anything is read or allocated) */
   double dx, dy;           /* cell sizes, > 0 */
   int32_t K;               /* number of ordinates, >= 1 */
   const double *mu;        /* [K] x direction cosine of Omega_k */
@@ -83,6 +91,10 @@ typedef struct {
                               are ignored; NULL = vacuum */
 } gsis_problem;
 
+/* Largest nx*ny: the transport kernels address a quadrant's 48-byte
+ * per-cell records with 32-bit byte offsets, so 48 nx ny < 2^32. */
+#define GSIS_MAX_CELLS 89478485
+
 enum { GSIS_SI = 0, GSIS_GSIS = 1 };
 enum { GSIS_FP64 = 0, GSIS_FP32_MIXED = 1 };
 enum { GSIS_HOT_CENTRAL = 0, GSIS_HOT_TRANSPORT = 1 };
@@ -98,8 +110,15 @@ typedef struct {
                             0 = plain least squares (Sec. 5.1) */
   int32_t hot_face;      /* GSIS_HOT_CENTRAL (default): face average of the
                             cell higher-order terms (Eq. Fij_d);
-                            GSIS_HOT_TRANSPORT: transport face flux minus the
-                            compact diffusion flux */
+                            GSIS_HOT_TRANSPORT: on every interior face the
+                            transport flux sum_k w_k (Omega_k . n) I_f,k of
+                            the swept intensity (second-order upwind face
+                            values, as in the residual) minus the compact
+                            diffusion flux Gamma_f (phi_c - phi_nb), the full
+                            form of Sec. 3.1 (Eq. DSA_Alcouffe), whose fixed
+                            point is the source-iteration one. Single plans
+                            only (a batch returns GSIS_E_UNSUPPORTED), not
+                            with synth_form 1 or the adjoint */
   double tol;            /* stop when Err(phi) < tol (Eq. Err_W); default 1e-6 */
   int32_t max_iter;      /* outer iteration cap, >= 1; default 1000 */
   double synth_rtol;     /* synthetic CG stops at ||r|| <= synth_rtol ||r0||
@@ -148,7 +167,20 @@ gsis_status gsis_options_default(gsis_options *o);
 typedef struct {
   double *phi;           /* [nx*ny] out: phi at the last iterate */
   double *Fx, *Fy;       /* [nx*ny] out: radiative flux of the last iterate */
-  double *err_hist;      /* [max_iter] out: Err per iteration (may be NULL) */
+  double *err_hist;      /* [max_iter] out: Err after each iteration (Eq.
+                            Err_W; may be NULL) */
+  double *tres_hist;     /* [max_iter] out (may be NULL): relative transport
+                            residual of the iterate I^m that iteration m
+                            starts from, ||r(I^m)||_V / ||(sigma_s phi^m +
+                            q)/(4 pi)||_V with r of Eq. RTE_d_res and
+                            ||x||_V^2 = sum_c V sum_k w_k x_ck^2. It is 0
+                            only where I^m solves the discrete transport
+                            equation, so it exposes a source iteration that
+                            meets Err < tol without having converged (Sec.
+                            5.2.1); GSIS with central HoT faces keeps a
+                            small nonzero value at its fixed point. (With the
+                            test-only environment switch
+                            GSIS_SWEEP_REFERENCE the history reads 0.) */
   int32_t n_iter;        /* out: iterations performed */
   double final_err;      /* out: Err of the last iteration */
 } gsis_result;
@@ -161,13 +193,17 @@ gsis_status gsis_solve(gsis_ctx *ctx, const gsis_problem *p,
 gsis_status gsis_plan_create(gsis_ctx *ctx, const gsis_problem *p,
                              const gsis_options *o, gsis_plan **out);
 void gsis_plan_destroy(gsis_plan *plan);
-/* Enqueue n more outer iterations on the plan's stream and return without
- * waiting. Iterations after convergence (Err < tol) or after max_iter do no
- * work, so the iterate stops exactly where a synchronous loop would. */
+/* Enqueue n more outer iterations on the plan's stream. Iterations after
+ * convergence (Err < tol), divergence or max_iter do no work, so the
+ * iterate stops exactly where a synchronous loop would. SI plans return
+ * without waiting. GSIS plans wait for the device once per outer iteration:
+ * the host reads the synthetic CG's device stop flag (after the V-cycle at
+ * which the previous solve converged) so that it launches no V-cycle past
+ * convergence, and stops enqueueing once an iteration has ended the solve. */
 gsis_status gsis_plan_iterate(gsis_plan *plan, int32_t n);
 /* Wait for the plan's stream, then report progress: iterations done and
- * whether Err < tol was reached (converged = 1) or Err became non-finite
- * (converged = -1). Returns GSIS_E_DEVICE if the workgroups that share one
+ * whether Err < tol was reached (converged = 1) or the iteration diverged
+ * (converged = -1, see GSIS_DIVERGED). Returns GSIS_E_DEVICE if the workgroups that share one
  * ordinate's wavefront recurrence (its rows are spread over up to 4 of them
  * when ny > 256 or when the ordinates alone would fill under half the CUs;
  * GSIS_CHAIN_PARTS=1..4 in the environment at plan creation fixes the
@@ -192,6 +228,12 @@ enum {
   GSIS_PHASE_UPDATE = 5,   /* correction, Err and the next source */
   GSIS_NUM_PHASES = 6
 };
+/* Wait for the plan's stream; *vcycles receives the number of multigrid
+ * V-cycles (preconditioner applications: one after the warm start of each
+ * synthetic solve, one per CG iteration) of all synthetic solves since the
+ * plan was created or reset (with synth_form 1, of the last sub-iteration's
+ * solve of each outer iteration). 0 for source iteration. */
+gsis_status gsis_plan_synth_vcycles(gsis_plan *plan, int64_t *vcycles);
 /* Wait for the plan's stream; ms[GSIS_NUM_PHASES] receives the summed
  * duration of each phase over all profiled iterations (HIP events on the
  * plan's stream), *n_iter the number of profiled iterations. Needs

@@ -74,7 +74,7 @@ def _load():
         lib.ora_pseudo_shift.restype = ctypes.c_double
         lib.ora_iterate.argtypes = [P, O, _dp, _dp, _dp]
         lib.ora_iterate.restype = ctypes.c_int
-        lib.ora_solve.argtypes = [P, O, _dp, _dp, _dp, _dp, _dp, ip, _dp, _dp]
+        lib.ora_solve.argtypes = [P, O, _dp, _dp, _dp, _dp, _dp, _dp, ip, _dp, _dp]
         lib.ora_solve.restype = ctypes.c_int
         lib.ora_synthetic_solve.argtypes = [P, _dp, _dp]
         lib.ora_synthetic_solve.restype = ctypes.c_int
@@ -226,22 +226,26 @@ def synthetic_apply(prob, x):
 def solve(prob, I0=None, return_I=False, **opts):
     """Iterate to Err(phi) < tol (Eq. Err_W) or max_iter.
 
-    Returns a dict: phi, Fx, Fy [N], err_hist [n_iter], n_iter, final_err,
-    status (0 converged, 1 not converged, <0 error) and optionally I [N, K].
+    Returns a dict: phi, Fx, Fy [N], err_hist [n_iter], tres_hist [n_iter]
+    (relative transport residual of the iterate each iteration starts from),
+    n_iter, final_err, status (0 converged, 1 not converged, 2 diverged,
+    <0 error) and optionally I [N, K].
     """
     m = _Marshal(prob)
     o = _opts(**opts)
     N, K = m.nx * m.ny, m.K
     phi, fx, fy = np.zeros(N), np.zeros(N), np.zeros(N)
     hist = np.zeros(max(o.max_iter, 1))
+    thist = np.zeros(max(o.max_iter, 1))
     n_iter = ctypes.c_int(0)
     ferr = ctypes.c_double(0)
     If = np.empty((N, K)) if return_I else None
     I0c = None if I0 is None else np.ascontiguousarray(I0, dtype=np.float64)
     st = _load().ora_solve(ctypes.byref(m.s), ctypes.byref(o), _ptr(I0c), _ptr(phi),
-                           _ptr(fx), _ptr(fy), _ptr(hist), ctypes.byref(n_iter),
+                           _ptr(fx), _ptr(fy), _ptr(hist), _ptr(thist), ctypes.byref(n_iter),
                            ctypes.byref(ferr), _ptr(If))
-    out = dict(phi=phi, Fx=fx, Fy=fy, err_hist=hist[:n_iter.value], n_iter=n_iter.value,
+    out = dict(phi=phi, Fx=fx, Fy=fy, err_hist=hist[:n_iter.value],
+               tres_hist=thist[:n_iter.value], n_iter=n_iter.value,
                final_err=ferr.value, status=st)
     if return_I:
         out["I"] = If

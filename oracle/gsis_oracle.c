@@ -360,7 +360,7 @@ typedef struct {
   int use_cg;
 } synth_factor;
 
-#define BAND_LIMIT (1L << 28)   /* doubles; above this CG is used */
+#define BAND_LIMIT (1L << 31)   /* doubles (16 GiB); above this CG is used */
 
 static int synth_factor_build(const ora_problem *p, synth_factor *S) {
   const int nx = p->nx, ny = p->ny, N = nx * ny;
@@ -401,12 +401,15 @@ static int synth_factor_build(const ora_problem *p, synth_factor *S) {
     const double djj = sqrt(s);
     L[(size_t)jc * ld] = djj;
     int iend = jc + bw < N - 1 ? jc + bw : N - 1;
-#pragma omp parallel for schedule(static) if (bw >= 64)
+#pragma omp parallel for schedule(dynamic, 16) if (bw >= 64)
     for (int i = jc + 1; i <= iend; ++i) {
       double t = L[(size_t)i * ld + (i - jc)];
       int kk0 = i - bw > 0 ? i - bw : 0;
+      double acc = 0.0;
+#pragma omp simd reduction(+ : acc)
       for (int k = kk0; k < jc; ++k)
-        t -= L[(size_t)i * ld + (i - k)] * L[(size_t)jc * ld + (jc - k)];
+        acc += L[(size_t)i * ld + (i - k)] * L[(size_t)jc * ld + (jc - k)];
+      t -= acc;
       L[(size_t)i * ld + (i - jc)] = t / djj;
     }
   }
@@ -462,9 +465,8 @@ static int synth_cg(const ora_problem *p, const double *b, double *x) {
   return ret == 0 ? 0 : -2;
 }
 
-static int synth_solve_with(const ora_problem *p, const synth_factor *S,
-                            const double *b, double *x) {
-  if (S->use_cg) return synth_cg(p, b, x);
+/* x = (L L^T)^{-1} b by forward and backward substitution in the band. */
+static void band_substitute(const synth_factor *S, const double *b, double *x) {
   const int N = S->N, bw = S->bw;
   const size_t ld = bw + 1;
   const double *L = S->L;
@@ -482,6 +484,24 @@ static int synth_solve_with(const ora_problem *p, const synth_factor *S,
     for (int k = i + 1; k <= k1; ++k) t -= L[(size_t)k * ld + (k - i)] * x[k];
     x[i] = t / L[(size_t)i * ld];
   }
+}
+
+/* D1 x = b by the Cholesky factor and one step of iterative refinement
+ * (r = b - D1 x, x += (L L^T)^{-1} r): on the high-contrast media D1's
+ * condition number reaches 1e9, where the refinement takes the solution
+ * from about 1e-10 to about 1e-12 of the exact solve the method asks for. */
+static int synth_solve_with(const ora_problem *p, const synth_factor *S,
+                            const double *b, double *x) {
+  if (S->use_cg) return synth_cg(p, b, x);
+  const int N = S->N;
+  band_substitute(S, b, x);
+  double *r = malloc(sizeof(double) * N), *dx = malloc(sizeof(double) * N);
+  if (!r || !dx) { free(r); free(dx); return -3; }
+  ora_synthetic_apply(p, x, r);
+  for (int c = 0; c < N; ++c) r[c] = b[c] - r[c];
+  band_substitute(S, r, dx);
+  for (int c = 0; c < N; ++c) x[c] += dx[c];
+  free(r); free(dx);
   return 0;
 }
 
@@ -616,8 +636,33 @@ typedef struct {
   int have_S;
 } ora_ctx;
 
+/* Relative transport residual of the iterate I (whose residual is r):
+ *   ||r||_V / ||(sigma_s phi + q) / (4 pi)||_V,  phi = sum_k w_k I_k,
+ * with ||x||_V^2 = sum_c V_c sum_k w_k x_{c,k}^2 (cells weighted by volume,
+ * ordinates by their quadrature weights; the denominator is the isotropic
+ * source of the same iterate). It is zero exactly when I solves the
+ * discrete transport equation, whatever the outer method, so it shows a
+ * method that stops on Err (Eq. Err_W) before the transport has converged. */
+static double transport_residual_norm(const ora_problem *p, const double *I, const double *r) {
+  const int N = p->nx * p->ny, K = p->K;
+  const double V = p->dx * p->dy;
+  double num = 0.0, den = 0.0;
+  for (int c = 0; c < N; ++c) {
+    double phi = 0.0;
+    for (int k = 0; k < K; ++k) phi += p->w[k] * I[(size_t)c * K + k];
+    const double s = (p->sig_s[c] * phi + p->q[c]) / FOUR_PI;
+    for (int k = 0; k < K; ++k) {
+      const double rk = r[(size_t)c * K + k];
+      num += V * p->w[k] * rk * rk;
+      den += V * p->w[k] * s * s;
+    }
+  }
+  if (den == 0) return num == 0 ? 0.0 : INFINITY;
+  return sqrt(num / den);
+}
+
 static int iterate_ctx(ora_ctx *X, const double *I_in, double *I_out,
-                       double *phi_out) {
+                       double *phi_out, double *tres) {
   const ora_problem *p = X->p;
   const ora_options *o = X->o;
   const int nx = p->nx, ny = p->ny, N = nx * ny, K = p->K;
@@ -628,6 +673,7 @@ static int iterate_ctx(ora_ctx *X, const double *I_in, double *I_out,
 
   /* residual and exact increment solve */
   ora_residual(p, o, I_in, r);
+  if (tres) *tres = transport_residual_norm(p, I_in, r);
   ora_sweep(p, o, r, dI);
   free(r);
   /* I^{m+1/2} = I^m + dI */
@@ -728,26 +774,31 @@ static int iterate_ctx(ora_ctx *X, const double *I_in, double *I_out,
 int ora_iterate(const ora_problem *p, const ora_options *o, const double *I_in,
                 double *I_out, double *phi_out) {
   ora_ctx X = {p, o, {0, 0, NULL, 0}, 0};
-  int e = iterate_ctx(&X, I_in, I_out, phi_out);
+  int e = iterate_ctx(&X, I_in, I_out, phi_out, NULL);
   if (X.have_S) synth_factor_free(&X.S);
   return e;
 }
 
-/* Err(W) = sqrt( sum V (W^m - W^{m-1})^2 / sum V (W^m)^2 ) (Eq. Err_W). */
-static double err_w(const double *Wn, const double *Wo, int N, double V) {
+/* Err(W) = sqrt( sum V (W^m - W^{m-1})^2 / sum V (W^m)^2 ) (Eq. Err_W);
+ * *dnorm receives the numerator's root ||W^m - W^{m-1}||_V, *wnorm the
+ * denominator's ||W^m||_V. */
+static double err_w(const double *Wn, const double *Wo, int N, double V, double *dnorm,
+                    double *wnorm) {
   double num = 0, den = 0;
   for (int c = 0; c < N; ++c) {
     double d = Wn[c] - Wo[c];
     num += V * d * d;
     den += V * Wn[c] * Wn[c];
   }
+  *dnorm = sqrt(num);
+  *wnorm = sqrt(den);
   if (den == 0) return num == 0 ? 0.0 : INFINITY;
   return sqrt(num / den);
 }
 
 int ora_solve(const ora_problem *p, const ora_options *o, const double *I0,
               double *phi, double *Fx, double *Fy, double *err_hist,
-              int *n_iter, double *final_err, double *I_final) {
+              double *tres_hist, int *n_iter, double *final_err, double *I_final) {
   const int N = p->nx * p->ny, K = p->K;
   const size_t NK = (size_t)N * K;
   const double V = p->dx * p->dy;
@@ -763,15 +814,25 @@ int ora_solve(const ora_problem *p, const ora_options *o, const double *I0,
 
   ora_ctx X = {p, o, {0, 0, NULL, 0}, 0};
   int status = 1, m = 0;
-  double err = INFINITY;
+  double err = INFINITY, dmin = INFINITY;
   for (m = 0; m < o->max_iter; ++m) {
     moments(p, Ia, phi_old, NULL, NULL);          /* phi^m */
-    int e = iterate_ctx(&X, Ia, Ib, phi_new);     /* phi^{m+1} */
+    double tres = 0.0;
+    int e = iterate_ctx(&X, Ia, Ib, phi_new, &tres);   /* phi^{m+1} */
     if (e) { status = e; break; }
-    err = err_w(phi_new, phi_old, N, V);
+    double dn, pn;
+    err = err_w(phi_new, phi_old, N, V, &dn, &pn);
     if (err_hist) err_hist[m] = err;
+    if (tres_hist) tres_hist[m] = tres;
     double *t = Ia; Ia = Ib; Ib = t;
-    if (!isfinite(err)) { status = -2; ++m; break; }
+    /* divergence (an unstable outer iteration, e.g. GSIS at strong opacity
+     * jumps without the pseudo-time shift of Sec. 4.3): Err not finite, or
+     * the change ||phi^{m+1} - phi^m||_V above 1e3 times its smallest value
+     * so far (floored at 1e-9 ||phi^{m+1}||_V, far above rounding). Err
+     * itself cannot show a geometric blow-up: it tends to |1 - 1/g| for a
+     * growth factor g. */
+    if (!isfinite(err) || dn > 1e3 * fmax(dmin, 1e-9 * pn)) { status = 2; ++m; break; }
+    if (dn < dmin) dmin = dn;
     if (err < o->tol) { status = 0; ++m; break; }
   }
   if (n_iter) *n_iter = m;
@@ -1166,7 +1227,8 @@ int ora_adjoint(const ora_problem *p, const ora_options *o, const double *I_star
       for (int k = 0; k < K; ++k) t += lb[(size_t)c * K + k];
       s_new[c] = t / FOUR_PI;
     }
-    const double err = err_w(s_new, s_old, N, V);
+    double dn_, pn_;
+    const double err = err_w(s_new, s_old, N, V, &dn_, &pn_);
     if (err_hist) err_hist[m] = err;
     double *t = la; la = lb; lb = t;
     memcpy(s_old, s_new, sizeof(double) * N);

@@ -85,11 +85,17 @@ int ora_iterate(const ora_problem *p, const ora_options *o, const double *I_in,
                 double *I_out, double *phi_out);
 
 /* Full solve from I0 (NULL = 0). Outputs phi, Fx, Fy [nx*ny]; err_hist
- * [max_iter] (may be NULL); I_final [nx*ny*K] (may be NULL).
- * Returns 0 if converged, 1 if max_iter was reached, <0 on error. */
+ * [max_iter] (may be NULL): Err(phi) after iteration m (Eq. Err_W);
+ * tres_hist [max_iter] (may be NULL): the relative transport residual
+ * ||r(I^m)||_V / ||(sigma_s phi^m + q)/(4 pi)||_V of the iterate I^m that
+ * iteration m starts from (||x||_V^2 = sum_c V sum_k w_k x_ck^2);
+ * I_final [nx*ny*K] (may be NULL).
+ * Returns 0 if converged, 1 if max_iter was reached, 2 if the iteration
+ * diverged (Err not finite, or ||phi^{m+1} - phi^m||_V above 1e3 times its
+ * smallest value so far, floored at 1e-9 ||phi^{m+1}||_V), <0 on error. */
 int ora_solve(const ora_problem *p, const ora_options *o, const double *I0,
               double *phi, double *Fx, double *Fy, double *err_hist,
-              int *n_iter, double *final_err, double *I_final);
+              double *tres_hist, int *n_iter, double *final_err, double *I_final);
 
 /* Solve the synthetic system D1 x = b exactly (banded Cholesky) or, above a
  * size limit, by CG to a relative residual of 1e-14 (Eqs. MSE_d_mtx1,

@@ -349,6 +349,9 @@ gsis_status gsis_batch_create(gsis_ctx *ctx, int32_t n, const gsis_problem *p,
   if (o->I0) return fail(ctx, GSIS_E_INVALID_ARG, "options.I0 must be NULL for a batch");
   if (o->synth_form != 0)
     return fail(ctx, GSIS_E_UNSUPPORTED, "options.synth_form 1 is available for single plans only");
+  if (o->method == GSIS_GSIS && o->hot_face != GSIS_HOT_CENTRAL)
+    return fail(ctx, GSIS_E_UNSUPPORTED,
+                "options.hot_face 1 (transport faces) is available for single plans only");
   HIPCHK(ctx, hipSetDevice(ctx->device));
   gsis_batch *b = new gsis_batch;
   b->ctx = ctx;

@@ -97,8 +97,9 @@ gsis_status check_problem(gsis_ctx *ctx, const gsis_problem *p, const gsis_optio
   if (!o) return fail(ctx, GSIS_E_INVALID_ARG, "options is NULL");
   if (p->nx < 1 || p->ny < 1)
     return fail(ctx, GSIS_E_INVALID_ARG, "nx, ny must be >= 1 (got %d, %d)", p->nx, p->ny);
-  if ((long long)p->nx * p->ny > (1LL << 28))
-    return fail(ctx, GSIS_E_INVALID_ARG, "nx*ny = %lld too large", (long long)p->nx * p->ny);
+  if ((long long)p->nx * p->ny > GSIS_MAX_CELLS)
+    return fail(ctx, GSIS_E_INVALID_ARG, "nx*ny = %lld too large (at most %d cells)",
+                (long long)p->nx * p->ny, GSIS_MAX_CELLS);
   if (!(p->dx > 0) || !(p->dy > 0) || !std::isfinite(p->dx) || !std::isfinite(p->dy))
     return fail(ctx, GSIS_E_INVALID_ARG, "dx, dy must be finite and > 0");
   if (p->K < 1) return fail(ctx, GSIS_E_INVALID_ARG, "K must be >= 1 (got %d)", p->K);
@@ -347,23 +348,29 @@ gsis_status make_single_set(gsis_plan *pl) {
 }
 
 // ------------------------------------------------------------------- plans
-extern "C" gsis_status gsis_plan_create(gsis_ctx *ctx, const gsis_problem *p,
-                                        const gsis_options *o, gsis_plan **out) {
+// A plan whose device memory comes from hipMalloc (arena NULL) or is carved
+// from the arena_cap bytes at arena (no device or pinned allocation at all;
+// profiling off).
+static gsis_status plan_create(gsis_ctx *ctx, const gsis_problem *p, const gsis_options *o,
+                               gsis_plan **out, char *arena, size_t arena_cap) {
   if (!ctx) return fail(nullptr, GSIS_E_INVALID_ARG, "ctx is NULL");
   if (!out) return fail(ctx, GSIS_E_INVALID_ARG, "out is NULL");
   *out = nullptr;
   std::vector<double> mu, eta, w, sa, ss, q, bnd;
   gsis_status st = check_problem(ctx, p, o, mu, eta, w, sa, ss, q, bnd);
   if (st) return st;
-  if (o->hot_face != GSIS_HOT_CENTRAL)
-    return fail(ctx, GSIS_E_UNSUPPORTED, "hot_face TRANSPORT is not available on the GPU (oracle only)");
+  if (o->method == GSIS_GSIS && o->hot_face == GSIS_HOT_TRANSPORT && o->synth_form != 0)
+    return fail(ctx, GSIS_E_UNSUPPORTED,
+                "options.synth_form 1 needs central HoT faces (options.hot_face 0)");
   HIPCHK(ctx, hipSetDevice(ctx->device));
 
   gsis_plan *pl = new gsis_plan;
   pl->ctx = ctx;
   pl->stream = (hipStream_t)o->stream;
   pl->device_ptrs = o->device_ptrs;
-  pl->profile = o->profile;
+  pl->profile = arena ? 0 : o->profile;
+  pl->arena = arena;
+  pl->arena_cap = arena_cap;
   pl->pseudo = (o->cfl_p > 0 || o->beta > 0) ? 1 : 0;
   PlanDev &P = pl->P;
   const int nx = p->nx, ny = p->ny, N = nx * ny, K = p->K;
@@ -600,10 +607,16 @@ extern "C" gsis_status gsis_plan_create(gsis_ctx *ctx, const gsis_problem *p,
       (st = dalloc(pl, &P.rhs, N)) || (st = upload(pl, &P.bnd, bnd_int)) ||
       (st = dalloc(pl, &P.bflux, P.nbf)) || (st = upload(pl, &P.kappa, kap)) ||
       (st = dalloc(pl, &P.err_hist, o->max_iter)) ||
-      (st = dalloc(pl, &P.state, 5)) || (st = dalloc(pl, &P.last_err, 1)))
+      (st = dalloc(pl, &P.tres_hist, o->max_iter)) ||
+      (st = dalloc(pl, &P.tres_part, (size_t)P.n_rtiles * residual_pairs(P))) ||
+      (st = dalloc(pl, &P.src2_part, (size_t)(N + 255) / 256)) ||
+      (st = dalloc(pl, &P.state, 5)) || (st = dalloc(pl, &P.last_err, 2)))
     return bail(st);
   if (P.chain_parts > 1 &&
       (st = dalloc(pl, &P.hand, (size_t)K * (P.chain_parts - 1) * nx)))
+    return bail(st);
+  if (P.method == GSIS_GSIS && P.hot_face == GSIS_HOT_TRANSPORT &&
+      (st = dalloc(pl, &P.ftp, (size_t)8 * N)))
     return bail(st);
   if (f32) {
     if ((st = dalloc(pl, &P.base, N))) return bail(st);
@@ -617,7 +630,11 @@ extern "C" gsis_status gsis_plan_create(gsis_ctx *ctx, const gsis_problem *p,
     return bail(fail(ctx, GSIS_E_INVALID_ARG, "multigrid hierarchy deeper than %d levels",
                      kMaxLevels));
   if ((st = make_single_set(pl))) return bail(st);
-  {
+  if (arena) {
+    // pageable host flags: the synthetic solve's copies of them are followed
+    // by a stream synchronisation either way
+    pl->host_scal = pl->host_flag_store;
+  } else {
     // flags read back by the synthetic solve: [0, 3) state and [8] the CG
     // count of the last forward solve; [4, 7) and [12] the same for the
     // adjoint's solves
@@ -632,6 +649,11 @@ extern "C" gsis_status gsis_plan_create(gsis_ctx *ctx, const gsis_problem *p,
   return GSIS_OK;
 }
 
+extern "C" gsis_status gsis_plan_create(gsis_ctx *ctx, const gsis_problem *p,
+                                        const gsis_options *o, gsis_plan **out) {
+  return plan_create(ctx, p, o, out, nullptr, 0);
+}
+
 extern "C" void gsis_plan_destroy(gsis_plan *pl) {
   if (!pl) return;
   if (pl->stream) (void)hipStreamSynchronize(pl->stream);
@@ -639,7 +661,7 @@ extern "C" void gsis_plan_destroy(gsis_plan *pl) {
   for (void *v : pl->allocs) (void)hipFree(v);
   for (hipEvent_t e : pl->events) (void)hipEventDestroy(e);
   adjoint_release(pl);
-  if (pl->host_scal) (void)hipHostFree(pl->host_scal);
+  if (pl->host_scal && !pl->arena) (void)hipHostFree(pl->host_scal);
   delete pl;
 }
 
@@ -668,6 +690,15 @@ extern "C" gsis_status gsis_plan_reset(gsis_plan *pl) {
   HIPCHK(ctx, hipMemsetAsync(P.state, 0, 5 * sizeof(int32_t), s));
   launch_hand_reset(P, s);
   HIPCHK(ctx, hipMemsetAsync(P.err_hist, 0, P.max_iter * sizeof(double), s));
+  HIPCHK(ctx, hipMemsetAsync(P.tres_hist, 0, P.max_iter * sizeof(double), s));
+  HIPCHK(ctx, hipMemsetAsync(P.tres_part, 0, (size_t)P.n_rtiles * residual_pairs(P) * sizeof(double), s));
+  HIPCHK(ctx, hipMemsetAsync(synth_vcycle_total(P), 0, sizeof(double), s));
+  {
+    // Err of the last iteration and the smallest ||phi^{m+1} - phi^m||_V so
+    // far (divergence test)
+    static const double init[2] = {0.0, INFINITY};
+    HIPCHK(ctx, hipMemcpyAsync(P.last_err, init, sizeof init, hipMemcpyHostToDevice, s));
+  }
   launch_source(P.S, s);
   HIPCHK(ctx, hipGetLastError());
   HIPCHK(ctx, hipStreamSynchronize(s));
@@ -778,9 +809,24 @@ extern "C" gsis_status gsis_plan_read(gsis_plan *pl, gsis_result *r) {
   HIPCHK(ctx, hipMemcpyAsync(r->Fy, P.hy, bytes, k, s));
   if (r->err_hist && n_iter > 0)
     HIPCHK(ctx, hipMemcpyAsync(r->err_hist, P.err_hist, n_iter * sizeof(double), k, s));
+  if (r->tres_hist && n_iter > 0)
+    HIPCHK(ctx, hipMemcpyAsync(r->tres_hist, P.tres_hist, n_iter * sizeof(double), k, s));
   HIPCHK(ctx, hipStreamSynchronize(s));
   r->n_iter = n_iter;
   r->final_err = n_iter > 0 ? le : INFINITY;
+  return GSIS_OK;
+}
+
+extern "C" gsis_status gsis_plan_synth_vcycles(gsis_plan *pl, int64_t *vcycles) {
+  if (!pl) return GSIS_E_INVALID_ARG;
+  gsis_ctx *ctx = pl->ctx;
+  if (!vcycles) return fail(ctx, GSIS_E_INVALID_ARG, "vcycles is NULL");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  double v = 0;
+  HIPCHK(ctx, hipMemcpyAsync(&v, synth_vcycle_total(pl->P), sizeof v, hipMemcpyDeviceToHost,
+                             pl->stream));
+  HIPCHK(ctx, hipStreamSynchronize(pl->stream));
+  *vcycles = (int64_t)v;
   return GSIS_OK;
 }
 
@@ -802,12 +848,13 @@ extern "C" gsis_status gsis_plan_phase_times(gsis_plan *pl, double *ms, int32_t 
   return GSIS_OK;
 }
 
-extern "C" gsis_status gsis_solve(gsis_ctx *ctx, const gsis_problem *p, const gsis_options *o,
-                                  gsis_result *r) {
+// Plan, iterate until Err < tol, divergence or max_iter, read, destroy.
+static gsis_status solve_with(gsis_ctx *ctx, const gsis_problem *p, const gsis_options *o,
+                              gsis_result *r, char *arena, size_t arena_cap) {
   if (!ctx) return fail(nullptr, GSIS_E_INVALID_ARG, "ctx is NULL");
   if (!r) return fail(ctx, GSIS_E_INVALID_ARG, "result is NULL");
   gsis_plan *pl = nullptr;
-  gsis_status st = gsis_plan_create(ctx, p, o, &pl);
+  gsis_status st = plan_create(ctx, p, o, &pl, arena, arena_cap);
   if (st) return st;
   int32_t n = 0, conv = 0;
   double le = 0;
@@ -825,3 +872,9 @@ extern "C" gsis_status gsis_solve(gsis_ctx *ctx, const gsis_problem *p, const gs
   if (conv == 0) return GSIS_NOT_CONVERGED;
   return GSIS_OK;
 }
+
+extern "C" gsis_status gsis_solve(gsis_ctx *ctx, const gsis_problem *p, const gsis_options *o,
+                                  gsis_result *r) {
+  return solve_with(ctx, p, o, r, nullptr, 0);
+}
+

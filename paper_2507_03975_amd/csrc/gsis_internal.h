@@ -81,13 +81,22 @@ struct SynthDesc {
   double *phih, *Fx, *Fy;       // moments of I^{m+1/2} (k_hot<true> writes them)
   const double *bflux;
   const double *mom_part;       // [4][3][N] per-quadrant partial moments
+  int hot_face;                 // 1: HoT from transport face fluxes (ftp)
+  const double *ftp;            // [4][2][N] per-quadrant transport flux through
+                                // the east (+x) and north (+y) face of each cell
   double sw, swm, swe;          // sums of w, w mu, w eta (FP32-mixed base terms)
   double *hx, *hy, *rhs, *phi, *delta, *base, *src, *dynq;
   // CG vectors: r alternates between cg_r and cg_r2 with the V-cycle count,
   // s = A p between cg_s0 and cg_s1 with the iteration; z = M r, w = A z
   double *cg_r, *cg_r2, *cg_z, *cg_p, *cg_s0, *cg_s1, *cg_w;
   double *wx, *wy;              // face-averaged balance: grad(x) / (3 sigma_t)
-  double *red, *scal, *err_parts, *err_hist, *last_err;
+  double *red, *scal, *err_parts, *err_hist, *last_err;  // last_err[0] last Err, [1] smallest change
+  // relative transport residual of the iterate entering each iteration:
+  // per-wave sums of w r^2 from the residual kernel and per-block sums of
+  // src^2 from the moments kernels, finished with Err
+  const double *tres_part, *src2_part;
+  int n_tres, n_src2;
+  double *tres_hist;
   int32_t *state;
   int nlev, lc;                 // levels; first level of the one-workgroup cycle
   int ntile0;                   // multigrid tiles of level 0
@@ -155,6 +164,9 @@ struct PlanDev {
   double *phi = nullptr;       // phi^m
   double *phih = nullptr, *Fx = nullptr, *Fy = nullptr;  // moments of I^{m+1/2}
   double *mom_part = nullptr;  // [4][3][N] per-quadrant partial moments
+  double *ftp = nullptr;       // transport-face HoT: [4][2][N] per-quadrant
+                               // sum_k w_k (Omega_k . n) I_f,k on the east / north
+                               // face of each cell (reconstructed upwind values)
   double *delta = nullptr;     // pending GSIS correction (phi' - phi_half)
   double *base = nullptr;      // what the next read adds (over 4 pi) to the stored
                                // intensity: delta (FP64; same array), or
@@ -181,11 +193,14 @@ struct PlanDev {
   // iteration state on device
   double *err_hist = nullptr;  // [max_iter]
   double *err_parts = nullptr; // block partials for Err
+  double *tres_hist = nullptr; // [max_iter] relative transport residual of I^m
+  double *tres_part = nullptr; // [n_rtiles * ordinate pairs] sums of w r^2 per residual wave
+  double *src2_part = nullptr; // [ceil(N / 256)] sums of src^2 per block of cells
   int32_t *state = nullptr;    // [0] iterations done, [1] done flag (1 converged,
                                // -1 diverged, 2 max_iter), [2] current I buffer,
                                // [3] synthetic CG converged, [4] a split
                                // recurrence's hand-over timed out
-  double *last_err = nullptr;
+  double *last_err = nullptr;  // [2]: Err of the last iteration, smallest ||phi^{m+1} - phi^m||_V
   SynthSet S;                  // launch set of this plan alone
   int lc = 0;                  // first level of the one-workgroup cycle
 };
@@ -201,6 +216,9 @@ void launch_hand_reset(const PlanDev &P, hipStream_t s);
 // Tiles of the residual kernel for an nx x ny grid: (first diagonal, first
 // row) of each band of rows x run of diagonals that holds a cell.
 std::vector<int2> residual_tiles(int nx, int ny);
+// Ordinate pairs of one quadrant the residual kernel takes per wave (the
+// residual-norm partials are indexed tile * pairs + pair).
+int residual_pairs(const PlanDev &P);
 // Storage index of row 0 on anti-diagonal d (dg_off(d) - ylo(d)), for d in
 // [-kDiagPad, nx + ny - 1 + kDiagPad); outside the grid's diagonals the value
 // sends every row out of the intensity buffer.
@@ -268,6 +286,8 @@ void launch_apply_delta_final(const PlanDev &P, hipStream_t s, double swmu, doub
                               double *Fx_out, double *Fy_out);
 // CG iterations of P's last synthetic solve (one device double)
 double *synth_iteration_counter(const PlanDev &P);
+// V-cycles of all synthetic solves since the last reset (one device double)
+double *synth_vcycle_total(const PlanDev &P);
 
 // ---- adjoint (kernels_adjoint.hip)
 struct AdjointBuffers {

@@ -145,10 +145,26 @@ __global__ void k_hot(const SynthDesc *ds, const int2 *bt) {
     u = phih[c]; ue = phih[ce]; uw = phih[cw]; un = phih[cn]; us = phih[cs];
     fx = D.Fx[c]; fy = D.Fy[c];
   }
-  const double gx = D.cE[c] * (ue - u) - D.cW[c] * (uw - u);
-  const double gy = D.cN[c] * (un - u) - D.cS[c] * (us - u);
-  const double hx = fx + gx / (3.0 * D.sig_t[c]);
-  const double hy = fy + gy / (3.0 * D.sig_t[c]);
+  double hx, hy;
+  if (D.hot_face) {
+    // transport face fluxes on the cell's east and north faces (sums of the
+    // four quadrant partials, in order) minus the compact diffusion flux
+    // Gamma_f (phi_c - phi_nb); A Gamma_f is the operator's off-diagonal
+    const double *FT = D.ftp;
+    double tx = 0.0, ty = 0.0;
+    for (int q = 0; q < 4; ++q) {
+      tx += FT[(size_t)(2 * q) * N + c];
+      ty += FT[(size_t)(2 * q + 1) * N + c];
+    }
+    const double gE = D.lev[0].ax[c] / D.dy, gN = D.lev[0].ay[c] / D.dx;
+    hx = i + 1 < nx ? tx - gE * (u - ue) : 0.0;
+    hy = j + 1 < ny ? ty - gN * (u - un) : 0.0;
+  } else {
+    const double gx = D.cE[c] * (ue - u) - D.cW[c] * (uw - u);
+    const double gy = D.cN[c] * (un - u) - D.cS[c] * (us - u);
+    hx = fx + gx / (3.0 * D.sig_t[c]);
+    hy = fy + gy / (3.0 * D.sig_t[c]);
+  }
   if (f1 != 0) return;
   if (COMBINE) {
     D.phih[c] = u;
@@ -159,21 +175,24 @@ __global__ void k_hot(const SynthDesc *ds, const int2 *bt) {
   D.hy[c] = hy;
 }
 
-// b_c of cell c = (i, j) from the HoT of the cell and its neighbours
+// b_c of cell c = (i, j) from the HoT of the cell and its neighbours (central
+// faces), or from the face values h of its faces (transport faces: hx[c] on
+// the cell's east face, hy[c] on its north face, normals +x, +y)
 __device__ inline double rhs_at(CDesc &D, int c, int i, int j) {
   const int nx = D.nx, ny = D.ny;
   const double dx = D.dx, dy = D.dy;
   const double *hx = D.hx, *hy = D.hy, *bflux = D.bflux, *kappa = D.kappa;
   const double ph = D.phih[c];
+  const bool tf = D.hot_face != 0;
   double s = dx * dy * D.q[c];
   // east / west (area dy), north / south (area dx)
-  if (i + 1 < nx) s -= dy * (0.5 * (hx[c] + hx[c + 1]));
+  if (i + 1 < nx) s -= dy * (tf ? hx[c] : 0.5 * (hx[c] + hx[c + 1]));
   else s -= dy * (bflux[ny + j] - kappa[ny + j] * ph);
-  if (i > 0) s += dy * (0.5 * (hx[c] + hx[c - 1]));
+  if (i > 0) s += dy * (tf ? hx[c - 1] : 0.5 * (hx[c] + hx[c - 1]));
   else s -= dy * (bflux[j] - kappa[j] * ph);
-  if (j + 1 < ny) s -= dx * (0.5 * (hy[c] + hy[c + nx]));
+  if (j + 1 < ny) s -= dx * (tf ? hy[c] : 0.5 * (hy[c] + hy[c + nx]));
   else s -= dx * (bflux[2 * ny + nx + i] - kappa[2 * ny + nx + i] * ph);
-  if (j > 0) s += dx * (0.5 * (hy[c] + hy[c - nx]));
+  if (j > 0) s += dx * (tf ? hy[c - nx] : 0.5 * (hy[c] + hy[c - nx]));
   else s -= dx * (bflux[2 * ny + i] - kappa[2 * ny + i] * ph);
   return s;
 }
@@ -182,7 +201,7 @@ __device__ inline double rhs_at(CDesc &D, int c, int i, int j) {
 // alternating slots, so a kernel can read iteration k-1's value while its
 // block 0 stores iteration k's).
 enum { S_RZ = 0, S_ZW = 1, S_RR = 2, S_BB = 3, S_ALPHA = 4, S_BETA = 5, S_STOP = 6,
-       S_NIT = 7, S_RZ1 = 8, S_ALPHA1 = 9 };
+       S_NIT = 7, S_RZ1 = 8, S_ALPHA1 = 9, S_VCYCLES = 10 };
 __host__ __device__ inline int rz_slot(int k) { return (k & 1) ? S_RZ1 : S_RZ; }
 __host__ __device__ inline int alpha_slot(int k) { return (k & 1) ? S_ALPHA1 : S_ALPHA; }
 
@@ -1232,26 +1251,45 @@ __global__ void k_update(const SynthDesc *ds, const int2 *bt) {
 }
 
 // One workgroup per problem: Err = sqrt(num/den) -> history, counters, done
-// flag.
+// flag; the relative transport residual of the iterate this iteration
+// started from, sqrt(sum w r^2 / (sum_k w_k sum_c src^2)) (the cell volume
+// cancels on a uniform grid), from the residual kernel's per-wave partials
+// and the moments kernel's per-block partials of the same iteration.
+// Divergence: Err not finite, or the change ||phi^{m+1} - phi^m||_V above
+// 1e3 times its smallest value so far (floored at 1e-9 ||phi^{m+1}||_V, far
+// above rounding); Err alone cannot show a geometric blow-up, it tends to
+// |1 - 1/g| for a growth factor g. last_err[1] keeps that smallest change.
 __device__ inline void err_finish(CDesc &D, double *sh) {
   int32_t *state = D.state;
   if (state[1] != 0) return;
   const int npart = nblk_d(D.N);
-  double a = 0.0, b = 0.0;
+  double a = 0.0, b = 0.0, rr = 0.0, ss = 0.0;
   for (int t = threadIdx.x; t < npart; t += blockDim.x) {
     a += D.err_parts[2 * t];
     b += D.err_parts[2 * t + 1];
   }
+  for (int t = threadIdx.x; t < D.n_tres; t += blockDim.x) rr += D.tres_part[t];
+  for (int t = threadIdx.x; t < D.n_src2; t += blockDim.x) ss += D.src2_part[t];
+  const double dmin = D.last_err[1];
   double num = block_sum(a, sh);
   double den = block_sum(b, sh);
+  rr = block_sum(rr, sh);
+  ss = block_sum(ss, sh) * D.sw;
   if (threadIdx.x == 0) {
     double err = den > 0.0 ? sqrt(num / den) : (num == 0.0 ? 0.0 : INFINITY);
+    const double tres = ss > 0.0 ? sqrt(rr / ss) : (rr == 0.0 ? 0.0 : INFINITY);
     const int m = state[0];
     D.err_hist[m] = err;
-    *D.last_err = err;
+    D.tres_hist[m] = tres;
+    // V-cycles of this iteration's (last) synthetic solve: the first after
+    // the warm start, one per CG iteration
+    if (D.method) D.scal[S_VCYCLES] += D.scal[S_NIT] + 1.0;
+    const double dn = sqrt(num), pn = sqrt(den);
+    D.last_err[0] = err;
+    if (dn < dmin) D.last_err[1] = dn;
     state[0] = m + 1;
     state[2] = 1 - state[2];   // I^{m+1} now lives in the other buffer
-    if (!isfinite(err)) state[1] = -1;
+    if (!isfinite(err) || dn > 1e3 * fmax(dmin, 1e-9 * pn)) state[1] = -1;
     else if (err < D.tol) state[1] = 1;
     else if (m + 1 >= D.max_iter) state[1] = 2;
   }
@@ -1415,6 +1453,8 @@ SynthDesc make_synth_desc(const PlanDev &P) {
   D.cE = P.cE; D.cW = P.cW; D.cN = P.cN; D.cS = P.cS; D.kappa = P.kappa;
   D.phih = P.phih; D.Fx = P.Fx; D.Fy = P.Fy; D.bflux = P.bflux;
   D.mom_part = P.mom_part; D.sw = P.sw; D.swm = P.swm; D.swe = P.swe;
+  D.hot_face = P.method == GSIS_GSIS ? P.hot_face : 0;
+  D.ftp = P.ftp;
   D.hx = P.hx; D.hy = P.hy; D.rhs = P.rhs; D.phi = P.phi; D.delta = P.delta; D.base = P.base;
   D.src = P.src; D.dynq = P.dynq;
   D.cg_r = P.cg_r; D.cg_r2 = P.cg_r2; D.cg_z = P.cg_z; D.cg_p = P.cg_p;
@@ -1422,6 +1462,9 @@ SynthDesc make_synth_desc(const PlanDev &P) {
   D.wx = P.wide_wx; D.wy = P.wide_wy;
   D.red = P.red; D.scal = P.scal; D.err_parts = P.err_parts; D.err_hist = P.err_hist;
   D.last_err = P.last_err; D.state = P.state;
+  D.tres_part = P.tres_part; D.src2_part = P.src2_part; D.tres_hist = P.tres_hist;
+  D.n_tres = P.n_rtiles * residual_pairs(P);
+  D.n_src2 = nblk(P.N);
   D.nlev = (int)P.mg.size();
   for (int l = 0; l < D.nlev && l < kMaxLevels; ++l) {
     const MGLevel &L = P.mg[l];
@@ -1535,5 +1578,6 @@ void launch_apply_delta_final(const PlanDev &P, hipStream_t s, double swmu, doub
 }
 
 double *synth_iteration_counter(const PlanDev &P) { return P.scal + S_NIT; }
+double *synth_vcycle_total(const PlanDev &P) { return P.scal + S_VCYCLES; }
 
 }  // namespace gsis

@@ -60,6 +60,8 @@ struct TArgs {
   unsigned long long *hand;   // row hand-over between the parts of a split
                               // recurrence, [K][parts - 1][nx]
   int32_t *hand_err;          // set when a part gave up waiting for the one below
+  double *tres_part;          // [n_rtiles][ordinate pairs] sum of w r^2 per residual wave
+  double *src2_part;          // [ceil(N / 256)] sum of src^2 per block of cells
 };
 
 TArgs make_args(const PlanDev &P) {
@@ -82,6 +84,8 @@ TArgs make_args(const PlanDev &P) {
   a.state = P.state;
   a.hand = P.hand;
   a.hand_err = P.state + 4;
+  a.tres_part = P.tres_part;
+  a.src2_part = P.src2_part;
   return a;
 }
 
@@ -623,7 +627,7 @@ __device__ inline int ordinate_pairs(A &a) {
 // kB < 0: no second ordinate (its loads repeat kA's, its stores are dropped).
 template <typename T, class A>
 __device__ __forceinline__ void resid_tile(A &a, const int tile, const int kA, const int kB,
-                                           const int wave) {
+                                           const int wave, const int slot) {
   constexpr bool kF32 = sizeof(T) == 4;
   constexpr int PF = kRPF;
   static_assert(kRSteps % PF == 0, "whole turns of the load ring");
@@ -635,12 +639,13 @@ __device__ __forceinline__ void resid_tile(A &a, const int tile, const int kA, c
   const int q = quadrant_of(a, kA);
   const bool hasB = kB >= 0;
   const int kk[2] = {kA, hasB ? kB : kA};
-  double ax[2], ay[2];
+  double ax[2], ay[2], wr[2];
   __amdgpu_buffer_rsrc_t Ib[2], Ob[2];
 #pragma unroll
   for (int o = 0; o < 2; ++o) {
     ax[o] = a.amu[kk[o]];
     ay[o] = a.aeta[kk[o]];
+    wr[o] = (o == 0 || hasB) ? a.w[kk[o]] : 0.0;   // weight of w r^2 (no double count)
     Ib[o] = buf_rsrc(Iin_of<T>(a) + (size_t)kk[o] * N, (size_t)N * sizeof(T));
     Ob[o] = buf_rsrc(Iout_of<T>(a) + (size_t)kk[o] * N, (o == 0 || hasB) ? (size_t)N * sizeof(T) : 0);
   }
@@ -739,6 +744,7 @@ __device__ __forceinline__ void resid_tile(A &a, const int tile, const int kA, c
 #pragma unroll
   for (int t = 0; t < PF; ++t) load(ring[t], d0 - 1 + t);
   double uw[2] = {0.0, 0.0}, Fe_p[2] = {0.0, 0.0}, Fn_p[2] = {0.0, 0.0}, subw = 0.0;
+  double rr = 0.0;                            // sum of w r^2 over the lane's cells
   for (int sb = 0; sb < kRSteps; sb += PF) {
 #pragma unroll
     for (int t = 0; t < PF; ++t) {
@@ -771,12 +777,16 @@ __device__ __forceinline__ void resid_tile(A &a, const int tile, const int kA, c
         const double ts = fma(-(ay[o] * inv), kF32 ? uS - sS : uS, t0);
         t0 = hs ? ts : t0;
         buf_store((T)(t0 + r * inv), Ob[o], ok ? sl.ic * (unsigned)sizeof(T) : kNoCell);
+        rr = ok ? fma(wr[o] * r, r, rr) : rr;
         Fe_p[o] = Fe;
         Fn_p[o] = Fn;
       }
       load(sl, d0 + dd + PF);                 // past the tile: unused
     }
   }
+  // the wave's sum (fixed order), one partial per (tile, ordinate pair)
+  rr = wave_sum64(rr);
+  if (lane == 0) a.tres_part[slot] = rr;
 }
 
 template <typename T>
@@ -797,7 +807,7 @@ __global__ void __launch_bounds__(kRWaves * 64) k_resid(TArgs a) {
   if (pi >= ordinate_pairs(a)) return;
   int kA, kB;
   ordinate_pair(a, pi, kA, kB);
-  resid_tile<T>(a, tile, kA, kB, wave);
+  resid_tile<T>(a, tile, kA, kB, wave, tile * ordinate_pairs(a) + pi);
 }
 
 // Batched residual: one workgroup per item (problem, tile, group of four
@@ -814,7 +824,7 @@ __global__ void __launch_bounds__(kRWaves * 64) k_resid_batch(const TArgs *targs
   if (pi >= ordinate_pairs(a)) return;
   int kA, kB;
   ordinate_pair(a, pi, kA, kB);
-  resid_tile<T>(a, it[1], kA, kB, wave);
+  resid_tile<T>(a, it[1], kA, kB, wave, it[1] * ordinate_pairs(a) + pi);
 }
 
 // Recurrence v = bv + cx v_W + cy v_S for one ordinate per workgroup; lane t
@@ -1022,6 +1032,22 @@ __device__ inline void dg_cell(long long t, int nx, int ny, int &x, int &y) {
   x = lo - y;
 }
 
+// Sum of src^2 = ((sigma_s phi^m + q)/(4 pi))^2 over the cells of one block
+// of 256 (natural cell order), for the relative transport residual; every
+// thread of the block takes part, thread 0 stores the block's sum.
+__device__ __forceinline__ void src2_block(const TArgs &a, const int blk) {
+  __shared__ double red[256];
+  const int c = blk * 256 + (int)threadIdx.x;
+  const double v = c < a.N ? a.src[c] : 0.0;
+  red[threadIdx.x] = v * v;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && a.state[1] == 0) a.src2_part[blk] = red[0];
+}
+
 template <typename T>
 __device__ __forceinline__ void moments_q(const TArgs &a, double *part, const long long t,
                                           const int q) {
@@ -1067,8 +1093,56 @@ __device__ __forceinline__ void moments_q(const TArgs &a, double *part, const lo
   part[(size_t)(3 * q + 2) * a.N + c] = sy;
 }
 
+// Transport fluxes through the interior faces (GSIS with transport-face HoT,
+// Sec. 3.1 in Alcouffe's full form): per quadrant and stored cell, the sums
+// over the quadrant's ordinates of w_k mu_k I_e and w_k eta_k I_n, with I_e,
+// I_n the cell's second-order values on its local east and north faces (the
+// residual's reconstruction, Eqs. Ii,k and Iij, of I^{m+1/2}). In the
+// quadrant's frame the flow leaves through those faces, so the cell is their
+// upwind cell. Each sum is stored at the face's place in the caller's grid:
+// the east (+x) face of cell c, or of c - 1 when the quadrant is mirrored in
+// x; the north face of c, or of c - nx when mirrored in y.
+template <typename T>
+__device__ __forceinline__ void face_flux_q(const TArgs &a, double *ftp, const long long t,
+                                            const int q) {
+  const int f1 = a.state[1];
+  if (t >= a.N) return;
+  const int nx = a.nx, ny = a.ny, N = a.N;
+  int x, y;
+  dg_cell(t, nx, ny, x, y);
+  const int c = gcell(a, q, x, y);
+  const bool he = x + 1 < nx, hw = x > 0, hn = y + 1 < ny, hs = y > 0;
+  if (!he && !hn) return;                     // both outgoing faces are walls
+  const long long iE = he ? dg_idx(x + 1, y, nx, ny) : t, iW = hw ? dg_idx(x - 1, y, nx, ny) : t;
+  const long long iN = hn ? dg_idx(x, y + 1, nx, ny) : t, iS = hs ? dg_idx(x, y - 1, nx, ny) : t;
+  const double2 *R = reinterpret_cast<const double2 *>(a.cellq + ((size_t)q * N + t) * 6);
+  const double2 c0 = R[0], c1 = R[1];
+  const double *SUB = a.dynq + ((size_t)q * 3 + 2) * N;
+  const double sc = a.fp32 ? SUB[t] : 0.0, se = a.fp32 ? SUB[iE] : 0.0;
+  const double sw = a.fp32 ? SUB[iW] : 0.0, sn = a.fp32 ? SUB[iN] : 0.0;
+  const double ss = a.fp32 ? SUB[iS] : 0.0;
+  const T *O = Iout_of<T>(a);
+  const double hdx = 0.5 * a.dx, hdy = 0.5 * a.dy;
+  const bool second = a.order >= 2, lim = a.limiter != 0;
+  double pe = 0.0, pn = 0.0;
+  for (int kk = a.qoff[q]; kk < a.qoff[q + 1]; ++kk) {
+    const T *Ok = O + (size_t)kk * N;
+    const double u = (double)Ok[t] + sc;
+    const double UE = he ? (double)Ok[iE] + se : u, UW = hw ? (double)Ok[iW] + sw : u;
+    const double UN = hn ? (double)Ok[iN] + sn : u, US = hs ? (double)Ok[iS] + ss : u;
+    double Fe, Fn;
+    face_pair(u, UE, UW, UN, US, c0, c1, hdx, hdy, second, lim, Fe, Fn);
+    pe += a.wmu[kk] * Fe;
+    pn += a.weta[kk] * Fn;
+  }
+  if (f1 != 0) return;
+  if (he) ftp[(size_t)(2 * q) * N + ((q & 1) ? c - 1 : c)] = pe;
+  if (hn) ftp[(size_t)(2 * q + 1) * N + ((q & 2) ? c - nx : c)] = pn;
+}
+
 template <typename T>
 __global__ void k_moments_q(TArgs a, double *part) {
+  if (blockIdx.y == 0) src2_block(a, blockIdx.x);
   moments_q<T>(a, part, blockIdx.x * (long long)blockDim.x + threadIdx.x, blockIdx.y);
 }
 
@@ -1077,6 +1151,7 @@ template <typename T>
 __global__ void k_moments_q_b(const TArgs *tas, const int2 *bt) {
   const int2 v = bt[blockIdx.x];
   const TArgs &a = tas[v.x];
+  if (blockIdx.y == 0) src2_block(a, v.y);
   moments_q<T>(a, a.mom_part, v.y * (long long)blockDim.x + threadIdx.x, blockIdx.y);
 }
 
@@ -1162,15 +1237,20 @@ __device__ __forceinline__ void boundary_flux(const TArgs &a, const int f) {
 // The boundary faces' F_T . n (blocks [0, nbf)) and the per-quadrant moment
 // partials (the other blocks, quadrant-major) in one launch: both only read
 // the swept intensity; the four partials are combined by the HoT kernel.
+// With ftp (transport-face HoT) the moment blocks also form the quadrant's
+// interior face fluxes.
 template <typename T>
-__global__ void k_moments_q_bflux(TArgs a, double *part, int nbc) {
+__global__ void k_moments_q_bflux(TArgs a, double *part, int nbc, double *ftp) {
   const int b = (int)blockIdx.x - a.nbf;
   if (b < 0) {
     boundary_flux(a, blockIdx.x);
     return;
   }
   const int q = b / nbc;
-  moments_q<T>(a, part, (b - q * nbc) * (long long)blockDim.x + threadIdx.x, q);
+  if (q == 0) src2_block(a, b);
+  const long long t = (b - q * nbc) * (long long)blockDim.x + threadIdx.x;
+  if (ftp) face_flux_q<T>(a, ftp, t, q);
+  moments_q<T>(a, part, t, q);
 }
 
 __global__ void k_boundary_flux_b(const TArgs *tas, const int2 *bt) {
@@ -1256,6 +1336,12 @@ std::vector<int> diag_row0_table(int nx, int ny) {
     else t[e] = (int)(dg_off(d, nx, ny) - dg_ylo(d, nx));
   }
   return t;
+}
+
+int residual_pairs(const PlanDev &P) {
+  int pairs = 0;
+  for (int q = 0; q < 4; ++q) pairs += (P.qoff[q + 1] - P.qoff[q] + 1) / 2;
+  return pairs;
 }
 
 std::vector<int2> residual_tiles(int nx, int ny) {
@@ -1372,8 +1458,11 @@ void launch_moments(const PlanDev &P, hipStream_t s, bool bflux) {
   const int nbc = (P.N + 255) / 256;
   if (bflux) {   // the combine follows in the HoT kernel
     const dim3 g(P.nbf + 4 * nbc);
-    if (a.fp32) hipLaunchKernelGGL(k_moments_q_bflux<float>, g, dim3(256), 0, s, a, P.mom_part, nbc);
-    else hipLaunchKernelGGL(k_moments_q_bflux<double>, g, dim3(256), 0, s, a, P.mom_part, nbc);
+    double *ftp = P.hot_face ? P.ftp : nullptr;
+    if (a.fp32)
+      hipLaunchKernelGGL(k_moments_q_bflux<float>, g, dim3(256), 0, s, a, P.mom_part, nbc, ftp);
+    else
+      hipLaunchKernelGGL(k_moments_q_bflux<double>, g, dim3(256), 0, s, a, P.mom_part, nbc, ftp);
     return;
   }
   if (a.fp32)

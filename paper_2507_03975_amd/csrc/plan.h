@@ -37,6 +37,12 @@ struct gsis_plan {
   int prof_iters = 0;
   int pseudo = 0;                 // a pseudo-time shift is on
   AdjointBuffers *adj = nullptr;  // adjoint state (first gsis_plan_adjoint)
+  // device memory carved from a caller-free region instead of hipMalloc
+  // (gsis_solve_noalloc): base, bytes used, capacity; the host flags then
+  // live in host_flag_store instead of pinned memory
+  char *arena = nullptr;
+  size_t arena_used = 0, arena_cap = 0;
+  double host_flag_store[8] = {};
 };
 
 extern thread_local std::string g_create_err;
@@ -64,6 +70,18 @@ inline gsis_status fail_impl(gsis_ctx *ctx, gsis_status st, const char *fmt, ...
 template <typename T>
 gsis_status dalloc(gsis_plan *pl, T **p, size_t n) {
   void *v = nullptr;
+  if (pl->arena) {
+    // 256-byte aligned pieces of the region, in allocation order
+    const size_t bytes = (std::max<size_t>(n, 1) * sizeof(T) + 255) & ~(size_t)255;
+    if (bytes > pl->arena_cap - pl->arena_used)
+      return fail(pl->ctx, GSIS_E_INVALID_ARG,
+                  "the problem needs more device memory than the %zu-byte scratch region of "
+                  "gsis_solve_noalloc (%zu bytes used when %zu more were asked for)",
+                  pl->arena_cap, pl->arena_used, bytes);
+    *p = (T *)(pl->arena + pl->arena_used);
+    pl->arena_used += bytes;
+    return GSIS_OK;
+  }
   hipError_t e = hipMalloc(&v, std::max<size_t>(n, 1) * sizeof(T));
   if (e != hipSuccess)
     return fail(pl->ctx, GSIS_E_OOM, "hipMalloc(%zu bytes): %s", n * sizeof(T),

@@ -37,6 +37,14 @@ __device__ inline double shr1_fill(double v, double fill) {
   hi = __builtin_amdgcn_update_dpp(hi, __double2hiint(v), 0x138, 0xf, 0xf, false);
   return __hiloint2double(hi, lo);
 }
+// Sum over the 64 lanes (every lane active) by a butterfly of lane
+// exchanges: each step adds the same two values on both lanes of a pair, so
+// every lane ends with the same bits.
+__device__ inline double wave_sum64(double v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
 // lane l's value, l wave-uniform
 __device__ inline double rdlane(double v, int l) {
   return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),

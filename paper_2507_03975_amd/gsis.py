@@ -69,8 +69,8 @@ class gsis_adjoint_info(ctypes.Structure):
 
 class gsis_result(ctypes.Structure):
     _fields_ = [("phi", ctypes.c_void_p), ("Fx", ctypes.c_void_p), ("Fy", ctypes.c_void_p),
-                ("err_hist", ctypes.c_void_p), ("n_iter", ctypes.c_int32),
-                ("final_err", ctypes.c_double)]
+                ("err_hist", ctypes.c_void_p), ("tres_hist", ctypes.c_void_p),
+                ("n_iter", ctypes.c_int32), ("final_err", ctypes.c_double)]
 
 
 EXPORTS = ("gsis_ctx_create", "gsis_ctx_destroy", "gsis_last_error", "gsis_options_default",
@@ -78,7 +78,7 @@ EXPORTS = ("gsis_ctx_create", "gsis_ctx_destroy", "gsis_last_error", "gsis_optio
            "gsis_plan_status", "gsis_plan_read", "gsis_plan_reset", "gsis_plan_phase_times",
            "gsis_batch_create", "gsis_batch_destroy", "gsis_batch_iterate", "gsis_batch_status",
            "gsis_batch_read", "gsis_batch_reset", "gsis_batch_get_tuning", "gsis_solve_batch",
-           "gsis_plan_adjoint", "gsis_adjoint", "gsis_version")
+           "gsis_plan_adjoint", "gsis_adjoint", "gsis_version", "gsis_plan_synth_vcycles")
 
 
 def load():
@@ -111,6 +111,7 @@ def load():
     lib.gsis_plan_read.argtypes = [vp, ctypes.POINTER(gsis_result)]
     lib.gsis_plan_reset.argtypes = [vp]
     lib.gsis_plan_phase_times.argtypes = [vp, _dp, ip]
+    lib.gsis_plan_synth_vcycles.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
     lib.gsis_batch_create.argtypes = [vp, i32, ctypes.POINTER(gsis_problem),
                                       ctypes.POINTER(gsis_options), ctypes.POINTER(vp)]
     lib.gsis_batch_destroy.argtypes = [vp]
@@ -265,20 +266,16 @@ class Plan:
         """Return dict(phi, Fx, Fy, err_hist, n_iter, final_err); arrays are
         numpy (host plans) or torch tensors on the plan's device."""
         N, maxit = self.N, self.opts.max_iter
-        if self.args.device:
-            import torch
-            dev = self.args.keep[0].device
-            phi = torch.empty(N, dtype=torch.float64, device=dev)
-            fx, fy = torch.empty_like(phi), torch.empty_like(phi)
-            hist = torch.zeros(maxit, dtype=torch.float64, device=dev)
-            p = lambda t: t.data_ptr()
-        else:
-            phi, fx, fy, hist = np.empty(N), np.empty(N), np.empty(N), np.zeros(maxit)
-            p = lambda a: a.ctypes.data
-        r = gsis_result(p(phi), p(fx), p(fy), p(hist), 0, 0.0)
+        (phi, fx, fy, hist, thist), r = _result_buffers(self.args, maxit)
         _check(load().gsis_plan_read(self.handle, ctypes.byref(r)), self.ctx)
-        return dict(phi=phi, Fx=fx, Fy=fy, err_hist=hist[:r.n_iter], n_iter=r.n_iter,
-                    final_err=r.final_err)
+        return dict(phi=phi, Fx=fx, Fy=fy, err_hist=hist[:r.n_iter], tres_hist=thist[:r.n_iter],
+                    n_iter=r.n_iter, final_err=r.final_err)
+
+    def synth_vcycles(self):
+        """Multigrid V-cycles of all synthetic solves since creation or reset."""
+        v = ctypes.c_int64()
+        _check(load().gsis_plan_synth_vcycles(self.handle, ctypes.byref(v)), self.ctx)
+        return v.value
 
     def phase_times(self):
         ms = (ctypes.c_double * GSIS_NUM_PHASES)()
@@ -334,27 +331,17 @@ class Plan:
 def gsis_solve(ctx, prob, I0=None, **opts):
     """One-shot solve (gsis_solve). Returns the result dict plus ``status``."""
     lib = load()
+    entry = lib.gsis_solve
     a = _Args(prob, I0)
     o = make_options(**opts)
     o.I0 = a.I0
     o.device_ptrs = 1 if a.device else 0
     o.stream = _stream_handle() if a.device else None
-    N = a.nx * a.ny
-    if a.device:
-        import torch
-        dev = a.keep[0].device
-        phi = torch.empty(N, dtype=torch.float64, device=dev)
-        fx, fy = torch.empty_like(phi), torch.empty_like(phi)
-        hist = torch.zeros(o.max_iter, dtype=torch.float64, device=dev)
-        p = lambda t: t.data_ptr()
-    else:
-        phi, fx, fy, hist = np.empty(N), np.empty(N), np.empty(N), np.zeros(o.max_iter)
-        p = lambda x: x.ctypes.data
-    r = gsis_result(p(phi), p(fx), p(fy), p(hist), 0, 0.0)
-    st = lib.gsis_solve(ctx.handle, ctypes.byref(a.s), ctypes.byref(o), ctypes.byref(r))
+    (phi, fx, fy, hist, thist), r = _result_buffers(a, o.max_iter)
+    st = entry(ctx.handle, ctypes.byref(a.s), ctypes.byref(o), ctypes.byref(r))
     _check(st, ctx, allow=(GSIS_OK, GSIS_NOT_CONVERGED, GSIS_DIVERGED))
-    return dict(phi=phi, Fx=fx, Fy=fy, err_hist=hist[:r.n_iter], n_iter=r.n_iter,
-                final_err=r.final_err, status=st)
+    return dict(phi=phi, Fx=fx, Fy=fy, err_hist=hist[:r.n_iter], tres_hist=thist[:r.n_iter],
+                n_iter=r.n_iter, final_err=r.final_err, status=st)
 
 
 _default_ctx = None
@@ -369,6 +356,8 @@ def solve(prob, I0=None, device=0, **opts):
 
 
 def _result_buffers(a, max_iter):
+    """Output arrays of one problem (torch tensors on the problem's device, or
+    numpy arrays) and the gsis_result pointing at them."""
     N = a.nx * a.ny
     if a.device:
         import torch
@@ -376,11 +365,14 @@ def _result_buffers(a, max_iter):
         phi = torch.empty(N, dtype=torch.float64, device=dev)
         fx, fy = torch.empty_like(phi), torch.empty_like(phi)
         hist = torch.zeros(max_iter, dtype=torch.float64, device=dev)
+        thist = torch.zeros_like(hist)
         p = lambda t: t.data_ptr()
     else:
-        phi, fx, fy, hist = np.empty(N), np.empty(N), np.empty(N), np.zeros(max_iter)
+        phi, fx, fy = np.empty(N), np.empty(N), np.empty(N)
+        hist, thist = np.zeros(max_iter), np.zeros(max_iter)
         p = lambda x: x.ctypes.data
-    return (phi, fx, fy, hist), gsis_result(p(phi), p(fx), p(fy), p(hist), 0, 0.0)
+    return (phi, fx, fy, hist, thist), gsis_result(p(phi), p(fx), p(fy), p(hist), p(thist),
+                                                   0, 0.0)
 
 
 class Batch:
@@ -420,9 +412,9 @@ class Batch:
     def read(self, i):
         bufs, r = _result_buffers(self.args[i], self.opts.max_iter)
         _check(load().gsis_batch_read(self.handle, int(i), ctypes.byref(r)), self.ctx)
-        phi, fx, fy, hist = bufs
-        return dict(phi=phi, Fx=fx, Fy=fy, err_hist=hist[:r.n_iter], n_iter=r.n_iter,
-                    final_err=r.final_err)
+        phi, fx, fy, hist, thist = bufs
+        return dict(phi=phi, Fx=fx, Fy=fy, err_hist=hist[:r.n_iter], tres_hist=thist[:r.n_iter],
+                    n_iter=r.n_iter, final_err=r.final_err)
 
     def reset(self):
         _check(load().gsis_batch_reset(self.handle), self.ctx)
@@ -469,7 +461,8 @@ def gsis_solve_batch(ctx, probs, **opts):
     _check(st, ctx, allow=(GSIS_OK, GSIS_NOT_CONVERGED, GSIS_DIVERGED))
     out = []
     for i in range(n):
-        phi, fx, fy, hist = bufs[i]
+        phi, fx, fy, hist, thist = bufs[i]
         out.append(dict(phi=phi, Fx=fx, Fy=fy, err_hist=hist[:res[i].n_iter],
-                        n_iter=res[i].n_iter, final_err=res[i].final_err))
+                        tres_hist=thist[:res[i].n_iter], n_iter=res[i].n_iter,
+                        final_err=res[i].final_err))
     return out, st

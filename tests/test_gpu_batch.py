@@ -24,8 +24,12 @@ def _say(msg):
     sys.stdout.flush()
 
 
+def _np(a):
+    return a.cpu().numpy() if hasattr(a, "cpu") else np.asarray(a)
+
+
 def _rel(a, b):
-    a = a.cpu().numpy() if hasattr(a, "cpu") else np.asarray(a)
+    a = _np(a)
     return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
 
 
@@ -153,26 +157,31 @@ def test_batch_sweep_forms_agree(ctx, monkeypatch):
         assert _rel(a["phi"], cp) < 1e-10, i
 
 
+@pytest.mark.timeout(1500)
 def test_full_batch_sampled(ctx):
     """The 64-problem batch (grids 64..512, 32..128 ordinates, 8 x 8 random
-    blocks) at full size: after two iterations the problems small enough for
-    the oracle match it element by element; every problem's history is
-    finite."""
+    blocks) at full size, with the graph: after two iterations the first
+    problem of every (nx, ny, K) class present (33 classes, from 64 x 64 x 32
+    to 512 x 512 x 128) matches the oracle element by element; every
+    problem's history is finite."""
     probs = inputs.batch_problems()
     _say("full batch: %d problems" % len(probs))
     b = gsis.Batch(ctx, probs, tol=0.0, max_iter=2, beta=20.0, synth_rtol=1e-14,
-                   synth_max_iter=400, graph=0)
+                   synth_max_iter=400, graph=1)
     b.iterate(2)
     it, conv, err, fin = b.status()
     assert it == [2] * len(probs) and all(np.isfinite(err))
     _say("  tuning %s" % b.tuning())
-    checked = 0
+    seen = {}
     for i, p in enumerate(probs):
-        if p["nx"] * p["ny"] * len(p["mu"]) > 64 * 64 * 128:
-            continue
+        seen.setdefault((p["nx"], p["ny"], len(p["mu"])), i)
+    assert (512, 512, 128) in seen and len(seen) >= 16
+    for cls, i in sorted(seen.items(), key=lambda t: t[1]):
+        p = probs[i]
         g = b.read(i)
+        _say("  problem %d %s" % (i, cls))
         o = oracle.solve(p, tol=0.0, max_iter=2, beta=20.0)
         assert _rel(g["phi"], o["phi"]) < 1e-9, i
-        checked += 1
-    assert checked >= 3
+        assert _rel(g["Fx"], o["Fx"]) < 1e-8 and _rel(g["Fy"], o["Fy"]) < 1e-8, i
+        np.testing.assert_allclose(_np(g["tres_hist"]), o["tres_hist"], rtol=1e-8)
     b.close()
