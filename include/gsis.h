@@ -189,6 +189,26 @@ typedef struct {
 gsis_status gsis_solve(gsis_ctx *ctx, const gsis_problem *p,
                        const gsis_options *o, gsis_result *r);
 
+/* For callers that cannot allocate device memory (code that must not call
+ * hipMalloc, such as tight serving loops or harnesses that forbid it): the
+ * same solve as gsis_solve, with every piece of device state (intensities,
+ * coefficients, multigrid hierarchy, CG vectors, flags) carved from one
+ * library-owned scratch region of 256 MiB per GPU, a static device array
+ * that each GPU the library runs on holds until the process ends. The call
+ * makes no hipMalloc, hipHostMalloc or hipFree (its host-side set-up uses
+ * ordinary heap memory) and profiling is off. The caller still passes the
+ * problem and result buffers (host or device memory as options.device_ptrs
+ * says). A problem whose state does not fit returns GSIS_E_INVALID_ARG with
+ * a message naming the sizes (about 16 N K + 800 N + 64 K (nx + ny) bytes
+ * for N = nx ny cells and K ordinates in FP64, 8 N K in place of 16 N K in
+ * FP32-mixed: 256 x 256 x 128 in FP64 takes about 190 MB).
+ * Every call on a GPU reuses that GPU's region, which keeps the last call's
+ * contents; each call initialises what it reads. Calls that overlap on one
+ * GPU (two host threads, or two streams) race on the region and must not
+ * be made. */
+gsis_status gsis_solve_noalloc(gsis_ctx *ctx, const gsis_problem *p,
+                               const gsis_options *o, gsis_result *r);
+
 /* Plans: set up once, then enqueue iterations. */
 gsis_status gsis_plan_create(gsis_ctx *ctx, const gsis_problem *p,
                              const gsis_options *o, gsis_plan **out);

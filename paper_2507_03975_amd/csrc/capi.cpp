@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -878,3 +879,44 @@ extern "C" gsis_status gsis_solve(gsis_ctx *ctx, const gsis_problem *p, const gs
   return solve_with(ctx, p, o, r, nullptr, 0);
 }
 
+// ------------------------------------------------------ solve without allocation
+// The device state of gsis_solve_noalloc lives in this file-scope array (one
+// copy per GPU, held until the process ends). In host code its name only
+// stands in for the symbol: the device address of each GPU's copy comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+constexpr size_t kScratchBytes = (size_t)256 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Device address of this device's scratch copy (the context's device is
+// current).
+gsis_status scratch_address(gsis_ctx *ctx, char **out) {
+  if (ctx->device < 0 || ctx->device >= kMaxScratchDevices)
+    return fail(ctx, GSIS_E_UNSUPPORTED, "gsis_solve_noalloc: device %d beyond %d", ctx->device,
+                kMaxScratchDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[ctx->device]) {
+    void *ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(ctx, GSIS_E_DEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_ptr[ctx->device] = ptr;
+  }
+  *out = (char *)g_scratch_ptr[ctx->device];
+  return GSIS_OK;
+}
+}  // namespace
+
+extern "C" gsis_status gsis_solve_noalloc(gsis_ctx *ctx, const gsis_problem *p,
+                                          const gsis_options *o, gsis_result *r) {
+  if (!ctx) return fail(nullptr, GSIS_E_INVALID_ARG, "ctx is NULL");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  char *base = nullptr;
+  gsis_status st = scratch_address(ctx, &base);
+  if (st) return st;
+  return solve_with(ctx, p, o, r, base, kScratchBytes);
+}

@@ -78,7 +78,8 @@ EXPORTS = ("gsis_ctx_create", "gsis_ctx_destroy", "gsis_last_error", "gsis_optio
            "gsis_plan_status", "gsis_plan_read", "gsis_plan_reset", "gsis_plan_phase_times",
            "gsis_batch_create", "gsis_batch_destroy", "gsis_batch_iterate", "gsis_batch_status",
            "gsis_batch_read", "gsis_batch_reset", "gsis_batch_get_tuning", "gsis_solve_batch",
-           "gsis_plan_adjoint", "gsis_adjoint", "gsis_version", "gsis_plan_synth_vcycles")
+           "gsis_plan_adjoint", "gsis_adjoint", "gsis_version", "gsis_solve_noalloc",
+           "gsis_plan_synth_vcycles")
 
 
 def load():
@@ -102,6 +103,7 @@ def load():
     lib.gsis_options_default.argtypes = [ctypes.POINTER(gsis_options)]
     lib.gsis_solve.argtypes = [vp, ctypes.POINTER(gsis_problem), ctypes.POINTER(gsis_options),
                                ctypes.POINTER(gsis_result)]
+    lib.gsis_solve_noalloc.argtypes = lib.gsis_solve.argtypes
     lib.gsis_plan_create.argtypes = [vp, ctypes.POINTER(gsis_problem),
                                      ctypes.POINTER(gsis_options), ctypes.POINTER(vp)]
     lib.gsis_plan_destroy.argtypes = [vp]
@@ -328,10 +330,11 @@ class Plan:
             pass
 
 
-def gsis_solve(ctx, prob, I0=None, **opts):
-    """One-shot solve (gsis_solve). Returns the result dict plus ``status``."""
+def gsis_solve(ctx, prob, I0=None, noalloc=False, **opts):
+    """One-shot solve (gsis_solve, or gsis_solve_noalloc with noalloc=True).
+    Returns the result dict plus ``status``."""
     lib = load()
-    entry = lib.gsis_solve
+    entry = lib.gsis_solve_noalloc if noalloc else lib.gsis_solve
     a = _Args(prob, I0)
     o = make_options(**opts)
     o.I0 = a.I0
