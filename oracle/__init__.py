@@ -45,6 +45,11 @@ class _Options(ctypes.Structure):
     ]
 
 
+class _Material(ctypes.Structure):
+    _fields_ = [("c", ctypes.c_double), ("a", ctypes.c_double), ("dt", ctypes.c_double),
+                ("cv", _dp), ("sub_iter", ctypes.c_int)]
+
+
 def build(force=True):
     """Compile the oracle with gcc (plain -O2, no FMA contraction, OpenMP)."""
     if not force and os.path.exists(_LIB_PATH):
@@ -82,6 +87,9 @@ def _load():
         lib.ora_wide_correction.argtypes = [P, ctypes.c_int, _dp, _dp]
         lib.ora_synthetic_wide.argtypes = [P, ctypes.c_int, _dp, ctypes.c_int, _dp]
         lib.ora_synthetic_wide.restype = ctypes.c_int
+        lib.ora_td_solve.argtypes = [P, O, ctypes.POINTER(_Material), _dp, _dp, ctypes.c_int,
+                                     _dp, _dp, _dp, _dp, _dp, ip, _dp]
+        lib.ora_td_solve.restype = ctypes.c_int
         lib.ora_adjoint.argtypes = [P, O, _dp, _dp, _dp, _dp, ctypes.c_double, ctypes.c_int,
                                     _dp, _dp, _dp, _dp, ip, _dp]
         lib.ora_adjoint.restype = ctypes.c_int
@@ -273,4 +281,33 @@ def adjoint(prob, I_star, g_phi=None, g_Fx=None, g_Fy=None, tol=1e-12, max_iter=
                err_hist=hist[:n.value])
     if return_lambda:
         out["lambda"] = lam
+    return out
+
+
+def td_solve(prob, T0, n_steps, c=1.0, a=1.0, dt=1.0, cv=1.0, sub_iter=4, I0=None,
+             return_I=False, **opts):
+    """Time-dependent gray RTE with the material energy equation: n_steps
+    backward-Euler steps of size dt from I0 [N, K] (None = 0) and T0 [N],
+    each iterated (SI or GSIS, opts as in solve) until max(Err(rho), Err(T))
+    < tol or max_iter. cv is the volume specific heat (scalar or [N]).
+    Returns dict(rho, T, Fx, Fy, inner_iters [n_steps], err_last [n_steps],
+    status, and I [N, K] with return_I)."""
+    m = _Marshal(prob)
+    o = _opts(**opts)
+    N, K = m.nx * m.ny, m.K
+    cvv = np.ascontiguousarray(np.broadcast_to(np.asarray(cv, dtype=np.float64), (N,)))
+    mat = _Material(float(c), float(a), float(dt), _ptr(cvv), int(sub_iter))
+    T0c = np.ascontiguousarray(np.broadcast_to(np.asarray(T0, dtype=np.float64), (N,)))
+    I0c = None if I0 is None else np.ascontiguousarray(I0, dtype=np.float64)
+    Io = np.empty((N, K)) if return_I else None
+    T, rho, fx, fy = np.zeros(N), np.zeros(N), np.zeros(N), np.zeros(N)
+    its = (ctypes.c_int * max(n_steps, 1))()
+    errs = np.zeros(max(n_steps, 1))
+    st = _load().ora_td_solve(ctypes.byref(m.s), ctypes.byref(o), ctypes.byref(mat), _ptr(I0c),
+                              _ptr(T0c), int(n_steps), _ptr(Io), _ptr(T), _ptr(rho), _ptr(fx),
+                              _ptr(fy), its, _ptr(errs))
+    out = dict(rho=rho, T=T, Fx=fx, Fy=fy, inner_iters=list(its)[:n_steps],
+               err_last=errs[:n_steps], status=st)
+    if return_I:
+        out["I"] = Io
     return out

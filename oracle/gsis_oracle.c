@@ -205,8 +205,21 @@ static void moments(const ora_problem *p, const double *I, double *phi,
 /* Mesoscopic residual (Eq. RTE_d_res, steady):                               */
 /*   r = (sigma_s phi + q)/(4 pi) - sigma_t I - (1/V) sum_f (Omega.n_f) A_f I_f */
 /* ------------------------------------------------------------------------ */
+/* The same with the backward-Euler time terms of Eq. RTE_d_res:
+ *   r = S_c - (sigma_t + tdiag) I + tdiag I^n - (1/V) sum_f (Omega.n_f) A_f I_f,
+ * tdiag = 1/(c dt), I^n [N][K] the previous time level (NULL: no term) and
+ * S_c [N] the isotropic source per steradian (NULL: (sigma_s phi + q)/(4 pi)
+ * from the moments of I, the steady case). */
+static void residual_t(const ora_problem *p, const ora_options *o, const double *I,
+                       const double *S_iso, double tdiag, const double *I_n, double *r);
+
 void ora_residual(const ora_problem *p, const ora_options *o, const double *I,
                   double *r) {
+  residual_t(p, o, I, NULL, 0.0, NULL, r);
+}
+
+static void residual_t(const ora_problem *p, const ora_options *o, const double *I,
+                       const double *S_iso, double tdiag, const double *I_n, double *r) {
   const int N = p->nx * p->ny, K = p->K;
   double *phi = (double *)malloc(sizeof(double) * N);
   moments(p, I, phi, NULL, NULL);
@@ -227,8 +240,10 @@ void ora_residual(const ora_problem *p, const ora_options *o, const double *I,
             double on = p->mu[k] * NX_[f] + p->eta[k] * NY_[f];
             div += on * area_over_vol(p, f) * face_value(p, &R, i, j, f, k);
           }
-          r[(size_t)c * K + k] = (p->sig_s[c] * phi[c] + p->q[c]) / FOUR_PI
-                                 - sig_t(p, c) * U[c] - div;
+          const double src = S_iso ? S_iso[c] : (p->sig_s[c] * phi[c] + p->q[c]) / FOUR_PI;
+          double rv = src - (sig_t(p, c) + tdiag) * U[c] - div;
+          if (I_n) rv += tdiag * I_n[(size_t)c * K + k];
+          r[(size_t)c * K + k] = rv;
         }
     }
     free(U);
@@ -274,7 +289,16 @@ double ora_pseudo_shift(const ora_problem *p, const ora_options *o, int c) {
 /* first-order upwind increments, zero increments on inflow boundary faces.   */
 /* Cells are visited in upwind order, which makes the solve exact.            */
 /* ------------------------------------------------------------------------ */
+/* The increment solve with tdiag = 1/(c dt) on the diagonal (Eq. elem_mtx). */
+static void sweep_t(const ora_problem *p, const ora_options *o, double tdiag, const double *r,
+                    double *dI);
+
 void ora_sweep(const ora_problem *p, const ora_options *o, const double *r, double *dI) {
+  sweep_t(p, o, 0.0, r, dI);
+}
+
+static void sweep_t(const ora_problem *p, const ora_options *o, double tdiag, const double *r,
+                    double *dI) {
   const int nx = p->nx, ny = p->ny, K = p->K;
 #pragma omp parallel for schedule(dynamic, 1)
   for (int k = 0; k < K; ++k) {
@@ -283,7 +307,7 @@ void ora_sweep(const ora_problem *p, const ora_options *o, const double *r, doub
     for (int jj = 0, j = j0; jj < ny; ++jj, j += dj)
       for (int ii = 0, i = i0; ii < nx; ++ii, i += di) {
         const int c = j * nx + i;
-        double d = sig_t(p, c) + ora_pseudo_shift(p, o, c), rhs = r[(size_t)c * K + k];
+        double d = sig_t(p, c) + tdiag + ora_pseudo_shift(p, o, c), rhs = r[(size_t)c * K + k];
         for (int f = 0; f < 4; ++f) {
           double on = p->mu[k] * NX_[f] + p->eta[k] * NY_[f];
           if (on > 0) {
@@ -336,14 +360,16 @@ void ora_face_coeffs(const ora_problem *p, double *gam_x, double *gam_y,
 
 /* D1 x (Eqs. MSE_d_mtx1, elem_mtx_M, steady, multiplied by V):               */
 /*   V sig_a x_c + sum_int A Gamma (x_c - x_nb) + sum_bnd A kappa x_c.         */
-void ora_synthetic_apply(const ora_problem *p, const double *x, double *y) {
+/* D1 x with tdiag = 1/(c dt) added to sigma_a on the diagonal (Eq.
+ * elem_mtx_M; tdiag = 0 in steady state). */
+static void synthetic_apply_t(const ora_problem *p, double tdiag, const double *x, double *y) {
   const int nx = p->nx, ny = p->ny;
   const double V = p->dx * p->dy;
 #pragma omp parallel for schedule(static)
   for (int j = 0; j < ny; ++j)
     for (int i = 0; i < nx; ++i) {
       const int c = j * nx + i;
-      double s = V * p->sig_a[c] * x[c];
+      double s = V * (p->sig_a[c] + tdiag) * x[c];
       for (int f = 0; f < 4; ++f) {
         int nb = neighbour(p, i, j, f);
         if (nb >= 0) s += face_area(p, f) * gamma_face(p, c, nb, f) * (x[c] - x[nb]);
@@ -353,19 +379,24 @@ void ora_synthetic_apply(const ora_problem *p, const double *x, double *y) {
     }
 }
 
+void ora_synthetic_apply(const ora_problem *p, const double *x, double *y) {
+  synthetic_apply_t(p, 0.0, x, y);
+}
+
 /* Dense-band entry of D1: row c, column c - d (d = 0, 1 or nx). */
 typedef struct {
   int N, bw;          /* bandwidth */
   double *L;          /* band of L: L[c*(bw+1) + d] = L(c, c-d) */
   int use_cg;
+  double tdiag;       /* 1/(c dt) on the diagonal (0: steady) */
 } synth_factor;
 
 #define BAND_LIMIT (1L << 31)   /* doubles (16 GiB); above this CG is used */
 
-static int synth_factor_build(const ora_problem *p, synth_factor *S) {
+static int synth_factor_build(const ora_problem *p, double tdiag, synth_factor *S) {
   const int nx = p->nx, ny = p->ny, N = nx * ny;
   const int bw = ny > 1 ? nx : 1;
-  S->N = N; S->bw = bw; S->L = NULL;
+  S->N = N; S->bw = bw; S->L = NULL; S->tdiag = tdiag;
   S->use_cg = ((long)N * (bw + 1) > BAND_LIMIT);
   if (S->use_cg) return 0;
   double *L = (double *)calloc((size_t)N * (bw + 1), sizeof(double));
@@ -375,7 +406,7 @@ static int synth_factor_build(const ora_problem *p, synth_factor *S) {
   for (int j = 0; j < ny; ++j)
     for (int i = 0; i < nx; ++i) {
       const int c = j * nx + i;
-      double diag = V * p->sig_a[c];
+      double diag = V * (p->sig_a[c] + tdiag);
       for (int f = 0; f < 4; ++f) {
         int nb = neighbour(p, i, j, f);
         if (nb >= 0) {
@@ -419,7 +450,7 @@ static int synth_factor_build(const ora_problem *p, synth_factor *S) {
 
 static void synth_factor_free(synth_factor *S) { free(S->L); S->L = NULL; }
 
-static int synth_cg(const ora_problem *p, const double *b, double *x) {
+static int synth_cg(const ora_problem *p, double tdiag, const double *b, double *x) {
   const int N = p->nx * p->ny;
   double *r = malloc(sizeof(double) * N), *z = malloc(sizeof(double) * N),
          *pp = malloc(sizeof(double) * N), *Ap = malloc(sizeof(double) * N),
@@ -433,7 +464,7 @@ static int synth_cg(const ora_problem *p, const double *b, double *x) {
     for (int j = 0; j < ny; ++j)
       for (int i = 0; i < nx; ++i) {
         const int c = j * nx + i;
-        double d = V * p->sig_a[c];
+        double d = V * (p->sig_a[c] + tdiag);
         for (int f = 0; f < 4; ++f) {
           int nb = neighbour(p, i, j, f);
           d += face_area(p, f) * (nb >= 0 ? gamma_face(p, c, nb, f) : kappa_face(p, c, f));
@@ -449,7 +480,7 @@ static int synth_cg(const ora_problem *p, const double *b, double *x) {
   double rz = 0;
   for (int c = 0; c < N; ++c) { z[c] = r[c] / dg[c]; pp[c] = z[c]; rz += r[c] * z[c]; }
   for (int it = 0; it < 200000 && ret; ++it) {
-    ora_synthetic_apply(p, pp, Ap);
+    synthetic_apply_t(p, tdiag, pp, Ap);
     double pAp = 0;
     for (int c = 0; c < N; ++c) pAp += pp[c] * Ap[c];
     double a = rz / pAp, rn = 0;
@@ -492,12 +523,12 @@ static void band_substitute(const synth_factor *S, const double *b, double *x) {
  * from about 1e-10 to about 1e-12 of the exact solve the method asks for. */
 static int synth_solve_with(const ora_problem *p, const synth_factor *S,
                             const double *b, double *x) {
-  if (S->use_cg) return synth_cg(p, b, x);
+  if (S->use_cg) return synth_cg(p, S->tdiag, b, x);
   const int N = S->N;
   band_substitute(S, b, x);
   double *r = malloc(sizeof(double) * N), *dx = malloc(sizeof(double) * N);
   if (!r || !dx) { free(r); free(dx); return -3; }
-  ora_synthetic_apply(p, x, r);
+  synthetic_apply_t(p, S->tdiag, x, r);
   for (int c = 0; c < N; ++c) r[c] = b[c] - r[c];
   band_substitute(S, r, dx);
   for (int c = 0; c < N; ++c) x[c] += dx[c];
@@ -507,7 +538,7 @@ static int synth_solve_with(const ora_problem *p, const synth_factor *S,
 
 int ora_synthetic_solve(const ora_problem *p, const double *b, double *x) {
   synth_factor S;
-  int e = synth_factor_build(p, &S);
+  int e = synth_factor_build(p, 0.0, &S);
   if (e) return e;
   e = synth_solve_with(p, &S, b, x);
   synth_factor_free(&S);
@@ -561,7 +592,7 @@ static int synth_wide_with(const ora_problem *p, const synth_factor *S, int alsm
 
 int ora_synthetic_wide(const ora_problem *p, int alsm, const double *b, int n_sub, double *x) {
   synth_factor S;
-  int e = synth_factor_build(p, &S);
+  int e = synth_factor_build(p, 0.0, &S);
   if (e) return e;
   e = synth_wide_with(p, &S, alsm, b, n_sub, x);
   synth_factor_free(&S);
@@ -634,6 +665,7 @@ typedef struct {
   const ora_options *o;
   synth_factor S;
   int have_S;
+  double tdiag;     /* 1/(c dt) of a time step (0: steady) */
 } ora_ctx;
 
 /* Relative transport residual of the iterate I (whose residual is r):
@@ -745,7 +777,7 @@ static int iterate_ctx(ora_ctx *X, const double *I_in, double *I_out,
   /* synthetic solve D1 phi' = b */
   int e = 0;
   if (!X->have_S) {
-    e = synth_factor_build(p, &X->S);
+    e = synth_factor_build(p, X->tdiag, &X->S);
     if (e == 0) X->have_S = 1;
   }
   if (e == 0) {
@@ -773,7 +805,7 @@ static int iterate_ctx(ora_ctx *X, const double *I_in, double *I_out,
 
 int ora_iterate(const ora_problem *p, const ora_options *o, const double *I_in,
                 double *I_out, double *phi_out) {
-  ora_ctx X = {p, o, {0, 0, NULL, 0}, 0};
+  ora_ctx X = {p, o, {0, 0, NULL, 0, 0.0}, 0, 0.0};
   int e = iterate_ctx(&X, I_in, I_out, phi_out, NULL);
   if (X.have_S) synth_factor_free(&X.S);
   return e;
@@ -812,7 +844,7 @@ int ora_solve(const ora_problem *p, const ora_options *o, const double *I0,
     return -1;
   }
 
-  ora_ctx X = {p, o, {0, 0, NULL, 0}, 0};
+  ora_ctx X = {p, o, {0, 0, NULL, 0, 0.0}, 0, 0.0};
   int status = 1, m = 0;
   double err = INFINITY, dmin = INFINITY;
   for (m = 0; m < o->max_iter; ++m) {
@@ -847,6 +879,206 @@ int ora_solve(const ora_problem *p, const ora_options *o, const double *I0,
   if (I_final) memcpy(I_final, Ia, sizeof(double) * NK);
   if (X.have_S) synth_factor_free(&X.S);
   free(Ia); free(Ib); free(phi_old); free(phi_new);
+  return status;
+}
+
+/* ======================================================================== */
+/* Time-dependent gray RTE with the material energy equation (Sec. 2.1 Eqs.   */
+/* RTE_g, Tm_g), backward Euler in time (Eqs. RTE_d, Tm_d), inner iterations  */
+/* per time step (Sec. 4.1, 4.2).                                             */
+/*                                                                            */
+/* One inner iteration m of step n -> n+1, from (I^m, T^m):                   */
+/*  1. residual of Eq. RTE_d_res with phi^m = a c (T^m)^4 and the time terms  */
+/*     -(I^m - I^n)/(c dt); increment solve with 1/(c dt) on the diagonal     */
+/*     (Eqs. RTE_d_increment, elem_mtx); I^{m+1/2} = I^m + dI;                */
+/*  2. SI: rho^{m+1} = rho^{m+1/2}, and the material equation (Eq. Tm_d) with  */
+/*     rho fixed at rho^{m+1/2} by sub_iter steps of dT = R2 / D2 (Eqs. MSE_d2,*/
+/*     R2_def, MSE_d_mtx2, elem_mtx_M);                                       */
+/*  3. GSIS: the synthetic and material equations (Eq. GSIS_dse) by sub_iter   */
+/*     sub-iterations s from (rho^{m+1/2}, T^m), each solving D1 d_rho = R1    */
+/*     and D2 d_T = R2 with the residuals of iteration s (Eqs. MSE_d1, MSE_d2, */
+/*     R1_def, R2_def, MSE_d_mtx1, MSE_d_mtx2, elem_mtx_M); the face flux of   */
+/*     R1 is the compact diffusion flux plus the face HoT as in the steady    */
+/*     synthetic equation, and on walls F_T . n + kappa (rho - rho^{m+1/2});   */
+/*     then I^{m+1} = I^{m+1/2} + (rho^{m+1} - rho^{m+1/2})/(4 pi) (Eq.        */
+/*     GSIS_update);                                                          */
+/*  4. Err = max(Err(rho), Err(T)) (Eq. Err_W and the criterion after it).    */
+/* ======================================================================== */
+static int td_iterate(ora_ctx *X, const ora_material *mt, const double *I_n,
+                      const double *rho_n, const double *T_n, const double *I_in,
+                      const double *T_in, double *I_out, double *T_out, double *rho_out) {
+  const ora_problem *p = X->p;
+  const ora_options *o = X->o;
+  const int nx = p->nx, ny = p->ny, N = nx * ny, K = p->K;
+  const size_t NK = (size_t)N * K;
+  const double V = p->dx * p->dy, dt = mt->dt, cl = mt->c, ar = mt->a;
+  const double tdiag = 1.0 / (cl * dt);
+  double *r = malloc(sizeof(double) * NK), *dI = malloc(sizeof(double) * NK);
+  double *wk = malloc(sizeof(double) * N * 8);
+  if (!r || !dI || !wk) { free(r); free(dI); free(wk); return -3; }
+  double *rho_m = wk, *Siso = wk + N, *ph = wk + 2 * N, *Fxh = wk + 3 * N, *Fyh = wk + 4 * N;
+  double *rs = wk + 5 * N, *Ts = wk + 6 * N, *R = wk + 7 * N;
+
+  /* 1. transport step */
+  moments(p, I_in, rho_m, NULL, NULL);
+  for (int c = 0; c < N; ++c) {
+    const double T = T_in[c];
+    Siso[c] = (p->sig_s[c] * rho_m[c] + p->sig_a[c] * ar * cl * T * T * T * T + p->q[c]) / FOUR_PI;
+  }
+  residual_t(p, o, I_in, Siso, tdiag, I_n, r);
+  sweep_t(p, o, tdiag, r, dI);
+  free(r);
+#pragma omp parallel for schedule(static)
+  for (size_t t = 0; t < NK; ++t) I_out[t] = I_in[t] + dI[t];
+  free(dI);
+  moments(p, I_out, ph, Fxh, Fyh);
+
+  /* material residual R2 and diagonal D2 of (rho_s, T_s): one step of T */
+  #define TD_T_STEP(RHO)                                                          \
+    for (int c = 0; c < N; ++c) {                                              \
+      const double T = Ts[c], sa = p->sig_a[c], cv = mt->cv[c];                \
+      const double R2 = -cv * (T - T_n[c]) / dt + sa * ((RHO)[c] - ar * cl * T * T * T * T); \
+      const double D2 = cv / dt + 4.0 * ar * cl * T * T * T * sa;              \
+      R[c] = T + R2 / D2;                                                      \
+    }                                                                          \
+    memcpy(Ts, R, sizeof(double) * N);
+
+  memcpy(Ts, T_in, sizeof(double) * N);
+  if (o->method == 0) {
+    /* 2. source iteration: rho^{m+1} = rho^{m+1/2}; material equation */
+    for (int s = 0; s < mt->sub_iter; ++s) { TD_T_STEP(ph) }
+    memcpy(rho_out, ph, sizeof(double) * N);
+    memcpy(T_out, Ts, sizeof(double) * N);
+    free(wk);
+    return 0;
+  }
+
+  /* 3. GSIS: wall (and, for the transport-face variant, interior) fluxes, HoT */
+  const int nb_f = 2 * (nx + ny);
+  double *bflux = malloc(sizeof(double) * nb_f);
+  double *fx = NULL, *fy = NULL;
+  if (o->hot_face == 1) {
+    fx = malloc(sizeof(double) * ((nx - 1) * ny + 1));
+    fy = malloc(sizeof(double) * (nx * (ny - 1) + 1));
+  }
+  transport_face_fluxes(p, o, I_out, bflux, fx, fy);
+  double *gpx = malloc(sizeof(double) * N * 2), *gpy = gpx + N;
+  ora_gradient(p, o->alsm, ph, gpx, gpy);
+  double *hx = malloc(sizeof(double) * N * 2), *hy = hx + N;
+  for (int c = 0; c < N; ++c) {
+    hx[c] = Fxh[c] + gpx[c] / (3.0 * sig_t(p, c));
+    hy[c] = Fyh[c] + gpy[c] / (3.0 * sig_t(p, c));
+  }
+  int e = 0;
+  if (!X->have_S) {
+    e = synth_factor_build(p, tdiag, &X->S);
+    if (e == 0) X->have_S = 1;
+  }
+  double *drho = malloc(sizeof(double) * N), *R1 = malloc(sizeof(double) * N);
+  memcpy(rs, ph, sizeof(double) * N);
+  for (int s = 0; s < mt->sub_iter && e == 0; ++s) {
+    /* R1 (Eq. R1_def) times V, at (rho_s, T_s) */
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        const int c = j * nx + i;
+        const double T = Ts[c];
+        double v = V * (-(rs[c] - rho_n[c]) / (cl * dt) +
+                        p->sig_a[c] * (ar * cl * T * T * T * T - rs[c]) + p->q[c]);
+        for (int f = 0; f < 4; ++f) {
+          const int nb = neighbour(p, i, j, f);
+          const double A = face_area(p, f);
+          if (nb >= 0) {
+            const double g = gamma_face(p, c, nb, f);
+            double h;
+            if (o->hot_face == 0) {
+              h = 0.5 * ((hx[c] + hx[nb]) * NX_[f] + (hy[c] + hy[nb]) * NY_[f]);
+            } else {
+              double ft;
+              if (f == 0) ft = fx[j * (nx - 1) + i];
+              else if (f == 1) ft = -fx[j * (nx - 1) + i - 1];
+              else if (f == 2) ft = fy[j * nx + i];
+              else ft = -fy[(j - 1) * nx + i];
+              h = ft - g * (ph[c] - ph[nb]);
+            }
+            v -= A * (g * (rs[c] - rs[nb]) + h);
+          } else {
+            v -= A * (bflux[bface(p, i, j, f)] + kappa_face(p, c, f) * (rs[c] - ph[c]));
+          }
+        }
+        R1[c] = v;
+      }
+    e = synth_solve_with(p, &X->S, R1, drho);
+    if (e) break;
+    TD_T_STEP(rs)                       /* T_{s+1} from (rho_s, T_s) */
+    for (int c = 0; c < N; ++c) rs[c] += drho[c];
+  }
+  #undef TD_T_STEP
+  if (e == 0) {
+    memcpy(rho_out, rs, sizeof(double) * N);
+    memcpy(T_out, Ts, sizeof(double) * N);
+#pragma omp parallel for schedule(static)
+    for (int c = 0; c < N; ++c) {
+      const double dl = (rs[c] - ph[c]) / FOUR_PI;
+      for (int k = 0; k < K; ++k) I_out[(size_t)c * K + k] += dl;
+    }
+  }
+  free(drho); free(R1); free(hx); free(gpx); free(bflux); free(fx); free(fy); free(wk);
+  return e;
+}
+
+int ora_td_solve(const ora_problem *p, const ora_options *o, const ora_material *mt,
+                 const double *I0, const double *T0, int n_steps, double *I_out,
+                 double *T_out, double *rho, double *Fx, double *Fy, int *inner_iters,
+                 double *err_last) {
+  const int N = p->nx * p->ny, K = p->K;
+  const size_t NK = (size_t)N * K;
+  const double V = p->dx * p->dy;
+  if (!(mt->c > 0) || !(mt->dt > 0) || !(mt->a >= 0) || mt->sub_iter < 1 || o->synth_form != 0)
+    return -1;
+  for (int c = 0; c < N; ++c)
+    if (!(mt->cv[c] > 0) || !(T0[c] >= 0)) return -1;
+  double *In = malloc(sizeof(double) * NK), *Ia = malloc(sizeof(double) * NK),
+         *Ib = malloc(sizeof(double) * NK);
+  double *Tn = malloc(sizeof(double) * N), *Ta = malloc(sizeof(double) * N),
+         *Tb = malloc(sizeof(double) * N), *rn = malloc(sizeof(double) * N),
+         *ra = malloc(sizeof(double) * N), *rb = malloc(sizeof(double) * N);
+  if (!In || !Ia || !Ib || !Tn || !Ta || !Tb || !rn || !ra || !rb) return -3;
+  if (I0) memcpy(Ia, I0, sizeof(double) * NK);
+  else memset(Ia, 0, sizeof(double) * NK);
+  memcpy(Ta, T0, sizeof(double) * N);
+  ora_ctx X = {p, o, {0, 0, NULL, 0, 0.0}, 0, 1.0 / (mt->c * mt->dt)};
+  int status = 0;
+  for (int n = 0; n < n_steps && status >= 0 && status != 2; ++n) {
+    /* time level n: the converged state of the previous step */
+    memcpy(In, Ia, sizeof(double) * NK);
+    memcpy(Tn, Ta, sizeof(double) * N);
+    moments(p, In, rn, NULL, NULL);
+    memcpy(ra, rn, sizeof(double) * N);
+    int m = 0;
+    double err = INFINITY, dmin = INFINITY;
+    for (m = 0; m < o->max_iter; ++m) {
+      int e = td_iterate(&X, mt, In, rn, Tn, Ia, Ta, Ib, Tb, rb);
+      if (e) { status = e; break; }
+      double dn, pn, dnT, pnT;
+      const double er = err_w(rb, ra, N, V, &dn, &pn);
+      const double et = err_w(Tb, Ta, N, V, &dnT, &pnT);
+      err = er > et ? er : et;
+      double *t = Ia; Ia = Ib; Ib = t;
+      t = Ta; Ta = Tb; Tb = t;
+      t = ra; ra = rb; rb = t;
+      if (!isfinite(err) || dn > 1e3 * fmax(dmin, 1e-9 * pn)) { status = 2; ++m; break; }
+      if (dn < dmin) dmin = dn;
+      if (err < o->tol) { ++m; break; }
+    }
+    if (status == 0 && !(err < o->tol)) status = 1;
+    if (inner_iters) inner_iters[n] = m;
+    if (err_last) err_last[n] = err;
+  }
+  if (I_out) memcpy(I_out, Ia, sizeof(double) * NK);
+  memcpy(T_out, Ta, sizeof(double) * N);
+  moments(p, Ia, rho, Fx, Fy);
+  if (X.have_S) synth_factor_free(&X.S);
+  free(In); free(Ia); free(Ib); free(Tn); free(Ta); free(Tb); free(rn); free(ra); free(rb);
   return status;
 }
 
@@ -1199,7 +1431,7 @@ int ora_adjoint(const ora_problem *p, const ora_options *o, const double *I_star
   const double V = p->dx * p->dy;
   synth_factor S = {0, 0, NULL, 0};
   int e = 0;
-  if (o->method == 1 && (e = synth_factor_build(p, &S))) return e;
+  if (o->method == 1 && (e = synth_factor_build(p, 0.0, &S))) return e;
   fwd_tape tp;
   if ((e = tape_build(p, o, &S, I_star, &tp))) { tape_free(&tp); synth_factor_free(&S); return e; }
   /* source M^T g: w_k (g_phi + mu_k g_Fx + eta_k g_Fy) */

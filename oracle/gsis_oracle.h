@@ -117,6 +117,30 @@ void ora_wide_correction(const ora_problem *p, int alsm, const double *x, double
  * MSE_d_mtx1, R1 the residual of the face-averaged balance. */
 int ora_synthetic_wide(const ora_problem *p, int alsm, const double *b, int n_sub, double *x);
 
+/* Time-dependent gray RTE with the material energy equation (Sec. 2.1 Eqs.
+ * RTE_g, Tm_g; emission phi = a c T^4), backward Euler in time (Eqs. RTE_d,
+ * Tm_d) with opacities constant in time, and inner iterations per step (SI,
+ * or GSIS with the synthetic and material equations of Eq. GSIS_dse solved
+ * by sub_iter sub-iterations of Eqs. MSE_d1, MSE_d2). */
+typedef struct {
+  double c;          /* speed of light, > 0 */
+  double a;          /* radiation constant, >= 0 */
+  double dt;         /* time step, > 0 */
+  const double *cv;  /* [nx*ny] volume specific heat, > 0 */
+  int sub_iter;      /* macroscopic sub-iterations per inner iteration, >= 1 */
+} ora_material;
+
+/* n_steps time steps from I0 [nx*ny*K] (NULL = 0) and T0 [nx*ny]; each step
+ * iterates until max(Err(rho), Err(T)) < o->tol or o->max_iter inner
+ * iterations. Outputs I_out (may be NULL), T_out, rho, Fx, Fy of the last
+ * step; inner_iters and err_last [n_steps] (may be NULL). Returns 0 if every
+ * step converged, 1 if a step reached max_iter, 2 on divergence, <0 on
+ * error (-1: invalid material data or synth_form 1). */
+int ora_td_solve(const ora_problem *p, const ora_options *o, const ora_material *mt,
+                 const double *I0, const double *T0, int n_steps, double *I_out,
+                 double *T_out, double *rho, double *Fx, double *Fy, int *inner_iters,
+                 double *err_last);
+
 /* Adjoint of the fixed point I* of the iteration (limiter off, central HoT
  * faces, no pseudo time; method SI or GSIS): lambda = G^T lambda + M^T g for
  * the output J = <g_phi, phi*> + <g_Fx, Fx*> + <g_Fy, Fy*> (any cotangent may

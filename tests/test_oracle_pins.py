@@ -639,3 +639,157 @@ def test_transport_residual_history_limits():
         assert abs(r["tres_hist"][0] - 1.0) < 1e-14
     assert si["tres_hist"][-1] < 1e-10 and ts["tres_hist"][-1] < 1e-10
     assert gc["tres_hist"][-1] > 1e-4
+
+
+# ----------------------- time-dependent RTE with the material energy equation
+def _be_step(rho, T, sa, c, a, dt, cv):
+    """One backward-Euler step of the infinite-medium equations
+    (rho' - rho)/(c dt) = sa (a c T'^4 - rho'), cv (T' - T)/dt = sa (rho' -
+    a c T'^4): their sum conserves rho/c + cv T, which leaves one monotone
+    equation in T', solved by bisection."""
+    E = rho / c + cv * T
+    f = lambda Tp: cv * (Tp - T) / dt - sa * (c * (E - cv * Tp) - a * c * Tp ** 4)
+    lo, hi = 0.0, E / cv
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if f(mid) > 0:
+            hi = mid
+        else:
+            lo = mid
+    Tp = 0.5 * (lo + hi)
+    return c * (E - cv * Tp), Tp
+
+
+@pytest.mark.parametrize("kw", [dict(method=0), dict(method=1, hot_face=0),
+                                dict(method=1, hot_face=1)])
+def test_td_infinite_medium_relaxation(kw):
+    """Radiation out of equilibrium with the material in an optically thick
+    uniform medium (cells 625 mean free paths wide): away from the walls the
+    discrete solution is the infinite-medium one, which relaxes towards
+    rho = a c T^4 while conserving rho/c + cv T; five steps against the
+    backward-Euler steps of the two ordinary differential equations."""
+    n, K = 16, 12
+    p = inputs.homogeneous(n, n, inputs.quad_s4(), sigma_t=1e4, c=0.5, q=0.0)
+    rho0, T0, c, a, dt, cv = 0.2, 1.0, 1.0, 1.0, 1e-4, 1.0
+    p["bnd_in"] = np.full((4 * n, K), rho0 / FOURPI)
+    r = oracle.td_solve(p, np.full(n * n, T0), 5, c=c, a=a, dt=dt, cv=cv, sub_iter=4,
+                        I0=np.full((n * n, K), rho0 / FOURPI), tol=1e-13, max_iter=300,
+                        limiter=0, **kw)
+    assert r["status"] == 0
+    rho, T = rho0, T0
+    for _ in range(5):
+        rho, T = _be_step(rho, T, 5000.0, c, a, dt, cv)
+    cc = (n // 2) * n + n // 2
+    assert abs(r["rho"][cc] - rho) < 1e-11 and abs(r["T"][cc] - T) < 1e-11
+    assert abs(r["rho"][cc] / c + cv * r["T"][cc] - (rho0 / c + cv * T0)) < 1e-12
+    assert abs(rho - a * c * T ** 4) < abs(rho0 - a * c * T0 ** 4)
+
+
+def test_td_equilibrium_is_stationary():
+    """rho = a c T^4 everywhere with matching isotropic inflow: nothing
+    changes, in any cell (random opacities, both methods)."""
+    n, K = 9, 12
+    p = inputs.random_problem(n, n, seed=12, sigma_range=(0.1, 50.0), inflow=False)
+    p["q"] = np.zeros(n * n)
+    T0, a, c = 0.7, 2.0, 3.0
+    rho0 = a * c * T0 ** 4
+    p["bnd_in"] = np.full((4 * n, K), rho0 / FOURPI)
+    for method in (0, 1):
+        r = oracle.td_solve(p, np.full(n * n, T0), 3, c=c, a=a, dt=0.05, cv=0.3, sub_iter=3,
+                            I0=np.full((n * n, K), rho0 / FOURPI), method=method, tol=1e-13,
+                            max_iter=50, limiter=1)
+        assert r["status"] == 0
+        assert np.abs(r["rho"] - rho0).max() < 1e-13 * rho0
+        assert np.abs(r["T"] - T0).max() < 1e-13
+        assert np.abs(r["Fx"]).max() < 1e-13 * rho0
+
+
+def test_td_single_ordinate_closed_form():
+    """One cell, one ordinate carrying the whole sphere (scattering then
+    cancels exactly), no absorption: each step solves (1/(c dt) + |mu|/dx +
+    |eta|/dy) I' = I/(c dt) + |mu|/dx I_W + |eta|/dy I_S exactly; the
+    temperature does not move."""
+    mu, eta = 0.6, -0.3
+    p = dict(nx=1, ny=1, dx=0.5, dy=0.25, mu=np.array([mu]), eta=np.array([eta]),
+             w=np.array([FOURPI]), sigma_a=np.zeros(1), sigma_s=np.array([2.0]),
+             q=np.zeros(1))
+    Iw, In_ = 0.3, 0.8          # inflow through the west face (mu > 0), north (eta < 0)
+    bnd = np.zeros((4, 1))
+    bnd[0, 0], bnd[3, 0] = Iw, In_
+    p["bnd_in"] = bnd
+    c, dt = 2.0, 0.1
+    ax, ay = mu / 0.5, 0.3 / 0.25
+    I = 0.05
+    r = oracle.td_solve(p, np.full(1, 0.4), 4, c=c, a=1.0, dt=dt, cv=1.0, sub_iter=2,
+                        I0=np.full((1, 1), I), method=0, tol=1e-15, max_iter=60, order=2,
+                        limiter=1, return_I=True)
+    for _ in range(4):
+        I = (I / (c * dt) + ax * Iw + ay * In_) / (1.0 / (c * dt) + ax + ay)
+    assert abs(r["I"][0, 0] - I) < 1e-14 * I
+    assert abs(r["T"][0] - 0.4) < 1e-15
+
+
+@pytest.mark.parametrize("kw", [dict(method=0), dict(method=1, hot_face=1)])
+def test_td_energy_balance(kw):
+    """Total energy per step (first-order faces, so a wall's outgoing value
+    is its cell's): sum V [(rho' - rho)/c + cv (T' - T)] / dt + sum over
+    walls A F_T . n = sum V q, at the converged step, for source iteration
+    and for GSIS with transport face fluxes (whose fixed point is SI's)."""
+    n, K = 7, 12
+    p = inputs.random_problem(n, n + 2, seed=17, sigma_range=(0.3, 30.0))
+    N = n * (n + 2)
+    c, a, dt = 1.5, 0.8, 0.02
+    cv = np.random.Generator(np.random.PCG64(3)).uniform(0.5, 2.0, N)
+    T0 = np.random.Generator(np.random.PCG64(4)).uniform(0.3, 1.0, N)
+    opts = dict(order=1, limiter=0, tol=1e-14, max_iter=3000, **kw)
+    r0 = oracle.td_solve(p, T0, 2, c=c, a=a, dt=dt, cv=cv, sub_iter=3, return_I=True, **opts)
+    r1 = oracle.td_solve(p, T0, 3, c=c, a=a, dt=dt, cv=cv, sub_iter=3, return_I=True, **opts)
+    assert r0["status"] == 0 and r1["status"] == 0
+    V = p["dx"] * p["dy"]
+    I = r1["I"]
+    nx, ny = p["nx"], p["ny"]
+    leak = 0.0
+    for j in range(ny):
+        for i in range(nx):
+            cell = j * nx + i
+            for (nxx, nyy, A, on_wall, f) in ((-1, 0, p["dy"], i == 0, j), (1, 0, p["dy"], i == nx - 1, ny + j),
+                                              (0, -1, p["dx"], j == 0, 2 * ny + i),
+                                              (0, 1, p["dx"], j == ny - 1, 2 * ny + nx + i)):
+                if not on_wall:
+                    continue
+                on = p["mu"] * nxx + p["eta"] * nyy
+                val = np.where(on > 0, I[cell], p["bnd_in"][f])
+                leak += A * np.sum(p["w"] * on * val)
+    lhs = V * np.sum((r1["rho"] - r0["rho"]) / c + cv * (r1["T"] - r0["T"])) / dt + leak
+    rhs = V * np.sum(p["q"])
+    assert abs(lhs - rhs) < 1e-10 * max(abs(rhs), 1.0)
+
+
+def test_td_large_step_is_steady():
+    """With no absorption the temperature decouples, and one step of size
+    1e12 from I = 0 reaches the steady solution of the same medium."""
+    p = inputs.random_problem(12, 10, seed=8, sigma_range=(0.5, 20.0))
+    p["sigma_s"] = p["sigma_s"] + p["sigma_a"]
+    p["sigma_a"] = np.zeros(120)
+    for method in (0, 1):
+        st = oracle.solve(p, method=method, tol=1e-13, max_iter=5000, limiter=0)
+        td = oracle.td_solve(p, np.full(120, 0.5), 1, c=1.0, a=1.0, dt=1e12, cv=1.0, sub_iter=2,
+                             method=method, tol=1e-13, max_iter=5000, limiter=0)
+        assert st["status"] == 0 and td["status"] == 0
+        assert np.abs(td["rho"] - st["phi"]).max() < 1e-9 * np.abs(st["phi"]).max()
+        assert np.abs(td["T"] - 0.5).max() == 0.0
+
+
+def test_td_gsis_fewer_iterations_in_thick_medium():
+    """Optically thick scattering medium and large steps: GSIS needs far fewer
+    inner iterations per step than source iteration (the paper's point)."""
+    p = inputs.homogeneous(24, 24, inputs.quad_s4(), sigma_t=200.0, c=0.99, q=1.0)
+    kw = dict(c=1.0, a=0.01, dt=1.0, cv=1.0, sub_iter=3, tol=1e-8, max_iter=20000, limiter=0)
+    si = oracle.td_solve(p, np.full(576, 0.1), 2, method=0, **kw)
+    gs = oracle.td_solve(p, np.full(576, 0.1), 2, method=1, **kw)
+    assert si["status"] == 0 and gs["status"] == 0
+    assert max(gs["inner_iters"]) * 10 < min(si["inner_iters"])
+    # the central-face GSIS solution differs from the transport (SI) one by a
+    # discretisation-sized amount (F1), largest in the wall cells (8 mean free
+    # paths wide here)
+    assert np.abs(gs["rho"] - si["rho"]).max() < 0.15 * np.abs(si["rho"]).max()
