@@ -345,6 +345,50 @@ gsis_status gsis_adjoint(gsis_ctx *ctx, const gsis_problem *p, const gsis_option
                          double *g_sigma_a, double *g_sigma_s, double *g_q, gsis_result *fwd,
                          gsis_adjoint_info *info);
 
+/* ------------------------------------------------------- time-dependent form
+ * The gray RTE with the material energy equation (Sec. 2.1 Eqs. RTE_g,
+ * Tm_g; emission phi = a c T^4, isotropic), backward Euler in time with a
+ * fixed step (Eqs. RTE_d, Tm_d), opacities constant in time. Each step
+ * n -> n+1 runs inner iterations from (I^n, T^n) until max(Err(rho),
+ * Err(T)) < options.tol (the criterion after Eq. Err_W) or options.max_iter:
+ *  - the transport residual and increment solve take the 1/(c dt) terms
+ *    (Eqs. RTE_d_res, RTE_d_increment, elem_mtx) and the emission of T^m;
+ *  - source iteration: rho^{m+1} = rho^{m+1/2}, then sub_iter steps
+ *    T <- T + R2 / D2 of the material equation with rho fixed (Eqs. MSE_d2,
+ *    R2_def, MSE_d_mtx2, elem_mtx_M);
+ *  - GSIS: sub_iter sub-iterations of the synthetic and material equations
+ *    (Eq. GSIS_dse), each D1 d_rho = R1 (D1 with 1/(c dt) on the diagonal,
+ *    Eqs. MSE_d1, R1_def, MSE_d_mtx1; compact diffusion flux plus the face
+ *    HoT as in the steady form, walls F_T . n + kappa (rho - rho^{m+1/2}))
+ *    and D2 d_T = R2 from the same sub-iterate, then the correction of Eq.
+ *    GSIS_update.
+ * FP64 only, synth_form 0, single plans (no batch, no adjoint). */
+typedef struct {
+  double c;            /* speed of light, > 0 */
+  double a;            /* radiation constant, >= 0 */
+  double dt;           /* time step, > 0 */
+  const double *cv;    /* [nx*ny] volume specific heat, > 0 */
+  const double *T0;    /* [nx*ny] initial material temperature, >= 0 */
+  int32_t sub_iter;    /* macroscopic sub-iterations per inner iteration, >= 1 */
+} gsis_material;
+
+/* A plan of the time-dependent form: options.I0 is the initial intensity
+ * (NULL = 0); cv and T0 host or device memory as options.device_ptrs says
+ * (copied). Destroy it with gsis_plan_destroy; gsis_plan_status and
+ * gsis_plan_read report the current step's inner iterations. */
+gsis_status gsis_td_create(gsis_ctx *ctx, const gsis_problem *p, const gsis_options *o,
+                           const gsis_material *m, gsis_plan **out);
+/* Advance n_steps time steps; inner_iters[n_steps] and last_err[n_steps]
+ * (may be NULL) receive each step's inner iterations and final Err. Waits
+ * for the device. Returns GSIS_NOT_CONVERGED if a step stopped at
+ * options.max_iter (the steps after it still run), GSIS_DIVERGED at the
+ * first step that diverged (no later step runs). */
+gsis_status gsis_td_advance(gsis_plan *plan, int32_t n_steps, int32_t *inner_iters,
+                            double *last_err);
+/* rho = phi, T, Fx, Fy [nx*ny] of the current state (host or device memory
+ * as the plan's device_ptrs says). */
+gsis_status gsis_td_read(gsis_plan *plan, double *rho, double *T, double *Fx, double *Fy);
+
 /* Library build string (compiler, target, options). */
 const char *gsis_version(void);
 

@@ -352,14 +352,40 @@ gsis_status make_single_set(gsis_plan *pl) {
 // A plan whose device memory comes from hipMalloc (arena NULL) or is carved
 // from the arena_cap bytes at arena (no device or pinned allocation at all;
 // profiling off).
+// With mt, the time-dependent form (backward-Euler steps of size mt->dt).
 static gsis_status plan_create(gsis_ctx *ctx, const gsis_problem *p, const gsis_options *o,
-                               gsis_plan **out, char *arena, size_t arena_cap) {
+                               gsis_plan **out, char *arena, size_t arena_cap,
+                               const gsis_material *mt = nullptr) {
   if (!ctx) return fail(nullptr, GSIS_E_INVALID_ARG, "ctx is NULL");
   if (!out) return fail(ctx, GSIS_E_INVALID_ARG, "out is NULL");
   *out = nullptr;
   std::vector<double> mu, eta, w, sa, ss, q, bnd;
   gsis_status st = check_problem(ctx, p, o, mu, eta, w, sa, ss, q, bnd);
   if (st) return st;
+  std::vector<double> cvh, T0h;
+  if (mt) {
+    if (!(mt->c > 0) || !std::isfinite(mt->c))
+      return fail(ctx, GSIS_E_INVALID_ARG, "material.c must be finite and > 0");
+    if (!(mt->a >= 0) || !std::isfinite(mt->a))
+      return fail(ctx, GSIS_E_INVALID_ARG, "material.a must be finite and >= 0");
+    if (!(mt->dt > 0) || !std::isfinite(mt->dt) || !std::isfinite(1.0 / (mt->c * mt->dt)))
+      return fail(ctx, GSIS_E_INVALID_ARG, "material.dt must be finite and > 0");
+    if (mt->sub_iter < 1) return fail(ctx, GSIS_E_INVALID_ARG, "material.sub_iter must be >= 1");
+    if (o->precision != GSIS_FP64)
+      return fail(ctx, GSIS_E_UNSUPPORTED, "the time-dependent form runs in FP64 only");
+    if (o->synth_form != 0)
+      return fail(ctx, GSIS_E_UNSUPPORTED, "the time-dependent form needs options.synth_form 0");
+    const size_t N = (size_t)p->nx * p->ny;
+    if ((st = fetch(ctx, mt->cv, N, o->device_ptrs, cvh, "material.cv")) ||
+        (st = fetch(ctx, mt->T0, N, o->device_ptrs, T0h, "material.T0")))
+      return st;
+    for (size_t c = 0; c < N; ++c) {
+      if (!(cvh[c] > 0) || !std::isfinite(cvh[c]))
+        return fail(ctx, GSIS_E_INVALID_ARG, "material.cv[%zu] must be finite and > 0", c);
+      if (!(T0h[c] >= 0) || !std::isfinite(T0h[c]))
+        return fail(ctx, GSIS_E_INVALID_ARG, "material.T0[%zu] must be finite and >= 0", c);
+    }
+  }
   if (o->method == GSIS_GSIS && o->hot_face == GSIS_HOT_TRANSPORT && o->synth_form != 0)
     return fail(ctx, GSIS_E_UNSUPPORTED,
                 "options.synth_form 1 needs central HoT faces (options.hot_face 0)");
@@ -383,6 +409,14 @@ static gsis_status plan_create(gsis_ctx *ctx, const gsis_problem *p, const gsis_
   P.synth_max_iter = o->synth_max_iter;
   P.synth_form = o->method == GSIS_GSIS ? o->synth_form : 0;
   P.synth_sub = o->synth_sub;
+  if (mt) {
+    P.td = 1;
+    P.sub_iter = mt->sub_iter;
+    P.tdiag = 1.0 / (mt->c * mt->dt);
+    P.ca = mt->a * mt->c;
+    P.dt = mt->dt;
+    pl->T0_host = T0h;
+  }
   auto bail = [&](gsis_status s) {
     gsis_plan_destroy(pl);
     return s;
@@ -469,7 +503,7 @@ static gsis_status plan_create(gsis_ctx *ctx, const gsis_problem *p, const gsis_
       if (i > 0) d += hl[0].ax[c - 1]; else d += p->dy * kap[j];
       if (j + 1 < ny) d += hl[0].ay[c]; else d += p->dx * kap[2 * ny + nx + i];
       if (j > 0) d += hl[0].ay[c - nx]; else d += p->dx * kap[2 * ny + i];
-      hl[0].diag[c] = d;
+      hl[0].diag[c] = d + P.V * P.tdiag;   // 1/(c dt) of Eq. elem_mtx_M (td form)
     }
   // -- pseudo-time shift of the increment-solve diagonal (Eqs. cfl_pse,
   // tau_pse, elem_main_shifted); |sigma_i r^L - sigma_j r^R| is
@@ -506,8 +540,11 @@ static gsis_status plan_create(gsis_ctx *ctx, const gsis_problem *p, const gsis_
         r[1] = (qd & 1) ? cE[c] : cW[c];
         r[2] = (qd & 2) ? cS[c] : cN[c];
         r[3] = (qd & 2) ? cN[c] : cS[c];
-        r[4] = st_[c];
-        r[5] = st_[c] + shift[c];
+        // the time-dependent form's 1/(c dt) joins sigma_t in the residual's
+        // -sigma_t I term and in the increment solve's diagonal (Eqs.
+        // RTE_d_res, elem_mtx)
+        r[4] = st_[c] + P.tdiag;
+        r[5] = st_[c] + P.tdiag + shift[c];
         sdq[(size_t)qd * N + dg_idx(xl, yl, nx, ny)] = r[5];
       }
   const std::vector<int2> rtiles = residual_tiles(nx, ny);
@@ -516,6 +553,7 @@ static gsis_status plan_create(gsis_ctx *ctx, const gsis_problem *p, const gsis_
     // 1: two-kernel reference, 2: fused wavefront sweep (tests compare them)
     const char *e = getenv("GSIS_SWEEP_REFERENCE");
     P.sweep_impl = (e && (e[0] == '1' || e[0] == '2')) ? e[0] - '0' : 0;
+    if (P.td) P.sweep_impl = 0;      // the time terms live in the residual kernel
   }
   {
     // workgroups per ordinate in the recurrence (GSIS_CHAIN_PARTS=1..4 sets
@@ -619,6 +657,13 @@ static gsis_status plan_create(gsis_ctx *ctx, const gsis_problem *p, const gsis_
   if (P.method == GSIS_GSIS && P.hot_face == GSIS_HOT_TRANSPORT &&
       (st = dalloc(pl, &P.ftp, (size_t)8 * N)))
     return bail(st);
+  if (P.td &&
+      ((st = upload(pl, &P.cv, cvh)) || (st = dalloc(pl, &P.Tm, N)) || (st = dalloc(pl, &P.Tn, N)) ||
+       (st = dalloc(pl, &P.Tsub0, N)) || (st = dalloc(pl, &P.Tsub1, N)) ||
+       (st = dalloc(pl, &P.rho_n, N)) ||
+       (st = dalloc(pl, &P.err_parts_T, 2 * (size_t)((N + 255) / 256) + 2)) ||
+       (st = dalloc(pl, &P.In, (size_t)N * K))))
+    return bail(st);
   if (f32) {
     if ((st = dalloc(pl, &P.base, N))) return bail(st);
   } else {
@@ -688,6 +733,9 @@ extern "C" gsis_status gsis_plan_reset(gsis_plan *pl) {
   if (f32)   // I^0 = Itilde + phi0/(4 pi)
     HIPCHK(ctx, hipMemcpyAsync(P.base, pl->phi0_host.data(), P.N * sizeof(double),
                                hipMemcpyHostToDevice, s));
+  if (P.td)   // T^0 (the source kernel below takes the emission of T^m)
+    HIPCHK(ctx, hipMemcpyAsync(P.Tm, pl->T0_host.data(), P.N * sizeof(double),
+                               hipMemcpyHostToDevice, s));
   HIPCHK(ctx, hipMemsetAsync(P.state, 0, 5 * sizeof(int32_t), s));
   launch_hand_reset(P, s);
   HIPCHK(ctx, hipMemsetAsync(P.err_hist, 0, P.max_iter * sizeof(double), s));
@@ -745,7 +793,17 @@ extern "C" gsis_status gsis_plan_iterate(gsis_plan *pl, int32_t n) {
     // so a nonzero value below was read during this iteration
     int32_t *host_flag = (int32_t *)pl->host_scal;
     host_flag[0] = 0;
-    if (P.method == GSIS_GSIS && P.synth_form == 1) {
+    if (P.td) {
+      // time-dependent form: sub-iterations of the material equation and
+      // (GSIS) the synthetic equation, each from the previous sub-iterate
+      for (int sub = 0; sub < P.sub_iter; ++sub) {
+        launch_material(P.S, s, sub);
+        if (P.method == GSIS_GSIS) {
+          launch_synth_solve(P.S, s, host_flag, sub == 0 ? 1 : 3, sub);
+          if (host_flag[0] != 0) break;
+        }
+      }
+    } else if (P.method == GSIS_GSIS && P.synth_form == 1) {
       // face-averaged balance: sub-iterations from phi^{m+1/2}
       for (int sub = 0; sub < P.synth_sub; ++sub) {
         launch_wide_grad(P.S, s, sub == 0);
@@ -919,4 +977,55 @@ extern "C" gsis_status gsis_solve_noalloc(gsis_ctx *ctx, const gsis_problem *p,
   gsis_status st = scratch_address(ctx, &base);
   if (st) return st;
   return solve_with(ctx, p, o, r, base, kScratchBytes);
+}
+
+// ------------------------------------------------------- time-dependent form
+extern "C" gsis_status gsis_td_create(gsis_ctx *ctx, const gsis_problem *p, const gsis_options *o,
+                                      const gsis_material *mt, gsis_plan **out) {
+  if (!mt) return fail(ctx, GSIS_E_INVALID_ARG, "material is NULL");
+  return plan_create(ctx, p, o, out, nullptr, 0, mt);
+}
+
+extern "C" gsis_status gsis_td_advance(gsis_plan *pl, int32_t n_steps, int32_t *inner_iters,
+                                       double *last_err) {
+  if (!pl) return GSIS_E_INVALID_ARG;
+  gsis_ctx *ctx = pl->ctx;
+  if (!pl->P.td) return fail(ctx, GSIS_E_INVALID_ARG, "not a time-dependent plan");
+  if (n_steps < 0) return fail(ctx, GSIS_E_INVALID_ARG, "n_steps must be >= 0");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  gsis_status worst = GSIS_OK;
+  for (int step = 0; step < n_steps; ++step) {
+    launch_td_begin(pl->P, pl->stream);
+    HIPCHK(ctx, hipGetLastError());
+    int32_t n = 0, conv = 0;
+    double le = 0;
+    gsis_status st;
+    while (true) {
+      if ((st = gsis_plan_iterate(pl, std::min(8, pl->P.max_iter - n)))) return st;
+      if ((st = gsis_plan_status(pl, &n, &conv, &le))) return st;
+      if (conv != 0 || n >= pl->P.max_iter) break;
+    }
+    if (inner_iters) inner_iters[step] = n;
+    if (last_err) last_err[step] = le;
+    if (conv == -1) return GSIS_DIVERGED;
+    if (conv == 0) worst = GSIS_NOT_CONVERGED;
+  }
+  return worst;
+}
+
+extern "C" gsis_status gsis_td_read(gsis_plan *pl, double *rho, double *T, double *Fx,
+                                    double *Fy) {
+  if (!pl) return GSIS_E_INVALID_ARG;
+  gsis_ctx *ctx = pl->ctx;
+  if (!pl->P.td) return fail(ctx, GSIS_E_INVALID_ARG, "not a time-dependent plan");
+  if (!rho || !T || !Fx || !Fy) return fail(ctx, GSIS_E_INVALID_ARG, "an output is NULL");
+  gsis_result r;
+  std::memset(&r, 0, sizeof r);
+  r.phi = rho; r.Fx = Fx; r.Fy = Fy;
+  gsis_status st = gsis_plan_read(pl, &r);
+  if (st) return st;
+  const hipMemcpyKind k = pl->device_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  HIPCHK(ctx, hipMemcpyAsync(T, pl->P.Tm, pl->P.N * sizeof(double), k, pl->stream));
+  HIPCHK(ctx, hipStreamSynchronize(pl->stream));
+  return GSIS_OK;
 }

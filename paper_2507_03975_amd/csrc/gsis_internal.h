@@ -77,7 +77,7 @@ struct SynthDesc {
   double dx, dy, V;
   int method, fp32, max_iter;
   double tol, rtol;
-  const double *sig_t, *sig_s, *q, *cE, *cW, *cN, *cS, *kappa;
+  const double *sig_t, *sig_s, *sig_a, *q, *cE, *cW, *cN, *cS, *kappa;
   double *phih, *Fx, *Fy;       // moments of I^{m+1/2} (k_hot<true> writes them)
   const double *bflux;
   const double *mom_part;       // [4][3][N] per-quadrant partial moments
@@ -86,6 +86,13 @@ struct SynthDesc {
                                 // the east (+x) and north (+y) face of each cell
   double sw, swm, swe;          // sums of w, w mu, w eta (FP32-mixed base terms)
   double *hx, *hy, *rhs, *phi, *delta, *base, *src, *dynq;
+  // time-dependent form (td = 1): backward-Euler step with 1/(c dt) = tdiag,
+  // emission ca T^4 (ca = a c), material T^m (Tm), time level n (Tn, rho_n),
+  // sub-iterates T(s) (s >= 1) in Tsub[(s - 1) & 1], sub_iter per iteration
+  int td, sub_iter;
+  double tdiag, ca, dt;
+  const double *cv, *Tn, *rho_n;
+  double *Tm, *Tsub0, *Tsub1, *err_parts_T;
   // CG vectors: r alternates between cg_r and cg_r2 with the V-cycle count,
   // s = A p between cg_s0 and cg_s1 with the iteration; z = M r, w = A z
   double *cg_r, *cg_r2, *cg_z, *cg_p, *cg_s0, *cg_s1, *cg_w;
@@ -196,6 +203,12 @@ struct PlanDev {
   double *tres_hist = nullptr; // [max_iter] relative transport residual of I^m
   double *tres_part = nullptr; // [n_rtiles * ordinate pairs] sums of w r^2 per residual wave
   double *src2_part = nullptr; // [ceil(N / 256)] sums of src^2 per block of cells
+  // time-dependent form (gsis_td_create): 1/(c dt), a c, dt, sub-iterations
+  int td = 0, sub_iter = 1;
+  double tdiag = 0, ca = 0, dt = 0;
+  double *cv = nullptr, *Tm = nullptr, *Tn = nullptr, *Tsub0 = nullptr, *Tsub1 = nullptr;
+  double *rho_n = nullptr, *err_parts_T = nullptr;
+  double *In = nullptr;        // [K][N] I^n in the intensity layout (FP64)
   int32_t *state = nullptr;    // [0] iterations done, [1] done flag (1 converged,
                                // -1 diverged, 2 max_iter), [2] current I buffer,
                                // [3] synthetic CG converged, [4] a split
@@ -280,8 +293,19 @@ void launch_wide_grad(const SynthSet &S, hipStream_t s, bool first);
 // balance's correction at the level-0 iterate, which is the warm start (one
 // defect-correction sub-iteration, after launch_wide_grad); 0: it reads the
 // descriptor's rhs (adjoint).
-void launch_synth_solve(const SynthSet &S, hipStream_t s, int32_t *host_flag, int rhs_mode);
+// sub: the time-dependent form's sub-iteration (its right-hand side takes
+// the emission of T(sub)); rhs_mode 3: as 1 with the level-0 iterate (the
+// previous sub-iterate) as warm start.
+void launch_synth_solve(const SynthSet &S, hipStream_t s, int32_t *host_flag, int rhs_mode,
+                        int sub = 0);
+// Time-dependent form: T(sub + 1) = T(sub) + R2 / D2 (Eqs. MSE_d2, R2_def,
+// MSE_d_mtx2, elem_mtx_M) with rho(sub) (rho^{m+1/2} at sub 0 or for source
+// iteration, else the last synthetic solution)
+void launch_material(const SynthSet &S, hipStream_t s, int sub);
 void launch_update(const SynthSet &S, hipStream_t s);
+// Time-dependent form, start of a time step: I^n = the current iterate (with
+// its pending correction), rho^n, T^n; the step's counters and flags cleared
+void launch_td_begin(const PlanDev &P, hipStream_t s);
 void launch_apply_delta_final(const PlanDev &P, hipStream_t s, double swmu, double sweta,
                               double *Fx_out, double *Fy_out);
 // CG iterations of P's last synthetic solve (one device double)

@@ -175,16 +175,29 @@ __global__ void k_hot(const SynthDesc *ds, const int2 *bt) {
   D.hy[c] = hy;
 }
 
+// The time-dependent form's material temperature of sub-iteration sub: T^m,
+// then the sub-iterates in two alternating buffers.
+__device__ inline double *t_sub(CDesc &D, int sub) {
+  return sub == 0 ? D.Tm : ((sub - 1) & 1) ? D.Tsub1 : D.Tsub0;
+}
+
 // b_c of cell c = (i, j) from the HoT of the cell and its neighbours (central
 // faces), or from the face values h of its faces (transport faces: hx[c] on
-// the cell's east face, hy[c] on its north face, normals +x, +y)
-__device__ inline double rhs_at(CDesc &D, int c, int i, int j) {
+// the cell's east face, hy[c] on its north face, normals +x, +y). The
+// time-dependent form adds V (rho^n / (c dt) + sigma_a a c T^4) with T the
+// temperature Ts of the sub-iteration (D1 carries V / (c dt) on its diagonal):
+// then D1 rho' = b is D1 d_rho = R1 of Eqs. MSE_d1, R1_def at rho' = rho + d_rho.
+__device__ inline double rhs_at(CDesc &D, int c, int i, int j, const double *Ts) {
   const int nx = D.nx, ny = D.ny;
   const double dx = D.dx, dy = D.dy;
   const double *hx = D.hx, *hy = D.hy, *bflux = D.bflux, *kappa = D.kappa;
   const double ph = D.phih[c];
   const bool tf = D.hot_face != 0;
   double s = dx * dy * D.q[c];
+  if (D.td) {
+    const double T = Ts[c], T2 = T * T;
+    s += dx * dy * (D.rho_n[c] * D.tdiag + D.sig_a[c] * (D.ca * (T2 * T2)));
+  }
   // east / west (area dy), north / south (area dx)
   if (i + 1 < nx) s -= dy * (tf ? hx[c] : 0.5 * (hx[c] + hx[c + 1]));
   else s -= dy * (bflux[ny + j] - kappa[ny + j] * ph);
@@ -310,14 +323,16 @@ __global__ void k_finish_rr(const SynthDesc *ds) {
 // RHS: the right-hand side b is formed here from the HoT (and stored)
 // rather than read.
 // MODE 0: b given in rhs (the adjoint), warm start phi; 1: b from the HoT
-// (rhs_at), warm start phi; 2: the face-averaged balance (Eq. Fij_d) by a
+// (rhs_at), warm start phi; 3: as 1 with the level-0 iterate as warm start
+// (the time-dependent form's later sub-iterations); 2: the face-averaged
+// balance (Eq. Fij_d) by a
 // defect-correction sub-iteration: b = rhs_at + corr(x) with x the level-0
 // iterate, which is also the warm start, and corr_c = sum over interior
 // faces of a_f (x_c - x_nb) + A_f (w_c + w_nb) . n_f / 2, a_f = A_f Gamma_f
 // the operator's off-diagonals and w = grad(x) / (3 sigma_t) from
 // k_wide_grad: then D1 x' = b is D1 (x' - x) = R1(x).
 template <int MODE>
-__global__ void k_cg_begin(const SynthDesc *ds, const int2 *bt) {
+__global__ void k_cg_begin(const SynthDesc *ds, const int2 *bt, int sub) {
   __shared__ double sh[kRedBlock];
   const Blk B = blk(bt);
   CDesc &D = cdesc(ds, B.p);
@@ -330,12 +345,12 @@ __global__ void k_cg_begin(const SynthDesc *ds, const int2 *bt) {
   cell_ij(cc, L.nx, i, j);
   const bool hE = i + 1 < L.nx, hW = i > 0, hN = j + 1 < L.ny, hS = j > 0;
   // warm start x for the cell and its neighbours (this kernel writes x)
-  const double *X = MODE == 2 ? L.x : D.phi;
+  const double *X = MODE >= 2 ? L.x : D.phi;
   const double xc = X[cc], xe = X[hE ? cc + 1 : cc], xw = X[hW ? cc - 1 : cc];
   const double xn = X[hN ? cc + L.nx : cc], xs = X[hS ? cc - L.nx : cc];
   const double dg = L.dg[cc], aE = L.ax[cc], aW = L.ax[hW ? cc - 1 : cc];
   const double aN = L.ay[cc], aS = L.ay[hS ? cc - L.nx : cc];
-  double b = MODE != 0 ? rhs_at(D, cc, i, j) : D.rhs[cc];
+  double b = MODE != 0 ? rhs_at(D, cc, i, j, D.td ? t_sub(D, sub) : nullptr) : D.rhs[cc];
   if (MODE == 2) {
     const double *WX = D.wx, *WY = D.wy;
     const double wxc = WX[cc], wyc = WY[cc];
@@ -1234,8 +1249,10 @@ __global__ void k_update(const SynthDesc *ds, const int2 *bt) {
   const int cc = in ? c : 0;
   const double pn = D.method ? D.lev[0].x[cc] : D.phih[cc];
   const double ph = D.phih[cc], po = D.phi[cc];
+  // time-dependent form: T^{m+1} = T(sub_iter), against T^m for Err(T)
+  const double tn = D.td ? t_sub(D, D.sub_iter)[cc] : 0.0, to = D.td ? D.Tm[cc] : 0.0;
   if (f1 != 0) return;
-  double num = 0.0, den = 0.0;
+  double num = 0.0, den = 0.0, numT = 0.0, denT = 0.0;
   if (in) {
     const double d = pn - po;
     num = D.V * d * d;
@@ -1244,10 +1261,43 @@ __global__ void k_update(const SynthDesc *ds, const int2 *bt) {
     D.delta[c] = dl;
     if (D.fp32) D.base[c] = po + dl;
     D.phi[c] = pn;
+    if (D.td) {
+      numT = D.V * (tn - to) * (tn - to);
+      denT = D.V * tn * tn;
+      D.Tm[c] = tn;
+    }
   }
   double a = block_sum(num, sh);
   double b = block_sum(den, sh);
   if (threadIdx.x == 0) { D.err_parts[2 * B.lb] = a; D.err_parts[2 * B.lb + 1] = b; }
+  if (D.td) {
+    a = block_sum(numT, sh);
+    b = block_sum(denT, sh);
+    if (threadIdx.x == 0) { D.err_parts_T[2 * B.lb] = a; D.err_parts_T[2 * B.lb + 1] = b; }
+  }
+}
+
+// Time-dependent form: one step of the material equation per cell (Eqs.
+// MSE_d2, R2_def, MSE_d_mtx2, elem_mtx_M),
+//   T(sub + 1) = T(sub) + R2 / D2,
+//   R2 = -cv (T(sub) - T^n) / dt + sigma_a (rho(sub) - a c T(sub)^4),
+//   D2 = cv / dt + 4 a c T(sub)^3 sigma_a,
+// with rho(sub) = rho^{m+1/2} for sub 0 and for source iteration, else the
+// synthetic solution of sub-iteration sub - 1 (the level-0 iterate).
+__global__ void k_material(const SynthDesc *ds, const int2 *bt, int sub) {
+  const Blk B = blk(bt);
+  CDesc &D = cdesc(ds, B.p);
+  const int32_t f1 = D.state[1];
+  const int c = B.lb * kRedBlock + threadIdx.x;
+  if (c >= D.N) return;
+  const double *Ts = t_sub(D, sub);
+  double *To = ((sub & 1) ? D.Tsub1 : D.Tsub0);
+  const double rho = (sub == 0 || !D.method) ? D.phih[c] : D.lev[0].x[c];
+  const double T = Ts[c], T2 = T * T, sa = D.sig_a[c], cv = D.cv[c], dt = D.dt;
+  const double R2 = -cv * (T - D.Tn[c]) / dt + sa * (rho - D.ca * (T2 * T2));
+  const double D2 = cv / dt + 4.0 * D.ca * (T2 * T) * sa;
+  if (f1 != 0) return;
+  To[c] = T + R2 / D2;
 }
 
 // One workgroup per problem: Err = sqrt(num/den) -> history, counters, done
@@ -1270,13 +1320,27 @@ __device__ inline void err_finish(CDesc &D, double *sh) {
   }
   for (int t = threadIdx.x; t < D.n_tres; t += blockDim.x) rr += D.tres_part[t];
   for (int t = threadIdx.x; t < D.n_src2; t += blockDim.x) ss += D.src2_part[t];
+  double aT = 0.0, bT = 0.0;
+  if (D.td)
+    for (int t = threadIdx.x; t < npart; t += blockDim.x) {
+      aT += D.err_parts_T[2 * t];
+      bT += D.err_parts_T[2 * t + 1];
+    }
   const double dmin = D.last_err[1];
   double num = block_sum(a, sh);
   double den = block_sum(b, sh);
   rr = block_sum(rr, sh);
   ss = block_sum(ss, sh) * D.sw;
+  if (D.td) {
+    aT = block_sum(aT, sh);
+    bT = block_sum(bT, sh);
+  }
   if (threadIdx.x == 0) {
     double err = den > 0.0 ? sqrt(num / den) : (num == 0.0 ? 0.0 : INFINITY);
+    if (D.td) {    // max(Err(rho), Err(T)), the criterion after Eq. Err_W
+      const double eT = bT > 0.0 ? sqrt(aT / bT) : (aT == 0.0 ? 0.0 : INFINITY);
+      err = eT > err ? eT : err;
+    }
     const double tres = ss > 0.0 ? sqrt(rr / ss) : (rr == 0.0 ? 0.0 : INFINITY);
     const int m = state[0];
     D.err_hist[m] = err;
@@ -1315,7 +1379,11 @@ __device__ inline void source_tile(CDesc &D, const Blk &B, double *s_sc, double 
     const int i = i0 + (t & (kSrcT - 1)), j = j0 + t / kSrcT;
     const bool in = i < nx && j < ny;
     const int c = in ? j * nx + i : 0;
-    const double sc = (D.sig_s[c] * D.phi[c] + D.q[c]) / kFourPi;
+    double sc = (D.sig_s[c] * D.phi[c] + D.q[c]) / kFourPi;
+    if (D.td) {                  // emission sigma_a a c (T^m)^4 / (4 pi)
+      const double T = D.Tm[c], T2 = T * T;
+      sc = (D.sig_s[c] * D.phi[c] + D.sig_a[c] * (D.ca * (T2 * T2)) + D.q[c]) / kFourPi;
+    }
     const double dq = D.base[c] / kFourPi;
     const double pq = D.phi[c] / kFourPi;
     if (f1 != 0) return;
@@ -1455,6 +1523,10 @@ SynthDesc make_synth_desc(const PlanDev &P) {
   D.mom_part = P.mom_part; D.sw = P.sw; D.swm = P.swm; D.swe = P.swe;
   D.hot_face = P.method == GSIS_GSIS ? P.hot_face : 0;
   D.ftp = P.ftp;
+  D.sig_a = P.sig_a;
+  D.td = P.td; D.sub_iter = P.sub_iter; D.tdiag = P.tdiag; D.ca = P.ca; D.dt = P.dt;
+  D.cv = P.cv; D.Tn = P.Tn; D.rho_n = P.rho_n; D.Tm = P.Tm; D.Tsub0 = P.Tsub0;
+  D.Tsub1 = P.Tsub1; D.err_parts_T = P.err_parts_T;
   D.hx = P.hx; D.hy = P.hy; D.rhs = P.rhs; D.phi = P.phi; D.delta = P.delta; D.base = P.base;
   D.src = P.src; D.dynq = P.dynq;
   D.cg_r = P.cg_r; D.cg_r2 = P.cg_r2; D.cg_z = P.cg_z; D.cg_p = P.cg_p;
@@ -1532,12 +1604,14 @@ void launch_hot(const SynthSet &S, hipStream_t s, bool combine) {
 // run waits once per solve. Without it (batches, graph capture) exactly
 // synth_max_iter iterations are launched and converged problems skip their
 // kernels.
-void launch_synth_solve(const SynthSet &S, hipStream_t s, int32_t *host_flag, int rhs_mode) {
+void launch_synth_solve(const SynthSet &S, hipStream_t s, int32_t *host_flag, int rhs_mode,
+                        int sub) {
   const SynthDesc *ds = S.desc;
   const dim3 gc(S.nb_cell), bk(kRedBlock);
-  if (rhs_mode == 1) hipLaunchKernelGGL(k_cg_begin<1>, gc, bk, 0, s, ds, S.bt_cell);
-  else if (rhs_mode == 2) hipLaunchKernelGGL(k_cg_begin<2>, gc, bk, 0, s, ds, S.bt_cell);
-  else hipLaunchKernelGGL(k_cg_begin<0>, gc, bk, 0, s, ds, S.bt_cell);
+  if (rhs_mode == 1) hipLaunchKernelGGL(k_cg_begin<1>, gc, bk, 0, s, ds, S.bt_cell, sub);
+  else if (rhs_mode == 2) hipLaunchKernelGGL(k_cg_begin<2>, gc, bk, 0, s, ds, S.bt_cell, sub);
+  else if (rhs_mode == 3) hipLaunchKernelGGL(k_cg_begin<3>, gc, bk, 0, s, ds, S.bt_cell, sub);
+  else hipLaunchKernelGGL(k_cg_begin<0>, gc, bk, 0, s, ds, S.bt_cell, sub);
   vcycle(S, 0, s);
   const int guess = host_flag ? host_flag[8] : 0;
   for (int it = 0; it < S.synth_max_iter; ++it) {
@@ -1563,6 +1637,10 @@ void launch_synth_solve(const SynthSet &S, hipStream_t s, int32_t *host_flag, in
       }
     }
   }
+}
+
+void launch_material(const SynthSet &S, hipStream_t s, int sub) {
+  hipLaunchKernelGGL(k_material, dim3(S.nb_cell), dim3(kRedBlock), 0, s, S.desc, S.bt_cell, sub);
 }
 
 void launch_update(const SynthSet &S, hipStream_t s) {

@@ -62,6 +62,8 @@ struct TArgs {
   int32_t *hand_err;          // set when a part gave up waiting for the one below
   double *tres_part;          // [n_rtiles][ordinate pairs] sum of w r^2 per residual wave
   double *src2_part;          // [ceil(N / 256)] sum of src^2 per block of cells
+  const double *In;           // time-dependent form: I^n, [K][N] like the intensity
+  double tdiag;               // 1/(c dt) (the records' sigma_t already include it)
 };
 
 TArgs make_args(const PlanDev &P) {
@@ -86,6 +88,8 @@ TArgs make_args(const PlanDev &P) {
   a.hand_err = P.state + 4;
   a.tres_part = P.tres_part;
   a.src2_part = P.src2_part;
+  a.In = P.In;
+  a.tdiag = P.tdiag;
   return a;
 }
 
@@ -588,6 +592,7 @@ struct RSlot {
   double sube;         // FP32 mode: phi^m/(4 pi) there
   double src;          // source at the cell (diagonal d)
   double2 c0, c1, st;  // its coefficient record
+  double in[2];        // time-dependent form: I^n at the cell, per ordinate
   unsigned ic;         // its storage index
 };
 
@@ -625,7 +630,9 @@ __device__ inline int ordinate_pairs(A &a) {
 // through buffer resources: for a lane with no cell it lies on another
 // diagonal or out of the buffer (read as 0), and the value is dropped.
 // kB < 0: no second ordinate (its loads repeat kA's, its stores are dropped).
-template <typename T, class A>
+// TD: the time-dependent form's residual (Eq. RTE_d_res) also takes
+// + I^n / (c dt); the -(1/(c dt)) I^m term rides in the records' sigma_t.
+template <typename T, bool TD = false, class A>
 __device__ __forceinline__ void resid_tile(A &a, const int tile, const int kA, const int kB,
                                            const int wave, const int slot) {
   constexpr bool kF32 = sizeof(T) == 4;
@@ -640,7 +647,7 @@ __device__ __forceinline__ void resid_tile(A &a, const int tile, const int kA, c
   const bool hasB = kB >= 0;
   const int kk[2] = {kA, hasB ? kB : kA};
   double ax[2], ay[2], wr[2];
-  __amdgpu_buffer_rsrc_t Ib[2], Ob[2];
+  __amdgpu_buffer_rsrc_t Ib[2], Ob[2], Nb[2];
 #pragma unroll
   for (int o = 0; o < 2; ++o) {
     ax[o] = a.amu[kk[o]];
@@ -648,6 +655,7 @@ __device__ __forceinline__ void resid_tile(A &a, const int tile, const int kA, c
     wr[o] = (o == 0 || hasB) ? a.w[kk[o]] : 0.0;   // weight of w r^2 (no double count)
     Ib[o] = buf_rsrc(Iin_of<T>(a) + (size_t)kk[o] * N, (size_t)N * sizeof(T));
     Ob[o] = buf_rsrc(Iout_of<T>(a) + (size_t)kk[o] * N, (o == 0 || hasB) ? (size_t)N * sizeof(T) : 0);
+    if constexpr (TD) Nb[o] = buf_rsrc(a.In + (size_t)kk[o] * N, (size_t)N * 8);
   }
   const double hdx = 0.5 * a.dx, hdy = 0.5 * a.dy;
   const bool second = a.order >= 2, lim = a.limiter != 0;
@@ -739,6 +747,10 @@ __device__ __forceinline__ void resid_tile(A &a, const int tile, const int kA, c
     sl.c0 = buf_ld128(Cb, ic * 48u);
     sl.c1 = buf_ld128(Cb, ic * 48u + 16u);
     sl.st = buf_ld128(Cb, ic * 48u + 32u);
+    if constexpr (TD) {
+      sl.in[0] = buf_ld64(Nb[0], ic * 8u);
+      sl.in[1] = buf_ld64(Nb[1], ic * 8u);
+    }
   };
   RSlot<T> ring[PF];
 #pragma unroll
@@ -769,7 +781,8 @@ __device__ __forceinline__ void resid_tile(A &a, const int tile, const int kA, c
         double Fe, Fn;
         face_pair(u, UE, UW, UN, US, sl.c0, sl.c1, hdx, hdy, second, lim, Fe, Fn);
         const double FeW = x > 0 ? Fe_p[o] : inW[o];
-        const double r = sl.src - sl.st.x * u - ax[o] * (Fe - FeW) - ay[o] * (Fn - FnS);
+        double r = sl.src - sl.st.x * u - ax[o] * (Fe - FeW) - ay[o] * (Fn - FnS);
+        if constexpr (TD) r += a.tdiag * sl.in[o];
         const double inv = rcp64(inv0 + (ax[o] + ay[o]));   // as in the recurrence
         double t0 = kF32 ? u - subc : u;
         const double tw = fma(-(ax[o] * inv), kF32 ? uw[o] - subw : uw[o], t0);
@@ -789,7 +802,7 @@ __device__ __forceinline__ void resid_tile(A &a, const int tile, const int kA, c
   if (lane == 0) a.tres_part[slot] = rr;
 }
 
-template <typename T>
+template <typename T, bool TD = false>
 __global__ void __launch_bounds__(kRWaves * 64) k_resid(TArgs a) {
   if (a.state[1] != 0) return;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform per wave
@@ -807,7 +820,7 @@ __global__ void __launch_bounds__(kRWaves * 64) k_resid(TArgs a) {
   if (pi >= ordinate_pairs(a)) return;
   int kA, kB;
   ordinate_pair(a, pi, kA, kB);
-  resid_tile<T>(a, tile, kA, kB, wave, tile * ordinate_pairs(a) + pi);
+  resid_tile<T, TD>(a, tile, kA, kB, wave, tile * ordinate_pairs(a) + pi);
 }
 
 // Batched residual: one workgroup per item (problem, tile, group of four
@@ -1295,8 +1308,44 @@ void launch_residual(const PlanDev &P, hipStream_t s) {
   for (int q = 0; q < 4; ++q) pairs += (P.qoff[q + 1] - P.qoff[q] + 1) / 2;
   const int G = (pairs + kRWaves - 1) / kRWaves;
   const int nb = 8 * ((G + 7) / 8) * P.n_rtiles;
-  if (a.fp32) hipLaunchKernelGGL(k_resid<float>, dim3(nb), dim3(kRWaves * 64), 0, s, a);
+  if (P.td) hipLaunchKernelGGL((k_resid<double, true>), dim3(nb), dim3(kRWaves * 64), 0, s, a);
+  else if (a.fp32) hipLaunchKernelGGL(k_resid<float>, dim3(nb), dim3(kRWaves * 64), 0, s, a);
   else hipLaunchKernelGGL(k_resid<double>, dim3(nb), dim3(kRWaves * 64), 0, s, a);
+}
+
+namespace {
+// Start of a time step: I^n = stored I + pending correction / (4 pi) for
+// every cell-ordinate (blocks over ordinate planes), rho^n = rho^m and T^n =
+// T^m per cell, and the step's iteration count, stop flag and smallest change
+// cleared (block 0).
+__global__ void k_td_begin(TArgs a, double *In, const double *Tm, double *Tn, double *rho_n,
+                           int32_t *state, double *last_err) {
+  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  const int kk = blockIdx.y;
+  if (kk < a.K) {
+    if (t < a.N) {
+      const int q = quadrant_of(a, kk);
+      const double *DQ = a.dynq + ((size_t)q * 3 + 1) * a.N;
+      In[(size_t)kk * a.N + t] = Iin_of<double>(a)[(size_t)kk * a.N + t] + DQ[t];
+    }
+    return;
+  }
+  if (t < a.N) {
+    Tn[t] = Tm[t];
+    rho_n[t] = a.phi[t];
+  }
+  if (t == 0) {
+    state[0] = 0;
+    state[1] = 0;
+    last_err[1] = INFINITY;
+  }
+}
+}  // namespace
+
+void launch_td_begin(const PlanDev &P, hipStream_t s) {
+  const TArgs a = make_args(P);
+  hipLaunchKernelGGL(k_td_begin, dim3((P.N + 255) / 256, P.K + 1), dim3(256), 0, s, a, P.In,
+                     (const double *)P.Tm, P.Tn, P.rho_n, P.state, P.last_err);
 }
 
 void launch_sweep(const PlanDev &P, hipStream_t s) {

@@ -30,6 +30,7 @@ struct gsis_plan {
   std::vector<double> I0_host;    // warm start in the internal layout (may be empty)
   std::vector<float> I0_host_f;   // FP32-mixed: I0 - phi0/(4 pi) in the internal layout
   std::vector<double> phi0_host;  // phi of the warm start
+  std::vector<double> T0_host;    // time-dependent form: initial temperature
   std::vector<void *> allocs;
   double *host_scal = nullptr;    // pinned
   // profiling: per iteration GSIS_NUM_PHASES + 1 events bracketing the phases

@@ -67,6 +67,11 @@ class gsis_adjoint_info(ctypes.Structure):
                 ("forward_iter", ctypes.c_int32)]
 
 
+class gsis_material(ctypes.Structure):
+    _fields_ = [("c", ctypes.c_double), ("a", ctypes.c_double), ("dt", ctypes.c_double),
+                ("cv", ctypes.c_void_p), ("T0", ctypes.c_void_p), ("sub_iter", ctypes.c_int32)]
+
+
 class gsis_result(ctypes.Structure):
     _fields_ = [("phi", ctypes.c_void_p), ("Fx", ctypes.c_void_p), ("Fy", ctypes.c_void_p),
                 ("err_hist", ctypes.c_void_p), ("tres_hist", ctypes.c_void_p),
@@ -79,7 +84,7 @@ EXPORTS = ("gsis_ctx_create", "gsis_ctx_destroy", "gsis_last_error", "gsis_optio
            "gsis_batch_create", "gsis_batch_destroy", "gsis_batch_iterate", "gsis_batch_status",
            "gsis_batch_read", "gsis_batch_reset", "gsis_batch_get_tuning", "gsis_solve_batch",
            "gsis_plan_adjoint", "gsis_adjoint", "gsis_version", "gsis_solve_noalloc",
-           "gsis_plan_synth_vcycles")
+           "gsis_plan_synth_vcycles", "gsis_td_create", "gsis_td_advance", "gsis_td_read")
 
 
 def load():
@@ -130,6 +135,10 @@ def load():
     lib.gsis_adjoint.argtypes = [vp, ctypes.POINTER(gsis_problem), ctypes.POINTER(gsis_options),
                                  vp, vp, vp, vp, vp, vp, ctypes.POINTER(gsis_result),
                                  ctypes.POINTER(gsis_adjoint_info)]
+    lib.gsis_td_create.argtypes = [vp, ctypes.POINTER(gsis_problem), ctypes.POINTER(gsis_options),
+                                   ctypes.POINTER(gsis_material), ctypes.POINTER(vp)]
+    lib.gsis_td_advance.argtypes = [vp, i32, ip, _dp]
+    lib.gsis_td_read.argtypes = [vp, vp, vp, vp, vp]
     lib.gsis_version.argtypes = []
     lib.gsis_version.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -469,3 +478,61 @@ def gsis_solve_batch(ctx, probs, **opts):
                         tres_hist=thist[:res[i].n_iter], n_iter=res[i].n_iter,
                         final_err=res[i].final_err))
     return out, st
+
+
+class TDPlan(Plan):
+    """gsis_td_create / gsis_td_advance / gsis_td_read: the time-dependent
+    form. c, a, dt scalars; cv and T0 per cell (arrays like the problem's,
+    or scalars); I0 the initial intensity [N, K] or None."""
+
+    def __init__(self, ctx, prob, T0, c=1.0, a=1.0, dt=1.0, cv=1.0, sub_iter=4, I0=None, **opts):
+        lib = load()
+        self.ctx = ctx
+        self.args = _Args(prob, I0)
+        N = self.args.nx * self.args.ny
+        self.N = N
+
+        def per_cell(v):
+            if _is_torch(v) or isinstance(v, np.ndarray):
+                return self.args._ptr(v)
+            if self.args.device:
+                import torch
+                t = torch.full((N,), float(v), dtype=torch.float64,
+                               device=self.args.keep[0].device)
+                self.args.keep.append(t)
+                return t.data_ptr()
+            return self.args._ptr(np.full(N, float(v)))
+        mat = gsis_material(float(c), float(a), float(dt), per_cell(cv), per_cell(T0),
+                            int(sub_iter))
+        o = make_options(**opts)
+        o.I0 = self.args.I0
+        o.device_ptrs = 1 if self.args.device else 0
+        o.stream = _stream_handle() if self.args.device else None
+        self.opts = o
+        h = ctypes.c_void_p()
+        _check(lib.gsis_td_create(ctx.handle, ctypes.byref(self.args.s), ctypes.byref(o),
+                                  ctypes.byref(mat), ctypes.byref(h)), ctx)
+        self.handle = h
+
+    def advance(self, n_steps):
+        """Run n_steps time steps; returns (status, inner iterations per step,
+        final Err per step)."""
+        its = (ctypes.c_int32 * max(n_steps, 1))()
+        errs = (ctypes.c_double * max(n_steps, 1))()
+        st = load().gsis_td_advance(self.handle, int(n_steps), its, errs)
+        _check(st, self.ctx, allow=(GSIS_OK, GSIS_NOT_CONVERGED, GSIS_DIVERGED))
+        return st, list(its)[:n_steps], list(errs)[:n_steps]
+
+    def read_td(self):
+        """dict(rho, T, Fx, Fy) of the current state."""
+        N = self.N
+        if self.args.device:
+            import torch
+            dev = self.args.keep[0].device
+            outs = [torch.empty(N, dtype=torch.float64, device=dev) for _ in range(4)]
+            p = lambda t: t.data_ptr()
+        else:
+            outs = [np.empty(N) for _ in range(4)]
+            p = lambda a: a.ctypes.data
+        _check(load().gsis_td_read(self.handle, *[p(x) for x in outs]), self.ctx)
+        return dict(rho=outs[0], T=outs[1], Fx=outs[2], Fy=outs[3])
