@@ -102,8 +102,10 @@ enum { GSIS_HOT_CENTRAL = 0, GSIS_HOT_TRANSPORT = 1 };
 typedef struct {
   int32_t method;        /* GSIS_SI or GSIS_GSIS (default) */
   int32_t precision;     /* GSIS_FP64 (default) or GSIS_FP32_MIXED: FP32
-                            intensities, sweep and moment sums; FP64
-                            synthetic solve, update and Err */
+                            intensities (stored as deviations from
+                            phi/(4 pi)) and FP32 wavefront recurrence;
+                            FP64 residual, moment sums, synthetic solve,
+                            update and Err */
   int32_t order;         /* 1 = first-order upwind, 2 = second order (default) */
   int32_t limiter;       /* Barth-Jespersen limiter on (1, default) or off */
   int32_t alsm;          /* 1 = adaptive least squares (Sec. 5.2, default),
@@ -123,7 +125,10 @@ typedef struct {
   int32_t max_iter;      /* outer iteration cap, >= 1; default 1000 */
   double synth_rtol;     /* synthetic CG stops at ||r|| <= synth_rtol ||r0||
                             (r0: residual of the warm start, the previous
-                            phi) or at ||r|| <= 1e-14 ||b||; default 1e-4 */
+                            phi) or at ||r|| <= 1e-14 ||b||; default 0.1.
+                            The fixed point does not depend on it (at the
+                            fixed point r0 = 0); it trades V-cycles per outer
+                            iteration against outer iterations */
   int32_t synth_max_iter;/* CG iteration cap per outer iteration; default 50 */
   const double *I0;      /* optional warm start [nx*ny][K] (cell-major, the
                             caller's ordinate order); NULL = zero */

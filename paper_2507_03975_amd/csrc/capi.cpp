@@ -58,7 +58,7 @@ gsis_status gsis_options_default(gsis_options *o) {
   o->hot_face = GSIS_HOT_CENTRAL;
   o->tol = 1e-6;
   o->max_iter = 1000;
-  o->synth_rtol = 1e-4;
+  o->synth_rtol = 0.1;
   o->synth_max_iter = 50;
   o->cfl_p = 0.0;
   o->beta = 0.0;
@@ -654,6 +654,10 @@ static gsis_status plan_create(gsis_ctx *ctx, const gsis_problem *p, const gsis_
   if (P.chain_parts > 1 &&
       (st = dalloc(pl, &P.hand, (size_t)K * (P.chain_parts - 1) * nx)))
     return bail(st);
+  if (f32) {
+    std::vector<float> sdqf(sdq.begin(), sdq.end());
+    if ((st = upload(pl, &P.sdq_f, sdqf))) return bail(st);
+  }
   if (P.method == GSIS_GSIS && P.hot_face == GSIS_HOT_TRANSPORT &&
       (st = dalloc(pl, &P.ftp, (size_t)8 * N)))
     return bail(st);

@@ -158,6 +158,7 @@ struct PlanDev {
   int chain_parts = 1;         // workgroups per ordinate in the recurrence
   int chain_rows = 0;          // rows per part (a multiple of 64, <= 1024)
   double *sdq = nullptr;       // [q][N] sigma_t + pseudo-time shift per stored cell
+  float *sdq_f = nullptr;      // FP32-mixed: the same in FP32 (FP32 recurrence)
   int2 *rtiles = nullptr;      // residual-kernel tiles (first diagonal, first row)
   int *dso = nullptr;          // [kDiagPad + nx + ny - 1 + kDiagPad] storage index of
                                // row 0 on each anti-diagonal (dg_off - ylo), padded

@@ -20,8 +20,9 @@
 // the sweep started from), and the read adds base/(4 pi) with
 // base = phi^m + delta. Itilde is the anisotropic part plus the last
 // change of phi, small where the medium is thick, so its FP32 rounding stays
-// far below the cancellation sigma_t I - sigma_s phi/(4 pi); every residual,
-// sweep and moment operation runs in FP64.
+// far below the cancellation sigma_t I - sigma_s phi/(4 pi). The residual
+// (with that cancellation) and the moment sums run in FP64; the wavefront
+// recurrence, which only propagates the residual's increments, runs in FP32.
 #include "gsis_internal.h"
 #include "wave_ops.h"
 
@@ -53,6 +54,7 @@ struct TArgs {
   const double *cellq, *dynq;
   double *rowbuf;
   const double *sdq;
+  const float *sdq_f;   // FP32-mixed: the same diagonal in FP32 (the FP32 recurrence)
   const int2 *rtiles;
   int n_rtiles;
   const int *dso;    // row-0 storage index per diagonal, at offset kDiagPad
@@ -78,7 +80,7 @@ TArgs make_args(const PlanDev &P) {
   a.bnd = P.bnd; a.phih = P.phih; a.Fx = P.Fx; a.Fy = P.Fy; a.bflux = P.bflux;
   a.mom_part = P.mom_part;
   a.cellq = P.cellq; a.dynq = P.dynq; a.rowbuf = P.rowbuf;
-  a.sdq = P.sdq; a.rtiles = P.rtiles; a.n_rtiles = P.n_rtiles;
+  a.sdq = P.sdq; a.sdq_f = P.sdq_f; a.rtiles = P.rtiles; a.n_rtiles = P.n_rtiles;
   a.dso = P.dso;
   a.fp32 = P.precision == GSIS_FP32_MIXED ? 1 : 0;
   a.phi = P.phi;
@@ -868,10 +870,20 @@ constexpr int kCMaxW = 16;           // up to 1024 rows per pass
 // Loads use the index dso[d] + y of the lane's row on the step's diagonal
 // d: for a lane with no cell it points at another diagonal or out of the
 // buffer (the hardware returns 0 there), and the value is never used.
+//
+// The recurrence runs in the storage type T: FP64, or FP32 in the
+// FP32-mixed form, where its values are deviations from phi^m/(4 pi) (small
+// where the medium is thick) and its right-hand side already holds the
+// residual formed in FP64; the diagonal sigma_t + shift then comes from an
+// FP32 copy (sdq_f) and 1/d from the single-precision reciprocal.
+__device__ inline float rcp_t(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline double rcp_t(double x) { return rcp64(x); }
+
 template <typename T, bool MULTI, bool SPLIT = false, class A>
 __device__ __forceinline__ void chain_ordinate(A &a, const int kk, const int part = 0,
                                                const int np = 1) {
   constexpr int PF = kCPF, LAG = kCLag, R = 4 * kCLag;
+  constexpr bool kF32 = sizeof(T) == 4;
   static_assert((R & (R - 1)) == 0 && LAG == PF, "ring sizes");
   static_assert(!(SPLIT && MULTI), "a split recurrence runs one pass per part");
   static_assert(kCMaxW * kCLag + 2 * kCPF <= kDiagPad, "diagonal table padding");
@@ -880,16 +892,18 @@ __device__ __forceinline__ void chain_ordinate(A &a, const int kk, const int par
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform per wave
   const int rows_pp = blockDim.x;
-  const double ax = a.amu[kk], ay = a.aeta[kk], axy = ax + ay;
+  const T ax = (T)a.amu[kk], ay = (T)a.aeta[kk], axy = (T)(a.amu[kk] + a.aeta[kk]);
   const T *Ok = Iout_of<T>(a) + (size_t)kk * N;
   const __amdgpu_buffer_rsrc_t Ob = buf_rsrc(Ok, (size_t)N * sizeof(T));
-  const __amdgpu_buffer_rsrc_t Sb = buf_rsrc(a.sdq + (size_t)q * N, (size_t)N * 8);
+  const __amdgpu_buffer_rsrc_t Sb =
+      kF32 ? buf_rsrc(a.sdq_f + (size_t)q * N, (size_t)N * 4)
+           : buf_rsrc(a.sdq + (size_t)q * N, (size_t)N * 8);
   // read through the constant address space: wave-uniform reads of it are
   // scalar loads and stay out of the vector memory counter
   const __attribute__((address_space(4))) int *DS =
       (const __attribute__((address_space(4))) int *)(a.dso + kDiagPad);
   double *RB = a.rowbuf + (size_t)kk * 3 * nx;
-  __shared__ double edge[kCMaxW][R];
+  __shared__ T edge[kCMaxW][R];
   // SPLIT: Hr the part below's top row (read), Hw this part's (written;
   // an empty resource for the top part)
   unsigned long long *Hr = nullptr;
@@ -916,24 +930,26 @@ __device__ __forceinline__ void chain_ordinate(A &a, const int kk, const int par
     // The ring is filled by a first block of steps before any lane's row
     // starts (no lane acts there), so every block of the loop, the first
     // included, runs the same code and the loads keep PF steps in flight.
-    T rb_b[PF] = {};
-    double rb_sd[PF] = {}, rb_v[PF] = {};
+    T rb_b[PF] = {}, rb_sd[PF] = {};
+    double rb_v[PF] = {};
     unsigned rb_i[PF] = {};
     auto load = [&](int t, int so, int st) {  // step st, row-0 index so of its diagonal
       const unsigned i = (unsigned)(so + y);
       rb_i[t] = i;
-      if constexpr (sizeof(T) == 8)
+      if constexpr (sizeof(T) == 8) {
         rb_b[t] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(Ob, (int)(i * 8u), 0, 0));
-      else
+        rb_sd[t] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(Sb, (int)(i * 8u), 0, 0));
+      } else {
         rb_b[t] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(Ob, (int)(i * 4u), 0, 0));
-      rb_sd[t] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(Sb, (int)(i * 8u), 0, 0));
+        rb_sd[t] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(Sb, (int)(i * 4u), 0, 0));
+      }
       if constexpr (MULTI) {
         // v below the first row of a later pass (column = step for lane 0)
         const unsigned c = (unsigned)min(max(st, 0), nx - 1);
         rb_v[t] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(RBr, (int)(c * 8u), 0, 0));
       }
     };
-    double vp = 0.0;
+    T vp = 0;
     // SPLIT, wave 0 of a part above the first: lane l < LAG holds the hand-over
     // entry of column (block's first step) + l, loaded one block ahead; 0 for
     // columns outside the grid
@@ -945,34 +961,37 @@ __device__ __forceinline__ void chain_ordinate(A &a, const int kk, const int par
       // v below lane 0 for the block's steps: the wave below's top lane
       // (written at least one barrier ago), the part below, the previous
       // pass, or 0
-      double bl[LAG];
+      T bl[LAG];
       if (wave > 0) {
 #pragma unroll
         for (int t2 = 0; t2 < LAG; ++t2) bl[t2] = edge[wave - 1][(sb - 1 + t2) & (R - 1)];
       } else if (SPLIT && part > 0) {
-        hand_take<LAG>(Hr, nx, sb, hv, gave_up, a.hand_err, bl);   // lane 0's column is its step
+        double hb[LAG];
+        hand_take<LAG>(Hr, nx, sb, hv, gave_up, a.hand_err, hb);   // lane 0's column is its step
+#pragma unroll
+        for (int t2 = 0; t2 < LAG; ++t2) bl[t2] = (T)hb[t2];
       } else {
 #pragma unroll
-        for (int t2 = 0; t2 < LAG; ++t2) bl[t2] = (MULTI && y0 > 0) ? rb_v[t2] : 0.0;
+        for (int t2 = 0; t2 < LAG; ++t2) bl[t2] = (MULTI && y0 > 0) ? (T)rb_v[t2] : (T)0;
       }
       int so[LAG];                            // diagonals of the loads issued in this block
 #pragma unroll
       for (int t2 = 0; t2 < LAG; ++t2) so[t2] = DS[y0 + sb + PF + t2];
-      double vv[LAG];
+      T vv[LAG];
 #pragma unroll
       for (int t2 = 0; t2 < LAG; ++t2) {
         const int s = sb + t2;
         const int x = s - xo;
         const bool act = (unsigned)x < (unsigned)nx;
-        const double vS = shr1_fill(vp, bl[t2]);
-        const double inv = rcp64(rb_sd[t2] + axy);
-        const double vn = fma(ax * inv, vp, fma(ay * inv, vS, (double)rb_b[t2]));
-        const double v = act ? vn : vp;
-        buf_store((T)v, Ob, act ? rb_i[t2] * (unsigned)sizeof(T) : kNoCell);
-        if constexpr (MULTI) buf_store(v, RBw, handoff && act ? (unsigned)x * 8u : kNoCell);
+        const T vS = shr1_fill(vp, bl[t2]);
+        const T inv = rcp_t(rb_sd[t2] + axy);
+        const T vn = fma(ax * inv, vp, fma(ay * inv, vS, rb_b[t2]));
+        const T v = act ? vn : vp;
+        buf_store(v, Ob, act ? rb_i[t2] * (unsigned)sizeof(T) : kNoCell);
+        if constexpr (MULTI) buf_store((double)v, RBw, handoff && act ? (unsigned)x * 8u : kNoCell);
         if constexpr (SPLIT) {
           if (wave == nw - 1 && part + 1 < np)
-            hand_put(Hw, v, top_lane && act ? (unsigned)x * 8u : kNoCell);
+            hand_put(Hw, (double)v, top_lane && act ? (unsigned)x * 8u : kNoCell);
         }
         vp = v;
         vv[t2] = v;

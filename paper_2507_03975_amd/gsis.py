@@ -225,7 +225,7 @@ class _Args:
 
 
 def make_options(method=GSIS_GSIS, precision=GSIS_FP64, order=2, limiter=1, alsm=1,
-                 hot_face=GSIS_HOT_CENTRAL, tol=1e-6, max_iter=1000, synth_rtol=1e-4,
+                 hot_face=GSIS_HOT_CENTRAL, tol=1e-6, max_iter=1000, synth_rtol=0.1,
                  synth_max_iter=50, profile=0, cfl_p=0.0, beta=0.0, graph=1, synth_form=0,
                  synth_sub=4):
     o = gsis_options()

@@ -33,7 +33,7 @@ def test_options_default():
     assert gsis.load().gsis_options_default(ctypes.byref(o)) == 0
     assert (o.method, o.precision, o.order, o.limiter, o.alsm, o.hot_face) == (1, 0, 2, 1, 1, 0)
     assert o.tol == 1e-6 and o.max_iter == 1000 and o.synth_max_iter == 50
-    assert o.synth_rtol == 1e-4 and o.cfl_p == 0.0 and o.beta == 0.0
+    assert o.synth_rtol == 0.1 and o.cfl_p == 0.0 and o.beta == 0.0
     assert gsis.load().gsis_options_default(None) == gsis.GSIS_E_INVALID_ARG
 
 

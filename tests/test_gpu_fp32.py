@@ -1,7 +1,8 @@
 """FP32-mixed form: FP32 storage of the angular intensity (as a deviation
-from the FP64 scalar flux), FP64 residual, sweep, moments, synthetic solve
-and Err. Compared with the FP64 oracle; the stated bound for converged
-results is 1e-5 relative (max norm over the field, relative to its max)."""
+from the FP64 scalar flux) and an FP32 wavefront recurrence; FP64 residual,
+moments, synthetic solve and Err. Compared with the FP64 oracle; the stated
+bound for converged results is 1e-5 relative (max norm over the field,
+relative to its max)."""
 import sys
 
 import numpy as np
@@ -58,13 +59,14 @@ def test_fp32_fixed_point(ctx, case):
         p, kw = inputs.checkerboard_blocks(64, inputs.quad_product(2, 16)), dict(limiter=0,
                                                                                  beta=10.0)
     _say("fp32 fixed point %s" % case)
-    # In a thin medium the stored deviation is as large as I itself, and Err
-    # levels off near 1e-10 (the FP32 floor); 600 iterations reach it.
+    # In a thin medium the stored deviation is as large as I itself and the
+    # FP32 recurrence rounds it at every step of a chain, so Err levels off
+    # near 1e-8 (the FP32 floor); 600 iterations reach it.
     g = gsis.gsis_solve(ctx, p, precision=gsis.GSIS_FP32_MIXED, tol=1e-10, max_iter=600,
                         synth_rtol=1e-12, synth_max_iter=300, **kw)
     o = oracle.solve(p, tol=1e-12, max_iter=3000, **kw)
     assert o["status"] == 0
-    assert g["status"] in (gsis.GSIS_OK, gsis.GSIS_NOT_CONVERGED) and g["final_err"] < 1e-8
+    assert g["status"] in (gsis.GSIS_OK, gsis.GSIS_NOT_CONVERGED) and g["final_err"] < 1e-7
     errs = [_rel(g[f], o[f]) for f in ("phi", "Fx", "Fy")]
     _say("  fp32 vs oracle: phi %.2e Fx %.2e Fy %.2e" % tuple(errs))
     assert max(errs) < FP32_BOUND
