@@ -175,6 +175,7 @@ gsis_status build_tables(gsis_batch *b, const std::vector<int> &act) {
   for (int a = 0; a < n; ++a) {
     const PlanDev &P = b->subs[act[a]]->P;
     D[a] = make_synth_desc(P);
+    D[a].n_tres = P.n_rtiles * residual_pairs(P);   // the batch's residual kernel's partials
     max_lc = std::max(max_lc, D[a].lc);
     min_lc = std::min(min_lc, D[a].lc);
     lds = std::max(lds, P.S.coarse_lds);
@@ -388,7 +389,7 @@ gsis_status gsis_batch_create(gsis_ctx *ctx, int32_t n, const gsis_problem *p,
   }
   // -- tables of all problems
   if ((st = balloc(b, &b->counter, 1))) return bail(st);
-  b->split = b->subs[0]->P.sweep_impl == 0;
+  b->split = b->subs[0]->P.sweep_impl == 0 || b->subs[0]->P.sweep_impl == 3;
   b->S.synth_max_iter = o->synth_max_iter;
   b->synth_cap = o->synth_max_iter;
   if ((st = build_tables(b, all_problems(n)))) return bail(st);

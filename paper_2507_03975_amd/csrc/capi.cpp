@@ -353,6 +353,12 @@ gsis_status make_single_set(gsis_plan *pl) {
 // from the arena_cap bytes at arena (no device or pinned allocation at all;
 // profiling off).
 // With mt, the time-dependent form (backward-Euler steps of size mt->dt).
+// room for the partial sums of w r^2 of either residual kernel (a batch
+// runs its own on a plan made for the pipelined step)
+static size_t tres_slots(const PlanDev &P) {
+  return std::max((size_t)P.n_tres, (size_t)P.n_rtiles * residual_pairs(P));
+}
+
 static gsis_status plan_create(gsis_ctx *ctx, const gsis_problem *p, const gsis_options *o,
                                gsis_plan **out, char *arena, size_t arena_cap,
                                const gsis_material *mt = nullptr) {
@@ -550,10 +556,31 @@ static gsis_status plan_create(gsis_ctx *ctx, const gsis_problem *p, const gsis_
   const std::vector<int2> rtiles = residual_tiles(nx, ny);
   P.n_rtiles = (int)rtiles.size();
   {
-    // 1: two-kernel reference, 2: fused wavefront sweep (tests compare them)
+    // transport step: 0 residual kernel + recurrence, 3 pipelined (one
+    // launch); 1 two-kernel reference and 2 fused wavefront sweep (tests
+    // compare them); GSIS_SWEEP_REFERENCE=0..3 picks one. By default the
+    // pipelined step runs FP64 problems of at least 2^26 cell-ordinates,
+    // where enough rows run at once to hide its longer step (1024 x 1024 x
+    // 128: 1.46 against 1.74 ms); on smaller grids the wavefront's length
+    // decides and the split step is faster (256 x 256 x 128: 0.20 against
+    // 0.13 ms), as it is in FP32-mixed form.
     const char *e = getenv("GSIS_SWEEP_REFERENCE");
-    P.sweep_impl = (e && (e[0] == '1' || e[0] == '2')) ? e[0] - '0' : 0;
-    if (P.td) P.sweep_impl = 0;      // the time terms live in the residual kernel
+    if (e && e[0] >= '0' && e[0] <= '3' && e[1] == 0)
+      P.sweep_impl = e[0] - '0';
+    else
+      P.sweep_impl = (!f32 && (long long)N * K >= (1LL << 26)) ? 3 : 0;
+    // the time terms live in the residual kernels of the split and
+    // pipelined steps only
+    if (P.td && P.sweep_impl != 3) P.sweep_impl = 0;
+  }
+  {
+    // pipelined step: bands of 64 rows per workgroup (GSIS_PIPE_BANDS=1, 2
+    // or 4 sets it), parts to cover the rows
+    int nb = 2;
+    const char *e = getenv("GSIS_PIPE_BANDS");
+    if (e && (e[0] == '1' || e[0] == '2' || e[0] == '4') && e[1] == 0) nb = e[0] - '0';
+    P.pipe_bands = nb;
+    P.pipe_parts = P.sweep_impl == 3 ? (ny + 64 * nb - 1) / (64 * nb) : 1;
   }
   {
     // workgroups per ordinate in the recurrence (GSIS_CHAIN_PARTS=1..4 sets
@@ -576,10 +603,13 @@ static gsis_status plan_create(gsis_ctx *ctx, const gsis_problem *p, const gsis_
       rows = ((ny + parts - 1) / parts + 63) / 64 * 64;
       if (rows <= 1024 && (parts - 1) * rows < ny) break;
     }
-    if (P.sweep_impl != 0) parts = 1;
+    if (P.sweep_impl == 1 || P.sweep_impl == 2) parts = 1;
     P.chain_parts = parts;
     P.chain_rows = parts > 1 ? rows : 0;
   }
+  // partial sums of w r^2: one per residual wave
+  P.n_tres = P.sweep_impl == 3 ? K * P.pipe_parts * P.pipe_bands
+                               : P.n_rtiles * residual_pairs(P);
 
   // -- boundary intensities in the internal ordinate order
   std::vector<double> bnd_int((size_t)P.nbf * K);
@@ -647,12 +677,12 @@ static gsis_status plan_create(gsis_ctx *ctx, const gsis_problem *p, const gsis_
       (st = dalloc(pl, &P.bflux, P.nbf)) || (st = upload(pl, &P.kappa, kap)) ||
       (st = dalloc(pl, &P.err_hist, o->max_iter)) ||
       (st = dalloc(pl, &P.tres_hist, o->max_iter)) ||
-      (st = dalloc(pl, &P.tres_part, (size_t)P.n_rtiles * residual_pairs(P))) ||
+      (st = dalloc(pl, &P.tres_part, tres_slots(P))) ||
       (st = dalloc(pl, &P.src2_part, (size_t)(N + 255) / 256)) ||
       (st = dalloc(pl, &P.state, 5)) || (st = dalloc(pl, &P.last_err, 2)))
     return bail(st);
-  if (P.chain_parts > 1 &&
-      (st = dalloc(pl, &P.hand, (size_t)K * (P.chain_parts - 1) * nx)))
+  if (std::max(P.chain_parts, P.pipe_parts) > 1 &&
+      (st = dalloc(pl, &P.hand, (size_t)K * (std::max(P.chain_parts, P.pipe_parts) - 1) * nx)))
     return bail(st);
   if (f32) {
     std::vector<float> sdqf(sdq.begin(), sdq.end());
@@ -744,7 +774,7 @@ extern "C" gsis_status gsis_plan_reset(gsis_plan *pl) {
   launch_hand_reset(P, s);
   HIPCHK(ctx, hipMemsetAsync(P.err_hist, 0, P.max_iter * sizeof(double), s));
   HIPCHK(ctx, hipMemsetAsync(P.tres_hist, 0, P.max_iter * sizeof(double), s));
-  HIPCHK(ctx, hipMemsetAsync(P.tres_part, 0, (size_t)P.n_rtiles * residual_pairs(P) * sizeof(double), s));
+  HIPCHK(ctx, hipMemsetAsync(P.tres_part, 0, tres_slots(P) * sizeof(double), s));
   HIPCHK(ctx, hipMemsetAsync(synth_vcycle_total(P), 0, sizeof(double), s));
   {
     // Err of the last iteration and the smallest ||phi^{m+1} - phi^m||_V so

@@ -38,6 +38,22 @@ __host__ __device__ inline long long dg_idx(int x, int y, int nx, int ny) {
   const int d = x + y;
   return dg_off(d, nx, ny) + (y - dg_ylo(d, nx));
 }
+// Storage index of row 0 on anti-diagonal d, dg_off(d) - dg_ylo(d), in
+// 32-bit arithmetic, for 0 <= d < nx + ny - 1 of a grid of fewer than 2^31
+// cells (every product below is at most twice the cell count).
+__host__ __device__ inline int dg_row0(int d, int nx, int ny) {
+  const int A = nx < ny ? nx : ny, B = nx < ny ? ny : nx;
+  int o;
+  if (d <= A) {
+    o = d * (d + 1) / 2;
+  } else if (d <= B) {
+    o = A * (A + 1) / 2 + (d - A) * A;
+  } else {
+    const int t = d - B;
+    o = A * (A + 1) / 2 + (B - A) * A + t * (nx + ny - 1 - B) - t * (t - 1) / 2;
+  }
+  return o - (d - nx + 1 > 0 ? d - nx + 1 : 0);
+}
 
 // One multigrid level of the synthetic operator D1 (5-point, SPD):
 //   (D x)_c = diag_c x_c - ax_c x_{c+1} - ax_{c-1} x_{c-1}
@@ -153,10 +169,14 @@ struct PlanDev {
   // rewritten after every update
   double *cellq = nullptr, *dynq = nullptr;
   double *rowbuf = nullptr;    // [K][3][nx] hand-off between sweep passes
-  unsigned long long *hand = nullptr;  // [K][chain_parts - 1][nx] row hand-over
-                               // between the workgroups of a split recurrence
+  unsigned long long *hand = nullptr;  // [K][parts - 1][nx] row hand-over between
+                               // the workgroups of one ordinate (split recurrence
+                               // or pipelined step; sized for the larger)
   int chain_parts = 1;         // workgroups per ordinate in the recurrence
   int chain_rows = 0;          // rows per part (a multiple of 64, <= 1024)
+  int pipe_bands = 0;          // pipelined step: bands of 64 rows per workgroup (1, 2, 4)
+  int pipe_parts = 1;          // pipelined step: workgroups per ordinate
+  int n_tres = 0;              // partial sums of w r^2 the transport step writes
   double *sdq = nullptr;       // [q][N] sigma_t + pseudo-time shift per stored cell
   float *sdq_f = nullptr;      // FP32-mixed: the same in FP32 (FP32 recurrence)
   int2 *rtiles = nullptr;      // residual-kernel tiles (first diagonal, first row)
@@ -164,7 +184,8 @@ struct PlanDev {
                                // row 0 on each anti-diagonal (dg_off - ylo), padded
   int n_rtiles = 0;
   int sweep_impl = 0;          // 0 residual kernel + wavefront recurrence,
-                               // 1 two-kernel reference, 2 fused wavefront sweep
+                               // 1 two-kernel reference, 2 fused wavefront sweep,
+                               // 3 pipelined residual + recurrence
   // per cell
   double *sig_t = nullptr, *sig_a = nullptr, *sig_s = nullptr, *q = nullptr;
   double *cE = nullptr, *cW = nullptr, *cN = nullptr, *cS = nullptr;  // ALSM

@@ -1535,7 +1535,7 @@ SynthDesc make_synth_desc(const PlanDev &P) {
   D.red = P.red; D.scal = P.scal; D.err_parts = P.err_parts; D.err_hist = P.err_hist;
   D.last_err = P.last_err; D.state = P.state;
   D.tres_part = P.tres_part; D.src2_part = P.src2_part; D.tres_hist = P.tres_hist;
-  D.n_tres = P.n_rtiles * residual_pairs(P);
+  D.n_tres = P.n_tres;
   D.n_src2 = nblk(P.N);
   D.nlev = (int)P.mg.size();
   for (int l = 0; l < D.nlev && l < kMaxLevels; ++l) {

@@ -1002,9 +1002,9 @@ __device__ __forceinline__ void chain_ordinate(A &a, const int kk, const int par
 #pragma unroll
         for (int t2 = 0; t2 < LAG; ++t2) edge[wave][(sb + t2) & (R - 1)] = vv[t2];
       }
-      __syncthreads();
+      lds_barrier();
     }
-    __syncthreads();
+    __syncthreads();   // the pass's row hand-off (rowbuf, global memory)
   }
 }
 
@@ -1021,6 +1021,353 @@ __global__ void __launch_bounds__(kCMaxW * 64) k_chain_split(TArgs a, int np) {
   if (a.state[1] != 0) return;
   const int part = blockIdx.x / a.K;
   chain_ordinate<T, false, true>(a, xcd_ordinate(blockIdx.x - part * a.K, a.K), part, np);
+}
+
+// ---------------------------------------------------------------------------
+// Pipelined transport step: the residual and the recurrence in one launch,
+// the recurrence's right-hand side passed through LDS instead of HBM.
+//
+// Workgroup b is part p = b / K (rows [p 64 NB, (p + 1) 64 NB)) of ordinate
+// xcd_ordinate(b % K), with 2 NB waves: wave w < NB runs the recurrence of
+// band w (rows p 64 NB + 64 w + lane), wave NB + w forms the residual of the
+// same band. Lane l of band w sits at row offset t = 64 w + l and at step s
+// at column x = s - t, so a step is one anti-diagonal (s plus the part's
+// first row), as in the split kernels. Time runs in blocks of LAG steps with
+// one barrier per block. In block i the residual wave of band w forms steps
+// [LAG (i - w), +LAG) and writes (bv, 1/d) per step and lane into LDS slot
+// i & 1; the recurrence wave of band w takes steps [LAG (i - w - 1), +LAG)
+// from slot (i - 1) & 1, written one barrier earlier.
+//
+// Neighbour rows. Inside a band they are the DPP-shifted lanes. The residual
+// wave of band w > 0 takes u, F_n (and, FP32-mixed, phi^m/(4 pi)) of the row
+// below from band w - 1's top lane through an LDS ring (that wave runs a
+// block ahead); band 0 of part 0 has the south inflow there, and band 0 of a
+// later part forms the face value of the row below itself (from I^m and the
+// records, so it has the same bits as the part below). The row above a band
+// runs later, so its u (I^m only) is loaded directly. These per-step values
+// are loaded a block ahead into lanes 0..LAG-1 and broadcast with readlane.
+// The recurrence waves are the split recurrence's steps: v of the row below
+// from band w - 1's top lane (LDS ring), from part p - 1 (hand_take /
+// hand_put), or 0 below the grid. Every value is formed by the same
+// operations as in the split path, so the two give the same bits.
+// ---------------------------------------------------------------------------
+constexpr int kPLag = 8;            // steps per block (one barrier per block)
+constexpr int kPRing = 4 * kPLag;   // the edge rings, in steps
+
+template <typename T>
+struct PPair {
+  T bv, inv;           // the recurrence's right-hand side and 1/d
+};
+
+template <typename T>
+struct PSlot {
+  T ib;                // stored value at the lookahead cell (next diagonal)
+  double dq;           // base/(4 pi) there
+  double sube;         // FP32 mode: phi^m/(4 pi) there
+  double src;          // source at the cell
+  double2 c0, c1, st;  // its record
+  double in;           // time-dependent form: I^n at the cell
+};
+
+// Loads of the per-step neighbour values of a residual block (lane j: step
+// j of the block): the row above the band and, for band 0, the south inflow
+// or the 5-point stencil of the row below the part.
+struct PHalo {
+  double nI, nq;                 // u of the row above: stored value, base/(4 pi)
+  double vin;                    // south inflow (part 0)
+  double fI, fq, eI, eq, wI, wq, uI, uq, sI, sq, sub;   // row below: the cell, E, W, N, S
+  double2 f0, f1;                // its record
+};
+
+// The two roles run loops of their own (the same number of barriers), so
+// that neither holds the other's registers. The recurrence waves, which
+// have time to spare, also load and form the residual waves' neighbour
+// values of the row above the band and of the row below band 0 a block
+// ahead and pass them through LDS.
+template <typename T, bool TD, int NB, int PF>
+__device__ __forceinline__ void pipe_ordinate(const TArgs &a, const int kk, const int part,
+                                              const int np) {
+  constexpr bool kF32 = sizeof(T) == 4;
+  constexpr int LAG = kPLag, R = kPRing;
+  static_assert(LAG % PF == 0, "whole turns of the load ring per block");
+  static_assert((R & (R - 1)) == 0 && R >= 4 * LAG, "ring sizes");
+  static_assert(NB * LAG + 3 * LAG + PF + 2 <= kDiagPad, "diagonal table padding");
+  const int q = quadrant_of(a, kk);
+  const int nx = a.nx, ny = a.ny, N = a.N;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform per wave
+  const bool res = wv >= NB;                    // a residual wave
+  const int band = res ? wv - NB : wv;
+  const int y0 = part * 64 * NB;                // the part's first row
+  const int rows = min(64 * NB, ny - y0);
+  const int nbw = (rows + 63) >> 6;             // bands with rows
+  const int t = band * 64 + lane;               // row offset in the part
+  const int y = y0 + t;
+  const bool rowok = t < rows;
+  const int nsteps = nx + rows - 1;
+  const int tend = ((nsteps + (nbw - 1) * LAG + LAG - 1) / LAG) * LAG;
+  const __attribute__((address_space(4))) int *DS =
+      (const __attribute__((address_space(4))) int *)(a.dso + kDiagPad);
+  const double axd = a.amu[kk], ayd = a.aeta[kk];
+  const __amdgpu_buffer_rsrc_t Ib =
+      buf_rsrc(Iin_of<T>(a) + (size_t)kk * N, (size_t)N * sizeof(T));
+  const __amdgpu_buffer_rsrc_t Cb = buf_rsrc(a.cellq + (size_t)q * N * 6, (size_t)N * 48);
+  const double *SRC = a.dynq + (size_t)q * 3 * N;
+  const __amdgpu_buffer_rsrc_t Qb = buf_rsrc(SRC + N, (size_t)N * 8);
+  const __amdgpu_buffer_rsrc_t Ub = buf_rsrc(SRC + 2 * N, (size_t)N * 8);
+  const double hdx = 0.5 * a.dx, hdy = 0.5 * a.dy;
+  const bool second = a.order >= 2, lim = a.limiter != 0;
+
+  __shared__ PPair<T> pbuf[2][NB][LAG][64];
+  __shared__ double pedge[NB][3][R];            // residual waves: u, F_n, sub of the top row
+  __shared__ T cedge[NB][R];                    // recurrence waves: v of the top row
+  __shared__ double hal[2][NB][4][LAG];         // u, F_n, sub below lane 0, u above lane 63
+
+  if (res) {
+    // ---------------------------------------------------------- residual wave
+    const __amdgpu_buffer_rsrc_t Sb = buf_rsrc(SRC, (size_t)N * 8);
+    __amdgpu_buffer_rsrc_t Nb = buf_rsrc(nullptr, 0);
+    if constexpr (TD) Nb = buf_rsrc(a.In + (size_t)kk * N, (size_t)N * 8);
+    const bool hn = y + 1 < ny, hs = y > 0;
+    const T axy = (T)(axd + ayd);
+    const double wk = a.w[kk];
+    auto load = [&](PSlot<T> &sl, int s) {      // step s: the cell, and the lookahead cell
+      const int D = s + y0;
+      const unsigned ic = (unsigned)(DS[D] + y), il = (unsigned)(DS[D + 1] + y);
+      sl.ib = buf_ldT<T>(Ib, il);
+      sl.dq = buf_ld64(Qb, il * 8u);
+      if constexpr (kF32) sl.sube = buf_ld64(Ub, il * 8u);
+      sl.src = buf_ld64(Sb, ic * 8u);
+      sl.c0 = buf_ld128(Cb, ic * 48u);
+      sl.c1 = buf_ld128(Cb, ic * 48u + 16u);
+      sl.st = buf_ld128(Cb, ic * 48u + 32u);
+      if constexpr (TD) sl.in = buf_ld64(Nb, ic * 8u);
+    };
+    double inW = 0.0;                           // inflow on the local west face of the row
+    {
+      const int yr = min(y, ny - 1);
+      const int j = (q & 2) ? ny - 1 - yr : yr;
+      inW = a.bnd[(size_t)((q & 1) ? ny + j : j) * a.K + kk];
+    }
+    PSlot<T> ring[PF];
+    double uw = 0.0, uc = 0.0, ue = 0.0, subw = 0.0, subc = 0.0, sube = 0.0;
+    double Fe_p = 0.0, Fn_p = 0.0, rr = 0.0;
+    double fU = 0.0, fFn = 0.0, fS = 0.0, fN = 0.0;   // lane j < LAG: step j's neighbour values
+    if (band < nbw) {
+      // window u(D - 1), u(D) of the first step's diagonal D, and the load ring
+      const int s0 = -LAG * band;
+      const unsigned i0 = (unsigned)(DS[s0 + y0 - 1] + y), i1 = (unsigned)(DS[s0 + y0] + y);
+      uc = (double)buf_ldT<T>(Ib, i0) + buf_ld64(Qb, i0 * 8u);
+      ue = (double)buf_ldT<T>(Ib, i1) + buf_ld64(Qb, i1 * 8u);
+      if constexpr (kF32) { subc = buf_ld64(Ub, i0 * 8u); sube = buf_ld64(Ub, i1 * 8u); }
+#pragma unroll
+      for (int p = 0; p < PF; ++p) load(ring[p], s0 + p);
+    }
+    // Everything loaded so far (the ring, the window, the west inflow) lands
+    // before the loop: with loads of the entry still counted at the loop
+    // head, the compiler's wait for the loop-invariant inflow would cover
+    // every load of the previous block and leave the ring one step deep.
+    __builtin_amdgcn_s_waitcnt(0);
+    lds_barrier();                            // the first block's neighbour values
+    for (int tb = -LAG, it = 0; tb < tend; tb += LAG, ++it) {
+      if (band < nbw) {
+        const int sb = tb + LAG - LAG * band;   // this block's first step
+        if (lane < LAG) {
+          fN = hal[it & 1][band][3][lane];
+          if (band > 0) {                       // band - 1's top row, a block ago
+            const int e = (sb - 1 + lane) & (R - 1);
+            fU = pedge[band - 1][0][e];
+            fFn = pedge[band - 1][1][e];
+            fS = pedge[band - 1][2][e];
+          } else {
+            fU = hal[it & 1][band][0][lane];
+            fFn = hal[it & 1][band][1][lane];
+            fS = hal[it & 1][band][2][lane];
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < LAG; ++j) {
+          const int s = sb + j;
+          PSlot<T> &sl = ring[j % PF];
+          if constexpr (kF32) { subw = subc; subc = sube; sube = sl.sube; }
+          uw = uc; uc = ue; ue = (double)sl.ib + sl.dq;
+          const double uS = shr1_fill(uw, rdlane(fU, j));
+          const double FnS = shr1_fill(Fn_p, rdlane(fFn, j));
+          const double uN = shl1_fill(ue, rdlane(fN, j));
+          double sS = 0.0;
+          if constexpr (kF32) sS = shr1_fill(subw, rdlane(fS, j));
+          const int x = s - t;
+          const bool ok = rowok && x >= 0 && x < nx;
+          const double u = uc;
+          const double UE = x + 1 < nx ? ue : u, UW = x > 0 ? uw : u;
+          const double UN = hn ? uN : u, US = hs ? uS : u;
+          double Fe, Fn;
+          face_pair(u, UE, UW, UN, US, sl.c0, sl.c1, hdx, hdy, second, lim, Fe, Fn);
+          const double FeW = x > 0 ? Fe_p : inW;
+          double r = sl.src - sl.st.x * u - axd * (Fe - FeW) - ayd * (Fn - FnS);
+          if constexpr (TD) r += a.tdiag * sl.in;
+          const double inv = rcp64(sl.st.y + (axd + ayd));   // as in the recurrence
+          double t0 = kF32 ? u - subc : u;
+          const double tw = fma(-(axd * inv), kF32 ? uw - subw : uw, t0);
+          t0 = x > 0 ? tw : t0;
+          const double ts = fma(-(ayd * inv), kF32 ? uS - sS : uS, t0);
+          t0 = hs ? ts : t0;
+          PPair<T> pp;
+          pp.bv = (T)(t0 + r * inv);
+          if constexpr (kF32) pp.inv = rcp_t((float)sl.st.y + axy);
+          else pp.inv = inv;
+          pbuf[it & 1][band][j][lane] = pp;
+          rr = ok ? fma(wk * r, r, rr) : rr;
+          Fe_p = Fe;
+          Fn_p = Fn;
+          if (lane == 63) {
+            pedge[band][0][s & (R - 1)] = uc;
+            pedge[band][1][s & (R - 1)] = Fn;
+            pedge[band][2][s & (R - 1)] = subc;
+          }
+          load(sl, s + PF);
+        }
+      }
+      lds_barrier();
+    }
+    // the wave's sum of w r^2 (fixed order), one partial per (ordinate, part, band)
+    rr = wave_sum64(rr);
+    if (lane == 0) a.tres_part[((size_t)kk * np + part) * NB + band] = rr;
+  } else {
+    // -------------------------------------------------------- recurrence wave
+    const T ax = (T)axd, ay = (T)ayd;
+    const __amdgpu_buffer_rsrc_t Ob =
+        buf_rsrc(Iout_of<T>(a) + (size_t)kk * N, (size_t)N * sizeof(T));
+    const int yN = y0 + 64 * band + 64;         // the row above the band
+    const bool northed = yN < ny;
+    const int yh = y0 - 1;                      // the row below the part
+    auto ldT = [&](unsigned i, bool m) -> double {
+      if constexpr (kF32)
+        return (double)__builtin_bit_cast(
+            float, __builtin_amdgcn_raw_buffer_load_b32(Ib, (int)(m ? i * 4u : kNoCell), 0, 0));
+      else
+        return buf_ld64(Ib, m ? i * 8u : kNoCell);
+    };
+    // Indices are formed arithmetically and every wave issues the same loads
+    // (those it does not need go to kNoCell and read 0): a load whose address
+    // came from another load, or loads on one side of a branch whose results
+    // the two sides merge, would make the wave wait for them before its
+    // recurrence steps.
+    const int nd = nx + ny - 1;
+    auto cidx = [&](int xx, int yy) {           // storage index, clamped into the grid
+      xx = min(max(xx, 0), nx - 1);
+      yy = min(max(yy, 0), ny - 1);
+      return (unsigned)(dg_row0(xx + yy, nx, ny) + yy);
+    };
+    const __amdgpu_buffer_rsrc_t Bb = buf_rsrc(a.bnd, (size_t)a.nbf * a.K * 8);
+    const bool mN = lane < LAG && northed;
+    const bool mB = lane < LAG && band == 0 && part == 0;
+    const bool mS = lane < LAG && band == 0 && part > 0;
+    auto halo_load = [&](PHalo &h, int sbn) {   // lane j < LAG: step sbn + j
+      const int s = sbn + lane;
+      // lane 63's north neighbour, on the next diagonal
+      const unsigned iN = (unsigned)(dg_row0(min(max(s + y0 + 1, 0), nd - 1), nx, ny) + yN);
+      h.nI = ldT(iN, mN);
+      h.nq = buf_ld64(Qb, mN ? iN * 8u : kNoCell);
+      // south inflow of lane 0's column (the step)
+      const int xi = min(max(s, 0), nx - 1);
+      const int gi = (q & 1) ? nx - 1 - xi : xi;
+      const unsigned fb = (unsigned)(((q & 2) ? 2 * ny + nx + gi : 2 * ny + gi) * a.K + kk);
+      h.vin = buf_ld64(Bb, mB ? fb * 8u : kNoCell);
+      // the row below the part around lane 0's column
+      const unsigned jf = cidx(s, yh), je = cidx(s + 1, yh), jw = cidx(s - 1, yh);
+      const unsigned jn = cidx(s, y0), js = cidx(s, yh - 1);
+      h.fI = ldT(jf, mS); h.fq = buf_ld64(Qb, mS ? jf * 8u : kNoCell);
+      h.eI = ldT(je, mS); h.eq = buf_ld64(Qb, mS ? je * 8u : kNoCell);
+      h.wI = ldT(jw, mS); h.wq = buf_ld64(Qb, mS ? jw * 8u : kNoCell);
+      h.uI = ldT(jn, mS); h.uq = buf_ld64(Qb, mS ? jn * 8u : kNoCell);
+      h.sI = ldT(js, mS); h.sq = buf_ld64(Qb, mS ? js * 8u : kNoCell);
+      h.f0 = buf_ld128(Cb, mS ? jf * 48u : kNoCell);
+      h.f1 = buf_ld128(Cb, mS ? jf * 48u + 16u : kNoCell);
+      h.sub = kF32 ? buf_ld64(Ub, mS ? jf * 8u : kNoCell) : 0.0;
+    };
+    auto halo_put = [&](const PHalo &h, int sbn, int slot) {
+      const int x = sbn + lane;
+      const double u = h.fI + h.fq, ve = h.eI + h.eq, vw = h.wI + h.wq;
+      const double vn = h.uI + h.uq, vs = h.sI + h.sq;
+      double Fe, Fn;
+      face_pair(u, x + 1 < nx ? ve : u, x > 0 ? vw : u, vn, yh > 0 ? vs : u, h.f0, h.f1, hdx, hdy,
+                second, lim, Fe, Fn);
+      const bool below = band == 0 && part > 0;
+      if (lane < LAG) {
+        hal[slot][band][0][lane] = below ? u : 0.0;
+        hal[slot][band][1][lane] = below ? Fn : h.vin;
+        hal[slot][band][2][lane] = below && kF32 ? h.sub : 0.0;
+        hal[slot][band][3][lane] = northed ? h.nI + h.nq : 0.0;
+      }
+    };
+    unsigned long long *Hr = nullptr;
+    __amdgpu_buffer_rsrc_t Hw = buf_rsrc(nullptr, 0);
+    {
+      unsigned long long *H = a.hand + (size_t)kk * (np - 1) * nx;
+      if (part > 0) Hr = H + (size_t)(part - 1) * nx;
+      if (part + 1 < np) Hw = buf_rsrc(H + (size_t)part * nx, (size_t)nx * 8);
+    }
+    const bool top_lane = t == rows - 1;        // the part's top row
+    T vp = 0;
+    unsigned long long hv = 0;
+    bool gave_up = false;
+    PHalo hl;
+    if (band < nbw) {                           // the residual wave's first block
+      halo_load(hl, -LAG * band);
+      halo_put(hl, -LAG * band, 0);
+    }
+    lds_barrier();
+    for (int tb = -LAG, it = 0; tb < tend; tb += LAG, ++it) {
+      if (band < nbw) {
+        const int sbr = tb + 2 * LAG - LAG * band;   // the residual wave's next block
+        halo_load(hl, sbr);
+        const int sb = tb - LAG * band;         // this block's first step
+        T bl[LAG];                              // v below lane 0
+        if (band > 0) {
+#pragma unroll
+          for (int j = 0; j < LAG; ++j) bl[j] = cedge[band - 1][(sb - 1 + j) & (R - 1)];
+        } else if (part > 0) {
+          double hb[LAG];
+          hand_take<LAG>(Hr, nx, sb, hv, gave_up, a.hand_err, hb);   // lane 0's column is its step
+#pragma unroll
+          for (int j = 0; j < LAG; ++j) bl[j] = (T)hb[j];
+        } else {
+#pragma unroll
+          for (int j = 0; j < LAG; ++j) bl[j] = (T)0;
+        }
+        T vv[LAG];
+#pragma unroll
+        for (int j = 0; j < LAG; ++j) {
+          const int s = sb + j;
+          const int x = s - t;
+          const bool act = rowok && (unsigned)x < (unsigned)nx;
+          const PPair<T> pv = pbuf[(it + 1) & 1][band][j][lane];
+          const T vS = shr1_fill(vp, bl[j]);
+          const T vn = fma(ax * pv.inv, vp, fma(ay * pv.inv, vS, pv.bv));
+          const T v = act ? vn : vp;
+          buf_store(v, Ob, act ? (unsigned)(DS[y0 + s] + y) * (unsigned)sizeof(T) : kNoCell);
+          if (band == nbw - 1 && part + 1 < np)
+            hand_put(Hw, (double)v, top_lane && act ? (unsigned)x * 8u : kNoCell);
+          vp = v;
+          vv[j] = v;
+        }
+        if (lane == 63) {
+#pragma unroll
+          for (int j = 0; j < LAG; ++j) cedge[band][(sb + j) & (R - 1)] = vv[j];
+        }
+        halo_put(hl, sbr, (it + 1) & 1);
+      }
+      lds_barrier();
+    }
+  }
+}
+
+template <typename T, bool TD, int NB, int PF>
+__global__ void __launch_bounds__(2 * NB * 64) k_pipe(TArgs a, int np) {
+  if (a.state[1] != 0) return;
+  const int part = blockIdx.x / a.K;
+  pipe_ordinate<T, TD, NB, PF>(a, xcd_ordinate(blockIdx.x - part * a.K, a.K), part, np);
 }
 
 __global__ void k_fill_u64(unsigned long long *p, size_t n, unsigned long long v) {
@@ -1315,10 +1662,11 @@ int sweep_rows(const PlanDev &P) {
 
 // sweep_impl 0: residual kernel, then the recurrence in place; 1: plain
 // two-kernel reference (FP64 only; FP32 falls back to the fused kernel);
-// 2: fused wavefront sweep (nothing in the residual phase).
+// 2: fused wavefront sweep; 3: pipelined residual + recurrence (2 and 3 put
+// nothing in the residual phase).
 void launch_residual(const PlanDev &P, hipStream_t s) {
   const TArgs a = make_args(P);
-  if (P.sweep_impl == 2 || (P.sweep_impl == 1 && a.fp32)) return;
+  if (P.sweep_impl == 2 || P.sweep_impl == 3 || (P.sweep_impl == 1 && a.fp32)) return;
   if (P.sweep_impl == 1) {
     hipLaunchKernelGGL(k_residual, dim3((P.N + 255) / 256, P.K), dim3(256), 0, s, a);
     return;
@@ -1367,9 +1715,29 @@ void launch_td_begin(const PlanDev &P, hipStream_t s) {
                      (const double *)P.Tm, P.Tn, P.rho_n, P.state, P.last_err);
 }
 
+namespace {
+template <typename T, bool TD>
+void launch_pipe_t(const TArgs &a, const PlanDev &P, hipStream_t s) {
+  constexpr int PF = 8;
+  const dim3 g(P.pipe_parts * P.K);
+  if (P.pipe_bands == 1)
+    hipLaunchKernelGGL((k_pipe<T, TD, 1, PF>), g, dim3(128), 0, s, a, P.pipe_parts);
+  else if (P.pipe_bands == 2)
+    hipLaunchKernelGGL((k_pipe<T, TD, 2, PF>), g, dim3(256), 0, s, a, P.pipe_parts);
+  else
+    hipLaunchKernelGGL((k_pipe<T, TD, 4, PF>), g, dim3(512), 0, s, a, P.pipe_parts);
+}
+}  // namespace
+
 void launch_sweep(const PlanDev &P, hipStream_t s) {
   const TArgs a = make_args(P);
   const int rows = sweep_rows(P);
+  if (P.sweep_impl == 3) {
+    if (P.td) launch_pipe_t<double, true>(a, P, s);
+    else if (a.fp32) launch_pipe_t<float, false>(a, P, s);
+    else launch_pipe_t<double, false>(a, P, s);
+    return;
+  }
   if (P.sweep_impl == 2 || (P.sweep_impl == 1 && a.fp32)) {
     if (a.fp32) launch_fused<float>(a, P, rows, s);
     else launch_fused<double>(a, P, rows, s);
@@ -1401,7 +1769,7 @@ std::vector<int> diag_row0_table(int nx, int ny) {
     const int d = e - kDiagPad;
     if (d < 0) t[e] = -(1 << 28);
     else if (d >= nd) t[e] = 1 << 28;
-    else t[e] = (int)(dg_off(d, nx, ny) - dg_ylo(d, nx));
+    else t[e] = dg_row0(d, nx, ny);
   }
   return t;
 }
@@ -1425,8 +1793,9 @@ std::vector<int2> residual_tiles(int nx, int ny) {
 size_t targs_bytes() { return sizeof(TArgs); }
 
 void launch_hand_reset(const PlanDev &P, hipStream_t s) {
-  if (P.chain_parts <= 1) return;
-  const size_t n = (size_t)P.K * (P.chain_parts - 1) * P.nx;
+  const int hp = std::max(P.chain_parts, P.pipe_parts);
+  if (hp <= 1) return;
+  const size_t n = (size_t)P.K * (hp - 1) * P.nx;
   hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, P.hand, n,
                      kHandEmpty);
 }

@@ -64,6 +64,15 @@ __device__ inline double shl1_fill(double v, double fill) {
   return __hiloint2double(hi, lo);
 }
 
+// Workgroup barrier that orders LDS only: the fences are limited to the
+// local address space, so a wave's global stores still in flight do not
+// hold it at the barrier (__syncthreads waits for them).
+__device__ inline void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Raw buffer stores (gfx9 resource word 3 = 0x00020000): a store whose byte
 // offset lies outside the resource's range is dropped by the hardware, so a
 // lane with no cell issues the same instruction as the others and no branch
