@@ -61,20 +61,21 @@ SYNTH_RTOL = 0.1
 # so FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0). Valid only for the kernel source
 # whose sha256 is recorded; any change to it turns the figures back to null.
 TRAFFIC = {
-    "thick256_fp64": {"sha256": "7e57f241f090680d5b6b8ceec1393cb3af4b70fbeb0aec5903676653a2509a27",
-                      "residual": 243533107,    # 83735.0 KiB x 2.0 + 70355.3 KiB
-                      "sweep": 138758348},      # 34863.5 KiB x 2.0 + 65779.2 KiB
-    "block1024_fp64": {"sha256": "7e57f241f090680d5b6b8ceec1393cb3af4b70fbeb0aec5903676653a2509a27",
-                       "residual": 4277558784,  # 1538204.2 KiB x 2.0 + 1100895.1 KiB
-                       "sweep": 2533175091},    # 690582.6 KiB x 2.0 + 1092638.6 KiB
-    "block1024_fp32": {"sha256": "7e57f241f090680d5b6b8ceec1393cb3af4b70fbeb0aec5903676653a2509a27",
-                       "residual": 2972580659,  # 1158861.0 KiB x 2.0 + 585188.8 KiB
-                       "sweep": 1281340928},    # 346831.5 KiB x 2.0 + 557646.5 KiB
+    "thick256_fp64": {"sha256": "68724e78a7a9ea14ef954a9a1b41ff288db667dcb691684399b386ac07c1daf2",
+                      "k_resid": 243937200,     # 83931.2 KiB x 2.0 + 70357.5 KiB
+                      "k_chain": 138761912},    # 34863.5 KiB x 2.0 + 65782.6 KiB
+    "block1024_fp64": {"sha256": "68724e78a7a9ea14ef954a9a1b41ff288db667dcb691684399b386ac07c1daf2",
+                       "k_pipe": 3160253616},   # 971567.2 KiB x 2.0 + 1143050.8 KiB
+    "block1024_fp32": {"sha256": "68724e78a7a9ea14ef954a9a1b41ff288db667dcb691684399b386ac07c1daf2",
+                       "k_resid": 2973909504,   # 1159512.1 KiB x 2.0 + 585184.3 KiB
+                       "k_chain": 1281183488},  # 346750.1 KiB x 2.0 + 557655.6 KiB
 }
-KERNELS = {"residual": "k_resid (second-order residual of every cell-ordinate, ALSM gradient "
-                       "and BJ limiter, written as the recurrence's right-hand side)",
-           "sweep": "k_chain / k_chain_split (first-order-upwind recurrence on the "
-                    "anti-diagonal wavefront)"}
+KERNELS = {"k_resid": "k_resid (second-order residual of every cell-ordinate, ALSM gradient "
+                      "and BJ limiter, written as the recurrence's right-hand side)",
+           "k_chain": "k_chain / k_chain_split (first-order-upwind recurrence on the "
+                      "anti-diagonal wavefront)",
+           "k_pipe": "k_pipe (pipelined transport step: residual waves pass the recurrence's "
+                     "right-hand side to recurrence waves through LDS, one launch)"}
 
 
 def log(msg):
@@ -112,14 +113,14 @@ def cpu_leg(prob, n_iter, inputs, with_refs):
     return base, refs
 
 
-def measure_controls(ctx, gsis, pd, opts, N, K, args, phases, nprof, achieved, torch, dev):
+def measure_controls(ctx, gsis, pd, opts, N, K, args, phases, nprof, achieved, torch, dev,
+                     tr_ms):
     """The transport step alone (residual + recurrence) as cell-ordinate
     updates/s, the same steps with the limiter off (the residual's arithmetic
     control), and a measured copy ceiling: a 1 GiB FP64 device copy, bytes
     read + written per second, with the transport step's algorithmic rate as
     a fraction of it."""
     n = max(nprof, 1)
-    tr_ms = (phases["residual"] + phases["sweep"]) / n
     res = {"transport": {"kernels": "residual + recurrence", "ms": tr_ms,
                          "cell_ordinate_updates_per_s": N * K / (tr_ms / 1e3)}}
     plan = gsis.Plan(ctx, pd, tol=0.0, max_iter=args.steps + args.warmup + 1, profile=1,
@@ -153,11 +154,11 @@ def measure_controls(ctx, gsis, pd, opts, N, K, args, phases, nprof, achieved, t
     return res
 
 
-def kernel_traffic(cfg, phase):
+def kernel_traffic(cfg, kernel):
     """Bytes per launch of a transport kernel from the PMC runs of this
     configuration, if the kernel source is unchanged since they were taken."""
     t = TRAFFIC.get(cfg)
-    if not t or t.get(phase) is None:
+    if not t or t.get(kernel) is None:
         return None
     src = os.path.join(ROOT, "paper_2507_03975_amd", "csrc", "kernels_transport.hip")
     with open(src, "rb") as f:
@@ -424,6 +425,8 @@ def main():
     phases, nprof = plan.phase_times()
     n_done = plan.status()[0]
     vcycles = plan.synth_vcycles()
+    form, bands, parts = plan.transport_form()
+    pipelined = form == 3
     assert n_done == args.steps, (n_done, args.steps)
     plan.close()
     ms_step = ms / args.steps
@@ -431,17 +434,21 @@ def main():
     nprof = max(nprof, 1)
     per = {k: v / nprof for k, v in phases.items()}
     alg = ALG_BYTES[args.precision] * N * K           # one read of I^m, one write of I^{m+1/2}
-    tr_ms = per["residual"] + per["sweep"]
+    # the pipelined step is one launch in the sweep phase (the residual
+    # phase then holds no kernel, only its two events)
+    tr_ms = per["sweep"] if pipelined else per["residual"] + per["sweep"]
     achieved = alg / (tr_ms / 1e3) / 1e9
     cfg_key = "%s_%s" % (args.config, args.precision)
     kern = {}
-    for ph in ("residual", "sweep"):
-        t = kernel_traffic(cfg_key, ph)
-        kern[ph] = {"kernel": KERNELS[ph], "avg_ms": per[ph], "traffic": t,
+    launches = ([("transport", "k_pipe", per["sweep"])] if pipelined else
+                [("residual", "k_resid", per["residual"]), ("sweep", "k_chain", per["sweep"])])
+    for ph, name, ms_k in launches:
+        t = kernel_traffic(cfg_key, name)
+        kern[ph] = {"kernel": KERNELS[name], "avg_ms": ms_k, "traffic": t,
                     "traffic_over_transport_algorithmic": None if t is None else t / alg}
     traffic = None
-    if kern["residual"]["traffic"] is not None and kern["sweep"]["traffic"] is not None:
-        traffic = kern["residual"]["traffic"] + kern["sweep"]["traffic"]
+    if all(k["traffic"] is not None for k in kern.values()):
+        traffic = sum(k["traffic"] for k in kern.values())
     vc_step = vcycles / args.steps
     synth_bytes = SYNTH_BYTES_PER_CELL * N * vc_step
     log("step %.3f ms; phases per step (ms): %s; V-cycles per step %.2f" % (
@@ -464,7 +471,10 @@ def main():
                    "method": "GSIS", "step": "one outer iteration"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "transport step: k_resid + recurrence (the two launches of "
+                     "kernel": ("transport step: k_pipe, residual and recurrence in one "
+                                "launch (Eqs. RTE_d_res..elem_mtx; %d bands of 64 rows, %d "
+                                "parts)" % (bands, parts)) if pipelined else
+                               "transport step: k_resid + recurrence (the two launches of "
                                "Eqs. RTE_d_res..elem_mtx)",
                      "algorithmic_bytes_per_launch": alg,
                      "algorithmic_bytes_per_cell_ordinate": ALG_BYTES[args.precision],
@@ -528,7 +538,7 @@ def main():
 
     if not args.no_forms:
         out["controls"] = measure_controls(ctx, gsis, pd, opts, N, K, args, phases, nprof,
-                                           achieved, torch, dev)
+                                           achieved, torch, dev, tr_ms)
         out["forms"] = measure_forms(ctx, gsis, inputs, np, torch, dev)
     f256 = out.get("forms", {}).get("fp32_mixed", {}).pop("block256_fields", None)
 

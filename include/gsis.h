@@ -259,6 +259,19 @@ enum {
  * plan was created or reset (with synth_form 1, of the last sub-iteration's
  * solve of each outer iteration). 0 for source iteration. */
 gsis_status gsis_plan_synth_vcycles(gsis_plan *plan, int64_t *vcycles);
+/* The transport step a plan runs: the residual of every cell-ordinate (Eq.
+ * RTE_d_res) and the exact first-order-upwind increment solve on the
+ * wavefront (Eqs. RTE_d_increment..elem_mtx). *form receives
+ * GSIS_TRANSPORT_SPLIT (a residual launch, then the recurrence) or
+ * GSIS_TRANSPORT_PIPELINED (one launch: workgroups of *bands bands of 64
+ * rows, *parts workgroups per ordinate); the two give the same bits. The
+ * choice is made at plan creation (FP64 problems of at least 2^26
+ * cell-ordinates run pipelined) and the environment variable
+ * GSIS_SWEEP_REFERENCE (0 split, 3 pipelined) overrides it. bands and parts
+ * may be NULL. No device work. */
+enum { GSIS_TRANSPORT_SPLIT = 0, GSIS_TRANSPORT_PIPELINED = 3 };
+gsis_status gsis_plan_transport_form(gsis_plan *plan, int32_t *form, int32_t *bands,
+                                     int32_t *parts);
 /* Wait for the plan's stream; ms[GSIS_NUM_PHASES] receives the summed
  * duration of each phase over all profiled iterations (HIP events on the
  * plan's stream), *n_iter the number of profiled iterations. Needs

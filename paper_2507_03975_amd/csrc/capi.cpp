@@ -910,6 +910,17 @@ extern "C" gsis_status gsis_plan_read(gsis_plan *pl, gsis_result *r) {
   return GSIS_OK;
 }
 
+extern "C" gsis_status gsis_plan_transport_form(gsis_plan *pl, int32_t *form, int32_t *bands,
+                                                int32_t *parts) {
+  if (!pl) return GSIS_E_INVALID_ARG;
+  if (!form) return fail(pl->ctx, GSIS_E_INVALID_ARG, "form is NULL");
+  const PlanDev &P = pl->P;
+  *form = P.sweep_impl;
+  if (bands) *bands = P.sweep_impl == 3 ? P.pipe_bands : 0;
+  if (parts) *parts = P.sweep_impl == 3 ? P.pipe_parts : P.chain_parts;
+  return GSIS_OK;
+}
+
 extern "C" gsis_status gsis_plan_synth_vcycles(gsis_plan *pl, int64_t *vcycles) {
   if (!pl) return GSIS_E_INVALID_ARG;
   gsis_ctx *ctx = pl->ctx;

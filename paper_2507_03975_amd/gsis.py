@@ -84,7 +84,8 @@ EXPORTS = ("gsis_ctx_create", "gsis_ctx_destroy", "gsis_last_error", "gsis_optio
            "gsis_batch_create", "gsis_batch_destroy", "gsis_batch_iterate", "gsis_batch_status",
            "gsis_batch_read", "gsis_batch_reset", "gsis_batch_get_tuning", "gsis_solve_batch",
            "gsis_plan_adjoint", "gsis_adjoint", "gsis_version", "gsis_solve_noalloc",
-           "gsis_plan_synth_vcycles", "gsis_td_create", "gsis_td_advance", "gsis_td_read")
+           "gsis_plan_synth_vcycles", "gsis_td_create", "gsis_td_advance", "gsis_td_read",
+           "gsis_plan_transport_form")
 
 
 def load():
@@ -119,6 +120,7 @@ def load():
     lib.gsis_plan_reset.argtypes = [vp]
     lib.gsis_plan_phase_times.argtypes = [vp, _dp, ip]
     lib.gsis_plan_synth_vcycles.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+    lib.gsis_plan_transport_form.argtypes = [vp, ip, ip, ip]
     lib.gsis_batch_create.argtypes = [vp, i32, ctypes.POINTER(gsis_problem),
                                       ctypes.POINTER(gsis_options), ctypes.POINTER(vp)]
     lib.gsis_batch_destroy.argtypes = [vp]
@@ -287,6 +289,14 @@ class Plan:
         v = ctypes.c_int64()
         _check(load().gsis_plan_synth_vcycles(self.handle, ctypes.byref(v)), self.ctx)
         return v.value
+
+    def transport_form(self):
+        """(form, bands, parts) of the plan's transport step: form 0 split
+        (residual launch, then the recurrence), 3 pipelined (one launch)."""
+        f, b, p = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(load().gsis_plan_transport_form(self.handle, ctypes.byref(f), ctypes.byref(b),
+                                               ctypes.byref(p)), self.ctx)
+        return f.value, b.value, p.value
 
     def phase_times(self):
         ms = (ctypes.c_double * GSIS_NUM_PHASES)()

@@ -125,3 +125,29 @@ def test_pipe_bitwise_time_dependent(ctx, shape, monkeypatch):
         pl.close()
         assert its == [3, 3]
     _same(out["0"], out["3"], ("rho", "T", "Fx", "Fy"))
+
+
+def test_pipe_default_selection(ctx, monkeypatch):
+    """The transport step a plan runs by default: split for the 256x256x128
+    thick square and in FP32-mixed form, pipelined with 2 bands of 64 rows for
+    FP64 problems of 2^26 cell-ordinates and more; the environment variable
+    overrides either way."""
+    monkeypatch.delenv("GSIS_SWEEP_REFERENCE", raising=False)
+    monkeypatch.delenv("GSIS_PIPE_BANDS", raising=False)
+    small = inputs.thick_square(256)
+    big = inputs.random_problem(512, 1024, quad=inputs.quad_product(4, 32), seed=3, inflow=False)
+    cases = [(small, {}, None, (0, 0)), (big, {}, None, (3, 2)),
+             (big, dict(precision=1), None, (0, 0)), (small, {}, "3", (3, 2)),
+             (big, {}, "0", (0, 0))]
+    for p, kw, env, want in cases:
+        if env is None:
+            monkeypatch.delenv("GSIS_SWEEP_REFERENCE", raising=False)
+        else:
+            monkeypatch.setenv("GSIS_SWEEP_REFERENCE", env)
+        _say("transport form %dx%d %s env=%s" % (p["nx"], p["ny"], kw, env))
+        pl = gsis.Plan(ctx, p, **kw)
+        form, bands, parts = pl.transport_form()
+        pl.close()
+        assert (form, bands) == want, (form, bands, parts)
+        if form == 3:
+            assert parts == -(-p["ny"] // 128)
