@@ -73,6 +73,7 @@ def _load():
         lib.ora_gradient.argtypes = [P, ctypes.c_int, _dp, _dp, _dp]
         lib.ora_bj_limiter.argtypes = [P, _dp, _dp, _dp, _dp]
         lib.ora_face_coeffs.argtypes = [P, _dp, _dp, _dp]
+        lib.ora_plant_kappa.argtypes = [ctypes.c_int]
         lib.ora_residual.argtypes = [P, O, _dp, _dp]
         lib.ora_sweep.argtypes = [P, O, _dp, _dp]
         lib.ora_pseudo_shift.argtypes = [P, O, ctypes.c_int]
@@ -160,6 +161,13 @@ def synthetic_wide(prob, b, x0, n_sub, alsm=1):
     st = _load().ora_synthetic_wide(ctypes.byref(m.s), int(alsm), _ptr(b), int(n_sub), _ptr(x))
     assert st == 0, st
     return x
+
+
+def plant_kappa(mode):
+    """Test hook: replace the wall coefficient kappa by a misreading of Eq.
+    macro_bc_delta_flux (1 escape term only, 2 diffusion term only, 3 the two
+    in series, 4 none); 0 restores the paper's sum."""
+    _load().ora_plant_kappa(int(mode))
 
 
 def face_coeffs(prob):

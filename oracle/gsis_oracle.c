@@ -337,9 +337,22 @@ static double gamma_face(const ora_problem *p, int c, int nb, int f) {
   return -(vx * NX_[f] + vy * NY_[f]) / (3.0 * (vx * vx + vy * vy));
 }
 
+/* Test hook: ora_plant_kappa(m) replaces kappa by a misreading (1: escape
+ * term only, 2: diffusion term only, 3: the two terms in series, 4: none) so
+ * that the pins can show they catch it; 0 restores the paper's form. */
+static int kappa_plant = 0;
+void ora_plant_kappa(int mode) { kappa_plant = mode; }
+
 static double kappa_face(const ora_problem *p, int c, int f) {
   double ox = face_ox(p, f), oy = face_oy(p, f);
-  return (ox * NX_[f] + oy * NY_[f]) / (3.0 * sig_t(p, c) * (ox * ox + oy * oy)) + 0.25;
+  const double kd = (ox * NX_[f] + oy * NY_[f]) / (3.0 * sig_t(p, c) * (ox * ox + oy * oy));
+  switch (kappa_plant) {
+    case 1: return 0.25;
+    case 2: return kd;
+    case 3: return 1.0 / (1.0 / kd + 4.0);
+    case 4: return 0.0;
+    default: return kd + 0.25;
+  }
 }
 
 void ora_face_coeffs(const ora_problem *p, double *gam_x, double *gam_y,

@@ -62,6 +62,7 @@ void ora_bj_limiter(const ora_problem *p, const double *U, const double *Gx,
  * [(nx-1)*ny] (face right of cell (i,j) at index j*(nx-1)+i) and y faces
  * [nx*(ny-1)] (face above (i,j) at j*nx+i) (Eq. Gamma_ij_com2); kappa per
  * boundary face [2(nx+ny)] (Eqs. macro_bc_delta_flux, macro_bc_delta_flux2). */
+void ora_plant_kappa(int mode);   /* test hook, see gsis_oracle.c */
 void ora_face_coeffs(const ora_problem *p, double *gam_x, double *gam_y,
                      double *kappa);
 

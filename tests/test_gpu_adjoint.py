@@ -104,11 +104,13 @@ def test_adjoint_full_size_against_central_differences(ctx):
     """512 x 512 x 128 noisy two-region medium, detector objective:
     dJ/dsigma at 16 sampled cells (4 in the window, 4 on the thick square's
     east edge, 4 between, 4 anywhere; seed 55) against central differences of
-    the GPU forward solve (h = 1e-3 relative: truncation about 1e-6
-    relative). The differences also carry the forward error over h: Err is
-    relative to the whole field, dominated by the thick square, so phi in the
-    thin detector region is known to about 1e-10 of itself; hence the bound
-    1e-5 relative plus 1e-6 of the largest gradient."""
+    GPU forward solves converged to Err < 1e-14 (h = 1e-3 relative), to 1e-6
+    of the gradient's largest value. The differences carry the forward
+    solves' rounding over h, about 1e-8 of J per unit relative step, which
+    sets their floor (measured: at most 1.8e-7 of the largest gradient over
+    the 32 values; the window cells agree to 1e-8 of themselves, while a cell
+    whose gradient is 1e-5 of the largest can only be checked against that
+    floor)."""
     import torch
     n = 512
     p = inputs.noisy_thick_square(n)
@@ -121,16 +123,16 @@ def test_adjoint_full_size_against_central_differences(ctx):
 
     def J(sa, ss):
         q = dict(pd, sigma_a=sa, sigma_s=ss)
-        r = gsis.gsis_solve(ctx, q, tol=1e-13, max_iter=2000, limiter=0, synth_rtol=1e-12)
+        r = gsis.gsis_solve(ctx, q, tol=1e-14, max_iter=3000, limiter=0, synth_rtol=1e-12)
         assert r["status"] == 0
         return float((V * sa * r["phi"] * Wt).sum())
     gphi = torch.where(Wt, V * pd["sigma_a"], torch.zeros_like(pd["sigma_a"]))
     _say("full-size adjoint")
-    plan = gsis.Plan(ctx, pd, tol=1e-13, max_iter=2000, limiter=0, synth_rtol=1e-12)
-    plan.iterate(2000)
+    plan = gsis.Plan(ctx, pd, tol=1e-14, max_iter=3000, limiter=0, synth_rtol=1e-12)
+    plan.iterate(3000)
     assert plan.status()[1] == 1
     phi = plan.read()["phi"]
-    ga, gs, gq, info = plan.adjoint(gphi, tol=1e-12, max_iter=2000)
+    ga, gs, gq, info = plan.adjoint(gphi, tol=1e-13, max_iter=3000)
     plan.close()
     ga = ga + torch.where(Wt, V * phi, torch.zeros_like(phi))   # explicit part of J
     cells = inputs.adjoint_fd_cells(n)
@@ -145,7 +147,7 @@ def test_adjoint_full_size_against_central_differences(ctx):
             fd = (J(*args_p) - J(*args_m)) / (2 * h)
             g = float(grad[c])
             _say("  %s cell %d fd %.9e adjoint %.9e" % (name, c, fd, g))
-            assert abs(fd - g) <= 1e-5 * abs(fd) + 1e-6 * float(grad.abs().max())
+            assert abs(fd - g) <= 1e-6 * float(grad.abs().max())
 
 
 def test_autograd_function(ctx):

@@ -313,6 +313,33 @@ def test_alsm_face_value_is_harmonic(s0, s1):
     assert abs(kap[0] - (1.0 / (3 * s0 * dx / 2) + GOLD["isotropic_half_range_flux"]["value"])) < 1e-14 * kap[0]
 
 
+@pytest.mark.parametrize("plant,converges", [(0, True), (2, False), (3, False), (4, False)])
+def test_kappa_escape_term_keeps_thick_walls_convergent(plant, converges):
+    """Homogeneous box with optically thick boundary cells (sigma_t dx =
+    312, c = 0.9999). The wall term of Eq. macro_bc_delta_flux makes the
+    synthetic equation's boundary flux follow the cell's energy: through the
+    escape part (Eq. macro_bc_delta_flux2, the isotropic half-range flux 1/4)
+    when the cell is thick, since the diffusion part 1/(3 sigma_t dx/2) is then
+    small. GSIS then contracts well below 1 per iteration. Readings that drop
+    the escape part, combine the two parts in series, or drop the wall term
+    make the boundary modes grow, and GSIS stops as diverged: planted in the
+    oracle, each of them fails this pin. (Dropping the diffusion part keeps
+    convergence; only the paper's text fixes that part.)"""
+    p = inputs.homogeneous(32, 32, inputs.quad_product(2, 16), sigma_t=1e4, c=0.9999, q=1.0)
+    oracle.plant_kappa(plant)
+    try:
+        g = oracle.solve(p, method=1, order=2, limiter=0, tol=1e-10, max_iter=100)
+    finally:
+        oracle.plant_kappa(0)
+    h = np.asarray(g["err_hist"])
+    if converges:
+        assert g["status"] == 0 and g["n_iter"] <= 40, (g["status"], g["n_iter"])
+        rate = np.exp(np.mean(np.log(h[10:20] / h[9:19])))
+        assert rate < 0.6, rate
+    else:
+        assert g["status"] != 0, (g["status"], g["n_iter"])
+
+
 def test_limiter_cases():
     p = inputs.random_problem(5, 5, seed=4)
     p["sigma_a"] = np.full(25, 1.0); p["sigma_s"] = np.zeros(25)
