@@ -103,9 +103,10 @@ typedef struct {
   int32_t method;        /* GSIS_SI or GSIS_GSIS (default) */
   int32_t precision;     /* GSIS_FP64 (default) or GSIS_FP32_MIXED: FP32
                             intensities (stored as deviations from
-                            phi/(4 pi)) and FP32 wavefront recurrence;
-                            FP64 residual, moment sums, synthetic solve,
-                            update and Err */
+                            phi/(4 pi)), FP32 wavefront recurrence and
+                            FP32 sums of the deviations' moments; FP64
+                            residual, phi^m part of the moments, synthetic
+                            solve, update and Err */
   int32_t order;         /* 1 = first-order upwind, 2 = second order (default) */
   int32_t limiter;       /* Barth-Jespersen limiter on (1, default) or off */
   int32_t alsm;          /* 1 = adaptive least squares (Sec. 5.2, default),

@@ -687,6 +687,14 @@ static gsis_status plan_create(gsis_ctx *ctx, const gsis_problem *p, const gsis_
   if (f32) {
     std::vector<float> sdqf(sdq.begin(), sdq.end());
     if ((st = upload(pl, &P.sdq_f, sdqf))) return bail(st);
+    // w, w mu, w eta in FP32 for the moment sums of the deviations
+    std::vector<float> wf(3 * (size_t)K);
+    for (int kk = 0; kk < K; ++kk) {
+      wf[kk] = (float)wv[kk];
+      wf[K + kk] = (float)wmu[kk];
+      wf[2 * K + kk] = (float)weta[kk];
+    }
+    if ((st = upload(pl, &P.w_f, wf))) return bail(st);
   }
   if (P.method == GSIS_GSIS && P.hot_face == GSIS_HOT_TRANSPORT &&
       (st = dalloc(pl, &P.ftp, (size_t)8 * N)))

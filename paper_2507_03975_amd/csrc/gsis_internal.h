@@ -179,6 +179,7 @@ struct PlanDev {
   int n_tres = 0;              // partial sums of w r^2 the transport step writes
   double *sdq = nullptr;       // [q][N] sigma_t + pseudo-time shift per stored cell
   float *sdq_f = nullptr;      // FP32-mixed: the same in FP32 (FP32 recurrence)
+  float *w_f = nullptr;        // FP32-mixed: w, w mu, w eta in FP32 ([3][K], moment sums)
   int2 *rtiles = nullptr;      // residual-kernel tiles (first diagonal, first row)
   int *dso = nullptr;          // [kDiagPad + nx + ny - 1 + kDiagPad] storage index of
                                // row 0 on each anti-diagonal (dg_off - ylo), padded

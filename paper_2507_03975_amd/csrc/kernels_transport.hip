@@ -21,8 +21,9 @@
 // base = phi^m + delta. Itilde is the anisotropic part plus the last
 // change of phi, small where the medium is thick, so its FP32 rounding stays
 // far below the cancellation sigma_t I - sigma_s phi/(4 pi). The residual
-// (with that cancellation) and the moment sums run in FP64; the wavefront
-// recurrence, which only propagates the residual's increments, runs in FP32.
+// (with that cancellation) runs in FP64; the wavefront recurrence, which
+// only propagates the residual's increments, and the moment sums of the
+// deviations run in FP32, the phi^m/(4 pi) part of the moments in FP64.
 #include "gsis_internal.h"
 #include "wave_ops.h"
 
@@ -55,6 +56,7 @@ struct TArgs {
   double *rowbuf;
   const double *sdq;
   const float *sdq_f;   // FP32-mixed: the same diagonal in FP32 (the FP32 recurrence)
+  const float *w_f;     // FP32-mixed: w, w mu, w eta in FP32, [3][K] (the moment sums)
   const int2 *rtiles;
   int n_rtiles;
   const int *dso;    // row-0 storage index per diagonal, at offset kDiagPad
@@ -80,7 +82,7 @@ TArgs make_args(const PlanDev &P) {
   a.bnd = P.bnd; a.phih = P.phih; a.Fx = P.Fx; a.Fy = P.Fy; a.bflux = P.bflux;
   a.mom_part = P.mom_part;
   a.cellq = P.cellq; a.dynq = P.dynq; a.rowbuf = P.rowbuf;
-  a.sdq = P.sdq; a.sdq_f = P.sdq_f; a.rtiles = P.rtiles; a.n_rtiles = P.n_rtiles;
+  a.sdq = P.sdq; a.sdq_f = P.sdq_f; a.w_f = P.w_f; a.rtiles = P.rtiles; a.n_rtiles = P.n_rtiles;
   a.dso = P.dso;
   a.fp32 = P.precision == GSIS_FP32_MIXED ? 1 : 0;
   a.phi = P.phi;
@@ -1443,6 +1445,50 @@ __device__ __forceinline__ void moments_q(const TArgs &a, double *part, const lo
   cdouble *W = (cdouble *)a.w, *WM = (cdouble *)a.wmu, *WE = (cdouble *)a.weta;
   double s0 = 0, sx = 0, sy = 0;
   int kk = a.qoff[q];
+  if constexpr (sizeof(T) == 4) {
+    // FP32-mixed form: the stored deviations are summed in FP32, each group
+    // of eight ordinates as a balanced tree and the groups in order (the
+    // rounding of the sum stays near that of the FP32 values themselves);
+    // the combine adds the phi^m/(4 pi) part in FP64
+    typedef const __attribute__((address_space(4))) float cfloat;
+    cfloat *Wf = (cfloat *)a.w_f, *WMf = Wf + a.K, *WEf = Wf + 2 * a.K;
+    float f0 = 0.f, fx = 0.f, fy = 0.f;
+    const int ke = a.qoff[q + 1];
+    bool tested = false;
+    auto tree8 = [](const float (&p)[8]) {
+      return ((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7]));
+    };
+    for (; kk + 8 <= ke; kk += 8) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = (float)O[(size_t)(kk + u) * a.N + t];
+      if (!tested) {
+        if (f1 != 0) return;
+        tested = true;
+      }
+      float p0[8], px[8], py[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        p0[u] = Wf[kk + u] * v[u];
+        px[u] = WMf[kk + u] * v[u];
+        py[u] = WEf[kk + u] * v[u];
+      }
+      f0 += tree8(p0);
+      fx += tree8(px);
+      fy += tree8(py);
+    }
+    if (f1 != 0) return;
+    for (; kk < ke; ++kk) {
+      const float v = (float)O[(size_t)kk * a.N + t];
+      f0 = fmaf(Wf[kk], v, f0);
+      fx = fmaf(WMf[kk], v, fx);
+      fy = fmaf(WEf[kk], v, fy);
+    }
+    part[(size_t)(3 * q) * a.N + c] = (double)f0;
+    part[(size_t)(3 * q + 1) * a.N + c] = (double)fx;
+    part[(size_t)(3 * q + 2) * a.N + c] = (double)fy;
+    return;
+  }
   const int ke = a.qoff[q + 1];
   bool tested = false;
   for (; kk + 8 <= ke; kk += 8) {
