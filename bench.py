@@ -294,6 +294,56 @@ def measure_forms(ctx, gsis, inputs, np, torch, dev):
         "forward": {"iterations": int(n), "seconds": fsec},
         "adjoint": {"iterations": info["n_iter"], "seconds": asec},
         "adjoint_over_forward_time": asec / fsec}
+    # time-dependent form (backward Euler with the material energy equation)
+    # on the headline medium: GSIS and SI time steps, each to Err < 1e-6
+    ptd = dv(inputs.thick_square(256))
+    ntd = int(ptd["nx"]) * int(ptd["ny"]) * int(ptd["mu"].shape[0])
+    td = {"workload": "thick square 256x256x128 as the timed steps, with emission and the "
+                      "material energy equation: c = 1, a = 1, cv = 1, T0 = 0.1, 3 sub-iterations "
+                      "per inner iteration, Err < 1e-6 per step (SI capped at 300 inner "
+                      "iterations); one untimed step first, then 5 (GSIS) or 2 (SI) timed steps"}
+    for cdt in (0.01, 1.0):
+        row = {}
+        for name, method, cap, steps in (("gsis", gsis.GSIS_GSIS, 500, 5), ("si", gsis.GSIS_SI, 300, 2)):
+            pl = gsis.TDPlan(ctx, ptd, 0.1, c=1.0, a=1.0, dt=cdt, cv=1.0, sub_iter=3, method=method,
+                             tol=1e-6, max_iter=cap, limiter=1, synth_rtol=SYNTH_RTOL,
+                             synth_max_iter=50)
+            pl.advance(1)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, its, errs = pl.advance(steps)
+            torch.cuda.synchronize()
+            sec = time.perf_counter() - t0
+            pl.close()
+            row[name] = {"status": int(st), "inner_iterations": [int(v) for v in its],
+                         "converged": bool(all(e < 1e-6 for e in errs)),
+                         "seconds_per_step": sec / steps,
+                         "ms_per_inner_iteration": sec / max(sum(its), 1) * 1e3,
+                         "cell_ordinate_updates_per_s": ntd * sum(its) / sec}
+        row["si_over_gsis_inner_iterations"] = (sum(row["si"]["inner_iterations"]) / 2) / (
+            sum(row["gsis"]["inner_iterations"]) / 5)
+        td["c_dt_%g" % cdt] = row
+        log("time-dependent c dt = %g: GSIS %s, SI %s" % (cdt, row["gsis"]["inner_iterations"],
+                                                          row["si"]["inner_iterations"]))
+    forms["time_dependent"] = td
+    del ptd
+    # pseudo-time shift (local tau_p with beta, Eqs. tau_pse, elem_main_shifted)
+    # on the block medium, whose 1e5 opacity contrasts make plain GSIS diverge
+    pb = dv(inputs.checkerboard_blocks(256))
+    pt = {"workload": "block medium 256x256x128 (7x7 blocks sigma_a logU[1e-2,1e2] sigma_s "
+                      "logU[1e-1,1e4], seed 3), GSIS, limiter off, Err < 1e-6, at most 500 "
+                      "iterations"}
+    for beta in (0.0, 10.0):
+        pl = gsis.Plan(ctx, pb, tol=1e-6, max_iter=500, limiter=0, beta=beta)
+        sec = _converge(pl, 500)
+        n, conv, err = pl.status()
+        pl.close()
+        pt["beta_%g" % beta] = {"iterations": int(n), "seconds": sec, "final_err": float(err),
+                                "outcome": {1: "converged", -1: "diverged"}.get(int(conv),
+                                                                               "not converged")}
+        log("pseudo time beta %g: %d iterations, %s" % (beta, n, pt["beta_%g" % beta]["outcome"]))
+    forms["pseudo_time"] = pt
+    del pb
     # face-averaged synthetic flux (Eq. Fij_d) by sub-iterations against the
     # compact flux, on the headline workload
     pc = dv(inputs.thick_square(256))
