@@ -63,14 +63,14 @@ SYNTH_RTOL = 0.1
 # so FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0). Valid only for the kernel source
 # whose sha256 is recorded; any change to it turns the figures back to null.
 TRAFFIC = {
-    "thick256_fp64": {"sha256": "68724e78a7a9ea14ef954a9a1b41ff288db667dcb691684399b386ac07c1daf2",
-                      "k_resid": 243937200,     # 83931.2 KiB x 2.0 + 70357.5 KiB
-                      "k_chain": 138761912},    # 34863.5 KiB x 2.0 + 65782.6 KiB
-    "block1024_fp64": {"sha256": "68724e78a7a9ea14ef954a9a1b41ff288db667dcb691684399b386ac07c1daf2",
-                       "k_pipe": 3160253616},   # 971567.2 KiB x 2.0 + 1143050.8 KiB
-    "block1024_fp32": {"sha256": "68724e78a7a9ea14ef954a9a1b41ff288db667dcb691684399b386ac07c1daf2",
-                       "k_resid": 2973909504,   # 1159512.1 KiB x 2.0 + 585184.3 KiB
-                       "k_chain": 1281183488},  # 346750.1 KiB x 2.0 + 557655.6 KiB
+    "thick256_fp64": {"sha256": "4547a8b912d36cacdbb462a889f8b2ca9c02333c3cc14bc02fb446e3f96b781b",
+                      "k_resid": 244183100,     # 84064.8 KiB x 2.0 + 70330.5 KiB
+                      "k_chain": 138760036},    # 34863.5 KiB x 2.0 + 65780.8 KiB
+    "block1024_fp64": {"sha256": "4547a8b912d36cacdbb462a889f8b2ca9c02333c3cc14bc02fb446e3f96b781b",
+                       "k_pipe": 3153750072},   # 968598.7 KiB x 2.0 + 1142636.7 KiB
+    "block1024_fp32": {"sha256": "4547a8b912d36cacdbb462a889f8b2ca9c02333c3cc14bc02fb446e3f96b781b",
+                       "k_resid": 2972098360,   # 1158625.8 KiB x 2.0 + 585188.2 KiB
+                       "k_chain": 1281365228},  # 346850.4 KiB x 2.0 + 557632.3 KiB
 }
 KERNELS = {"k_resid": "k_resid (second-order residual of every cell-ordinate, ALSM gradient "
                       "and BJ limiter, written as the recurrence's right-hand side)",
