@@ -167,7 +167,7 @@ def kernel_traffic(cfg, kernel):
         sha = hashlib.sha256(f.read()).hexdigest()
     if sha != t["sha256"]:
         return None
-    return t[phase]
+    return t[kernel]
 
 
 def _converge(pl, cap, chunk=16):
