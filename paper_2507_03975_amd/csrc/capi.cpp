@@ -723,16 +723,6 @@ static gsis_status plan_create(gsis_ctx *ctx, const gsis_problem *p, const gsis_
     // by a stream synchronisation either way
     pl->host_scal = pl->host_flag_store;
   } else {
-    // the event the synthetic solve waits on while its next CG step runs
-    // (GSIS_SYNTH_SPECULATE=0: wait for the whole stream instead)
-    const char *sp = getenv("GSIS_SYNTH_SPECULATE");
-    if (!(sp && sp[0] == '0' && sp[1] == 0)) {
-      const hipError_t ee = hipEventCreateWithFlags(&P.S.flag_ev, hipEventDisableTiming);
-      if (ee != hipSuccess) {
-        P.S.flag_ev = nullptr;
-        return bail(fail(ctx, GSIS_E_DEVICE, "hipEventCreate: %s", hipGetErrorString(ee)));
-      }
-    }
     // flags read back by the synthetic solve: [0, 3) state and [8] the CG
     // count of the last forward solve; [4, 7) and [12] the same for the
     // adjoint's solves
@@ -758,7 +748,6 @@ extern "C" void gsis_plan_destroy(gsis_plan *pl) {
   else (void)hipDeviceSynchronize();
   for (void *v : pl->allocs) (void)hipFree(v);
   for (hipEvent_t e : pl->events) (void)hipEventDestroy(e);
-  if (pl->P.S.flag_ev) (void)hipEventDestroy(pl->P.S.flag_ev);
   adjoint_release(pl);
   if (pl->host_scal && !pl->arena) (void)hipHostFree(pl->host_scal);
   delete pl;

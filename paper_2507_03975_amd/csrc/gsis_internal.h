@@ -144,9 +144,6 @@ struct SynthSet {
   std::vector<int2 *> bt_tile;        // [l]: level-l tiles of problems with lc > l
   std::vector<int> nb_tile;
   int32_t *state0 = nullptr;          // single problem: its state (host checks)
-  hipEvent_t flag_ev = nullptr;       // single problem: marks the flags' copy, so
-                                      // the host can wait for it while the next
-                                      // CG step runs (none: wait for the stream)
 };
 
 struct PlanDev {

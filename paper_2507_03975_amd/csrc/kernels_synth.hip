@@ -1629,27 +1629,12 @@ void launch_synth_solve(const SynthSet &S, hipStream_t s, int32_t *host_flag, in
     if (host_flag && S.state0 && due) {
       (void)hipMemcpyAsync(host_flag, S.state0 + 1, 3 * sizeof(int32_t), hipMemcpyDeviceToHost,
                            s);
-      // With an event, the next CG step goes into the stream before the
-      // host waits for the flags, so the device keeps working while the host
-      // wakes up. If the flags then show the solve converged, that step's
-      // kernels find the device flag set and return before touching anything
-      // (the same results as without it); if not, it is the step that comes
-      // next anyway.
-      const bool spec = S.flag_ev && it + 2 < S.synth_max_iter;
-      if (spec) {
-        (void)hipEventRecord(S.flag_ev, s);
-        if (S.min_lc == 0) hipLaunchKernelGGL(k_cg_update, gc, bk, 0, s, ds, S.bt_cell, it + 1, 0);
-        vcycle(S, it + 2, s);
-        (void)hipEventSynchronize(S.flag_ev);
-      } else {
-        (void)hipStreamSynchronize(s);
-      }
+      (void)hipStreamSynchronize(s);
       if (host_flag[0] != 0) return;
       if (host_flag[2] != 0) {
         host_flag[8] = it + 1;
         return;
       }
-      if (spec) ++it;       // CG step it + 1 is in the stream already
     }
   }
 }
