@@ -299,11 +299,11 @@ __device__ inline bool finish_rr(CDesc &D, bool first, bool tiles, double *sh, c
     if (first) {
       scal[S_BB] = bb;
       scal[S_STOP] = stop;
-      scal[S_NIT] = 0.0;
-    } else {
-      scal[S_NIT] += 1.0;
     }
-    if (conv) D.state[3] = 1;
+    const double nit = first ? 0.0 : scal[S_NIT] + 1.0;
+    scal[S_NIT] = nit;
+    // converged: 1 + the CG iterations it took (the host's next check point)
+    if (conv) D.state[3] = 1 + (int32_t)nit;
   }
   return conv;
 }
@@ -1597,13 +1597,14 @@ void launch_hot(const SynthSet &S, hipStream_t s, bool combine) {
 // level-0 up kernel forms w = A z and the partials of r.z and z.w, and
 // every reduction is finished inside the kernel that needs it (see the
 // partial regions above). The stop test runs on the device (state[3] per
-// problem). With host_flag (a single problem), the host stops launching
-// once the solve has converged: it checks the device flags after the
-// V-cycle of the iteration at which the previous solve converged
-// (host_flag[8] keeps that count) and after every later one, so a steady
-// run waits once per solve. Without it (batches, graph capture) exactly
-// synth_max_iter iterations are launched and converged problems skip their
-// kernels.
+// problem: 1 + the iterations taken once converged). With host_flag (a
+// single problem), the host stops launching once the solve has converged:
+// it checks the device flags after the V-cycle that would make the test at
+// the iteration count the previous solve took (host_flag[8] keeps that
+// count) and after every later one, so a run whose counts stay level waits
+// once per solve and launches no V-cycle past convergence. Without it
+// (batches, graph capture) exactly synth_max_iter iterations are launched
+// and converged problems skip their kernels.
 void launch_synth_solve(const SynthSet &S, hipStream_t s, int32_t *host_flag, int rhs_mode,
                         int sub) {
   const SynthDesc *ds = S.desc;
@@ -1632,7 +1633,7 @@ void launch_synth_solve(const SynthSet &S, hipStream_t s, int32_t *host_flag, in
       (void)hipStreamSynchronize(s);
       if (host_flag[0] != 0) return;
       if (host_flag[2] != 0) {
-        host_flag[8] = it + 1;
+        host_flag[8] = max(1, host_flag[2] - 1);
         return;
       }
     }
