@@ -66,6 +66,8 @@ struct gsis_batch {
   int *counter = nullptr;
   int2 *bt_face = nullptr;         // (problem, boundary face)
   int nb_face = 0;
+  int2 *bt_mtile = nullptr;        // (problem, moment tile or -1): each problem's
+  int nb_mtile = 0;                // tiles in 8 runs, one per XCD (see the kernel)
   int32_t **state_p = nullptr;
   double **err_p = nullptr;
   int32_t *st_all = nullptr;
@@ -204,6 +206,19 @@ gsis_status build_tables(gsis_batch *b, const std::vector<int> &act) {
       for (int lb = 0; lb < source_tiles_of(D[a].nx, D[a].ny); ++lb) ts.push_back(make_int2(a, lb));
     S.nb_src = (int)ts.size();
     if ((st = tupload(b, &S.bt_src, ts))) return st;
+    // moment tiles: per problem 8 runs of tr = ceil(tiles / 8), entry p of
+    // the problem's 8 tr (a multiple of 8, so p % 8 is the XCD) taking tile
+    // (p % 8) tr + p / 8, or none
+    std::vector<int2> tm;
+    for (int a = 0; a < n; ++a) {
+      const int nt = moment_tiles_of(D[a].nx, D[a].ny), tr = (nt + 7) / 8;
+      for (int p = 0; p < 8 * tr; ++p) {
+        const int tl = (p % 8) * tr + p / 8;
+        tm.push_back(make_int2(a, tl < nt ? tl : -1));
+      }
+    }
+    b->nb_mtile = (int)tm.size();
+    if ((st = tupload(b, &b->bt_mtile, tm))) return st;
   }
   S.bt_tile.assign(max_lc, nullptr);
   S.nb_tile.assign(max_lc, 0);
@@ -295,7 +310,8 @@ void enqueue_iteration(gsis_batch *b, bool capture) {
   } else {
     launch_sweep_batch(b->targs, b->items, b->n_items, b->counter, b->cfg, b->fp32, b->grid, s);
   }
-  launch_moments_batch(b->targs, b->S.bt_cell, b->S.nb_cell, b->fp32, s);
+  launch_moments_batch(b->targs, b->S.bt_cell, b->S.nb_cell, b->bt_mtile, b->nb_mtile, b->fp32,
+                       s);
   if (b->method == GSIS_GSIS) {
     launch_boundary_flux_batch(b->targs, b->bt_face, b->nb_face, s);
     launch_hot(b->S, s, false);

@@ -282,10 +282,11 @@ void fill_targs(const PlanDev &P, void *dst);
 int sweep_batch_blocks_per_cu(int cfg, bool fp32);
 void launch_sweep_batch(const void *targs, const int2 *items, int n_items, int *counter, int cfg,
                         bool fp32, int grid, hipStream_t s);
-// moments over blocks (problem, 256-cell block) and boundary fluxes over
-// (problem, boundary face) of a batch
-void launch_moments_batch(const void *targs, const int2 *bt_cell, int nb_cell, bool fp32,
-                          hipStream_t s);
+// moments of a batch: partials over (problem, 16 x 16 tile or -1) blocks,
+// then the combine over (problem, 256-cell block) blocks; boundary fluxes
+// over (problem, boundary face)
+void launch_moments_batch(const void *targs, const int2 *bt_cell, int nb_cell,
+                          const int2 *bt_tile, int nb_tile, bool fp32, hipStream_t s);
 void launch_boundary_flux_batch(const void *targs, const int2 *bt_face, int nb_face,
                                 hipStream_t s);
 // phi, F of the swept intensity; with bflux (GSIS) only the per-quadrant
@@ -301,6 +302,7 @@ int coarse_start(const PlanDev &P);
 size_t coarse_lds_bytes(const PlanDev &P);
 int tiles_of(int nx, int ny);   // multigrid tiles covering an nx x ny level
 int source_tiles_of(int nx, int ny);   // 16 x 16 tiles of the source kernel
+int moment_tiles_of(int nx, int ny);   // tiles of the moment kernels
 void prepare_synth(size_t coarse_lds);      // kernel attribute for the LDS size
 void launch_source(const SynthSet &S, hipStream_t s);          // src from phi
 // HoT of every cell; combine: first phi, F of I^{m+1/2} from the quadrant

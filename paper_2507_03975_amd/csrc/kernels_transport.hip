@@ -1400,9 +1400,10 @@ __global__ void __launch_bounds__(kCMaxW * 64)
 
 __global__ void k_zero_int(int *p) { *p = 0; }
 
-// phi, F of I^{m+1/2} in two passes: per quadrant, one thread per stored
-// cell sums the quadrant's ordinates (contiguous reads) into partials at the
-// caller's cell index; then the four partials are added in a fixed order.
+// phi, F of I^{m+1/2} in two passes: per quadrant and tile, sums over the
+// quadrant's ordinates into partials at the caller's cell index (below);
+// then the four partials are added in a fixed order. dg_cell: the cell (x,
+// y) of stored index t.
 __device__ inline void dg_cell(long long t, int nx, int ny, int &x, int &y) {
   int lo = 0, hi = nx + ny - 2;               // find d with off(d) <= t < off(d+1)
   while (lo < hi) {
@@ -1429,14 +1430,47 @@ __device__ __forceinline__ void src2_block(const TArgs &a, const int blk) {
   if (threadIdx.x == 0 && a.state[1] == 0) a.src2_part[blk] = red[0];
 }
 
+// Moment partials of one quadrant over one kMT x kMT tile of the caller's
+// grid, one thread per cell. In the quadrant's mirrored frame the tile is a
+// square whose anti-diagonals are contiguous runs of the stored intensity:
+// thread t takes the square's t-th cell in anti-diagonal order, so the
+// loads of a wave run along those runs; the sums go through LDS and the
+// partials are stored by rows of the caller's grid. ftp (transport-face
+// HoT): the thread also forms its cell's interior face fluxes.
+constexpr int kMT = 16;
+static_assert(kMT * kMT == 256, "one thread per tile cell");
+// cell t of a kMT x kMT square in anti-diagonal order (diagonal e = u + w,
+// then w): its place (u, w) in the square
+__device__ inline void square_diag(int t, int &u, int &w) {
+  int e = 0, before = 0;
+  for (;; ++e) {
+    const int len = e < kMT ? e + 1 : 2 * kMT - 1 - e;
+    if (t < before + len) break;
+    before += len;
+  }
+  w = (e < kMT ? 0 : e - kMT + 1) + (t - before);
+  u = e - w;
+}
 template <typename T>
-__device__ __forceinline__ void moments_q(const TArgs &a, double *part, const long long t,
-                                          const int q) {
+__device__ void face_flux_q(const TArgs &a, double *ftp, const long long t, const int q);
+
+template <typename T>
+__device__ __forceinline__ void moments_tile(const TArgs &a, double *part, double *ftp,
+                                             const int tile, const int q) {
+  __shared__ double sm[3][kMT * kMT];
   const int f1 = a.state[1];   // tested once the first values are loaded
-  if (t >= a.N) return;
-  int x, y;
-  dg_cell(t, a.nx, a.ny, x, y);
-  const int c = gcell(a, q, x, y);
+  const int nx = a.nx, ny = a.ny, N = a.N;
+  const int tw = (nx + kMT - 1) / kMT;
+  const int i0 = (tile % tw) * kMT, j0 = (tile / tw) * kMT;
+  int u, w;
+  square_diag(threadIdx.x, u, w);
+  // the square in the quadrant's frame: local x runs against x when the
+  // quadrant is mirrored in x, local y against y when mirrored in y
+  const int xl = (q & 1) ? nx - i0 - kMT + u : i0 + u;
+  const int yl = (q & 2) ? ny - j0 - kMT + w : j0 + w;
+  const bool in = xl >= 0 && xl < nx && yl >= 0 && yl < ny;
+  const long long t = in ? dg_idx(xl, yl, nx, ny) : 0;
+  if (ftp && in) face_flux_q<T>(a, ftp, t, q);
   const T *O = Iout_of<T>(a);
   // weights through the constant address space (scalar loads); the
   // ordinates' values are loaded eight at a time before they are summed,
@@ -1445,6 +1479,7 @@ __device__ __forceinline__ void moments_q(const TArgs &a, double *part, const lo
   cdouble *W = (cdouble *)a.w, *WM = (cdouble *)a.wmu, *WE = (cdouble *)a.weta;
   double s0 = 0, sx = 0, sy = 0;
   int kk = a.qoff[q];
+  const int ke = a.qoff[q + 1];
   if constexpr (sizeof(T) == 4) {
     // FP32-mixed form: the stored deviations are summed in FP32, each group
     // of eight ordinates as a balanced tree and the groups in order (the
@@ -1453,69 +1488,66 @@ __device__ __forceinline__ void moments_q(const TArgs &a, double *part, const lo
     typedef const __attribute__((address_space(4))) float cfloat;
     cfloat *Wf = (cfloat *)a.w_f, *WMf = Wf + a.K, *WEf = Wf + 2 * a.K;
     float f0 = 0.f, fx = 0.f, fy = 0.f;
-    const int ke = a.qoff[q + 1];
-    bool tested = false;
     auto tree8 = [](const float (&p)[8]) {
       return ((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7]));
     };
+    if (in) {
+      for (; kk + 8 <= ke; kk += 8) {
+        float v[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) v[m] = (float)O[(size_t)(kk + m) * N + t];
+        float p0[8], px[8], py[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+          p0[m] = Wf[kk + m] * v[m];
+          px[m] = WMf[kk + m] * v[m];
+          py[m] = WEf[kk + m] * v[m];
+        }
+        f0 += tree8(p0);
+        fx += tree8(px);
+        fy += tree8(py);
+      }
+      for (; kk < ke; ++kk) {
+        const float v = (float)O[(size_t)kk * N + t];
+        f0 = fmaf(Wf[kk], v, f0);
+        fx = fmaf(WMf[kk], v, fx);
+        fy = fmaf(WEf[kk], v, fy);
+      }
+    }
+    s0 = (double)f0; sx = (double)fx; sy = (double)fy;
+  } else if (in) {
     for (; kk + 8 <= ke; kk += 8) {
-      float v[8];
+      double v[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = (float)O[(size_t)(kk + u) * a.N + t];
-      if (!tested) {
-        if (f1 != 0) return;
-        tested = true;
-      }
-      float p0[8], px[8], py[8];
+      for (int m = 0; m < 8; ++m) v[m] = (double)O[(size_t)(kk + m) * N + t];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        p0[u] = Wf[kk + u] * v[u];
-        px[u] = WMf[kk + u] * v[u];
-        py[u] = WEf[kk + u] * v[u];
+      for (int m = 0; m < 8; ++m) {
+        s0 += W[kk + m] * v[m];
+        sx += WM[kk + m] * v[m];
+        sy += WE[kk + m] * v[m];
       }
-      f0 += tree8(p0);
-      fx += tree8(px);
-      fy += tree8(py);
     }
-    if (f1 != 0) return;
     for (; kk < ke; ++kk) {
-      const float v = (float)O[(size_t)kk * a.N + t];
-      f0 = fmaf(Wf[kk], v, f0);
-      fx = fmaf(WMf[kk], v, fx);
-      fy = fmaf(WEf[kk], v, fy);
-    }
-    part[(size_t)(3 * q) * a.N + c] = (double)f0;
-    part[(size_t)(3 * q + 1) * a.N + c] = (double)fx;
-    part[(size_t)(3 * q + 2) * a.N + c] = (double)fy;
-    return;
-  }
-  const int ke = a.qoff[q + 1];
-  bool tested = false;
-  for (; kk + 8 <= ke; kk += 8) {
-    double v[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = (double)O[(size_t)(kk + u) * a.N + t];
-    if (!tested) {
-      if (f1 != 0) return;
-      tested = true;
-    }
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      s0 += W[kk + u] * v[u];
-      sx += WM[kk + u] * v[u];
-      sy += WE[kk + u] * v[u];
+      const double v = (double)O[(size_t)kk * N + t];
+      s0 += W[kk] * v;
+      sx += WM[kk] * v;
+      sy += WE[kk] * v;
     }
   }
-  if (f1 != 0) return;
-  for (; kk < ke; ++kk) {
-    const double v = (double)O[(size_t)kk * a.N + t];
-    s0 += W[kk] * v;
-    sx += WM[kk] * v;
-    sy += WE[kk] * v;
+  if (f1 != 0) return;   // the whole block
+  // place in the tile of the caller's grid
+  const int l = ((q & 2) ? kMT - 1 - w : w) * kMT + ((q & 1) ? kMT - 1 - u : u);
+  sm[0][l] = s0;
+  sm[1][l] = sx;
+  sm[2][l] = sy;
+  __syncthreads();
+  const int i = i0 + (int)(threadIdx.x & (kMT - 1)), j = j0 + (int)threadIdx.x / kMT;
+  if (i < nx && j < ny) {
+    const size_t c = (size_t)j * nx + i;
+    part[(size_t)(3 * q) * N + c] = sm[0][threadIdx.x];
+    part[(size_t)(3 * q + 1) * N + c] = sm[1][threadIdx.x];
+    part[(size_t)(3 * q + 2) * N + c] = sm[2][threadIdx.x];
   }
-  part[(size_t)(3 * q) * a.N + c] = s0;
-  part[(size_t)(3 * q + 1) * a.N + c] = sx;
-  part[(size_t)(3 * q + 2) * a.N + c] = sy;
 }
 
 // Transport fluxes through the interior faces (GSIS with transport-face HoT,
@@ -1528,8 +1560,7 @@ __device__ __forceinline__ void moments_q(const TArgs &a, double *part, const lo
 // the east (+x) face of cell c, or of c - 1 when the quadrant is mirrored in
 // x; the north face of c, or of c - nx when mirrored in y.
 template <typename T>
-__device__ __forceinline__ void face_flux_q(const TArgs &a, double *ftp, const long long t,
-                                            const int q) {
+__device__ void face_flux_q(const TArgs &a, double *ftp, const long long t, const int q) {
   const int f1 = a.state[1];
   if (t >= a.N) return;
   const int nx = a.nx, ny = a.ny, N = a.N;
@@ -1565,19 +1596,31 @@ __device__ __forceinline__ void face_flux_q(const TArgs &a, double *ftp, const l
   if (hn) ftp[(size_t)(2 * q + 1) * N + ((q & 2) ? c - nx : c)] = pn;
 }
 
+// Tiles by XCD: the tiles (row-major) fall into 8 runs of ts = ceil(ntile /
+// 8), one per XCD, so tiles whose stored diagonals share cache lines mostly
+// meet in one L2. Block b (of a range that starts at a multiple of 8) runs
+// on XCD b % 8 and takes tile (b % 8) ts + b / 8, none past the grid.
+__device__ inline int xcd_tile(int b, int ts) { return (b & 7) * ts + (b >> 3); }
+
+// Moment partials: block (tile slot, quadrant); the quadrant-0 blocks whose
+// tile lies below ceil(N / 256) also sum src^2 over that block of 256 cells.
 template <typename T>
-__global__ void k_moments_q(TArgs a, double *part) {
-  if (blockIdx.y == 0) src2_block(a, blockIdx.x);
-  moments_q<T>(a, part, blockIdx.x * (long long)blockDim.x + threadIdx.x, blockIdx.y);
+__global__ void k_moments_q(TArgs a, double *part, int ntile, int ts) {
+  const int tile = xcd_tile(blockIdx.x, ts);
+  if (tile >= ntile || (blockIdx.x >> 3) >= ts) return;
+  if (blockIdx.y == 0 && tile < (a.N + 255) / 256) src2_block(a, tile);
+  moments_tile<T>(a, part, nullptr, tile, blockIdx.y);
 }
 
-// Batched launches: bt maps block -> (problem, block of that problem).
+// Batched launches: bt maps block -> (problem, tile of that problem, or -1:
+// none), each problem's tiles in runs by XCD as above.
 template <typename T>
 __global__ void k_moments_q_b(const TArgs *tas, const int2 *bt) {
   const int2 v = bt[blockIdx.x];
+  if (v.y < 0) return;
   const TArgs &a = tas[v.x];
-  if (blockIdx.y == 0) src2_block(a, v.y);
-  moments_q<T>(a, a.mom_part, v.y * (long long)blockDim.x + threadIdx.x, blockIdx.y);
+  if (blockIdx.y == 0 && v.y < (a.N + 255) / 256) src2_block(a, v.y);
+  moments_tile<T>(a, a.mom_part, nullptr, v.y, blockIdx.y);
 }
 
 __device__ __forceinline__ void moments_combine(const TArgs &a, const double *part, const int c) {
@@ -1665,17 +1708,18 @@ __device__ __forceinline__ void boundary_flux(const TArgs &a, const int f) {
 // With ftp (transport-face HoT) the moment blocks also form the quadrant's
 // interior face fluxes.
 template <typename T>
-__global__ void k_moments_q_bflux(TArgs a, double *part, int nbc, double *ftp) {
-  const int b = (int)blockIdx.x - a.nbf;
+__global__ void k_moments_q_bflux(TArgs a, double *part, int nbf8, int ntile, int ts,
+                                  double *ftp) {
+  const int b = (int)blockIdx.x - nbf8;   // nbf8: a.nbf rounded up to a multiple of 8
   if (b < 0) {
-    boundary_flux(a, blockIdx.x);
+    if ((int)blockIdx.x < a.nbf) boundary_flux(a, blockIdx.x);
     return;
   }
-  const int q = b / nbc;
-  if (q == 0) src2_block(a, b);
-  const long long t = (b - q * nbc) * (long long)blockDim.x + threadIdx.x;
-  if (ftp) face_flux_q<T>(a, ftp, t, q);
-  moments_q<T>(a, part, t, q);
+  const int q = b / (8 * ts), r = b - q * 8 * ts;
+  const int tile = xcd_tile(r, ts);
+  if (tile >= ntile || (r >> 3) >= ts) return;
+  if (q == 0 && tile < (a.N + 255) / 256) src2_block(a, tile);
+  moments_tile<T>(a, part, ftp, tile, q);
 }
 
 __global__ void k_boundary_flux_b(const TArgs *tas, const int2 *bt) {
@@ -1826,6 +1870,8 @@ int residual_pairs(const PlanDev &P) {
   return pairs;
 }
 
+int moment_tiles_of(int nx, int ny) { return ((nx + kMT - 1) / kMT) * ((ny + kMT - 1) / kMT); }
+
 std::vector<int2> residual_tiles(int nx, int ny) {
   std::vector<int2> t;
   for (int y0 = 0; y0 < ny; y0 += 64) {
@@ -1939,30 +1985,37 @@ void launch_sweep_batch(const void *targs, const int2 *items, int n_items, int *
 void launch_moments(const PlanDev &P, hipStream_t s, bool bflux) {
   TArgs a = make_args(P);
   const int nbc = (P.N + 255) / 256;
+  const int ntile = moment_tiles_of(P.nx, P.ny);   // >= nbc
+  const int ts = (ntile + 7) / 8;   // tiles per XCD
   if (bflux) {   // the combine follows in the HoT kernel
-    const dim3 g(P.nbf + 4 * nbc);
+    const int nbf8 = (P.nbf + 7) / 8 * 8;
+    const dim3 g(nbf8 + 4 * 8 * ts);
     double *ftp = P.hot_face ? P.ftp : nullptr;
     if (a.fp32)
-      hipLaunchKernelGGL(k_moments_q_bflux<float>, g, dim3(256), 0, s, a, P.mom_part, nbc, ftp);
+      hipLaunchKernelGGL(k_moments_q_bflux<float>, g, dim3(256), 0, s, a, P.mom_part, nbf8, ntile,
+                         ts, ftp);
     else
-      hipLaunchKernelGGL(k_moments_q_bflux<double>, g, dim3(256), 0, s, a, P.mom_part, nbc, ftp);
+      hipLaunchKernelGGL(k_moments_q_bflux<double>, g, dim3(256), 0, s, a, P.mom_part, nbf8,
+                         ntile, ts, ftp);
     return;
   }
   if (a.fp32)
-    hipLaunchKernelGGL(k_moments_q<float>, dim3(nbc, 4), dim3(256), 0, s, a, P.mom_part);
+    hipLaunchKernelGGL(k_moments_q<float>, dim3(8 * ts, 4), dim3(256), 0, s, a, P.mom_part, ntile,
+                       ts);
   else
-    hipLaunchKernelGGL(k_moments_q<double>, dim3(nbc, 4), dim3(256), 0, s, a, P.mom_part);
+    hipLaunchKernelGGL(k_moments_q<double>, dim3(8 * ts, 4), dim3(256), 0, s, a, P.mom_part,
+                       ntile, ts);
   hipLaunchKernelGGL(k_moments_combine, dim3(nbc), dim3(256), 0, s, a,
                      (const double *)P.mom_part);
 }
 
-void launch_moments_batch(const void *targs, const int2 *bt_cell, int nb_cell, bool fp32,
-                          hipStream_t s) {
+void launch_moments_batch(const void *targs, const int2 *bt_cell, int nb_cell,
+                          const int2 *bt_tile, int nb_tile, bool fp32, hipStream_t s) {
   const TArgs *ta = reinterpret_cast<const TArgs *>(targs);
   if (fp32)
-    hipLaunchKernelGGL(k_moments_q_b<float>, dim3(nb_cell, 4), dim3(256), 0, s, ta, bt_cell);
+    hipLaunchKernelGGL(k_moments_q_b<float>, dim3(nb_tile, 4), dim3(256), 0, s, ta, bt_tile);
   else
-    hipLaunchKernelGGL(k_moments_q_b<double>, dim3(nb_cell, 4), dim3(256), 0, s, ta, bt_cell);
+    hipLaunchKernelGGL(k_moments_q_b<double>, dim3(nb_tile, 4), dim3(256), 0, s, ta, bt_tile);
   hipLaunchKernelGGL(k_moments_combine_b, dim3(nb_cell), dim3(256), 0, s, ta, bt_cell);
 }
 
