@@ -211,7 +211,8 @@ gsis_status build_tables(gsis_batch *b, const std::vector<int> &act) {
     // (p % 8) tr + p / 8, or none
     std::vector<int2> tm;
     for (int a = 0; a < n; ++a) {
-      const int nt = moment_tiles_of(D[a].nx, D[a].ny), tr = (nt + 7) / 8;
+      const int nt = moment_tiles_of(D[a].nx, D[a].ny, moment_tile_size_batch());
+      const int tr = (nt + 7) / 8;
       for (int p = 0; p < 8 * tr; ++p) {
         const int tl = (p % 8) * tr + p / 8;
         tm.push_back(make_int2(a, tl < nt ? tl : -1));

@@ -302,7 +302,11 @@ int coarse_start(const PlanDev &P);
 size_t coarse_lds_bytes(const PlanDev &P);
 int tiles_of(int nx, int ny);   // multigrid tiles covering an nx x ny level
 int source_tiles_of(int nx, int ny);   // 16 x 16 tiles of the source kernel
-int moment_tiles_of(int nx, int ny);   // tiles of the moment kernels
+// tiles of the moment kernels: edge mt (16 or 32; moment_tile_size for a
+// plan, moment_tile_size_batch for batches)
+int moment_tile_size(int nx, int ny);
+int moment_tile_size_batch();
+int moment_tiles_of(int nx, int ny, int mt);
 void prepare_synth(size_t coarse_lds);      // kernel attribute for the LDS size
 void launch_source(const SynthSet &S, hipStream_t s);          // src from phi
 // HoT of every cell; combine: first phi, F of I^{m+1/2} from the quadrant

@@ -1430,17 +1430,19 @@ __device__ __forceinline__ void src2_block(const TArgs &a, const int blk) {
   if (threadIdx.x == 0 && a.state[1] == 0) a.src2_part[blk] = red[0];
 }
 
-// Moment partials of one quadrant over one kMT x kMT tile of the caller's
-// grid, one thread per cell. In the quadrant's mirrored frame the tile is a
-// square whose anti-diagonals are contiguous runs of the stored intensity:
-// thread t takes the square's t-th cell in anti-diagonal order, so the
-// loads of a wave run along those runs; the sums go through LDS and the
-// partials are stored by rows of the caller's grid. ftp (transport-face
-// HoT): the thread also forms its cell's interior face fluxes.
-constexpr int kMT = 16;
-static_assert(kMT * kMT == 256, "one thread per tile cell");
+// Moment partials of one quadrant over one MT x MT tile of the caller's
+// grid (MT = 16 or 32), MT^2 / 256 cells per thread. In the quadrant's
+// mirrored frame the tile is a square whose anti-diagonals are contiguous
+// runs (up to MT cells) of the stored intensity: the square's cells are
+// numbered in anti-diagonal order and thread t takes cells t, t + 256, ...,
+// so the loads of a wave run along those runs; the sums go through LDS and
+// the partials are stored by rows of the caller's grid. Larger tiles waste
+// less of the cache lines at the runs' ends; smaller ones give small grids
+// more workgroups. ftp (transport-face HoT): the thread also forms its
+// cells' interior face fluxes.
 // cell t of a kMT x kMT square in anti-diagonal order (diagonal e = u + w,
 // then w): its place (u, w) in the square
+template <int kMT>
 __device__ inline void square_diag(int t, int &u, int &w) {
   int e = 0, before = 0;
   for (;; ++e) {
@@ -1451,35 +1453,42 @@ __device__ inline void square_diag(int t, int &u, int &w) {
   w = (e < kMT ? 0 : e - kMT + 1) + (t - before);
   u = e - w;
 }
+
 template <typename T>
 __device__ void face_flux_q(const TArgs &a, double *ftp, const long long t, const int q);
 
-template <typename T>
+template <typename T, int kMT>
 __device__ __forceinline__ void moments_tile(const TArgs &a, double *part, double *ftp,
                                              const int tile, const int q) {
+  constexpr int kMC = kMT * kMT / 256;
+  static_assert(kMC * 256 == kMT * kMT, "whole cells per thread");
   __shared__ double sm[3][kMT * kMT];
   const int f1 = a.state[1];   // tested once the first values are loaded
   const int nx = a.nx, ny = a.ny, N = a.N;
   const int tw = (nx + kMT - 1) / kMT;
   const int i0 = (tile % tw) * kMT, j0 = (tile / tw) * kMT;
-  int u, w;
-  square_diag(threadIdx.x, u, w);
-  // the square in the quadrant's frame: local x runs against x when the
-  // quadrant is mirrored in x, local y against y when mirrored in y
-  const int xl = (q & 1) ? nx - i0 - kMT + u : i0 + u;
-  const int yl = (q & 2) ? ny - j0 - kMT + w : j0 + w;
-  const bool in = xl >= 0 && xl < nx && yl >= 0 && yl < ny;
-  const long long t = in ? dg_idx(xl, yl, nx, ny) : 0;
-  if (ftp && in) face_flux_q<T>(a, ftp, t, q);
+  int u[kMC], w[kMC];
+  bool in[kMC];
+  long long t[kMC];
+#pragma unroll
+  for (int h = 0; h < kMC; ++h) {
+    square_diag<kMT>((int)threadIdx.x + 256 * h, u[h], w[h]);
+    // the square in the quadrant's frame: local x runs against x when the
+    // quadrant is mirrored in x, local y against y when mirrored in y
+    const int xl = (q & 1) ? nx - i0 - kMT + u[h] : i0 + u[h];
+    const int yl = (q & 2) ? ny - j0 - kMT + w[h] : j0 + w[h];
+    in[h] = xl >= 0 && xl < nx && yl >= 0 && yl < ny;
+    t[h] = in[h] ? dg_idx(xl, yl, nx, ny) : 0;
+    if (ftp && in[h]) face_flux_q<T>(a, ftp, t[h], q);
+  }
   const T *O = Iout_of<T>(a);
-  // weights through the constant address space (scalar loads); the
-  // ordinates' values are loaded eight at a time before they are summed,
-  // in the same order as one at a time
+  // weights through the constant address space (scalar loads); each cell's
+  // ordinates are loaded eight at a time (all the thread's cells at once)
+  // before they are summed, in the same order as one at a time
   typedef const __attribute__((address_space(4))) double cdouble;
   cdouble *W = (cdouble *)a.w, *WM = (cdouble *)a.wmu, *WE = (cdouble *)a.weta;
-  double s0 = 0, sx = 0, sy = 0;
-  int kk = a.qoff[q];
-  const int ke = a.qoff[q + 1];
+  double s0[kMC], sx[kMC], sy[kMC];
+  const int kb = a.qoff[q], ke = a.qoff[q + 1];
   if constexpr (sizeof(T) == 4) {
     // FP32-mixed form: the stored deviations are summed in FP32, each group
     // of eight ordinates as a balanced tree and the groups in order (the
@@ -1487,67 +1496,106 @@ __device__ __forceinline__ void moments_tile(const TArgs &a, double *part, doubl
     // the combine adds the phi^m/(4 pi) part in FP64
     typedef const __attribute__((address_space(4))) float cfloat;
     cfloat *Wf = (cfloat *)a.w_f, *WMf = Wf + a.K, *WEf = Wf + 2 * a.K;
-    float f0 = 0.f, fx = 0.f, fy = 0.f;
+    float f0[kMC] = {}, fx[kMC] = {}, fy[kMC] = {};
     auto tree8 = [](const float (&p)[8]) {
       return ((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7]));
     };
-    if (in) {
-      for (; kk + 8 <= ke; kk += 8) {
-        float v[8];
+    int kk = kb;
+    for (; kk + 8 <= ke; kk += 8) {
+      float v[kMC][8];
 #pragma unroll
-        for (int m = 0; m < 8; ++m) v[m] = (float)O[(size_t)(kk + m) * N + t];
+      for (int h = 0; h < kMC; ++h)
+#pragma unroll
+        for (int m = 0; m < 8; ++m) v[h][m] = in[h] ? (float)O[(size_t)(kk + m) * N + t[h]] : 0.f;
+#pragma unroll
+      for (int h = 0; h < kMC; ++h) {
         float p0[8], px[8], py[8];
 #pragma unroll
         for (int m = 0; m < 8; ++m) {
-          p0[m] = Wf[kk + m] * v[m];
-          px[m] = WMf[kk + m] * v[m];
-          py[m] = WEf[kk + m] * v[m];
+          p0[m] = Wf[kk + m] * v[h][m];
+          px[m] = WMf[kk + m] * v[h][m];
+          py[m] = WEf[kk + m] * v[h][m];
         }
-        f0 += tree8(p0);
-        fx += tree8(px);
-        fy += tree8(py);
-      }
-      for (; kk < ke; ++kk) {
-        const float v = (float)O[(size_t)kk * N + t];
-        f0 = fmaf(Wf[kk], v, f0);
-        fx = fmaf(WMf[kk], v, fx);
-        fy = fmaf(WEf[kk], v, fy);
-      }
-    }
-    s0 = (double)f0; sx = (double)fx; sy = (double)fy;
-  } else if (in) {
-    for (; kk + 8 <= ke; kk += 8) {
-      double v[8];
-#pragma unroll
-      for (int m = 0; m < 8; ++m) v[m] = (double)O[(size_t)(kk + m) * N + t];
-#pragma unroll
-      for (int m = 0; m < 8; ++m) {
-        s0 += W[kk + m] * v[m];
-        sx += WM[kk + m] * v[m];
-        sy += WE[kk + m] * v[m];
+        f0[h] += tree8(p0);
+        fx[h] += tree8(px);
+        fy[h] += tree8(py);
       }
     }
     for (; kk < ke; ++kk) {
-      const double v = (double)O[(size_t)kk * N + t];
-      s0 += W[kk] * v;
-      sx += WM[kk] * v;
-      sy += WE[kk] * v;
+#pragma unroll
+      for (int h = 0; h < kMC; ++h) {
+        const float v = in[h] ? (float)O[(size_t)kk * N + t[h]] : 0.f;
+        f0[h] = fmaf(Wf[kk], v, f0[h]);
+        fx[h] = fmaf(WMf[kk], v, fx[h]);
+        fy[h] = fmaf(WEf[kk], v, fy[h]);
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < kMC; ++h) {
+      s0[h] = (double)f0[h]; sx[h] = (double)fx[h]; sy[h] = (double)fy[h];
+    }
+  } else {
+#pragma unroll
+    for (int h = 0; h < kMC; ++h) s0[h] = sx[h] = sy[h] = 0.0;
+    int kk = kb;
+    for (; kk + 8 <= ke; kk += 8) {
+      double v[kMC][8];
+#pragma unroll
+      for (int h = 0; h < kMC; ++h)
+#pragma unroll
+        for (int m = 0; m < 8; ++m) v[h][m] = in[h] ? (double)O[(size_t)(kk + m) * N + t[h]] : 0.0;
+#pragma unroll
+      for (int h = 0; h < kMC; ++h)
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+          s0[h] += W[kk + m] * v[h][m];
+          sx[h] += WM[kk + m] * v[h][m];
+          sy[h] += WE[kk + m] * v[h][m];
+        }
+    }
+    for (; kk < ke; ++kk) {
+#pragma unroll
+      for (int h = 0; h < kMC; ++h) {
+        const double v = in[h] ? (double)O[(size_t)kk * N + t[h]] : 0.0;
+        s0[h] += W[kk] * v;
+        sx[h] += WM[kk] * v;
+        sy[h] += WE[kk] * v;
+      }
     }
   }
   if (f1 != 0) return;   // the whole block
-  // place in the tile of the caller's grid
-  const int l = ((q & 2) ? kMT - 1 - w : w) * kMT + ((q & 1) ? kMT - 1 - u : u);
-  sm[0][l] = s0;
-  sm[1][l] = sx;
-  sm[2][l] = sy;
-  __syncthreads();
-  const int i = i0 + (int)(threadIdx.x & (kMT - 1)), j = j0 + (int)threadIdx.x / kMT;
-  if (i < nx && j < ny) {
-    const size_t c = (size_t)j * nx + i;
-    part[(size_t)(3 * q) * N + c] = sm[0][threadIdx.x];
-    part[(size_t)(3 * q + 1) * N + c] = sm[1][threadIdx.x];
-    part[(size_t)(3 * q + 2) * N + c] = sm[2][threadIdx.x];
+#pragma unroll
+  for (int h = 0; h < kMC; ++h) {
+    // place in the tile of the caller's grid
+    const int l = ((q & 2) ? kMT - 1 - w[h] : w[h]) * kMT + ((q & 1) ? kMT - 1 - u[h] : u[h]);
+    sm[0][l] = s0[h];
+    sm[1][l] = sx[h];
+    sm[2][l] = sy[h];
   }
+  __syncthreads();
+#pragma unroll
+  for (int h = 0; h < kMC; ++h) {
+    const int l = (int)threadIdx.x + 256 * h;
+    const int i = i0 + (l & (kMT - 1)), j = j0 + l / kMT;
+    if (i < nx && j < ny) {
+      const size_t c = (size_t)j * nx + i;
+      part[(size_t)(3 * q) * N + c] = sm[0][l];
+      part[(size_t)(3 * q + 1) * N + c] = sm[1][l];
+      part[(size_t)(3 * q + 2) * N + c] = sm[2][l];
+    }
+  }
+}
+
+// src^2 over the blocks of 256 cells (natural order) that go with moment
+// tile `tile`: blocks kMC tile .. kMC tile + kMC - 1, those below nbc (the
+// tiles number at least nbc / kMC)
+template <int kMT>
+__device__ __forceinline__ void src2_tile(const TArgs &a, const int tile) {
+  constexpr int kMC = kMT * kMT / 256;
+  const int nbc = (a.N + 255) / 256;
+#pragma unroll
+  for (int h = 0; h < kMC; ++h)
+    if (kMC * tile + h < nbc) src2_block(a, kMC * tile + h);
 }
 
 // Transport fluxes through the interior faces (GSIS with transport-face HoT,
@@ -1602,25 +1650,27 @@ __device__ void face_flux_q(const TArgs &a, double *ftp, const long long t, cons
 // on XCD b % 8 and takes tile (b % 8) ts + b / 8, none past the grid.
 __device__ inline int xcd_tile(int b, int ts) { return (b & 7) * ts + (b >> 3); }
 
-// Moment partials: block (tile slot, quadrant); the quadrant-0 blocks whose
-// tile lies below ceil(N / 256) also sum src^2 over that block of 256 cells.
-template <typename T>
+// Moment partials: block (tile slot, quadrant); the quadrant-0 blocks also
+// sum src^2 over the tile's blocks of 256 cells (src2_tile).
+template <typename T, int MT>
 __global__ void k_moments_q(TArgs a, double *part, int ntile, int ts) {
   const int tile = xcd_tile(blockIdx.x, ts);
   if (tile >= ntile || (blockIdx.x >> 3) >= ts) return;
-  if (blockIdx.y == 0 && tile < (a.N + 255) / 256) src2_block(a, tile);
-  moments_tile<T>(a, part, nullptr, tile, blockIdx.y);
+  if (blockIdx.y == 0) src2_tile<MT>(a, tile);
+  moments_tile<T, MT>(a, part, nullptr, tile, blockIdx.y);
 }
 
 // Batched launches: bt maps block -> (problem, tile of that problem, or -1:
-// none), each problem's tiles in runs by XCD as above.
+// none), each problem's tiles in runs by XCD as above; kBatchMT x kBatchMT
+// tiles.
+constexpr int kBatchMT = 32;
 template <typename T>
 __global__ void k_moments_q_b(const TArgs *tas, const int2 *bt) {
   const int2 v = bt[blockIdx.x];
   if (v.y < 0) return;
   const TArgs &a = tas[v.x];
-  if (blockIdx.y == 0 && v.y < (a.N + 255) / 256) src2_block(a, v.y);
-  moments_tile<T>(a, a.mom_part, nullptr, v.y, blockIdx.y);
+  if (blockIdx.y == 0) src2_tile<kBatchMT>(a, v.y);
+  moments_tile<T, kBatchMT>(a, a.mom_part, nullptr, v.y, blockIdx.y);
 }
 
 __device__ __forceinline__ void moments_combine(const TArgs &a, const double *part, const int c) {
@@ -1707,7 +1757,7 @@ __device__ __forceinline__ void boundary_flux(const TArgs &a, const int f) {
 // the swept intensity; the four partials are combined by the HoT kernel.
 // With ftp (transport-face HoT) the moment blocks also form the quadrant's
 // interior face fluxes.
-template <typename T>
+template <typename T, int MT>
 __global__ void k_moments_q_bflux(TArgs a, double *part, int nbf8, int ntile, int ts,
                                   double *ftp) {
   const int b = (int)blockIdx.x - nbf8;   // nbf8: a.nbf rounded up to a multiple of 8
@@ -1718,8 +1768,8 @@ __global__ void k_moments_q_bflux(TArgs a, double *part, int nbf8, int ntile, in
   const int q = b / (8 * ts), r = b - q * 8 * ts;
   const int tile = xcd_tile(r, ts);
   if (tile >= ntile || (r >> 3) >= ts) return;
-  if (q == 0 && tile < (a.N + 255) / 256) src2_block(a, tile);
-  moments_tile<T>(a, part, ftp, tile, q);
+  if (q == 0) src2_tile<MT>(a, tile);
+  moments_tile<T, MT>(a, part, ftp, tile, q);
 }
 
 __global__ void k_boundary_flux_b(const TArgs *tas, const int2 *bt) {
@@ -1870,7 +1920,11 @@ int residual_pairs(const PlanDev &P) {
   return pairs;
 }
 
-int moment_tiles_of(int nx, int ny) { return ((nx + kMT - 1) / kMT) * ((ny + kMT - 1) / kMT); }
+int moment_tile_size(int nx, int ny) { return (long long)nx * ny >= (1 << 18) ? 32 : 16; }
+int moment_tile_size_batch() { return kBatchMT; }
+int moment_tiles_of(int nx, int ny, int mt) {
+  return ((nx + mt - 1) / mt) * ((ny + mt - 1) / mt);
+}
 
 std::vector<int2> residual_tiles(int nx, int ny) {
   std::vector<int2> t;
@@ -1982,31 +2036,32 @@ void launch_sweep_batch(const void *targs, const int2 *items, int n_items, int *
 #undef GSIS_BATCH_LAUNCH
 }
 
-void launch_moments(const PlanDev &P, hipStream_t s, bool bflux) {
-  TArgs a = make_args(P);
-  const int nbc = (P.N + 255) / 256;
-  const int ntile = moment_tiles_of(P.nx, P.ny);   // >= nbc
+template <typename T, int MT>
+void launch_moments_t(const TArgs &a, const PlanDev &P, hipStream_t s, bool bflux) {
+  const int ntile = moment_tiles_of(P.nx, P.ny, MT);
   const int ts = (ntile + 7) / 8;   // tiles per XCD
   if (bflux) {   // the combine follows in the HoT kernel
     const int nbf8 = (P.nbf + 7) / 8 * 8;
-    const dim3 g(nbf8 + 4 * 8 * ts);
-    double *ftp = P.hot_face ? P.ftp : nullptr;
-    if (a.fp32)
-      hipLaunchKernelGGL(k_moments_q_bflux<float>, g, dim3(256), 0, s, a, P.mom_part, nbf8, ntile,
-                         ts, ftp);
-    else
-      hipLaunchKernelGGL(k_moments_q_bflux<double>, g, dim3(256), 0, s, a, P.mom_part, nbf8,
-                         ntile, ts, ftp);
+    hipLaunchKernelGGL((k_moments_q_bflux<T, MT>), dim3(nbf8 + 4 * 8 * ts), dim3(256), 0, s, a,
+                       P.mom_part, nbf8, ntile, ts, P.hot_face ? P.ftp : nullptr);
     return;
   }
-  if (a.fp32)
-    hipLaunchKernelGGL(k_moments_q<float>, dim3(8 * ts, 4), dim3(256), 0, s, a, P.mom_part, ntile,
-                       ts);
-  else
-    hipLaunchKernelGGL(k_moments_q<double>, dim3(8 * ts, 4), dim3(256), 0, s, a, P.mom_part,
-                       ntile, ts);
-  hipLaunchKernelGGL(k_moments_combine, dim3(nbc), dim3(256), 0, s, a,
+  hipLaunchKernelGGL((k_moments_q<T, MT>), dim3(8 * ts, 4), dim3(256), 0, s, a, P.mom_part, ntile,
+                     ts);
+  hipLaunchKernelGGL(k_moments_combine, dim3((P.N + 255) / 256), dim3(256), 0, s, a,
                      (const double *)P.mom_part);
+}
+
+void launch_moments(const PlanDev &P, hipStream_t s, bool bflux) {
+  const TArgs a = make_args(P);
+  const bool big = moment_tile_size(P.nx, P.ny) == 32;
+  if (a.fp32) {
+    if (big) launch_moments_t<float, 32>(a, P, s, bflux);
+    else launch_moments_t<float, 16>(a, P, s, bflux);
+  } else {
+    if (big) launch_moments_t<double, 32>(a, P, s, bflux);
+    else launch_moments_t<double, 16>(a, P, s, bflux);
+  }
 }
 
 void launch_moments_batch(const void *targs, const int2 *bt_cell, int nb_cell,
