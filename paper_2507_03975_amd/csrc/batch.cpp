@@ -173,6 +173,7 @@ gsis_status build_tables(gsis_batch *b, const std::vector<int> &act) {
   SynthSet &S = b->S;
   std::vector<SynthDesc> D(n);
   int max_lc = 0, min_lc = 1 << 30;
+  bool any_sep = false;
   size_t lds = 0;
   for (int a = 0; a < n; ++a) {
     const PlanDev &P = b->subs[act[a]]->P;
@@ -180,6 +181,7 @@ gsis_status build_tables(gsis_batch *b, const std::vector<int> &act) {
     D[a].n_tres = P.n_rtiles * residual_pairs(P);   // the batch's residual kernel's partials
     max_lc = std::max(max_lc, D[a].lc);
     min_lc = std::min(min_lc, D[a].lc);
+    any_sep = any_sep || D[a].coef_sep != 0;
     lds = std::max(lds, P.S.coarse_lds);
   }
   {
@@ -193,6 +195,7 @@ gsis_status build_tables(gsis_batch *b, const std::vector<int> &act) {
   S.max_lc = max_lc;
   S.min_lc = n ? min_lc : 0;
   S.coarse_lds = lds;
+  S.any_coef_sep = any_sep;
   S.state0 = nullptr;
   auto nb = [](long long m) { return (int)((m + 255) / 256); };
   std::vector<int2> t;

@@ -333,6 +333,7 @@ gsis_status make_single_set(gsis_plan *pl) {
   S.n = 1;
   S.max_lc = D.lc;
   S.min_lc = D.lc;
+  S.any_coef_sep = D.coef_sep != 0;
   P.lc = D.lc;
   S.coarse_lds = coarse_lds_bytes(P);
   S.synth_max_iter = P.synth_max_iter;

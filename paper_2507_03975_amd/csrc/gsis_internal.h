@@ -124,6 +124,7 @@ struct SynthDesc {
   int nlev, lc;                 // levels; first level of the one-workgroup cycle
   int ntile0;                   // multigrid tiles of level 0
   int ntp;                      // slots of each tile-partial region: max(ntile0, cell blocks)
+  int coef_sep;                 // 1: the CG coefficients come from k_cg_coef (many partials)
   LevelDev lev[kMaxLevels];
   CoarseLevels cl;
   const double *coarse_inv;
@@ -144,6 +145,7 @@ struct SynthSet {
   std::vector<int2 *> bt_tile;        // [l]: level-l tiles of problems with lc > l
   std::vector<int> nb_tile;
   int32_t *state0 = nullptr;          // single problem: its state (host checks)
+  bool any_coef_sep = false;          // some problem's CG coefficients come from k_cg_coef
 };
 
 struct PlanDev {

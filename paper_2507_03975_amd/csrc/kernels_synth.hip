@@ -431,11 +431,18 @@ __device__ inline CGCoef cg_coef(bool first, double ga, double de, double ga_pre
 }
 __device__ inline double *cg_s(CDesc &D, int it) { return (it & 1) ? D.cg_s1 : D.cg_s0; }
 // the update's scalar operands, loaded before the caller waits for its flags
+// (coef_sep: the coefficients themselves, from k_cg_coef)
 struct UpdPre {
   double rz0, zw0, ga_prev, al_prev;
 };
 __device__ inline UpdPre upd_prefetch(CDesc &D, int it) {
   UpdPre q;
+  if (D.coef_sep) {
+    q.rz0 = it > 0 ? D.scal[S_BETA] : 0.0;
+    q.zw0 = D.scal[alpha_slot(it)];
+    q.ga_prev = q.al_prev = 0.0;
+    return q;
+  }
   q.rz0 = first_partial(red_rz(D), n_rz(D));
   q.zw0 = first_partial(red_zw(D), n_rz(D));
   q.ga_prev = it > 0 ? D.scal[rz_slot(it - 1)] : 1.0;
@@ -443,8 +450,11 @@ __device__ inline UpdPre upd_prefetch(CDesc &D, int it) {
   return q;
 }
 // every block forms the coefficients from the same partials in the same
-// order; block 0 stores gamma, delta, alpha and beta
+// order; block 0 stores gamma, delta, alpha and beta. With many partials
+// (coef_sep) one workgroup does this in k_cg_coef instead, in the same
+// order, and the blocks take the stored beta and alpha.
 __device__ inline CGCoef upd_coef(CDesc &D, const Blk &B, int it, const UpdPre &q, double *sh) {
+  if (D.coef_sep) return {q.rz0, q.zw0};
   const double ga = sum_partials(red_rz(D), n_rz(D), sh, q.rz0);
   const double de = sum_partials(red_zw(D), n_rz(D), sh, q.zw0);
   const CGCoef k = cg_coef(it == 0, ga, de, q.ga_prev, q.al_prev);
@@ -455,6 +465,33 @@ __device__ inline CGCoef upd_coef(CDesc &D, const Blk &B, int it, const UpdPre &
     D.scal[S_ZW] = de;
   }
   return k;
+}
+
+// CG coefficients of iteration it for the problems whose level-0 tiles are
+// many (coef_sep): one workgroup per problem sums the r.z and z.w partials
+// (the order of upd_coef) and stores gamma, delta, alpha and beta, so each
+// block of the update reads two scalars instead of every partial. Launched
+// after V-cycle it.
+constexpr int kCoefSepTiles = 2048;
+__global__ void __launch_bounds__(kRedBlock) k_cg_coef(const SynthDesc *ds, int it) {
+  __shared__ double sh[kRedBlock];
+  CDesc &D = cdesc(ds, blockIdx.x);
+  if (!D.coef_sep) return;
+  UpdPre q;
+  q.rz0 = first_partial(red_rz(D), n_rz(D));
+  q.zw0 = first_partial(red_zw(D), n_rz(D));
+  q.ga_prev = it > 0 ? D.scal[rz_slot(it - 1)] : 1.0;
+  q.al_prev = it > 0 ? D.scal[alpha_slot(it - 1)] : 1.0;
+  if (cg_off(D.state)) return;
+  const double ga = sum_partials(red_rz(D), n_rz(D), sh, q.rz0);
+  const double de = sum_partials(red_zw(D), n_rz(D), sh, q.zw0);
+  const CGCoef k = cg_coef(it == 0, ga, de, q.ga_prev, q.al_prev);
+  if (threadIdx.x == 0) {
+    D.scal[rz_slot(it)] = ga;
+    D.scal[alpha_slot(it)] = k.al;
+    D.scal[S_BETA] = k.be;
+    D.scal[S_ZW] = de;
+  }
 }
 
 // CG iteration it on every cell of a problem, with the partial of r.r.
@@ -1470,6 +1507,8 @@ void vcycle(const SynthSet &S, int v, hipStream_t s) {
                        kOmega);
   if (S.min_lc == 0)
     hipLaunchKernelGGL(k_cg_zw, dim3(S.nb_cell), dim3(kRedBlock), 0, s, ds, S.bt_cell, v);
+  if (S.any_coef_sep)
+    hipLaunchKernelGGL(k_cg_coef, dim3(S.n), dim3(kRedBlock), 0, s, ds, v);
 }
 
 }  // namespace
@@ -1546,6 +1585,7 @@ SynthDesc make_synth_desc(const PlanDev &P) {
   D.lc = lc;
   D.ntile0 = tiles_of(P.mg[0].nx, P.mg[0].ny);
   D.ntp = std::max(D.ntile0, nblk(P.N));
+  D.coef_sep = lc > 0 && D.ntile0 >= kCoefSepTiles ? 1 : 0;
   CoarseLevels &CL = D.cl;
   CL.nlev = D.nlev - lc;
   int off = 0;
