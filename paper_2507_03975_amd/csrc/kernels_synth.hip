@@ -1459,22 +1459,31 @@ __global__ void __launch_bounds__(kRedBlock) k_source(const SynthDesc *ds, const
 }
 
 // End of an outer iteration: blocks [0, n) finish Err of problem blockIdx.x,
-// the others make source tiles (table bt, or one problem's tiles in order).
-// The two do not depend on each other; the source is written also on the
-// iteration that ends the solve.
+// blocks from n8 (n rounded up to a multiple of 8) make source tiles (table
+// bt, or one problem's tiles). The two do not depend on each other; the
+// source is written also on the iteration that ends the solve. One problem:
+// its ntile tiles (row-major) fall into 8 runs of ts, one per XCD (block
+// n8 + b runs on XCD b % 8 and takes tile (b % 8) ts + b / 8), so the
+// partly written cache lines at the ends of a tile's diagonal runs mostly
+// meet the neighbouring tile's part in the same L2.
 __global__ void __launch_bounds__(kRedBlock) k_err_source(const SynthDesc *ds, const int2 *bt,
-                                                          int n) {
+                                                          int n, int n8, int ntile, int ts) {
   __shared__ double s_sc[kRedBlock], s_dq[kRedBlock], s_pq[kRedBlock];
   if ((int)blockIdx.x < n) {
     err_finish(cdesc(ds, blockIdx.x), s_sc);
     return;
   }
-  const int idx = blockIdx.x - n;
-  Blk B = {0, idx};
+  const int idx = blockIdx.x - n8;
+  if (idx < 0) return;
+  Blk B;
   if (bt) {
     const __attribute__((address_space(4))) int *q =
         (const __attribute__((address_space(4))) int *)bt;
     B = {q[2 * idx], q[2 * idx + 1]};
+  } else {
+    const int tile = (idx & 7) * ts + (idx >> 3);
+    if (tile >= ntile || (idx >> 3) >= ts) return;
+    B = {0, tile};
   }
   source_tile(cdesc(ds, B.p), B, s_sc, s_dq, s_pq);
 }
@@ -1686,8 +1695,10 @@ void launch_material(const SynthSet &S, hipStream_t s, int sub) {
 
 void launch_update(const SynthSet &S, hipStream_t s) {
   hipLaunchKernelGGL(k_update, dim3(S.nb_cell), dim3(kRedBlock), 0, s, S.desc, S.bt_cell);
-  hipLaunchKernelGGL(k_err_source, dim3(S.n + S.nb_src), dim3(kRedBlock), 0, s, S.desc, S.bt_src,
-                     S.n);
+  const int n8 = (S.n + 7) / 8 * 8, ts = (S.nb_src + 7) / 8;
+  const int nb = S.bt_src ? S.nb_src : 8 * ts;
+  hipLaunchKernelGGL(k_err_source, dim3(n8 + nb), dim3(kRedBlock), 0, s, S.desc, S.bt_src, S.n,
+                     n8, S.nb_src, ts);
 }
 
 void launch_apply_delta_final(const PlanDev &P, hipStream_t s, double swmu, double sweta,
