@@ -258,7 +258,18 @@ __device__ inline double first_partial(const double *p, int n) {
 __device__ inline double sum_partials(const double *p, int n, double *sh, double first) {
   double v = 0.0;
   v += first;
-  for (int t = threadIdx.x + blockDim.x; t < n; t += blockDim.x) v += p[t];
+  // sixteen loads in flight at a time, added in order (terms past n add 0)
+  constexpr int U = 16;
+  for (int t0 = threadIdx.x + blockDim.x; t0 < n; t0 += U * (int)blockDim.x) {
+    double w[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int t = t0 + u * (int)blockDim.x;
+      w[u] = t < n ? p[t] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) v += w[u];
+  }
   return block_sum(v, sh);
 }
 
@@ -1346,23 +1357,38 @@ __global__ void k_material(const SynthDesc *ds, const int2 *bt, int sub) {
 // 1e3 times its smallest value so far (floored at 1e-9 ||phi^{m+1}||_V, far
 // above rounding); Err alone cannot show a geometric blow-up, it tends to
 // |1 - 1/g| for a growth factor g. last_err[1] keeps that smallest change.
+// p[e t], p[e (t + blockDim)], ... (t = threadIdx.x; n terms in all) added
+// in that order; sixteen loads in flight at a time (terms past n add 0, and
+// every sum here is of squares)
+__device__ inline double strided_sum(const double *p, int n, int e) {
+  constexpr int U = 16;
+  double s = 0.0;
+  for (int t0 = threadIdx.x; t0 < n; t0 += U * (int)blockDim.x) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int t = t0 + u * (int)blockDim.x;
+      v[u] = t < n ? p[(size_t)e * t] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) s += v[u];
+  }
+  return s;
+}
+
 __device__ inline void err_finish(CDesc &D, double *sh) {
   int32_t *state = D.state;
   if (state[1] != 0) return;
   const int npart = nblk_d(D.N);
-  double a = 0.0, b = 0.0, rr = 0.0, ss = 0.0;
-  for (int t = threadIdx.x; t < npart; t += blockDim.x) {
-    a += D.err_parts[2 * t];
-    b += D.err_parts[2 * t + 1];
-  }
-  for (int t = threadIdx.x; t < D.n_tres; t += blockDim.x) rr += D.tres_part[t];
-  for (int t = threadIdx.x; t < D.n_src2; t += blockDim.x) ss += D.src2_part[t];
+  // (the residual-norm partials number one per residual wave: tens of
+  // thousands on large grids)
+  double a = strided_sum(D.err_parts, npart, 2), b = strided_sum(D.err_parts + 1, npart, 2);
+  double rr = strided_sum(D.tres_part, D.n_tres, 1), ss = strided_sum(D.src2_part, D.n_src2, 1);
   double aT = 0.0, bT = 0.0;
-  if (D.td)
-    for (int t = threadIdx.x; t < npart; t += blockDim.x) {
-      aT += D.err_parts_T[2 * t];
-      bT += D.err_parts_T[2 * t + 1];
-    }
+  if (D.td) {
+    aT = strided_sum(D.err_parts_T, npart, 2);
+    bT = strided_sum(D.err_parts_T + 1, npart, 2);
+  }
   const double dmin = D.last_err[1];
   double num = block_sum(a, sh);
   double den = block_sum(b, sh);
