@@ -63,14 +63,14 @@ SYNTH_RTOL = 0.1
 # so FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0). Valid only for the kernel source
 # whose sha256 is recorded; any change to it turns the figures back to null.
 TRAFFIC = {
-    "thick256_fp64": {"sha256": "4547a8b912d36cacdbb462a889f8b2ca9c02333c3cc14bc02fb446e3f96b781b",
-                      "k_resid": 244183100,     # 84064.8 KiB x 2.0 + 70330.5 KiB
-                      "k_chain": 138760036},    # 34863.5 KiB x 2.0 + 65780.8 KiB
-    "block1024_fp64": {"sha256": "4547a8b912d36cacdbb462a889f8b2ca9c02333c3cc14bc02fb446e3f96b781b",
-                       "k_pipe": 3153750072},   # 968598.7 KiB x 2.0 + 1142636.7 KiB
-    "block1024_fp32": {"sha256": "4547a8b912d36cacdbb462a889f8b2ca9c02333c3cc14bc02fb446e3f96b781b",
-                       "k_resid": 2972098360,   # 1158625.8 KiB x 2.0 + 585188.2 KiB
-                       "k_chain": 1281365228},  # 346850.4 KiB x 2.0 + 557632.3 KiB
+    "thick256_fp64": {"sha256": "77e682fda62ebc2174f0f252ca9724940a9cbe9356dfc638100bc9595f2f60b2",
+                      "k_resid": 243727008,     # 83825.4 KiB x 2.0 + 70363.8 KiB
+                      "k_chain": 138753744},    # 34861.0 KiB x 2.0 + 65779.7 KiB
+    "block1024_fp64": {"sha256": "77e682fda62ebc2174f0f252ca9724940a9cbe9356dfc638100bc9595f2f60b2",
+                       "k_pipe": 3184758404},   # 982599.1 KiB x 2.0 + 1144917.5 KiB
+    "block1024_fp32": {"sha256": "77e682fda62ebc2174f0f252ca9724940a9cbe9356dfc638100bc9595f2f60b2",
+                       "k_resid": 2973722348,   # 1159418.5 KiB x 2.0 + 585188.7 KiB
+                       "k_chain": 1281201460},  # 346798.5 KiB x 2.0 + 557576.3 KiB
 }
 KERNELS = {"k_resid": "k_resid (second-order residual of every cell-ordinate, ALSM gradient "
                       "and BJ limiter, written as the recurrence's right-hand side)",
