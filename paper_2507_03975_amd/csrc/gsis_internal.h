@@ -284,9 +284,9 @@ void fill_targs(const PlanDev &P, void *dst);
 int sweep_batch_blocks_per_cu(int cfg, bool fp32);
 void launch_sweep_batch(const void *targs, const int2 *items, int n_items, int *counter, int cfg,
                         bool fp32, int grid, hipStream_t s);
-// moments of a batch: partials over (problem, 16 x 16 tile or -1) blocks,
-// then the combine over (problem, 256-cell block) blocks; boundary fluxes
-// over (problem, boundary face)
+// moments of a batch: partials over (problem, moment tile or -1) blocks
+// (moment_tile_size_batch), then the combine over (problem, 256-cell block)
+// blocks; boundary fluxes over (problem, boundary face)
 void launch_moments_batch(const void *targs, const int2 *bt_cell, int nb_cell,
                           const int2 *bt_tile, int nb_tile, bool fp32, hipStream_t s);
 void launch_boundary_flux_batch(const void *targs, const int2 *bt_face, int nb_face,

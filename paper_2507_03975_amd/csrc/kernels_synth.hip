@@ -1348,15 +1348,6 @@ __global__ void k_material(const SynthDesc *ds, const int2 *bt, int sub) {
   To[c] = T + R2 / D2;
 }
 
-// One workgroup per problem: Err = sqrt(num/den) -> history, counters, done
-// flag; the relative transport residual of the iterate this iteration
-// started from, sqrt(sum w r^2 / (sum_k w_k sum_c src^2)) (the cell volume
-// cancels on a uniform grid), from the residual kernel's per-wave partials
-// and the moments kernel's per-block partials of the same iteration.
-// Divergence: Err not finite, or the change ||phi^{m+1} - phi^m||_V above
-// 1e3 times its smallest value so far (floored at 1e-9 ||phi^{m+1}||_V, far
-// above rounding); Err alone cannot show a geometric blow-up, it tends to
-// |1 - 1/g| for a growth factor g. last_err[1] keeps that smallest change.
 // p[e t], p[e (t + blockDim)], ... (t = threadIdx.x; n terms in all) added
 // in that order; sixteen loads in flight at a time (terms past n add 0, and
 // every sum here is of squares)
@@ -1376,6 +1367,15 @@ __device__ inline double strided_sum(const double *p, int n, int e) {
   return s;
 }
 
+// One workgroup per problem: Err = sqrt(num/den) -> history, counters, done
+// flag; the relative transport residual of the iterate this iteration
+// started from, sqrt(sum w r^2 / (sum_k w_k sum_c src^2)) (the cell volume
+// cancels on a uniform grid), from the residual kernel's per-wave partials
+// and the moments kernel's per-block partials of the same iteration.
+// Divergence: Err not finite, or the change ||phi^{m+1} - phi^m||_V above
+// 1e3 times its smallest value so far (floored at 1e-9 ||phi^{m+1}||_V, far
+// above rounding); Err alone cannot show a geometric blow-up, it tends to
+// |1 - 1/g| for a growth factor g. last_err[1] keeps that smallest change.
 __device__ inline void err_finish(CDesc &D, double *sh) {
   int32_t *state = D.state;
   if (state[1] != 0) return;
