@@ -554,8 +554,6 @@ static gsis_status plan_create(gsis_ctx *ctx, const gsis_problem *p, const gsis_
         r[5] = st_[c] + P.tdiag + shift[c];
         sdq[(size_t)qd * N + dg_idx(xl, yl, nx, ny)] = r[5];
       }
-  const std::vector<int2> rtiles = residual_tiles(nx, ny);
-  P.n_rtiles = (int)rtiles.size();
   {
     // transport step: 0 residual kernel + recurrence, 3 pipelined (one
     // launch); 1 two-kernel reference and 2 fused wavefront sweep (tests
@@ -608,6 +606,14 @@ static gsis_status plan_create(gsis_ctx *ctx, const gsis_problem *p, const gsis_
     P.chain_parts = parts;
     P.chain_rows = parts > 1 ? rows : 0;
   }
+  // residual tiles (GSIS_RESID_DIAGONALS=31 or 47 sets their length)
+  P.resid_rd = residual_tile_diagonals((long long)N * K);
+  {
+    const char *e = getenv("GSIS_RESID_DIAGONALS");
+    if (e && (!strcmp(e, "31") || !strcmp(e, "47"))) P.resid_rd = atoi(e);
+  }
+  const std::vector<int2> rtiles = residual_tiles(nx, ny, P.resid_rd);
+  P.n_rtiles = (int)rtiles.size();
   // partial sums of w r^2: one per residual wave
   P.n_tres = P.sweep_impl == 3 ? K * P.pipe_parts * P.pipe_bands
                                : P.n_rtiles * residual_pairs(P);

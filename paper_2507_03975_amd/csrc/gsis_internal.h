@@ -186,6 +186,7 @@ struct PlanDev {
   int *dso = nullptr;          // [kDiagPad + nx + ny - 1 + kDiagPad] storage index of
                                // row 0 on each anti-diagonal (dg_off - ylo), padded
   int n_rtiles = 0;
+  int resid_rd = 31;           // diagonals per residual tile
   int sweep_impl = 0;          // 0 residual kernel + wavefront recurrence,
                                // 1 two-kernel reference, 2 fused wavefront sweep,
                                // 3 pipelined residual + recurrence
@@ -253,7 +254,10 @@ void launch_sweep(const PlanDev &P, hipStream_t s);
 void launch_hand_reset(const PlanDev &P, hipStream_t s);
 // Tiles of the residual kernel for an nx x ny grid: (first diagonal, first
 // row) of each band of rows x run of diagonals that holds a cell.
-std::vector<int2> residual_tiles(int nx, int ny);
+// Residual-kernel tiles of rd diagonals (residual_tile_diagonals: 31, or 47
+// from 2^26 cell-ordinates on)
+int residual_tile_diagonals(long long cell_ordinates);
+std::vector<int2> residual_tiles(int nx, int ny, int rd);
 // Ordinate pairs of one quadrant the residual kernel takes per wave (the
 // residual-norm partials are indexed tile * pairs + pair).
 int residual_pairs(const PlanDev &P);
