@@ -329,6 +329,19 @@ __global__ void k_finish_rr(const SynthDesc *ds) {
   (void)finish_rr(D, false, false, sh, q);
 }
 
+// The r.r test of CG iteration v - 1 (v > 0) on its level-0 tile partials,
+// for a problem whose V-cycle starts with a tile level: the test the level-1
+// kernel of V-cycle v would make, run on its own when the host is about to
+// look at the flags (that V-cycle's later kernels, which the test would
+// usually turn into no-ops, are then launched only if it fails).
+__global__ void k_rr_test(const SynthDesc *ds) {
+  __shared__ double sh[kRedBlock];
+  CDesc &D = cdesc(ds, blockIdx.x);
+  const RRPre q = rr_prefetch(D, false, true);
+  if (cg_off(D.state)) return;
+  (void)finish_rr(D, false, true, sh, q);
+}
+
 // Start of a synthetic solve: warm start x = phi, clear the converged flag;
 // r = b - A x; partials of r.r and b.b.
 // RHS: the right-hand side b is formed here from the HoT (and stored)
@@ -682,7 +695,7 @@ __device__ inline void cg_update_tile(CDesc &D, const Blk &B, const Tile &T, int
 }
 
 __global__ void __launch_bounds__(kRedBlock) k_mg_down(const SynthDesc *ds, const int2 *bt, int l,
-                                                       int v) {
+                                                       int v, int rr_ext) {
   __shared__ double sb[kRN], sd[kRN], sax[kRN], say[kRN], sx[kRN], ss[kRN], sh[kRedBlock];
   const Blk B = blk(bt);
   CDesc &D = cdesc(ds, B.p);
@@ -714,7 +727,7 @@ __global__ void __launch_bounds__(kRedBlock) k_mg_down(const SynthDesc *ds, cons
   // the r.r test of the CG step before this V-cycle is made by the next
   // kernel of the cycle (level 1 here, block 0; the other blocks go on: if
   // it converged, their results are not used)
-  const bool fin = l == 1 && B.lb == 0;
+  const bool fin = l == 1 && B.lb == 0 && !rr_ext;   // rr_ext: k_rr_test made it
   RRPre qr = {0.0, 0.0, 0.0};
   if (fin) qr = rr_prefetch(D, v == 0, v > 0);
   if (f1 != 0 || f3 != 0) return;
@@ -980,14 +993,14 @@ struct OwnCell {
 };
 
 __global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(const SynthDesc *ds, double omega,
-                                                              int vc) {
+                                                              int vc, int rr_ext) {
   extern __shared__ double sm[];
   __shared__ double red[kCoarseThreads];
   CDesc &D = cdesc(ds, blockIdx.x);
   // a problem whose V-cycle starts here or on level 1 makes the r.r test of
   // the CG step before it here (level 1: the level-0 tile kernel made the
   // update)
-  const bool fin = D.lc <= 1;
+  const bool fin = D.lc == 0 || (D.lc == 1 && !rr_ext);   // rr_ext: k_rr_test made it
   RRPre q = {0.0, 0.0, 0.0};
   if (fin) q = rr_prefetch(D, vc == 0, vc > 0 && D.lc == 1);
   if (cg_off(D.state)) return;
@@ -1526,14 +1539,18 @@ __global__ void k_final_flux(int n, const double *Fx, const double *Fy, const do
 
 // z = M^{-1} r_v (one V(1,1) cycle with scaled coarse corrections) for
 // every problem of the set, with the partials of r.z. V-cycle v > 0 follows
-// CG iteration v - 1, whose update its level-0 tile kernel makes.
-void vcycle(const SynthSet &S, int v, hipStream_t s) {
+// CG iteration v - 1, whose update its level-0 tile kernel makes. part 1
+// launches only that level-0 kernel, part 2 the rest, after k_rr_test has
+// made the r.r test (problems that start with a tile level); part 0 all.
+void vcycle(const SynthSet &S, int v, hipStream_t s, int part = 0) {
   const SynthDesc *ds = S.desc;
-  for (int l = 0; l < S.max_lc; ++l)
+  const int rr_ext = part == 2 ? 1 : 0;
+  for (int l = part == 2 ? 1 : 0; l < (part == 1 ? 1 : S.max_lc); ++l)
     hipLaunchKernelGGL(k_mg_down, dim3(S.nb_tile[l]), dim3(kRedBlock), 0, s, ds, S.bt_tile[l], l,
-                       v);
+                       v, rr_ext);
+  if (part == 1) return;
   hipLaunchKernelGGL(k_mg_coarse, dim3(S.n), dim3(kCoarseThreads), S.coarse_lds, s, ds, kOmega,
-                     v);
+                     v, rr_ext);
   for (int l = S.max_lc - 1; l >= 1; --l)
     hipLaunchKernelGGL(k_mg_up, dim3(S.nb_tile[l]), dim3(kRedBlock), 0, s, ds, S.bt_tile[l], l, v,
                        kOmega);
@@ -1700,9 +1717,18 @@ void launch_synth_solve(const SynthSet &S, hipStream_t s, int32_t *host_flag, in
     // problems whose V-cycle runs wholly in the one-workgroup kernel have
     // no level-0 tile kernel to make the update
     if (S.min_lc == 0) hipLaunchKernelGGL(k_cg_update, gc, bk, 0, s, ds, S.bt_cell, it, 0);
-    vcycle(S, it + 1, s);   // makes the update (level 0) and the r.r test
     const bool due = guess > 0 ? it + 1 >= guess : (it >= 3 && ((it - 3) & 1) == 0);
-    if (host_flag && S.state0 && due) {
+    const bool check = host_flag && S.state0 && due;
+    // at a check of a problem that starts with a tile level, the update and
+    // the r.r test go first and the rest of the V-cycle only if it fails
+    const bool split = check && S.n == 1 && S.min_lc >= 1;
+    if (split) {
+      vcycle(S, it + 1, s, 1);   // the update (level 0)
+      hipLaunchKernelGGL(k_rr_test, dim3(S.n), bk, 0, s, ds);
+    } else {
+      vcycle(S, it + 1, s);   // makes the update (level 0) and the r.r test
+    }
+    if (check) {
       (void)hipMemcpyAsync(host_flag, S.state0 + 1, 3 * sizeof(int32_t), hipMemcpyDeviceToHost,
                            s);
       (void)hipStreamSynchronize(s);
@@ -1711,6 +1737,7 @@ void launch_synth_solve(const SynthSet &S, hipStream_t s, int32_t *host_flag, in
         host_flag[8] = max(1, host_flag[2] - 1);
         return;
       }
+      if (split) vcycle(S, it + 1, s, 2);
     }
   }
 }
