@@ -331,13 +331,16 @@ void launch_wide_grad(const SynthSet &S, hipStream_t s, bool first);
 // sub: the time-dependent form's sub-iteration (its right-hand side takes
 // the emission of T(sub)); rhs_mode 3: as 1 with the level-0 iterate (the
 // previous sub-iterate) as warm start.
-void launch_synth_solve(const SynthSet &S, hipStream_t s, int32_t *host_flag, int rhs_mode,
-                        int sub = 0);
+// spec: see the definition (true: the end of the outer iteration is
+// already in the stream)
+bool launch_synth_solve(const SynthSet &S, hipStream_t s, int32_t *host_flag, int rhs_mode,
+                        int sub = 0, hipEvent_t spec = nullptr);
 // Time-dependent form: T(sub + 1) = T(sub) + R2 / D2 (Eqs. MSE_d2, R2_def,
 // MSE_d_mtx2, elem_mtx_M) with rho(sub) (rho^{m+1/2} at sub 0 or for source
 // iteration, else the last synthetic solution)
 void launch_material(const SynthSet &S, hipStream_t s, int sub);
-void launch_update(const SynthSet &S, hipStream_t s);
+// cond: only for problems whose synthetic solve has converged (state[3])
+void launch_update(const SynthSet &S, hipStream_t s, int cond = 0);
 // Time-dependent form, start of a time step: I^n = the current iterate (with
 // its pending correction), rho^n, T^n; the step's counters and flags cleared
 void launch_td_begin(const PlanDev &P, hipStream_t s);

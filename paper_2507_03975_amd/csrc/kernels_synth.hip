@@ -1300,11 +1300,13 @@ constexpr double kOmega = 1.7;   // coarse-grid correction scaling (aggregation 
 // ------------------------------------------------------------- update / Err
 // delta = phi' - phi_half (GSIS) or 0 (SI); Err partials; phi = phi_new.
 // FP32-mixed mode also records base = phi^m + delta (see the transport file).
-__global__ void k_update(const SynthDesc *ds, const int2 *bt) {
+// cond: launched ahead of the host's look at the synthetic solve's flags;
+// runs only if that solve has converged (state[3]), else returns
+__global__ void k_update(const SynthDesc *ds, const int2 *bt, int cond) {
   __shared__ double sh[kRedBlock];
   const Blk B = blk(bt);
   CDesc &D = cdesc(ds, B.p);
-  const int32_t f1 = D.state[1];   // tested after the operands are loaded
+  const int32_t f1 = D.state[1] | (cond && D.state[3] == 0);   // tested after the operand loads
   const int c = B.lb * kRedBlock + threadIdx.x;
   const bool in = c < D.N;
   const int cc = in ? c : 0;
@@ -1506,10 +1508,13 @@ __global__ void __launch_bounds__(kRedBlock) k_source(const SynthDesc *ds, const
 // partly written cache lines at the ends of a tile's diagonal runs mostly
 // meet the neighbouring tile's part in the same L2.
 __global__ void __launch_bounds__(kRedBlock) k_err_source(const SynthDesc *ds, const int2 *bt,
-                                                          int n, int n8, int ntile, int ts) {
+                                                          int n, int n8, int ntile, int ts,
+                                                          int cond) {
   __shared__ double s_sc[kRedBlock], s_dq[kRedBlock], s_pq[kRedBlock];
   if ((int)blockIdx.x < n) {
-    err_finish(cdesc(ds, blockIdx.x), s_sc);
+    CDesc &D = cdesc(ds, blockIdx.x);
+    if (cond && D.state[3] == 0) return;   // as k_update
+    err_finish(D, s_sc);
     return;
   }
   const int idx = blockIdx.x - n8;
@@ -1524,7 +1529,9 @@ __global__ void __launch_bounds__(kRedBlock) k_err_source(const SynthDesc *ds, c
     if (tile >= ntile || (idx >> 3) >= ts) return;
     B = {0, tile};
   }
-  source_tile(cdesc(ds, B.p), B, s_sc, s_dq, s_pq);
+  CDesc &D = cdesc(ds, B.p);
+  if (cond && D.state[3] == 0) return;
+  source_tile(D, B, s_sc, s_dq, s_pq);
 }
 
 // Final F with the pending correction: F = F_half + delta/(4 pi) sum_k w Omega_k
@@ -1696,9 +1703,13 @@ void launch_hot(const SynthSet &S, hipStream_t s, bool combine) {
 // count) and after every later one, so a run whose counts stay level waits
 // once per solve and launches no V-cycle past convergence. Without it
 // (batches, graph capture) exactly synth_max_iter iterations are launched
-// and converged problems skip their kernels.
-void launch_synth_solve(const SynthSet &S, hipStream_t s, int32_t *host_flag, int rhs_mode,
-                        int sub) {
+// and converged problems skip their kernels. spec (an event; single plans,
+// plain GSIS): at each check the end of the outer iteration (launch_update,
+// made conditional on convergence) is put into the stream before the host
+// waits; true is returned when the solve has converged at a check, the
+// update then being in the stream.
+bool launch_synth_solve(const SynthSet &S, hipStream_t s, int32_t *host_flag, int rhs_mode,
+                        int sub, hipEvent_t spec) {
   const SynthDesc *ds = S.desc;
   const dim3 gc(S.nb_cell), bk(kRedBlock);
   if (rhs_mode == 1) hipLaunchKernelGGL(k_cg_begin<1>, gc, bk, 0, s, ds, S.bt_cell, sub);
@@ -1731,27 +1742,37 @@ void launch_synth_solve(const SynthSet &S, hipStream_t s, int32_t *host_flag, in
     if (check) {
       (void)hipMemcpyAsync(host_flag, S.state0 + 1, 3 * sizeof(int32_t), hipMemcpyDeviceToHost,
                            s);
-      (void)hipStreamSynchronize(s);
-      if (host_flag[0] != 0) return;
+      if (spec) {
+        // the end of the outer iteration goes into the stream before the
+        // host waits (on the flags' copy alone); it runs only if the solve
+        // has converged, so the GPU need not idle while the host wakes
+        (void)hipEventRecord(spec, s);
+        launch_update(S, s, 1);
+        (void)hipEventSynchronize(spec);
+      } else {
+        (void)hipStreamSynchronize(s);
+      }
+      if (host_flag[0] != 0) return false;
       if (host_flag[2] != 0) {
         host_flag[8] = max(1, host_flag[2] - 1);
-        return;
+        return spec != nullptr;
       }
       if (split) vcycle(S, it + 1, s, 2);
     }
   }
+  return false;
 }
 
 void launch_material(const SynthSet &S, hipStream_t s, int sub) {
   hipLaunchKernelGGL(k_material, dim3(S.nb_cell), dim3(kRedBlock), 0, s, S.desc, S.bt_cell, sub);
 }
 
-void launch_update(const SynthSet &S, hipStream_t s) {
-  hipLaunchKernelGGL(k_update, dim3(S.nb_cell), dim3(kRedBlock), 0, s, S.desc, S.bt_cell);
+void launch_update(const SynthSet &S, hipStream_t s, int cond) {
+  hipLaunchKernelGGL(k_update, dim3(S.nb_cell), dim3(kRedBlock), 0, s, S.desc, S.bt_cell, cond);
   const int n8 = (S.n + 7) / 8 * 8, ts = (S.nb_src + 7) / 8;
   const int nb = S.bt_src ? S.nb_src : 8 * ts;
   hipLaunchKernelGGL(k_err_source, dim3(n8 + nb), dim3(kRedBlock), 0, s, S.desc, S.bt_src, S.n,
-                     n8, S.nb_src, ts);
+                     n8, S.nb_src, ts, cond);
 }
 
 void launch_apply_delta_final(const PlanDev &P, hipStream_t s, double swmu, double sweta,

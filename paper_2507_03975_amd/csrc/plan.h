@@ -33,6 +33,8 @@ struct gsis_plan {
   std::vector<double> T0_host;    // time-dependent form: initial temperature
   std::vector<void *> allocs;
   double *host_scal = nullptr;    // pinned
+  hipEvent_t spec_ev = nullptr;   // marks the synthetic solve's flag copy (see
+                                  // launch_synth_solve); not in the allocation-free solve
   // profiling: per iteration GSIS_NUM_PHASES + 1 events bracketing the phases
   std::vector<hipEvent_t> events;
   int prof_iters = 0;
