@@ -63,14 +63,14 @@ SYNTH_RTOL = 0.1
 # so FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0). Valid only for the kernel source
 # whose sha256 is recorded; any change to it turns the figures back to null.
 TRAFFIC = {
-    "thick256_fp64": {"sha256": "77e682fda62ebc2174f0f252ca9724940a9cbe9356dfc638100bc9595f2f60b2",
-                      "k_resid": 243727008,     # 83825.4 KiB x 2.0 + 70363.8 KiB
-                      "k_chain": 138753744},    # 34861.0 KiB x 2.0 + 65779.7 KiB
-    "block1024_fp64": {"sha256": "77e682fda62ebc2174f0f252ca9724940a9cbe9356dfc638100bc9595f2f60b2",
-                       "k_pipe": 3184758404},   # 982599.1 KiB x 2.0 + 1144917.5 KiB
-    "block1024_fp32": {"sha256": "77e682fda62ebc2174f0f252ca9724940a9cbe9356dfc638100bc9595f2f60b2",
-                       "k_resid": 2973722348,   # 1159418.5 KiB x 2.0 + 585188.7 KiB
-                       "k_chain": 1281201460},  # 346798.5 KiB x 2.0 + 557576.3 KiB
+    "thick256_fp64": {"sha256": "d5168b39377afbc1a54b93b6d4b31ecf9b6fa7bbcad6be3fc928b2fd1c1703c7",
+                      "k_resid": 243825248,     # 83885.9 KiB x 2.0 + 70338.8 KiB
+                      "k_chain": 138760084},    # 34863.5 KiB x 2.0 + 65780.9 KiB
+    "block1024_fp64": {"sha256": "d5168b39377afbc1a54b93b6d4b31ecf9b6fa7bbcad6be3fc928b2fd1c1703c7",
+                       "k_pipe": 3179445808},   # 980505.0 KiB x 2.0 + 1143917.5 KiB
+    "block1024_fp32": {"sha256": "d5168b39377afbc1a54b93b6d4b31ecf9b6fa7bbcad6be3fc928b2fd1c1703c7",
+                       "k_resid": 2965315440,   # 1153648.2 KiB x 2.0 + 588519.4 KiB
+                       "k_chain": 1281044288},  # 346705.4 KiB x 2.0 + 557609.0 KiB
 }
 KERNELS = {"k_resid": "k_resid (second-order residual of every cell-ordinate, ALSM gradient "
                       "and BJ limiter, written as the recurrence's right-hand side)",
