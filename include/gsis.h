@@ -223,9 +223,11 @@ void gsis_plan_destroy(gsis_plan *plan);
  * convergence (Err < tol), divergence or max_iter do no work, so the
  * iterate stops exactly where a synchronous loop would. SI plans return
  * without waiting. GSIS plans wait for the device once per outer iteration:
- * the host reads the synthetic CG's device stop flag (after the V-cycle at
- * which the previous solve converged) so that it launches no V-cycle past
- * convergence, and stops enqueueing once an iteration has ended the solve. */
+ * the host reads the synthetic CG's device stop flag (after the CG update
+ * of the iteration at which the previous solve stopped, the end of the
+ * outer iteration already in the stream behind it) so that it launches no
+ * V-cycle past convergence, and stops enqueueing once an iteration has
+ * ended the solve. */
 gsis_status gsis_plan_iterate(gsis_plan *plan, int32_t n);
 /* Wait for the plan's stream, then report progress: iterations done and
  * whether Err < tol was reached (converged = 1) or the iteration diverged
