@@ -1713,44 +1713,52 @@ __global__ void k_moments_combine_b(const TArgs *tas, const int2 *bt) {
   moments_combine(a, a.mom_part, v.y * blockDim.x + threadIdx.x);
 }
 
-// F_T . n_out on each boundary face: one workgroup per face, threads over
-// ordinates, fixed-order tree sum.
-__device__ __forceinline__ void boundary_flux(const TArgs &a, const int f) {
-  const int f1 = a.state[1];   // tested before the store
-  int side, pos;
+// Wall face f: its side (0 W, 1 E, 2 S, 3 N) and position along it, and
+// ordinate kk's term w (Omega . n_out) I of F_T . n_out there.
+__device__ inline void face_side(const TArgs &a, const int f, int &side, int &pos) {
   if (f < a.ny) { side = 0; pos = f; }                       // W
   else if (f < 2 * a.ny) { side = 1; pos = f - a.ny; }        // E
   else if (f < 2 * a.ny + a.nx) { side = 2; pos = f - 2 * a.ny; }   // S
   else { side = 3; pos = f - 2 * a.ny - a.nx; }               // N
-  double acc = 0.0;
-  for (int kk = threadIdx.x; kk < a.K; kk += blockDim.x) {
-    const int q = quadrant_of(a, kk);
-    // w * (Omega . n_out)
-    const double won = side == 0 ? -a.wmu[kk] : side == 1 ? a.wmu[kk]
-                     : side == 2 ? -a.weta[kk] : a.weta[kk];
-    double val = 0.0;
-    if (won < 0.0) {
-      val = a.bnd[(size_t)f * a.K + kk];
-    } else if (won > 0.0) {
-      // outgoing: this face is the local east (x sides) or north (y sides)
-      // face of the boundary cell in the ordinate's mirrored frame
-      int i = side == 0 ? 0 : side == 1 ? a.nx - 1 : pos;
-      int j = side == 2 ? 0 : side == 3 ? a.ny - 1 : pos;
-      int xl = (q & 1) ? a.nx - 1 - i : i;
-      int yl = (q & 2) ? a.ny - 1 - j : j;
-      const long long base = (long long)kk * a.N;
-      const double *SUB = a.dynq + ((size_t)q * 3 + 2) * a.N;
-      auto ld = [&](int x, int y) {
-        const long long o = dg_idx(x, y, a.nx, a.ny);
-        if (a.fp32) return (double)Iout_of<float>(a)[base + o] + SUB[o];
-        return Iout_of<double>(a)[base + o];
-      };
-      double Fe, Fn;
-      out_faces(a, q, xl, yl, ld, Fe, Fn);
-      val = side < 2 ? Fe : Fn;
-    }
-    acc += won * val;
+}
+__device__ __forceinline__ double face_term(const TArgs &a, const int f, const int side,
+                                            const int pos, const int kk) {
+  const int q = quadrant_of(a, kk);
+  // w * (Omega . n_out)
+  const double won = side == 0 ? -a.wmu[kk] : side == 1 ? a.wmu[kk]
+                   : side == 2 ? -a.weta[kk] : a.weta[kk];
+  double val = 0.0;
+  if (won < 0.0) {
+    val = a.bnd[(size_t)f * a.K + kk];
+  } else if (won > 0.0) {
+    // outgoing: this face is the local east (x sides) or north (y sides)
+    // face of the boundary cell in the ordinate's mirrored frame
+    int i = side == 0 ? 0 : side == 1 ? a.nx - 1 : pos;
+    int j = side == 2 ? 0 : side == 3 ? a.ny - 1 : pos;
+    int xl = (q & 1) ? a.nx - 1 - i : i;
+    int yl = (q & 2) ? a.ny - 1 - j : j;
+    const long long base = (long long)kk * a.N;
+    const double *SUB = a.dynq + ((size_t)q * 3 + 2) * a.N;
+    auto ld = [&](int x, int y) {
+      const long long o = dg_idx(x, y, a.nx, a.ny);
+      if (a.fp32) return (double)Iout_of<float>(a)[base + o] + SUB[o];
+      return Iout_of<double>(a)[base + o];
+    };
+    double Fe, Fn;
+    out_faces(a, q, xl, yl, ld, Fe, Fn);
+    val = side < 2 ? Fe : Fn;
   }
+  return won * val;
+}
+
+// F_T . n_out on each boundary face: one workgroup per face, threads over
+// ordinates, fixed-order tree sum (batches).
+__device__ __forceinline__ void boundary_flux(const TArgs &a, const int f) {
+  const int f1 = a.state[1];   // tested before the store
+  int side, pos;
+  face_side(a, f, side, pos);
+  double acc = 0.0;
+  for (int kk = threadIdx.x; kk < a.K; kk += blockDim.x) acc += face_term(a, f, side, pos, kk);
   __shared__ double red[256];
   red[threadIdx.x] = acc;
   __syncthreads();
@@ -1759,6 +1767,18 @@ __device__ __forceinline__ void boundary_flux(const TArgs &a, const int f) {
     __syncthreads();
   }
   if (threadIdx.x == 0 && f1 == 0) a.bflux[f] = red[0];
+}
+// the same with one wave per face (lanes over ordinates, a fixed-order wave
+// sum, no barrier)
+__device__ __forceinline__ void boundary_flux_wave(const TArgs &a, const int f) {
+  const int f1 = a.state[1];
+  const int lane = threadIdx.x & 63;
+  int side, pos;
+  face_side(a, f, side, pos);
+  double acc = 0.0;
+  for (int kk = lane; kk < a.K; kk += 64) acc += face_term(a, f, side, pos, kk);
+  acc = wave_sum64(acc);
+  if (lane == 0 && f1 == 0) a.bflux[f] = acc;
 }
 
 // The boundary faces' F_T . n (blocks [0, nbf)) and the per-quadrant moment
@@ -1769,9 +1789,12 @@ __device__ __forceinline__ void boundary_flux(const TArgs &a, const int f) {
 template <typename T, int MT>
 __global__ void k_moments_q_bflux(TArgs a, double *part, int nbf8, int ntile, int ts,
                                   double *ftp) {
-  const int b = (int)blockIdx.x - nbf8;   // nbf8: a.nbf rounded up to a multiple of 8
+  // nbf8: blocks of four wall faces (one per wave), rounded up to a
+  // multiple of 8
+  const int b = (int)blockIdx.x - nbf8;
   if (b < 0) {
-    if ((int)blockIdx.x < a.nbf) boundary_flux(a, blockIdx.x);
+    const int f = 4 * (int)blockIdx.x + ((int)threadIdx.x >> 6);
+    if (f < a.nbf) boundary_flux_wave(a, f);
     return;
   }
   const int q = b / (8 * ts), r = b - q * 8 * ts;
@@ -2060,7 +2083,7 @@ void launch_moments_t(const TArgs &a, const PlanDev &P, hipStream_t s, bool bflu
   const int ntile = moment_tiles_of(P.nx, P.ny, MT);
   const int ts = (ntile + 7) / 8;   // tiles per XCD
   if (bflux) {   // the combine follows in the HoT kernel
-    const int nbf8 = (P.nbf + 7) / 8 * 8;
+    const int nbf8 = ((P.nbf + 3) / 4 + 7) / 8 * 8;
     hipLaunchKernelGGL((k_moments_q_bflux<T, MT>), dim3(nbf8 + 4 * 8 * ts), dim3(256), 0, s, a,
                        P.mom_part, nbf8, ntile, ts, P.hot_face ? P.ftp : nullptr);
     return;
