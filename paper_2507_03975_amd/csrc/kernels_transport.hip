@@ -1751,25 +1751,8 @@ __device__ __forceinline__ double face_term(const TArgs &a, const int f, const i
   return won * val;
 }
 
-// F_T . n_out on each boundary face: one workgroup per face, threads over
-// ordinates, fixed-order tree sum (batches).
-__device__ __forceinline__ void boundary_flux(const TArgs &a, const int f) {
-  const int f1 = a.state[1];   // tested before the store
-  int side, pos;
-  face_side(a, f, side, pos);
-  double acc = 0.0;
-  for (int kk = threadIdx.x; kk < a.K; kk += blockDim.x) acc += face_term(a, f, side, pos, kk);
-  __shared__ double red[256];
-  red[threadIdx.x] = acc;
-  __syncthreads();
-  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
-    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0 && f1 == 0) a.bflux[f] = red[0];
-}
-// the same with one wave per face (lanes over ordinates, a fixed-order wave
-// sum, no barrier)
+// F_T . n_out on wall face f: one wave, lanes over ordinates, a fixed-order
+// wave sum
 __device__ __forceinline__ void boundary_flux_wave(const TArgs &a, const int f) {
   const int f1 = a.state[1];
   const int lane = threadIdx.x & 63;
@@ -1804,9 +1787,12 @@ __global__ void k_moments_q_bflux(TArgs a, double *part, int nbf8, int ntile, in
   moments_tile<T, MT>(a, part, ftp, tile, q);
 }
 
-__global__ void k_boundary_flux_b(const TArgs *tas, const int2 *bt) {
-  const int2 v = bt[blockIdx.x];
-  boundary_flux(tas[v.x], v.y);
+// Batched wall faces: four (problem, face) entries per workgroup, a wave each.
+__global__ void k_boundary_flux_b(const TArgs *tas, const int2 *bt, int n) {
+  const int e = 4 * (int)blockIdx.x + ((int)threadIdx.x >> 6);
+  if (e >= n) return;
+  const int2 v = bt[e];
+  boundary_flux_wave(tas[v.x], v.y);
 }
 
 }  // namespace
@@ -2118,8 +2104,8 @@ void launch_moments_batch(const void *targs, const int2 *bt_cell, int nb_cell,
 
 void launch_boundary_flux_batch(const void *targs, const int2 *bt_face, int nb_face,
                                 hipStream_t s) {
-  hipLaunchKernelGGL(k_boundary_flux_b, dim3(nb_face), dim3(256), 0, s,
-                     reinterpret_cast<const TArgs *>(targs), bt_face);
+  hipLaunchKernelGGL(k_boundary_flux_b, dim3((nb_face + 3) / 4), dim3(256), 0, s,
+                     reinterpret_cast<const TArgs *>(targs), bt_face, nb_face);
 }
 
 }  // namespace gsis
