@@ -63,14 +63,14 @@ SYNTH_RTOL = 0.1
 # so FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0). Valid only for the kernel source
 # whose sha256 is recorded; any change to it turns the figures back to null.
 TRAFFIC = {
-    "thick256_fp64": {"sha256": "5dea0b09848117ee9bf14263a61d5902241a77a0c9ef01b9d2e763e1f915821b",
-                      "k_resid": 243611388,     # 83763.5 KiB x 2.0 + 70374.7 KiB
-                      "k_chain": 138759336},    # 34863.7 KiB x 2.0 + 65779.9 KiB
-    "block1024_fp64": {"sha256": "5dea0b09848117ee9bf14263a61d5902241a77a0c9ef01b9d2e763e1f915821b",
-                       "k_pipe": 3178688940},   # 980035.6 KiB x 2.0 + 1144117.2 KiB
-    "block1024_fp32": {"sha256": "5dea0b09848117ee9bf14263a61d5902241a77a0c9ef01b9d2e763e1f915821b",
-                       "k_resid": 2963764028,   # 1152936.1 KiB x 2.0 + 588428.5 KiB
-                       "k_chain": 1281094288},  # 346706.5 KiB x 2.0 + 557655.6 KiB
+    "thick256_fp64": {"sha256": "ef21c50e3453abfe4908ea33e2db821cfd4579441718adc9832c2b9b970a5699",
+                      "k_resid": 243632992,     # 83788.1 KiB x 2.0 + 70346.7 KiB
+                      "k_chain": 138782184},    # 34856.1 KiB x 2.0 + 65817.2 KiB
+    "block1024_fp64": {"sha256": "ef21c50e3453abfe4908ea33e2db821cfd4579441718adc9832c2b9b970a5699",
+                       "k_pipe": 3180814064},   # 981171.5 KiB x 2.0 + 1143920.8 KiB
+    "block1024_fp32": {"sha256": "ef21c50e3453abfe4908ea33e2db821cfd4579441718adc9832c2b9b970a5699",
+                       "k_resid": 2964364684,   # 1153238.9 KiB x 2.0 + 588409.6 KiB
+                       "k_chain": 1283360308},  # 348005.2 KiB x 2.0 + 557271.2 KiB
 }
 KERNELS = {"k_resid": "k_resid (second-order residual of every cell-ordinate, ALSM gradient "
                       "and BJ limiter, written as the recurrence's right-hand side)",

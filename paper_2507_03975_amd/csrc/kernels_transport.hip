@@ -897,7 +897,7 @@ __device__ __forceinline__ void chain_ordinate(A &a, const int kk, const int par
   constexpr bool kF32 = sizeof(T) == 4;
   static_assert((R & (R - 1)) == 0 && LAG == PF, "ring sizes");
   static_assert(!(SPLIT && MULTI), "a split recurrence runs one pass per part");
-  static_assert(kCMaxW * kCLag + 2 * kCPF <= kDiagPad, "diagonal table padding");
+  static_assert(kCMaxW * kCLag + 2 * kCPF + kCLag <= kDiagPad, "diagonal table padding");
   const int q = quadrant_of(a, kk);
   const int nx = a.nx, ny = a.ny, N = a.N;
   const int tid = threadIdx.x, lane = tid & 63;
@@ -967,8 +967,18 @@ __device__ __forceinline__ void chain_ordinate(A &a, const int kk, const int par
     unsigned long long hv = 0;
     bool gave_up = false;                     // a wait timed out: wait no more
     const bool top_lane = SPLIT && tid == rows - 1;   // this part's top row
+    // diagonal offsets of a block's loads, one block ahead: lane l holds that
+    // of the block's load l, read back as a wave-uniform lane value (a vector
+    // load, in order with the ring's, so no scalar-load wait in a block)
+    int dsn = DS[y0 - LAG + s0 + PF + (lane & (LAG - 1))];
+    // (the first one lands before the loop: still in flight at the loop
+    // head, the wait pass would cover it conservatively in every block, with
+    // all the ring's loads behind it)
+    asm volatile("" : "+v"(dsn));
     for (int tb = -LAG; tb < tend; tb += LAG) {
       const int sb = tb + s0;                 // this wave's first step of the block
+      const int dsc = dsn;
+      dsn = DS[y0 + sb + LAG + PF + (lane & (LAG - 1))];
       // v below lane 0 for the block's steps: the wave below's top lane
       // (written at least one barrier ago), the part below, the previous
       // pass, or 0
@@ -987,7 +997,7 @@ __device__ __forceinline__ void chain_ordinate(A &a, const int kk, const int par
       }
       int so[LAG];                            // diagonals of the loads issued in this block
 #pragma unroll
-      for (int t2 = 0; t2 < LAG; ++t2) so[t2] = DS[y0 + sb + PF + t2];
+      for (int t2 = 0; t2 < LAG; ++t2) so[t2] = __builtin_amdgcn_readlane(dsc, t2);
       T vv[LAG];
 #pragma unroll
       for (int t2 = 0; t2 < LAG; ++t2) {
