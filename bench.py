@@ -60,17 +60,17 @@ SYNTH_RTOL = 0.1
 # (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), scaled by what the same
 # counters read for a 256 MiB device copy (bench.py --copy-calibration: it
 # reads 131084.5 KiB of FETCH_SIZE and 262144 KiB of WRITE_SIZE per dispatch,
-# so FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0). Valid only for the kernel source
-# whose sha256 is recorded; any change to it turns the figures back to null.
+# so FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0). Valid only for the build whose
+# traffic_key() is recorded; any change to it turns the figures back to null.
 TRAFFIC = {
-    "thick256_fp64": {"sha256": "ef21c50e3453abfe4908ea33e2db821cfd4579441718adc9832c2b9b970a5699",
-                      "k_resid": 243632992,     # 83788.1 KiB x 2.0 + 70346.7 KiB
-                      "k_chain": 138782184},    # 34856.1 KiB x 2.0 + 65817.2 KiB
-    "block1024_fp64": {"sha256": "ef21c50e3453abfe4908ea33e2db821cfd4579441718adc9832c2b9b970a5699",
-                       "k_pipe": 3180814064},   # 981171.5 KiB x 2.0 + 1143920.8 KiB
-    "block1024_fp32": {"sha256": "ef21c50e3453abfe4908ea33e2db821cfd4579441718adc9832c2b9b970a5699",
-                       "k_resid": 2964364684,   # 1153238.9 KiB x 2.0 + 588409.6 KiB
-                       "k_chain": 1283360308},  # 348005.2 KiB x 2.0 + 557271.2 KiB
+    "thick256_fp64": {"sha256": "87b8dd5c5c0bb5a95f7669edeab150399734c57078e5c4d7b3c1cf5eb4da77cf",
+                      "k_resid": 244573448,     # 84267.8 KiB x 2.0 + 70305.6 KiB
+                      "k_chain": 138782520},    # 34856.4 KiB x 2.0 + 65817.0 KiB
+    "block1024_fp64": {"sha256": "87b8dd5c5c0bb5a95f7669edeab150399734c57078e5c4d7b3c1cf5eb4da77cf",
+                       "k_pipe": 3179074724},   # 980894.8 KiB x 2.0 + 1142775.5 KiB
+    "block1024_fp32": {"sha256": "87b8dd5c5c0bb5a95f7669edeab150399734c57078e5c4d7b3c1cf5eb4da77cf",
+                       "k_resid": 2965954644,   # 1153944.9 KiB x 2.0 + 588550.3 KiB
+                       "k_chain": 1283219692},  # 347933.3 KiB x 2.0 + 557277.6 KiB
 }
 KERNELS = {"k_resid": "k_resid (second-order residual of every cell-ordinate, ALSM gradient "
                       "and BJ limiter, written as the recurrence's right-hand side)",
@@ -156,16 +156,26 @@ def measure_controls(ctx, gsis, pd, opts, N, K, args, phases, nprof, achieved, t
     return res
 
 
+def traffic_key():
+    """sha256 of what the transport kernels are built from: their source, the
+    device header it includes and the compile flags (include paths aside)."""
+    from paper_2507_03975_amd import build
+    h = hashlib.sha256()
+    for name in ("kernels_transport.hip", "wave_ops.h"):
+        with open(os.path.join(ROOT, "paper_2507_03975_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    h.update(" ".join(a for a in build.COMMON if not a.startswith("-I")).encode())
+    return h.hexdigest()
+
+
 def kernel_traffic(cfg, kernel):
     """Bytes per launch of a transport kernel from the PMC runs of this
-    configuration, if the kernel source is unchanged since they were taken."""
+    configuration, if the kernels are built as they were when those runs
+    were taken (traffic_key)."""
     t = TRAFFIC.get(cfg)
     if not t or t.get(kernel) is None:
         return None
-    src = os.path.join(ROOT, "paper_2507_03975_amd", "csrc", "kernels_transport.hip")
-    with open(src, "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()
-    if sha != t["sha256"]:
+    if traffic_key() != t["sha256"]:
         return None
     return t[kernel]
 

@@ -1,7 +1,7 @@
 """Host-side pieces of bench.py: the traffic table's lookup (every committed
-figure is reachable while the kernel source is the one it was measured on,
-and unknown kernels read as None) and the refusal of more than one GPU."""
-import hashlib
+figure is reachable while the kernels are built as they were measured:
+source, device header and compile flags; unknown kernels read as None) and
+the refusal of more than one GPU."""
 import importlib.util
 import os
 import subprocess
@@ -19,9 +19,7 @@ def _bench():
 
 def test_traffic_lookup():
     b = _bench()
-    src = os.path.join(ROOT, "paper_2507_03975_amd", "csrc", "kernels_transport.hip")
-    with open(src, "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()
+    sha = b.traffic_key()
     for cfg, table in b.TRAFFIC.items():
         for name, val in table.items():
             if name == "sha256":
